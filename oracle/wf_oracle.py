@@ -1,0 +1,480 @@
+"""FP64 CPU oracle of the Wiener-filter-as-MAP hot path (test infrastructure only).
+
+Written from the paper's equations; each function cites the passage it follows.
+numpy's FFT is the one library primitive used per transform; numpy.linalg provides
+the Cholesky factorisation and small dense solves.  Nothing here is blocked, fused
+or reordered beyond what the equations state, so it can be checked by eye.
+
+Conventions the paper leaves open (fixed identically for the HIP library):
+
+* grid n x n (n even), pixel (y, x); signed wavenumbers k = (kx, ky) in [-n/2, n/2);
+* unitary DFT: (F x)_k = n^-1 sum_j x_j exp(-2 pi i k.j/n); the response R is
+  F^-1 restricted to Hermitian spectra (sec. 2, eq. ddecomp; R is an isometry);
+* live modes: k != 0, |kx| < n/2, |ky| < n/2 and prior S_k > 0; everything else is
+  dead (not a variable).  Half-plane storage [ncomp][n][n/2+1]; the independent
+  ("free") entries are kx in [1, n/2) (every row but ky = -n/2) and kx = 0 with
+  ky in [1, n/2); the rows kx = 0, ky in (n/2, n) hold their conjugate partners;
+* S_k = Theta_{band(k)} P_k is the variance of the unitary coefficient
+  (band -1: amplitude fixed at 1);
+* spin-2 (appendix C): with kappa = -k^2 phi absorbed into S, the shear spectra are
+  g1 = cos2a E - sin2a B, g2 = sin2a E + cos2a B, a = atan2(ky, kx) (per-mode
+  rotation, orthogonal, so R stays an isometry);
+* the L-BFGS variable is the whitened field w = S^-1/2 s on the free entries, with
+  the Euclidean inner product of their real and imaginary parts; f = chi^2 / 4.
+
+Parity status: every function below is pinned by the not-gpu tests in
+tests/test_oracle_*.py (brute-force DFT, plane-wave derivatives, finite
+differences, the dense Wiener filter, closed forms of the homogeneous unmasked
+case, Philox known answers).  Iteration counts of the solver are not pinned
+(the paper prints none).
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+__all__ = [
+    "signed_k", "live_mask", "free_mask", "partner_mask", "prior_S", "full_plane",
+    "forward", "adjoint", "inner_half", "chi2", "grad_chi2", "whitened_grad", "whitened_hvp",
+    "lbfgs_solve", "wiener_dense", "band_E", "dchi2_dtheta", "simulate", "sim_fisher",
+    "bandpower_qe", "dense_bias_fisher", "newton_update", "homogeneous_wiener",
+    "homogeneous_band_moments",
+]
+
+
+# ----------------------------------------------------------------------------- conventions
+
+def signed_k(n: int):
+    """(ky, kx) float64 broadcastable to the half plane [n][n/2+1]."""
+    iy = np.arange(n)
+    ky = np.where(iy < n // 2, iy, iy - n).astype(np.float64)[:, None]
+    kx = np.arange(n // 2 + 1, dtype=np.float64)[None, :]
+    return ky, kx
+
+
+def live_mask(n: int) -> np.ndarray:
+    """Live modes of the half plane: not DC, not on either Nyquist line."""
+    iy = np.arange(n)[:, None]
+    kx = np.arange(n // 2 + 1)[None, :]
+    return ~(((iy == 0) & (kx == 0)) | (iy == n // 2) | (kx == n // 2))
+
+
+def free_mask(n: int) -> np.ndarray:
+    """Independent live entries of the half plane (conjugate partners excluded)."""
+    iy = np.arange(n)[:, None]
+    kx = np.arange(n // 2 + 1)[None, :]
+    return live_mask(n) & ((kx > 0) | ((iy >= 1) & (iy < n // 2)))
+
+
+def partner_mask(n: int) -> np.ndarray:
+    iy = np.arange(n)[:, None]
+    kx = np.arange(n // 2 + 1)[None, :]
+    return live_mask(n) & (kx == 0) & (iy > n // 2)
+
+
+def prior_S(pshape: np.ndarray, band: np.ndarray, theta) -> np.ndarray:
+    """S_k = Theta_{b(k)} P_k (sec. 2.3, eqs. pi / pilin); 0 on dead modes."""
+    theta = np.asarray(theta, np.float64)
+    amp = np.where(band >= 0, theta[np.clip(band, 0, None)] if theta.size else 1.0, 1.0)
+    n = pshape.shape[1]
+    S = amp * pshape
+    S = np.where(live_mask(n)[None] & (S > 0), S, 0.0)
+    return S
+
+
+def _rotation_full(n: int):
+    """cos 2a, sin 2a on the full plane (appendix C rotation); (1, 0) at k = 0."""
+    k = np.fft.fftfreq(n, 1.0 / n)
+    ky = k[:, None]
+    kx = k[None, :]
+    k2 = kx * kx + ky * ky
+    with np.errstate(invalid="ignore", divide="ignore"):
+        c2 = np.where(k2 > 0, (kx * kx - ky * ky) / k2, 1.0)
+        s2 = np.where(k2 > 0, 2.0 * kx * ky / k2, 0.0)
+    return c2, s2
+
+
+def full_plane(half: np.ndarray, free: np.ndarray) -> np.ndarray:
+    """Full-plane [n][n] spectrum from the free half-plane entries by Hermitian symmetry."""
+    n = half.shape[0]
+    F = np.zeros((n, n), np.complex128)
+    iy, kx = np.nonzero(free)
+    v = half[iy, kx]
+    F[iy, kx] = v
+    F[(-iy) % n, (-kx) % n] = np.conj(v)
+    return F
+
+
+# ----------------------------------------------------------------------------- response R
+
+def forward(s: np.ndarray, free: np.ndarray | None = None) -> np.ndarray:
+    """x = R s (eq. ddecomp without noise): [ncomp][n][n/2+1] complex -> [ncomp][n][n] real.
+
+    Only the free entries of s are read.  Spin-0: x = F^-1 s.  Spin-2: rotate (E, B)
+    to (g1, g2) per mode (appendix C) and invert each component."""
+    ncomp, n = s.shape[0], s.shape[1]
+    fr = free_mask(n) if free is None else free
+    full = [full_plane(s[c], fr if fr.ndim == 2 else fr[c]) for c in range(ncomp)]
+    if ncomp == 2:
+        c2, s2 = _rotation_full(n)
+        full = [c2 * full[0] - s2 * full[1], s2 * full[0] + c2 * full[1]]
+    out = np.empty((ncomp, n, n))
+    for c in range(ncomp):
+        z = np.fft.ifft2(full[c]) * n
+        assert np.max(np.abs(z.imag)) <= 1e-9 * (np.max(np.abs(z.real)) + 1e-300)
+        out[c] = z.real
+    return out
+
+
+def adjoint(x: np.ndarray) -> np.ndarray:
+    """R^T x in the full-plane metric: unitary forward DFT, inverse rotation, dead modes
+    zeroed; conjugate partners are filled (they are part of the half plane)."""
+    ncomp, n = x.shape[0], x.shape[1]
+    t = [np.fft.fft2(x[c]) / n for c in range(ncomp)]
+    if ncomp == 2:
+        c2, s2 = _rotation_full(n)
+        t = [c2 * t[0] + s2 * t[1], -s2 * t[0] + c2 * t[1]]
+    live = live_mask(n)
+    return np.stack([np.where(live, tc[:, : n // 2 + 1], 0.0) for tc in t])
+
+
+def inner_half(a: np.ndarray, b: np.ndarray) -> float:
+    """Full-plane inner product Re sum_k conj(a_k) b_k for half-plane arrays that carry
+    every entry of the half plane (columns 0 and n/2 count once, the others twice)."""
+    n = a.shape[1]
+    wgt = np.full(n // 2 + 1, 2.0)
+    wgt[0] = 1.0
+    wgt[-1] = 1.0
+    return float(np.sum(wgt[None, None, :] * (np.conj(a) * b).real))
+
+
+# ----------------------------------------------------------------------------- objective
+
+def _free_with_prior(S):
+    n = S.shape[1]
+    return free_mask(n)[None] & (S > 0)
+
+
+def chi2(s, d, W, S) -> float:
+    """chi^2 = s^dag S^-1 s + (d - R s)^T N^-1 (d - R s) (sec. 2.2, eq. eq_chi), with
+    the mask folded into W = M N^-1 and the prior sum taken over the full plane."""
+    fr = _free_with_prior(S)
+    prior = 0.0
+    for c in range(S.shape[0]):
+        Fs = full_plane(s[c], fr[c])
+        Sf = full_plane(S[c].astype(np.complex128), fr[c]).real
+        nz = Sf > 0
+        prior += float(np.sum(np.abs(Fs[nz]) ** 2 / Sf[nz]))
+    x = forward(np.where(fr, s, 0), fr)
+    r = d - x
+    return prior + float(np.sum(W[None] * r * r))
+
+
+def grad_chi2(s, d, W, S) -> np.ndarray:
+    """d chi^2 / d s per stored coefficient (d/dRe + i d/dIm): 4 g on the free entries,
+    g = S^-1 s - R^dag N^-1 (d - R s) (eq. eq_cost); 0 elsewhere."""
+    fr = _free_with_prior(S)
+    sf = np.where(fr, s, 0)
+    x = forward(sf, fr)
+    Fr = adjoint(W[None] * (d - x))
+    with np.errstate(divide="ignore", invalid="ignore"):
+        g = np.where(fr, sf / np.where(fr, S, 1.0) - Fr, 0)
+    return 4.0 * g
+
+
+def whitened_grad(w, d, W, S) -> np.ndarray:
+    """Gradient of f = chi^2/4 in w = S^-1/2 s: w - S^1/2 R^T W (d - R S^1/2 w)."""
+    fr = _free_with_prior(S)
+    sq = np.sqrt(S)
+    x = forward(np.where(fr, sq * w, 0), fr)
+    return np.where(fr, w - sq * adjoint(W[None] * (d - x)), 0)
+
+
+def whitened_hvp(p, W, S) -> np.ndarray:
+    """Curvature of f applied to p: p + S^1/2 R^T W R S^1/2 p (eq. eq_curv, whitened)."""
+    fr = _free_with_prior(S)
+    sq = np.sqrt(S)
+    x = forward(np.where(fr, sq * p, 0), fr)
+    return np.where(fr, p + sq * adjoint(W[None] * x), 0)
+
+
+def _dot(a, b) -> float:
+    return float(np.vdot(a, b).real)
+
+
+def lbfgs_solve(d, W, S, m: int = 10, tol: float = 1e-10, max_iter: int = 20000,
+                dchi2_tol: float = 0.0, x0=None):
+    """MAP field by L-BFGS (sec. 2.2): textbook two-loop recursion (Nocedal & Wright,
+    Numerical Optimization, 2nd ed., algorithms 7.4/7.5) in the whitened variable,
+    H0 = gamma I with gamma = s.y / y.y of the newest pair, and the exact line search of
+    a quadratic, alpha = -g.p / p.D p (eq. eq_chib).  Starts from w = 0 unless given
+    (the start does not matter for a convex problem).  Stops when
+    |g| <= tol |g(0)|, or |delta chi^2| < dchi2_tol (sec. 3), or after max_iter.
+
+    Returns dict(s, w, iters, rel_grad, chi2, status) with s on the free entries and
+    its conjugate partners filled."""
+    fr = _free_with_prior(S)
+    sq = np.sqrt(S)
+    w = np.zeros_like(S, dtype=np.complex128) if x0 is None else np.where(fr, x0, 0).astype(np.complex128)
+    g = whitened_grad(np.zeros_like(w), d, W, S)
+    g0 = math.sqrt(_dot(g, g))
+    if w.any():
+        g = whitened_grad(w, d, W, S)
+    pairs: list[tuple[np.ndarray, np.ndarray, float]] = []
+    it = 0
+    status = 0
+    f_prev = None
+    rel = math.sqrt(_dot(g, g)) / g0 if g0 > 0 else 0.0
+    while True:
+        rel = math.sqrt(_dot(g, g)) / g0 if g0 > 0 else 0.0
+        if rel <= tol:
+            break
+        if it >= max_iter:
+            status = 1
+            break
+        q = g.copy()
+        alph = []
+        for sv, yv, rho in reversed(pairs):
+            a = rho * _dot(sv, q)
+            q = q - a * yv
+            alph.append(a)
+        if pairs:
+            sv, yv, _ = pairs[-1]
+            q = (_dot(sv, yv) / _dot(yv, yv)) * q
+        for (sv, yv, rho), a in zip(pairs, reversed(alph)):
+            b = rho * _dot(yv, q)
+            q = q + sv * (a - b)
+        p = -q
+        Dp = whitened_hvp(p, W, S)
+        pDp = _dot(p, Dp)
+        if not (pDp > 0):
+            status = 2
+            break
+        alpha = -_dot(g, p) / pDp
+        w_new = w + alpha * p
+        g_new = whitened_grad(w_new, d, W, S)
+        sv, yv = w_new - w, g_new - g
+        sy = _dot(sv, yv)
+        if sy > 1e-12 * math.sqrt(_dot(sv, sv) * _dot(yv, yv)):
+            pairs.append((sv, yv, 1.0 / sy))
+            if len(pairs) > m:
+                pairs.pop(0)
+        dchi = 4.0 * (alpha * _dot(g, p) + 0.5 * alpha * alpha * pDp)
+        w, g = w_new, g_new
+        it += 1
+        if dchi2_tol > 0 and abs(dchi) < dchi2_tol:
+            break
+    s = np.where(fr, sq * w, 0)
+    s = _fill_partners(s)
+    return dict(s=s, w=w, iters=it, rel_grad=rel, chi2=chi2(s, d, W, S), status=status)
+
+
+def _fill_partners(s):
+    n = s.shape[1]
+    out = s.copy()
+    iy = np.arange(n // 2 + 1, n)
+    out[:, iy, 0] = np.conj(s[:, n - iy, 0])
+    out[:, n // 2, :] = 0
+    return out
+
+
+# ----------------------------------------------------------------------------- dense Wiener filter
+
+def _coords(S):
+    """Real coordinates of the field: (comp, iy, kx, part) of each free entry with S > 0."""
+    fr = _free_with_prior(S)
+    cc, iy, kx = np.nonzero(fr)
+    comp = np.concatenate([cc, cc])
+    yy = np.concatenate([iy, iy])
+    xx = np.concatenate([kx, kx])
+    part = np.concatenate([np.zeros_like(cc), np.ones_like(cc)])
+    return comp, yy, xx, part
+
+
+def _response_matrix(S):
+    """A with x = A theta for the real coordinates theta (Re, Im of each free entry):
+    column j is R applied to the j-th unit coordinate."""
+    ncomp, n = S.shape[0], S.shape[1]
+    fr = _free_with_prior(S)
+    comp, yy, xx, part = _coords(S)
+    A = np.empty((ncomp * n * n, comp.size))
+    for j in range(comp.size):
+        e = np.zeros(S.shape, np.complex128)
+        e[comp[j], yy[j], xx[j]] = 1.0 if part[j] == 0 else 1.0j
+        A[:, j] = forward(e, fr).reshape(-1)
+    return A, (comp, yy, xx, part)
+
+
+def wiener_dense(d, W, S):
+    """Exact Wiener filter s = S R^dag C^-1 d, C = R S R^dag + N (appendix A, eq. eq:wiener),
+    in the real coordinates of the field (each of Re, Im carries variance S_k / 2);
+    masked pixels (W = 0) are dropped from d and C.  Also returns
+    chi^2_min = d^T C^-1 d.  Dense: O(n^6); for n <= 64 only."""
+    A, (comp, yy, xx, part) = _response_matrix(S)
+    var = 0.5 * S[comp, yy, xx]
+    obs = np.broadcast_to(W[None] > 0, d.shape).reshape(-1)
+    Ao = A[obs]
+    C = (Ao * var[None, :]) @ Ao.T
+    C[np.diag_indices_from(C)] += 1.0 / np.broadcast_to(W[None], d.shape).reshape(-1)[obs]
+    L = np.linalg.cholesky(C)
+    do = d.reshape(-1)[obs]
+    u = np.linalg.solve(L.T, np.linalg.solve(L, do))
+    theta = var * (Ao.T @ u)
+    s = np.zeros(S.shape, np.complex128)
+    np.add.at(s, (comp[part == 0], yy[part == 0], xx[part == 0]), theta[part == 0])
+    np.add.at(s, (comp[part == 1], yy[part == 1], xx[part == 1]), 1j * theta[part == 1])
+    return dict(s=_fill_partners(s), chi2_min=float(do @ u))
+
+
+def dense_bias_fisher(W, pshape, band, theta, nbands):
+    """Exact noise bias and Fisher matrix of the band powers (appendix A, eqs. bl and
+    eq:wf_exact_f read as the Gaussian-likelihood derivatives):
+    b_l = 1/2 tr(C^-1 Q_l), F_ll' = 1/2 tr(C^-1 Q_l C^-1 Q_l'), Q_l = R Pi_l R^dag,
+    evaluated as b_l = 1/2 sum_{j in l} pi_j G_jj, F_ll' = 1/2 sum pi_j pi_j' G_jj'^2 with
+    G = A^T C^-1 A over the real field coordinates (pi_j = P_k / 2).  n <= 32."""
+    S = prior_S(pshape, band, theta)
+    A, (comp, yy, xx, part) = _response_matrix(S)
+    var = 0.5 * S[comp, yy, xx]
+    ncomp = S.shape[0]
+    n = S.shape[1]
+    obs = np.broadcast_to(W[None] > 0, (ncomp, n, n)).reshape(-1)
+    Ao = A[obs]
+    C = (Ao * var[None, :]) @ Ao.T
+    C[np.diag_indices_from(C)] += 1.0 / np.broadcast_to(W[None], (ncomp, n, n)).reshape(-1)[obs]
+    G = Ao.T @ np.linalg.solve(C, Ao)
+    pi = 0.5 * pshape[comp, yy, xx]
+    bj = band[comp, yy, xx]
+    b = np.zeros(nbands)
+    F = np.zeros((nbands, nbands))
+    for l in range(nbands):
+        il = np.nonzero(bj == l)[0]
+        b[l] = 0.5 * np.sum(pi[il] * np.diag(G)[il])
+        for l2 in range(nbands):
+            i2 = np.nonzero(bj == l2)[0]
+            F[l, l2] = 0.5 * np.sum((pi[il][:, None] * pi[i2][None, :]) * G[np.ix_(il, i2)] ** 2)
+    return b, F
+
+
+# ----------------------------------------------------------------------------- band powers
+
+def band_E(s, S_fid, band, theta_fid, nbands) -> np.ndarray:
+    """E_l = 1/2 sum_{k in band l} |s_k|^2 / (Theta_fid,l S_fid,k) over the full plane
+    (sec. 2.3, eq. el)."""
+    ncomp, n = S_fid.shape[0], S_fid.shape[1]
+    fr = _free_with_prior(S_fid)
+    E = np.zeros(nbands)
+    for c in range(ncomp):
+        Fs = full_plane(s[c], fr[c])
+        Sf = full_plane(S_fid[c].astype(np.complex128), fr[c]).real
+        Bf = full_plane((band[c] + 1).astype(np.complex128), fr[c]).real.round().astype(int) - 1
+        for l in range(nbands):
+            sel = (Bf == l) & (Sf > 0)
+            E[l] += 0.5 * np.sum(np.abs(Fs[sel]) ** 2 / (theta_fid[l] * Sf[sel]))
+    return E
+
+
+def dchi2_dtheta(s, pshape, band, theta, nbands) -> np.ndarray:
+    """d chi^2 / d Theta_b at fixed s: the prior term's derivative,
+    -sum_{k in b, full plane} |s_k|^2 / (Theta_b^2 P_k)."""
+    S = prior_S(pshape, band, theta)
+    return -2.0 * band_E(s, S, band, np.asarray(theta, np.float64), nbands)
+
+
+def simulate(draw, S_true, W):
+    """One simulated data map (sec. 2.4 and the procedure summary): a Gaussian random
+    field with spectrum S_true, s_k = (S_true,k / 2)^1/2 (z_re + i z_im) on the free
+    entries, x = R s, plus pixel noise of variance 1/W, zero on masked pixels.
+    draw: [2][ncomp][n][n] standard normals (part 0 signal, part 1 noise)."""
+    ncomp, n = S_true.shape[0], S_true.shape[1]
+    h = n // 2
+    fr = _free_with_prior(S_true)
+    zr = draw[0][:, :, 0:2 * h:2][:, :, :h]
+    zi = draw[0][:, :, 1:2 * h:2][:, :, :h]
+    z = np.zeros(S_true.shape, np.complex128)
+    z[:, :, :h] = zr + 1j * zi
+    s = np.where(fr, np.sqrt(0.5 * S_true) * z, 0)
+    x = forward(s, fr)
+    with np.errstate(divide="ignore"):
+        sig = np.where(W > 0, 1.0 / np.sqrt(np.where(W > 0, W, 1.0)), 0.0)
+    return np.where(W[None] > 0, x + sig[None] * draw[1], 0.0)
+
+
+def _boosted_S(pshape, band, theta_fid, lb, factor):
+    th = np.asarray(theta_fid, np.float64).copy()
+    if lb >= 0:
+        th[lb] *= factor
+    return prior_S(pshape, band, th)
+
+
+def sim_fisher(W, pshape, band, theta_fid, nbands, draws, m=10, tol=1e-8, max_iter=20000):
+    """Simulation noise bias and Fisher matrix (sec. 2.4):
+    b_l = < E_l(Theta_fid, s_hat[d_sim]) > over sims drawn at Theta_fid (eq. blmv);
+    F_ll' Delta_l' = < E_l(s_hat[d_sim at Theta_fid + Delta_l' e_l']) - E_l(s_hat[d_sim]) >
+    (eq. fisher) with common random numbers, Delta_l' = Theta_fid,l' and every solve
+    using the fiducial prior; F is symmetrised.  Returns (b, F, E_sims[nsim][nbands])."""
+    theta_fid = np.asarray(theta_fid, np.float64)
+    S_fid = prior_S(pshape, band, theta_fid)
+    nsim = draws.shape[0]
+    Es = np.zeros((nsim, nbands))
+    Fs = np.zeros((nsim, nbands, nbands))
+    for i in range(nsim):
+        d0 = simulate(draws[i], S_fid, W)
+        E0 = band_E(lbfgs_solve(d0, W, S_fid, m, tol, max_iter)["s"], S_fid, band, theta_fid, nbands)
+        Es[i] = E0
+        for l2 in range(nbands):
+            S2 = _boosted_S(pshape, band, theta_fid, l2, 2.0)
+            d2 = simulate(draws[i], S2, W)
+            E2 = band_E(lbfgs_solve(d2, W, S_fid, m, tol, max_iter)["s"], S_fid, band, theta_fid, nbands)
+            Fs[i, :, l2] = (E2 - E0) / theta_fid[l2]
+    b = Es.mean(0)
+    F = Fs.mean(0)
+    return b, 0.5 * (F + F.T), Es
+
+
+def newton_update(theta_fid, F, E, b):
+    """Theta_hat = Theta_fid + F^-1 (E - b) (sec. 2.3, eq. eq:wfmv)."""
+    return np.asarray(theta_fid, np.float64) + np.linalg.solve(F, E - b)
+
+
+def bandpower_qe(d, W, pshape, band, theta_fid, nbands, draws, m=10, tol=1e-8, max_iter=20000):
+    """Quadratic band-power estimate (procedure summary, sec. 2.5): MAP of the data,
+    E_l of it, simulation b and F, Newton step.  Returns (theta_hat, E, b, F)."""
+    theta_fid = np.asarray(theta_fid, np.float64)
+    S_fid = prior_S(pshape, band, theta_fid)
+    sh = lbfgs_solve(d, W, S_fid, m, tol, max_iter)["s"]
+    E = band_E(sh, S_fid, band, theta_fid, nbands)
+    b, F, _ = sim_fisher(W, pshape, band, theta_fid, nbands, draws, m, tol, max_iter)
+    return newton_update(theta_fid, F, E, b), E, b, F
+
+
+# ----------------------------------------------------------------------------- closed forms
+
+def homogeneous_wiener(d, sigma2, S):
+    """Unmasked, homogeneous white noise: the filter is diagonal in Fourier space,
+    s_k = S_k / (S_k + sigma^2) (F d)_k (appendix A with R unitary, N = sigma^2 I).
+    Spin-0 only (the spin-2 case rotates first, still diagonal)."""
+    t = adjoint(d)
+    with np.errstate(invalid="ignore"):
+        return np.where(S > 0, S / (S + sigma2) * t, 0)
+
+
+def homogeneous_band_moments(pshape, band, theta_fid, theta_true, nbands, sigma2):
+    """Unmasked homogeneous noise, full-plane sums per band (diagonal C in Fourier space):
+    <E_l> = 1/2 sum P_k (S_true + s2) / (S_fid + s2)^2, b_l = 1/2 sum P_k / (S_fid + s2),
+    F_ll' = delta_ll' 1/2 sum P_k^2 / (S_fid + s2)^2."""
+    S_fid = prior_S(pshape, band, theta_fid)
+    S_tr = prior_S(pshape, band, theta_true)
+    n = pshape.shape[1]
+    fr = free_mask(n)[None] & (S_fid > 0)
+    mean = np.zeros(nbands)
+    b = np.zeros(nbands)
+    F = np.zeros((nbands, nbands))
+    for l in range(nbands):
+        sel = fr & (band == l)
+        # each free entry stands for two full-plane modes
+        P, Sf, St = pshape[sel], S_fid[sel], S_tr[sel]
+        mean[l] = np.sum(P * (St + sigma2) / (Sf + sigma2) ** 2)
+        b[l] = np.sum(P / (Sf + sigma2))
+        F[l, l] = np.sum(P * P / (Sf + sigma2) ** 2)
+    return mean, b, F
