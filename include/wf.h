@@ -1,0 +1,191 @@
+/*
+ * wf.h -- C-ABI of libwf: batched Wiener-filter-as-MAP reconstruction and band-power
+ * estimation on AMD MI355X (gfx950).
+ *
+ * Method: Horowitz, Seljak & Aslanyan, "Efficient optimal reconstruction of linear
+ * fields and band-powers from cosmological data" (arXiv:1810.00503).
+ *
+ *   data model          d = M (R s + n)                         (sec. 2, eq. ddecomp)
+ *   objective           chi^2(s) = s^dag S^-1 s + (d - R s)^T N^-1 (d - R s)   (eq. eq_chi)
+ *   gradient            g = S^-1 s - R^dag N^-1 (d - R s)        (eq. eq_cost)
+ *   curvature           D = S^-1 + R^dag N^-1 R                  (eq. eq_curv)
+ *   MAP solve           L-BFGS with the exact line search of a quadratic (sec. 2.2, eq. eq_chib)
+ *   band statistic      E_l = 1/2 s^dag S^-1 Pi_l S^-1 s          (sec. 2.3, eq. el)
+ *   noise bias          b_l = < E_l(s_hat[d_sim]) >               (sec. 2.4, eq. blmv)
+ *   Fisher              F_ll' Delta_l' = < E_l(Theta + Delta_l') - E_l(Theta) >  (eq. fisher)
+ *   Newton step         Theta_hat = Theta_fid + F^-1 (E - b)      (eq. eq:wfmv)
+ *   spin-2 response     appendix C (flat-sky E/B -> gamma1, gamma2)
+ *
+ * Conventions (the paper leaves them open; fixed here):
+ *   - grid n x n, pixel (y, x) row-major; n even, n % 8 == 0, 8 <= n <= 1024, and
+ *     n = 2^a or 3 * 2^a;
+ *   - unitary DFT (F x)_k = n^-1 sum_j x_j exp(-2 pi i k.j / n); R = F^-1 on Hermitian
+ *     spectra, so R is an isometry;
+ *   - field coefficients are stored on the half plane [ncomp][n][n/2+1] (interleaved
+ *     re, im of the element type): row iy holds ky = iy (iy < n/2) or iy - n, column kx;
+ *   - live modes: k != 0, |kx| < n/2, |ky| < n/2, prior S_k > 0.  Free (independent)
+ *     entries: kx in [1, n/2) on every row but iy = n/2, and kx = 0 with iy in [1, n/2).
+ *     Entries (kx = 0, iy > n/2) hold the conjugates of their partners; inputs are read
+ *     on free entries only; outputs write partners as conjugates and dead entries as 0;
+ *   - prior S_k = theta[band_k] * pshape_k (band -1: amplitude 1), the variance of the
+ *     unitary coefficient;
+ *   - spin-2 (ncomp = 2, s = (E, B)): gamma1 = cos2a E - sin2a B, gamma2 = sin2a E + cos2a B,
+ *     a = atan2(ky, kx), applied per mode before the inverse transform;
+ *   - W = M N^-1 >= 0 per pixel, shared by both spin-2 components; W = 0 masks a pixel;
+ *     the noise standard deviation of an observed pixel is W^-1/2.
+ *
+ * Memory: every array argument is caller-owned.  Unless stated otherwise, arrays are
+ * DEVICE pointers on the context's device.  The context owns its workspace (grown on
+ * demand, freed by wf_destroy).  Calls are enqueued on `stream` (a hipStream_t; NULL
+ * means the legacy default stream); calls that return host results synchronise it.
+ *
+ * Errors: 0 = success; WF_NOT_CONVERGED (+1) = soft status (some instance stopped at
+ * max_iter or on a non-finite value; see the per-instance stats); negative = error,
+ * with a message in wf_last_error(ctx).  No C++ exception crosses this boundary.
+ * One context per host thread.
+ */
+#ifndef WF_H
+#define WF_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct wf_ctx wf_ctx;
+
+enum {
+  WF_OK = 0,
+  WF_NOT_CONVERGED = 1,
+  WF_EINVAL = -1,      /* bad argument (null pointer, bad n / ncomp / dtype / batch) */
+  WF_ESHAPE = -2,      /* shapes of a batch or of two arguments disagree              */
+  WF_ENOMEM = -3,      /* device or host allocation failed                            */
+  WF_EHIP = -4,        /* a HIP runtime call failed                                   */
+  WF_ENONFINITE = -5   /* non-finite input or result                                  */
+};
+
+enum { WF_F32 = 0, WF_F64 = 1 };
+
+/* per-instance solver status */
+enum { WF_SOLVE_CONVERGED = 0, WF_SOLVE_MAXITER = 1, WF_SOLVE_NONFINITE = 2 };
+
+/* wf_adjoint flags */
+enum {
+  WF_ADJ_METRIC = 0,   /* s = R^T x in the full-plane metric (partners filled)          */
+  WF_ADJ_GRAD = 1      /* gradient of a function of x = R s w.r.t. the stored s, in the
+                          d/dRe + i d/dIm convention: 2 R^T x on free entries, 0 else  */
+};
+
+typedef struct {
+  int32_t n;              /* grid side                                                   */
+  int32_t ncomp;          /* 1 = spin-0 field, 2 = spin-2 (E, B) -> (gamma1, gamma2)     */
+  int32_t dtype;          /* WF_F32 or WF_F64: type of d, w and of the coefficients      */
+  int32_t nbands;         /* number of band amplitudes (0 allowed)                       */
+  const void* d;          /* [ncomp][n][n] data; values on masked pixels are ignored     */
+  const void* w;          /* [n][n] inverse-noise weight with the mask, M N^-1 >= 0      */
+  const double* pshape;   /* [ncomp][n][n/2+1] prior shape P_k >= 0 (float64)            */
+  const int32_t* band;    /* [ncomp][n][n/2+1] band index in [-1, nbands)                */
+  const double* theta;    /* HOST [nbands] band amplitudes                               */
+} wf_problem;
+
+typedef struct {
+  int32_t m;              /* L-BFGS memory (pairs kept), 1..16; default 10               */
+  int32_t max_iter;       /* default 20000                                               */
+  double rel_grad_tol;    /* stop when |g(s)| <= tol |g(0)|, whitened gradient; 1e-6     */
+  double dchi2_tol;       /* also stop when |chi^2_k - chi^2_{k-1}| < this (0 = off)      */
+  int32_t refresh_every;  /* recompute the exact gradient every this many iterations
+                             (0 = only when the running gradient meets the tolerance)    */
+  int32_t iters_per_poll; /* iterations enqueued between host checks (0 = automatic)     */
+  int32_t use_graph;      /* 1 = replay captured HIP graphs of the iteration (default),
+                             0 = launch kernels one by one                               */
+  int32_t reserved;
+} wf_lbfgs_opts;
+
+typedef struct {
+  int32_t iters;          /* L-BFGS directions taken                                      */
+  int32_t status;         /* WF_SOLVE_*                                                   */
+  int32_t ngrad;          /* exact gradient evaluations (first one included)             */
+  int32_t reserved;
+  double chi2;            /* chi^2 at the returned s (from the last exact evaluation
+                             and the exact quadratic updates since)                      */
+  double rel_grad;        /* |g(s)| / |g(0)| (exact gradient when converged)             */
+} wf_solve_stats;
+
+/* context ----------------------------------------------------------------------------- */
+int wf_create(wf_ctx** out, int hip_device);
+void wf_destroy(wf_ctx* ctx);
+const char* wf_last_error(const wf_ctx* ctx);
+void wf_lbfgs_default(wf_lbfgs_opts* opts);
+
+/* MAP solve (sec. 2.2): for each of `batch` problems, s_hat = argmin chi^2.
+ *   probs    HOST [batch]; sizes and types may differ between instances (uneven batch);
+ *   s_out    HOST [batch] of device pointers, each [ncomp][n][n/2+1] complex (dtype);
+ *   map_out  nullable; HOST [batch] of device pointers (entries may be NULL), each
+ *            [ncomp][n][n] real: the map R s_hat;
+ *   stats    HOST [batch] (nullable).
+ * Returns WF_OK if every instance converged, WF_NOT_CONVERGED otherwise.             */
+int map_wf_solve(wf_ctx* ctx, const wf_problem* probs, int32_t batch, const wf_lbfgs_opts* opts,
+                 void* const* s_out, void* const* map_out, wf_solve_stats* stats, void* stream);
+
+/* Simulated data (sec. 2.4, procedure summary): d_i = M (R s_i + n_i) with
+ * s ~ N(0, S_true) on free modes and n_i of variance 1/W on observed pixels; 0 on masked.
+ * S_true = theta_true[band] pshape (theta_true HOST [nbands], NULL = prob->theta), with
+ * band `boost_band` (-1 = none) scaled by boost_factor.
+ * Normals: `draws` (device, [nsim][2][ncomp][n][n], dtype; part 0 signal: [c][ky][2kx],
+ * [c][ky][2kx+1] are re, im of mode (ky, kx); part 1 pixel noise), or, if NULL, the
+ * Philox4x32-10 stream of simulation sim0 + i with `seed` (key = seed lo/hi 32 bits,
+ * counter (q/4, sim, 0, 0) for normal q, Box-Muller pairs in float64).
+ *   d_out    [nsim][ncomp][n][n] (dtype).                                               */
+int wf_simulate(wf_ctx* ctx, const wf_problem* prob, int32_t nsim, uint64_t seed, int32_t sim0,
+                const void* draws, const double* theta_true, int32_t boost_band, double boost_factor,
+                void* d_out, void* stream);
+
+/* Simulation noise bias and Fisher matrix around prob->theta (eqs. blmv, fisher):
+ * nsim * (1 + nbands) MAP solves with the fiducial prior, common random numbers,
+ * Delta_l = theta_l; F symmetrised.  F HOST [nbands*nbands], b HOST [nbands],
+ * E_sims nullable HOST [nsim][nbands] (E of the fiducial simulations).               */
+int sim_fisher(wf_ctx* ctx, const wf_problem* prob, int32_t nsim, uint64_t seed, const void* draws,
+               const wf_lbfgs_opts* opts, double* F, double* b, double* E_sims, void* stream);
+
+/* Quadratic band-power estimator (sec. 2.3-2.5): MAP of prob->d, E_l of it, sim_fisher,
+ * Newton step.  theta_hat, E, b HOST [nbands]; F HOST [nbands*nbands] (nullable).      */
+int bandpower_qe(wf_ctx* ctx, const wf_problem* prob, int32_t nsim, uint64_t seed, const void* draws,
+                 const wf_lbfgs_opts* opts, double* theta_hat, double* E, double* b, double* F,
+                 void* stream);
+
+/* operator-level calls: `batch` fields sharing prob's geometry, packed contiguously -- */
+
+/* x = R s (eq. ddecomp): s [batch][ncomp][n][n/2+1] complex -> x [batch][ncomp][n][n]. */
+int wf_forward(wf_ctx* ctx, const wf_problem* prob, int32_t batch, const void* s, void* x, void* stream);
+
+/* s = R^T x (flags WF_ADJ_METRIC) or the stored-coefficient gradient (WF_ADJ_GRAD).  */
+int wf_adjoint(wf_ctx* ctx, const wf_problem* prob, int32_t batch, const void* x, void* s, int32_t flags,
+               void* stream);
+
+/* chi^2 (eq. eq_chi) of each field and, if grad_s != NULL, d chi^2 / d s per stored
+ * coefficient (d/dRe + i d/dIm): 4 g on free entries with S > 0 (eq. eq_cost), 0 else.
+ * chi2 HOST [batch].                                                                   */
+int wf_chi2_grad(wf_ctx* ctx, const wf_problem* prob, int32_t batch, const void* s, double* chi2,
+                 void* grad_s, void* stream);
+
+/* curvature product in the same convention: Dp = 4 (S^-1 p + R^T W R p) (eq. eq_curv). */
+int wf_hvp(wf_ctx* ctx, const wf_problem* prob, int32_t batch, const void* p, void* Dp, void* stream);
+
+/* band statistic E_l (eq. el) of each field with the prior of prob: E HOST [batch][nbands]. */
+int wf_band_E(wf_ctx* ctx, const wf_problem* prob, int32_t batch, const void* s, double* E, void* stream);
+
+/* instrumentation: per-kernel-kind launch counts, accumulated kernel time (HIP events
+ * around each launch; only while profiling is on, which disables graph replay) and
+ * algorithmic bytes (counted on the device for every launch).  Kinds are named by
+ * wf_kernel_kind_name(k) for k in [0, wf_kernel_kinds()).                            */
+int wf_set_profiling(wf_ctx* ctx, int32_t on);
+int wf_kernel_kinds(void);
+const char* wf_kernel_kind_name(int32_t kind);
+int wf_get_kernel_stats(wf_ctx* ctx, int64_t* launches, double* ms, double* bytes);
+int wf_reset_kernel_stats(wf_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* WF_H */

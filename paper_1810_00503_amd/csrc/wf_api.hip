@@ -1,0 +1,1177 @@
+// C-ABI of libwf: context, batched MAP solve driver, simulations, band powers,
+// operator-level calls and instrumentation.  The declarations and the contract of
+// every entry point are in include/wf.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <new>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "wf.h"
+#include "wf_launch.hpp"
+
+using namespace wf;
+
+namespace {
+
+constexpr size_t kAlign = 256;
+constexpr int kNdot = 5 * MMAX + 1;
+constexpr double kSimBudgetBytes = 48.0 * 1024 * 1024 * 1024;   // workspace cap of a sim chunk
+constexpr int kMaxChunk = 256;
+
+const char* kKindNames[KK_COUNT] = {"colinv", "row", "colfwd", "passA", "passB", "post", "coef", "misc"};
+
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+struct Arena {
+  char* base = nullptr;
+  size_t cap = 0;
+  size_t used = 0;
+  int gen = 0;
+};
+
+}  // namespace
+
+struct wf_ctx {
+  int dev = 0;
+  std::string err;
+  hipStream_t cs = nullptr;
+  hipEvent_t evIn = nullptr, evOut = nullptr;
+  std::map<std::pair<int, int>, void*> tw;   // (n, dtype) -> twiddles
+  std::map<std::tuple<int, int, int>, bool> prepared;
+  Arena solveA, simA, opA;
+  int* hstat = nullptr;
+  size_t hstatCap = 0;
+  // instrumentation
+  bool prof = false;
+  int64_t launches[KK_COUNT] = {};
+  double ms[KK_COUNT] = {};
+  double bytes[KK_COUNT] = {};
+  std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> pendingEv;
+  std::vector<hipEvent_t> evPool;
+  // graph cache
+  hipGraphExec_t gexec = nullptr;
+  std::string gkey;
+};
+
+namespace {
+
+int fail(wf_ctx* c, int code, const std::string& msg) {
+  if (c) c->err = msg;
+  return code;
+}
+
+#define HIPCHK(call)                                                                              \
+  do {                                                                                            \
+    hipError_t _e = (call);                                                                       \
+    if (_e != hipSuccess)                                                                         \
+      return fail(ctx, WF_EHIP, std::string(#call) + ": " + hipGetErrorString(_e));               \
+  } while (0)
+
+int esize_of(int dtype) { return dtype == WF_F64 ? 16 : 8; }
+int rsize_of(int dtype) { return dtype == WF_F64 ? 8 : 4; }
+
+int arena_reserve(wf_ctx* ctx, Arena& a, size_t bytes) {
+  if (bytes <= a.cap) {
+    a.used = 0;
+    return WF_OK;
+  }
+  if (a.base) {
+    HIPCHK(hipStreamSynchronize(ctx->cs));
+    HIPCHK(hipFree(a.base));
+    a.base = nullptr;
+    a.cap = 0;
+  }
+  size_t want = bytes + bytes / 8;
+  if (hipMalloc((void**)&a.base, want) != hipSuccess) {
+    (void)hipGetLastError();
+    a.base = nullptr;
+    if (hipMalloc((void**)&a.base, bytes) != hipSuccess) {
+      (void)hipGetLastError();
+      a.base = nullptr;
+      return fail(ctx, WF_ENOMEM, "device allocation of " + std::to_string(bytes) + " bytes failed");
+    }
+    want = bytes;
+  }
+  a.cap = want;
+  a.used = 0;
+  a.gen++;
+  if (&a == &ctx->solveA && ctx->gexec) {
+    (void)hipGraphExecDestroy(ctx->gexec);
+    ctx->gexec = nullptr;
+    ctx->gkey.clear();
+  }
+  return WF_OK;
+}
+
+char* arena_take(Arena& a, size_t bytes) {
+  char* p = a.base + a.used;
+  a.used += align_up(bytes);
+  return p;
+}
+
+int host_status(wf_ctx* ctx, size_t n) {
+  if (n <= ctx->hstatCap) return WF_OK;
+  if (ctx->hstat) (void)hipHostFree(ctx->hstat);
+  ctx->hstat = nullptr;
+  HIPCHK(hipHostMalloc((void**)&ctx->hstat, n * sizeof(int), hipHostMallocDefault));
+  ctx->hstatCap = n;
+  return WF_OK;
+}
+
+// twiddles exp(-2 pi i k / n), k in [0, n), generated in float64
+int twiddles(wf_ctx* ctx, int n, int dtype, const void** out) {
+  auto key = std::make_pair(n, dtype);
+  auto it = ctx->tw.find(key);
+  if (it != ctx->tw.end()) {
+    *out = it->second;
+    return WF_OK;
+  }
+  std::vector<double> h(2 * (size_t)n);
+  for (int k = 0; k < n; ++k) {
+    // reduce to the first octant for accuracy, then apply symmetries
+    const double a = 2.0 * M_PI * (double)k / (double)n;
+    h[2 * k] = std::cos(a);
+    h[2 * k + 1] = -std::sin(a);
+  }
+  void* d = nullptr;
+  const size_t bytes = (size_t)n * esize_of(dtype);
+  HIPCHK(hipMalloc(&d, bytes));
+  if (dtype == WF_F64) {
+    HIPCHK(hipMemcpy(d, h.data(), bytes, hipMemcpyHostToDevice));
+  } else {
+    std::vector<float> f(h.begin(), h.end());
+    HIPCHK(hipMemcpy(d, f.data(), bytes, hipMemcpyHostToDevice));
+  }
+  ctx->tw[key] = d;
+  *out = d;
+  return WF_OK;
+}
+
+int prepare(wf_ctx* ctx, int n, int c, int dtype) {
+  auto key = std::make_tuple(n, c, dtype);
+  if (ctx->prepared.count(key)) return WF_OK;
+  HIPCHK(dtype == WF_F64 ? chain_prepare_f64(n, c) : chain_prepare_f32(n, c));
+  ctx->prepared[key] = true;
+  return WF_OK;
+}
+
+// ---------------------------------------------------------------------------- launch helpers
+hipEvent_t ev_get(wf_ctx* ctx) {
+  if (!ctx->evPool.empty()) {
+    hipEvent_t e = ctx->evPool.back();
+    ctx->evPool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  (void)hipEventCreate(&e);
+  return e;
+}
+
+struct Timed {
+  wf_ctx* ctx;
+  int kind;
+  hipEvent_t a = nullptr, b = nullptr;
+  Timed(wf_ctx* c, int k) : ctx(c), kind(k) {
+    ctx->launches[k]++;
+    if (ctx->prof) {
+      a = ev_get(ctx);
+      b = ev_get(ctx);
+      (void)hipEventRecord(a, ctx->cs);
+    }
+  }
+  ~Timed() {
+    if (ctx->prof) {
+      (void)hipEventRecord(b, ctx->cs);
+      ctx->pendingEv.push_back({kind, {a, b}});
+    }
+  }
+};
+
+int drain_events(wf_ctx* ctx) {
+  if (ctx->pendingEv.empty()) return WF_OK;
+  HIPCHK(hipStreamSynchronize(ctx->cs));
+  for (auto& pe : ctx->pendingEv) {
+    float t = 0.f;
+    if (hipEventElapsedTime(&t, pe.second.first, pe.second.second) == hipSuccess) ctx->ms[pe.first] += t;
+    ctx->evPool.push_back(pe.second.first);
+    ctx->evPool.push_back(pe.second.second);
+  }
+  ctx->pendingEv.clear();
+  return WF_OK;
+}
+
+hipError_t chain(wf_ctx* ctx, int dtype, int n, int c, int which, const Job* jobs, int batch, const void* tw) {
+  Timed t(ctx, which == CH_COLINV ? KK_COLINV : (which == CH_ROW ? KK_ROW : KK_COLFWD));
+  return dtype == WF_F64 ? chain_launch_f64(n, c, which, jobs, batch, tw, ctx->cs)
+                         : chain_launch_f32(n, c, which, jobs, batch, tw, ctx->cs);
+}
+
+// ---------------------------------------------------------------------------- validation
+int check_problem(wf_ctx* ctx, const wf_problem* p, bool need_data) {
+  if (!p) return fail(ctx, WF_EINVAL, "null problem");
+  if (!chain_supported(p->n))
+    return fail(ctx, WF_EINVAL, "unsupported n=" + std::to_string(p->n) +
+                                    " (need n % 8 == 0, 8 <= n <= 1024, n = 2^a or 3*2^a)");
+  if (p->ncomp != 1 && p->ncomp != 2) return fail(ctx, WF_EINVAL, "ncomp must be 1 or 2");
+  if (p->dtype != WF_F32 && p->dtype != WF_F64) return fail(ctx, WF_EINVAL, "dtype must be WF_F32 or WF_F64");
+  if (p->nbands < 0 || p->nbands > 4096) return fail(ctx, WF_EINVAL, "nbands out of range");
+  if (!p->w || !p->pshape || !p->band) return fail(ctx, WF_EINVAL, "null w / pshape / band");
+  if (p->nbands > 0 && !p->theta) return fail(ctx, WF_EINVAL, "null theta");
+  if (need_data && !p->d) return fail(ctx, WF_EINVAL, "null d");
+  if (p->theta)
+    for (int b = 0; b < p->nbands; ++b)
+      if (!std::isfinite(p->theta[b])) return fail(ctx, WF_ENONFINITE, "non-finite theta");
+  return WF_OK;
+}
+
+void fill_opts(const wf_lbfgs_opts* o, wf_lbfgs_opts& r) {
+  wf_lbfgs_default(&r);
+  if (o) r = *o;
+  if (r.m <= 0) r.m = 10;
+  if (r.max_iter <= 0) r.max_iter = 20000;
+  if (!(r.rel_grad_tol > 0)) r.rel_grad_tol = 1e-6;
+}
+
+// ---------------------------------------------------------------------------- prior tables
+struct PriorTab {
+  void* sq = nullptr;         // [c][n][h] real
+  int32_t* bandI = nullptr;   // [c][n][h]
+  double* theta = nullptr;    // [nbands]
+};
+
+size_t prior_bytes(const wf_problem* p) {
+  const size_t L = (size_t)p->ncomp * p->n * (p->n / 2);
+  return align_up(L * rsize_of(p->dtype)) + align_up(L * 4) + align_up(sizeof(double) * std::max(1, p->nbands));
+}
+
+int build_prior(wf_ctx* ctx, Arena& a, const wf_problem* p, const double* theta, PriorTab& t) {
+  const size_t L = (size_t)p->ncomp * p->n * (p->n / 2);
+  t.sq = arena_take(a, L * rsize_of(p->dtype));
+  t.bandI = (int32_t*)arena_take(a, L * 4);
+  t.theta = (double*)arena_take(a, sizeof(double) * std::max(1, p->nbands));
+  if (p->nbands > 0)
+    HIPCHK(hipMemcpyAsync(t.theta, theta, sizeof(double) * p->nbands, hipMemcpyHostToDevice, ctx->cs));
+  HIPCHK(prior_table_launch(p->dtype, p->n, p->ncomp, p->pshape, p->band, t.theta, p->nbands, t.sq, t.bandI, ctx->cs));
+  return WF_OK;
+}
+
+struct StreamScope {
+  wf_ctx* ctx;
+  hipStream_t us;
+  StreamScope(wf_ctx* c, void* s) : ctx(c), us((hipStream_t)s) {
+    (void)hipSetDevice(ctx->dev);
+    (void)hipEventRecord(ctx->evIn, us);
+    (void)hipStreamWaitEvent(ctx->cs, ctx->evIn, 0);
+  }
+  ~StreamScope() {
+    (void)hipEventRecord(ctx->evOut, ctx->cs);
+    (void)hipStreamWaitEvent(us, ctx->evOut, 0);
+  }
+};
+
+// ---------------------------------------------------------------------------- solve core
+struct Klass {
+  int n, c, dtype;
+  std::vector<int> members;   // user indices
+  int first = 0;              // position in the class-ordered arrays
+  int64_t L = 0;
+  int nblkA = 0, nblkB = 0, pstride = 0;
+  const void* tw = nullptr;
+};
+
+struct SolveOut {
+  std::vector<void*> w;         // per user index: whitened solution (internal layout)
+  std::vector<void*> y;         // per user index: intermediate buffer
+  std::vector<PriorTab> prior;  // per user index
+  std::vector<LbState> st;      // per user index
+  std::vector<int> order;       // class-ordered position of each user index
+};
+
+int solve_core(wf_ctx* ctx, const wf_problem* probs, int B, const wf_lbfgs_opts& o, SolveOut& out) {
+  const int m = o.m;
+  if (m < 1 || m > MMAX) return fail(ctx, WF_EINVAL, "m must be in [1, 16]");
+  // group into classes of equal (n, ncomp, dtype)
+  std::vector<Klass> ks;
+  for (int i = 0; i < B; ++i) {
+    const wf_problem* p = &probs[i];
+    int rc = check_problem(ctx, p, true);
+    if (rc) return rc;
+    bool found = false;
+    for (auto& k : ks)
+      if (k.n == p->n && k.c == p->ncomp && k.dtype == p->dtype) {
+        k.members.push_back(i);
+        found = true;
+        break;
+      }
+    if (!found) {
+      Klass k;
+      k.n = p->n;
+      k.c = p->ncomp;
+      k.dtype = p->dtype;
+      k.members.push_back(i);
+      ks.push_back(k);
+    }
+  }
+  // distinct priors within the call
+  std::map<std::tuple<const void*, const void*, int, int, int, std::vector<double>>, int> pmap;
+  std::vector<int> pidx(B);
+  std::vector<int> prepIdx;
+  for (int i = 0; i < B; ++i) {
+    const wf_problem* p = &probs[i];
+    std::vector<double> th(p->theta, p->theta + p->nbands);
+    auto key = std::make_tuple((const void*)p->pshape, (const void*)p->band, p->n, p->ncomp, p->dtype, th);
+    auto it = pmap.find(key);
+    if (it == pmap.end()) {
+      const int id = (int)prepIdx.size();
+      pmap[key] = id;
+      prepIdx.push_back(i);
+      pidx[i] = id;
+    } else {
+      pidx[i] = it->second;
+    }
+  }
+  // sizes
+  size_t total = 0;
+  for (int id : prepIdx) total += prior_bytes(&probs[id]);
+  int pos = 0;
+  for (auto& k : ks) {
+    k.first = pos;
+    pos += (int)k.members.size();
+    k.L = (int64_t)k.c * k.n * (k.n / 2);
+    const int vw = k.dtype == WF_F64 ? 2 : 4;
+    const int64_t nvec = k.L * 2 / vw;
+    const int64_t chunk = (int64_t)NT * 8;   // PASS_EPT vectors per thread
+    k.nblkA = (int)((nvec + chunk - 1) / chunk);
+    k.nblkB = k.nblkA;
+    k.pstride = k.n / RB;
+    const size_t eb = esize_of(k.dtype);
+    const size_t per = align_up((size_t)(3 + 2 * m) * k.L * eb) + align_up(sizeof(double) * PK_COUNT * k.pstride) +
+                       align_up(sizeof(double) * kNdot * k.nblkA);
+    total += per * k.members.size();
+    int rc = twiddles(ctx, k.n, k.dtype, &k.tw);
+    if (rc) return rc;
+    rc = prepare(ctx, k.n, k.c, k.dtype);
+    if (rc) return rc;
+  }
+  total += align_up(sizeof(InstDesc) * B) + align_up(sizeof(LbState) * B) + align_up(sizeof(Job) * B) +
+           align_up(sizeof(int) * B);
+  int rc = arena_reserve(ctx, ctx->solveA, total);
+  if (rc) return rc;
+  Arena& A = ctx->solveA;
+  InstDesc* ddesc = (InstDesc*)arena_take(A, sizeof(InstDesc) * B);
+  LbState* dst = (LbState*)arena_take(A, sizeof(LbState) * B);
+  Job* djobs = (Job*)arena_take(A, sizeof(Job) * B);
+  int* dstat = (int*)arena_take(A, sizeof(int) * B);
+  std::vector<PriorTab> ptabs(prepIdx.size());
+  for (size_t id = 0; id < prepIdx.size(); ++id) {
+    rc = build_prior(ctx, A, &probs[prepIdx[id]], probs[prepIdx[id]].theta, ptabs[id]);
+    if (rc) return rc;
+  }
+  std::vector<InstDesc> hd(B);
+  out.w.assign(B, nullptr);
+  out.y.assign(B, nullptr);
+  out.prior.assign(B, PriorTab());
+  out.order.assign(B, 0);
+  for (auto& k : ks) {
+    const size_t eb = esize_of(k.dtype);
+    for (size_t j = 0; j < k.members.size(); ++j) {
+      const int ui = k.members[j];
+      const int gi = k.first + (int)j;
+      const wf_problem* p = &probs[ui];
+      char* v = arena_take(A, (size_t)(3 + 2 * m) * k.L * eb);
+      InstDesc& D = hd[gi];
+      D.w = v;
+      D.g = v + (size_t)k.L * eb;
+      D.y = v + 2 * (size_t)k.L * eb;
+      D.P = v + 3 * (size_t)k.L * eb;
+      D.D = v + (3 + (size_t)m) * k.L * eb;
+      D.d = p->d;
+      D.W = p->w;
+      D.sq = ptabs[pidx[ui]].sq;
+      D.partChain = (double*)arena_take(A, sizeof(double) * PK_COUNT * k.pstride);
+      D.partA = (double*)arena_take(A, sizeof(double) * kNdot * k.nblkA);
+      D.statusOut = dstat + gi;
+      D.n = k.n;
+      D.c = k.c;
+      D.L = k.L;
+      D.pstride = k.pstride;
+      D.nblkA = k.nblkA;
+      D.nblkB = k.nblkB;
+      D.m = m;
+      D.esize = (int)eb;
+      D.maxIter = o.max_iter;
+      D.refreshEvery = o.refresh_every;
+      D.tol = o.rel_grad_tol;
+      D.dchi2Tol = o.dchi2_tol;
+      D.vbytes = (double)k.L * eb;
+      out.w[ui] = D.w;
+      out.y[ui] = D.y;
+      out.prior[ui] = ptabs[pidx[ui]];
+      out.order[ui] = gi;
+    }
+  }
+  HIPCHK(hipMemcpyAsync(ddesc, hd.data(), sizeof(InstDesc) * B, hipMemcpyHostToDevice, ctx->cs));
+  // init
+  for (auto& k : ks) {
+    const int cnt = (int)k.members.size();
+    {
+      Timed t(ctx, KK_MISC);
+      const int64_t nvec = k.L * 2 / (k.dtype == WF_F64 ? 2 : 4);
+      const unsigned bx = (unsigned)std::min<int64_t>((nvec + 255) / 256, 1024);
+      HIPCHK(lbfgs_launch(k.dtype == WF_F64, m, LB_ZERO, dim3(bx, cnt), ddesc + k.first, dst + k.first,
+                          djobs + k.first, cnt, ctx->cs));
+    }
+    {
+      Timed t(ctx, KK_MISC);
+      HIPCHK(lbfgs_launch(k.dtype == WF_F64, m, LB_INIT, dim3(1), ddesc + k.first, dst + k.first, djobs + k.first, cnt,
+                          ctx->cs));
+    }
+  }
+  // one iteration for every class
+  auto body = [&](void) -> int {
+    for (auto& k : ks) {
+      const int cnt = (int)k.members.size();
+      for (int w = 0; w < 3; ++w) HIPCHK(chain(ctx, k.dtype, k.n, k.c, w, djobs + k.first, cnt, k.tw));
+    }
+    for (auto& k : ks) {
+      const int cnt = (int)k.members.size();
+      const int dt = k.dtype == WF_F64;
+      {
+        Timed t(ctx, KK_POST);
+        HIPCHK(lbfgs_launch(dt, m, LB_POST, dim3(cnt), ddesc + k.first, dst + k.first, djobs + k.first, cnt, ctx->cs));
+      }
+      {
+        Timed t(ctx, KK_PASSA);
+        HIPCHK(lbfgs_launch(dt, m, LB_PASSA, dim3(k.nblkA, cnt), ddesc + k.first, dst + k.first, djobs + k.first, cnt,
+                            ctx->cs));
+      }
+      {
+        Timed t(ctx, KK_COEF);
+        HIPCHK(lbfgs_launch(dt, m, LB_COEF, dim3(cnt), ddesc + k.first, dst + k.first, djobs + k.first, cnt, ctx->cs));
+      }
+      {
+        Timed t(ctx, KK_PASSB);
+        HIPCHK(lbfgs_launch(dt, m, LB_PASSB, dim3(k.nblkB, cnt), ddesc + k.first, dst + k.first, djobs + k.first, cnt,
+                            ctx->cs));
+      }
+    }
+    return WF_OK;
+  };
+  rc = host_status(ctx, B);
+  if (rc) return rc;
+  int K = o.iters_per_poll > 0 ? o.iters_per_poll : (B > 1 ? 8 : 1);
+  const bool graph = o.use_graph != 0 && !ctx->prof && K > 0;
+  std::string key;
+  if (graph) {
+    char buf[128];
+    snprintf(buf, sizeof buf, "%p/%d/%d/%d/%d|", (void*)A.base, A.gen, B, m, K);
+    key = buf;
+    for (auto& k : ks) key += std::to_string(k.n) + "," + std::to_string(k.c) + "," + std::to_string(k.dtype) + "," +
+                              std::to_string(k.members.size()) + ";";
+    if (key != ctx->gkey) {
+      if (ctx->gexec) (void)hipGraphExecDestroy(ctx->gexec);
+      ctx->gexec = nullptr;
+      ctx->gkey.clear();
+      hipGraph_t g = nullptr;
+      HIPCHK(hipStreamBeginCapture(ctx->cs, hipStreamCaptureModeRelaxed));
+      int brc = WF_OK;
+      int64_t saved[KK_COUNT];
+      std::memcpy(saved, ctx->launches, sizeof saved);
+      for (int r = 0; r < K && brc == WF_OK; ++r) brc = body();
+      std::memcpy(ctx->launches, saved, sizeof saved);
+      hipError_t e = hipStreamEndCapture(ctx->cs, &g);
+      if (brc) return brc;
+      if (e != hipSuccess) return fail(ctx, WF_EHIP, std::string("graph capture: ") + hipGetErrorString(e));
+      e = hipGraphInstantiate(&ctx->gexec, g, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(g);
+      if (e != hipSuccess) return fail(ctx, WF_EHIP, std::string("graph instantiate: ") + hipGetErrorString(e));
+      ctx->gkey = key;
+    }
+  }
+  const int64_t maxBodies = 2LL * o.max_iter + 64;
+  int64_t bodies = 0;
+  while (true) {
+    if (graph) {
+      HIPCHK(hipGraphLaunch(ctx->gexec, ctx->cs));
+      // count launches as if enqueued one by one
+      for (auto& k : ks) {
+        (void)k;
+        ctx->launches[KK_COLINV] += K;
+        ctx->launches[KK_ROW] += K;
+        ctx->launches[KK_COLFWD] += K;
+        ctx->launches[KK_POST] += K;
+        ctx->launches[KK_PASSA] += K;
+        ctx->launches[KK_COEF] += K;
+        ctx->launches[KK_PASSB] += K;
+      }
+    } else {
+      for (int r = 0; r < K; ++r) {
+        rc = body();
+        if (rc) return rc;
+      }
+    }
+    bodies += K;
+    HIPCHK(hipMemcpyAsync(ctx->hstat, dstat, sizeof(int) * B, hipMemcpyDeviceToHost, ctx->cs));
+    HIPCHK(hipStreamSynchronize(ctx->cs));
+    rc = drain_events(ctx);
+    if (rc) return rc;
+    int running = 0;
+    for (int i = 0; i < B; ++i) running += (ctx->hstat[i] == ST_RUNNING);
+    if (running == 0 || bodies >= maxBodies) break;
+  }
+  std::vector<LbState> hs(B);
+  HIPCHK(hipMemcpyAsync(hs.data(), dst, sizeof(LbState) * B, hipMemcpyDeviceToHost, ctx->cs));
+  HIPCHK(hipStreamSynchronize(ctx->cs));
+  out.st.assign(B, LbState());
+  for (int ui = 0; ui < B; ++ui) {
+    out.st[ui] = hs[out.order[ui]];
+    if (out.st[ui].status == ST_RUNNING) out.st[ui].status = WF_SOLVE_MAXITER;
+    for (int k = 0; k < KK_COUNT; ++k) ctx->bytes[k] += hs[out.order[ui]].bytes[k];
+  }
+  return WF_OK;
+}
+
+void fill_stats(const SolveOut& so, int B, wf_solve_stats* stats) {
+  if (!stats) return;
+  for (int i = 0; i < B; ++i) {
+    const LbState& S = so.st[i];
+    stats[i].iters = S.iter;
+    stats[i].status = S.status;
+    stats[i].ngrad = S.ngrad;
+    stats[i].reserved = 0;
+    stats[i].chi2 = S.chi2;
+    stats[i].rel_grad = S.g0norm > 0 ? std::sqrt(S.gg) / S.g0norm : 0.0;
+  }
+}
+
+// forward map of solved fields into caller buffers (mode CM_FWD on the whitened w)
+int maps_from_solution(wf_ctx* ctx, const wf_problem* probs, int B, const SolveOut& so, void* const* map_out) {
+  if (!map_out) return WF_OK;
+  std::map<std::tuple<int, int, int>, std::vector<int>> cls;
+  for (int i = 0; i < B; ++i)
+    if (map_out[i]) cls[std::make_tuple(probs[i].n, probs[i].ncomp, probs[i].dtype)].push_back(i);
+  for (auto& kv : cls) {
+    const int n = std::get<0>(kv.first), c = std::get<1>(kv.first), dt = std::get<2>(kv.first);
+    const auto& mem = kv.second;
+    std::vector<Job> hj(mem.size());
+    for (size_t j = 0; j < mem.size(); ++j) {
+      Job& jb = hj[j];
+      std::memset(&jb, 0, sizeof jb);
+      jb.mode = CM_FWD;
+      jb.boost_band = -1;
+      jb.vin = so.w[mem[j]];
+      jb.y = so.y[mem[j]];
+      jb.sIn = so.prior[mem[j]].sq;
+      jb.xout = map_out[mem[j]];
+    }
+    int rc = arena_reserve(ctx, ctx->opA, align_up(sizeof(Job) * mem.size()));
+    if (rc) return rc;
+    Job* dj = (Job*)arena_take(ctx->opA, sizeof(Job) * mem.size());
+    HIPCHK(hipMemcpyAsync(dj, hj.data(), sizeof(Job) * mem.size(), hipMemcpyHostToDevice, ctx->cs));
+    const void* tw = nullptr;
+    rc = twiddles(ctx, n, dt, &tw);
+    if (rc) return rc;
+    HIPCHK(chain(ctx, dt, n, c, CH_COLINV, dj, (int)mem.size(), tw));
+    HIPCHK(chain(ctx, dt, n, c, CH_ROW, dj, (int)mem.size(), tw));
+    HIPCHK(hipStreamSynchronize(ctx->cs));   // the job array is reused by the next group
+  }
+  return WF_OK;
+}
+
+// ---------------------------------------------------------------------------- small dense solve
+// Gaussian elimination with partial pivoting, float64 (A is n x n row-major, overwritten).
+bool dense_solve(std::vector<double> A, std::vector<double>& x, int n) {
+  for (int k = 0; k < n; ++k) {
+    int piv = k;
+    for (int r = k + 1; r < n; ++r)
+      if (std::fabs(A[(size_t)r * n + k]) > std::fabs(A[(size_t)piv * n + k])) piv = r;
+    if (!(std::fabs(A[(size_t)piv * n + k]) > 0)) return false;
+    if (piv != k) {
+      for (int cc = 0; cc < n; ++cc) std::swap(A[(size_t)k * n + cc], A[(size_t)piv * n + cc]);
+      std::swap(x[k], x[piv]);
+    }
+    for (int r = k + 1; r < n; ++r) {
+      const double f = A[(size_t)r * n + k] / A[(size_t)k * n + k];
+      for (int cc = k; cc < n; ++cc) A[(size_t)r * n + cc] -= f * A[(size_t)k * n + cc];
+      x[r] -= f * x[k];
+    }
+  }
+  for (int k = n - 1; k >= 0; --k) {
+    double s = x[k];
+    for (int cc = k + 1; cc < n; ++cc) s -= A[(size_t)k * n + cc] * x[cc];
+    x[k] = s / A[(size_t)k * n + k];
+  }
+  return true;
+}
+
+// ---------------------------------------------------------------------------- band powers
+// E of the solved (whitened) fields, HOST [B][nbands]
+int band_E_solved(wf_ctx* ctx, const wf_problem* probs, int B, const SolveOut& so, std::vector<double>& E) {
+  const int nb = probs[0].nbands;
+  E.assign((size_t)B * nb, 0.0);
+  if (nb == 0 || B == 0) return WF_OK;
+  const int64_t L = (int64_t)probs[0].ncomp * probs[0].n * (probs[0].n / 2);
+  const int nblk = band_nblk(L);
+  const size_t need = align_up(sizeof(BandJob) * B) + align_up(sizeof(double) * (size_t)B * nblk * nb) +
+                      align_up(sizeof(double) * (size_t)B * nb);
+  int rc = arena_reserve(ctx, ctx->opA, need);
+  if (rc) return rc;
+  BandJob* dj = (BandJob*)arena_take(ctx->opA, sizeof(BandJob) * B);
+  double* part = (double*)arena_take(ctx->opA, sizeof(double) * (size_t)B * nblk * nb);
+  double* dE = (double*)arena_take(ctx->opA, sizeof(double) * (size_t)B * nb);
+  std::vector<BandJob> hj(B);
+  for (int i = 0; i < B; ++i) {
+    hj[i].f = so.w[i];
+    hj[i].sq = so.prior[i].sq;
+    hj[i].bandI = so.prior[i].bandI;
+    hj[i].theta = so.prior[i].theta;
+    hj[i].part = part + (size_t)i * nblk * nb;
+    hj[i].E = dE + (size_t)i * nb;
+    hj[i].L = L;
+    hj[i].nbands = nb;
+    hj[i].raw = 0;
+  }
+  HIPCHK(hipMemcpyAsync(dj, hj.data(), sizeof(BandJob) * B, hipMemcpyHostToDevice, ctx->cs));
+  {
+    Timed t(ctx, KK_MISC);
+    HIPCHK(band_launch(probs[0].dtype, dj, B, L, ctx->cs));
+  }
+  HIPCHK(hipMemcpyAsync(E.data(), dE, sizeof(double) * (size_t)B * nb, hipMemcpyDeviceToHost, ctx->cs));
+  HIPCHK(hipStreamSynchronize(ctx->cs));
+  return WF_OK;
+}
+
+struct SimEntry {
+  int kind;   // 0 data, 1 fiducial simulation, 2 boosted simulation
+  int sim;
+  int band;
+};
+
+// Simulate the data of a list of simulation entries into dbuf (d of entry j at dbuf + j * c n^2).
+// `draws` (nullable) holds the normals of simulation simBase at its start.
+int simulate_entries(wf_ctx* ctx, const wf_problem* p, const std::vector<SimEntry>& ents, uint64_t seed,
+                     const void* draws, int simBase, const PriorTab& ptrue, void* dbuf, void* ybuf,
+                     double boost_factor) {
+  const int n = p->n, c = p->ncomp, dt = p->dtype;
+  const size_t rs = rsize_of(dt), eb = esize_of(dt);
+  const int64_t L = (int64_t)c * n * (n / 2);
+  const int64_t npix = (int64_t)c * n * n;
+  std::vector<Job> hj;
+  std::vector<int> slot;
+  for (size_t j = 0; j < ents.size(); ++j) {
+    if (ents[j].kind == 0) continue;
+    Job jb;
+    std::memset(&jb, 0, sizeof jb);
+    jb.mode = CM_SIM;
+    jb.boost_band = ents[j].kind == 2 ? ents[j].band : -1;
+    jb.boost_factor = std::sqrt(boost_factor);
+    jb.sim = ents[j].sim;
+    jb.seed = seed;
+    jb.y = (char*)ybuf + (size_t)hj.size() * L * eb;
+    jb.W = p->w;
+    jb.sIn = ptrue.sq;
+    jb.band = ptrue.bandI;
+    jb.draws = draws ? (const char*)draws + (size_t)(ents[j].sim - simBase) * 2 * npix * rs : nullptr;
+    jb.xout = (char*)dbuf + j * npix * rs;
+    hj.push_back(jb);
+  }
+  if (hj.empty()) return WF_OK;
+  Job* dj = (Job*)arena_take(ctx->simA, sizeof(Job) * hj.size());
+  HIPCHK(hipMemcpyAsync(dj, hj.data(), sizeof(Job) * hj.size(), hipMemcpyHostToDevice, ctx->cs));
+  const void* tw = nullptr;
+  int rc = twiddles(ctx, n, dt, &tw);
+  if (rc) return rc;
+  rc = prepare(ctx, n, c, dt);
+  if (rc) return rc;
+  HIPCHK(chain(ctx, dt, n, c, CH_COLINV, dj, (int)hj.size(), tw));
+  HIPCHK(chain(ctx, dt, n, c, CH_ROW, dj, (int)hj.size(), tw));
+  return WF_OK;
+}
+
+// The quadratic estimator's solves (sec. 2.3-2.4): optional data map, nsim fiducial
+// simulations and nsim * nbands boosted ones, in chunks of one batched solve each.
+int run_qe(wf_ctx* ctx, const wf_problem* p, bool with_data, int nsim, uint64_t seed, const void* draws,
+           const wf_lbfgs_opts& o, std::vector<double>& Edata, std::vector<double>& E0, std::vector<double>& E2,
+           int& notConverged) {
+  const int nb = p->nbands;
+  const int n = p->n, c = p->ncomp, dt = p->dtype;
+  std::vector<SimEntry> all;
+  if (with_data) all.push_back({0, 0, -1});
+  for (int i = 0; i < nsim; ++i) {
+    all.push_back({1, i, -1});
+    for (int l = 0; l < nb; ++l) all.push_back({2, i, l});
+  }
+  Edata.assign(nb, 0.0);
+  E0.assign((size_t)nsim * nb, 0.0);
+  E2.assign((size_t)nsim * nb * nb, 0.0);
+  notConverged = 0;
+  const size_t rs = rsize_of(dt), eb = esize_of(dt);
+  const int64_t L = (int64_t)c * n * (n / 2);
+  const int64_t npix = (int64_t)c * n * n;
+  const double perInst = (double)(3 + 2 * o.m) * L * eb + (double)npix * rs + (double)L * eb;
+  int chunk = (int)std::max(1.0, std::min((double)kMaxChunk, kSimBudgetBytes / perInst));
+  for (size_t off = 0; off < all.size(); off += chunk) {
+    const size_t cnt = std::min(all.size() - off, (size_t)chunk);
+    std::vector<SimEntry> ents(all.begin() + off, all.begin() + off + cnt);
+    const size_t need = prior_bytes(p) + align_up(sizeof(Job) * cnt) + align_up((size_t)npix * rs * cnt) +
+                        align_up((size_t)L * eb * cnt);
+    int rc = arena_reserve(ctx, ctx->simA, need);
+    if (rc) return rc;
+    PriorTab ptrue;
+    rc = build_prior(ctx, ctx->simA, p, p->theta, ptrue);
+    if (rc) return rc;
+    void* dbuf = arena_take(ctx->simA, (size_t)npix * rs * cnt);
+    void* ybuf = arena_take(ctx->simA, (size_t)L * eb * cnt);
+    rc = simulate_entries(ctx, p, ents, seed, draws, 0, ptrue, dbuf, ybuf, 2.0);
+    if (rc) return rc;
+    std::vector<wf_problem> probs(cnt, *p);
+    for (size_t j = 0; j < cnt; ++j)
+      if (ents[j].kind != 0) probs[j].d = (const char*)dbuf + j * npix * rs;
+    SolveOut so;
+    rc = solve_core(ctx, probs.data(), (int)cnt, o, so);
+    if (rc) return rc;
+    for (size_t j = 0; j < cnt; ++j) notConverged += so.st[j].status != WF_SOLVE_CONVERGED;
+    std::vector<double> E;
+    rc = band_E_solved(ctx, probs.data(), (int)cnt, so, E);
+    if (rc) return rc;
+    for (size_t j = 0; j < cnt; ++j) {
+      const double* e = &E[j * nb];
+      if (ents[j].kind == 0)
+        std::copy(e, e + nb, Edata.begin());
+      else if (ents[j].kind == 1)
+        std::copy(e, e + nb, E0.begin() + (size_t)ents[j].sim * nb);
+      else
+        for (int l = 0; l < nb; ++l) E2[((size_t)ents[j].sim * nb + ents[j].band) * nb + l] = e[l];
+    }
+  }
+  return WF_OK;
+}
+
+void bias_fisher(const double* theta, int nsim, int nb, const std::vector<double>& E0, const std::vector<double>& E2,
+                 double* b, double* F) {
+  for (int l = 0; l < nb; ++l) {
+    double s = 0.0;
+    for (int i = 0; i < nsim; ++i) s += E0[(size_t)i * nb + l];
+    b[l] = nsim > 0 ? s / nsim : 0.0;
+  }
+  std::vector<double> Fr((size_t)nb * nb, 0.0);
+  for (int l = 0; l < nb; ++l)          // row of E
+    for (int l2 = 0; l2 < nb; ++l2) {   // boosted band
+      double s = 0.0;
+      for (int i = 0; i < nsim; ++i) s += E2[((size_t)i * nb + l2) * nb + l] - E0[(size_t)i * nb + l];
+      Fr[(size_t)l * nb + l2] = nsim > 0 ? s / nsim / theta[l2] : 0.0;
+    }
+  for (int l = 0; l < nb; ++l)
+    for (int l2 = 0; l2 < nb; ++l2) F[(size_t)l * nb + l2] = 0.5 * (Fr[(size_t)l * nb + l2] + Fr[(size_t)l2 * nb + l]);
+}
+
+// ---------------------------------------------------------------------------- operator jobs
+int op_setup(wf_ctx* ctx, const wf_problem* p, int batch, size_t extra, PriorTab* pt, void** vin, void** vy,
+             void** vout, Job** dj, double** part, const void** tw) {
+  const int n = p->n, c = p->ncomp, dt = p->dtype;
+  const int64_t L = (int64_t)c * n * (n / 2);
+  const size_t eb = esize_of(dt);
+  const int pstride = n / RB;
+  const size_t need = prior_bytes(p) + 3 * align_up((size_t)L * eb * batch) + align_up(sizeof(Job) * batch) +
+                      align_up(sizeof(double) * PK_COUNT * pstride * batch) + extra;
+  int rc = arena_reserve(ctx, ctx->opA, need);
+  if (rc) return rc;
+  if (pt) {
+    rc = build_prior(ctx, ctx->opA, p, p->theta, *pt);
+    if (rc) return rc;
+  } else {
+    arena_take(ctx->opA, prior_bytes(p));
+  }
+  *vin = arena_take(ctx->opA, (size_t)L * eb * batch);
+  *vy = arena_take(ctx->opA, (size_t)L * eb * batch);
+  *vout = arena_take(ctx->opA, (size_t)L * eb * batch);
+  *dj = (Job*)arena_take(ctx->opA, sizeof(Job) * batch);
+  *part = (double*)arena_take(ctx->opA, sizeof(double) * PK_COUNT * pstride * batch);
+  rc = twiddles(ctx, n, dt, tw);
+  if (rc) return rc;
+  return prepare(ctx, n, c, dt);
+}
+
+int check_op(wf_ctx* ctx, const wf_problem* p, int batch, const void* a, const void* b) {
+  if (!ctx) return WF_EINVAL;
+  if (!p) return fail(ctx, WF_EINVAL, "null problem");
+  if (!chain_supported(p->n)) return fail(ctx, WF_EINVAL, "unsupported n=" + std::to_string(p->n));
+  if (p->ncomp != 1 && p->ncomp != 2) return fail(ctx, WF_EINVAL, "ncomp must be 1 or 2");
+  if (p->dtype != WF_F32 && p->dtype != WF_F64) return fail(ctx, WF_EINVAL, "bad dtype");
+  if (batch < 0 || batch > 65535) return fail(ctx, WF_EINVAL, "batch out of range");
+  if (batch > 0 && (!a || !b)) return fail(ctx, WF_EINVAL, "null array");
+  return WF_OK;
+}
+
+}  // namespace
+
+// ============================================================================ C-ABI
+extern "C" {
+
+void wf_lbfgs_default(wf_lbfgs_opts* o) {
+  if (!o) return;
+  o->m = 10;
+  o->max_iter = 20000;
+  o->rel_grad_tol = 1e-6;
+  o->dchi2_tol = 0.0;
+  o->refresh_every = 0;
+  o->iters_per_poll = 0;
+  o->use_graph = 1;
+  o->reserved = 0;
+}
+
+int wf_create(wf_ctx** out, int hip_device) {
+  if (!out) return WF_EINVAL;
+  *out = nullptr;
+  wf_ctx* c = new (std::nothrow) wf_ctx();
+  if (!c) return WF_ENOMEM;
+  c->dev = hip_device;
+  if (hipSetDevice(hip_device) != hipSuccess || hipStreamCreateWithFlags(&c->cs, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&c->evIn, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&c->evOut, hipEventDisableTiming) != hipSuccess) {
+    (void)hipGetLastError();
+    delete c;
+    return WF_EHIP;
+  }
+  *out = c;
+  return WF_OK;
+}
+
+void wf_destroy(wf_ctx* c) {
+  if (!c) return;
+  (void)hipSetDevice(c->dev);
+  if (c->cs) (void)hipStreamSynchronize(c->cs);
+  if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+  for (auto& kv : c->tw) (void)hipFree(kv.second);
+  for (Arena* a : {&c->solveA, &c->simA, &c->opA})
+    if (a->base) (void)hipFree(a->base);
+  if (c->hstat) (void)hipHostFree(c->hstat);
+  for (auto& pe : c->pendingEv) {
+    (void)hipEventDestroy(pe.second.first);
+    (void)hipEventDestroy(pe.second.second);
+  }
+  for (auto e : c->evPool) (void)hipEventDestroy(e);
+  if (c->evIn) (void)hipEventDestroy(c->evIn);
+  if (c->evOut) (void)hipEventDestroy(c->evOut);
+  if (c->cs) (void)hipStreamDestroy(c->cs);
+  delete c;
+}
+
+const char* wf_last_error(const wf_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+int map_wf_solve(wf_ctx* ctx, const wf_problem* probs, int32_t batch, const wf_lbfgs_opts* opts, void* const* s_out,
+                 void* const* map_out, wf_solve_stats* stats, void* stream) {
+  if (!ctx) return WF_EINVAL;
+  if (batch < 0 || batch > 65535 || (batch > 0 && (!probs || !s_out)))
+    return fail(ctx, WF_EINVAL, "bad batch / null arrays");
+  if (batch == 0) return WF_OK;
+  for (int i = 0; i < batch; ++i)
+    if (!s_out[i]) return fail(ctx, WF_EINVAL, "null s_out entry");
+  wf_lbfgs_opts o;
+  fill_opts(opts, o);
+  StreamScope ss(ctx, stream);
+  SolveOut so;
+  int rc = solve_core(ctx, probs, batch, o, so);
+  if (rc) return rc;
+  // s = sqrt(S) w with partners filled, into the caller's buffers
+  for (int i = 0; i < batch; ++i) {
+    const wf_problem* p = &probs[i];
+    HIPCHK(pack_launch(p->dtype, p->n, p->ncomp, 1, so.w[i], 0, so.prior[i].sq, 1, nullptr, s_out[i], ctx->cs));
+  }
+  rc = maps_from_solution(ctx, probs, batch, so, map_out);
+  if (rc) return rc;
+  HIPCHK(hipStreamSynchronize(ctx->cs));
+  fill_stats(so, batch, stats);
+  for (int i = 0; i < batch; ++i)
+    if (so.st[i].status != WF_SOLVE_CONVERGED) return WF_NOT_CONVERGED;
+  return WF_OK;
+}
+
+int wf_simulate(wf_ctx* ctx, const wf_problem* p, int32_t nsim, uint64_t seed, int32_t sim0, const void* draws,
+                const double* theta_true, int32_t boost_band, double boost_factor, void* d_out, void* stream) {
+  if (!ctx) return WF_EINVAL;
+  int rc = check_problem(ctx, p, false);
+  if (rc) return rc;
+  if (nsim < 0 || nsim > 65535 || (nsim > 0 && !d_out)) return fail(ctx, WF_EINVAL, "bad nsim / null d_out");
+  if (!(boost_factor > 0)) return fail(ctx, WF_EINVAL, "boost_factor must be > 0");
+  if (nsim == 0) return WF_OK;
+  StreamScope ss(ctx, stream);
+  const int n = p->n, c = p->ncomp, dt = p->dtype;
+  const int64_t L = (int64_t)c * n * (n / 2);
+  const size_t eb = esize_of(dt), rs = rsize_of(dt);
+  const size_t need = prior_bytes(p) + align_up(sizeof(Job) * nsim) + align_up((size_t)L * eb * nsim);
+  rc = arena_reserve(ctx, ctx->simA, need);
+  if (rc) return rc;
+  PriorTab pt;
+  rc = build_prior(ctx, ctx->simA, p, theta_true ? theta_true : p->theta, pt);
+  if (rc) return rc;
+  void* ybuf = arena_take(ctx->simA, (size_t)L * eb * nsim);
+  std::vector<SimEntry> ents;
+  for (int i = 0; i < nsim; ++i) ents.push_back({boost_band >= 0 ? 2 : 1, sim0 + i, boost_band});
+  rc = simulate_entries(ctx, p, ents, seed, draws, sim0, pt, d_out, ybuf, boost_factor);
+  if (rc) return rc;
+  return WF_OK;
+}
+
+int sim_fisher(wf_ctx* ctx, const wf_problem* p, int32_t nsim, uint64_t seed, const void* draws,
+               const wf_lbfgs_opts* opts, double* F, double* b, double* E_sims, void* stream) {
+  if (!ctx) return WF_EINVAL;
+  int rc = check_problem(ctx, p, false);
+  if (rc) return rc;
+  if (nsim < 1 || !F || !b) return fail(ctx, WF_EINVAL, "need nsim >= 1 and F, b");
+  for (int l = 0; l < p->nbands; ++l)
+    if (!(p->theta[l] > 0)) return fail(ctx, WF_EINVAL, "fiducial band amplitudes must be > 0");
+  wf_lbfgs_opts o;
+  fill_opts(opts, o);
+  StreamScope ss(ctx, stream);
+  std::vector<double> Ed, E0, E2;
+  int nc = 0;
+  rc = run_qe(ctx, p, false, nsim, seed, draws, o, Ed, E0, E2, nc);
+  if (rc) return rc;
+  bias_fisher(p->theta, nsim, p->nbands, E0, E2, b, F);
+  if (E_sims) std::copy(E0.begin(), E0.end(), E_sims);
+  return nc ? WF_NOT_CONVERGED : WF_OK;
+}
+
+int bandpower_qe(wf_ctx* ctx, const wf_problem* p, int32_t nsim, uint64_t seed, const void* draws,
+                 const wf_lbfgs_opts* opts, double* theta_hat, double* E, double* b, double* F, void* stream) {
+  if (!ctx) return WF_EINVAL;
+  int rc = check_problem(ctx, p, true);
+  if (rc) return rc;
+  if (nsim < 1 || !theta_hat) return fail(ctx, WF_EINVAL, "need nsim >= 1 and theta_hat");
+  for (int l = 0; l < p->nbands; ++l)
+    if (!(p->theta[l] > 0)) return fail(ctx, WF_EINVAL, "fiducial band amplitudes must be > 0");
+  wf_lbfgs_opts o;
+  fill_opts(opts, o);
+  StreamScope ss(ctx, stream);
+  const int nb = p->nbands;
+  std::vector<double> Ed, E0, E2;
+  int nc = 0;
+  rc = run_qe(ctx, p, true, nsim, seed, draws, o, Ed, E0, E2, nc);
+  if (rc) return rc;
+  std::vector<double> hb(nb), hF((size_t)nb * nb);
+  bias_fisher(p->theta, nsim, nb, E0, E2, hb.data(), hF.data());
+  std::vector<double> x(nb);
+  for (int l = 0; l < nb; ++l) x[l] = Ed[l] - hb[l];
+  if (!dense_solve(hF, x, nb)) return fail(ctx, WF_ENONFINITE, "singular Fisher matrix");
+  for (int l = 0; l < nb; ++l) theta_hat[l] = p->theta[l] + x[l];
+  if (E) std::copy(Ed.begin(), Ed.end(), E);
+  if (b) std::copy(hb.begin(), hb.end(), b);
+  if (F) std::copy(hF.begin(), hF.end(), F);
+  return nc ? WF_NOT_CONVERGED : WF_OK;
+}
+
+int wf_forward(wf_ctx* ctx, const wf_problem* p, int32_t batch, const void* s, void* x, void* stream) {
+  int rc = check_op(ctx, p, batch, s, x);
+  if (rc || batch == 0) return rc;
+  StreamScope ss(ctx, stream);
+  void *vin, *vy, *vout;
+  Job* dj;
+  double* part;
+  const void* tw;
+  rc = op_setup(ctx, p, batch, 0, nullptr, &vin, &vy, &vout, &dj, &part, &tw);
+  if (rc) return rc;
+  const int n = p->n, c = p->ncomp, dt = p->dtype;
+  const int64_t L = (int64_t)c * n * (n / 2);
+  const size_t eb = esize_of(dt), rs = rsize_of(dt);
+  HIPCHK(unpack_launch(dt, n, c, batch, s, vin, ctx->cs));
+  std::vector<Job> hj(batch);
+  for (int i = 0; i < batch; ++i) {
+    std::memset(&hj[i], 0, sizeof(Job));
+    hj[i].mode = CM_FWD;
+    hj[i].boost_band = -1;
+    hj[i].vin = (char*)vin + (size_t)i * L * eb;
+    hj[i].y = (char*)vy + (size_t)i * L * eb;
+    hj[i].xout = (char*)x + (size_t)i * c * n * n * rs;
+  }
+  HIPCHK(hipMemcpyAsync(dj, hj.data(), sizeof(Job) * batch, hipMemcpyHostToDevice, ctx->cs));
+  HIPCHK(chain(ctx, dt, n, c, CH_COLINV, dj, batch, tw));
+  HIPCHK(chain(ctx, dt, n, c, CH_ROW, dj, batch, tw));
+  HIPCHK(hipStreamSynchronize(ctx->cs));
+  return WF_OK;
+}
+
+int wf_adjoint(wf_ctx* ctx, const wf_problem* p, int32_t batch, const void* x, void* s, int32_t flags, void* stream) {
+  int rc = check_op(ctx, p, batch, x, s);
+  if (rc || batch == 0) return rc;
+  if (flags != WF_ADJ_METRIC && flags != WF_ADJ_GRAD) return fail(ctx, WF_EINVAL, "bad flags");
+  StreamScope ss(ctx, stream);
+  void *vin, *vy, *vout;
+  Job* dj;
+  double* part;
+  const void* tw;
+  rc = op_setup(ctx, p, batch, 0, nullptr, &vin, &vy, &vout, &dj, &part, &tw);
+  if (rc) return rc;
+  const int n = p->n, c = p->ncomp, dt = p->dtype;
+  const int64_t L = (int64_t)c * n * (n / 2);
+  const size_t eb = esize_of(dt), rs = rsize_of(dt);
+  std::vector<Job> hj(batch);
+  for (int i = 0; i < batch; ++i) {
+    std::memset(&hj[i], 0, sizeof(Job));
+    hj[i].mode = flags == WF_ADJ_GRAD ? CM_ADJ_GRAD : CM_ADJ;
+    hj[i].boost_band = -1;
+    hj[i].d = (const char*)x + (size_t)i * c * n * n * rs;
+    hj[i].y = (char*)vy + (size_t)i * L * eb;
+    hj[i].vout = (char*)vout + (size_t)i * L * eb;
+  }
+  HIPCHK(hipMemcpyAsync(dj, hj.data(), sizeof(Job) * batch, hipMemcpyHostToDevice, ctx->cs));
+  HIPCHK(chain(ctx, dt, n, c, CH_ROW, dj, batch, tw));
+  HIPCHK(chain(ctx, dt, n, c, CH_COLFWD, dj, batch, tw));
+  HIPCHK(pack_launch(dt, n, c, batch, vout, L, nullptr, 0, nullptr, s, ctx->cs));
+  HIPCHK(hipStreamSynchronize(ctx->cs));
+  return WF_OK;
+}
+
+static int raw_chain(wf_ctx* ctx, const wf_problem* p, int batch, const void* s, double* chi2, void* out, int mode,
+                     void* stream) {
+  StreamScope ss(ctx, stream);
+  void *vin, *vy, *vout;
+  Job* dj;
+  double* part;
+  const void* tw;
+  PriorTab pt;
+  int rc = op_setup(ctx, p, batch, 0, &pt, &vin, &vy, &vout, &dj, &part, &tw);
+  if (rc) return rc;
+  const int n = p->n, c = p->ncomp, dt = p->dtype;
+  const int64_t L = (int64_t)c * n * (n / 2);
+  const size_t eb = esize_of(dt);
+  const int pstride = n / RB;
+  HIPCHK(unpack_launch(dt, n, c, batch, s, vin, ctx->cs));
+  std::vector<Job> hj(batch);
+  for (int i = 0; i < batch; ++i) {
+    std::memset(&hj[i], 0, sizeof(Job));
+    hj[i].mode = mode;
+    hj[i].boost_band = -1;
+    hj[i].vin = (char*)vin + (size_t)i * L * eb;
+    hj[i].vadd = hj[i].vin;
+    hj[i].y = (char*)vy + (size_t)i * L * eb;
+    hj[i].vout = (char*)vout + (size_t)i * L * eb;
+    hj[i].d = p->d;
+    hj[i].W = p->w;
+    hj[i].sOut = pt.sq;
+    hj[i].part = part + (size_t)i * PK_COUNT * pstride;
+    hj[i].pstride = pstride;
+  }
+  HIPCHK(hipMemcpyAsync(dj, hj.data(), sizeof(Job) * batch, hipMemcpyHostToDevice, ctx->cs));
+  for (int w = 0; w < 3; ++w) HIPCHK(chain(ctx, dt, n, c, w, dj, batch, tw));
+  if (out) HIPCHK(pack_launch(dt, n, c, batch, vout, L, nullptr, 0, nullptr, out, ctx->cs));
+  if (chi2) {
+    std::vector<double> hp((size_t)PK_COUNT * pstride * batch);
+    HIPCHK(hipMemcpyAsync(hp.data(), part, sizeof(double) * hp.size(), hipMemcpyDeviceToHost, ctx->cs));
+    HIPCHK(hipStreamSynchronize(ctx->cs));
+    const int ncol = (n / 2) / TB, nrow = n / RB;
+    for (int i = 0; i < batch; ++i) {
+      const double* q = &hp[(size_t)i * PK_COUNT * pstride];
+      double pr = 0.0, rs = 0.0;
+      for (int b = 0; b < ncol; ++b) pr += q[PK_PRIOR * pstride + b];
+      for (int b = 0; b < nrow; ++b) rs += q[PK_RES * pstride + b];
+      chi2[i] = 2.0 * pr + rs;
+    }
+  }
+  HIPCHK(hipStreamSynchronize(ctx->cs));
+  return WF_OK;
+}
+
+int wf_chi2_grad(wf_ctx* ctx, const wf_problem* p, int32_t batch, const void* s, double* chi2, void* grad_s,
+                 void* stream) {
+  int rc = check_op(ctx, p, batch, s, chi2);
+  if (rc || batch == 0) return rc;
+  rc = check_problem(ctx, p, true);
+  if (rc) return rc;
+  return raw_chain(ctx, p, batch, s, chi2, grad_s, CM_RAW_GRAD, stream);
+}
+
+int wf_hvp(wf_ctx* ctx, const wf_problem* p, int32_t batch, const void* pv, void* Dp, void* stream) {
+  int rc = check_op(ctx, p, batch, pv, Dp);
+  if (rc || batch == 0) return rc;
+  rc = check_problem(ctx, p, false);
+  if (rc) return rc;
+  return raw_chain(ctx, p, batch, pv, nullptr, Dp, CM_RAW_HV, stream);
+}
+
+int wf_band_E(wf_ctx* ctx, const wf_problem* p, int32_t batch, const void* s, double* E, void* stream) {
+  int rc = check_op(ctx, p, batch, s, E);
+  if (rc || batch == 0) return rc;
+  rc = check_problem(ctx, p, false);
+  if (rc) return rc;
+  const int nb = p->nbands;
+  if (nb == 0) return WF_OK;
+  StreamScope ss(ctx, stream);
+  const int n = p->n, c = p->ncomp, dt = p->dtype;
+  const int64_t L = (int64_t)c * n * (n / 2);
+  const size_t eb = esize_of(dt);
+  const int nblk = band_nblk(L);
+  const size_t extra = align_up(sizeof(BandJob) * batch) + align_up(sizeof(double) * (size_t)batch * nblk * nb) +
+                       align_up(sizeof(double) * (size_t)batch * nb);
+  void *vin, *vy, *vout;
+  Job* dj;
+  double* part;
+  const void* tw;
+  PriorTab pt;
+  rc = op_setup(ctx, p, batch, extra, &pt, &vin, &vy, &vout, &dj, &part, &tw);
+  if (rc) return rc;
+  HIPCHK(unpack_launch(dt, n, c, batch, s, vin, ctx->cs));
+  BandJob* bj = (BandJob*)arena_take(ctx->opA, sizeof(BandJob) * batch);
+  double* bpart = (double*)arena_take(ctx->opA, sizeof(double) * (size_t)batch * nblk * nb);
+  double* dE = (double*)arena_take(ctx->opA, sizeof(double) * (size_t)batch * nb);
+  std::vector<BandJob> hj(batch);
+  for (int i = 0; i < batch; ++i) {
+    hj[i].f = (char*)vin + (size_t)i * L * eb;
+    hj[i].sq = pt.sq;
+    hj[i].bandI = pt.bandI;
+    hj[i].theta = pt.theta;
+    hj[i].part = bpart + (size_t)i * nblk * nb;
+    hj[i].E = dE + (size_t)i * nb;
+    hj[i].L = L;
+    hj[i].nbands = nb;
+    hj[i].raw = 1;
+  }
+  HIPCHK(hipMemcpyAsync(bj, hj.data(), sizeof(BandJob) * batch, hipMemcpyHostToDevice, ctx->cs));
+  HIPCHK(band_launch(dt, bj, batch, L, ctx->cs));
+  HIPCHK(hipMemcpyAsync(E, dE, sizeof(double) * (size_t)batch * nb, hipMemcpyDeviceToHost, ctx->cs));
+  HIPCHK(hipStreamSynchronize(ctx->cs));
+  return WF_OK;
+}
+
+int wf_set_profiling(wf_ctx* ctx, int32_t on) {
+  if (!ctx) return WF_EINVAL;
+  ctx->prof = on != 0;
+  return WF_OK;
+}
+
+int wf_kernel_kinds(void) { return KK_COUNT; }
+
+const char* wf_kernel_kind_name(int32_t k) { return (k >= 0 && k < KK_COUNT) ? kKindNames[k] : ""; }
+
+int wf_get_kernel_stats(wf_ctx* ctx, int64_t* launches, double* ms, double* bytes) {
+  if (!ctx) return WF_EINVAL;
+  int rc = drain_events(ctx);
+  if (rc) return rc;
+  for (int k = 0; k < KK_COUNT; ++k) {
+    if (launches) launches[k] = ctx->launches[k];
+    if (ms) ms[k] = ctx->ms[k];
+    if (bytes) bytes[k] = ctx->bytes[k];
+  }
+  return WF_OK;
+}
+
+int wf_reset_kernel_stats(wf_ctx* ctx) {
+  if (!ctx) return WF_EINVAL;
+  int rc = drain_events(ctx);
+  if (rc) return rc;
+  for (int k = 0; k < KK_COUNT; ++k) {
+    ctx->launches[k] = 0;
+    ctx->ms[k] = 0.0;
+    ctx->bytes[k] = 0.0;
+  }
+  return WF_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,186 @@
+// Shared device/host definitions of libwf (gfx950).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace wf {
+
+// ------------------------------------------------------------------------ complex
+template <typename T>
+struct cpx {
+  T x, y;
+};
+
+template <typename T>
+__device__ __forceinline__ cpx<T> mk(T a, T b) {
+  cpx<T> r;
+  r.x = a;
+  r.y = b;
+  return r;
+}
+template <typename T>
+__device__ __forceinline__ cpx<T> add(cpx<T> a, cpx<T> b) { return mk(a.x + b.x, a.y + b.y); }
+template <typename T>
+__device__ __forceinline__ cpx<T> sub(cpx<T> a, cpx<T> b) { return mk(a.x - b.x, a.y - b.y); }
+template <typename T>
+__device__ __forceinline__ cpx<T> mul(cpx<T> a, cpx<T> b) {
+  return mk(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+// a * conj(b)
+template <typename T>
+__device__ __forceinline__ cpx<T> mulc(cpx<T> a, cpx<T> b) {
+  return mk(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y);
+}
+template <typename T>
+__device__ __forceinline__ cpx<T> conj(cpx<T> a) { return mk(a.x, -a.y); }
+template <typename T>
+__device__ __forceinline__ cpx<T> scale(cpx<T> a, T s) { return mk(a.x * s, a.y * s); }
+
+// ------------------------------------------------------------------------ layout
+// Internal storage of a harmonic field: column blocks of TB columns, each block a
+// contiguous [n][TB] array, so a column pass reads contiguous memory and a row pass
+// over 4 consecutive rows reads contiguous 4*TB runs.  The Nyquist column kx = n/2
+// (always dead) is not stored.
+constexpr int TB = 4;
+constexpr int RB = 4;      // rows per work-group of the row pass
+constexpr int NT = 256;    // threads per work-group of the transform passes
+
+__host__ __device__ __forceinline__ int64_t fidx(int n, int c, int ky, int kx) {
+  const int h = n >> 1;
+  return ((int64_t)(c * (h / TB) + kx / TB) * n + ky) * TB + (kx % TB);
+}
+
+// live = not DC, not on a Nyquist line; free = live and not a kx = 0 conjugate partner
+__host__ __device__ __forceinline__ bool is_live(int n, int ky, int kx) {
+  return !((ky == 0 && kx == 0) || ky == (n >> 1) || kx == (n >> 1));
+}
+__host__ __device__ __forceinline__ bool is_partner(int n, int ky, int kx) {
+  return kx == 0 && ky > (n >> 1);
+}
+__host__ __device__ __forceinline__ bool is_free(int n, int ky, int kx) {
+  return is_live(n, ky, kx) && !is_partner(n, ky, kx);
+}
+
+// ------------------------------------------------------------------------ chain jobs
+// One instance's work for one pass of the transform chain (column inverse, row,
+// column forward).  The solver kernels write these on the device every iteration;
+// operator-level calls fill them on the host.
+enum ChainMode : int {
+  CM_NONE = 0,
+  CM_HV = 1,        // out = v + sOut . R^T W R (sIn . v)             (whitened curvature)
+  CM_GRAD = 2,      // out = v + sOut . R^T W (R (sIn . v) - d)       (whitened gradient)
+  CM_FWD = 3,       // x = R (sIn . v)  (sIn may be null)             (forward only)
+  CM_ADJ = 4,       // out = R^T x                                     (metric adjoint)
+  CM_ADJ_GRAD = 5,  // out = 2 R^T x on free entries
+  CM_RAW_GRAD = 6,  // out = 4 (S^-1 v + R^T W (R v - d)), chi^2 partials (raw field)
+  CM_RAW_HV = 7,    // out = 4 (S^-1 v + R^T W R v)
+  CM_SIM = 8        // x = M (R (sIn . boost . z / sqrt 2) + noise)     (simulation)
+};
+
+// partial-sum kinds written per block
+enum { PK_PRIOR = 0, PK_RES = 1, PK_VO = 2, PK_OO = 3, PK_COUNT = 4 };
+
+struct Job {
+  int mode;
+  int boost_band;       // CM_SIM
+  int sim;              // CM_SIM: simulation index (Philox counter word 1)
+  int pad0;
+  double boost_factor;  // CM_SIM
+  uint64_t seed;        // CM_SIM (Philox key), used when draws == nullptr
+  const void* vin;      // column-inverse input (internal layout)
+  void* y;              // intermediate (internal layout)
+  void* vout;           // column-forward output (internal layout)
+  const void* vadd;     // added term in the column-forward epilogue
+  const void* d;        // data [c][n][n] (CM_GRAD, CM_RAW_GRAD) or pixel input (CM_ADJ*)
+  const void* W;        // [n][n]
+  const void* sIn;      // scale table for the column inverse (sqrt S), nullable
+  const void* sOut;     // scale / liveness table for the column forward (sqrt S)
+  const int32_t* band;  // internal-layout band table (CM_SIM boost)
+  const void* draws;    // [2][c][n][n] normals (CM_SIM), nullable -> Philox
+  void* xout;           // pixel output (CM_FWD, CM_SIM)
+  double* part;         // [PK_COUNT][pstride] partial sums
+  int pstride;
+  int pad1;
+};
+
+// ------------------------------------------------------------------------ solver state
+constexpr int MMAX = 16;
+
+enum { ST_RUNNING = -1 };   // otherwise WF_SOLVE_* values
+
+// kernel kinds for instrumentation
+enum {
+  KK_COLINV = 0, KK_ROW = 1, KK_COLFWD = 2, KK_PASSA = 3, KK_PASSB = 4, KK_POST = 5, KK_COEF = 6,
+  KK_MISC = 7, KK_COUNT = 8
+};
+
+struct LbState {
+  int status;
+  int iter;
+  int nhist;
+  int head;
+  int pending;       // newest pair's step not yet applied to w and g
+  int chainMode;     // mode of the chain enqueued in this iteration
+  int lastWasGrad;   // g currently holds an exact gradient
+  int ngrad;
+  int lastGradIter;
+  int newslot;
+  int m;
+  int pad;
+  double g0norm;
+  double gg;
+  double chi2;
+  double dchi2;
+  double gdotp;
+  double pDp;
+  double alpha[MMAX];
+  double PD[MMAX][MMAX];   // p_i . Dp_j
+  double DD[MMAX][MMAX];   // Dp_i . Dp_j
+  double gP[MMAX];
+  double gD[MMAX];
+  double coef[2 * MMAX + 1];   // direction on (p_0..p_{m-1}, Dp_0..Dp_{m-1}, g)
+  double bytes[KK_COUNT];      // algorithmic bytes moved for this instance
+};
+
+// One field's band-statistic job.
+struct BandJob {
+  const void* f;          // field, internal layout
+  const void* sq;         // sqrt S table (raw fields)
+  const int32_t* bandI;   // internal band table (-1 = none / not free)
+  const double* theta;    // [nbands] (device)
+  double* part;           // [nblk][nbands]
+  double* E;              // [nbands] output (device)
+  int64_t L;
+  int nbands;
+  int raw;
+};
+
+// Static per-instance description of a solve.
+struct InstDesc {
+  void* w;
+  void* g;
+  void* y;
+  void* P;          // m slots of L complex
+  void* D;          // m slots
+  const void* d;
+  const void* W;
+  const void* sq;   // sqrt S table (internal layout, real)
+  double* partChain;   // [PK_COUNT][pstride]
+  double* partA;       // [nblkA][NDOT]
+  int* statusOut;      // compact per-instance status for host polling
+  int n, c;
+  int64_t L;           // complex elements per vector
+  int pstride;
+  int nblkA;
+  int nblkB;
+  int m;
+  int esize;           // bytes of one complex element
+  int maxIter;
+  int refreshEvery;
+  double tol;
+  double dchi2Tol;
+  double vbytes;       // bytes of one vector
+};
+
+}  // namespace wf

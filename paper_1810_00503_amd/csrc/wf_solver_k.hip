@@ -1,0 +1,97 @@
+// Instantiations and host launchers of the solver, table, packing and band kernels.
+#include "wf_solver.hpp"
+#include "wf_launch.hpp"
+
+namespace wf {
+
+bool chain_supported(int n) {
+  if (n < 8 || n > 1024 || (n % 8) != 0) return false;
+  int m = n;
+  if (m % 3 == 0) m /= 3;
+  return (m & (m - 1)) == 0;
+}
+
+template <typename T, int M>
+static hipError_t lb_t(int which, dim3 grid, InstDesc* desc, LbState* st, Job* jobs, int count, hipStream_t s) {
+  switch (which) {
+    case LB_ZERO: k_zero<T><<<grid, dim3(256), 0, s>>>(desc, count); break;
+    case LB_INIT: k_init<<<dim3((count + 63) / 64), dim3(64), 0, s>>>(desc, st, jobs, count); break;
+    case LB_POST: k_post<<<dim3(count), dim3(64), 0, s>>>(desc, st, jobs); break;
+    case LB_PASSA: k_passA<T, M><<<grid, dim3(NT), 0, s>>>(desc, st); break;
+    case LB_COEF: k_coef<M><<<dim3(count), dim3(64), 0, s>>>(desc, st, jobs); break;
+    case LB_PASSB: k_passB<T, M><<<grid, dim3(NT), 0, s>>>(desc, st); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t lb_m(int m, int which, dim3 grid, InstDesc* desc, LbState* st, Job* jobs, int count, hipStream_t s) {
+  switch (m) {
+#define WF_M(M) case M: return lb_t<T, M>(which, grid, desc, st, jobs, count, s);
+    WF_M(1) WF_M(2) WF_M(3) WF_M(4) WF_M(5) WF_M(6) WF_M(7) WF_M(8)
+    WF_M(9) WF_M(10) WF_M(11) WF_M(12) WF_M(13) WF_M(14) WF_M(15) WF_M(16)
+#undef WF_M
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t lbfgs_launch(int dtype, int m, int which, dim3 grid, InstDesc* desc, LbState* st, Job* jobs, int count,
+                        hipStream_t s) {
+  return dtype == 0 ? lb_m<float>(m, which, grid, desc, st, jobs, count, s)
+                    : lb_m<double>(m, which, grid, desc, st, jobs, count, s);
+}
+
+static dim3 flat_grid(int64_t tot) {
+  int64_t b = (tot + 255) / 256;
+  if (b > 4096) b = 4096;
+  if (b < 1) b = 1;
+  return dim3((unsigned)b);
+}
+
+hipError_t prior_table_launch(int dtype, int n, int c, const double* pshape, const int32_t* band, const double* theta,
+                              int nbands, void* sq, int32_t* bandI, hipStream_t s) {
+  const dim3 g = flat_grid((int64_t)c * n * (n / 2));
+  if (dtype == 0)
+    k_prior_table<float><<<g, 256, 0, s>>>(n, c, pshape, band, theta, nbands, (float*)sq, bandI);
+  else
+    k_prior_table<double><<<g, 256, 0, s>>>(n, c, pshape, band, theta, nbands, (double*)sq, bandI);
+  return hipGetLastError();
+}
+
+hipError_t unpack_launch(int dtype, int n, int c, int batch, const void* ext, void* in, hipStream_t s) {
+  const dim3 g = flat_grid((int64_t)batch * c * n * (n / 2));
+  if (dtype == 0)
+    k_unpack<float><<<g, 256, 0, s>>>(n, c, batch, (const cpx<float>*)ext, (cpx<float>*)in);
+  else
+    k_unpack<double><<<g, 256, 0, s>>>(n, c, batch, (const cpx<double>*)ext, (cpx<double>*)in);
+  return hipGetLastError();
+}
+
+hipError_t pack_launch(int dtype, int n, int c, int batch, const void* in, int64_t inStride, const void* sq, int fill,
+                       void* const* outs, void* out0, hipStream_t s) {
+  const dim3 g = flat_grid((int64_t)batch * c * n * (n / 2 + 1));
+  if (dtype == 0)
+    k_pack<float><<<g, 256, 0, s>>>(n, c, batch, (const cpx<float>*)in, inStride, (const float*)sq, fill,
+                                    (cpx<float>* const*)outs, (cpx<float>*)out0);
+  else
+    k_pack<double><<<g, 256, 0, s>>>(n, c, batch, (const cpx<double>*)in, inStride, (const double*)sq, fill,
+                                     (cpx<double>* const*)outs, (cpx<double>*)out0);
+  return hipGetLastError();
+}
+
+int band_nblk(int64_t L) { return (int)((L + (int64_t)NT * BAND_EPT - 1) / ((int64_t)NT * BAND_EPT)); }
+
+hipError_t band_launch(int dtype, const BandJob* jobs, int count, int64_t L, hipStream_t s) {
+  const int nb = band_nblk(L);
+  if (dtype == 0)
+    k_band_part<float><<<dim3(nb, count), NT, 0, s>>>(jobs);
+  else
+    k_band_part<double><<<dim3(nb, count), NT, 0, s>>>(jobs);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  k_band_final<<<dim3(count), dim3(64), 0, s>>>(jobs, nb);
+  return hipGetLastError();
+}
+
+}  // namespace wf

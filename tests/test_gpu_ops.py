@@ -1,0 +1,125 @@
+"""GPU parity of the operator-level calls against the FP64 oracle (element by element).
+
+Tolerances: float64 kernels agree with the oracle to 1e-11 relative (round-off of a few
+FFT passes); float32 kernels to 3e-6 relative L2 and 2e-5 of the maximum per element,
+which is the float32 round-off of two FFT passes (eps * log2 n with eps = 6e-8) with
+a margin of ~5."""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1810_00503_amd import workloads as WL
+from tests.gpu_util import fill_partners, make_problem, random_half, rel_l2
+
+pytestmark = pytest.mark.gpu
+
+SIZES = [8, 16, 24, 32, 48, 64, 96, 128, 192, 256, 384, 512, 768, 1024]
+TOL = {"f32": (3e-6, 2e-5), "f64": (1e-11, 1e-11)}
+
+
+def _wl(n, ncomp, seed=1):
+    if ncomp == 1:
+        return WL.density_workload(n, seed, nbands=4, holes=3, target_mask=0.2)
+    return WL.shear_workload(n, seed, nbands_e=3, nbands_b=3)
+
+
+def _close(got, ref, dtype):
+    r, m = TOL[dtype]
+    assert rel_l2(got, ref) < r, (rel_l2(got, ref), r)
+    assert np.max(np.abs(got - ref)) <= m * max(np.max(np.abs(ref)), 1e-300)
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+@pytest.mark.parametrize("ncomp", [1, 2])
+@pytest.mark.parametrize("n", SIZES)
+def test_forward_adjoint_match_oracle(lib, n, ncomp, dtype):
+    import torch
+    if dtype == "f64" and n > 256:
+        pytest.skip("float64 transforms are checked up to 256^2")
+    print(f"[forward/adjoint n={n} ncomp={ncomp} {dtype}]", flush=True)
+    wl = _wl(n, ncomp)
+    prob = make_problem(lib, torch, wl, dtype)
+    rng = np.random.default_rng(n * 10 + ncomp)
+    B = 2
+    s = np.stack([random_half(rng, ncomp, n) for _ in range(B)])
+    st = torch.tensor(s, dtype=prob.cdtype, device="cuda:0")
+    x = lib.wf_forward(prob, st).cpu().numpy()
+    for b in range(B):
+        _close(x[b], O.forward(s[b]), dtype)
+    # partner entries and the Nyquist column of the input are ignored
+    s2 = s.copy()
+    s2[:, :, n // 2 + 1:, 0] = 123.0
+    s2[:, :, :, n // 2] = -7.0
+    x2 = lib.wf_forward(prob, torch.tensor(s2, dtype=prob.cdtype, device="cuda:0")).cpu().numpy()
+    np.testing.assert_array_equal(x2, x)
+    xr = rng.standard_normal((B, ncomp, n, n))
+    a = lib.wf_adjoint(prob, torch.tensor(xr, dtype=prob.rdtype, device="cuda:0")).cpu().numpy()
+    for b in range(B):
+        _close(a[b], O.adjoint(xr[b]), dtype)
+    g = lib.wf_adjoint(prob, torch.tensor(xr, dtype=prob.rdtype, device="cuda:0"), flags=lib.WF_ADJ_GRAD)
+    g = g.cpu().numpy()
+    fr = O.free_mask(n)[None]
+    for b in range(B):
+        _close(g[b], np.where(fr, 2.0 * O.adjoint(xr[b]), 0), dtype)
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+@pytest.mark.parametrize("ncomp", [1, 2])
+@pytest.mark.parametrize("n", [16, 48, 64, 256, 512])
+def test_chi2_grad_hvp_band_E_match_oracle(lib, n, ncomp, dtype):
+    import torch
+    if dtype == "f64" and n > 256:
+        pytest.skip("float64 checked up to 256^2")
+    print(f"[chi2/grad/hvp/E n={n} ncomp={ncomp} {dtype}]", flush=True)
+    if ncomp == 2:
+        wl = WL.shear_workload(n, 3, nbands_e=3, nbands_b=3)
+    else:
+        wl = WL.density_workload(n, 3, nbands=4, holes=3, target_mask=0.2)
+        wl.pshape = WL.density_pshape(n, kd=n / 4.0)   # keep S^-1 finite in float32
+    rng = np.random.default_rng(5)
+    d = rng.standard_normal((ncomp, n, n))
+    prob = make_problem(lib, torch, wl, dtype, d=d)
+    S = O.prior_S(wl.pshape, wl.band, wl.theta_fid)
+    fr = O.free_mask(n)[None] & (S > 0)
+    s = np.where(fr, np.sqrt(S) * (rng.standard_normal(S.shape) + 1j * rng.standard_normal(S.shape)), 0)
+    st = torch.tensor(fill_partners(s), dtype=prob.cdtype, device="cuda:0")
+    chi, g = lib.wf_chi2_grad(prob, st)
+    ref_chi = O.chi2(s, d, wl.W, S)
+    ref_g = O.grad_chi2(s, d, wl.W, S)
+    r = 2e-6 if dtype == "f32" else 1e-11
+    assert abs(chi - ref_chi) <= r * abs(ref_chi), (chi, ref_chi)
+    _close(g.cpu().numpy(), ref_g, dtype)
+    p = np.where(fr, rng.standard_normal(S.shape) + 1j * rng.standard_normal(S.shape), 0)
+    Dp = lib.wf_hvp(prob, torch.tensor(p, dtype=prob.cdtype, device="cuda:0")).cpu().numpy()
+    ref_Dp = O.grad_chi2(s + p, d, wl.W, S) - O.grad_chi2(s, d, wl.W, S)
+    _close(Dp, ref_Dp, dtype)
+    E = lib.wf_band_E(prob, st)
+    ref_E = O.band_E(s, S, wl.band, wl.theta_fid, wl.nbands)
+    np.testing.assert_allclose(E, ref_E, rtol=2e-6 if dtype == "f32" else 1e-12)
+
+
+@pytest.mark.parametrize("ncomp", [1, 2])
+@pytest.mark.parametrize("n", [16, 64, 512])
+def test_simulation_matches_oracle(lib, n, ncomp):
+    import torch
+    print(f"[simulate n={n} ncomp={ncomp}]", flush=True)
+    wl = _wl(n, ncomp, seed=9)
+    prob = make_problem(lib, torch, wl, "f32")
+    draws = WL.white_draws(n, ncomp, 3, 17)
+    d = lib.wf_simulate(prob, 3, 0, draws=torch.tensor(draws, dtype=torch.float32, device="cuda:0"),
+                        theta_true=wl.theta_true).cpu().numpy()
+    S_true = O.prior_S(wl.pshape, wl.band, wl.theta_true)
+    for i in range(3):
+        _close(d[i], O.simulate(draws[i], S_true, wl.W), "f32")
+    # boosted band (Fisher simulations): S_true of band 1 doubled
+    db = lib.wf_simulate(prob, 1, 0, draws=torch.tensor(draws[:1], dtype=torch.float32, device="cuda:0"),
+                         theta_true=wl.theta_true, boost_band=1, boost_factor=2.0).cpu().numpy()
+    th = wl.theta_true.copy()
+    th[1] *= 2.0
+    _close(db[0], O.simulate(draws[0], O.prior_S(wl.pshape, wl.band, th), wl.W), "f32")
+    # counter-based draws: the device Philox stream equals the oracle's
+    seed = 0x1234_5678_9ABC
+    dp = lib.wf_simulate(prob, 2, seed, sim0=5, theta_true=wl.theta_true).cpu().numpy()
+    for i in range(2):
+        dr = O.philox.draws_for_sims(seed, [5 + i], n, ncomp)[0]
+        _close(dp[i], O.simulate(dr, S_true, wl.W), "f32")
