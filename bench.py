@@ -1,0 +1,211 @@
+"""Benchmark: MAP solves/s at 512^2 (joint E/B shear) to 1e-6 relative gradient on one MI355X.
+
+One step is one pass of the whole hot path over one batch: simulate the quadratic
+estimator's maps on the device (fiducial and band-boosted simulations, Philox draws),
+solve all of them together with the data map as ONE batched L-BFGS solve (127 MAP
+solves: 1 data + 6 simulations x (1 + 20 bands)), reduce the band statistics E_l and
+form the noise bias, Fisher matrix and Newton step (bandpower_qe).  `value` is MAP
+solves per second of that step, inputs resident in HBM.
+
+Also reported: the same 127 solves through the plain path (one map at a time, host
+check after every iteration, no graph), the batched solve alone, the roofline of the
+dominant kernel (HIP events around every launch of one instrumented step; bytes are
+the kernels' algorithmic bytes counted on the device), and the FP64 oracle on the host
+(cpu_baseline, one solve of the same data map).
+
+    python bench.py [--steps K] [--warmup W] [--nsim 6] [--n 512] [--no-cpu] [--no-plain]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import subprocess
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "MAP solves/sec at 512² to 1e-6 rel. grad, batched vs plain; % HBM roofline"
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--n", type=int, default=512)
+    ap.add_argument("--nsim", type=int, default=6)
+    ap.add_argument("--tol", type=float, default=1e-6)
+    ap.add_argument("--m", type=int, default=10)
+    ap.add_argument("--seed", type=int, default=3000)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--plain-solves", type=int, default=0, help="plain-path solves to time (0 = all)")
+    ap.add_argument("--cpu-child", action="store_true", help=argparse.SUPPRESS)
+    return ap.parse_args()
+
+
+def cpu_baseline(args):
+    """The oracle (float64 numpy, one thread) solving the data map of the workload."""
+    env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
+    cmd = [sys.executable, os.path.abspath(__file__), "--cpu-child", "--n", str(args.n), "--tol", str(args.tol),
+           "--m", str(args.m), "--seed", str(args.seed)]
+    r = subprocess.run(cmd, capture_output=True, text=True, env=env, timeout=600)
+    if r.returncode != 0:
+        return {"error": r.stderr[-400:]}
+    return json.loads(r.stdout.strip().splitlines()[-1])
+
+
+def cpu_child(args):
+    import numpy as np
+
+    import oracle as O
+    from paper_1810_00503_amd import workloads as WL
+    wl = WL.config3(args.n)
+    S_true = O.prior_S(wl.pshape, wl.band, wl.theta_true)
+    S = O.prior_S(wl.pshape, wl.band, wl.theta_fid)
+    # the data map (Philox stream 0 of the data seed) and the first two fiducial simulations
+    maps = [O.simulate(O.philox.draws_for_sims(args.seed, [0], wl.n, wl.ncomp)[0], S_true, wl.W)]
+    for i in range(2):
+        maps.append(O.simulate(O.philox.draws_for_sims(args.seed + 1, [i], wl.n, wl.ncomp)[0], S, wl.W))
+    t0 = time.perf_counter()
+    its = [O.lbfgs_solve(d, wl.W, S, m=args.m, tol=args.tol)["iters"] for d in maps]
+    dt = time.perf_counter() - t0
+    print(json.dumps({"value": len(maps) / dt, "unit": "solves/s", "cores": 1, "kind": "oracle",
+                      "sample": f"{len(maps)} MAP solves (the {args.n}^2 E/B shear data map and 2 fiducial "
+                                f"simulations) to {args.tol:g} rel. grad, float64 numpy on 1 thread, "
+                                f"iterations {its}, {dt:.1f} s"}))
+
+
+def main():
+    args = parse()
+    if args.cpu_child:
+        cpu_child(args)
+        return
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the simulation batches would shard "
+              f"across GPUs with one all-reduce of E and F, which this build does not implement.", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import paper_1810_00503_amd as wf
+    from paper_1810_00503_amd import workloads as WL
+
+    wf.load()
+    dev = "cuda:0"
+    wl = WL.config3(args.n)
+    W = torch.tensor(wl.W, dtype=torch.float32, device=dev)
+    base = wf.Problem(W, wl.pshape, wl.band, wl.theta_fid)
+    # the observed map: a simulation from the truth (Theta = 1), Philox stream 0
+    d = wf.wf_simulate(base, 1, args.seed, sim0=0, theta_true=wl.theta_true)[0]
+    prob = base.with_data(d)
+    opts = wf.LbfgsOpts(m=args.m, rel_grad_tol=args.tol)
+    nb = wl.nbands
+    nsolve = 1 + args.nsim * (1 + nb)
+    sim_seed = args.seed + 1
+
+    def step():
+        return wf.bandpower_qe(prob, args.nsim, sim_seed, opts=opts)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        th, E, b, F, rc = step()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ms_step = 1e3 * elapsed / args.steps
+    value = nsolve * args.steps / elapsed
+
+    # the step's solves as separate problems (for the solve-only and plain comparisons)
+    sims = [prob]
+    dsim = wf.wf_simulate(base, args.nsim, sim_seed, sim0=0)
+    for i in range(args.nsim):
+        sims.append(base.with_data(dsim[i]))
+        for l in range(nb):
+            di = wf.wf_simulate(base, 1, sim_seed, sim0=i, boost_band=l, boost_factor=2.0)[0]
+            sims.append(base.with_data(di))
+    torch.cuda.synchronize()
+    wf.map_wf_solve(sims, opts)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, _, st_b, _ = wf.map_wf_solve(sims, opts)
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t0
+    iters = [s.iters for s in st_b]
+    conv = sum(s.status == wf.WF_SOLVE_CONVERGED for s in st_b)
+
+    plain = None
+    if not args.no_plain:
+        npl = len(sims) if args.plain_solves <= 0 else min(args.plain_solves, len(sims))
+        popts = wf.LbfgsOpts(m=args.m, rel_grad_tol=args.tol, use_graph=0, iters_per_poll=1)
+        wf.map_wf_solve(sims[:1], popts)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for p in sims[:npl]:
+            wf.map_wf_solve([p], popts)
+        torch.cuda.synchronize()
+        plain = npl / (time.perf_counter() - t0)
+
+    # one instrumented step: events around every launch, device-counted algorithmic bytes
+    wf.reset_kernel_stats()
+    wf.set_profiling(True)
+    step()
+    torch.cuda.synchronize()
+    ks = wf.kernel_stats()
+    wf.set_profiling(False)
+    dom = max(ks, key=lambda k: ks[k]["ms"])
+    kd = ks[dom]
+    achieved = kd["bytes"] / (kd["ms"] * 1e-3) / 1e9 if kd["ms"] > 0 else 0.0
+    per_kernel = {k: {"launches": v["launches"], "ms": round(v["ms"], 3),
+                      "GB_per_s": round(v["bytes"] / (v["ms"] * 1e-3) / 1e9, 1) if v["ms"] > 0 and v["bytes"] > 0
+                      else None} for k, v in ks.items()}
+    roof = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "avg_launch_us": round(1e3 * kd["ms"] / max(kd["launches"], 1), 2),
+            "bytes_per_launch": kd["bytes"] / max(kd["launches"], 1)}
+
+    # measured copy ceiling (context for the roofline): device-to-device copy of 2 GiB
+    src = torch.empty(512 * 1024 * 1024, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(5):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    copy_gbs = 5 * 2 * src.numel() * 4 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del src, dst
+    roof["copy_ceiling_GBps"] = round(copy_gbs, 1)
+
+    cpu = None if args.no_cpu else cpu_baseline(args)
+    out = {
+        "metric": METRIC, "value": round(value, 2), "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms_step, 2), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"{args.n}^2 joint E/B shear (config-3 generator), {nb} bands; one bandpower_qe "
+                               f"step = {nsolve} MAP solves (1 data + {args.nsim} sims x (1 + {nb} bands)) in one "
+                               f"batch to {args.tol:g} rel. grad, L-BFGS m={args.m}",
+                   "n": args.n, "ncomp": 2, "batch": nsolve, "nsim": args.nsim, "nbands": nb,
+                   "rel_grad_tol": args.tol, "m": args.m},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "batched_solve_only_solves_per_s": round(len(sims) / t_batch, 2),
+        "plain_solves_per_s": None if plain is None else round(plain, 2),
+        "speedup_batched_vs_plain": None if plain is None else round(len(sims) / t_batch / plain, 2),
+        "bandpower_estimates_per_s": round(args.steps / elapsed, 3),
+        "iters_mean": round(float(np.mean(iters)), 1), "iters_max": int(np.max(iters)),
+        "converged": f"{conv}/{len(sims)}",
+        "per_kernel": per_kernel,
+    }
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <cstdlib>
 #include <map>
 #include <new>
 #include <string>
@@ -24,6 +25,10 @@ constexpr size_t kAlign = 256;
 constexpr int kNdot = 5 * MMAX + 1;
 constexpr double kSimBudgetBytes = 48.0 * 1024 * 1024 * 1024;   // workspace cap of a sim chunk
 constexpr int kMaxChunk = 256;
+// Vectors of one instance are laid out back to back with this many extra bytes between
+// them (an odd multiple of 256 B), so the 2m + 3 streams of a pass do not start at the same
+// offset modulo a large power of two.
+constexpr size_t kVecPadBytes = 4096 + 256;
 
 const char* kKindNames[KK_COUNT] = {"colinv", "row", "colfwd", "passA", "passB", "post", "coef", "misc"};
 
@@ -282,12 +287,14 @@ struct Klass {
   std::vector<int> members;   // user indices
   int first = 0;              // position in the class-ordered arrays
   int64_t L = 0;
-  int nblkA = 0, nblkB = 0, pstride = 0;
+  int nchunk = 0, pstride = 0;
+  int group = 0;   // instances per launch of the transform chain (0 = all)
   const void* tw = nullptr;
 };
 
 struct SolveOut {
-  std::vector<void*> w;         // per user index: whitened solution (internal layout)
+  std::vector<void*> w;         // per user index: whitened solution (chunk-interleaved view)
+  std::vector<int64_t> vcs, vcstr;   // its view
   std::vector<void*> y;         // per user index: intermediate buffer
   std::vector<PriorTab> prior;  // per user index
   std::vector<LbState> st;      // per user index
@@ -345,15 +352,14 @@ int solve_core(wf_ctx* ctx, const wf_problem* probs, int B, const wf_lbfgs_opts&
     k.first = pos;
     pos += (int)k.members.size();
     k.L = (int64_t)k.c * k.n * (k.n / 2);
-    const int vw = k.dtype == WF_F64 ? 2 : 4;
-    const int64_t nvec = k.L * 2 / vw;
-    const int64_t chunk = (int64_t)NT * 8;   // PASS_EPT vectors per thread
-    k.nblkA = (int)((nvec + chunk - 1) / chunk);
-    k.nblkB = k.nblkA;
-    k.pstride = k.n / RB;
     const size_t eb = esize_of(k.dtype);
-    const size_t per = align_up((size_t)(3 + 2 * m) * k.L * eb) + align_up(sizeof(double) * PK_COUNT * k.pstride) +
-                       align_up(sizeof(double) * kNdot * k.nblkA);
+    const int64_t nvec = k.L * 2 / (k.dtype == WF_F64 ? 2 : 4);
+    k.nchunk = (int)((nvec + PASS_CV - 1) / PASS_CV);
+    k.pstride = k.n / RB;
+    if (const char* ge = getenv("WF_CHAIN_GROUP")) k.group = atoi(ge);
+    const size_t vsb = (size_t)k.L * eb + kVecPadBytes;
+    const size_t per = align_up((size_t)(2 + 2 * m) * vsb) + align_up(vsb) +
+                       align_up(sizeof(double) * PK_COUNT * k.pstride) + align_up(sizeof(double) * kNdot * k.nchunk);
     total += per * k.members.size();
     int rc = twiddles(ctx, k.n, k.dtype, &k.tw);
     if (rc) return rc;
@@ -376,6 +382,8 @@ int solve_core(wf_ctx* ctx, const wf_problem* probs, int B, const wf_lbfgs_opts&
   }
   std::vector<InstDesc> hd(B);
   out.w.assign(B, nullptr);
+  out.vcs.assign(B, 0);
+  out.vcstr.assign(B, 0);
   out.y.assign(B, nullptr);
   out.prior.assign(B, PriorTab());
   out.order.assign(B, 0);
@@ -385,25 +393,23 @@ int solve_core(wf_ctx* ctx, const wf_problem* probs, int B, const wf_lbfgs_opts&
       const int ui = k.members[j];
       const int gi = k.first + (int)j;
       const wf_problem* p = &probs[ui];
-      char* v = arena_take(A, (size_t)(3 + 2 * m) * k.L * eb);
       InstDesc& D = hd[gi];
-      D.w = v;
-      D.g = v + (size_t)k.L * eb;
-      D.y = v + 2 * (size_t)k.L * eb;
-      D.P = v + 3 * (size_t)k.L * eb;
-      D.D = v + (3 + (size_t)m) * k.L * eb;
+      const size_t vsb = (size_t)k.L * eb + kVecPadBytes;
+      D.X = arena_take(A, (size_t)(2 + 2 * m) * vsb);
+      D.y = arena_take(A, vsb);
+      D.vstride = (int64_t)(vsb / eb);
+      D.NV = 2 + 2 * m;
+      D.nchunk = k.nchunk;
       D.d = p->d;
       D.W = p->w;
       D.sq = ptabs[pidx[ui]].sq;
       D.partChain = (double*)arena_take(A, sizeof(double) * PK_COUNT * k.pstride);
-      D.partA = (double*)arena_take(A, sizeof(double) * kNdot * k.nblkA);
+      D.partA = (double*)arena_take(A, sizeof(double) * kNdot * k.nchunk);
       D.statusOut = dstat + gi;
       D.n = k.n;
       D.c = k.c;
       D.L = k.L;
       D.pstride = k.pstride;
-      D.nblkA = k.nblkA;
-      D.nblkB = k.nblkB;
       D.m = m;
       D.esize = (int)eb;
       D.maxIter = o.max_iter;
@@ -411,7 +417,9 @@ int solve_core(wf_ctx* ctx, const wf_problem* probs, int B, const wf_lbfgs_opts&
       D.tol = o.rel_grad_tol;
       D.dchi2Tol = o.dchi2_tol;
       D.vbytes = (double)k.L * eb;
-      out.w[ui] = D.w;
+      out.w[ui] = D.X;
+      out.vcs[ui] = k.L;
+      out.vcstr[ui] = k.L;
       out.y[ui] = D.y;
       out.prior[ui] = ptabs[pidx[ui]];
       out.order[ui] = gi;
@@ -438,7 +446,11 @@ int solve_core(wf_ctx* ctx, const wf_problem* probs, int B, const wf_lbfgs_opts&
   auto body = [&](void) -> int {
     for (auto& k : ks) {
       const int cnt = (int)k.members.size();
-      for (int w = 0; w < 3; ++w) HIPCHK(chain(ctx, k.dtype, k.n, k.c, w, djobs + k.first, cnt, k.tw));
+      const int G = k.group > 0 ? std::min(k.group, cnt) : cnt;
+      for (int g0 = 0; g0 < cnt; g0 += G) {
+        const int gc = std::min(G, cnt - g0);
+        for (int w = 0; w < 3; ++w) HIPCHK(chain(ctx, k.dtype, k.n, k.c, w, djobs + k.first + g0, gc, k.tw));
+      }
     }
     for (auto& k : ks) {
       const int cnt = (int)k.members.size();
@@ -449,7 +461,7 @@ int solve_core(wf_ctx* ctx, const wf_problem* probs, int B, const wf_lbfgs_opts&
       }
       {
         Timed t(ctx, KK_PASSA);
-        HIPCHK(lbfgs_launch(dt, m, LB_PASSA, dim3(k.nblkA, cnt), ddesc + k.first, dst + k.first, djobs + k.first, cnt,
+        HIPCHK(lbfgs_launch(dt, m, LB_PASSA, dim3(k.nchunk, cnt), ddesc + k.first, dst + k.first, djobs + k.first, cnt,
                             ctx->cs));
       }
       {
@@ -458,7 +470,7 @@ int solve_core(wf_ctx* ctx, const wf_problem* probs, int B, const wf_lbfgs_opts&
       }
       {
         Timed t(ctx, KK_PASSB);
-        HIPCHK(lbfgs_launch(dt, m, LB_PASSB, dim3(k.nblkB, cnt), ddesc + k.first, dst + k.first, djobs + k.first, cnt,
+        HIPCHK(lbfgs_launch(dt, m, LB_PASSB, dim3(k.nchunk, cnt), ddesc + k.first, dst + k.first, djobs + k.first, cnt,
                             ctx->cs));
       }
     }
@@ -567,6 +579,8 @@ int maps_from_solution(wf_ctx* ctx, const wf_problem* probs, int B, const SolveO
       jb.mode = CM_FWD;
       jb.boost_band = -1;
       jb.vin = so.w[mem[j]];
+      jb.vcs = so.vcs[mem[j]];
+      jb.vcstr = so.vcstr[mem[j]];
       jb.y = so.y[mem[j]];
       jb.sIn = so.prior[mem[j]].sq;
       jb.xout = map_out[mem[j]];
@@ -635,6 +649,8 @@ int band_E_solved(wf_ctx* ctx, const wf_problem* probs, int B, const SolveOut& s
     hj[i].part = part + (size_t)i * nblk * nb;
     hj[i].E = dE + (size_t)i * nb;
     hj[i].L = L;
+    hj[i].vcs = so.vcs[i];
+    hj[i].vcstr = so.vcstr[i];
     hj[i].nbands = nb;
     hj[i].raw = 0;
   }
@@ -883,7 +899,8 @@ int map_wf_solve(wf_ctx* ctx, const wf_problem* probs, int32_t batch, const wf_l
   // s = sqrt(S) w with partners filled, into the caller's buffers
   for (int i = 0; i < batch; ++i) {
     const wf_problem* p = &probs[i];
-    HIPCHK(pack_launch(p->dtype, p->n, p->ncomp, 1, so.w[i], 0, so.prior[i].sq, 1, nullptr, s_out[i], ctx->cs));
+    HIPCHK(pack_launch(p->dtype, p->n, p->ncomp, 1, so.w[i], 0, so.vcs[i], so.vcstr[i], so.prior[i].sq, 1, nullptr,
+                       s_out[i], ctx->cs));
   }
   rc = maps_from_solution(ctx, probs, batch, so, map_out);
   if (rc) return rc;
@@ -985,6 +1002,7 @@ int wf_forward(wf_ctx* ctx, const wf_problem* p, int32_t batch, const void* s, v
   std::vector<Job> hj(batch);
   for (int i = 0; i < batch; ++i) {
     std::memset(&hj[i], 0, sizeof(Job));
+    hj[i].vcs = hj[i].vcstr = L;
     hj[i].mode = CM_FWD;
     hj[i].boost_band = -1;
     hj[i].vin = (char*)vin + (size_t)i * L * eb;
@@ -1015,6 +1033,7 @@ int wf_adjoint(wf_ctx* ctx, const wf_problem* p, int32_t batch, const void* x, v
   std::vector<Job> hj(batch);
   for (int i = 0; i < batch; ++i) {
     std::memset(&hj[i], 0, sizeof(Job));
+    hj[i].vcs = hj[i].vcstr = L;
     hj[i].mode = flags == WF_ADJ_GRAD ? CM_ADJ_GRAD : CM_ADJ;
     hj[i].boost_band = -1;
     hj[i].d = (const char*)x + (size_t)i * c * n * n * rs;
@@ -1024,7 +1043,7 @@ int wf_adjoint(wf_ctx* ctx, const wf_problem* p, int32_t batch, const void* x, v
   HIPCHK(hipMemcpyAsync(dj, hj.data(), sizeof(Job) * batch, hipMemcpyHostToDevice, ctx->cs));
   HIPCHK(chain(ctx, dt, n, c, CH_ROW, dj, batch, tw));
   HIPCHK(chain(ctx, dt, n, c, CH_COLFWD, dj, batch, tw));
-  HIPCHK(pack_launch(dt, n, c, batch, vout, L, nullptr, 0, nullptr, s, ctx->cs));
+  HIPCHK(pack_launch(dt, n, c, batch, vout, L, L, L, nullptr, 0, nullptr, s, ctx->cs));
   HIPCHK(hipStreamSynchronize(ctx->cs));
   return WF_OK;
 }
@@ -1047,6 +1066,7 @@ static int raw_chain(wf_ctx* ctx, const wf_problem* p, int batch, const void* s,
   std::vector<Job> hj(batch);
   for (int i = 0; i < batch; ++i) {
     std::memset(&hj[i], 0, sizeof(Job));
+    hj[i].vcs = hj[i].vcstr = L;
     hj[i].mode = mode;
     hj[i].boost_band = -1;
     hj[i].vin = (char*)vin + (size_t)i * L * eb;
@@ -1061,7 +1081,7 @@ static int raw_chain(wf_ctx* ctx, const wf_problem* p, int batch, const void* s,
   }
   HIPCHK(hipMemcpyAsync(dj, hj.data(), sizeof(Job) * batch, hipMemcpyHostToDevice, ctx->cs));
   for (int w = 0; w < 3; ++w) HIPCHK(chain(ctx, dt, n, c, w, dj, batch, tw));
-  if (out) HIPCHK(pack_launch(dt, n, c, batch, vout, L, nullptr, 0, nullptr, out, ctx->cs));
+  if (out) HIPCHK(pack_launch(dt, n, c, batch, vout, L, L, L, nullptr, 0, nullptr, out, ctx->cs));
   if (chi2) {
     std::vector<double> hp((size_t)PK_COUNT * pstride * batch);
     HIPCHK(hipMemcpyAsync(hp.data(), part, sizeof(double) * hp.size(), hipMemcpyDeviceToHost, ctx->cs));
@@ -1130,6 +1150,8 @@ int wf_band_E(wf_ctx* ctx, const wf_problem* p, int32_t batch, const void* s, do
     hj[i].part = bpart + (size_t)i * nblk * nb;
     hj[i].E = dE + (size_t)i * nb;
     hj[i].L = L;
+    hj[i].vcs = L;
+    hj[i].vcstr = L;
     hj[i].nbands = nb;
     hj[i].raw = 1;
   }

@@ -113,6 +113,13 @@ __global__ __launch_bounds__(NT) void k_colinv(const Job* __restrict__ jobs, con
   const T* draws = reinterpret_cast<const T*>(jb.draws);
   const T bamp = T(jb.boost_factor);
   double acc = 0.0;
+  // offset of this column block in the (chunk-interleaved) input view
+  int64_t dv[C];
+#pragma unroll
+  for (int c = 0; c < C; ++c) {
+    const int64_t bs = fidx(N, c, 0, q * TB);
+    dv[c] = jb.vcs > 0 ? vview(bs, jb.vcs, jb.vcstr) - bs : 0;
+  }
 
   for (int e = tid; e < N * TB; e += NT) {
     const int ky = e / TB, col = e % TB, kx = q * TB + col;
@@ -139,7 +146,7 @@ __global__ __launch_bounds__(NT) void k_colinv(const Job* __restrict__ jobs, con
           sc = sIn[src] * T(0.70710678118654752440084436210485);
           if (jb.band && jb.boost_band >= 0 && jb.band[src] == jb.boost_band) sc *= bamp;
         } else {
-          v = vin[src];
+          v = vin[src + dv[c]];
           if (sIn) sc = sIn[src];
           if (raw) {
             const T sq = sOut[src];
@@ -365,6 +372,12 @@ __global__ __launch_bounds__(NT) void k_colfwd(const Job* __restrict__ jobs, con
   const T* sOut = reinterpret_cast<const T*>(jb.sOut);
   cpx<T>* vout = reinterpret_cast<cpx<T>*>(jb.vout);
   double avo = 0.0, aoo = 0.0;
+  int64_t dv[C];
+#pragma unroll
+  for (int c = 0; c < C; ++c) {
+    const int64_t bs = fidx(N, c, 0, q * TB);
+    dv[c] = jb.vcs > 0 ? vview(bs, jb.vcs, jb.vcstr) - bs : 0;
+  }
   for (int e = tid; e < N * TB; e += NT) {
     const int ky = e / TB, col = e % TB, kx = q * TB + col;
     cpx<T> t[C];
@@ -385,7 +398,7 @@ __global__ __launch_bounds__(NT) void k_colfwd(const Job* __restrict__ jobs, con
       if (mode == CM_HV || mode == CM_GRAD) {
         const T sq = sOut[o];
         if (fr && sq != T(0)) {
-          const cpx<T> v = vadd[o];
+          const cpx<T> v = vadd[o + dv[c]];
           out = mk(v.x + sq * t[c].x, v.y + sq * t[c].y);
           avo += (double)v.x * out.x + (double)v.y * out.y;
         }
@@ -393,7 +406,7 @@ __global__ __launch_bounds__(NT) void k_colfwd(const Job* __restrict__ jobs, con
       } else if (mode == CM_RAW_GRAD || mode == CM_RAW_HV) {
         const T sq = sOut[o];
         if (fr && sq != T(0)) {
-          const cpx<T> v = vadd[o];
+          const cpx<T> v = vadd[o + dv[c]];
           const T is = T(1) / (sq * sq);
           out = mk(T(4) * (v.x * is + t[c].x), T(4) * (v.y * is + t[c].y));
         }
@@ -402,7 +415,7 @@ __global__ __launch_bounds__(NT) void k_colfwd(const Job* __restrict__ jobs, con
       } else {  // CM_ADJ_GRAD
         if (fr) out = scale(t[c], T(2));
       }
-      vout[o] = out;
+      vout[o + dv[c]] = out;
     }
   }
   if (mode == CM_HV) {

@@ -44,7 +44,9 @@ __device__ __forceinline__ cpx<T> scale(cpx<T> a, T s) { return mk(a.x * s, a.y 
 // (always dead) is not stored.
 constexpr int TB = 4;
 constexpr int RB = 4;      // rows per work-group of the row pass
-constexpr int NT = 256;    // threads per work-group of the transform passes
+constexpr int NT = 256;    // threads per work-group of the transform and vector passes
+constexpr int PASS_U = 4;                // vector loads per thread per stream in a vector pass
+constexpr int PASS_CV = NT * PASS_U;     // vector elements of one stream per work-group
 
 __host__ __device__ __forceinline__ int64_t fidx(int n, int c, int ky, int kx) {
   const int h = n >> 1;
@@ -102,7 +104,17 @@ struct Job {
   double* part;         // [PK_COUNT][pstride] partial sums
   int pstride;
   int pad1;
+  // vin, vadd and vout are chunk-interleaved views: element e of such a vector lives at
+  // ptr + (e / vcs) * vcstr + e % vcs (vcs = vcstr = L for a plain contiguous vector).
+  // Chunks are whole column blocks, so a column tile is contiguous.
+  int64_t vcs;
+  int64_t vcstr;
 };
+
+// element offset of e in a chunk-interleaved vector view
+__host__ __device__ __forceinline__ int64_t vview(int64_t e, int64_t vcs, int64_t vcstr) {
+  return (e / vcs) * vcstr + (e % vcs);
+}
 
 // ------------------------------------------------------------------------ solver state
 constexpr int MMAX = 16;
@@ -152,17 +164,19 @@ struct BandJob {
   double* part;           // [nblk][nbands]
   double* E;              // [nbands] output (device)
   int64_t L;
+  int64_t vcs;            // view of f (see Job)
+  int64_t vcstr;
   int nbands;
   int raw;
 };
 
 // Static per-instance description of a solve.
+// The 2m + 2 vectors of an instance (w, g, p_0..p_{m-1}, Dp_0..Dp_{m-1}) are stored one
+// after the other, vstride complex elements apart (each vector padded by an odd multiple of
+// 256 B so the streams of a pass do not share offsets modulo a large power of two).
 struct InstDesc {
-  void* w;
-  void* g;
-  void* y;
-  void* P;          // m slots of L complex
-  void* D;          // m slots
+  void* X;          // vector v at X + v * vstride
+  void* y;          // transform intermediate
   const void* d;
   const void* W;
   const void* sq;   // sqrt S table (internal layout, real)
@@ -171,9 +185,10 @@ struct InstDesc {
   int* statusOut;      // compact per-instance status for host polling
   int n, c;
   int64_t L;           // complex elements per vector
+  int64_t vstride;     // complex elements between vectors
+  int NV;              // vectors per instance (2m + 2)
+  int nchunk;          // work-groups of a vector pass
   int pstride;
-  int nblkA;
-  int nblkB;
   int m;
   int esize;           // bytes of one complex element
   int maxIter;

@@ -36,10 +36,12 @@ __device__ __forceinline__ double2 vaxpy(double a, const double2& x, const doubl
 __device__ __forceinline__ float4 vscale(float a, const float4& x) { return make_float4(a * x.x, a * x.y, a * x.z, a * x.w); }
 __device__ __forceinline__ double2 vscale(double a, const double2& x) { return make_double2(a * x.x, a * x.y); }
 
-constexpr int PASS_EPT = 8;                 // vector loads per thread per pass
 constexpr int NDOT = 5 * MMAX + 1;          // partials per block of k_passA
 
-__host__ __device__ inline int pass_chunk_reals(int vw) { return NT * PASS_EPT * vw; }
+// keeps the compiler from moving the loads of the next stream above this point, so a
+// work-group streams one vector at a time (measurably better HBM efficiency than issuing
+// the loads of every stream element by element)
+__device__ __forceinline__ void stream_fence() { asm volatile("" ::: "memory"); }
 
 // ------------------------------------------------------------------------ init
 template <typename T>
@@ -48,16 +50,18 @@ __global__ void k_zero(InstDesc* desc, int batch) {
   if (i >= batch) return;
   using V = typename VecT<T>::type;
   constexpr int VW = VecT<T>::W;
-  V* w = reinterpret_cast<V*>(desc[i].w);
-  const int64_t nv = desc[i].L * 2 / VW;
+  const InstDesc& D = desc[i];
+  V* X = reinterpret_cast<V*>(D.X);   // vector 0 is w
+  const int64_t nv = D.L * 2 / VW;
   V z;
   if constexpr (VW == 4) z = make_float4(0.f, 0.f, 0.f, 0.f); else z = make_double2(0.0, 0.0);
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nv; e += (int64_t)gridDim.x * blockDim.x)
-    w[e] = z;
+    X[e] = z;
 }
 
 __device__ __forceinline__ void make_job(Job& jb, const InstDesc& D, int mode, int slot) {
   const size_t eb = (size_t)D.esize;
+  char* X = reinterpret_cast<char*>(D.X);
   jb.mode = mode;
   jb.boost_band = -1;
   jb.sim = 0;
@@ -73,16 +77,19 @@ __device__ __forceinline__ void make_job(Job& jb, const InstDesc& D, int mode, i
   jb.xout = nullptr;
   jb.part = D.partChain;
   jb.pstride = D.pstride;
+  jb.vcs = D.L;
+  jb.vcstr = D.L;
+  const size_t vb = (size_t)D.vstride * eb;
   if (mode == CM_HV) {
-    char* p = reinterpret_cast<char*>(D.P) + (size_t)slot * D.L * eb;
-    char* dp = reinterpret_cast<char*>(D.D) + (size_t)slot * D.L * eb;
+    char* p = X + (size_t)(2 + slot) * vb;
+    char* dp = X + (size_t)(2 + D.m + slot) * vb;
     jb.vin = p;
     jb.vadd = p;
     jb.vout = dp;
   } else {
-    jb.vin = D.w;
-    jb.vadd = D.w;
-    jb.vout = D.g;
+    jb.vin = X;         // w
+    jb.vadd = X;
+    jb.vout = X + vb;   // g
   }
 }
 
@@ -122,18 +129,23 @@ __global__ void k_init(InstDesc* desc, LbState* st, Job* jobs, int batch) {
 }
 
 // ------------------------------------------------------------------------ post-chain
+__device__ __forceinline__ double wave_block_sum(const double* p, int nb) {
+  double a = 0.0;
+  for (int b = threadIdx.x; b < nb; b += 64) a += p[b];
+  return wave_sum(a);
+}
+
 __global__ __launch_bounds__(64) void k_post(const InstDesc* __restrict__ desc, LbState* st, Job* jobs) {
   const int i = blockIdx.x;
   LbState& S = st[i];
   if (S.status != ST_RUNNING) return;
   const InstDesc& D = desc[i];
-  if (threadIdx.x != 0) return;
   const int mode = S.chainMode;
   const int ncol = (D.n / 2) / TB, nrow = D.n / RB;
   const double* part = D.partChain;
   if (mode == CM_HV) {
-    double pDp = 0.0;
-    for (int b = 0; b < ncol; ++b) pDp += part[PK_VO * D.pstride + b];
+    const double pDp = wave_block_sum(part + PK_VO * D.pstride, ncol);
+    if (threadIdx.x != 0) return;
     if (!(pDp > 0.0) || !isfinite(pDp)) {
       S.status = 2;
       D.statusOut[0] = 2;
@@ -151,9 +163,9 @@ __global__ __launch_bounds__(64) void k_post(const InstDesc* __restrict__ desc, 
     S.chi2 += S.dchi2;
     S.iter += 1;
   } else if (mode == CM_GRAD) {
-    double wsq = 0.0, rsq = 0.0;
-    for (int b = 0; b < ncol; ++b) wsq += part[PK_PRIOR * D.pstride + b];
-    for (int b = 0; b < nrow; ++b) rsq += part[PK_RES * D.pstride + b];
+    const double wsq = wave_block_sum(part + PK_PRIOR * D.pstride, ncol);
+    const double rsq = wave_block_sum(part + PK_RES * D.pstride, nrow);
+    if (threadIdx.x != 0) return;
     S.chi2 = 2.0 * wsq + rsq;
     S.ngrad += 1;
     S.lastGradIter = S.iter;
@@ -178,55 +190,84 @@ __global__ __launch_bounds__(NT) void k_passA(const InstDesc* __restrict__ desc,
   __shared__ double red[NT / 64][NDOT];
   const int nh = S.nhist, head = S.head, pend = S.pending;
   const T al = pend ? T(S.alpha[head]) : T(0);
-  const int64_t nvec = D.L * 2 / VW;     // vector elements per field
-  V* g = reinterpret_cast<V*>(D.g);
-  V* w = reinterpret_cast<V*>(D.w);
-  const V* P = reinterpret_cast<const V*>(D.P);
-  const V* Dp = reinterpret_cast<const V*>(D.D);
-  int sl[M];
+  const int64_t nvec = D.L * 2 / VW;
+  const int64_t vs = D.vstride * 2 / VW;                  // vector elements between vectors
+  const int64_t e0 = (int64_t)blockIdx.x * PASS_CV + threadIdx.x;
+  V* X = reinterpret_cast<V*>(D.X);
+  V* w = X;
+  V* g = X + vs;
+  const V* P = X + 2 * vs;
+  const V* Dp = X + (2 + M) * vs;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  bool ok[PASS_U];
 #pragma unroll
-  for (int j = 0; j < M; ++j) sl[j] = (head - j + 2 * M) % M;
-  double gP[M], gD[M], hP[M], Ph[M], hD[M], gg = 0.0;
-#pragma unroll
-  for (int j = 0; j < M; ++j) gP[j] = gD[j] = hP[j] = Ph[j] = hD[j] = 0.0;
+  for (int u = 0; u < PASS_U; ++u) ok[u] = e0 + (int64_t)u * NT < nvec;
 
-  const int64_t base = (int64_t)blockIdx.x * NT * PASS_EPT;
-#pragma unroll 2
-  for (int kk = 0; kk < PASS_EPT; ++kk) {
-    const int64_t e = base + (int64_t)kk * NT + threadIdx.x;
-    if (e >= nvec) break;
-    V gv = g[e];
-    V ph, dh;
-    if (pend) {
-      ph = P[(int64_t)head * nvec + e];
-      dh = Dp[(int64_t)head * nvec + e];
-      const V wv = w[e];
-      w[e] = vaxpy(al, ph, wv);
-      gv = vaxpy(al, dh, gv);
-      g[e] = gv;
-    }
-    gg += vdot(gv, gv);
+  // the new gradient (after the pending step) and the newest pair
+  V gv[PASS_U], ph[PASS_U], dh[PASS_U];
 #pragma unroll
-    for (int j = 0; j < M; ++j) {
-      if (j < nh) {
-        const V pv = P[(int64_t)sl[j] * nvec + e];
-        const V dv = Dp[(int64_t)sl[j] * nvec + e];
-        gP[j] += vdot(gv, pv);
-        gD[j] += vdot(gv, dv);
-        if (pend) {
-          hP[j] += vdot(ph, dv);
-          Ph[j] += vdot(pv, dh);
-          hD[j] += vdot(dh, dv);
-        }
+  for (int u = 0; u < PASS_U; ++u) {
+    const int64_t e = e0 + (int64_t)u * NT;
+    if (ok[u]) {
+      gv[u] = g[e];
+      if (pend) {
+        ph[u] = P[(int64_t)head * vs + e];
+        dh[u] = Dp[(int64_t)head * vs + e];
       }
     }
   }
-  // block reduction of the 5M+1 sums
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  double gg = 0.0;
+  if (pend) {
+#pragma unroll
+    for (int u = 0; u < PASS_U; ++u) {
+      const int64_t e = e0 + (int64_t)u * NT;
+      if (ok[u]) {
+        const V wv0 = w[e];
+        w[e] = vaxpy(al, ph[u], wv0);
+        gv[u] = vaxpy(al, dh[u], gv[u]);
+        g[e] = gv[u];
+      }
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < PASS_U; ++u)
+    if (ok[u]) gg += vdot(gv[u], gv[u]);
+  {
+    const double a = wave_sum(gg);
+    if (lane == 0) red[wv][5 * M] = a;
+  }
+  // one history slot at a time: dots with the new gradient and with the newest pair
 #pragma unroll
   for (int j = 0; j < M; ++j) {
-    const double a0 = wave_sum(gP[j]), a1 = wave_sum(gD[j]);
-    const double a2 = wave_sum(hP[j]), a3 = wave_sum(Ph[j]), a4 = wave_sum(hD[j]);
+    stream_fence();
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0, a4 = 0.0;
+    if (j < nh) {
+      const int64_t sp = (int64_t)((head - j + 2 * M) % M) * vs;
+      V pv[PASS_U], dv[PASS_U];
+#pragma unroll
+      for (int u = 0; u < PASS_U; ++u)
+        if (ok[u]) pv[u] = P[sp + e0 + (int64_t)u * NT];
+#pragma unroll
+      for (int u = 0; u < PASS_U; ++u)
+        if (ok[u]) dv[u] = Dp[sp + e0 + (int64_t)u * NT];
+#pragma unroll
+      for (int u = 0; u < PASS_U; ++u) {
+        if (ok[u]) {
+          a0 += vdot(gv[u], pv[u]);
+          a1 += vdot(gv[u], dv[u]);
+          if (pend) {
+            a2 += vdot(ph[u], dv[u]);
+            a3 += vdot(pv[u], dh[u]);
+            a4 += vdot(dh[u], dv[u]);
+          }
+        }
+      }
+    }
+    a0 = wave_sum(a0);
+    a1 = wave_sum(a1);
+    a2 = wave_sum(a2);
+    a3 = wave_sum(a3);
+    a4 = wave_sum(a4);
     if (lane == 0) {
       red[wv][j] = a0;
       red[wv][M + j] = a1;
@@ -234,10 +275,6 @@ __global__ __launch_bounds__(NT) void k_passA(const InstDesc* __restrict__ desc,
       red[wv][3 * M + j] = a3;
       red[wv][4 * M + j] = a4;
     }
-  }
-  {
-    const double a = wave_sum(gg);
-    if (lane == 0) red[wv][5 * M] = a;
   }
   __syncthreads();
   if (threadIdx.x < 5 * M + 1) {
@@ -249,65 +286,104 @@ __global__ __launch_bounds__(NT) void k_passA(const InstDesc* __restrict__ desc,
 }
 
 // ------------------------------------------------------------------------ coefficients
-// One work-group per instance; thread 0 runs the scalar recursion.
+// One work-group per instance: the partial sums and the small Gram state are staged in
+// LDS by all threads, then thread 0 runs the scalar recursion out of LDS.
 template <int M>
-__global__ __launch_bounds__(64) void k_coef(const InstDesc* __restrict__ desc, LbState* st, Job* jobs) {
+__global__ __launch_bounds__(256) void k_coef(const InstDesc* __restrict__ desc, LbState* st, Job* jobs) {
   const int i = blockIdx.x;
   LbState& S = st[i];
   if (S.status != ST_RUNNING) return;
   const InstDesc& D = desc[i];
   __shared__ double sums[NDOT];
-  for (int t = threadIdx.x; t < 5 * M + 1; t += blockDim.x) {
-    double a = 0.0;
-    for (int b = 0; b < D.nblkA; ++b) a += D.partA[(int64_t)b * NDOT + t];
-    sums[t] = a;
+  __shared__ double sPD[M][M], sDD[M][M], sal[M], sgP[M], sgD[M];
+  const int nblk = D.nchunk;
+  {
+    // 4 threads per sum, each over every 4th block with 4 independent loads in flight;
+    // the four parts are combined in a fixed order
+    __shared__ double part4[4][NDOT];
+    const int t = threadIdx.x & 63, q = threadIdx.x >> 6;
+    if (t < 5 * M + 1) {
+      double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+      int b = q;
+      for (; b + 12 < nblk; b += 16) {
+        a0 += D.partA[(int64_t)b * NDOT + t];
+        a1 += D.partA[(int64_t)(b + 4) * NDOT + t];
+        a2 += D.partA[(int64_t)(b + 8) * NDOT + t];
+        a3 += D.partA[(int64_t)(b + 12) * NDOT + t];
+      }
+      for (; b < nblk; b += 4) a0 += D.partA[(int64_t)b * NDOT + t];
+      part4[q][t] = (a0 + a1) + (a2 + a3);
+    }
+    __syncthreads();
+    if (threadIdx.x < 5 * M + 1)
+      sums[threadIdx.x] = (part4[0][threadIdx.x] + part4[1][threadIdx.x]) +
+                          (part4[2][threadIdx.x] + part4[3][threadIdx.x]);
   }
+  for (int t = threadIdx.x; t < M * M; t += blockDim.x) {
+    sPD[t / M][t % M] = S.PD[t / M][t % M];
+    sDD[t / M][t % M] = S.DD[t / M][t % M];
+  }
+  for (int t = threadIdx.x; t < M; t += blockDim.x) sal[t] = S.alpha[t];
   __syncthreads();
   if (threadIdx.x != 0) return;
 
   const int nh = S.nhist, head = S.head;
+  const int pend = S.pending;
   int sl[M];
   for (int j = 0; j < M; ++j) sl[j] = (head - j + 2 * M) % M;
   // bytes of the pass just finished
-  S.bytes[KK_PASSA] += D.vbytes * (1.0 + 2.0 * nh + (S.pending ? 3.0 : 0.0));
+  S.bytes[KK_PASSA] += D.vbytes * (1.0 + 2.0 * nh + (pend ? 3.0 : 0.0));
   for (int j = 0; j < nh; ++j) {
     const int s = sl[j];
+    sgP[s] = sums[j];
+    sgD[s] = sums[M + j];
     S.gP[s] = sums[j];
     S.gD[s] = sums[M + j];
-    if (S.pending) {
+    if (pend) {
+      sPD[head][s] = sums[2 * M + j];
+      sPD[s][head] = sums[3 * M + j];
+      sDD[head][s] = sums[4 * M + j];
+      sDD[s][head] = sums[4 * M + j];
       S.PD[head][s] = sums[2 * M + j];
       S.PD[s][head] = sums[3 * M + j];
       S.DD[head][s] = sums[4 * M + j];
       S.DD[s][head] = sums[4 * M + j];
     }
   }
-  S.gg = sums[5 * M];
-  const int wasPending = S.pending;
+  const double gg = sums[5 * M];
+  S.gg = gg;
   S.pending = 0;
-  if (S.g0norm < 0.0) S.g0norm = sqrt(S.gg);
-  const double rel = S.g0norm > 0.0 ? sqrt(S.gg) / S.g0norm : 0.0;
+  double g0 = S.g0norm;
+  if (g0 < 0.0) {
+    g0 = sqrt(gg);
+    S.g0norm = g0;
+  }
+  const double rel = g0 > 0.0 ? sqrt(gg) / g0 : 0.0;
+  const int lastWasGrad = S.lastWasGrad;
+  const int iter = S.iter;
 
   int next = CM_HV;
-  if (!isfinite(S.gg)) {
-    S.status = 2;
+  int status = ST_RUNNING;
+  if (!isfinite(gg)) {
+    status = 2;
     next = CM_NONE;
-  } else if (S.g0norm == 0.0) {
-    S.status = 0;
+  } else if (g0 == 0.0) {
+    status = 0;
     next = CM_NONE;
   } else if (rel <= D.tol) {
-    if (S.lastWasGrad) {
-      S.status = 0;
+    if (lastWasGrad) {
+      status = 0;
       next = CM_NONE;
     } else {
       next = CM_GRAD;
     }
-  } else if (S.iter >= D.maxIter) {
-    S.status = 1;
+  } else if (iter >= D.maxIter) {
+    status = 1;
     next = CM_NONE;
-  } else if (D.dchi2Tol > 0.0 && wasPending && fabs(S.dchi2) < D.dchi2Tol) {
-    S.status = 0;
+  } else if (D.dchi2Tol > 0.0 && pend && fabs(S.dchi2) < D.dchi2Tol) {
+    status = 0;
     next = CM_NONE;
-  } else if (D.refreshEvery > 0 && S.iter - S.lastGradIter >= D.refreshEvery && !S.lastWasGrad) {
+  } else if (D.refreshEvery > 0 && iter - S.lastGradIter >= D.refreshEvery && !lastWasGrad) {
     next = CM_GRAD;
   }
 
@@ -319,27 +395,27 @@ __global__ __launch_bounds__(64) void k_coef(const InstDesc* __restrict__ desc, 
     double a[M], rho[M];
     for (int j = 0; j < nh; ++j) {           // newest to oldest
       const int s = sl[j];
-      const double al = S.alpha[s];
-      rho[j] = 1.0 / (al * al * S.PD[s][s]);
-      double sq = c[2 * M] * S.gP[s];
-      for (int t = 0; t < nh; ++t) sq += c[M + sl[t]] * S.PD[s][sl[t]];
+      const double al = sal[s];
+      rho[j] = 1.0 / (al * al * sPD[s][s]);
+      double sq = c[2 * M] * sgP[s];
+      for (int t = 0; t < nh; ++t) sq += c[M + sl[t]] * sPD[s][sl[t]];
       a[j] = rho[j] * al * sq;
       c[M + s] -= a[j] * al;
     }
     if (nh > 0) {
-      const double gam = S.PD[head][head] / S.DD[head][head];
+      const double gam = sPD[head][head] / sDD[head][head];
       for (int k = 0; k < 2 * M + 1; ++k) c[k] *= gam;
     }
     for (int j = nh - 1; j >= 0; --j) {      // oldest to newest
       const int s = sl[j];
-      const double al = S.alpha[s];
-      double yr = c[2 * M] * S.gD[s];
-      for (int t = 0; t < nh; ++t) yr += c[M + sl[t]] * S.DD[s][sl[t]] + c[sl[t]] * S.PD[sl[t]][s];
+      const double al = sal[s];
+      double yr = c[2 * M] * sgD[s];
+      for (int t = 0; t < nh; ++t) yr += c[M + sl[t]] * sDD[s][sl[t]] + c[sl[t]] * sPD[sl[t]][s];
       const double beta = rho[j] * al * yr;
       c[s] += al * (a[j] - beta);
     }
-    double gdp = -c[2 * M] * S.gg;
-    for (int t = 0; t < nh; ++t) gdp -= c[sl[t]] * S.gP[sl[t]] + c[M + sl[t]] * S.gD[sl[t]];
+    double gdp = -c[2 * M] * gg;
+    for (int t = 0; t < nh; ++t) gdp -= c[sl[t]] * sgP[sl[t]] + c[M + sl[t]] * sgD[sl[t]];
     for (int k = 0; k < M; ++k) {
       S.coef[k] = -c[k];
       S.coef[MMAX + k] = -c[M + k];
@@ -350,8 +426,8 @@ __global__ __launch_bounds__(64) void k_coef(const InstDesc* __restrict__ desc, 
     if (!(gdp < 0.0) || !isfinite(gdp)) {
       // not a descent direction (round-off at the end of a solve): fall back to an
       // exact-gradient refresh, which resets the scalar bookkeeping
-      next = S.lastWasGrad ? CM_NONE : CM_GRAD;
-      if (next == CM_NONE) S.status = (rel <= 10.0 * D.tol) ? 0 : 2;
+      next = lastWasGrad ? CM_NONE : CM_GRAD;
+      if (next == CM_NONE) status = (rel <= 10.0 * D.tol) ? 0 : 2;
     }
   }
   if (next == CM_HV) {
@@ -364,9 +440,10 @@ __global__ __launch_bounds__(64) void k_coef(const InstDesc* __restrict__ desc, 
   } else {
     jobs[i].mode = CM_NONE;
   }
+  S.status = status;
   S.chainMode = next;
-  S.lastWasGrad = (next == CM_GRAD) ? 1 : (next == CM_HV ? 0 : S.lastWasGrad);
-  D.statusOut[0] = S.status;
+  S.lastWasGrad = (next == CM_GRAD) ? 1 : (next == CM_HV ? 0 : lastWasGrad);
+  D.statusOut[0] = status;
 }
 
 // ------------------------------------------------------------------------ pass B
@@ -389,24 +466,36 @@ __global__ __launch_bounds__(NT) void k_passB(const InstDesc* __restrict__ desc,
   }
   const T cg = T(S.coef[2 * MMAX]);
   const int64_t nvec = D.L * 2 / VW;
-  const V* g = reinterpret_cast<const V*>(D.g);
-  V* P = reinterpret_cast<V*>(D.P);
-  const V* Dp = reinterpret_cast<const V*>(D.D);
-  const int64_t base = (int64_t)blockIdx.x * NT * PASS_EPT;
-#pragma unroll 2
-  for (int kk = 0; kk < PASS_EPT; ++kk) {
-    const int64_t e = base + (int64_t)kk * NT + threadIdx.x;
-    if (e >= nvec) break;
-    V acc = vscale(cg, g[e]);
+  const int64_t vs = D.vstride * 2 / VW;
+  const int64_t e0 = (int64_t)blockIdx.x * PASS_CV + threadIdx.x;
+  V* X = reinterpret_cast<V*>(D.X);
+  const V* g = X + vs;
+  V* P = X + 2 * vs;
+  const V* Dp = X + (2 + M) * vs;
+  bool ok[PASS_U];
+  V acc[PASS_U];
 #pragma unroll
-    for (int j = 0; j < M; ++j) {
-      if (j < nh) {
-        acc = vaxpy(cP[j], P[(int64_t)sl[j] * nvec + e], acc);
-        acc = vaxpy(cD[j], Dp[(int64_t)sl[j] * nvec + e], acc);
-      }
-    }
-    P[(int64_t)ns * nvec + e] = acc;
+  for (int u = 0; u < PASS_U; ++u) {
+    ok[u] = e0 + (int64_t)u * NT < nvec;
+    if (ok[u]) acc[u] = vscale(cg, g[e0 + (int64_t)u * NT]);
   }
+#pragma unroll
+  for (int j = 0; j < M; ++j) {
+    stream_fence();
+    if (j < nh) {
+      const int64_t sp = (int64_t)sl[j] * vs;
+#pragma unroll
+      for (int u = 0; u < PASS_U; ++u)
+        if (ok[u]) acc[u] = vaxpy(cP[j], P[sp + e0 + (int64_t)u * NT], acc[u]);
+#pragma unroll
+      for (int u = 0; u < PASS_U; ++u)
+        if (ok[u]) acc[u] = vaxpy(cD[j], Dp[sp + e0 + (int64_t)u * NT], acc[u]);
+    }
+  }
+  stream_fence();
+#pragma unroll
+  for (int u = 0; u < PASS_U; ++u)
+    if (ok[u]) P[(int64_t)ns * vs + e0 + (int64_t)u * NT] = acc[u];
 }
 
 // ------------------------------------------------------------------------ tables and packing
@@ -457,8 +546,9 @@ __global__ void k_unpack(int n, int C, int batch, const cpx<T>* __restrict__ ext
 // conjugates of their free entries, dead entries 0.  fill = 0: copy every stored entry
 // (live ones; dead entries 0).
 template <typename T>
-__global__ void k_pack(int n, int C, int batch, const cpx<T>* __restrict__ in, int64_t inStride,
-                       const T* __restrict__ sq, int fill, cpx<T>* const* __restrict__ outs, cpx<T>* __restrict__ out0) {
+__global__ void k_pack(int n, int C, int batch, const cpx<T>* __restrict__ in, int64_t inStride, int64_t vcs,
+                       int64_t vcstr, const T* __restrict__ sq, int fill, cpx<T>* const* __restrict__ outs,
+                       cpx<T>* __restrict__ out0) {
   const int h = n / 2;
   const int64_t per = (int64_t)C * n * (h + 1);
   const int64_t tot = per * batch;
@@ -472,7 +562,7 @@ __global__ void k_pack(int n, int C, int batch, const cpx<T>* __restrict__ in, i
       const bool part = is_partner(n, ky, kx);
       const int kyr = (fill && part) ? n - ky : ky;
       const int64_t src = fidx(n, c, kyr, kx);
-      v = in[i * inStride + src];
+      v = in[i * inStride + vview(src, vcs, vcstr)];
       if (sq) v = scale(v, sq[src]);
       if (fill && part) v = conj(v);
     }
@@ -504,7 +594,7 @@ __global__ __launch_bounds__(NT) void k_band_part(const BandJob* __restrict__ jo
     if (e < jb.L) {
       bl[k] = jb.bandI[e];
       if (bl[k] >= 0) {
-        const cpx<T> a = f[e];
+        const cpx<T> a = f[vview(e, jb.vcs, jb.vcstr)];
         double t = (double)a.x * a.x + (double)a.y * a.y;
         if (jb.raw) {
           const double s = (double)sq[e];
