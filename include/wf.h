@@ -70,11 +70,12 @@ enum { WF_F32 = 0, WF_F64 = 1 };
 /* per-instance solver status */
 enum { WF_SOLVE_CONVERGED = 0, WF_SOLVE_MAXITER = 1, WF_SOLVE_NONFINITE = 2 };
 
-/* wf_adjoint flags */
+/* wf_adjoint flags (may be or-ed with WF_MASK) */
 enum {
   WF_ADJ_METRIC = 0,   /* s = R^T x in the full-plane metric (partners filled)          */
-  WF_ADJ_GRAD = 1      /* gradient of a function of x = R s w.r.t. the stored s, in the
+  WF_ADJ_GRAD = 1,     /* gradient of a function of x = R s w.r.t. the stored s, in the
                           d/dRe + i d/dIm convention: 2 R^T x on free entries, 0 else  */
+  WF_MASK = 2          /* wf_forward: x = M R s; wf_adjoint: R^T M x (M = [w > 0])      */
 };
 
 typedef struct {
@@ -156,10 +157,13 @@ int bandpower_qe(wf_ctx* ctx, const wf_problem* prob, int32_t nsim, uint64_t see
 
 /* operator-level calls: `batch` fields sharing prob's geometry, packed contiguously -- */
 
-/* x = R s (eq. ddecomp): s [batch][ncomp][n][n/2+1] complex -> x [batch][ncomp][n][n]. */
-int wf_forward(wf_ctx* ctx, const wf_problem* prob, int32_t batch, const void* s, void* x, void* stream);
+/* x = R s (eq. ddecomp), or M R s with flags WF_MASK:
+ * s [batch][ncomp][n][n/2+1] complex -> x [batch][ncomp][n][n].                         */
+int wf_forward(wf_ctx* ctx, const wf_problem* prob, int32_t batch, const void* s, void* x, int32_t flags,
+               void* stream);
 
-/* s = R^T x (flags WF_ADJ_METRIC) or the stored-coefficient gradient (WF_ADJ_GRAD).  */
+/* s = R^T x (flags WF_ADJ_METRIC) or the stored-coefficient gradient (WF_ADJ_GRAD);
+ * with WF_MASK the input is masked first (adjoint of the masked forward operator).    */
 int wf_adjoint(wf_ctx* ctx, const wf_problem* prob, int32_t batch, const void* x, void* s, int32_t flags,
                void* stream);
 

@@ -18,13 +18,13 @@ from typing import Sequence
 import numpy as np
 
 from . import _lib as L
-from ._lib import (WF_ADJ_GRAD, WF_ADJ_METRIC, WF_F32, WF_F64, WF_NOT_CONVERGED, WF_OK,  # noqa: F401
+from ._lib import (WF_ADJ_GRAD, WF_ADJ_METRIC, WF_F32, WF_F64, WF_MASK, WF_NOT_CONVERGED, WF_OK,  # noqa: F401
                    WF_SOLVE_CONVERGED, WF_SOLVE_MAXITER, WF_SOLVE_NONFINITE)
 
 __all__ = [
     "load", "Context", "Problem", "LbfgsOpts", "SolveStats", "context", "map_wf_solve", "wf_simulate",
     "sim_fisher", "bandpower_qe", "wf_forward", "wf_adjoint", "wf_chi2_grad", "wf_hvp", "wf_band_E",
-    "WFError", "kernel_stats", "reset_kernel_stats", "set_profiling",
+    "WFError", "kernel_stats", "reset_kernel_stats", "set_profiling", "autograd",
 ]
 
 
@@ -299,8 +299,8 @@ def _batch_shape(problem, t, kind):
     raise ValueError(f"expected [batch]{list(shp)}, got {list(t.shape)}")
 
 
-def wf_forward(problem: Problem, s, ctx: Context | None = None):
-    """x = R s for one field [c][n][n/2+1] or a batch [B][c][n][n/2+1] (complex)."""
+def wf_forward(problem: Problem, s, flags: int = 0, ctx: Context | None = None):
+    """x = R s (or M R s with WF_MASK) for one field [c][n][n/2+1] or a batch [B][c][n][n/2+1]."""
     torch = _torch()
     s = s.contiguous()
     if s.dtype != problem.cdtype:
@@ -310,7 +310,7 @@ def wf_forward(problem: Problem, s, ctx: Context | None = None):
     cx = ctx or context(dev)
     x = torch.empty((B, problem.ncomp, problem.n, problem.n), dtype=problem.rdtype, device=s.device)
     cp = problem.c()
-    cx.check(cx.lib.wf_forward(cx.h, C.byref(cp), B, s.data_ptr(), x.data_ptr(), _stream(dev)))
+    cx.check(cx.lib.wf_forward(cx.h, C.byref(cp), B, s.data_ptr(), x.data_ptr(), int(flags), _stream(dev)))
     return x if batched else x[0]
 
 
@@ -392,3 +392,6 @@ def kernel_stats(ctx: Context | None = None) -> dict:
 def reset_kernel_stats(ctx: Context | None = None):
     cx = ctx or context(0)
     cx.check(cx.lib.wf_reset_kernel_stats(cx.h))
+
+
+from . import autograd  # noqa: E402,F401  (torch.autograd.Function wrappers)

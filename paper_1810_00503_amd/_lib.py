@@ -11,7 +11,7 @@ WF_OK, WF_NOT_CONVERGED = 0, 1
 WF_EINVAL, WF_ESHAPE, WF_ENOMEM, WF_EHIP, WF_ENONFINITE = -1, -2, -3, -4, -5
 WF_F32, WF_F64 = 0, 1
 WF_SOLVE_CONVERGED, WF_SOLVE_MAXITER, WF_SOLVE_NONFINITE = 0, 1, 2
-WF_ADJ_METRIC, WF_ADJ_GRAD = 0, 1
+WF_ADJ_METRIC, WF_ADJ_GRAD, WF_MASK = 0, 1, 2
 
 EXPORTS = [
     "wf_create", "wf_destroy", "wf_last_error", "wf_lbfgs_default", "map_wf_solve", "wf_simulate",
@@ -70,7 +70,7 @@ def load(path: str | None = None):
     L.sim_fisher.argtypes = [vp, C.POINTER(WfProblem), i32, C.c_uint64, vp, C.POINTER(WfLbfgsOpts), dp, dp, dp, vp]
     L.bandpower_qe.argtypes = [vp, C.POINTER(WfProblem), i32, C.c_uint64, vp, C.POINTER(WfLbfgsOpts), dp, dp, dp,
                                dp, vp]
-    L.wf_forward.argtypes = [vp, C.POINTER(WfProblem), i32, vp, vp, vp]
+    L.wf_forward.argtypes = [vp, C.POINTER(WfProblem), i32, vp, vp, i32, vp]
     L.wf_adjoint.argtypes = [vp, C.POINTER(WfProblem), i32, vp, vp, i32, vp]
     L.wf_chi2_grad.argtypes = [vp, C.POINTER(WfProblem), i32, vp, dp, vp, vp]
     L.wf_hvp.argtypes = [vp, C.POINTER(WfProblem), i32, vp, vp, vp]

@@ -985,9 +985,12 @@ int bandpower_qe(wf_ctx* ctx, const wf_problem* p, int32_t nsim, uint64_t seed, 
   return nc ? WF_NOT_CONVERGED : WF_OK;
 }
 
-int wf_forward(wf_ctx* ctx, const wf_problem* p, int32_t batch, const void* s, void* x, void* stream) {
+int wf_forward(wf_ctx* ctx, const wf_problem* p, int32_t batch, const void* s, void* x, int32_t flags,
+               void* stream) {
   int rc = check_op(ctx, p, batch, s, x);
   if (rc || batch == 0) return rc;
+  if (flags & ~WF_MASK) return fail(ctx, WF_EINVAL, "bad flags");
+  if ((flags & WF_MASK) && !p->w) return fail(ctx, WF_EINVAL, "WF_MASK needs w");
   StreamScope ss(ctx, stream);
   void *vin, *vy, *vout;
   Job* dj;
@@ -1005,6 +1008,7 @@ int wf_forward(wf_ctx* ctx, const wf_problem* p, int32_t batch, const void* s, v
     hj[i].vcs = hj[i].vcstr = L;
     hj[i].mode = CM_FWD;
     hj[i].boost_band = -1;
+    hj[i].W = (flags & WF_MASK) ? p->w : nullptr;
     hj[i].vin = (char*)vin + (size_t)i * L * eb;
     hj[i].y = (char*)vy + (size_t)i * L * eb;
     hj[i].xout = (char*)x + (size_t)i * c * n * n * rs;
@@ -1019,7 +1023,8 @@ int wf_forward(wf_ctx* ctx, const wf_problem* p, int32_t batch, const void* s, v
 int wf_adjoint(wf_ctx* ctx, const wf_problem* p, int32_t batch, const void* x, void* s, int32_t flags, void* stream) {
   int rc = check_op(ctx, p, batch, x, s);
   if (rc || batch == 0) return rc;
-  if (flags != WF_ADJ_METRIC && flags != WF_ADJ_GRAD) return fail(ctx, WF_EINVAL, "bad flags");
+  if (flags & ~(WF_ADJ_GRAD | WF_MASK)) return fail(ctx, WF_EINVAL, "bad flags");
+  if ((flags & WF_MASK) && !p->w) return fail(ctx, WF_EINVAL, "WF_MASK needs w");
   StreamScope ss(ctx, stream);
   void *vin, *vy, *vout;
   Job* dj;
@@ -1034,8 +1039,9 @@ int wf_adjoint(wf_ctx* ctx, const wf_problem* p, int32_t batch, const void* x, v
   for (int i = 0; i < batch; ++i) {
     std::memset(&hj[i], 0, sizeof(Job));
     hj[i].vcs = hj[i].vcstr = L;
-    hj[i].mode = flags == WF_ADJ_GRAD ? CM_ADJ_GRAD : CM_ADJ;
+    hj[i].mode = (flags & WF_ADJ_GRAD) ? CM_ADJ_GRAD : CM_ADJ;
     hj[i].boost_band = -1;
+    hj[i].W = (flags & WF_MASK) ? p->w : nullptr;
     hj[i].d = (const char*)x + (size_t)i * c * n * n * rs;
     hj[i].y = (char*)vy + (size_t)i * L * eb;
     hj[i].vout = (char*)vout + (size_t)i * L * eb;

@@ -261,13 +261,18 @@ __global__ __launch_bounds__(NT) void k_row(const Job* __restrict__ jobs, const 
     const int64_t cp = (int64_t)c * N * N + pix;
     cpx<T> zf;
     if (adjIn) {
-      zf = mk(dd[cp] * invn, dd[cp + 1] * invn);
+      T x0 = dd[cp], x1 = dd[cp + 1];
+      if (W) {   // masked adjoint: R^T M x
+        if (!(W[pix] > T(0))) x0 = T(0);
+        if (!(W[pix + 1] > T(0))) x1 = T(0);
+      }
+      zf = mk(x0 * invn, x1 * invn);
     } else {
       const cpx<T> zz = buf[b * SBR + j];
       const T x0 = zz.x * invn, x1 = zz.y * invn;
-      if (mode == CM_FWD) {
-        xout[cp] = x0;
-        xout[cp + 1] = x1;
+      if (mode == CM_FWD) {   // masked forward M R s when W is given
+        xout[cp] = (W && !(W[pix] > T(0))) ? T(0) : x0;
+        xout[cp + 1] = (W && !(W[pix + 1] > T(0))) ? T(0) : x1;
         continue;
       }
       const T W0 = W[pix], W1 = W[pix + 1];
