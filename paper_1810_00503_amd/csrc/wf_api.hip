@@ -456,10 +456,6 @@ int solve_core(wf_ctx* ctx, const wf_problem* probs, int B, const wf_lbfgs_opts&
       const int cnt = (int)k.members.size();
       const int dt = k.dtype == WF_F64;
       {
-        Timed t(ctx, KK_POST);
-        HIPCHK(lbfgs_launch(dt, m, LB_POST, dim3(cnt), ddesc + k.first, dst + k.first, djobs + k.first, cnt, ctx->cs));
-      }
-      {
         Timed t(ctx, KK_PASSA);
         HIPCHK(lbfgs_launch(dt, m, LB_PASSA, dim3(k.nchunk, cnt), ddesc + k.first, dst + k.first, djobs + k.first, cnt,
                             ctx->cs));
@@ -472,6 +468,10 @@ int solve_core(wf_ctx* ctx, const wf_problem* probs, int B, const wf_lbfgs_opts&
         Timed t(ctx, KK_PASSB);
         HIPCHK(lbfgs_launch(dt, m, LB_PASSB, dim3(k.nchunk, cnt), ddesc + k.first, dst + k.first, djobs + k.first, cnt,
                             ctx->cs));
+      }
+      {
+        Timed t(ctx, KK_POST);
+        HIPCHK(lbfgs_launch(dt, m, LB_POSTB, dim3(cnt), ddesc + k.first, dst + k.first, djobs + k.first, cnt, ctx->cs));
       }
     }
     return WF_OK;

@@ -376,13 +376,20 @@ __global__ __launch_bounds__(NT) void k_colfwd(const Job* __restrict__ jobs, con
   const cpx<T>* vadd = reinterpret_cast<const cpx<T>*>(jb.vadd);
   const T* sOut = reinterpret_cast<const T*>(jb.sOut);
   cpx<T>* vout = reinterpret_cast<cpx<T>*>(jb.vout);
-  double avo = 0.0, aoo = 0.0;
+  double avo = 0.0, aoo = 0.0, adg = 0.0;
+  double add[MMAX];
+#pragma unroll
+  for (int j = 0; j < MMAX; ++j) add[j] = 0.0;
   int64_t dv[C];
 #pragma unroll
   for (int c = 0; c < C; ++c) {
     const int64_t bs = fidx(N, c, 0, q * TB);
     dv[c] = jb.vcs > 0 ? vview(bs, jb.vcs, jb.vcstr) - bs : 0;
   }
+  // curvature products inside the solver also dot the new Dp with g and the kept Dp_j
+  const bool extras = (mode == CM_HV) && jb.dpBase != nullptr;
+  const cpx<T>* gvec = reinterpret_cast<const cpx<T>*>(jb.gvec);
+  const cpx<T>* dpb = reinterpret_cast<const cpx<T>*>(jb.dpBase);
   for (int e = tid; e < N * TB; e += NT) {
     const int ky = e / TB, col = e % TB, kx = q * TB + col;
     cpx<T> t[C];
@@ -408,6 +415,17 @@ __global__ __launch_bounds__(NT) void k_colfwd(const Job* __restrict__ jobs, con
           avo += (double)v.x * out.x + (double)v.y * out.y;
         }
         aoo += (double)out.x * out.x + (double)out.y * out.y;
+        if (extras) {
+          const cpx<T> gv = gvec[o + dv[c]];
+          adg += (double)gv.x * out.x + (double)gv.y * out.y;
+#pragma unroll
+          for (int j = 0; j < MMAX; ++j) {
+            if ((jb.dpMask >> j) & 1u) {
+              const cpx<T> dj = dpb[(int64_t)j * jb.dpStride + o + dv[c]];
+              add[j] += (double)dj.x * out.x + (double)dj.y * out.y;
+            }
+          }
+        }
       } else if (mode == CM_RAW_GRAD || mode == CM_RAW_HV) {
         const T sq = sOut[o];
         if (fr && sq != T(0)) {
@@ -423,14 +441,37 @@ __global__ __launch_bounds__(NT) void k_colfwd(const Job* __restrict__ jobs, con
       vout[o + dv[c]] = out;
     }
   }
-  if (mode == CM_HV) {
-    const double s1 = block_sum(avo, red);
-    if (tid == 0) jb.part[PK_VO * jb.pstride + q] = s1;
-    const double s2 = block_sum(aoo, red);
-    if (tid == 0) jb.part[PK_OO * jb.pstride + q] = s2;
-  } else if (mode == CM_GRAD) {
-    const double s2 = block_sum(aoo, red);
-    if (tid == 0) jb.part[PK_OO * jb.pstride + q] = s2;
+  if (mode == CM_HV || mode == CM_GRAD) {
+    // one combined reduction: [VO, OO, DG, DD_0 .. DD_{MMAX-1}] -> kinds PK_VO + idx
+    __shared__ double red2[NT / 64][3 + MMAX];
+    const int lane = tid & 63, wv = tid >> 6;
+    const int nv = extras ? 3 + MMAX : 2;
+    const uint32_t mask = jb.dpMask;
+    {
+      const double a0 = wave_sum(avo), a1 = wave_sum(aoo);
+      if (lane == 0) {
+        red2[wv][0] = a0;
+        red2[wv][1] = a1;
+      }
+    }
+    if (extras) {
+      const double a2 = wave_sum(adg);
+      if (lane == 0) red2[wv][2] = a2;
+#pragma unroll
+      for (int j = 0; j < MMAX; ++j) {
+        if ((mask >> j) & 1u) {
+          const double aj = wave_sum(add[j]);
+          if (lane == 0) red2[wv][3 + j] = aj;
+        }
+      }
+    }
+    __syncthreads();
+    if (tid < nv && (tid < 3 || ((mask >> (tid - 3)) & 1u))) {
+      double sum = 0.0;
+#pragma unroll
+      for (int k = 0; k < NT / 64; ++k) sum += red2[k][tid];
+      jb.part[(PK_VO + tid) * jb.pstride + q] = sum;
+    }
   }
 }
 

@@ -81,7 +81,9 @@ enum ChainMode : int {
 };
 
 // partial-sum kinds written per block
-enum { PK_PRIOR = 0, PK_RES = 1, PK_VO = 2, PK_OO = 3, PK_COUNT = 4 };
+enum { PK_PRIOR = 0, PK_RES = 1, PK_VO = 2, PK_OO = 3, PK_DG = 4, PK_DD = 5 };   // PK_DD + j, j < MMAX
+constexpr int MMAX = 16;
+constexpr int PK_COUNT = PK_DD + MMAX;
 
 struct Job {
   int mode;
@@ -109,6 +111,13 @@ struct Job {
   // Chunks are whole column blocks, so a column tile is contiguous.
   int64_t vcs;
   int64_t vcstr;
+  // curvature mode inside the solver: also accumulate out . g (gvec) and out . Dp_j for the
+  // history slots j set in dpMask (Dp_j at dpBase + j * dpStride), all in the same view
+  const void* gvec;
+  const void* dpBase;
+  int64_t dpStride;
+  uint32_t dpMask;
+  int pad2;
 };
 
 // element offset of e in a chunk-interleaved vector view
@@ -117,7 +126,6 @@ __host__ __device__ __forceinline__ int64_t vview(int64_t e, int64_t vcs, int64_
 }
 
 // ------------------------------------------------------------------------ solver state
-constexpr int MMAX = 16;
 
 enum { ST_RUNNING = -1 };   // otherwise WF_SOLVE_* values
 
@@ -130,27 +138,28 @@ enum {
 struct LbState {
   int status;
   int iter;
-  int nhist;
+  int nhist;         // kept pairs: slots head, head-1, ..., head-nhist+1 (mod m)
   int head;
-  int pending;       // newest pair's step not yet applied to w and g
+  int pending;       // the newest pair's step is not yet applied to w and g
   int chainMode;     // mode of the chain enqueued in this iteration
   int lastWasGrad;   // g currently holds an exact gradient
   int ngrad;
   int lastGradIter;
-  int newslot;
+  int newslot;       // slot of the direction being formed
   int m;
-  int pad;
+  int doB;           // pass B runs in this iteration
   double g0norm;
   double gg;
   double chi2;
   double dchi2;
-  double gdotp;
+  double gdotp;      // g . p of the current direction (measured)
   double pDp;
   double alpha[MMAX];
   double PD[MMAX][MMAX];   // p_i . Dp_j
   double DD[MMAX][MMAX];   // Dp_i . Dp_j
-  double gP[MMAX];
-  double gD[MMAX];
+  double gP[MMAX];         // g . p_i of the current gradient
+  double gD[MMAX];         // g . Dp_i
+  double pkD[MMAX];        // p . Dp_j of the current direction (from the Gram entries)
   double coef[2 * MMAX + 1];   // direction on (p_0..p_{m-1}, Dp_0..Dp_{m-1}, g)
   double bytes[KK_COUNT];      // algorithmic bytes moved for this instance
 };

@@ -17,7 +17,7 @@ hipError_t chain_launch_f64(int n, int c, int which, const Job* jobs, int batch,
 hipError_t chain_prepare_f32(int n, int c);
 hipError_t chain_prepare_f64(int n, int c);
 
-enum { LB_ZERO = 0, LB_INIT = 1, LB_POST = 2, LB_PASSA = 3, LB_COEF = 4, LB_PASSB = 5 };
+enum { LB_ZERO = 0, LB_INIT = 1, LB_POSTB = 2, LB_PASSA = 3, LB_COEF = 4, LB_PASSB = 5 };
 hipError_t lbfgs_launch(int dtype, int m, int which, dim3 grid, InstDesc* desc, LbState* st, Job* jobs, int count,
                         hipStream_t s);
 

@@ -1,16 +1,20 @@
 // Device-resident batched L-BFGS (sec. 2.2) and the small kernels around it.
 //
-// Per iteration and instance the sequence is
-//   chain (gradient or curvature product)  ->  k_post  ->  k_passA  ->  k_coef  ->  k_passB
-// k_post   takes the exact step of the quadratic, alpha = -g.p / p.Dp (eq. eq_chib), or
-//          records an exact gradient evaluation;
-// k_passA  applies the step to w and g (w += alpha p, g += alpha Dp) and computes the
-//          dot products of the new g and of the newest pair with the kept pairs;
-// k_coef   updates the Gram entries, tests convergence and runs the two-loop recursion
-//          on coefficients: the direction is a combination of the kept p_i, Dp_i and g
-//          (s_i = alpha_i p_i, y_i = alpha_i Dp_i), so only scalars are touched;
-// k_passB  forms the direction p = sum coef_j b_j in the next history slot.
-// Instances that have stopped skip every kernel (per-instance convergence masks).
+// One iteration of an instance (every kernel skips instances that have stopped):
+//   chain    curvature product Dp = D p of the new direction, or the exact gradient
+//            (transform passes, wf_chain.hpp); in curvature mode it also returns the dots
+//            of Dp with g and with the kept Dp_j;
+//   passA    only after an exact-gradient evaluation: dots of the new g with the kept
+//            pairs (otherwise these come from the previous pass B and a one-step update);
+//   coef     step length alpha = -g.p / p.Dp of the exact line search of a quadratic
+//            (eq. eq_chib), Gram entries of the new pair, stop test after an exact gradient,
+//            and the two-loop recursion run on coefficients: the direction is a combination
+//            of the kept p_i, Dp_i and g (s_i = alpha_i p_i, y_i = alpha_i Dp_i);
+//   passB    applies the pending step (w += alpha p, g += alpha Dp), forms the direction in
+//            the next history slot and measures g.g, g.p and the dots of g with the pairs;
+//   postB    stop test on the measured g, choice of the next chain (curvature product,
+//            exact-gradient refresh, or none) and the remaining Gram entries.
+// Per iteration the vector traffic is about 3m + 13 field vectors (m kept pairs).
 #pragma once
 #include "wf_chain.hpp"
 
@@ -59,9 +63,14 @@ __global__ void k_zero(InstDesc* desc, int batch) {
     X[e] = z;
 }
 
-__device__ __forceinline__ void make_job(Job& jb, const InstDesc& D, int mode, int slot) {
-  const size_t eb = (size_t)D.esize;
-  char* X = reinterpret_cast<char*>(D.X);
+__device__ __forceinline__ char* vec_ptr(const InstDesc& D, int v) {
+  return reinterpret_cast<char*>(D.X) + (size_t)v * D.vstride * D.esize;
+}
+
+// slots of the kept pairs, newest first
+__device__ __forceinline__ int slot_of(int head, int j, int m) { return (head - j + 2 * m) % m; }
+
+__device__ __forceinline__ void make_job(Job& jb, const InstDesc& D, int mode, int slot, uint32_t dpMask) {
   jb.mode = mode;
   jb.boost_band = -1;
   jb.sim = 0;
@@ -79,25 +88,30 @@ __device__ __forceinline__ void make_job(Job& jb, const InstDesc& D, int mode, i
   jb.pstride = D.pstride;
   jb.vcs = D.L;
   jb.vcstr = D.L;
-  const size_t vb = (size_t)D.vstride * eb;
+  jb.gvec = nullptr;
+  jb.dpBase = nullptr;
+  jb.dpStride = D.vstride;
+  jb.dpMask = 0;
   if (mode == CM_HV) {
-    char* p = X + (size_t)(2 + slot) * vb;
-    char* dp = X + (size_t)(2 + D.m + slot) * vb;
+    char* p = vec_ptr(D, 2 + slot);
     jb.vin = p;
     jb.vadd = p;
-    jb.vout = dp;
+    jb.vout = vec_ptr(D, 2 + D.m + slot);
+    jb.gvec = vec_ptr(D, 1);
+    jb.dpBase = vec_ptr(D, 2 + D.m);
+    jb.dpMask = dpMask;
   } else {
-    jb.vin = X;         // w
-    jb.vadd = X;
-    jb.vout = X + vb;   // g
+    jb.vin = vec_ptr(D, 0);    // w
+    jb.vadd = vec_ptr(D, 0);
+    jb.vout = vec_ptr(D, 1);   // g
   }
 }
 
-__device__ __forceinline__ void add_chain_bytes(LbState& S, const InstDesc& D, int mode) {
+__device__ __forceinline__ void add_chain_bytes(LbState& S, const InstDesc& D, int mode, int extra) {
   const double V = D.vbytes;
   S.bytes[KK_COLINV] += 2.0 * V;                              // read field, write intermediate
   S.bytes[KK_ROW] += 2.0 * V + (mode == CM_GRAD ? V : 0.0);    // intermediate in/out (+ data)
-  S.bytes[KK_COLFWD] += 3.0 * V;                              // intermediate, added term, output
+  S.bytes[KK_COLFWD] += (3.0 + extra) * V;                    // intermediate, added term, output (+ dots)
 }
 
 __global__ void k_init(InstDesc* desc, LbState* st, Job* jobs, int batch) {
@@ -116,6 +130,7 @@ __global__ void k_init(InstDesc* desc, LbState* st, Job* jobs, int batch) {
   S.lastWasGrad = 0;
   S.ngrad = 0;
   S.lastGradIter = 0;
+  S.doB = 0;
   S.g0norm = -1.0;
   S.gg = 0.0;
   S.chi2 = 0.0;
@@ -124,125 +139,52 @@ __global__ void k_init(InstDesc* desc, LbState* st, Job* jobs, int batch) {
   S.pDp = 0.0;
   for (int k = 0; k < KK_COUNT; ++k) S.bytes[k] = 0.0;
   S.bytes[KK_MISC] += D.vbytes;   // zeroing w
-  add_chain_bytes(S, D, CM_GRAD);
-  make_job(jobs[i], D, CM_GRAD, 0);
+  add_chain_bytes(S, D, CM_GRAD, 0);
+  make_job(jobs[i], D, CM_GRAD, 0, 0u);
+  D.statusOut[0] = ST_RUNNING;
 }
 
-// ------------------------------------------------------------------------ post-chain
-__device__ __forceinline__ double wave_block_sum(const double* p, int nb) {
-  double a = 0.0;
-  for (int b = threadIdx.x; b < nb; b += 64) a += p[b];
-  return wave_sum(a);
-}
-
-__global__ __launch_bounds__(64) void k_post(const InstDesc* __restrict__ desc, LbState* st, Job* jobs) {
-  const int i = blockIdx.x;
-  LbState& S = st[i];
-  if (S.status != ST_RUNNING) return;
-  const InstDesc& D = desc[i];
-  const int mode = S.chainMode;
-  const int ncol = (D.n / 2) / TB, nrow = D.n / RB;
-  const double* part = D.partChain;
-  if (mode == CM_HV) {
-    const double pDp = wave_block_sum(part + PK_VO * D.pstride, ncol);
-    if (threadIdx.x != 0) return;
-    if (!(pDp > 0.0) || !isfinite(pDp)) {
-      S.status = 2;
-      D.statusOut[0] = 2;
-      jobs[i].mode = CM_NONE;
-      return;
-    }
-    const double alpha = -S.gdotp / pDp;
-    const int ns = S.newslot;
-    S.alpha[ns] = alpha;
-    S.head = ns;
-    S.nhist = S.nhist + 1 < S.m ? S.nhist + 1 : S.m;
-    S.pending = 1;
-    S.pDp = pDp;
-    S.dchi2 = 4.0 * (alpha * S.gdotp + 0.5 * alpha * alpha * pDp);
-    S.chi2 += S.dchi2;
-    S.iter += 1;
-  } else if (mode == CM_GRAD) {
-    const double wsq = wave_block_sum(part + PK_PRIOR * D.pstride, ncol);
-    const double rsq = wave_block_sum(part + PK_RES * D.pstride, nrow);
-    if (threadIdx.x != 0) return;
-    S.chi2 = 2.0 * wsq + rsq;
-    S.ngrad += 1;
-    S.lastGradIter = S.iter;
-    S.pending = 0;
-    if (!isfinite(S.chi2)) {
-      S.status = 2;
-      D.statusOut[0] = 2;
-      jobs[i].mode = CM_NONE;
-    }
-  }
-}
-
-// ------------------------------------------------------------------------ pass A
+// ------------------------------------------------------------------------ pass A (dots only)
+// After an exact gradient: g.g, g.p_j, g.Dp_j for the kept pairs, one slot at a time.
 template <typename T, int M>
 __global__ __launch_bounds__(NT) void k_passA(const InstDesc* __restrict__ desc, const LbState* __restrict__ st) {
   const int i = blockIdx.y;
   const LbState& S = st[i];
-  if (S.status != ST_RUNNING) return;
+  if (S.status != ST_RUNNING || S.chainMode != CM_GRAD) return;
   const InstDesc& D = desc[i];
   using V = typename VecT<T>::type;
   constexpr int VW = VecT<T>::W;
   __shared__ double red[NT / 64][NDOT];
-  const int nh = S.nhist, head = S.head, pend = S.pending;
-  const T al = pend ? T(S.alpha[head]) : T(0);
+  const int nh = S.nhist, head = S.head;
   const int64_t nvec = D.L * 2 / VW;
-  const int64_t vs = D.vstride * 2 / VW;                  // vector elements between vectors
+  const int64_t vs = D.vstride * 2 / VW;
   const int64_t e0 = (int64_t)blockIdx.x * PASS_CV + threadIdx.x;
-  V* X = reinterpret_cast<V*>(D.X);
-  V* w = X;
-  V* g = X + vs;
+  const V* X = reinterpret_cast<const V*>(D.X);
+  const V* g = X + vs;
   const V* P = X + 2 * vs;
   const V* Dp = X + (2 + M) * vs;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   bool ok[PASS_U];
-#pragma unroll
-  for (int u = 0; u < PASS_U; ++u) ok[u] = e0 + (int64_t)u * NT < nvec;
-
-  // the new gradient (after the pending step) and the newest pair
-  V gv[PASS_U], ph[PASS_U], dh[PASS_U];
+  V gv[PASS_U];
+  double gg = 0.0;
 #pragma unroll
   for (int u = 0; u < PASS_U; ++u) {
-    const int64_t e = e0 + (int64_t)u * NT;
+    ok[u] = e0 + (int64_t)u * NT < nvec;
     if (ok[u]) {
-      gv[u] = g[e];
-      if (pend) {
-        ph[u] = P[(int64_t)head * vs + e];
-        dh[u] = Dp[(int64_t)head * vs + e];
-      }
+      gv[u] = g[e0 + (int64_t)u * NT];
+      gg += vdot(gv[u], gv[u]);
     }
   }
-  double gg = 0.0;
-  if (pend) {
-#pragma unroll
-    for (int u = 0; u < PASS_U; ++u) {
-      const int64_t e = e0 + (int64_t)u * NT;
-      if (ok[u]) {
-        const V wv0 = w[e];
-        w[e] = vaxpy(al, ph[u], wv0);
-        gv[u] = vaxpy(al, dh[u], gv[u]);
-        g[e] = gv[u];
-      }
-    }
-  }
-#pragma unroll
-  for (int u = 0; u < PASS_U; ++u)
-    if (ok[u]) gg += vdot(gv[u], gv[u]);
   {
     const double a = wave_sum(gg);
-    if (lane == 0) red[wv][5 * M] = a;
+    if (lane == 0) red[wv][2 * M] = a;
   }
-  // one history slot at a time: dots with the new gradient and with the newest pair
 #pragma unroll
   for (int j = 0; j < M; ++j) {
     stream_fence();
-    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0, a4 = 0.0;
+    double a0 = 0.0, a1 = 0.0;
     if (j < nh) {
-      const int64_t sp = (int64_t)((head - j + 2 * M) % M) * vs;
+      const int64_t sp = (int64_t)slot_of(head, j, M) * vs;
       V pv[PASS_U], dv[PASS_U];
 #pragma unroll
       for (int u = 0; u < PASS_U; ++u)
@@ -255,29 +197,18 @@ __global__ __launch_bounds__(NT) void k_passA(const InstDesc* __restrict__ desc,
         if (ok[u]) {
           a0 += vdot(gv[u], pv[u]);
           a1 += vdot(gv[u], dv[u]);
-          if (pend) {
-            a2 += vdot(ph[u], dv[u]);
-            a3 += vdot(pv[u], dh[u]);
-            a4 += vdot(dh[u], dv[u]);
-          }
         }
       }
     }
     a0 = wave_sum(a0);
     a1 = wave_sum(a1);
-    a2 = wave_sum(a2);
-    a3 = wave_sum(a3);
-    a4 = wave_sum(a4);
     if (lane == 0) {
       red[wv][j] = a0;
       red[wv][M + j] = a1;
-      red[wv][2 * M + j] = a2;
-      red[wv][3 * M + j] = a3;
-      red[wv][4 * M + j] = a4;
     }
   }
   __syncthreads();
-  if (threadIdx.x < 5 * M + 1) {
+  if (threadIdx.x < 2 * M + 1) {
     double t = 0.0;
 #pragma unroll
     for (int k = 0; k < NT / 64; ++k) t += red[k][threadIdx.x];
@@ -285,165 +216,194 @@ __global__ __launch_bounds__(NT) void k_passA(const InstDesc* __restrict__ desc,
   }
 }
 
+// sum of `cnt` partial rows (stride `stride`) of column t, 4 threads per column
+__device__ __forceinline__ void reduce_columns(const double* part, int nblk, int stride, int ncol, double* sums,
+                                               double (*part4)[NDOT]) {
+  const int t = threadIdx.x & 63, q = threadIdx.x >> 6;
+  if (t < ncol) {
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    int b = q;
+    for (; b + 12 < nblk; b += 16) {
+      a0 += part[(int64_t)b * stride + t];
+      a1 += part[(int64_t)(b + 4) * stride + t];
+      a2 += part[(int64_t)(b + 8) * stride + t];
+      a3 += part[(int64_t)(b + 12) * stride + t];
+    }
+    for (; b < nblk; b += 4) a0 += part[(int64_t)b * stride + t];
+    part4[q][t] = (a0 + a1) + (a2 + a3);
+  }
+  __syncthreads();
+  if (threadIdx.x < ncol) sums[threadIdx.x] = (part4[0][threadIdx.x] + part4[1][threadIdx.x]) +
+                                              (part4[2][threadIdx.x] + part4[3][threadIdx.x]);
+  __syncthreads();
+}
+
+// sum over the `nb` blocks of chain partial kind k (a row of stride pstride)
+__device__ __forceinline__ double chain_sum(const InstDesc& D, int kind, int nb) {
+  double a = 0.0;
+  for (int b = 0; b < nb; ++b) a += D.partChain[kind * D.pstride + b];
+  return a;
+}
+
 // ------------------------------------------------------------------------ coefficients
-// One work-group per instance: the partial sums and the small Gram state are staged in
-// LDS by all threads, then thread 0 runs the scalar recursion out of LDS.
+// 256 threads per instance; thread 0 runs the scalar part out of LDS.
 template <int M>
 __global__ __launch_bounds__(256) void k_coef(const InstDesc* __restrict__ desc, LbState* st, Job* jobs) {
   const int i = blockIdx.x;
   LbState& S = st[i];
   if (S.status != ST_RUNNING) return;
   const InstDesc& D = desc[i];
+  const int mode = S.chainMode;
   __shared__ double sums[NDOT];
+  __shared__ double part4[4][NDOT];
+  __shared__ double chs[3 + MMAX + 2];
   __shared__ double sPD[M][M], sDD[M][M], sal[M], sgP[M], sgD[M];
-  const int nblk = D.nchunk;
-  {
-    // 4 threads per sum, each over every 4th block with 4 independent loads in flight;
-    // the four parts are combined in a fixed order
-    __shared__ double part4[4][NDOT];
-    const int t = threadIdx.x & 63, q = threadIdx.x >> 6;
-    if (t < 5 * M + 1) {
-      double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-      int b = q;
-      for (; b + 12 < nblk; b += 16) {
-        a0 += D.partA[(int64_t)b * NDOT + t];
-        a1 += D.partA[(int64_t)(b + 4) * NDOT + t];
-        a2 += D.partA[(int64_t)(b + 8) * NDOT + t];
-        a3 += D.partA[(int64_t)(b + 12) * NDOT + t];
-      }
-      for (; b < nblk; b += 4) a0 += D.partA[(int64_t)b * NDOT + t];
-      part4[q][t] = (a0 + a1) + (a2 + a3);
+  const int ncol = (D.n / 2) / TB, nrow = D.n / RB;
+  if (mode == CM_GRAD) reduce_columns(D.partA, D.nchunk, NDOT, 2 * M + 1, sums, part4);
+  // chain partial sums (fixed order, one thread per kind)
+  if (threadIdx.x < 3 + M + 2) {
+    const int t = threadIdx.x;
+    double a = 0.0;
+    if (t < 3 + M) {
+      if (mode == CM_HV && (t < 3 || t - 3 < M)) a = chain_sum(D, PK_VO + t, ncol);
+    } else if (mode == CM_GRAD) {
+      a = (t == 3 + M) ? chain_sum(D, PK_PRIOR, ncol) : chain_sum(D, PK_RES, nrow);
     }
-    __syncthreads();
-    if (threadIdx.x < 5 * M + 1)
-      sums[threadIdx.x] = (part4[0][threadIdx.x] + part4[1][threadIdx.x]) +
-                          (part4[2][threadIdx.x] + part4[3][threadIdx.x]);
+    chs[t] = a;
   }
   for (int t = threadIdx.x; t < M * M; t += blockDim.x) {
     sPD[t / M][t % M] = S.PD[t / M][t % M];
     sDD[t / M][t % M] = S.DD[t / M][t % M];
   }
-  for (int t = threadIdx.x; t < M; t += blockDim.x) sal[t] = S.alpha[t];
+  for (int t = threadIdx.x; t < M; t += blockDim.x) {
+    sal[t] = S.alpha[t];
+    sgP[t] = S.gP[t];
+    sgD[t] = S.gD[t];
+  }
   __syncthreads();
   if (threadIdx.x != 0) return;
 
-  const int nh = S.nhist, head = S.head;
-  const int pend = S.pending;
-  int sl[M];
-  for (int j = 0; j < M; ++j) sl[j] = (head - j + 2 * M) % M;
-  // bytes of the pass just finished
-  S.bytes[KK_PASSA] += D.vbytes * (1.0 + 2.0 * nh + (pend ? 3.0 : 0.0));
-  for (int j = 0; j < nh; ++j) {
-    const int s = sl[j];
-    sgP[s] = sums[j];
-    sgD[s] = sums[M + j];
-    S.gP[s] = sums[j];
-    S.gD[s] = sums[M + j];
-    if (pend) {
-      sPD[head][s] = sums[2 * M + j];
-      sPD[s][head] = sums[3 * M + j];
-      sDD[head][s] = sums[4 * M + j];
-      sDD[s][head] = sums[4 * M + j];
-      S.PD[head][s] = sums[2 * M + j];
-      S.PD[s][head] = sums[3 * M + j];
-      S.DD[head][s] = sums[4 * M + j];
-      S.DD[s][head] = sums[4 * M + j];
-    }
-  }
-  const double gg = sums[5 * M];
-  S.gg = gg;
-  S.pending = 0;
-  double g0 = S.g0norm;
-  if (g0 < 0.0) {
-    g0 = sqrt(gg);
-    S.g0norm = g0;
-  }
-  const double rel = g0 > 0.0 ? sqrt(gg) / g0 : 0.0;
-  const int lastWasGrad = S.lastWasGrad;
-  const int iter = S.iter;
-
-  int next = CM_HV;
   int status = ST_RUNNING;
-  if (!isfinite(gg)) {
-    status = 2;
-    next = CM_NONE;
-  } else if (g0 == 0.0) {
-    status = 0;
-    next = CM_NONE;
-  } else if (rel <= D.tol) {
-    if (lastWasGrad) {
-      status = 0;
-      next = CM_NONE;
-    } else {
-      next = CM_GRAD;
+  int nh = S.nhist, head = S.head;
+  if (mode == CM_HV) {
+    const double pDp = chs[0], DpDp = chs[1], DpG = chs[2];
+    if (!(pDp > 0.0) || !isfinite(pDp) || !isfinite(DpDp)) {
+      S.status = 2;
+      D.statusOut[0] = 2;
+      jobs[i].mode = CM_NONE;
+      S.chainMode = CM_NONE;
+      S.doB = 0;
+      return;
     }
-  } else if (iter >= D.maxIter) {
-    status = 1;
-    next = CM_NONE;
-  } else if (D.dchi2Tol > 0.0 && pend && fabs(S.dchi2) < D.dchi2Tol) {
-    status = 0;
-    next = CM_NONE;
-  } else if (D.refreshEvery > 0 && iter - S.lastGradIter >= D.refreshEvery && !lastWasGrad) {
-    next = CM_GRAD;
+    const int ns = S.newslot;
+    const double alpha = -S.gdotp / pDp;
+    // Gram entries of the new pair (p_k, Dp_k) in slot ns against the kept pairs: p_k . Dp_j
+    // from the previous pass B, p_j . Dp_k = p_k . Dp_j (D is symmetric), Dp_k . Dp_j
+    // measured by the chain
+    for (int j = 0; j < nh; ++j) {
+      const int sj = slot_of(head, j, M);
+      if (sj == ns) continue;
+      sPD[ns][sj] = S.pkD[sj];
+      sPD[sj][ns] = S.pkD[sj];
+      sDD[ns][sj] = chs[3 + sj];
+      sDD[sj][ns] = chs[3 + sj];
+      // one-step update of the dots of g_{k+1} = g_k + alpha Dp_k with the kept pairs
+      sgP[sj] += alpha * sPD[sj][ns];
+      sgD[sj] += alpha * sDD[ns][sj];
+    }
+    sPD[ns][ns] = pDp;
+    sDD[ns][ns] = DpDp;
+    sgP[ns] = S.gdotp + alpha * pDp;
+    sgD[ns] = DpG + alpha * DpDp;
+    sal[ns] = alpha;
+    head = ns;
+    nh = nh + 1 < M ? nh + 1 : M;
+    S.head = head;
+    S.nhist = nh;
+    S.alpha[ns] = alpha;
+    S.pending = 1;
+    S.pDp = pDp;
+    S.dchi2 = 4.0 * (alpha * S.gdotp + 0.5 * alpha * alpha * pDp);
+    S.chi2 += S.dchi2;
+    S.iter += 1;
+    S.lastWasGrad = 0;
+    for (int j = 0; j < nh; ++j) {
+      const int sj = slot_of(head, j, M);
+      for (int t = 0; t < nh; ++t) {
+        const int st2 = slot_of(head, t, M);
+        S.PD[sj][st2] = sPD[sj][st2];
+        S.DD[sj][st2] = sDD[sj][st2];
+      }
+      S.gP[sj] = sgP[sj];
+      S.gD[sj] = sgD[sj];
+    }
+  } else if (mode == CM_GRAD) {
+    S.chi2 = 2.0 * chs[3 + M] + chs[4 + M];
+    S.ngrad += 1;
+    S.lastGradIter = S.iter;
+    S.pending = 0;
+    S.lastWasGrad = 1;
+    S.bytes[KK_PASSA] += D.vbytes * (1.0 + 2.0 * nh);
+    for (int j = 0; j < nh; ++j) {
+      const int sj = slot_of(head, j, M);
+      sgP[sj] = sums[j];
+      sgD[sj] = sums[M + j];
+      S.gP[sj] = sums[j];
+      S.gD[sj] = sums[M + j];
+    }
+    const double gg = sums[2 * M];
+    S.gg = gg;
+    if (S.g0norm < 0.0) S.g0norm = sqrt(gg);
+    const double g0 = S.g0norm;
+    const double rel = g0 > 0.0 ? sqrt(gg) / g0 : 0.0;
+    if (!isfinite(gg) || !isfinite(S.chi2)) status = 2;
+    else if (g0 == 0.0 || rel <= D.tol) status = 0;
+    else if (S.iter >= D.maxIter) status = 1;
   }
-
-  if (next == CM_HV) {
-    // two-loop recursion in the coefficients of (p_0..p_{M-1}, Dp_0..Dp_{M-1}, g)
-    double c[2 * M + 1];
-    for (int k = 0; k < 2 * M + 1; ++k) c[k] = 0.0;
-    c[2 * M] = 1.0;
-    double a[M], rho[M];
-    for (int j = 0; j < nh; ++j) {           // newest to oldest
-      const int s = sl[j];
-      const double al = sal[s];
-      rho[j] = 1.0 / (al * al * sPD[s][s]);
-      double sq = c[2 * M] * sgP[s];
-      for (int t = 0; t < nh; ++t) sq += c[M + sl[t]] * sPD[s][sl[t]];
-      a[j] = rho[j] * al * sq;
-      c[M + s] -= a[j] * al;
-    }
-    if (nh > 0) {
-      const double gam = sPD[head][head] / sDD[head][head];
-      for (int k = 0; k < 2 * M + 1; ++k) c[k] *= gam;
-    }
-    for (int j = nh - 1; j >= 0; --j) {      // oldest to newest
-      const int s = sl[j];
-      const double al = sal[s];
-      double yr = c[2 * M] * sgD[s];
-      for (int t = 0; t < nh; ++t) yr += c[M + sl[t]] * sDD[s][sl[t]] + c[sl[t]] * sPD[sl[t]][s];
-      const double beta = rho[j] * al * yr;
-      c[s] += al * (a[j] - beta);
-    }
-    double gdp = -c[2 * M] * gg;
-    for (int t = 0; t < nh; ++t) gdp -= c[sl[t]] * sgP[sl[t]] + c[M + sl[t]] * sgD[sl[t]];
-    for (int k = 0; k < M; ++k) {
-      S.coef[k] = -c[k];
-      S.coef[MMAX + k] = -c[M + k];
-    }
-    S.coef[2 * MMAX] = -c[2 * M];
-    S.gdotp = gdp;
-    S.newslot = (head + 1) % M;
-    if (!(gdp < 0.0) || !isfinite(gdp)) {
-      // not a descent direction (round-off at the end of a solve): fall back to an
-      // exact-gradient refresh, which resets the scalar bookkeeping
-      next = lastWasGrad ? CM_NONE : CM_GRAD;
-      if (next == CM_NONE) status = (rel <= 10.0 * D.tol) ? 0 : 2;
-    }
-  }
-  if (next == CM_HV) {
-    S.bytes[KK_PASSB] += D.vbytes * (2.0 * nh + 2.0);
-    add_chain_bytes(S, D, CM_HV);
-    make_job(jobs[i], D, CM_HV, S.newslot);
-  } else if (next == CM_GRAD) {
-    add_chain_bytes(S, D, CM_GRAD);
-    make_job(jobs[i], D, CM_GRAD, 0);
-  } else {
+  if (status != ST_RUNNING) {
+    S.status = status;
+    D.statusOut[0] = status;
     jobs[i].mode = CM_NONE;
+    S.chainMode = CM_NONE;
+    S.doB = 0;
+    return;
   }
-  S.status = status;
-  S.chainMode = next;
-  S.lastWasGrad = (next == CM_GRAD) ? 1 : (next == CM_HV ? 0 : lastWasGrad);
-  D.statusOut[0] = status;
+  // two-loop recursion in the coefficients of (p_0..p_{M-1}, Dp_0..Dp_{M-1}, g)
+  double c[2 * M + 1];
+  for (int k = 0; k < 2 * M + 1; ++k) c[k] = 0.0;
+  c[2 * M] = 1.0;
+  double a[M], rho[M];
+  int sl[M];
+  for (int j = 0; j < M; ++j) sl[j] = slot_of(head, j, M);
+  for (int j = 0; j < nh; ++j) {           // newest to oldest
+    const int s = sl[j];
+    const double al = sal[s];
+    rho[j] = 1.0 / (al * al * sPD[s][s]);
+    double sq = c[2 * M] * sgP[s];
+    for (int t = 0; t < nh; ++t) sq += c[M + sl[t]] * sPD[s][sl[t]];
+    a[j] = rho[j] * al * sq;
+    c[M + s] -= a[j] * al;
+  }
+  if (nh > 0) {
+    const double gam = sPD[head][head] / sDD[head][head];
+    for (int k = 0; k < 2 * M + 1; ++k) c[k] *= gam;
+  }
+  for (int j = nh - 1; j >= 0; --j) {      // oldest to newest
+    const int s = sl[j];
+    const double al = sal[s];
+    double yr = c[2 * M] * sgD[s];
+    for (int t = 0; t < nh; ++t) yr += c[M + sl[t]] * sDD[s][sl[t]] + c[sl[t]] * sPD[sl[t]][s];
+    const double beta = rho[j] * al * yr;
+    c[s] += al * (a[j] - beta);
+  }
+  for (int k = 0; k < M; ++k) {
+    S.coef[k] = -c[k];
+    S.coef[MMAX + k] = -c[M + k];
+  }
+  S.coef[2 * MMAX] = -c[2 * M];
+  S.newslot = (head + 1) % M;
+  S.doB = 1;
+  S.bytes[KK_PASSB] += D.vbytes * (2.0 * nh + 2.0 + (S.pending ? 3.0 : 0.0));
 }
 
 // ------------------------------------------------------------------------ pass B
@@ -451,51 +411,183 @@ template <typename T, int M>
 __global__ __launch_bounds__(NT) void k_passB(const InstDesc* __restrict__ desc, const LbState* __restrict__ st) {
   const int i = blockIdx.y;
   const LbState& S = st[i];
-  if (S.status != ST_RUNNING || S.chainMode != CM_HV) return;
+  if (S.status != ST_RUNNING || !S.doB) return;
   const InstDesc& D = desc[i];
   using V = typename VecT<T>::type;
   constexpr int VW = VecT<T>::W;
-  const int nh = S.nhist, head = S.head, ns = S.newslot;
-  int sl[M];
+  __shared__ double red[NT / 64][NDOT];
+  const int nh = S.nhist, head = S.head, ns = S.newslot, pend = S.pending;
+  const T al = pend ? T(S.alpha[head]) : T(0);
   T cP[M], cD[M];
 #pragma unroll
   for (int j = 0; j < M; ++j) {
-    sl[j] = (head - j + 2 * M) % M;
-    cP[j] = T(S.coef[sl[j]]);
-    cD[j] = T(S.coef[MMAX + sl[j]]);
+    const int sj = slot_of(head, j, M);
+    cP[j] = T(S.coef[sj]);
+    cD[j] = T(S.coef[MMAX + sj]);
   }
   const T cg = T(S.coef[2 * MMAX]);
   const int64_t nvec = D.L * 2 / VW;
   const int64_t vs = D.vstride * 2 / VW;
   const int64_t e0 = (int64_t)blockIdx.x * PASS_CV + threadIdx.x;
   V* X = reinterpret_cast<V*>(D.X);
-  const V* g = X + vs;
+  V* w = X;
+  V* g = X + vs;
   V* P = X + 2 * vs;
   const V* Dp = X + (2 + M) * vs;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   bool ok[PASS_U];
-  V acc[PASS_U];
+  V gv[PASS_U], acc[PASS_U];
 #pragma unroll
   for (int u = 0; u < PASS_U; ++u) {
     ok[u] = e0 + (int64_t)u * NT < nvec;
-    if (ok[u]) acc[u] = vscale(cg, g[e0 + (int64_t)u * NT]);
+    if (ok[u]) gv[u] = g[e0 + (int64_t)u * NT];
   }
+  if (pend) {   // the step of the newest pair: w += alpha p, g += alpha Dp
+    const int64_t sh = (int64_t)head * vs;
+#pragma unroll
+    for (int u = 0; u < PASS_U; ++u) {
+      const int64_t e = e0 + (int64_t)u * NT;
+      if (ok[u]) {
+        const V ph = P[sh + e], dh = Dp[sh + e];
+        w[e] = vaxpy(al, ph, w[e]);
+        gv[u] = vaxpy(al, dh, gv[u]);
+        g[e] = gv[u];
+      }
+    }
+  }
+  double gg = 0.0;
+#pragma unroll
+  for (int u = 0; u < PASS_U; ++u) {
+    if (ok[u]) {
+      gg += vdot(gv[u], gv[u]);
+      acc[u] = vscale(cg, gv[u]);
+    }
+  }
+  {
+    const double a = wave_sum(gg);
+    if (lane == 0) red[wv][2 * M] = a;
+  }
+  // one kept pair at a time: accumulate the direction and the dots of g with the pair
 #pragma unroll
   for (int j = 0; j < M; ++j) {
     stream_fence();
+    double a0 = 0.0, a1 = 0.0;
     if (j < nh) {
-      const int64_t sp = (int64_t)sl[j] * vs;
+      const int64_t sp = (int64_t)slot_of(head, j, M) * vs;
+      V pv[PASS_U], dv[PASS_U];
 #pragma unroll
       for (int u = 0; u < PASS_U; ++u)
-        if (ok[u]) acc[u] = vaxpy(cP[j], P[sp + e0 + (int64_t)u * NT], acc[u]);
+        if (ok[u]) pv[u] = P[sp + e0 + (int64_t)u * NT];
 #pragma unroll
       for (int u = 0; u < PASS_U; ++u)
-        if (ok[u]) acc[u] = vaxpy(cD[j], Dp[sp + e0 + (int64_t)u * NT], acc[u]);
+        if (ok[u]) dv[u] = Dp[sp + e0 + (int64_t)u * NT];
+#pragma unroll
+      for (int u = 0; u < PASS_U; ++u) {
+        if (ok[u]) {
+          a0 += vdot(gv[u], pv[u]);
+          a1 += vdot(gv[u], dv[u]);
+          acc[u] = vaxpy(cP[j], pv[u], acc[u]);
+          acc[u] = vaxpy(cD[j], dv[u], acc[u]);
+        }
+      }
+    }
+    a0 = wave_sum(a0);
+    a1 = wave_sum(a1);
+    if (lane == 0) {
+      red[wv][j] = a0;
+      red[wv][M + j] = a1;
     }
   }
   stream_fence();
+  double gp = 0.0;
 #pragma unroll
-  for (int u = 0; u < PASS_U; ++u)
-    if (ok[u]) P[(int64_t)ns * vs + e0 + (int64_t)u * NT] = acc[u];
+  for (int u = 0; u < PASS_U; ++u) {
+    if (ok[u]) {
+      P[(int64_t)ns * vs + e0 + (int64_t)u * NT] = acc[u];
+      gp += vdot(gv[u], acc[u]);
+    }
+  }
+  {
+    const double a = wave_sum(gp);
+    if (lane == 0) red[wv][2 * M + 1] = a;
+  }
+  __syncthreads();
+  if (threadIdx.x < 2 * M + 2) {
+    double t = 0.0;
+#pragma unroll
+    for (int k = 0; k < NT / 64; ++k) t += red[k][threadIdx.x];
+    D.partA[(int64_t)blockIdx.x * NDOT + threadIdx.x] = t;
+  }
+}
+
+// ------------------------------------------------------------------------ post B
+template <int M>
+__global__ __launch_bounds__(256) void k_postB(const InstDesc* __restrict__ desc, LbState* st, Job* jobs) {
+  const int i = blockIdx.x;
+  LbState& S = st[i];
+  if (S.status != ST_RUNNING || !S.doB) return;
+  const InstDesc& D = desc[i];
+  __shared__ double sums[NDOT];
+  __shared__ double part4[4][NDOT];
+  reduce_columns(D.partA, D.nchunk, NDOT, 2 * M + 2, sums, part4);
+  if (threadIdx.x != 0) return;
+  const int nh = S.nhist, head = S.head, ns = S.newslot;
+  S.pending = 0;
+  S.doB = 0;
+  // the measured dots of the current gradient replace the one-step updates
+  for (int j = 0; j < nh; ++j) {
+    const int sj = slot_of(head, j, M);
+    S.gP[sj] = sums[j];
+    S.gD[sj] = sums[M + j];
+  }
+  const double gg = sums[2 * M], gp = sums[2 * M + 1];
+  S.gg = gg;
+  S.gdotp = gp;
+  const double g0 = S.g0norm;
+  const double rel = g0 > 0.0 ? sqrt(gg) / g0 : 0.0;
+  int next = CM_HV, status = ST_RUNNING;
+  if (!isfinite(gg) || !isfinite(gp)) {
+    status = 2;
+  } else if (rel <= D.tol) {
+    next = CM_GRAD;                 // confirm with the exact gradient
+  } else if (S.iter >= D.maxIter) {
+    status = 1;
+  } else if (D.dchi2Tol > 0.0 && S.iter > 0 && fabs(S.dchi2) < D.dchi2Tol) {
+    status = 0;
+  } else if (!(gp < 0.0)) {
+    next = CM_GRAD;                 // not a descent direction (round-off): refresh
+  } else if (D.refreshEvery > 0 && S.iter - S.lastGradIter >= D.refreshEvery) {
+    next = CM_GRAD;
+  }
+  if (status != ST_RUNNING) {
+    S.status = status;
+    D.statusOut[0] = status;
+    jobs[i].mode = CM_NONE;
+    S.chainMode = CM_NONE;
+    return;
+  }
+  uint32_t mask = 0u;
+  if (next == CM_HV) {
+    // p . Dp_j of the new direction from its coefficients: p = sum c b, b in {p_i, Dp_i, g}
+    for (int j = 0; j < nh; ++j) {
+      const int sj = slot_of(head, j, M);
+      double v = S.coef[2 * MMAX] * S.gD[sj];
+      for (int t = 0; t < nh; ++t) {
+        const int st2 = slot_of(head, t, M);
+        v += S.coef[st2] * S.PD[st2][sj] + S.coef[MMAX + st2] * S.DD[st2][sj];
+      }
+      S.pkD[sj] = v;
+      if (sj != ns) mask |= 1u << sj;
+    }
+    add_chain_bytes(S, D, CM_HV, 1 + __popc(mask));
+  } else {
+    // the direction just formed overwrote slot ns: if that slot held the oldest pair, drop it
+    if (nh == M) S.nhist = M - 1;
+    add_chain_bytes(S, D, CM_GRAD, 0);
+  }
+  make_job(jobs[i], D, next, ns, mask);
+  S.chainMode = next;
+  D.statusOut[0] = ST_RUNNING;
 }
 
 // ------------------------------------------------------------------------ tables and packing

@@ -16,7 +16,7 @@ static hipError_t lb_t(int which, dim3 grid, InstDesc* desc, LbState* st, Job* j
   switch (which) {
     case LB_ZERO: k_zero<T><<<grid, dim3(256), 0, s>>>(desc, count); break;
     case LB_INIT: k_init<<<dim3((count + 63) / 64), dim3(64), 0, s>>>(desc, st, jobs, count); break;
-    case LB_POST: k_post<<<dim3(count), dim3(64), 0, s>>>(desc, st, jobs); break;
+    case LB_POSTB: k_postB<M><<<dim3(count), dim3(256), 0, s>>>(desc, st, jobs); break;
     case LB_PASSA: k_passA<T, M><<<grid, dim3(NT), 0, s>>>(desc, st); break;
     case LB_COEF: k_coef<M><<<dim3(count), dim3(256), 0, s>>>(desc, st, jobs); break;
     case LB_PASSB: k_passB<T, M><<<grid, dim3(NT), 0, s>>>(desc, st); break;
