@@ -138,6 +138,7 @@ def main():
     torch.cuda.synchronize()
     t_batch = time.perf_counter() - t0
     iters = [s.iters for s in st_b]
+    tiles = wf.get_chain_tiles(args.n, 2, wf.WF_F32, nsolve)
     conv = sum(s.status == wf.WF_SOLVE_CONVERGED for s in st_b)
 
     plain = None
@@ -201,6 +202,8 @@ def main():
         "speedup_batched_vs_plain": None if plain is None else round(len(sims) / t_batch / plain, 2),
         "bandpower_estimates_per_s": round(args.steps / elapsed, 3),
         "iters_mean": round(float(np.mean(iters)), 1), "iters_max": int(np.max(iters)),
+        "chain_tiles": {"rows_per_wg": tiles[0], "col_blocks_per_wg": tiles[1], "instances_per_launch": tiles[2],
+                        "autotuned": tiles[3]},
         "converged": f"{conv}/{len(sims)}",
         "per_kernel": per_kernel,
     }

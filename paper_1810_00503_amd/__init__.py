@@ -24,7 +24,8 @@ from ._lib import (WF_ADJ_GRAD, WF_ADJ_METRIC, WF_F32, WF_F64, WF_MASK, WF_NOT_C
 __all__ = [
     "load", "Context", "Problem", "LbfgsOpts", "SolveStats", "context", "map_wf_solve", "wf_simulate",
     "sim_fisher", "bandpower_qe", "wf_forward", "wf_adjoint", "wf_chi2_grad", "wf_hvp", "wf_band_E",
-    "WFError", "kernel_stats", "reset_kernel_stats", "set_profiling", "autograd",
+    "WFError", "kernel_stats", "reset_kernel_stats", "set_profiling", "autograd", "set_chain_tiles",
+    "get_chain_tiles",
 ]
 
 
@@ -392,6 +393,21 @@ def kernel_stats(ctx: Context | None = None) -> dict:
 def reset_kernel_stats(ctx: Context | None = None):
     cx = ctx or context(0)
     cx.check(cx.lib.wf_reset_kernel_stats(cx.h))
+
+
+def set_chain_tiles(rbv: int = 0, cpb: int = 1, group: int = 0, ctx: Context | None = None):
+    """Fix the transform chain's tiles (rbv rows, cpb column blocks, group instances per
+    launch), or return to autotuning with rbv = 0."""
+    cx = ctx or context(0)
+    cx.check(cx.lib.wf_set_chain_tiles(cx.h, int(rbv), int(cpb), int(group)))
+
+
+def get_chain_tiles(n: int, ncomp: int, dtype: int = WF_F32, batch: int = 64, ctx: Context | None = None):
+    """(rbv, cpb, group, tuned) in use for this shape and batch size."""
+    cx = ctx or context(0)
+    a, b, g = C.c_int32(), C.c_int32(), C.c_int32()
+    rc = cx.check(cx.lib.wf_get_chain_tiles(cx.h, n, ncomp, dtype, batch, C.byref(a), C.byref(b), C.byref(g)))
+    return a.value, b.value, g.value, rc == 0
 
 
 from . import autograd  # noqa: E402,F401  (torch.autograd.Function wrappers)

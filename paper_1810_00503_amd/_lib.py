@@ -17,7 +17,7 @@ EXPORTS = [
     "wf_create", "wf_destroy", "wf_last_error", "wf_lbfgs_default", "map_wf_solve", "wf_simulate",
     "sim_fisher", "bandpower_qe", "wf_forward", "wf_adjoint", "wf_chi2_grad", "wf_hvp", "wf_band_E",
     "wf_set_profiling", "wf_kernel_kinds", "wf_kernel_kind_name", "wf_get_kernel_stats",
-    "wf_reset_kernel_stats",
+    "wf_reset_kernel_stats", "wf_set_chain_tiles", "wf_get_chain_tiles",
 ]
 
 
@@ -81,6 +81,8 @@ def load(path: str | None = None):
     L.wf_kernel_kind_name.restype = C.c_char_p
     L.wf_get_kernel_stats.argtypes = [vp, C.POINTER(C.c_int64), dp, dp]
     L.wf_reset_kernel_stats.argtypes = [vp]
+    L.wf_set_chain_tiles.argtypes = [vp, i32, i32, i32]
+    L.wf_get_chain_tiles.argtypes = [vp, i32, i32, i32, i32, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32)]
     for name in EXPORTS:
         fn = getattr(L, name)
         if fn.restype is C.c_int:

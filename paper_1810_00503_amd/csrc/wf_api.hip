@@ -63,6 +63,10 @@ struct wf_ctx {
   // graph cache
   hipGraphExec_t gexec = nullptr;
   std::string gkey;
+  // chain tile choices: fixed by the caller (rbv > 0) or tuned per shape and batch size
+  ChainCfg fixedCfg;
+  bool fixedSet = false;
+  std::map<std::tuple<int, int, int, int>, ChainCfg> tuned;
 };
 
 namespace {
@@ -162,7 +166,7 @@ int twiddles(wf_ctx* ctx, int n, int dtype, const void** out) {
 int prepare(wf_ctx* ctx, int n, int c, int dtype) {
   auto key = std::make_tuple(n, c, dtype);
   if (ctx->prepared.count(key)) return WF_OK;
-  HIPCHK(dtype == WF_F64 ? chain_prepare_f64(n, c) : chain_prepare_f32(n, c));
+  HIPCHK(chain_prepare(dtype, n, c));
   ctx->prepared[key] = true;
   return WF_OK;
 }
@@ -212,10 +216,10 @@ int drain_events(wf_ctx* ctx) {
   return WF_OK;
 }
 
-hipError_t chain(wf_ctx* ctx, int dtype, int n, int c, int which, const Job* jobs, int batch, const void* tw) {
+hipError_t chain(wf_ctx* ctx, int dtype, int n, int c, int which, const Job* jobs, int batch, const void* tw,
+                 const ChainCfg& cfg = ChainCfg()) {
   Timed t(ctx, which == CH_COLINV ? KK_COLINV : (which == CH_ROW ? KK_ROW : KK_COLFWD));
-  return dtype == WF_F64 ? chain_launch_f64(n, c, which, jobs, batch, tw, ctx->cs)
-                         : chain_launch_f32(n, c, which, jobs, batch, tw, ctx->cs);
+  return chain_launch(dtype, n, c, which, cfg, jobs, batch, tw, ctx->cs);
 }
 
 // ---------------------------------------------------------------------------- validation
@@ -288,7 +292,7 @@ struct Klass {
   int first = 0;              // position in the class-ordered arrays
   int64_t L = 0;
   int nchunk = 0, pstride = 0;
-  int group = 0;   // instances per launch of the transform chain (0 = all)
+  ChainCfg cfg;    // tile choice of the transform chain
   const void* tw = nullptr;
 };
 
@@ -300,6 +304,95 @@ struct SolveOut {
   std::vector<LbState> st;      // per user index
   std::vector<int> order;       // class-ordered position of each user index
 };
+
+// Autotuner of the transform chain's tiles: times the curvature product of this class's own
+// instances (zero direction, real W and prior tables) for every supported tile choice and
+// keeps the fastest per (n, ncomp, dtype, batch-size bucket).  Runs once per key and
+// context, outside graph capture; the buffers it touches are initialised afterwards.
+int tune_chain(wf_ctx* ctx, Klass& k, const std::vector<InstDesc>& hd, Job* djobs, int m) {
+  const int cnt = (int)k.members.size();
+  const int bucket = cnt >= 64 ? 64 : (cnt >= 16 ? 16 : (cnt >= 4 ? 4 : 1));
+  if (ctx->fixedSet) {
+    k.cfg = chain_cfg_supported(k.dtype, k.n, ctx->fixedCfg) ? ctx->fixedCfg : ChainCfg();
+    return WF_OK;
+  }
+  const auto key = std::make_tuple(k.n, k.c, k.dtype, bucket);
+  auto it = ctx->tuned.find(key);
+  if (it != ctx->tuned.end()) {
+    k.cfg = it->second;
+    return WF_OK;
+  }
+  k.cfg = ChainCfg();
+  if (k.dtype != WF_F32 || cnt < 4 || ctx->prof) {
+    ctx->tuned[key] = k.cfg;
+    return WF_OK;
+  }
+  std::vector<Job> hj(cnt);
+  for (int j = 0; j < cnt; ++j) {
+    const InstDesc& D = hd[k.first + j];
+    Job& jb = hj[j];
+    std::memset(&jb, 0, sizeof jb);
+    const size_t vb = (size_t)D.vstride * D.esize;
+    jb.mode = CM_HV;
+    jb.boost_band = -1;
+    jb.vin = (char*)D.X + 2 * vb;
+    jb.vadd = jb.vin;
+    jb.vout = (char*)D.X + (2 + (size_t)m) * vb;
+    jb.y = D.y;
+    jb.W = D.W;
+    jb.sIn = D.sq;
+    jb.sOut = D.sq;
+    jb.part = D.partChain;
+    jb.pstride = D.pstride;
+    jb.vcs = jb.vcstr = D.L;
+    HIPCHK(hipMemsetAsync((void*)jb.vin, 0, (size_t)D.L * D.esize, ctx->cs));
+  }
+  Job* dj = djobs + k.first;
+  HIPCHK(hipMemcpyAsync(dj, hj.data(), sizeof(Job) * cnt, hipMemcpyHostToDevice, ctx->cs));
+  std::vector<ChainCfg> cands;
+  for (int rbv : {2, 4, 8})
+    for (int cpb : {1, 2})
+      for (int grp : {0, 32}) {
+        if (grp > 0 && cnt <= grp) continue;
+        ChainCfg c;
+        c.rbv = rbv;
+        c.cpb = cpb;
+        c.group = grp;
+        if (chain_cfg_supported(k.dtype, k.n, c)) cands.push_back(c);
+      }
+  hipEvent_t e0 = ev_get(ctx), e1 = ev_get(ctx);
+  float best = 1e30f;
+  for (const ChainCfg& c : cands) {
+    auto run = [&]() -> hipError_t {
+      const int G = c.group > 0 ? std::min(c.group, cnt) : cnt;
+      for (int g0 = 0; g0 < cnt; g0 += G)
+        for (int w = 0; w < 3; ++w) {
+          hipError_t e = chain_launch(k.dtype, k.n, k.c, w, c, dj + g0, std::min(G, cnt - g0), k.tw, ctx->cs);
+          if (e != hipSuccess) return e;
+        }
+      return hipSuccess;
+    };
+    HIPCHK(run());   // warm-up
+    float tmin = 1e30f;
+    for (int r = 0; r < 3; ++r) {
+      HIPCHK(hipEventRecord(e0, ctx->cs));
+      HIPCHK(run());
+      HIPCHK(hipEventRecord(e1, ctx->cs));
+      HIPCHK(hipEventSynchronize(e1));
+      float t = 0.f;
+      HIPCHK(hipEventElapsedTime(&t, e0, e1));
+      tmin = std::min(tmin, t);
+    }
+    if (tmin < best) {
+      best = tmin;
+      k.cfg = c;
+    }
+  }
+  ctx->evPool.push_back(e0);
+  ctx->evPool.push_back(e1);
+  ctx->tuned[key] = k.cfg;
+  return WF_OK;
+}
 
 int solve_core(wf_ctx* ctx, const wf_problem* probs, int B, const wf_lbfgs_opts& o, SolveOut& out) {
   const int m = o.m;
@@ -355,8 +448,7 @@ int solve_core(wf_ctx* ctx, const wf_problem* probs, int B, const wf_lbfgs_opts&
     const size_t eb = esize_of(k.dtype);
     const int64_t nvec = k.L * 2 / (k.dtype == WF_F64 ? 2 : 4);
     k.nchunk = (int)((nvec + PASS_CV - 1) / PASS_CV);
-    k.pstride = k.n / RB;
-    if (const char* ge = getenv("WF_CHAIN_GROUP")) k.group = atoi(ge);
+    k.pstride = k.n / RB_MIN;
     const size_t vsb = (size_t)k.L * eb + kVecPadBytes;
     const size_t per = align_up((size_t)(2 + 2 * m) * vsb) + align_up(vsb) +
                        align_up(sizeof(double) * PK_COUNT * k.pstride) + align_up(sizeof(double) * kNdot * k.nchunk);
@@ -426,6 +518,10 @@ int solve_core(wf_ctx* ctx, const wf_problem* probs, int B, const wf_lbfgs_opts&
     }
   }
   HIPCHK(hipMemcpyAsync(ddesc, hd.data(), sizeof(InstDesc) * B, hipMemcpyHostToDevice, ctx->cs));
+  for (auto& k : ks) {
+    rc = tune_chain(ctx, k, hd, djobs, m);
+    if (rc) return rc;
+  }
   // init
   for (auto& k : ks) {
     const int cnt = (int)k.members.size();
@@ -446,10 +542,10 @@ int solve_core(wf_ctx* ctx, const wf_problem* probs, int B, const wf_lbfgs_opts&
   auto body = [&](void) -> int {
     for (auto& k : ks) {
       const int cnt = (int)k.members.size();
-      const int G = k.group > 0 ? std::min(k.group, cnt) : cnt;
+      const int G = k.cfg.group > 0 ? std::min(k.cfg.group, cnt) : cnt;
       for (int g0 = 0; g0 < cnt; g0 += G) {
         const int gc = std::min(G, cnt - g0);
-        for (int w = 0; w < 3; ++w) HIPCHK(chain(ctx, k.dtype, k.n, k.c, w, djobs + k.first + g0, gc, k.tw));
+        for (int w = 0; w < 3; ++w) HIPCHK(chain(ctx, k.dtype, k.n, k.c, w, djobs + k.first + g0, gc, k.tw, k.cfg));
       }
     }
     for (auto& k : ks) {
@@ -486,7 +582,8 @@ int solve_core(wf_ctx* ctx, const wf_problem* probs, int B, const wf_lbfgs_opts&
     snprintf(buf, sizeof buf, "%p/%d/%d/%d/%d|", (void*)A.base, A.gen, B, m, K);
     key = buf;
     for (auto& k : ks) key += std::to_string(k.n) + "," + std::to_string(k.c) + "," + std::to_string(k.dtype) + "," +
-                              std::to_string(k.members.size()) + ";";
+                              std::to_string(k.members.size()) + "," + std::to_string(k.cfg.rbv) + "," +
+                              std::to_string(k.cfg.cpb) + "," + std::to_string(k.cfg.group) + ";";
     if (key != ctx->gkey) {
       if (ctx->gexec) (void)hipGraphExecDestroy(ctx->gexec);
       ctx->gexec = nullptr;
@@ -794,7 +891,7 @@ int op_setup(wf_ctx* ctx, const wf_problem* p, int batch, size_t extra, PriorTab
   const int n = p->n, c = p->ncomp, dt = p->dtype;
   const int64_t L = (int64_t)c * n * (n / 2);
   const size_t eb = esize_of(dt);
-  const int pstride = n / RB;
+  const int pstride = n / RB_MIN;
   const size_t need = prior_bytes(p) + 3 * align_up((size_t)L * eb * batch) + align_up(sizeof(Job) * batch) +
                       align_up(sizeof(double) * PK_COUNT * pstride * batch) + extra;
   int rc = arena_reserve(ctx, ctx->opA, need);
@@ -1067,7 +1164,7 @@ static int raw_chain(wf_ctx* ctx, const wf_problem* p, int batch, const void* s,
   const int n = p->n, c = p->ncomp, dt = p->dtype;
   const int64_t L = (int64_t)c * n * (n / 2);
   const size_t eb = esize_of(dt);
-  const int pstride = n / RB;
+  const int pstride = n / RB_MIN;
   HIPCHK(unpack_launch(dt, n, c, batch, s, vin, ctx->cs));
   std::vector<Job> hj(batch);
   for (int i = 0; i < batch; ++i) {
@@ -1092,7 +1189,7 @@ static int raw_chain(wf_ctx* ctx, const wf_problem* p, int batch, const void* s,
     std::vector<double> hp((size_t)PK_COUNT * pstride * batch);
     HIPCHK(hipMemcpyAsync(hp.data(), part, sizeof(double) * hp.size(), hipMemcpyDeviceToHost, ctx->cs));
     HIPCHK(hipStreamSynchronize(ctx->cs));
-    const int ncol = (n / 2) / TB, nrow = n / RB;
+    const int ncol = (n / 2) / TB, nrow = n / RB_MIN;
     for (int i = 0; i < batch; ++i) {
       const double* q = &hp[(size_t)i * PK_COUNT * pstride];
       double pr = 0.0, rs = 0.0;
@@ -1166,6 +1263,34 @@ int wf_band_E(wf_ctx* ctx, const wf_problem* p, int32_t batch, const void* s, do
   HIPCHK(hipMemcpyAsync(E, dE, sizeof(double) * (size_t)batch * nb, hipMemcpyDeviceToHost, ctx->cs));
   HIPCHK(hipStreamSynchronize(ctx->cs));
   return WF_OK;
+}
+
+int wf_set_chain_tiles(wf_ctx* ctx, int32_t rbv, int32_t cpb, int32_t group) {
+  if (!ctx) return WF_EINVAL;
+  if (rbv == 0) {
+    ctx->fixedSet = false;
+    return WF_OK;
+  }
+  if (!(rbv == 2 || rbv == 4 || rbv == 8) || !(cpb == 1 || cpb == 2) || group < 0)
+    return fail(ctx, WF_EINVAL, "tiles: rbv in {2,4,8}, cpb in {1,2}, group >= 0");
+  ctx->fixedCfg.rbv = rbv;
+  ctx->fixedCfg.cpb = cpb;
+  ctx->fixedCfg.group = group;
+  ctx->fixedSet = true;
+  return WF_OK;
+}
+
+int wf_get_chain_tiles(wf_ctx* ctx, int32_t n, int32_t ncomp, int32_t dtype, int32_t batch, int32_t* rbv, int32_t* cpb,
+                       int32_t* group) {
+  if (!ctx || !rbv || !cpb || !group) return WF_EINVAL;
+  const int bucket = batch >= 64 ? 64 : (batch >= 16 ? 16 : (batch >= 4 ? 4 : 1));
+  auto it = ctx->tuned.find(std::make_tuple((int)n, (int)ncomp, (int)dtype, bucket));
+  ChainCfg c = it != ctx->tuned.end() ? it->second : ChainCfg();
+  if (ctx->fixedSet) c = ctx->fixedCfg;
+  *rbv = c.rbv;
+  *cpb = c.cpb;
+  *group = c.group;
+  return it != ctx->tuned.end() || ctx->fixedSet ? WF_OK : WF_NOT_CONVERGED;
 }
 
 int wf_set_profiling(wf_ctx* ctx, int32_t on) {

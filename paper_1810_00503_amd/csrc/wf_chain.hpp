@@ -9,8 +9,9 @@
 //                           added term, dot-product partials.
 //
 // Every pass stages its tile in LDS and transforms it with the Stockham FFT of
-// wf_fft.hpp.  A work-group of the column passes owns one TB-column block (both
-// components, contiguous in memory); a work-group of the row pass owns RB rows.
+// wf_fft.hpp.  A work-group of the column passes owns CPB column blocks of TB columns
+// (both components; each block contiguous in memory); a work-group of the row pass owns
+// RBV rows.  CPB and RBV are tile choices made per problem shape by the autotuner.
 #pragma once
 #include "wf_fft.hpp"
 
@@ -92,12 +93,12 @@ template <typename T>
 __device__ __forceinline__ size_t chain_lds_col(int N, int C) { return (size_t)(N + N * C * TB) * sizeof(cpx<T>); }
 
 // ------------------------------------------------------------------------ column inverse
-template <typename T, int N, int C>
+template <typename T, int N, int C, int CPB>
 __global__ __launch_bounds__(NT) void k_colinv(const Job* __restrict__ jobs, const cpx<T>* __restrict__ twg) {
   const Job& jb = jobs[blockIdx.y];
   const int mode = jb.mode;
   if (mode == CM_NONE || mode == CM_ADJ || mode == CM_ADJ_GRAD) return;
-  constexpr int NB = C * TB;
+  constexpr int NB = CPB * C * TB;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cpx<T>* tw = reinterpret_cast<cpx<T>*>(smem_raw);
   cpx<T>* buf = tw + N;
@@ -113,16 +114,17 @@ __global__ __launch_bounds__(NT) void k_colinv(const Job* __restrict__ jobs, con
   const T* draws = reinterpret_cast<const T*>(jb.draws);
   const T bamp = T(jb.boost_factor);
   double acc = 0.0;
-  // offset of this column block in the (chunk-interleaved) input view
-  int64_t dv[C];
+  for (int ee = tid; ee < CPB * N * TB; ee += NT) {
+    const int cb = ee / (N * TB), e = ee % (N * TB);
+    const int qb = q * CPB + cb;                     // column block
+    const int ky = e / TB, col = e % TB, kx = qb * TB + col;
+    // offset of this column block in the (chunk-interleaved) input view
+    int64_t dv[C];
 #pragma unroll
-  for (int c = 0; c < C; ++c) {
-    const int64_t bs = fidx(N, c, 0, q * TB);
-    dv[c] = jb.vcs > 0 ? vview(bs, jb.vcs, jb.vcstr) - bs : 0;
-  }
-
-  for (int e = tid; e < N * TB; e += NT) {
-    const int ky = e / TB, col = e % TB, kx = q * TB + col;
+    for (int c = 0; c < C; ++c) {
+      const int64_t bs = fidx(N, c, 0, qb * TB);
+      dv[c] = jb.vcs > 0 ? vview(bs, jb.vcs, jb.vcstr) - bs : 0;
+    }
     cpx<T> a[C];
 #pragma unroll
     for (int c = 0; c < C; ++c) a[c] = mk(T(0), T(0));
@@ -174,29 +176,31 @@ __global__ __launch_bounds__(NT) void k_colinv(const Job* __restrict__ jobs, con
       }
     }
 #pragma unroll
-    for (int c = 0; c < C; ++c) buf[ky * NB + c * TB + col] = a[c];
+    for (int c = 0; c < C; ++c) buf[ky * NB + (cb * C + c) * TB + col] = a[c];
   }
   __syncthreads();
   lds_fft<T, N, NB, 1, NB, 1, false, true>(buf, tw);
 
   cpx<T>* y = reinterpret_cast<cpx<T>*>(jb.y);
-  for (int e = tid; e < N * TB; e += NT) {
+  for (int ee = tid; ee < CPB * N * TB; ee += NT) {
+    const int cb = ee / (N * TB), e = ee % (N * TB);
     const int ky = e / TB, col = e % TB;
 #pragma unroll
-    for (int c = 0; c < C; ++c) y[fidx(N, c, 0, q * TB) + e] = buf[ky * NB + c * TB + col];
+    for (int c = 0; c < C; ++c) y[fidx(N, c, 0, (q * CPB + cb) * TB) + e] = buf[ky * NB + (cb * C + c) * TB + col];
   }
   if (mode == CM_GRAD || mode == CM_RAW_GRAD) {
     const double t = block_sum(acc, red);
-    if (tid == 0) jb.part[PK_PRIOR * jb.pstride + q] = t;
+    if (tid < CPB) jb.part[PK_PRIOR * jb.pstride + q * CPB + tid] = tid == 0 ? t : 0.0;
   }
 }
 
 // ------------------------------------------------------------------------ row pass
-template <typename T, int N, int C>
+template <typename T, int N, int C, int RBV>
 __global__ __launch_bounds__(NT) void k_row(const Job* __restrict__ jobs, const cpx<T>* __restrict__ twg) {
   const Job& jb = jobs[blockIdx.y];
   const int mode = jb.mode;
   if (mode == CM_NONE) return;
+  constexpr int RB = RBV;
   constexpr int H = N / 2, NBR = C * RB, SBR = H;
   constexpr int NE = NBR * H;
   constexpr int KP = (NE + NT - 1) / NT;
@@ -346,18 +350,19 @@ __global__ __launch_bounds__(NT) void k_row(const Job* __restrict__ jobs, const 
     Y[fidx(N, c, y0, qq * TB) + w2] = buf[(c * RB + yl) * SBR + qq * TB + col];
   }
   if (mode == CM_GRAD || mode == CM_RAW_GRAD) {
+    // partials are kept per RB_MIN rows so the reduction does not depend on RBV
     const double t = block_sum(acc, red);
-    if (tid == 0) jb.part[PK_RES * jb.pstride + blockIdx.x] = t;
+    if (tid < RB / RB_MIN) jb.part[PK_RES * jb.pstride + blockIdx.x * (RB / RB_MIN) + tid] = tid == 0 ? t : 0.0;
   }
 }
 
 // ------------------------------------------------------------------------ column forward
-template <typename T, int N, int C>
+template <typename T, int N, int C, int CPB>
 __global__ __launch_bounds__(NT) void k_colfwd(const Job* __restrict__ jobs, const cpx<T>* __restrict__ twg) {
   const Job& jb = jobs[blockIdx.y];
   const int mode = jb.mode;
   if (mode == CM_NONE || mode == CM_FWD || mode == CM_SIM) return;
-  constexpr int NB = C * TB;
+  constexpr int NB = CPB * C * TB;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cpx<T>* tw = reinterpret_cast<cpx<T>*>(smem_raw);
   cpx<T>* buf = tw + N;
@@ -365,10 +370,11 @@ __global__ __launch_bounds__(NT) void k_colfwd(const Job* __restrict__ jobs, con
   const int tid = threadIdx.x, q = blockIdx.x;
   for (int i = tid; i < N; i += NT) tw[i] = twg[i];
   const cpx<T>* Y = reinterpret_cast<const cpx<T>*>(jb.y);
-  for (int e = tid; e < N * TB; e += NT) {
+  for (int ee = tid; ee < CPB * N * TB; ee += NT) {
+    const int cb = ee / (N * TB), e = ee % (N * TB);
     const int ky = e / TB, col = e % TB;
 #pragma unroll
-    for (int c = 0; c < C; ++c) buf[ky * NB + c * TB + col] = Y[fidx(N, c, 0, q * TB) + e];
+    for (int c = 0; c < C; ++c) buf[ky * NB + (cb * C + c) * TB + col] = Y[fidx(N, c, 0, (q * CPB + cb) * TB) + e];
   }
   __syncthreads();
   lds_fft<T, N, NB, 1, NB, 1, false, false>(buf, tw);
@@ -380,21 +386,23 @@ __global__ __launch_bounds__(NT) void k_colfwd(const Job* __restrict__ jobs, con
   double add[MMAX];
 #pragma unroll
   for (int j = 0; j < MMAX; ++j) add[j] = 0.0;
-  int64_t dv[C];
-#pragma unroll
-  for (int c = 0; c < C; ++c) {
-    const int64_t bs = fidx(N, c, 0, q * TB);
-    dv[c] = jb.vcs > 0 ? vview(bs, jb.vcs, jb.vcstr) - bs : 0;
-  }
   // curvature products inside the solver also dot the new Dp with g and the kept Dp_j
   const bool extras = (mode == CM_HV) && jb.dpBase != nullptr;
   const cpx<T>* gvec = reinterpret_cast<const cpx<T>*>(jb.gvec);
   const cpx<T>* dpb = reinterpret_cast<const cpx<T>*>(jb.dpBase);
-  for (int e = tid; e < N * TB; e += NT) {
-    const int ky = e / TB, col = e % TB, kx = q * TB + col;
+  for (int ee = tid; ee < CPB * N * TB; ee += NT) {
+    const int cb = ee / (N * TB), e = ee % (N * TB);
+    const int qb = q * CPB + cb;
+    const int ky = e / TB, col = e % TB, kx = qb * TB + col;
+    int64_t dv[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      const int64_t bs = fidx(N, c, 0, qb * TB);
+      dv[c] = jb.vcs > 0 ? vview(bs, jb.vcs, jb.vcstr) - bs : 0;
+    }
     cpx<T> t[C];
 #pragma unroll
-    for (int c = 0; c < C; ++c) t[c] = buf[ky * NB + c * TB + col];
+    for (int c = 0; c < C; ++c) t[c] = buf[ky * NB + (cb * C + c) * TB + col];
     if constexpr (C == 2) {
       T c2, s2;
       rot2<T>(kx, ky < N / 2 ? ky : ky - N, c2, s2);
@@ -470,7 +478,9 @@ __global__ __launch_bounds__(NT) void k_colfwd(const Job* __restrict__ jobs, con
       double sum = 0.0;
 #pragma unroll
       for (int k = 0; k < NT / 64; ++k) sum += red2[k][tid];
-      jb.part[(PK_VO + tid) * jb.pstride + q] = sum;
+      jb.part[(PK_VO + tid) * jb.pstride + q * CPB] = sum;
+#pragma unroll
+      for (int cb = 1; cb < CPB; ++cb) jb.part[(PK_VO + tid) * jb.pstride + q * CPB + cb] = 0.0;
     }
   }
 }

@@ -1,50 +1,93 @@
-// Instantiation of the transform-chain kernels for one element type.  Included once
-// per type by wf_chain_f32.hip / wf_chain_f64.hip with WF_T defined.
+// Instantiation of the transform-chain kernels for one element type and a list of grid
+// sides.  Included by the wf_chain_*.hip units with WF_T, WF_SIZES, WF_VARIANTS and the
+// entry-point names defined.
 #include "wf_chain.hpp"
 #include "wf_launch.hpp"
 
 namespace wf {
 
-template <typename T, int N, int C>
-static size_t lds_colpass() { return (size_t)(N + N * C * TB) * sizeof(cpx<T>); }
-template <typename T, int N, int C>
-static size_t lds_rowpass() { return (size_t)(N + C * RB * (N / 2)) * sizeof(cpx<T>); }
+template <typename T, int N, int C, int CPB>
+static size_t lds_colpass() { return (size_t)(N + N * CPB * C * TB) * sizeof(cpx<T>); }
+template <typename T, int N, int C, int RBV>
+static size_t lds_rowpass() { return (size_t)(N + C * RBV * (N / 2)) * sizeof(cpx<T>); }
 
-template <typename T, int N, int C>
-static hipError_t prep_t() {
-  hipError_t e;
-  e = hipFuncSetAttribute((const void*)k_colinv<T, N, C>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                          (int)lds_colpass<T, N, C>());
+template <typename T, int N, int C, int CPB>
+static hipError_t prep_col() {
+  if ((N / 8) % CPB != 0) return hipSuccess;
+  hipError_t e = hipFuncSetAttribute((const void*)k_colinv<T, N, C, CPB>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)lds_colpass<T, N, C, CPB>());
   if (e != hipSuccess) return e;
-  e = hipFuncSetAttribute((const void*)k_colfwd<T, N, C>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                          (int)lds_colpass<T, N, C>());
-  if (e != hipSuccess) return e;
-  return hipFuncSetAttribute((const void*)k_row<T, N, C>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                             (int)lds_rowpass<T, N, C>());
+  return hipFuncSetAttribute((const void*)k_colfwd<T, N, C, CPB>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)lds_colpass<T, N, C, CPB>());
+}
+template <typename T, int N, int C, int RBV>
+static hipError_t prep_row() {
+  return hipFuncSetAttribute((const void*)k_row<T, N, C, RBV>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)lds_rowpass<T, N, C, RBV>());
 }
 
 template <typename T, int N, int C>
-static hipError_t launch_t(int which, const Job* jobs, int batch, const void* tw, hipStream_t st) {
+static hipError_t prep_t() {
+  hipError_t e = prep_col<T, N, C, 1>();
+  if (e == hipSuccess) e = prep_row<T, N, C, 4>();
+#if WF_VARIANTS
+  if (e == hipSuccess) e = prep_col<T, N, C, 2>();
+  if (e == hipSuccess) e = prep_row<T, N, C, 2>();
+  if (e == hipSuccess) e = prep_row<T, N, C, 8>();
+#endif
+  return e;
+}
+
+template <typename T, int N, int C, int CPB>
+static void launch_col(int which, const Job* jobs, int batch, const cpx<T>* t, hipStream_t st) {
+  const size_t lc = lds_colpass<T, N, C, CPB>();
+  const dim3 grid(N / 8 / CPB, batch);
+  if (which == CH_COLINV)
+    k_colinv<T, N, C, CPB><<<grid, dim3(NT), lc, st>>>(jobs, t);
+  else
+    k_colfwd<T, N, C, CPB><<<grid, dim3(NT), lc, st>>>(jobs, t);
+}
+
+template <typename T, int N, int C, int RBV>
+static void launch_row(const Job* jobs, int batch, const cpx<T>* t, hipStream_t st) {
+  k_row<T, N, C, RBV><<<dim3(N / RBV, batch), dim3(NT), lds_rowpass<T, N, C, RBV>(), st>>>(jobs, t);
+}
+
+template <typename T, int N, int C>
+static hipError_t launch_t(int which, const ChainCfg& cfg, const Job* jobs, int batch, const void* tw,
+                           hipStream_t st) {
   const cpx<T>* t = reinterpret_cast<const cpx<T>*>(tw);
-  const size_t lc = lds_colpass<T, N, C>(), lr = lds_rowpass<T, N, C>();
-  if (which == CH_COLINV) {
-    k_colinv<T, N, C><<<dim3(N / 2 / TB, batch), dim3(NT), lc, st>>>(jobs, t);
-  } else if (which == CH_ROW) {
-    k_row<T, N, C><<<dim3(N / RB, batch), dim3(NT), lr, st>>>(jobs, t);
+  if (which == CH_ROW) {
+    switch (cfg.rbv) {
+      case 4: launch_row<T, N, C, 4>(jobs, batch, t, st); break;
+#if WF_VARIANTS
+      case 2: launch_row<T, N, C, 2>(jobs, batch, t, st); break;
+      case 8: launch_row<T, N, C, 8>(jobs, batch, t, st); break;
+#endif
+      default: return hipErrorInvalidValue;
+    }
   } else {
-    k_colfwd<T, N, C><<<dim3(N / 2 / TB, batch), dim3(NT), lc, st>>>(jobs, t);
+    switch (cfg.cpb) {
+      case 1: launch_col<T, N, C, 1>(which, jobs, batch, t, st); break;
+#if WF_VARIANTS
+      case 2:
+        if ((N / 8) % 2 != 0) return hipErrorInvalidValue;
+        launch_col<T, N, C, 2>(which, jobs, batch, t, st);
+        break;
+#endif
+      default: return hipErrorInvalidValue;
+    }
   }
   return hipGetLastError();
 }
 
-#define WF_SIZES(X) X(8) X(16) X(24) X(32) X(48) X(64) X(96) X(128) X(192) X(256) X(384) X(512) X(768) X(1024)
-
 #define WF_CASE_L(N) \
-  case N: return c == 1 ? launch_t<WF_T, N, 1>(which, jobs, batch, tw, st) : launch_t<WF_T, N, 2>(which, jobs, batch, tw, st);
+  case N: return c == 1 ? launch_t<WF_T, N, 1>(which, cfg, jobs, batch, tw, st) : launch_t<WF_T, N, 2>(which, cfg, jobs, batch, tw, st);
 #define WF_CASE_P(N) \
   case N: return c == 1 ? prep_t<WF_T, N, 1>() : prep_t<WF_T, N, 2>();
 
-hipError_t WF_LAUNCH_NAME(int n, int c, int which, const Job* jobs, int batch, const void* tw, hipStream_t st) {
+hipError_t WF_LAUNCH_NAME(int n, int c, int which, const ChainCfg& cfg, const Job* jobs, int batch, const void* tw,
+                          hipStream_t st) {
   if (c != 1 && c != 2) return hipErrorInvalidValue;
   switch (n) {
     WF_SIZES(WF_CASE_L)

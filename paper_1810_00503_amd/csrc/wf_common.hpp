@@ -43,7 +43,7 @@ __device__ __forceinline__ cpx<T> scale(cpx<T> a, T s) { return mk(a.x * s, a.y 
 // over 4 consecutive rows reads contiguous 4*TB runs.  The Nyquist column kx = n/2
 // (always dead) is not stored.
 constexpr int TB = 4;
-constexpr int RB = 4;      // rows per work-group of the row pass
+constexpr int RB_MIN = 2;  // granularity of the row pass's partial sums (rows)
 constexpr int NT = 256;    // threads per work-group of the transform and vector passes
 constexpr int PASS_U = 4;                // vector loads per thread per stream in a vector pass
 constexpr int PASS_CV = NT * PASS_U;     // vector elements of one stream per work-group

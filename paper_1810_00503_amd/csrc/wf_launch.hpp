@@ -9,13 +9,42 @@ enum { CH_COLINV = 0, CH_ROW = 1, CH_COLFWD = 2 };
 // supported grid sides: n % 8 == 0, n = 2^a or 3 * 2^a, 8 <= n <= 1024
 bool chain_supported(int n);
 
+// Tile choice of the transform chain: rows per work-group of the row pass (2, 4, 8),
+// column blocks per work-group of the column passes (1, 2) and instances per launch
+// (0 = all).  float32 supports every choice, float64 the defaults (4, 1).
+struct ChainCfg {
+  int rbv = 4;
+  int cpb = 1;
+  int group = 0;
+};
+
 // Launch one pass of the transform chain for `batch` jobs.  Returns hipSuccess or the
-// launch error; hipErrorInvalidValue if (n, c) has no instantiation.
-hipError_t chain_launch_f32(int n, int c, int which, const Job* jobs, int batch, const void* tw, hipStream_t st);
-hipError_t chain_launch_f64(int n, int c, int which, const Job* jobs, int batch, const void* tw, hipStream_t st);
+// launch error; hipErrorInvalidValue if (n, c, cfg) has no instantiation.
+hipError_t chain_launch_f32_s(int n, int c, int which, const ChainCfg& cfg, const Job* jobs, int batch,
+                              const void* tw, hipStream_t st);
+hipError_t chain_launch_f32_l(int n, int c, int which, const ChainCfg& cfg, const Job* jobs, int batch,
+                              const void* tw, hipStream_t st);
+hipError_t chain_launch_f64(int n, int c, int which, const ChainCfg& cfg, const Job* jobs, int batch,
+                            const void* tw, hipStream_t st);
 // one-time per-kernel set-up (LDS limits); must run outside stream capture
-hipError_t chain_prepare_f32(int n, int c);
+hipError_t chain_prepare_f32_s(int n, int c);
+hipError_t chain_prepare_f32_l(int n, int c);
 hipError_t chain_prepare_f64(int n, int c);
+
+inline hipError_t chain_launch(int dtype, int n, int c, int which, const ChainCfg& cfg, const Job* jobs, int batch,
+                               const void* tw, hipStream_t st) {
+  if (dtype != 0) return chain_launch_f64(n, c, which, cfg, jobs, batch, tw, st);
+  return n <= 96 ? chain_launch_f32_s(n, c, which, cfg, jobs, batch, tw, st)
+                 : chain_launch_f32_l(n, c, which, cfg, jobs, batch, tw, st);
+}
+inline hipError_t chain_prepare(int dtype, int n, int c) {
+  if (dtype != 0) return chain_prepare_f64(n, c);
+  return n <= 96 ? chain_prepare_f32_s(n, c) : chain_prepare_f32_l(n, c);
+}
+inline bool chain_cfg_supported(int dtype, int n, const ChainCfg& cfg) {
+  if (dtype != 0) return cfg.rbv == 4 && cfg.cpb == 1;
+  return (cfg.rbv == 2 || cfg.rbv == 4 || cfg.rbv == 8) && (cfg.cpb == 1 || (cfg.cpb == 2 && (n / 8) % 2 == 0));
+}
 
 enum { LB_ZERO = 0, LB_INIT = 1, LB_POSTB = 2, LB_PASSA = 3, LB_COEF = 4, LB_PASSB = 5 };
 hipError_t lbfgs_launch(int dtype, int m, int which, dim3 grid, InstDesc* desc, LbState* st, Job* jobs, int count,

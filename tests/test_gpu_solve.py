@@ -177,3 +177,30 @@ def test_sim_fisher_philox_path(lib):
     bo, Fo, Eso = O.sim_fisher(wl.W, wl.pshape, wl.band, wl.theta_fid, wl.nbands, draws, tol=1e-11)
     np.testing.assert_allclose(Es, Eso, rtol=1e-4)
     np.testing.assert_allclose(F, Fo, rtol=1e-4, atol=1e-4 * np.abs(Fo).max())
+
+
+def test_tile_variants_agree_and_autotune(lib):
+    """Every tile choice of the transform chain gives the same MAP (to round-off of the
+    reduction order), and the autotuner records a choice for a batched float32 shape."""
+    import torch
+    print("[tile variants]", flush=True)
+    wls = [WL.shear_workload(64, 200 + i, nbands_e=3, nbands_b=3) for i in range(5)]
+    probs = [make_problem(lib, torch, wl, "f32", d=oracle_data(wl, 300 + i)) for i, wl in enumerate(wls)]
+    try:
+        lib.set_chain_tiles(4, 1, 0)
+        ref, _, st0, _ = _solve(lib, probs, rel_grad_tol=1e-7)
+        for rbv in (2, 4, 8):
+            for cpb in (1, 2):
+                for grp in (0, 2):
+                    lib.set_chain_tiles(rbv, cpb, grp)
+                    got, _, st, _ = _solve(lib, probs, rel_grad_tol=1e-7)
+                    for i in range(len(probs)):
+                        assert st[i].status == lib.WF_SOLVE_CONVERGED
+                        assert rel_l2(got[i], ref[i]) < 2e-6, (rbv, cpb, grp, rel_l2(got[i], ref[i]))
+    finally:
+        lib.set_chain_tiles(0)
+    got, _, st, _ = _solve(lib, probs, rel_grad_tol=1e-7)
+    rbv, cpb, grp, tuned = lib.get_chain_tiles(64, 2, lib.WF_F32, len(probs))
+    assert tuned and rbv in (2, 4, 8) and cpb in (1, 2)
+    for i in range(len(probs)):
+        assert rel_l2(got[i], ref[i]) < 2e-6
