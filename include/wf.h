@@ -180,12 +180,13 @@ int wf_hvp(wf_ctx* ctx, const wf_problem* prob, int32_t batch, const void* p, vo
 int wf_band_E(wf_ctx* ctx, const wf_problem* prob, int32_t batch, const void* s, double* E, void* stream);
 
 /* Tiles of the transform chain (the three passes of every gradient / curvature product):
- * rbv = image rows per work-group of the row pass (2, 4, 8), cpb = column blocks of 4
- * columns per work-group of the column passes (1, 2; 2 needs n % 16 == 0), group =
+ * rbv = image rows per work-group of the row pass (2, 4, 8), cpb = column blocks of 2
+ * columns per work-group of the column passes (1, 2, 4; must divide n/4), group =
  * instances per launch (0 = all).  By default (rbv = 0) the library autotunes them: on
  * the first float32 solve of a batch of >= 4 maps of a given (n, ncomp, batch-size
  * bucket) it times every choice on that batch and keeps the fastest for the context.
- * float64 uses (4, 1, 0).  wf_get_chain_tiles reports the choice in use (WF_OK) or the
+ * float64 uses (4, 1, 0).  Every choice computes the same result up to the order of the
+ * FP64 partial sums.  wf_get_chain_tiles reports the choice in use (WF_OK) or the
  * default if none was tuned yet (WF_NOT_CONVERGED).                                   */
 int wf_set_chain_tiles(wf_ctx* ctx, int32_t rbv, int32_t cpb, int32_t group);
 int wf_get_chain_tiles(wf_ctx* ctx, int32_t n, int32_t ncomp, int32_t dtype, int32_t batch, int32_t* rbv, int32_t* cpb,

@@ -306,8 +306,9 @@ struct SolveOut {
 };
 
 // Autotuner of the transform chain's tiles: times the curvature product of this class's own
-// instances (zero direction, real W and prior tables) for every supported tile choice and
-// keeps the fastest per (n, ncomp, dtype, batch-size bucket).  Runs once per key and
+// instances as the solver runs it (zero direction, real W and prior tables, the extra dots
+// with g and m - 1 kept Dp_j) for every supported tile choice, best of 5, and keeps the
+// fastest per (n, ncomp, dtype, batch-size bucket).  Runs once per key and
 // context, outside graph capture; the buffers it touches are initialised afterwards.
 int tune_chain(wf_ctx* ctx, Klass& k, const std::vector<InstDesc>& hd, Job* djobs, int m) {
   const int cnt = (int)k.members.size();
@@ -345,13 +346,19 @@ int tune_chain(wf_ctx* ctx, Klass& k, const std::vector<InstDesc>& hd, Job* djob
     jb.part = D.partChain;
     jb.pstride = D.pstride;
     jb.vcs = jb.vcstr = D.L;
-    HIPCHK(hipMemsetAsync((void*)jb.vin, 0, (size_t)D.L * D.esize, ctx->cs));
+    // the solver's curvature products also read g and the m - 1 other kept Dp_j
+    jb.gvec = (char*)D.X + vb;
+    jb.dpBase = (char*)D.X + (2 + (size_t)m) * vb;
+    jb.dpStride = D.vstride;
+    jb.dpMask = m > 1 ? ((1u << m) - 2u) : 0u;
+    for (int v = 1; v < 2 + 2 * m; ++v)
+      if (v == 1 || v == 2 || v >= 3 + m) HIPCHK(hipMemsetAsync((char*)D.X + v * vb, 0, (size_t)D.L * D.esize, ctx->cs));
   }
   Job* dj = djobs + k.first;
   HIPCHK(hipMemcpyAsync(dj, hj.data(), sizeof(Job) * cnt, hipMemcpyHostToDevice, ctx->cs));
   std::vector<ChainCfg> cands;
   for (int rbv : {2, 4, 8})
-    for (int cpb : {1, 2})
+    for (int cpb : {1, 2, 4})
       for (int grp : {0, 32}) {
         if (grp > 0 && cnt <= grp) continue;
         ChainCfg c;
@@ -374,7 +381,7 @@ int tune_chain(wf_ctx* ctx, Klass& k, const std::vector<InstDesc>& hd, Job* djob
     };
     HIPCHK(run());   // warm-up
     float tmin = 1e30f;
-    for (int r = 0; r < 3; ++r) {
+    for (int r = 0; r < 5; ++r) {
       HIPCHK(hipEventRecord(e0, ctx->cs));
       HIPCHK(run());
       HIPCHK(hipEventRecord(e1, ctx->cs));
@@ -1271,8 +1278,8 @@ int wf_set_chain_tiles(wf_ctx* ctx, int32_t rbv, int32_t cpb, int32_t group) {
     ctx->fixedSet = false;
     return WF_OK;
   }
-  if (!(rbv == 2 || rbv == 4 || rbv == 8) || !(cpb == 1 || cpb == 2) || group < 0)
-    return fail(ctx, WF_EINVAL, "tiles: rbv in {2,4,8}, cpb in {1,2}, group >= 0");
+  if (!(rbv == 2 || rbv == 4 || rbv == 8) || !(cpb == 1 || cpb == 2 || cpb == 4) || group < 0)
+    return fail(ctx, WF_EINVAL, "tiles: rbv in {2,4,8}, cpb in {1,2,4}, group >= 0");
   ctx->fixedCfg.rbv = rbv;
   ctx->fixedCfg.cpb = cpb;
   ctx->fixedCfg.group = group;

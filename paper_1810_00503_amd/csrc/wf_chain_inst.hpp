@@ -13,7 +13,7 @@ static size_t lds_rowpass() { return (size_t)(N + C * RBV * (N / 2)) * sizeof(cp
 
 template <typename T, int N, int C, int CPB>
 static hipError_t prep_col() {
-  if ((N / 8) % CPB != 0) return hipSuccess;
+  if ((N / 2 / TB) % CPB != 0) return hipSuccess;
   hipError_t e = hipFuncSetAttribute((const void*)k_colinv<T, N, C, CPB>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                      (int)lds_colpass<T, N, C, CPB>());
   if (e != hipSuccess) return e;
@@ -32,6 +32,7 @@ static hipError_t prep_t() {
   if (e == hipSuccess) e = prep_row<T, N, C, 4>();
 #if WF_VARIANTS
   if (e == hipSuccess) e = prep_col<T, N, C, 2>();
+  if (e == hipSuccess) e = prep_col<T, N, C, 4>();
   if (e == hipSuccess) e = prep_row<T, N, C, 2>();
   if (e == hipSuccess) e = prep_row<T, N, C, 8>();
 #endif
@@ -41,7 +42,7 @@ static hipError_t prep_t() {
 template <typename T, int N, int C, int CPB>
 static void launch_col(int which, const Job* jobs, int batch, const cpx<T>* t, hipStream_t st) {
   const size_t lc = lds_colpass<T, N, C, CPB>();
-  const dim3 grid(N / 8 / CPB, batch);
+  const dim3 grid(N / 2 / TB / CPB, batch);
   if (which == CH_COLINV)
     k_colinv<T, N, C, CPB><<<grid, dim3(NT), lc, st>>>(jobs, t);
   else
@@ -71,8 +72,12 @@ static hipError_t launch_t(int which, const ChainCfg& cfg, const Job* jobs, int 
       case 1: launch_col<T, N, C, 1>(which, jobs, batch, t, st); break;
 #if WF_VARIANTS
       case 2:
-        if ((N / 8) % 2 != 0) return hipErrorInvalidValue;
+        if ((N / 2 / TB) % 2 != 0) return hipErrorInvalidValue;
         launch_col<T, N, C, 2>(which, jobs, batch, t, st);
+        break;
+      case 4:
+        if ((N / 2 / TB) % 4 != 0) return hipErrorInvalidValue;
+        launch_col<T, N, C, 4>(which, jobs, batch, t, st);
         break;
 #endif
       default: return hipErrorInvalidValue;

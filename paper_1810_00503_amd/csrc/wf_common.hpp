@@ -40,9 +40,9 @@ __device__ __forceinline__ cpx<T> scale(cpx<T> a, T s) { return mk(a.x * s, a.y 
 // ------------------------------------------------------------------------ layout
 // Internal storage of a harmonic field: column blocks of TB columns, each block a
 // contiguous [n][TB] array, so a column pass reads contiguous memory and a row pass
-// over 4 consecutive rows reads contiguous 4*TB runs.  The Nyquist column kx = n/2
+// over R consecutive rows reads contiguous R*TB runs.  The Nyquist column kx = n/2
 // (always dead) is not stored.
-constexpr int TB = 4;
+constexpr int TB = 2;
 constexpr int RB_MIN = 2;  // granularity of the row pass's partial sums (rows)
 constexpr int NT = 256;    // threads per work-group of the transform and vector passes
 constexpr int PASS_U = 4;                // vector loads per thread per stream in a vector pass

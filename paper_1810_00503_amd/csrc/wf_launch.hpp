@@ -10,7 +10,7 @@ enum { CH_COLINV = 0, CH_ROW = 1, CH_COLFWD = 2 };
 bool chain_supported(int n);
 
 // Tile choice of the transform chain: rows per work-group of the row pass (2, 4, 8),
-// column blocks per work-group of the column passes (1, 2) and instances per launch
+// column blocks per work-group of the column passes (1, 2, 4) and instances per launch
 // (0 = all).  float32 supports every choice, float64 the defaults (4, 1).
 struct ChainCfg {
   int rbv = 4;
@@ -43,7 +43,9 @@ inline hipError_t chain_prepare(int dtype, int n, int c) {
 }
 inline bool chain_cfg_supported(int dtype, int n, const ChainCfg& cfg) {
   if (dtype != 0) return cfg.rbv == 4 && cfg.cpb == 1;
-  return (cfg.rbv == 2 || cfg.rbv == 4 || cfg.rbv == 8) && (cfg.cpb == 1 || (cfg.cpb == 2 && (n / 8) % 2 == 0));
+  const int ncb = n / 2 / TB;   // column blocks
+  return (cfg.rbv == 2 || cfg.rbv == 4 || cfg.rbv == 8) && (cfg.cpb == 1 || cfg.cpb == 2 || cfg.cpb == 4) &&
+         ncb % cfg.cpb == 0;
 }
 
 enum { LB_ZERO = 0, LB_INIT = 1, LB_POSTB = 2, LB_PASSA = 3, LB_COEF = 4, LB_PASSB = 5 };

@@ -190,7 +190,7 @@ def test_tile_variants_agree_and_autotune(lib):
         lib.set_chain_tiles(4, 1, 0)
         ref, _, st0, _ = _solve(lib, probs, rel_grad_tol=1e-7)
         for rbv in (2, 4, 8):
-            for cpb in (1, 2):
+            for cpb in (1, 2, 4):
                 for grp in (0, 2):
                     lib.set_chain_tiles(rbv, cpb, grp)
                     got, _, st, _ = _solve(lib, probs, rel_grad_tol=1e-7)
@@ -201,6 +201,6 @@ def test_tile_variants_agree_and_autotune(lib):
         lib.set_chain_tiles(0)
     got, _, st, _ = _solve(lib, probs, rel_grad_tol=1e-7)
     rbv, cpb, grp, tuned = lib.get_chain_tiles(64, 2, lib.WF_F32, len(probs))
-    assert tuned and rbv in (2, 4, 8) and cpb in (1, 2)
+    assert tuned and rbv in (2, 4, 8) and cpb in (1, 2, 4)
     for i in range(len(probs)):
         assert rel_l2(got[i], ref[i]) < 2e-6
