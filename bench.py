@@ -48,6 +48,24 @@ def parse():
     return ap.parse_args()
 
 
+def measured_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 PMC summary
+    (profiles/pmc_traffic.json), or None if the kernel sources changed since it was taken."""
+    import glob
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "pmc_traffic.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    h = hashlib.sha1()
+    for p in sorted(glob.glob(os.path.join(ROOT, "paper_1810_00503_amd", "csrc", "*"))):
+        h.update(open(p, "rb").read())
+    if h.hexdigest() != rec.get("csrc_sha1"):
+        return None
+    k = rec.get("kernels", {}).get("k_" + kernel)
+    return None if k is None else k["traffic_bytes_per_launch"]
+
+
 def cpu_baseline(args):
     """The oracle (float64 numpy, one thread) solving the data map of the workload."""
     env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
@@ -167,7 +185,7 @@ def main():
                       "GB_per_s": round(v["bytes"] / (v["ms"] * 1e-3) / 1e9, 1) if v["ms"] > 0 and v["bytes"] > 0
                       else None} for k, v in ks.items()}
     roof = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(dom),
             "avg_launch_us": round(1e3 * kd["ms"] / max(kd["launches"], 1), 2),
             "bytes_per_launch": kd["bytes"] / max(kd["launches"], 1)}
 
