@@ -100,7 +100,11 @@ typedef struct {
   int32_t iters_per_poll; /* iterations enqueued between host checks (0 = automatic)     */
   int32_t use_graph;      /* 1 = replay captured HIP graphs of the iteration (default),
                              0 = launch kernels one by one                               */
-  int32_t reserved;
+  int32_t precond;        /* 0 = H0 = gamma I in the whitened variable w = S^-1/2 s (the
+                             paper's unpreconditioned L-BFGS, default); 1 = diagonal
+                             noise-aware H0 = gamma diag(1 / (1 + S_k <W>)), <W> the pixel
+                             mean of w, for very red spectra.  The stop test always uses
+                             the whitened gradient norm; the solution is the same MAP.   */
 } wf_lbfgs_opts;
 
 typedef struct {

@@ -94,10 +94,11 @@ class LbfgsOpts:
     refresh_every: int = 0
     iters_per_poll: int = 0
     use_graph: int = 1
+    precond: int = 0
 
     def c(self) -> L.WfLbfgsOpts:
         return L.WfLbfgsOpts(self.m, self.max_iter, self.rel_grad_tol, self.dchi2_tol, self.refresh_every,
-                             self.iters_per_poll, self.use_graph, 0)
+                             self.iters_per_poll, self.use_graph, self.precond)
 
 
 @dataclasses.dataclass

@@ -246,6 +246,7 @@ void fill_opts(const wf_lbfgs_opts* o, wf_lbfgs_opts& r) {
   if (r.m <= 0) r.m = 10;
   if (r.max_iter <= 0) r.max_iter = 20000;
   if (!(r.rel_grad_tol > 0)) r.rel_grad_tol = 1e-6;
+  if (r.precond != 0) r.precond = 1;
 }
 
 // ---------------------------------------------------------------------------- prior tables
@@ -253,21 +254,31 @@ struct PriorTab {
   void* sq = nullptr;         // [c][n][h] real
   int32_t* bandI = nullptr;   // [c][n][h]
   double* theta = nullptr;    // [nbands]
+  void* a = nullptr;          // preconditioned solves: P = 1 / (1 + S <W>)
+  void* ainv = nullptr;       // and 1 / P
 };
 
-size_t prior_bytes(const wf_problem* p) {
+size_t prior_bytes(const wf_problem* p, bool precond = false) {
   const size_t L = (size_t)p->ncomp * p->n * (p->n / 2);
-  return align_up(L * rsize_of(p->dtype)) + align_up(L * 4) + align_up(sizeof(double) * std::max(1, p->nbands));
+  return align_up(L * rsize_of(p->dtype)) + align_up(L * 4) + align_up(sizeof(double) * (std::max(1, p->nbands) + 1)) +
+         (precond ? 2 * align_up(L * rsize_of(p->dtype)) : 0);
 }
 
-int build_prior(wf_ctx* ctx, Arena& a, const wf_problem* p, const double* theta, PriorTab& t) {
+int build_prior(wf_ctx* ctx, Arena& a, const wf_problem* p, const double* theta, PriorTab& t, bool precond = false) {
   const size_t L = (size_t)p->ncomp * p->n * (p->n / 2);
   t.sq = arena_take(a, L * rsize_of(p->dtype));
   t.bandI = (int32_t*)arena_take(a, L * 4);
-  t.theta = (double*)arena_take(a, sizeof(double) * std::max(1, p->nbands));
+  t.theta = (double*)arena_take(a, sizeof(double) * (std::max(1, p->nbands) + 1));
+  double* meanW = t.theta + std::max(1, p->nbands);
+  t.a = t.ainv = nullptr;
+  if (precond) {
+    t.a = arena_take(a, L * rsize_of(p->dtype));
+    t.ainv = arena_take(a, L * rsize_of(p->dtype));
+  }
   if (p->nbands > 0)
     HIPCHK(hipMemcpyAsync(t.theta, theta, sizeof(double) * p->nbands, hipMemcpyHostToDevice, ctx->cs));
-  HIPCHK(prior_table_launch(p->dtype, p->n, p->ncomp, p->pshape, p->band, t.theta, p->nbands, t.sq, t.bandI, ctx->cs));
+  HIPCHK(prior_table_launch(p->dtype, p->n, p->ncomp, p->pshape, p->band, t.theta, p->nbands,
+                            precond ? p->w : nullptr, meanW, t.sq, t.bandI, t.a, t.ainv, ctx->cs));
   return WF_OK;
 }
 
@@ -343,6 +354,7 @@ int tune_chain(wf_ctx* ctx, Klass& k, const std::vector<InstDesc>& hd, Job* djob
     jb.W = D.W;
     jb.sIn = D.sq;
     jb.sOut = D.sq;
+    jb.aTab = D.aTab;
     jb.part = D.partChain;
     jb.pstride = D.pstride;
     jb.vcs = jb.vcstr = D.L;
@@ -433,6 +445,8 @@ int solve_core(wf_ctx* ctx, const wf_problem* probs, int B, const wf_lbfgs_opts&
   for (int i = 0; i < B; ++i) {
     const wf_problem* p = &probs[i];
     std::vector<double> th(p->theta, p->theta + p->nbands);
+    // a preconditioned table also depends on W
+    th.push_back(o.precond ? (double)(uintptr_t)p->w : 0.0);
     auto key = std::make_tuple((const void*)p->pshape, (const void*)p->band, p->n, p->ncomp, p->dtype, th);
     auto it = pmap.find(key);
     if (it == pmap.end()) {
@@ -446,7 +460,7 @@ int solve_core(wf_ctx* ctx, const wf_problem* probs, int B, const wf_lbfgs_opts&
   }
   // sizes
   size_t total = 0;
-  for (int id : prepIdx) total += prior_bytes(&probs[id]);
+  for (int id : prepIdx) total += prior_bytes(&probs[id], o.precond != 0);
   int pos = 0;
   for (auto& k : ks) {
     k.first = pos;
@@ -476,7 +490,7 @@ int solve_core(wf_ctx* ctx, const wf_problem* probs, int B, const wf_lbfgs_opts&
   int* dstat = (int*)arena_take(A, sizeof(int) * B);
   std::vector<PriorTab> ptabs(prepIdx.size());
   for (size_t id = 0; id < prepIdx.size(); ++id) {
-    rc = build_prior(ctx, A, &probs[prepIdx[id]], probs[prepIdx[id]].theta, ptabs[id]);
+    rc = build_prior(ctx, A, &probs[prepIdx[id]], probs[prepIdx[id]].theta, ptabs[id], o.precond != 0);
     if (rc) return rc;
   }
   std::vector<InstDesc> hd(B);
@@ -502,6 +516,8 @@ int solve_core(wf_ctx* ctx, const wf_problem* probs, int B, const wf_lbfgs_opts&
       D.d = p->d;
       D.W = p->w;
       D.sq = ptabs[pidx[ui]].sq;
+      D.aTab = ptabs[pidx[ui]].a;
+      D.ainv = ptabs[pidx[ui]].ainv;
       D.partChain = (double*)arena_take(A, sizeof(double) * PK_COUNT * k.pstride);
       D.partA = (double*)arena_take(A, sizeof(double) * kNdot * k.nchunk);
       D.statusOut = dstat + gi;
@@ -748,6 +764,7 @@ int band_E_solved(wf_ctx* ctx, const wf_problem* probs, int B, const SolveOut& s
   for (int i = 0; i < B; ++i) {
     hj[i].f = so.w[i];
     hj[i].sq = so.prior[i].sq;
+    hj[i].aw = so.prior[i].a;
     hj[i].bandI = so.prior[i].bandI;
     hj[i].theta = so.prior[i].theta;
     hj[i].part = part + (size_t)i * nblk * nb;
@@ -944,7 +961,7 @@ void wf_lbfgs_default(wf_lbfgs_opts* o) {
   o->refresh_every = 0;
   o->iters_per_poll = 0;
   o->use_graph = 1;
-  o->reserved = 0;
+  o->precond = 0;
 }
 
 int wf_create(wf_ctx** out, int hip_device) {
@@ -1255,6 +1272,7 @@ int wf_band_E(wf_ctx* ctx, const wf_problem* p, int32_t batch, const void* s, do
   for (int i = 0; i < batch; ++i) {
     hj[i].f = (char*)vin + (size_t)i * L * eb;
     hj[i].sq = pt.sq;
+    hj[i].aw = nullptr;
     hj[i].bandI = pt.bandI;
     hj[i].theta = pt.theta;
     hj[i].part = bpart + (size_t)i * nblk * nb;

@@ -158,7 +158,8 @@ __global__ __launch_bounds__(NT) void k_colinv(const Job* __restrict__ jobs, con
               acc += ((double)v.x * v.x + (double)v.y * v.y) / ((double)sq * sq);
             }
           } else if (mode == CM_GRAD && !part) {
-            acc += (double)v.x * v.x + (double)v.y * v.y;
+            const double wa = jb.aTab ? (double)reinterpret_cast<const T*>(jb.aTab)[src] : 1.0;
+            acc += wa * ((double)v.x * v.x + (double)v.y * v.y);
           }
         }
         a[c] = scale(v, sc);
@@ -419,7 +420,8 @@ __global__ __launch_bounds__(NT) void k_colfwd(const Job* __restrict__ jobs, con
         const T sq = sOut[o];
         if (fr && sq != T(0)) {
           const cpx<T> v = vadd[o + dv[c]];
-          out = mk(v.x + sq * t[c].x, v.y + sq * t[c].y);
+          const T wa = jb.aTab ? reinterpret_cast<const T*>(jb.aTab)[o] : T(1);
+          out = mk(wa * v.x + sq * t[c].x, wa * v.y + sq * t[c].y);
           avo += (double)v.x * out.x + (double)v.y * out.y;
         }
         aoo += (double)out.x * out.x + (double)out.y * out.y;

@@ -100,6 +100,7 @@ struct Job {
   const void* W;        // [n][n]
   const void* sIn;      // scale table for the column inverse (sqrt S), nullable
   const void* sOut;     // scale / liveness table for the column forward (sqrt S)
+  const void* aTab;     // prior weight of the solver variable (preconditioned solves), nullable -> 1
   const int32_t* band;  // internal-layout band table (CM_SIM boost)
   const void* draws;    // [2][c][n][n] normals (CM_SIM), nullable -> Philox
   void* xout;           // pixel output (CM_FWD, CM_SIM)
@@ -168,6 +169,7 @@ struct LbState {
 struct BandJob {
   const void* f;          // field, internal layout
   const void* sq;         // sqrt S table (raw fields)
+  const void* aw;         // solver-variable weight P_k (preconditioned solution), nullable
   const int32_t* bandI;   // internal band table (-1 = none / not free)
   const double* theta;    // [nbands] (device)
   double* part;           // [nblk][nbands]
@@ -188,7 +190,9 @@ struct InstDesc {
   void* y;          // transform intermediate
   const void* d;
   const void* W;
-  const void* sq;   // sqrt S table (internal layout, real)
+  const void* sq;   // scale table (internal layout, real): sqrt S, or sqrt(S P) when preconditioned
+  const void* aTab; // preconditioned solves: P_k = 1 / (1 + S_k <W>); else null
+  const void* ainv; // preconditioned solves: 1 / P_k (whitened gradient norm); else null
   double* partChain;   // [PK_COUNT][pstride]
   double* partA;       // [nblkA][NDOT]
   int* statusOut;      // compact per-instance status for host polling

@@ -52,8 +52,10 @@ enum { LB_ZERO = 0, LB_INIT = 1, LB_POSTB = 2, LB_PASSA = 3, LB_COEF = 4, LB_PAS
 hipError_t lbfgs_launch(int dtype, int m, int which, dim3 grid, InstDesc* desc, LbState* st, Job* jobs, int count,
                         hipStream_t s);
 
+// prior tables; with W non-null also the preconditioner (mean of W into meanW, a, ainv)
 hipError_t prior_table_launch(int dtype, int n, int c, const double* pshape, const int32_t* band, const double* theta,
-                              int nbands, void* sq, int32_t* bandI, hipStream_t s);
+                              int nbands, const void* W, double* meanW, void* sq, int32_t* bandI, void* aT, void* ainvT,
+                              hipStream_t s);
 hipError_t unpack_launch(int dtype, int n, int c, int batch, const void* ext, void* in, hipStream_t s);
 hipError_t pack_launch(int dtype, int n, int c, int batch, const void* in, int64_t inStride, int64_t vcs,
                        int64_t vcstr, const void* sq, int fill, void* const* outs, void* out0, hipStream_t s);

@@ -38,6 +38,15 @@ __device__ __forceinline__ double2 vaxpy(double a, const double2& x, const doubl
   return make_double2(y.x + a * x.x, y.y + a * x.y);
 }
 __device__ __forceinline__ float4 vscale(float a, const float4& x) { return make_float4(a * x.x, a * x.y, a * x.z, a * x.w); }
+// |g|^2 in the whitened norm of a preconditioned solve: sum over the complex elements of the
+// vector element e of |g_k|^2 / P_k (ainv = 1 / P)
+__device__ __forceinline__ double wnorm2(const float4& g, const float* ainv, int64_t e) {
+  const float2 a = reinterpret_cast<const float2*>(ainv)[e];
+  return (double)a.x * ((double)g.x * g.x + (double)g.y * g.y) + (double)a.y * ((double)g.z * g.z + (double)g.w * g.w);
+}
+__device__ __forceinline__ double wnorm2(const double2& g, const double* ainv, int64_t e) {
+  return ainv[e] * (g.x * g.x + g.y * g.y);
+}
 __device__ __forceinline__ double2 vscale(double a, const double2& x) { return make_double2(a * x.x, a * x.y); }
 
 constexpr int NDOT = 5 * MMAX + 1;          // partials per block of k_passA
@@ -81,6 +90,7 @@ __device__ __forceinline__ void make_job(Job& jb, const InstDesc& D, int mode, i
   jb.W = D.W;
   jb.sIn = D.sq;
   jb.sOut = D.sq;
+  jb.aTab = D.aTab;
   jb.band = nullptr;
   jb.draws = nullptr;
   jb.xout = nullptr;
@@ -167,12 +177,13 @@ __global__ __launch_bounds__(NT) void k_passA(const InstDesc* __restrict__ desc,
   bool ok[PASS_U];
   V gv[PASS_U];
   double gg = 0.0;
+  const T* ainv = reinterpret_cast<const T*>(D.ainv);
 #pragma unroll
   for (int u = 0; u < PASS_U; ++u) {
     ok[u] = e0 + (int64_t)u * NT < nvec;
     if (ok[u]) {
       gv[u] = g[e0 + (int64_t)u * NT];
-      gg += vdot(gv[u], gv[u]);
+      gg += ainv ? wnorm2(gv[u], ainv, e0 + (int64_t)u * NT) : vdot(gv[u], gv[u]);
     }
   }
   {
@@ -456,10 +467,11 @@ __global__ __launch_bounds__(NT) void k_passB(const InstDesc* __restrict__ desc,
     }
   }
   double gg = 0.0;
+  const T* ainv = reinterpret_cast<const T*>(D.ainv);
 #pragma unroll
   for (int u = 0; u < PASS_U; ++u) {
     if (ok[u]) {
-      gg += vdot(gv[u], gv[u]);
+      gg += ainv ? wnorm2(gv[u], ainv, e0 + (int64_t)u * NT) : vdot(gv[u], gv[u]);
       acc[u] = vscale(cg, gv[u]);
     }
   }
@@ -592,11 +604,14 @@ __global__ __launch_bounds__(256) void k_postB(const InstDesc* __restrict__ desc
 
 // ------------------------------------------------------------------------ tables and packing
 // sqrt S on the internal layout (0 on dead modes and conjugate partners), computed in
-// float64 from P_k and theta; internal band table (-1 off the free modes).
+// float64 from P_k and theta; internal band table (-1 off the free modes).  With meanW
+// (preconditioned solves) the scale becomes sqrt(S P) with P = 1 / (1 + S <W>), and a = P,
+// ainv = 1 / P are written as well.
 template <typename T>
 __global__ void k_prior_table(int n, int C, const double* __restrict__ pshape, const int32_t* __restrict__ band,
-                              const double* __restrict__ theta, int nbands, T* __restrict__ sq,
-                              int32_t* __restrict__ bandI) {
+                              const double* __restrict__ theta, int nbands, const double* __restrict__ meanW,
+                              T* __restrict__ sq, int32_t* __restrict__ bandI, T* __restrict__ aT,
+                              T* __restrict__ ainvT) {
   const int h = n / 2;
   const int64_t tot = (int64_t)C * n * h;
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < tot; e += (int64_t)gridDim.x * blockDim.x) {
@@ -604,18 +619,38 @@ __global__ void k_prior_table(int n, int C, const double* __restrict__ pshape, c
     const int r = (int)(e % ((int64_t)n * h));
     const int ky = r / h, kx = r % h;
     const int64_t src = ((int64_t)c * n + ky) * (h + 1) + kx;
-    double s = 0.0;
+    double S = 0.0;
     int b = -1;
     if (is_free(n, ky, kx)) {
       b = band[src];
       const double amp = (b >= 0 && b < nbands) ? theta[b] : 1.0;
-      const double S = amp * pshape[src];
-      s = S > 0.0 ? sqrt(S) : 0.0;
+      S = amp * pshape[src];
+      if (!(S > 0.0)) S = 0.0;
       if (!(b >= 0 && b < nbands)) b = -1;
     }
     const int64_t o = fidx(n, c, ky, kx);
-    sq[o] = T(s);
-    bandI[o] = (s > 0.0) ? b : -1;
+    double P = 1.0;
+    if (meanW) P = 1.0 / (1.0 + S * meanW[0]);
+    sq[o] = T(sqrt(S * P));
+    bandI[o] = (S > 0.0) ? b : -1;
+    if (aT) aT[o] = T(P);
+    if (ainvT) ainvT[o] = T(1.0 / P);
+  }
+}
+
+// pixel mean of W in float64 (one work-group)
+template <typename T>
+__global__ __launch_bounds__(1024) void k_mean_w(const T* __restrict__ W, int64_t npix, double* __restrict__ out) {
+  __shared__ double red[1024 / 64];
+  double a = 0.0;
+  for (int64_t e = threadIdx.x; e < npix; e += 1024) a += (double)W[e];
+  a = wave_sum(a);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = a;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int i = 0; i < 1024 / 64; ++i) t += red[i];
+    out[0] = t / (double)npix;
   }
 }
 
@@ -688,6 +723,7 @@ __global__ __launch_bounds__(NT) void k_band_part(const BandJob* __restrict__ jo
       if (bl[k] >= 0) {
         const cpx<T> a = f[vview(e, jb.vcs, jb.vcstr)];
         double t = (double)a.x * a.x + (double)a.y * a.y;
+        if (jb.aw) t *= (double)reinterpret_cast<const T*>(jb.aw)[e];
         if (jb.raw) {
           const double s = (double)sq[e];
           t /= s * s;

@@ -50,12 +50,22 @@ static dim3 flat_grid(int64_t tot) {
 }
 
 hipError_t prior_table_launch(int dtype, int n, int c, const double* pshape, const int32_t* band, const double* theta,
-                              int nbands, void* sq, int32_t* bandI, hipStream_t s) {
+                              int nbands, const void* W, double* meanW, void* sq, int32_t* bandI, void* aT, void* ainvT,
+                              hipStream_t s) {
   const dim3 g = flat_grid((int64_t)c * n * (n / 2));
+  if (W) {
+    if (dtype == 0)
+      k_mean_w<float><<<1, 1024, 0, s>>>((const float*)W, (int64_t)n * n, meanW);
+    else
+      k_mean_w<double><<<1, 1024, 0, s>>>((const double*)W, (int64_t)n * n, meanW);
+  }
+  const double* mw = W ? meanW : nullptr;
   if (dtype == 0)
-    k_prior_table<float><<<g, 256, 0, s>>>(n, c, pshape, band, theta, nbands, (float*)sq, bandI);
+    k_prior_table<float><<<g, 256, 0, s>>>(n, c, pshape, band, theta, nbands, mw, (float*)sq, bandI, (float*)aT,
+                                          (float*)ainvT);
   else
-    k_prior_table<double><<<g, 256, 0, s>>>(n, c, pshape, band, theta, nbands, (double*)sq, bandI);
+    k_prior_table<double><<<g, 256, 0, s>>>(n, c, pshape, band, theta, nbands, mw, (double*)sq, bandI, (double*)aT,
+                                           (double*)ainvT);
   return hipGetLastError();
 }
 
