@@ -221,7 +221,9 @@ def main():
         "bandpower_estimates_per_s": round(args.steps / elapsed, 3),
         "iters_mean": round(float(np.mean(iters)), 1), "iters_max": int(np.max(iters)),
         "chain_tiles": {"rows_per_wg": tiles[0], "col_blocks_per_wg": tiles[1], "instances_per_launch": tiles[2],
-                        "autotuned": tiles[3]},
+                        "register_staged": {"row": bool(tiles[3] & 1), "column_inverse": bool(tiles[3] & 2),
+                                            "column_forward": bool(tiles[3] & 4)},
+                        "autotuned": tiles[4]},
         "converged": f"{conv}/{len(sims)}",
         "per_kernel": per_kernel,
     }

@@ -186,15 +186,19 @@ int wf_band_E(wf_ctx* ctx, const wf_problem* prob, int32_t batch, const void* s,
 /* Tiles of the transform chain (the three passes of every gradient / curvature product):
  * rbv = image rows per work-group of the row pass (2, 4, 8), cpb = column blocks of 2
  * columns per work-group of the column passes (1, 2, 4; must divide n/4), group =
- * instances per launch (0 = all).  By default (rbv = 0) the library autotunes them: on
- * the first float32 solve of a batch of >= 4 maps of a given (n, ncomp, batch-size
- * bucket) it times every choice on that batch and keeps the fastest for the context.
- * float64 uses (4, 1, 0).  Every choice computes the same result up to the order of the
- * FP64 partial sums.  wf_get_chain_tiles reports the choice in use (WF_OK) or the
- * default if none was tuned yet (WF_NOT_CONVERGED).                                   */
-int wf_set_chain_tiles(wf_ctx* ctx, int32_t rbv, int32_t cpb, int32_t group);
+ * instances per launch (0 = all), reg = which passes run the register-staged FFT instead
+ * of the LDS-staged one (bit 0: row pass, whose rows per work-group are then fixed by n;
+ * bit 1: column inverse, bit 2: column forward, which need cpb * ncomp * 2 * n / 256 in
+ * [4, 32]; float32 and power-of-two n >= 128 only).  By default (rbv = 0) the library autotunes them: on the
+ * first float32 solve of a batch of >= 4 maps of a given (n, ncomp, batch-size bucket) it
+ * times every supported choice on that batch and keeps the fastest for the context.
+ * float64 uses (4, 1, 0, 0), as does a fixed choice that the shape does not support.
+ * Every choice computes the same result up to the rounding of the transforms and the
+ * order of the FP64 partial sums.  wf_get_chain_tiles reports the choice in use (WF_OK)
+ * or the default if none was tuned yet (WF_NOT_CONVERGED).                             */
+int wf_set_chain_tiles(wf_ctx* ctx, int32_t rbv, int32_t cpb, int32_t group, int32_t reg);
 int wf_get_chain_tiles(wf_ctx* ctx, int32_t n, int32_t ncomp, int32_t dtype, int32_t batch, int32_t* rbv, int32_t* cpb,
-                       int32_t* group);
+                       int32_t* group, int32_t* reg);
 
 /* instrumentation: per-kernel-kind launch counts, accumulated kernel time (HIP events
  * around each launch; only while profiling is on, which disables graph replay) and

@@ -396,19 +396,22 @@ def reset_kernel_stats(ctx: Context | None = None):
     cx.check(cx.lib.wf_reset_kernel_stats(cx.h))
 
 
-def set_chain_tiles(rbv: int = 0, cpb: int = 1, group: int = 0, ctx: Context | None = None):
+def set_chain_tiles(rbv: int = 0, cpb: int = 1, group: int = 0, reg: int = 0, ctx: Context | None = None):
     """Fix the transform chain's tiles (rbv rows, cpb column blocks, group instances per
-    launch), or return to autotuning with rbv = 0."""
+    launch, reg = register-staged passes: bit 0 row, bit 1 column inverse, bit 2 column
+    forward), or return to
+    autotuning with rbv = 0."""
     cx = ctx or context(0)
-    cx.check(cx.lib.wf_set_chain_tiles(cx.h, int(rbv), int(cpb), int(group)))
+    cx.check(cx.lib.wf_set_chain_tiles(cx.h, int(rbv), int(cpb), int(group), int(reg)))
 
 
 def get_chain_tiles(n: int, ncomp: int, dtype: int = WF_F32, batch: int = 64, ctx: Context | None = None):
-    """(rbv, cpb, group, tuned) in use for this shape and batch size."""
+    """(rbv, cpb, group, reg, tuned) in use for this shape and batch size."""
     cx = ctx or context(0)
-    a, b, g = C.c_int32(), C.c_int32(), C.c_int32()
-    rc = cx.check(cx.lib.wf_get_chain_tiles(cx.h, n, ncomp, dtype, batch, C.byref(a), C.byref(b), C.byref(g)))
-    return a.value, b.value, g.value, rc == 0
+    a, b, g, r = C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32()
+    rc = cx.check(cx.lib.wf_get_chain_tiles(cx.h, n, ncomp, dtype, batch, C.byref(a), C.byref(b), C.byref(g),
+                                            C.byref(r)))
+    return a.value, b.value, g.value, r.value, rc == 0
 
 
 from . import autograd  # noqa: E402,F401  (torch.autograd.Function wrappers)

@@ -81,8 +81,9 @@ def load(path: str | None = None):
     L.wf_kernel_kind_name.restype = C.c_char_p
     L.wf_get_kernel_stats.argtypes = [vp, C.POINTER(C.c_int64), dp, dp]
     L.wf_reset_kernel_stats.argtypes = [vp]
-    L.wf_set_chain_tiles.argtypes = [vp, i32, i32, i32]
-    L.wf_get_chain_tiles.argtypes = [vp, i32, i32, i32, i32, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32)]
+    L.wf_set_chain_tiles.argtypes = [vp, i32, i32, i32, i32]
+    L.wf_get_chain_tiles.argtypes = [vp, i32, i32, i32, i32, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32),
+                                     C.POINTER(i32)]
     for name in EXPORTS:
         fn = getattr(L, name)
         if fn.restype is C.c_int:

@@ -16,6 +16,7 @@
 
 #include "wf.h"
 #include "wf_launch.hpp"
+#include "wf_rfft.hpp"
 
 using namespace wf;
 
@@ -134,7 +135,25 @@ int host_status(wf_ctx* ctx, size_t n) {
   return WF_OK;
 }
 
-// twiddles exp(-2 pi i k / n), k in [0, n), generated in float64
+// Twiddles, generated in float64: exp(-2 pi i k / n) for k in [0, n); for power-of-two n
+// also the stage tables of the register-staged transforms (column schedules of length n
+// and row schedules of length n / 2, at tw_col_off / tw_row_off).
+static void stage_table(std::vector<double>& h, int64_t at, int len, int E, bool rev) {
+  const int S = rs_nst(len, E), R0 = rs_radix(len, E, rev, 0);
+  for (int s = 1; s < S; ++s) {
+    const int R = rs_radix(len, E, rev, s), NS = rs_ns(len, E, rev, s);
+    const int64_t off = at + (NS - R0);
+    for (int r = 1; r < R; ++r)
+      for (int k = 0; k < NS; ++k) {
+        const int64_t M = (int64_t)NS * R;
+        const double a = 2.0 * M_PI * (double)(((int64_t)r * k) % M) / (double)M;
+        const int64_t e = off + (int64_t)(r - 1) * NS + k;
+        h[2 * e] = std::cos(a);
+        h[2 * e + 1] = -std::sin(a);
+      }
+  }
+}
+
 int twiddles(wf_ctx* ctx, int n, int dtype, const void** out) {
   auto key = std::make_pair(n, dtype);
   auto it = ctx->tw.find(key);
@@ -142,15 +161,23 @@ int twiddles(wf_ctx* ctx, int n, int dtype, const void** out) {
     *out = it->second;
     return WF_OK;
   }
-  std::vector<double> h(2 * (size_t)n);
+  const bool pow2 = (n & (n - 1)) == 0 && n >= 8;
+  const int64_t entries = pow2 ? tw_ext_entries(n) : n;
+  std::vector<double> h(2 * (size_t)entries, 0.0);
   for (int k = 0; k < n; ++k) {
-    // reduce to the first octant for accuracy, then apply symmetries
     const double a = 2.0 * M_PI * (double)k / (double)n;
     h[2 * k] = std::cos(a);
     h[2 * k + 1] = -std::sin(a);
   }
+  if (pow2) {
+    for (int E = 2; E <= 32; E *= 2) stage_table(h, tw_col_off(n, E), n, E, false);
+    for (int E = 8; E <= 32; E *= 2) {
+      stage_table(h, tw_row_off(n, E, false), n / 2, E, false);
+      stage_table(h, tw_row_off(n, E, true), n / 2, E, true);
+    }
+  }
   void* d = nullptr;
-  const size_t bytes = (size_t)n * esize_of(dtype);
+  const size_t bytes = (size_t)entries * esize_of(dtype);
   HIPCHK(hipMalloc(&d, bytes));
   if (dtype == WF_F64) {
     HIPCHK(hipMemcpy(d, h.data(), bytes, hipMemcpyHostToDevice));
@@ -216,9 +243,15 @@ int drain_events(wf_ctx* ctx) {
   return WF_OK;
 }
 
+// tiles of operator-level calls: the fixed choice if one is set and supported, else the default
+ChainCfg op_cfg(const wf_ctx* ctx, int dtype, int n, int c) {
+  return ctx->fixedSet && chain_cfg_supported(dtype, n, c, ctx->fixedCfg) ? ctx->fixedCfg : ChainCfg();
+}
+
 hipError_t chain(wf_ctx* ctx, int dtype, int n, int c, int which, const Job* jobs, int batch, const void* tw,
-                 const ChainCfg& cfg = ChainCfg()) {
+                 const ChainCfg* cfgp = nullptr) {
   Timed t(ctx, which == CH_COLINV ? KK_COLINV : (which == CH_ROW ? KK_ROW : KK_COLFWD));
+  const ChainCfg cfg = cfgp ? *cfgp : op_cfg(ctx, dtype, n, c);
   return chain_launch(dtype, n, c, which, cfg, jobs, batch, tw, ctx->cs);
 }
 
@@ -325,7 +358,7 @@ int tune_chain(wf_ctx* ctx, Klass& k, const std::vector<InstDesc>& hd, Job* djob
   const int cnt = (int)k.members.size();
   const int bucket = cnt >= 64 ? 64 : (cnt >= 16 ? 16 : (cnt >= 4 ? 4 : 1));
   if (ctx->fixedSet) {
-    k.cfg = chain_cfg_supported(k.dtype, k.n, ctx->fixedCfg) ? ctx->fixedCfg : ChainCfg();
+    k.cfg = chain_cfg_supported(k.dtype, k.n, k.c, ctx->fixedCfg) ? ctx->fixedCfg : ChainCfg();
     return WF_OK;
   }
   const auto key = std::make_tuple(k.n, k.c, k.dtype, bucket);
@@ -369,16 +402,20 @@ int tune_chain(wf_ctx* ctx, Klass& k, const std::vector<InstDesc>& hd, Job* djob
   Job* dj = djobs + k.first;
   HIPCHK(hipMemcpyAsync(dj, hj.data(), sizeof(Job) * cnt, hipMemcpyHostToDevice, ctx->cs));
   std::vector<ChainCfg> cands;
-  for (int rbv : {2, 4, 8})
-    for (int cpb : {1, 2, 4})
-      for (int grp : {0, 32}) {
-        if (grp > 0 && cnt <= grp) continue;
-        ChainCfg c;
-        c.rbv = rbv;
-        c.cpb = cpb;
-        c.group = grp;
-        if (chain_cfg_supported(k.dtype, k.n, c)) cands.push_back(c);
-      }
+  for (int reg = 0; reg < 8; ++reg)
+    for (int rbv : {2, 4, 8}) {
+      if ((reg & 1) && rbv != 4) continue;   // the register-staged row pass has its own tile
+      for (int cpb : {1, 2, 4})
+        for (int grp : {0, 32}) {
+          if (grp > 0 && cnt <= grp) continue;
+          ChainCfg c;
+          c.rbv = rbv;
+          c.cpb = cpb;
+          c.group = grp;
+          c.reg = reg;
+          if (chain_cfg_supported(k.dtype, k.n, k.c, c)) cands.push_back(c);
+        }
+    }
   hipEvent_t e0 = ev_get(ctx), e1 = ev_get(ctx);
   float best = 1e30f;
   for (const ChainCfg& c : cands) {
@@ -469,7 +506,7 @@ int solve_core(wf_ctx* ctx, const wf_problem* probs, int B, const wf_lbfgs_opts&
     const size_t eb = esize_of(k.dtype);
     const int64_t nvec = k.L * 2 / (k.dtype == WF_F64 ? 2 : 4);
     k.nchunk = (int)((nvec + PASS_CV - 1) / PASS_CV);
-    k.pstride = k.n / RB_MIN;
+    k.pstride = k.c * k.n / RB_MIN;   // row partials per component and RB_MIN rows
     const size_t vsb = (size_t)k.L * eb + kVecPadBytes;
     const size_t per = align_up((size_t)(2 + 2 * m) * vsb) + align_up(vsb) +
                        align_up(sizeof(double) * PK_COUNT * k.pstride) + align_up(sizeof(double) * kNdot * k.nchunk);
@@ -568,7 +605,7 @@ int solve_core(wf_ctx* ctx, const wf_problem* probs, int B, const wf_lbfgs_opts&
       const int G = k.cfg.group > 0 ? std::min(k.cfg.group, cnt) : cnt;
       for (int g0 = 0; g0 < cnt; g0 += G) {
         const int gc = std::min(G, cnt - g0);
-        for (int w = 0; w < 3; ++w) HIPCHK(chain(ctx, k.dtype, k.n, k.c, w, djobs + k.first + g0, gc, k.tw, k.cfg));
+        for (int w = 0; w < 3; ++w) HIPCHK(chain(ctx, k.dtype, k.n, k.c, w, djobs + k.first + g0, gc, k.tw, &k.cfg));
       }
     }
     for (auto& k : ks) {
@@ -606,7 +643,7 @@ int solve_core(wf_ctx* ctx, const wf_problem* probs, int B, const wf_lbfgs_opts&
     key = buf;
     for (auto& k : ks) key += std::to_string(k.n) + "," + std::to_string(k.c) + "," + std::to_string(k.dtype) + "," +
                               std::to_string(k.members.size()) + "," + std::to_string(k.cfg.rbv) + "," +
-                              std::to_string(k.cfg.cpb) + "," + std::to_string(k.cfg.group) + ";";
+                              std::to_string(k.cfg.cpb) + "," + std::to_string(k.cfg.group) + "," + std::to_string(k.cfg.reg) + ";";
     if (key != ctx->gkey) {
       if (ctx->gexec) (void)hipGraphExecDestroy(ctx->gexec);
       ctx->gexec = nullptr;
@@ -827,8 +864,10 @@ int simulate_entries(wf_ctx* ctx, const wf_problem* p, const std::vector<SimEntr
   if (rc) return rc;
   rc = prepare(ctx, n, c, dt);
   if (rc) return rc;
-  HIPCHK(chain(ctx, dt, n, c, CH_COLINV, dj, (int)hj.size(), tw));
-  HIPCHK(chain(ctx, dt, n, c, CH_ROW, dj, (int)hj.size(), tw));
+  ChainCfg scfg;
+  scfg.sim = 1;
+  HIPCHK(chain(ctx, dt, n, c, CH_COLINV, dj, (int)hj.size(), tw, &scfg));
+  HIPCHK(chain(ctx, dt, n, c, CH_ROW, dj, (int)hj.size(), tw, &scfg));
   return WF_OK;
 }
 
@@ -915,7 +954,7 @@ int op_setup(wf_ctx* ctx, const wf_problem* p, int batch, size_t extra, PriorTab
   const int n = p->n, c = p->ncomp, dt = p->dtype;
   const int64_t L = (int64_t)c * n * (n / 2);
   const size_t eb = esize_of(dt);
-  const int pstride = n / RB_MIN;
+  const int pstride = c * n / RB_MIN;
   const size_t need = prior_bytes(p) + 3 * align_up((size_t)L * eb * batch) + align_up(sizeof(Job) * batch) +
                       align_up(sizeof(double) * PK_COUNT * pstride * batch) + extra;
   int rc = arena_reserve(ctx, ctx->opA, need);
@@ -1188,7 +1227,7 @@ static int raw_chain(wf_ctx* ctx, const wf_problem* p, int batch, const void* s,
   const int n = p->n, c = p->ncomp, dt = p->dtype;
   const int64_t L = (int64_t)c * n * (n / 2);
   const size_t eb = esize_of(dt);
-  const int pstride = n / RB_MIN;
+  const int pstride = c * n / RB_MIN;
   HIPCHK(unpack_launch(dt, n, c, batch, s, vin, ctx->cs));
   std::vector<Job> hj(batch);
   for (int i = 0; i < batch; ++i) {
@@ -1213,7 +1252,7 @@ static int raw_chain(wf_ctx* ctx, const wf_problem* p, int batch, const void* s,
     std::vector<double> hp((size_t)PK_COUNT * pstride * batch);
     HIPCHK(hipMemcpyAsync(hp.data(), part, sizeof(double) * hp.size(), hipMemcpyDeviceToHost, ctx->cs));
     HIPCHK(hipStreamSynchronize(ctx->cs));
-    const int ncol = (n / 2) / TB, nrow = n / RB_MIN;
+    const int ncol = (n / 2) / TB, nrow = c * n / RB_MIN;
     for (int i = 0; i < batch; ++i) {
       const double* q = &hp[(size_t)i * PK_COUNT * pstride];
       double pr = 0.0, rs = 0.0;
@@ -1290,31 +1329,33 @@ int wf_band_E(wf_ctx* ctx, const wf_problem* p, int32_t batch, const void* s, do
   return WF_OK;
 }
 
-int wf_set_chain_tiles(wf_ctx* ctx, int32_t rbv, int32_t cpb, int32_t group) {
+int wf_set_chain_tiles(wf_ctx* ctx, int32_t rbv, int32_t cpb, int32_t group, int32_t reg) {
   if (!ctx) return WF_EINVAL;
   if (rbv == 0) {
     ctx->fixedSet = false;
     return WF_OK;
   }
-  if (!(rbv == 2 || rbv == 4 || rbv == 8) || !(cpb == 1 || cpb == 2 || cpb == 4) || group < 0)
-    return fail(ctx, WF_EINVAL, "tiles: rbv in {2,4,8}, cpb in {1,2,4}, group >= 0");
+  if (!(rbv == 2 || rbv == 4 || rbv == 8) || !(cpb == 1 || cpb == 2 || cpb == 4) || group < 0 || reg < 0 || reg > 7)
+    return fail(ctx, WF_EINVAL, "tiles: rbv in {2,4,8}, cpb in {1,2,4}, group >= 0, reg in [0, 7]");
   ctx->fixedCfg.rbv = rbv;
   ctx->fixedCfg.cpb = cpb;
   ctx->fixedCfg.group = group;
+  ctx->fixedCfg.reg = reg;
   ctx->fixedSet = true;
   return WF_OK;
 }
 
 int wf_get_chain_tiles(wf_ctx* ctx, int32_t n, int32_t ncomp, int32_t dtype, int32_t batch, int32_t* rbv, int32_t* cpb,
-                       int32_t* group) {
-  if (!ctx || !rbv || !cpb || !group) return WF_EINVAL;
+                       int32_t* group, int32_t* reg) {
+  if (!ctx || !rbv || !cpb || !group || !reg) return WF_EINVAL;
   const int bucket = batch >= 64 ? 64 : (batch >= 16 ? 16 : (batch >= 4 ? 4 : 1));
   auto it = ctx->tuned.find(std::make_tuple((int)n, (int)ncomp, (int)dtype, bucket));
   ChainCfg c = it != ctx->tuned.end() ? it->second : ChainCfg();
-  if (ctx->fixedSet) c = ctx->fixedCfg;
+  if (ctx->fixedSet) c = chain_cfg_supported(dtype, n, ncomp, ctx->fixedCfg) ? ctx->fixedCfg : ChainCfg();
   *rbv = c.rbv;
   *cpb = c.cpb;
   *group = c.group;
+  *reg = c.reg;
   return it != ctx->tuned.end() || ctx->fixedSet ? WF_OK : WF_NOT_CONVERGED;
 }
 

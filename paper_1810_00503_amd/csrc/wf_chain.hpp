@@ -9,11 +9,12 @@
 //                           added term, dot-product partials.
 //
 // Every pass stages its tile in LDS and transforms it with the Stockham FFT of
-// wf_fft.hpp.  A work-group of the column passes owns CPB column blocks of TB columns
+// wf_fft.hpp; for power-of-two grids in float32 a register-staged variant of each pass
+// (wf_rfft.hpp, end of this file) keeps the transform in registers between LDS exchanges.  A work-group of the column passes owns CPB column blocks of TB columns
 // (both components; each block contiguous in memory); a work-group of the row pass owns
 // RBV rows.  CPB and RBV are tile choices made per problem shape by the autotuner.
 #pragma once
-#include "wf_fft.hpp"
+#include "wf_rfft.hpp"
 
 namespace wf {
 
@@ -92,12 +93,222 @@ __device__ __forceinline__ void rot2(int kx, int kys, T& c2, T& s2) {
 template <typename T>
 __device__ __forceinline__ size_t chain_lds_col(int N, int C) { return (size_t)(N + N * C * TB) * sizeof(cpx<T>); }
 
+// ------------------------------------------------------------------------ per-element steps
+// Column-inverse input of component c at (ky, kx): scale (sqrt S, simulation amplitude),
+// liveness, prior partial (gradient modes).  Returns the value before the spin-2 rotation;
+// part/kyr tell whether (ky, kx) is a kx = 0 conjugate partner and which stored row holds its
+// free entry.  dvc: offset of the input view of this column block.  SIMK: the simulation mode
+// (normals from draws or Philox, in float64) is compiled in; it costs registers, so only the
+// kernels that simulation launches use it.
+template <typename T, int N, bool SIMK>
+__device__ __forceinline__ cpx<T> colinv_in(const Job& jb, int mode, int c, int ky, int kx, int64_t dvc, bool& part,
+                                            int& kyr, double& acc) {
+  cpx<T> a = mk(T(0), T(0));
+  part = false;
+  kyr = ky;
+  if (!is_live(N, ky, kx)) return a;
+  part = is_partner(N, ky, kx);
+  kyr = part ? N - ky : ky;
+  const int64_t src = fidx(N, c, kyr, kx);
+  const T* sIn = reinterpret_cast<const T*>(jb.sIn);
+  cpx<T> v;
+  T sc = T(1);
+  if (SIMK && mode == CM_SIM) {
+    const T* draws = reinterpret_cast<const T*>(jb.draws);
+    const int64_t qn = ((int64_t)c * N + kyr) * N + 2 * kx;
+    if (draws) {
+      v = mk(draws[qn], draws[qn + 1]);
+    } else {
+      double z0, z1;
+      philox_normal_pair(jb.seed, jb.sim, qn, z0, z1);
+      v = mk(T(z0), T(z1));
+    }
+    sc = sIn[src] * T(0.70710678118654752440084436210485);
+    if (jb.band && jb.boost_band >= 0 && jb.band[src] == jb.boost_band) sc *= T(jb.boost_factor);
+  } else {
+    v = reinterpret_cast<const cpx<T>*>(jb.vin)[src + dvc];
+    if (sIn) sc = sIn[src];
+    if (mode == CM_RAW_GRAD || mode == CM_RAW_HV) {
+      const T sq = reinterpret_cast<const T*>(jb.sOut)[src];
+      if (sq == T(0)) {
+        v = mk(T(0), T(0));
+      } else if (!part && mode == CM_RAW_GRAD) {
+        acc += ((double)v.x * v.x + (double)v.y * v.y) / ((double)sq * sq);
+      }
+    } else if (mode == CM_GRAD && !part) {
+      const double wa = jb.aTab ? (double)reinterpret_cast<const T*>(jb.aTab)[src] : 1.0;
+      acc += wa * ((double)v.x * v.x + (double)v.y * v.y);
+    }
+  }
+  return scale(v, sc);
+}
+
+// Pixel step of the row pass for complex element j of image row y of component c (pixels
+// 2j, 2j + 1).  Adjoint modes read the pixels into z; otherwise z holds the unnormalised
+// inverse transform and becomes the input of the forward transform (or is written to xout
+// and the pass ends there: CM_FWD, CM_SIM).
+template <typename T, int N, int C, bool SIMK>
+__device__ __forceinline__ void row_pixel(const Job& jb, int mode, bool adjIn, int c, int y, int j, cpx<T>& z,
+                                          double& acc) {
+  const T invn = T(1) / T(N);
+  const T* W = reinterpret_cast<const T*>(jb.W);
+  const T* dd = reinterpret_cast<const T*>(jb.d);
+  const int64_t pix = (int64_t)y * N + 2 * j;
+  const int64_t cp = (int64_t)c * N * N + pix;
+  if (adjIn) {
+    T x0 = dd[cp], x1 = dd[cp + 1];
+    if (W) {   // masked adjoint: R^T M x
+      if (!(W[pix] > T(0))) x0 = T(0);
+      if (!(W[pix + 1] > T(0))) x1 = T(0);
+    }
+    z = mk(x0 * invn, x1 * invn);
+    return;
+  }
+  const T x0 = z.x * invn, x1 = z.y * invn;
+  T* xout = reinterpret_cast<T*>(jb.xout);
+  if (mode == CM_FWD) {   // masked forward M R s when W is given
+    xout[cp] = (W && !(W[pix] > T(0))) ? T(0) : x0;
+    xout[cp + 1] = (W && !(W[pix + 1] > T(0))) ? T(0) : x1;
+    return;
+  }
+  const T W0 = W[pix], W1 = W[pix + 1];
+  if (SIMK && mode == CM_SIM) {
+    const T* draws = reinterpret_cast<const T*>(jb.draws);
+    T n0, n1;
+    const int64_t qn = (int64_t)C * N * N + cp;
+    if (draws) {
+      n0 = draws[qn];
+      n1 = draws[qn + 1];
+    } else {
+      double z0, z1;
+      philox_normal_pair(jb.seed, jb.sim, qn, z0, z1);
+      n0 = T(z0);
+      n1 = T(z1);
+    }
+    xout[cp] = W0 > T(0) ? x0 + n0 / sqrt(W0) : T(0);
+    xout[cp + 1] = W1 > T(0) ? x1 + n1 / sqrt(W1) : T(0);
+    return;
+  }
+  T r0, r1;
+  if (mode == CM_HV || mode == CM_RAW_HV) {
+    r0 = W0 * x0;
+    r1 = W1 * x1;
+  } else {  // CM_GRAD, CM_RAW_GRAD: r = W (x - d); masked pixels contribute nothing
+    r0 = T(0);
+    r1 = T(0);
+    if (W0 > T(0)) {
+      const T e0 = x0 - dd[cp];
+      r0 = W0 * e0;
+      acc += (double)r0 * e0;
+    }
+    if (W1 > T(0)) {
+      const T e1 = x1 - dd[cp + 1];
+      r1 = W1 * e1;
+      acc += (double)r1 * e1;
+    }
+  }
+  z = mk(r0 * invn, r1 * invn);
+}
+
+// Column-forward output of component c at (ky, kx) = internal index o (t: forward
+// transform after the inverse rotation): prior scale, added term, the v.out and out.out
+// partials; writes and returns the output.
+template <typename T, int N>
+__device__ __forceinline__ cpx<T> colfwd_val(const Job& jb, int mode, int ky, int kx, int64_t o, int64_t dvc,
+                                             cpx<T> t, double& avo, double& aoo) {
+  const bool fr = is_free(N, ky, kx);
+  cpx<T> out = mk(T(0), T(0));
+  if (mode == CM_HV || mode == CM_GRAD) {
+    const T sq = reinterpret_cast<const T*>(jb.sOut)[o];
+    if (fr && sq != T(0)) {
+      const cpx<T> v = reinterpret_cast<const cpx<T>*>(jb.vadd)[o + dvc];
+      const T wa = jb.aTab ? reinterpret_cast<const T*>(jb.aTab)[o] : T(1);
+      out = mk(wa * v.x + sq * t.x, wa * v.y + sq * t.y);
+      avo += (double)v.x * out.x + (double)v.y * out.y;
+    }
+    aoo += (double)out.x * out.x + (double)out.y * out.y;
+  } else if (mode == CM_RAW_GRAD || mode == CM_RAW_HV) {
+    const T sq = reinterpret_cast<const T*>(jb.sOut)[o];
+    if (fr && sq != T(0)) {
+      const cpx<T> v = reinterpret_cast<const cpx<T>*>(jb.vadd)[o + dvc];
+      const T is = T(1) / (sq * sq);
+      out = mk(T(4) * (v.x * is + t.x), T(4) * (v.y * is + t.y));
+    }
+  } else if (mode == CM_ADJ) {
+    if (is_live(N, ky, kx)) out = t;
+  } else {  // CM_ADJ_GRAD
+    if (fr) out = scale(t, T(2));
+  }
+  reinterpret_cast<cpx<T>*>(jb.vout)[o + dvc] = out;
+  return out;
+}
+
+// The same plus, for curvature products inside the solver (extras), the dots of the output
+// with g and with the kept Dp_j.
+template <typename T, int N>
+__device__ __forceinline__ void colfwd_out(const Job& jb, int mode, bool extras, int ky, int kx, int64_t o,
+                                           int64_t dvc, cpx<T> t, double& avo, double& aoo, double& adg,
+                                           double (&add)[MMAX]) {
+  const cpx<T> out = colfwd_val<T, N>(jb, mode, ky, kx, o, dvc, t, avo, aoo);
+  if (extras) {
+    const cpx<T> gv = reinterpret_cast<const cpx<T>*>(jb.gvec)[o + dvc];
+    adg += (double)gv.x * out.x + (double)gv.y * out.y;
+    const cpx<T>* dpb = reinterpret_cast<const cpx<T>*>(jb.dpBase);
+#pragma unroll
+    for (int j = 0; j < MMAX; ++j) {
+      if ((jb.dpMask >> j) & 1u) {
+        const cpx<T> dj = dpb[(int64_t)j * jb.dpStride + o + dvc];
+        add[j] += (double)dj.x * out.x + (double)dj.y * out.y;
+      }
+    }
+  }
+}
+
+// Work-group reduction of the column-forward partials: [VO, OO, DG, DD_0 .. DD_{MMAX-1}] ->
+// kinds PK_VO + idx, one value per column block (the first block of the work-group holds the
+// sum, the others 0).  Every thread must call it.
+__device__ __forceinline__ void colfwd_reduce(const Job& jb, int mode, bool extras, double avo, double aoo, double adg,
+                                              const double (&add)[MMAX], int q, int cpb) {
+  if (!(mode == CM_HV || mode == CM_GRAD)) return;
+  __shared__ double red2[NT / 64][3 + MMAX];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int nv = extras ? 3 + MMAX : 2;
+  const uint32_t mask = jb.dpMask;
+  {
+    const double a0 = wave_sum(avo), a1 = wave_sum(aoo);
+    if (lane == 0) {
+      red2[wv][0] = a0;
+      red2[wv][1] = a1;
+    }
+  }
+  if (extras) {
+    const double a2 = wave_sum(adg);
+    if (lane == 0) red2[wv][2] = a2;
+#pragma unroll
+    for (int j = 0; j < MMAX; ++j) {
+      if ((mask >> j) & 1u) {
+        const double aj = wave_sum(add[j]);
+        if (lane == 0) red2[wv][3 + j] = aj;
+      }
+    }
+  }
+  __syncthreads();
+  if (tid < nv && (tid < 3 || ((mask >> (tid - 3)) & 1u))) {
+    double sum = 0.0;
+#pragma unroll
+    for (int k = 0; k < NT / 64; ++k) sum += red2[k][tid];
+    jb.part[(PK_VO + tid) * jb.pstride + q * cpb] = sum;
+    for (int cb = 1; cb < cpb; ++cb) jb.part[(PK_VO + tid) * jb.pstride + q * cpb + cb] = 0.0;
+  }
+}
+
 // ------------------------------------------------------------------------ column inverse
-template <typename T, int N, int C, int CPB>
+// SIMK: the variant launched for simulation jobs (CM_SIM); the others skip such jobs.
+template <typename T, int N, int C, int CPB, bool SIMK>
 __global__ __launch_bounds__(NT) void k_colinv(const Job* __restrict__ jobs, const cpx<T>* __restrict__ twg) {
   const Job& jb = jobs[blockIdx.y];
   const int mode = jb.mode;
-  if (mode == CM_NONE || mode == CM_ADJ || mode == CM_ADJ_GRAD) return;
+  if (mode == CM_NONE || mode == CM_ADJ || mode == CM_ADJ_GRAD || (!SIMK && mode == CM_SIM)) return;
   constexpr int NB = CPB * C * TB;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cpx<T>* tw = reinterpret_cast<cpx<T>*>(smem_raw);
@@ -106,75 +317,30 @@ __global__ __launch_bounds__(NT) void k_colinv(const Job* __restrict__ jobs, con
   const int tid = threadIdx.x, q = blockIdx.x;
   for (int i = tid; i < N; i += NT) tw[i] = twg[i];
 
-  const cpx<T>* vin = reinterpret_cast<const cpx<T>*>(jb.vin);
-  const T* sIn = reinterpret_cast<const T*>(jb.sIn);
-  const T* sOut = reinterpret_cast<const T*>(jb.sOut);
-  const bool raw = (mode == CM_RAW_GRAD || mode == CM_RAW_HV);
-  const bool sim = (mode == CM_SIM);
-  const T* draws = reinterpret_cast<const T*>(jb.draws);
-  const T bamp = T(jb.boost_factor);
   double acc = 0.0;
   for (int ee = tid; ee < CPB * N * TB; ee += NT) {
     const int cb = ee / (N * TB), e = ee % (N * TB);
     const int qb = q * CPB + cb;                     // column block
     const int ky = e / TB, col = e % TB, kx = qb * TB + col;
-    // offset of this column block in the (chunk-interleaved) input view
-    int64_t dv[C];
+    cpx<T> a[C];
+    bool part = false;
+    int kyr = ky;
 #pragma unroll
     for (int c = 0; c < C; ++c) {
       const int64_t bs = fidx(N, c, 0, qb * TB);
-      dv[c] = jb.vcs > 0 ? vview(bs, jb.vcs, jb.vcstr) - bs : 0;
+      const int64_t dvc = jb.vcs > 0 ? vview(bs, jb.vcs, jb.vcstr) - bs : 0;
+      a[c] = colinv_in<T, N, SIMK>(jb, mode, c, ky, kx, dvc, part, kyr, acc);
     }
-    cpx<T> a[C];
+    if constexpr (C == 2) {
+      T c2, s2;
+      rot2<T>(kx, kyr < N / 2 ? kyr : kyr - N, c2, s2);
+      const cpx<T> e0 = a[0], b0 = a[1];
+      a[0] = mk(c2 * e0.x - s2 * b0.x, c2 * e0.y - s2 * b0.y);
+      a[1] = mk(s2 * e0.x + c2 * b0.x, s2 * e0.y + c2 * b0.y);
+    }
+    if (part) {
 #pragma unroll
-    for (int c = 0; c < C; ++c) a[c] = mk(T(0), T(0));
-    if (is_live(N, ky, kx)) {
-      const bool part = is_partner(N, ky, kx);
-      const int kyr = part ? N - ky : ky;   // stored (free) entry of the pair
-#pragma unroll
-      for (int c = 0; c < C; ++c) {
-        const int64_t src = fidx(N, c, kyr, kx);
-        cpx<T> v;
-        T sc = T(1);
-        if (sim) {
-          const int64_t qn = ((int64_t)c * N + kyr) * N + 2 * kx;
-          if (draws) {
-            v = mk(draws[qn], draws[qn + 1]);
-          } else {
-            double z0, z1;
-            philox_normal_pair(jb.seed, jb.sim, qn, z0, z1);
-            v = mk(T(z0), T(z1));
-          }
-          sc = sIn[src] * T(0.70710678118654752440084436210485);
-          if (jb.band && jb.boost_band >= 0 && jb.band[src] == jb.boost_band) sc *= bamp;
-        } else {
-          v = vin[src + dv[c]];
-          if (sIn) sc = sIn[src];
-          if (raw) {
-            const T sq = sOut[src];
-            if (sq == T(0)) {
-              v = mk(T(0), T(0));
-            } else if (!part && mode == CM_RAW_GRAD) {
-              acc += ((double)v.x * v.x + (double)v.y * v.y) / ((double)sq * sq);
-            }
-          } else if (mode == CM_GRAD && !part) {
-            const double wa = jb.aTab ? (double)reinterpret_cast<const T*>(jb.aTab)[src] : 1.0;
-            acc += wa * ((double)v.x * v.x + (double)v.y * v.y);
-          }
-        }
-        a[c] = scale(v, sc);
-      }
-      if constexpr (C == 2) {
-        T c2, s2;
-        rot2<T>(kx, kyr < N / 2 ? kyr : kyr - N, c2, s2);
-        const cpx<T> e0 = a[0], b0 = a[1];
-        a[0] = mk(c2 * e0.x - s2 * b0.x, c2 * e0.y - s2 * b0.y);
-        a[1] = mk(s2 * e0.x + c2 * b0.x, s2 * e0.y + c2 * b0.y);
-      }
-      if (part) {
-#pragma unroll
-        for (int c = 0; c < C; ++c) a[c] = conj(a[c]);
-      }
+      for (int c = 0; c < C; ++c) a[c] = conj(a[c]);
     }
 #pragma unroll
     for (int c = 0; c < C; ++c) buf[ky * NB + (cb * C + c) * TB + col] = a[c];
@@ -196,11 +362,11 @@ __global__ __launch_bounds__(NT) void k_colinv(const Job* __restrict__ jobs, con
 }
 
 // ------------------------------------------------------------------------ row pass
-template <typename T, int N, int C, int RBV>
+template <typename T, int N, int C, int RBV, bool SIMK>
 __global__ __launch_bounds__(NT) void k_row(const Job* __restrict__ jobs, const cpx<T>* __restrict__ twg) {
   const Job& jb = jobs[blockIdx.y];
   const int mode = jb.mode;
-  if (mode == CM_NONE) return;
+  if (mode == CM_NONE || (!SIMK && mode == CM_SIM)) return;
   constexpr int RB = RBV;
   constexpr int H = N / 2, NBR = C * RB, SBR = H;
   constexpr int NE = NBR * H;
@@ -253,71 +419,12 @@ __global__ __launch_bounds__(NT) void k_row(const Job* __restrict__ jobs, const 
   }
 
   // pixel operation: element j of row b holds pixels (2j, 2j+1)
-  const T invn = T(1) / T(N);
-  const T* W = reinterpret_cast<const T*>(jb.W);
-  const T* dd = reinterpret_cast<const T*>(jb.d);
-  T* xout = reinterpret_cast<T*>(jb.xout);
-  const T* draws = reinterpret_cast<const T*>(jb.draws);
   double acc = 0.0;
   for (int e = tid; e < NE; e += NT) {
     const int b = e / H, j = e % H;
-    const int c = b / RB, yl = b % RB;
-    const int64_t pix = (int64_t)(y0 + yl) * N + 2 * j;
-    const int64_t cp = (int64_t)c * N * N + pix;
-    cpx<T> zf;
-    if (adjIn) {
-      T x0 = dd[cp], x1 = dd[cp + 1];
-      if (W) {   // masked adjoint: R^T M x
-        if (!(W[pix] > T(0))) x0 = T(0);
-        if (!(W[pix + 1] > T(0))) x1 = T(0);
-      }
-      zf = mk(x0 * invn, x1 * invn);
-    } else {
-      const cpx<T> zz = buf[b * SBR + j];
-      const T x0 = zz.x * invn, x1 = zz.y * invn;
-      if (mode == CM_FWD) {   // masked forward M R s when W is given
-        xout[cp] = (W && !(W[pix] > T(0))) ? T(0) : x0;
-        xout[cp + 1] = (W && !(W[pix + 1] > T(0))) ? T(0) : x1;
-        continue;
-      }
-      const T W0 = W[pix], W1 = W[pix + 1];
-      if (mode == CM_SIM) {
-        T n0, n1;
-        const int64_t qn = (int64_t)C * N * N + cp;
-        if (draws) {
-          n0 = draws[qn];
-          n1 = draws[qn + 1];
-        } else {
-          double z0, z1;
-          philox_normal_pair(jb.seed, jb.sim, qn, z0, z1);
-          n0 = T(z0);
-          n1 = T(z1);
-        }
-        xout[cp] = W0 > T(0) ? x0 + n0 / sqrt(W0) : T(0);
-        xout[cp + 1] = W1 > T(0) ? x1 + n1 / sqrt(W1) : T(0);
-        continue;
-      }
-      T r0, r1;
-      if (mode == CM_HV || mode == CM_RAW_HV) {
-        r0 = W0 * x0;
-        r1 = W1 * x1;
-      } else {  // CM_GRAD, CM_RAW_GRAD: r = W (x - d); masked pixels contribute nothing
-        r0 = T(0);
-        r1 = T(0);
-        if (W0 > T(0)) {
-          const T e0 = x0 - dd[cp];
-          r0 = W0 * e0;
-          acc += (double)r0 * e0;
-        }
-        if (W1 > T(0)) {
-          const T e1 = x1 - dd[cp + 1];
-          r1 = W1 * e1;
-          acc += (double)r1 * e1;
-        }
-      }
-      zf = mk(r0 * invn, r1 * invn);
-    }
-    buf[b * SBR + j] = zf;
+    cpx<T> zf = buf[b * SBR + j];
+    row_pixel<T, N, C, SIMK>(jb, mode, adjIn, b / RB, y0 + b % RB, j, zf, acc);
+    if (mode != CM_FWD && mode != CM_SIM) buf[b * SBR + j] = zf;
   }
   if (mode == CM_FWD || mode == CM_SIM) return;
   __syncthreads();
@@ -351,9 +458,12 @@ __global__ __launch_bounds__(NT) void k_row(const Job* __restrict__ jobs, const 
     Y[fidx(N, c, y0, qq * TB) + w2] = buf[(c * RB + yl) * SBR + qq * TB + col];
   }
   if (mode == CM_GRAD || mode == CM_RAW_GRAD) {
-    // partials are kept per RB_MIN rows so the reduction does not depend on RBV
+    // partials are kept per component and RB_MIN rows (slot c * N / RB_MIN + row / RB_MIN), so
+    // the reduction does not depend on the row tile; this tile's sum goes to its first slot
     const double t = block_sum(acc, red);
-    if (tid < RB / RB_MIN) jb.part[PK_RES * jb.pstride + blockIdx.x * (RB / RB_MIN) + tid] = tid == 0 ? t : 0.0;
+    constexpr int PR = RB / RB_MIN;
+    if (tid < C * PR)
+      jb.part[PK_RES * jb.pstride + (tid / PR) * (N / RB_MIN) + blockIdx.x * PR + tid % PR] = tid == 0 ? t : 0.0;
   }
 }
 
@@ -367,7 +477,6 @@ __global__ __launch_bounds__(NT) void k_colfwd(const Job* __restrict__ jobs, con
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cpx<T>* tw = reinterpret_cast<cpx<T>*>(smem_raw);
   cpx<T>* buf = tw + N;
-  __shared__ double red[NT / 64];
   const int tid = threadIdx.x, q = blockIdx.x;
   for (int i = tid; i < N; i += NT) tw[i] = twg[i];
   const cpx<T>* Y = reinterpret_cast<const cpx<T>*>(jb.y);
@@ -380,27 +489,16 @@ __global__ __launch_bounds__(NT) void k_colfwd(const Job* __restrict__ jobs, con
   __syncthreads();
   lds_fft<T, N, NB, 1, NB, 1, false, false>(buf, tw);
 
-  const cpx<T>* vadd = reinterpret_cast<const cpx<T>*>(jb.vadd);
-  const T* sOut = reinterpret_cast<const T*>(jb.sOut);
-  cpx<T>* vout = reinterpret_cast<cpx<T>*>(jb.vout);
   double avo = 0.0, aoo = 0.0, adg = 0.0;
   double add[MMAX];
 #pragma unroll
   for (int j = 0; j < MMAX; ++j) add[j] = 0.0;
   // curvature products inside the solver also dot the new Dp with g and the kept Dp_j
   const bool extras = (mode == CM_HV) && jb.dpBase != nullptr;
-  const cpx<T>* gvec = reinterpret_cast<const cpx<T>*>(jb.gvec);
-  const cpx<T>* dpb = reinterpret_cast<const cpx<T>*>(jb.dpBase);
   for (int ee = tid; ee < CPB * N * TB; ee += NT) {
     const int cb = ee / (N * TB), e = ee % (N * TB);
     const int qb = q * CPB + cb;
     const int ky = e / TB, col = e % TB, kx = qb * TB + col;
-    int64_t dv[C];
-#pragma unroll
-    for (int c = 0; c < C; ++c) {
-      const int64_t bs = fidx(N, c, 0, qb * TB);
-      dv[c] = jb.vcs > 0 ? vview(bs, jb.vcs, jb.vcstr) - bs : 0;
-    }
     cpx<T> t[C];
 #pragma unroll
     for (int c = 0; c < C; ++c) t[c] = buf[ky * NB + (cb * C + c) * TB + col];
@@ -411,79 +509,318 @@ __global__ __launch_bounds__(NT) void k_colfwd(const Job* __restrict__ jobs, con
       t[0] = mk(c2 * g1.x + s2 * g2.x, c2 * g1.y + s2 * g2.y);
       t[1] = mk(-s2 * g1.x + c2 * g2.x, -s2 * g1.y + c2 * g2.y);
     }
-    const bool fr = is_free(N, ky, kx);
 #pragma unroll
     for (int c = 0; c < C; ++c) {
-      const int64_t o = fidx(N, c, ky, kx);
-      cpx<T> out = mk(T(0), T(0));
-      if (mode == CM_HV || mode == CM_GRAD) {
-        const T sq = sOut[o];
-        if (fr && sq != T(0)) {
-          const cpx<T> v = vadd[o + dv[c]];
-          const T wa = jb.aTab ? reinterpret_cast<const T*>(jb.aTab)[o] : T(1);
-          out = mk(wa * v.x + sq * t[c].x, wa * v.y + sq * t[c].y);
-          avo += (double)v.x * out.x + (double)v.y * out.y;
-        }
-        aoo += (double)out.x * out.x + (double)out.y * out.y;
-        if (extras) {
-          const cpx<T> gv = gvec[o + dv[c]];
-          adg += (double)gv.x * out.x + (double)gv.y * out.y;
-#pragma unroll
-          for (int j = 0; j < MMAX; ++j) {
-            if ((jb.dpMask >> j) & 1u) {
-              const cpx<T> dj = dpb[(int64_t)j * jb.dpStride + o + dv[c]];
-              add[j] += (double)dj.x * out.x + (double)dj.y * out.y;
-            }
-          }
-        }
-      } else if (mode == CM_RAW_GRAD || mode == CM_RAW_HV) {
-        const T sq = sOut[o];
-        if (fr && sq != T(0)) {
-          const cpx<T> v = vadd[o + dv[c]];
-          const T is = T(1) / (sq * sq);
-          out = mk(T(4) * (v.x * is + t[c].x), T(4) * (v.y * is + t[c].y));
-        }
-      } else if (mode == CM_ADJ) {
-        if (is_live(N, ky, kx)) out = t[c];
-      } else {  // CM_ADJ_GRAD
-        if (fr) out = scale(t[c], T(2));
-      }
-      vout[o + dv[c]] = out;
+      const int64_t bs = fidx(N, c, 0, qb * TB);
+      const int64_t dvc = jb.vcs > 0 ? vview(bs, jb.vcs, jb.vcstr) - bs : 0;
+      colfwd_out<T, N>(jb, mode, extras, ky, kx, bs + e, dvc, t[c], avo, aoo, adg, add);
     }
   }
-  if (mode == CM_HV || mode == CM_GRAD) {
-    // one combined reduction: [VO, OO, DG, DD_0 .. DD_{MMAX-1}] -> kinds PK_VO + idx
-    __shared__ double red2[NT / 64][3 + MMAX];
-    const int lane = tid & 63, wv = tid >> 6;
-    const int nv = extras ? 3 + MMAX : 2;
-    const uint32_t mask = jb.dpMask;
-    {
-      const double a0 = wave_sum(avo), a1 = wave_sum(aoo);
-      if (lane == 0) {
-        red2[wv][0] = a0;
-        red2[wv][1] = a1;
-      }
-    }
-    if (extras) {
-      const double a2 = wave_sum(adg);
-      if (lane == 0) red2[wv][2] = a2;
-#pragma unroll
-      for (int j = 0; j < MMAX; ++j) {
-        if ((mask >> j) & 1u) {
-          const double aj = wave_sum(add[j]);
-          if (lane == 0) red2[wv][3 + j] = aj;
+  colfwd_reduce(jb, mode, extras, avo, aoo, adg, add, q, CPB);
+}
+
+// ======================================================================== register-staged
+// Power-of-two n >= 128, float32: the same passes with the register-staged FFT of
+// wf_rfft.hpp (simulation jobs run on the LDS-staged variants).  First-stage inputs are read from global memory (column passes) or from the
+// LDS staging tile (row pass) straight into registers; last-stage outputs go from registers
+// to global memory; the row pass chains its inverse and forward transforms in registers
+// around the pixel step.  The spin-2 rotation exchanges the partner component between lanes.
+
+// Register-staged row pass: a work-group owns RB rows of one component, E elements per
+// thread.  LDS row strides of the staging tile and of the exchange layouts (index
+// i + i / R_0 in a row) were chosen for at most 2-way bank conflicts of every access pattern.
+__host__ __device__ constexpr int rowr_e(int n) { return n <= 512 ? 8 : 16; }
+__host__ __device__ constexpr int rowr_rb(int n) { return rowr_e(n) * NT / (n / 2); }
+__host__ __device__ constexpr int rowr_io_stride(int H) { return H + (H == 64 ? 6 : (H == 512 ? 4 : 2)); }
+__host__ __device__ constexpr int rowr_x_stride(int H, int E, bool rev) { return H + H / rs_radix(H, E, rev, 0); }
+__host__ __device__ constexpr int rowr_data_stride(int H, int E) {
+  const int a = rowr_io_stride(H), b = rowr_x_stride(H, E, false), c = rowr_x_stride(H, E, true);
+  return a > b ? (a > c ? a : c) : (b > c ? b : c);
+}
+template <int N>
+constexpr size_t lds_rowr() {
+  return ((size_t)rowr_rb(N) * rowr_data_stride(N / 2, rowr_e(N)) + (size_t)N) * sizeof(cpx<float>);
+}
+template <int N, int C, int CPB>
+constexpr size_t lds_colr() {
+  constexpr int NB = CPB * C * TB, E = NB * N / NT;
+  return ((size_t)(N + N / rs_radix(N, E, false, 0)) * NB + (size_t)N) * sizeof(cpx<float>);
+}
+
+template <int N, int C, int CPB>
+__global__ __launch_bounds__(NT) void k_colinvr(const Job* __restrict__ jobs, const cpx<float>* __restrict__ twg) {
+  using T = float;
+  const Job& jb = jobs[blockIdx.y];
+  const int mode = jb.mode;
+  if (mode == CM_NONE || mode == CM_ADJ || mode == CM_ADJ_GRAD || mode == CM_SIM) return;
+  constexpr int NB = CPB * C * TB, E = NB * N / NT;
+  constexpr int PQ = rs_radix(N, E, false, 0), NST = rs_nst(N, E);
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cpx<T>* data = reinterpret_cast<cpx<T>*>(smem_raw);
+  cpx<T>* st = data + (N + N / PQ) * NB;
+  __shared__ double red[NT / 64];
+  const int tid = threadIdx.x, q = blockIdx.x;
+  {
+    const cpx<T>* g = twg + tw_col_off(N, E);
+    for (int i = tid; i < N; i += NT) st[i] = g[i];
+  }
+  auto lx = [](int b, int i) { return (i + i / PQ) * NB + b; };
+  // this thread's transform (the same in every stage: NT is a multiple of NB)
+  const int b = tid % NB;
+  const int col = b % TB, c = (b / TB) % C, cb = b / (TB * C);
+  const int qb = q * CPB + cb, kx = qb * TB + col;
+  const int64_t bs = fidx(N, c, 0, qb * TB);
+  const int64_t dvc = jb.vcs > 0 ? vview(bs, jb.vcs, jb.vcstr) - bs : 0;
+  double acc = 0.0;
+  cpx<T> v[E];
+  {
+    constexpr int R0 = PQ, NQ0 = N / R0, K0 = E / R0;
+    sfor<0, K0>([&](auto KK) {
+      constexpr int kk = decltype(KK)::value;
+      const int j = (tid + kk * NT) / NB;
+      sfor<0, R0>([&](auto RR) {
+        constexpr int r = decltype(RR)::value;
+        const int ky = j + r * NQ0;
+        bool part;
+        int kyr;
+        cpx<T> a = colinv_in<T, N, false>(jb, mode, c, ky, kx, dvc, part, kyr, acc);
+        if constexpr (C == 2) {
+          const T ox = lane_xor2(a.x), oy = lane_xor2(a.y);   // the other component
+          T c2, s2;
+          rot2<T>(kx, kyr < N / 2 ? kyr : kyr - N, c2, s2);
+          a = (c == 0) ? mk(c2 * a.x - s2 * ox, c2 * a.y - s2 * oy) : mk(s2 * ox + c2 * a.x, s2 * oy + c2 * a.y);
         }
-      }
+        v[kk * R0 + r] = part ? conj(a) : a;
+      });
+    });
+  }
+  rs_fft<T, N, NB, E, false, true, false>(v, data, st, lx);
+  {
+    constexpr int RL = rs_radix(N, E, false, NST - 1), NQL = N / RL, KL = E / RL;
+    cpx<T>* y = reinterpret_cast<cpx<T>*>(jb.y);
+    sfor<0, KL>([&](auto KK) {
+      constexpr int kk = decltype(KK)::value;
+      const int j = (tid + kk * NT) / NB;
+      sfor<0, RL>([&](auto RR) {
+        constexpr int r = decltype(RR)::value;
+        y[bs + (j + r * NQL) * TB + col] = v[kk * RL + r];
+      });
+    });
+  }
+  if (mode == CM_GRAD || mode == CM_RAW_GRAD) {
+    const double t = block_sum(acc, red);
+    if (tid < CPB) jb.part[PK_PRIOR * jb.pstride + q * CPB + tid] = tid == 0 ? t : 0.0;
+  }
+}
+
+template <int N, int C>
+__global__ __launch_bounds__(NT) void k_rowr(const Job* __restrict__ jobs, const cpx<float>* __restrict__ twg) {
+  using T = float;
+  const Job& jb = jobs[blockIdx.y];
+  const int mode = jb.mode;
+  if (mode == CM_NONE || mode == CM_SIM) return;
+  constexpr int H = N / 2, E = rowr_e(N), RB = rowr_rb(N), NE = RB * H;
+  static_assert(RB % RB_MIN == 0 && N % RB == 0, "row tile");
+  constexpr int NST = rs_nst(H, E);
+  constexpr int PQI = rs_radix(H, E, false, 0), PQF = rs_radix(H, E, true, 0);
+  constexpr int SBIO = rowr_io_stride(H), SBXI = rowr_x_stride(H, E, false), SBXF = rowr_x_stride(H, E, true);
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cpx<T>* data = reinterpret_cast<cpx<T>*>(smem_raw);
+  cpx<T>* stI = data + RB * rowr_data_stride(H, E);
+  cpx<T>* stF = stI + H;
+  __shared__ double red[NT / 64];
+  const int tid = threadIdx.x;
+  const int c = blockIdx.x / (N / RB), tile = blockIdx.x % (N / RB), y0 = tile * RB;
+  {
+    const cpx<T>* gI = twg + tw_row_off(N, E, false);
+    const cpx<T>* gF = twg + tw_row_off(N, E, true);
+    for (int i = tid; i < H; i += NT) {
+      stI[i] = gI[i];
+      stF[i] = gF[i];
+    }
+  }
+  auto lio = [](int b, int i) { return b * SBIO + i; };
+  auto lxi = [](int b, int i) { return b * SBXI + i + i / PQI; };
+  auto lxf = [](int b, int i) { return b * SBXF + i + i / PQF; };
+  const bool adjIn = (mode == CM_ADJ || mode == CM_ADJ_GRAD);
+  cpx<T>* Y = reinterpret_cast<cpx<T>*>(jb.y) + fidx(N, c, y0, 0);   // column block 0 of this tile
+  cpx<T> v[E];
+  double acc = 0.0;
+  if (!adjIn) {
+    for (int e = tid; e < NE; e += NT) {
+      const int qq = e / (RB * TB), w2 = e % (RB * TB);
+      data[lio(w2 / TB, qq * TB + w2 % TB)] = Y[(int64_t)qq * N * TB + w2];
     }
     __syncthreads();
-    if (tid < nv && (tid < 3 || ((mask >> (tid - 3)) & 1u))) {
-      double sum = 0.0;
-#pragma unroll
-      for (int k = 0; k < NT / 64; ++k) sum += red2[k][tid];
-      jb.part[(PK_VO + tid) * jb.pstride + q * CPB] = sum;
-#pragma unroll
-      for (int cb = 1; cb < CPB; ++cb) jb.part[(PK_VO + tid) * jb.pstride + q * CPB + cb] = 0.0;
+    // complex-to-real pre-processing into the first stage's registers (see k_row)
+    constexpr int R0 = PQI, NQ0 = H / R0, K0 = E / R0;
+    sfor<0, K0>([&](auto KK) {
+      constexpr int kk = decltype(KK)::value;
+      const int u = tid + kk * NT, b = u / NQ0, j = u % NQ0;
+      sfor<0, R0>([&](auto RR) {
+        constexpr int r = decltype(RR)::value;
+        const int k = j + r * NQ0;
+        const cpx<T> X = data[lio(b, k)];
+        cpx<T> z;
+        if (k == 0) {
+          z = mk(X.x, X.x);
+        } else {
+          const cpx<T> Xm = conj(data[lio(b, H - k)]);
+          const cpx<T> t = mulc(sub(X, Xm), twg[k]);
+          const cpx<T> s = add(X, Xm);
+          z = mk(s.x - t.y, s.y + t.x);
+        }
+        v[kk * R0 + r] = z;
+      });
+    });
+    rs_fft<T, H, RB, E, true, true, false>(v, data, stI, lxi);
+  }
+  {
+    // pixel step in the inverse's last-stage layout, which is the forward's first-stage one
+    constexpr int RL = rs_radix(H, E, false, NST - 1), NQL = H / RL, KL = E / RL;
+    sfor<0, KL>([&](auto KK) {
+      constexpr int kk = decltype(KK)::value;
+      const int u = tid + kk * NT, b = u / NQL, j = u % NQL;
+      sfor<0, RL>([&](auto RR) {
+        constexpr int r = decltype(RR)::value;
+        row_pixel<T, N, C, false>(jb, mode, adjIn, c, y0 + b, j + r * NQL, v[kk * RL + r], acc);
+      });
+    });
+  }
+  if (mode == CM_FWD) return;
+  rs_fft<T, H, RB, E, true, false, true>(v, data, stF, lxf);
+  {
+    // outputs are in the inverse's first-stage layout: to LDS in natural order for the
+    // real-to-complex untangle, which pairs k with H - k
+    constexpr int R0 = PQI, NQ0 = H / R0, K0 = E / R0;
+    __syncthreads();
+    sfor<0, K0>([&](auto KK) {
+      constexpr int kk = decltype(KK)::value;
+      const int u = tid + kk * NT, b = u / NQ0, j = u % NQ0;
+      sfor<0, R0>([&](auto RR) {
+        constexpr int r = decltype(RR)::value;
+        data[lio(b, j + r * NQ0)] = v[kk * R0 + r];
+      });
+    });
+    __syncthreads();
+  }
+  for (int e = tid; e < NE; e += NT) {
+    const int qq = e / (RB * TB), w2 = e % (RB * TB);
+    const int b = w2 / TB, k = qq * TB + w2 % TB;
+    const cpx<T> Zk = data[lio(b, k)];
+    const cpx<T> Zm = conj(data[lio(b, k == 0 ? 0 : H - k)]);
+    const cpx<T> A = add(Zk, Zm);
+    const cpx<T> t = mul(twg[k], sub(Zk, Zm));
+    Y[(int64_t)qq * N * TB + w2] = mk(T(0.5) * (A.x + t.y), T(0.5) * (A.y - t.x));
+  }
+  if (mode == CM_GRAD || mode == CM_RAW_GRAD) {
+    const double t = block_sum(acc, red);
+    constexpr int PR = RB / RB_MIN;
+    if (tid < PR) jb.part[PK_RES * jb.pstride + c * (N / RB_MIN) + tile * PR + tid] = tid == 0 ? t : 0.0;
+  }
+}
+
+template <int N, int C, int CPB>
+__global__ __launch_bounds__(NT) void k_colfwdr(const Job* __restrict__ jobs, const cpx<float>* __restrict__ twg) {
+  using T = float;
+  const Job& jb = jobs[blockIdx.y];
+  const int mode = jb.mode;
+  if (mode == CM_NONE || mode == CM_FWD || mode == CM_SIM) return;
+  constexpr int NB = CPB * C * TB, E = NB * N / NT;
+  constexpr int PQ = rs_radix(N, E, false, 0), NST = rs_nst(N, E);
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cpx<T>* data = reinterpret_cast<cpx<T>*>(smem_raw);
+  cpx<T>* st = data + (N + N / PQ) * NB;
+  const int tid = threadIdx.x, q = blockIdx.x;
+  {
+    const cpx<T>* g = twg + tw_col_off(N, E);
+    for (int i = tid; i < N; i += NT) st[i] = g[i];
+  }
+  auto lx = [](int b, int i) { return (i + i / PQ) * NB + b; };
+  const int b = tid % NB;
+  const int col = b % TB, c = (b / TB) % C, cb = b / (TB * C);
+  const int qb = q * CPB + cb, kx = qb * TB + col;
+  const int64_t bs = fidx(N, c, 0, qb * TB);
+  const int64_t dvc = jb.vcs > 0 ? vview(bs, jb.vcs, jb.vcstr) - bs : 0;
+  const cpx<T>* Y = reinterpret_cast<const cpx<T>*>(jb.y);
+  cpx<T> v[E];
+  {
+    constexpr int R0 = PQ, NQ0 = N / R0, K0 = E / R0;
+    sfor<0, K0>([&](auto KK) {
+      constexpr int kk = decltype(KK)::value;
+      const int j = (tid + kk * NT) / NB;
+      sfor<0, R0>([&](auto RR) {
+        constexpr int r = decltype(RR)::value;
+        v[kk * R0 + r] = Y[bs + (j + r * NQ0) * TB + col];
+      });
+    });
+  }
+  rs_fft<T, N, NB, E, false, false, false>(v, data, st, lx);
+  constexpr int RL = rs_radix(N, E, false, NST - 1), NQL = N / RL, KL = E / RL;
+  double avo = 0.0, aoo = 0.0;
+  sfor<0, KL>([&](auto KK) {
+    constexpr int kk = decltype(KK)::value;
+    const int j = (tid + kk * NT) / NB;
+    sfor<0, RL>([&](auto RR) {
+      constexpr int r = decltype(RR)::value;
+      const int ky = j + r * NQL;
+      cpx<T> t = v[kk * RL + r];
+      if constexpr (C == 2) {
+        const T ox = lane_xor2(t.x), oy = lane_xor2(t.y);   // the other component
+        T c2, s2;
+        rot2<T>(kx, ky < N / 2 ? ky : ky - N, c2, s2);
+        t = (c == 0) ? mk(c2 * t.x + s2 * ox, c2 * t.y + s2 * oy) : mk(-s2 * ox + c2 * t.x, -s2 * oy + c2 * t.y);
+      }
+      v[kk * RL + r] = colfwd_val<T, N>(jb, mode, ky, kx, bs + ky * TB + col, dvc, t, avo, aoo);
+    });
+  });
+  if (!(mode == CM_HV || mode == CM_GRAD)) return;
+  // partials [VO, OO, DG, DD_0 .. DD_{MMAX-1}] -> kinds PK_VO + idx.  The dots with g and the
+  // kept Dp_j (curvature products inside the solver) run one vector at a time, so only one
+  // FP64 accumulator is live.
+  __shared__ double red2[NT / 64][3 + MMAX];
+  const int lane = tid & 63, wv = tid >> 6;
+  const bool extras = (mode == CM_HV) && jb.dpBase != nullptr;
+  const uint32_t mask = extras ? jb.dpMask : 0u;
+  {
+    const double a0 = wave_sum(avo), a1 = wave_sum(aoo);
+    if (lane == 0) {
+      red2[wv][0] = a0;
+      red2[wv][1] = a1;
     }
+  }
+  auto dot_with = [&](const cpx<T>* u) {
+    double a = 0.0;
+    sfor<0, KL>([&](auto KK) {
+      constexpr int kk = decltype(KK)::value;
+      const int j = (tid + kk * NT) / NB;
+      sfor<0, RL>([&](auto RR) {
+        constexpr int r = decltype(RR)::value;
+        const cpx<T> w = u[bs + (j + r * NQL) * TB + col + dvc];
+        a += (double)w.x * v[kk * RL + r].x + (double)w.y * v[kk * RL + r].y;
+      });
+    });
+    return wave_sum(a);
+  };
+  if (extras) {
+    const double ag = dot_with(reinterpret_cast<const cpx<T>*>(jb.gvec));
+    if (lane == 0) red2[wv][2] = ag;
+    const cpx<T>* dpb = reinterpret_cast<const cpx<T>*>(jb.dpBase);
+    for (int jj = 0; jj < MMAX; ++jj) {
+      if ((mask >> jj) & 1u) {
+        const double aj = dot_with(dpb + (int64_t)jj * jb.dpStride);
+        if (lane == 0) red2[wv][3 + jj] = aj;
+      }
+    }
+  }
+  __syncthreads();
+  const int nv = extras ? 3 + MMAX : 2;
+  if (tid < nv && (tid < 3 || ((mask >> (tid - 3)) & 1u))) {
+    double sum = 0.0;
+#pragma unroll
+    for (int k = 0; k < NT / 64; ++k) sum += red2[k][tid];
+    jb.part[(PK_VO + tid) * jb.pstride + q * CPB] = sum;
+    for (int cb = 1; cb < CPB; ++cb) jb.part[(PK_VO + tid) * jb.pstride + q * CPB + cb] = 0.0;
   }
 }
 

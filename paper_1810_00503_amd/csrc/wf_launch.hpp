@@ -10,12 +10,17 @@ enum { CH_COLINV = 0, CH_ROW = 1, CH_COLFWD = 2 };
 bool chain_supported(int n);
 
 // Tile choice of the transform chain: rows per work-group of the row pass (2, 4, 8),
-// column blocks per work-group of the column passes (1, 2, 4) and instances per launch
-// (0 = all).  float32 supports every choice, float64 the defaults (4, 1).
+// column blocks per work-group of the column passes (1, 2, 4), instances per launch
+// (0 = all) and which passes use the register-staged FFT (bit 0: row pass, whose tile is
+// then fixed by n; bit 1: column inverse; bit 2: column forward).  float32 supports every
+// choice (register-staged passes for power-of-two n >= 128), float64 the defaults (4, 1,
+// LDS-staged).
 struct ChainCfg {
   int rbv = 4;
   int cpb = 1;
   int group = 0;
+  int reg = 0;
+  int sim = 0;   // simulation passes (CM_SIM jobs): fixed LDS-staged variants, the other fields ignored
 };
 
 // Launch one pass of the transform chain for `batch` jobs.  Returns hipSuccess or the
@@ -41,9 +46,18 @@ inline hipError_t chain_prepare(int dtype, int n, int c) {
   if (dtype != 0) return chain_prepare_f64(n, c);
   return n <= 96 ? chain_prepare_f32_s(n, c) : chain_prepare_f32_l(n, c);
 }
-inline bool chain_cfg_supported(int dtype, int n, const ChainCfg& cfg) {
-  if (dtype != 0) return cfg.rbv == 4 && cfg.cpb == 1;
+inline bool chain_reg_supported(int dtype, int n) { return dtype == 0 && n >= 128 && (n & (n - 1)) == 0; }
+// register-staged column passes: elements per thread cpb * c * TB * n / NT in [4, 32]
+inline bool chain_regcol_supported(int n, int c, int cpb) {
+  const int e = cpb * c * TB * n / NT;
+  return e >= 4 && e <= 32;
+}
+inline bool chain_cfg_supported(int dtype, int n, int c, const ChainCfg& cfg) {
+  if (dtype != 0) return cfg.rbv == 4 && cfg.cpb == 1 && cfg.reg == 0;
   const int ncb = n / 2 / TB;   // column blocks
+  if (cfg.reg < 0 || cfg.reg > 7) return false;
+  if (cfg.reg != 0 && !chain_reg_supported(dtype, n)) return false;
+  if ((cfg.reg & 6) && !chain_regcol_supported(n, c, cfg.cpb)) return false;
   return (cfg.rbv == 2 || cfg.rbv == 4 || cfg.rbv == 8) && (cfg.cpb == 1 || cfg.cpb == 2 || cfg.cpb == 4) &&
          ncb % cfg.cpb == 0;
 }

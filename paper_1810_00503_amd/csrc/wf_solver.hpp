@@ -269,7 +269,7 @@ __global__ __launch_bounds__(256) void k_coef(const InstDesc* __restrict__ desc,
   __shared__ double part4[4][NDOT];
   __shared__ double chs[3 + MMAX + 2];
   __shared__ double sPD[M][M], sDD[M][M], sal[M], sgP[M], sgD[M];
-  const int ncol = (D.n / 2) / TB, nrow = D.n / RB_MIN;
+  const int ncol = (D.n / 2) / TB, nrow = D.c * D.n / RB_MIN;
   if (mode == CM_GRAD) reduce_columns(D.partA, D.nchunk, NDOT, 2 * M + 1, sums, part4);
   // chain partial sums (fixed order, one thread per kind)
   if (threadIdx.x < 3 + M + 2) {

@@ -10,7 +10,7 @@ import pytest
 
 import oracle as O
 from paper_1810_00503_amd import workloads as WL
-from tests.gpu_util import make_problem, oracle_data, rel_l2
+from tests.gpu_util import fill_partners, make_problem, oracle_data, rel_l2
 
 pytestmark = pytest.mark.gpu
 
@@ -200,10 +200,53 @@ def test_tile_variants_agree_and_autotune(lib):
     finally:
         lib.set_chain_tiles(0)
     got, _, st, _ = _solve(lib, probs, rel_grad_tol=1e-7)
-    rbv, cpb, grp, tuned = lib.get_chain_tiles(64, 2, lib.WF_F32, len(probs))
-    assert tuned and rbv in (2, 4, 8) and cpb in (1, 2, 4)
+    rbv, cpb, grp, reg, tuned = lib.get_chain_tiles(64, 2, lib.WF_F32, len(probs))
+    assert tuned and rbv in (2, 4, 8) and cpb in (1, 2, 4) and reg == 0
     for i in range(len(probs)):
         assert rel_l2(got[i], ref[i]) < 2e-6
+
+
+@pytest.mark.parametrize("n,ncomp", [(128, 2), (256, 1), (512, 2), (1024, 1)])
+def test_register_staged_passes_match_oracle(lib, n, ncomp):
+    """The register-staged row and column passes (power-of-two n >= 128, float32) give the
+    oracle's operators and the same MAP as the LDS-staged passes, for every supported
+    column tile."""
+    import torch
+    print(f"[register-staged n={n} c={ncomp}]", flush=True)
+    if ncomp == 2:
+        wl = WL.shear_workload(n, 40 + n, nbands_e=3, nbands_b=3)
+    else:
+        wl = WL.density_workload(n, 40 + n, nbands=4, holes=6, target_mask=0.2)
+        wl.pshape = WL.density_pshape(n, kd=n / 4.0)   # keep S^-1 finite in float32
+    data = [oracle_data(wl, 500 + i) for i in range(4)]
+    probs = [make_problem(lib, torch, wl, "f32", d=dd) for dd in data]
+    rng = np.random.default_rng(n)
+    S = O.prior_S(wl.pshape, wl.band, wl.theta_fid)
+    fr = O.free_mask(n)[None] & (S > 0)
+    s0 = np.where(fr, np.sqrt(S) * (rng.standard_normal(S.shape) + 1j * rng.standard_normal(S.shape)), 0)
+    st = torch.tensor(fill_partners(s0), dtype=probs[0].cdtype, device="cuda:0")
+    ref_x = O.forward(s0)
+    ref_chi = O.chi2(s0, data[0], wl.W, S)
+    ref_g = O.grad_chi2(s0, data[0], wl.W, S)
+    cpbs = [cpb for cpb in (1, 2, 4) if 4 <= cpb * ncomp * 2 * n // 256 <= 32]
+    try:
+        lib.set_chain_tiles(4, 1, 0, 0)
+        ref, _, _, _ = _solve(lib, probs, rel_grad_tol=1e-6)
+        for reg in (1, 2, 4, 7):
+            for cpb in (cpbs if reg & 6 else [1]):
+                lib.set_chain_tiles(4, cpb, 0, reg)
+                x = lib.wf_forward(probs[0], st).cpu().numpy()
+                assert np.linalg.norm(x - ref_x) <= 3e-6 * np.linalg.norm(ref_x), (reg, cpb)
+                chi, g = lib.wf_chi2_grad(probs[0], st)
+                assert abs(chi - ref_chi) <= 1e-5 * abs(ref_chi), (reg, cpb)
+                g = g.cpu().numpy()
+                assert np.linalg.norm(g - ref_g) <= 3e-5 * np.linalg.norm(ref_g), (reg, cpb)
+                got, _, stt, _ = _solve(lib, probs, rel_grad_tol=1e-6)
+                for i in range(len(probs)):
+                    assert stt[i].status == lib.WF_SOLVE_CONVERGED
+                    assert rel_l2(got[i], ref[i]) < 3e-6, (reg, cpb, rel_l2(got[i], ref[i]))
+    finally:
+        lib.set_chain_tiles(0)
 
 
 @pytest.mark.parametrize("kind,n", [("cmb", 64), ("shear", 64), ("density", 128)])
