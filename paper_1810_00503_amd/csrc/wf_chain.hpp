@@ -109,7 +109,7 @@ __device__ __forceinline__ cpx<T> colinv_in(const Job& jb, int mode, int c, int 
   if (!is_live(N, ky, kx)) return a;
   part = is_partner(N, ky, kx);
   kyr = part ? N - ky : ky;
-  const int64_t src = fidx(N, c, kyr, kx);
+  const uint32_t src = (uint32_t)fidx(N, c, kyr, kx);
   const T* sIn = reinterpret_cast<const T*>(jb.sIn);
   cpx<T> v;
   T sc = T(1);
@@ -123,20 +123,20 @@ __device__ __forceinline__ cpx<T> colinv_in(const Job& jb, int mode, int c, int 
       philox_normal_pair(jb.seed, jb.sim, qn, z0, z1);
       v = mk(T(z0), T(z1));
     }
-    sc = sIn[src] * T(0.70710678118654752440084436210485);
-    if (jb.band && jb.boost_band >= 0 && jb.band[src] == jb.boost_band) sc *= T(jb.boost_factor);
+    sc = gld(sIn, src) * T(0.70710678118654752440084436210485);
+    if (jb.band && jb.boost_band >= 0 && gld(jb.band, src) == jb.boost_band) sc *= T(jb.boost_factor);
   } else {
-    v = reinterpret_cast<const cpx<T>*>(jb.vin)[src + dvc];
-    if (sIn) sc = sIn[src];
+    v = gld(reinterpret_cast<const cpx<T>*>(jb.vin), src + (uint32_t)dvc);
+    if (sIn) sc = gld(sIn, src);
     if (mode == CM_RAW_GRAD || mode == CM_RAW_HV) {
-      const T sq = reinterpret_cast<const T*>(jb.sOut)[src];
+      const T sq = gld(reinterpret_cast<const T*>(jb.sOut), src);
       if (sq == T(0)) {
         v = mk(T(0), T(0));
       } else if (!part && mode == CM_RAW_GRAD) {
         acc += ((double)v.x * v.x + (double)v.y * v.y) / ((double)sq * sq);
       }
     } else if (mode == CM_GRAD && !part) {
-      const double wa = jb.aTab ? (double)reinterpret_cast<const T*>(jb.aTab)[src] : 1.0;
+      const double wa = jb.aTab ? (double)gld(reinterpret_cast<const T*>(jb.aTab), src) : 1.0;
       acc += wa * ((double)v.x * v.x + (double)v.y * v.y);
     }
   }
@@ -153,13 +153,13 @@ __device__ __forceinline__ void row_pixel(const Job& jb, int mode, bool adjIn, i
   const T invn = T(1) / T(N);
   const T* W = reinterpret_cast<const T*>(jb.W);
   const T* dd = reinterpret_cast<const T*>(jb.d);
-  const int64_t pix = (int64_t)y * N + 2 * j;
-  const int64_t cp = (int64_t)c * N * N + pix;
+  const uint32_t pix = (uint32_t)y * N + 2 * j;
+  const uint32_t cp = (uint32_t)c * N * N + pix;
   if (adjIn) {
-    T x0 = dd[cp], x1 = dd[cp + 1];
+    T x0 = gld(dd, cp), x1 = gld(dd, cp + 1);
     if (W) {   // masked adjoint: R^T M x
-      if (!(W[pix] > T(0))) x0 = T(0);
-      if (!(W[pix + 1] > T(0))) x1 = T(0);
+      if (!(gld(W, pix) > T(0))) x0 = T(0);
+      if (!(gld(W, pix + 1) > T(0))) x1 = T(0);
     }
     z = mk(x0 * invn, x1 * invn);
     return;
@@ -167,11 +167,11 @@ __device__ __forceinline__ void row_pixel(const Job& jb, int mode, bool adjIn, i
   const T x0 = z.x * invn, x1 = z.y * invn;
   T* xout = reinterpret_cast<T*>(jb.xout);
   if (mode == CM_FWD) {   // masked forward M R s when W is given
-    xout[cp] = (W && !(W[pix] > T(0))) ? T(0) : x0;
-    xout[cp + 1] = (W && !(W[pix + 1] > T(0))) ? T(0) : x1;
+    gst(xout, cp, (W && !(gld(W, pix) > T(0))) ? T(0) : x0);
+    gst(xout, cp + 1, (W && !(gld(W, pix + 1) > T(0))) ? T(0) : x1);
     return;
   }
-  const T W0 = W[pix], W1 = W[pix + 1];
+  const T W0 = gld(W, pix), W1 = gld(W, pix + 1);
   if (SIMK && mode == CM_SIM) {
     const T* draws = reinterpret_cast<const T*>(jb.draws);
     T n0, n1;
@@ -197,12 +197,12 @@ __device__ __forceinline__ void row_pixel(const Job& jb, int mode, bool adjIn, i
     r0 = T(0);
     r1 = T(0);
     if (W0 > T(0)) {
-      const T e0 = x0 - dd[cp];
+      const T e0 = x0 - gld(dd, cp);
       r0 = W0 * e0;
       acc += (double)r0 * e0;
     }
     if (W1 > T(0)) {
-      const T e1 = x1 - dd[cp + 1];
+      const T e1 = x1 - gld(dd, cp + 1);
       r1 = W1 * e1;
       acc += (double)r1 * e1;
     }
@@ -217,20 +217,21 @@ template <typename T, int N>
 __device__ __forceinline__ cpx<T> colfwd_val(const Job& jb, int mode, int ky, int kx, int64_t o, int64_t dvc,
                                              cpx<T> t, double& avo, double& aoo) {
   const bool fr = is_free(N, ky, kx);
+  const uint32_t oi = (uint32_t)o, ov = (uint32_t)(o + dvc);
   cpx<T> out = mk(T(0), T(0));
   if (mode == CM_HV || mode == CM_GRAD) {
-    const T sq = reinterpret_cast<const T*>(jb.sOut)[o];
+    const T sq = gld(reinterpret_cast<const T*>(jb.sOut), oi);
     if (fr && sq != T(0)) {
-      const cpx<T> v = reinterpret_cast<const cpx<T>*>(jb.vadd)[o + dvc];
-      const T wa = jb.aTab ? reinterpret_cast<const T*>(jb.aTab)[o] : T(1);
+      const cpx<T> v = gld(reinterpret_cast<const cpx<T>*>(jb.vadd), ov);
+      const T wa = jb.aTab ? gld(reinterpret_cast<const T*>(jb.aTab), oi) : T(1);
       out = mk(wa * v.x + sq * t.x, wa * v.y + sq * t.y);
       avo += (double)v.x * out.x + (double)v.y * out.y;
     }
     aoo += (double)out.x * out.x + (double)out.y * out.y;
   } else if (mode == CM_RAW_GRAD || mode == CM_RAW_HV) {
-    const T sq = reinterpret_cast<const T*>(jb.sOut)[o];
+    const T sq = gld(reinterpret_cast<const T*>(jb.sOut), oi);
     if (fr && sq != T(0)) {
-      const cpx<T> v = reinterpret_cast<const cpx<T>*>(jb.vadd)[o + dvc];
+      const cpx<T> v = gld(reinterpret_cast<const cpx<T>*>(jb.vadd), ov);
       const T is = T(1) / (sq * sq);
       out = mk(T(4) * (v.x * is + t.x), T(4) * (v.y * is + t.y));
     }
@@ -239,7 +240,7 @@ __device__ __forceinline__ cpx<T> colfwd_val(const Job& jb, int mode, int ky, in
   } else {  // CM_ADJ_GRAD
     if (fr) out = scale(t, T(2));
   }
-  reinterpret_cast<cpx<T>*>(jb.vout)[o + dvc] = out;
+  gst(reinterpret_cast<cpx<T>*>(jb.vout), ov, out);
   return out;
 }
 
@@ -564,9 +565,9 @@ __global__ __launch_bounds__(NT) void k_colinvr(const Job* __restrict__ jobs, co
     const cpx<T>* g = twg + tw_col_off(N, E);
     for (int i = tid; i < N; i += NT) st[i] = g[i];
   }
-  auto lx = [](int b, int i) { return (i + i / PQ) * NB + b; };
+  auto lx = [](uint32_t b, uint32_t i) { return (i + i / PQ) * NB + b; };
   // this thread's transform (the same in every stage: NT is a multiple of NB)
-  const int b = tid % NB;
+  const uint32_t b = (uint32_t)tid % NB;
   const int col = b % TB, c = (b / TB) % C, cb = b / (TB * C);
   const int qb = q * CPB + cb, kx = qb * TB + col;
   const int64_t bs = fidx(N, c, 0, qb * TB);
@@ -577,7 +578,7 @@ __global__ __launch_bounds__(NT) void k_colinvr(const Job* __restrict__ jobs, co
     constexpr int R0 = PQ, NQ0 = N / R0, K0 = E / R0;
     sfor<0, K0>([&](auto KK) {
       constexpr int kk = decltype(KK)::value;
-      const int j = (tid + kk * NT) / NB;
+      const int j = ((uint32_t)tid + kk * NT) / NB;
       sfor<0, R0>([&](auto RR) {
         constexpr int r = decltype(RR)::value;
         const int ky = j + r * NQ0;
@@ -594,16 +595,16 @@ __global__ __launch_bounds__(NT) void k_colinvr(const Job* __restrict__ jobs, co
       });
     });
   }
-  rs_fft<T, N, NB, E, false, true, false>(v, data, st, lx);
+  rs_fft<T, N, NB, E, false, true, false>(v, data, st, lx, tid);
   {
     constexpr int RL = rs_radix(N, E, false, NST - 1), NQL = N / RL, KL = E / RL;
     cpx<T>* y = reinterpret_cast<cpx<T>*>(jb.y);
     sfor<0, KL>([&](auto KK) {
       constexpr int kk = decltype(KK)::value;
-      const int j = (tid + kk * NT) / NB;
+      const uint32_t j = ((uint32_t)tid + kk * NT) / NB;
       sfor<0, RL>([&](auto RR) {
         constexpr int r = decltype(RR)::value;
-        y[bs + (j + r * NQL) * TB + col] = v[kk * RL + r];
+        gst(y, (uint32_t)bs + (j + r * NQL) * TB + col, v[kk * RL + r]);
       });
     });
   }
@@ -613,14 +614,16 @@ __global__ __launch_bounds__(NT) void k_colinvr(const Job* __restrict__ jobs, co
   }
 }
 
+// Persistent: work-group w takes tiles t = w, w + G, ... (G = gridDim.x) of the flattened
+// (instance, component, row tile) list and loads the next tile's input into registers while
+// it transforms the current one.
 template <int N, int C>
-__global__ __launch_bounds__(NT) void k_rowr(const Job* __restrict__ jobs, const cpx<float>* __restrict__ twg) {
+__global__ __launch_bounds__(NT) void k_rowr(const Job* __restrict__ jobs, const cpx<float>* __restrict__ twg,
+                                             int batch) {
   using T = float;
-  const Job& jb = jobs[blockIdx.y];
-  const int mode = jb.mode;
-  if (mode == CM_NONE || mode == CM_SIM) return;
-  constexpr int H = N / 2, E = rowr_e(N), RB = rowr_rb(N), NE = RB * H;
-  static_assert(RB % RB_MIN == 0 && N % RB == 0, "row tile");
+  constexpr int H = N / 2, E = rowr_e(N), RB = rowr_rb(N), NE = RB * H, KS = NE / NT;
+  static_assert(RB % RB_MIN == 0 && N % RB == 0 && NE % NT == 0, "row tile");
+  constexpr int TPC = N / RB, TPI = C * TPC;   // tiles per component and per instance
   constexpr int NST = rs_nst(H, E);
   constexpr int PQI = rs_radix(H, E, false, 0), PQF = rs_radix(H, E, true, 0);
   constexpr int SBIO = rowr_io_stride(H), SBXI = rowr_x_stride(H, E, false), SBXF = rowr_x_stride(H, E, true);
@@ -630,7 +633,7 @@ __global__ __launch_bounds__(NT) void k_rowr(const Job* __restrict__ jobs, const
   cpx<T>* stF = stI + H;
   __shared__ double red[NT / 64];
   const int tid = threadIdx.x;
-  const int c = blockIdx.x / (N / RB), tile = blockIdx.x % (N / RB), y0 = tile * RB;
+  const int total = batch * TPI, G = gridDim.x;
   {
     const cpx<T>* gI = twg + tw_row_off(N, E, false);
     const cpx<T>* gF = twg + tw_row_off(N, E, true);
@@ -639,84 +642,119 @@ __global__ __launch_bounds__(NT) void k_rowr(const Job* __restrict__ jobs, const
       stF[i] = gF[i];
     }
   }
-  auto lio = [](int b, int i) { return b * SBIO + i; };
-  auto lxi = [](int b, int i) { return b * SBXI + i + i / PQI; };
-  auto lxf = [](int b, int i) { return b * SBXF + i + i / PQF; };
-  const bool adjIn = (mode == CM_ADJ || mode == CM_ADJ_GRAD);
-  cpx<T>* Y = reinterpret_cast<cpx<T>*>(jb.y) + fidx(N, c, y0, 0);   // column block 0 of this tile
-  cpx<T> v[E];
-  double acc = 0.0;
-  if (!adjIn) {
-    for (int e = tid; e < NE; e += NT) {
-      const int qq = e / (RB * TB), w2 = e % (RB * TB);
-      data[lio(w2 / TB, qq * TB + w2 % TB)] = Y[(int64_t)qq * N * TB + w2];
+  auto lio = [](uint32_t b, uint32_t i) { return b * SBIO + i; };
+  auto lxi = [](uint32_t b, uint32_t i) { return b * SBXI + i + i / PQI; };
+  auto lxf = [](uint32_t b, uint32_t i) { return b * SBXF + i + i / PQF; };
+  auto staged = [](int mode) { return mode != CM_NONE && mode != CM_SIM && mode != CM_ADJ && mode != CM_ADJ_GRAD; };
+  // this thread's staging elements e = tid + k NT of a tile: column block qq, offset w2
+  auto tile_ptr = [&](const Job& jb, int t) {
+    const int r = t % TPI;
+    return reinterpret_cast<cpx<T>*>(jb.y) + fidx(N, r / TPC, (r % TPC) * RB, 0);
+  };
+  cpx<T> pf[KS];
+  auto prefetch = [&](int t, uint32_t tid) {
+    if (t >= total) return;
+    const Job& jn = jobs[t / TPI];
+    if (!staged(jn.mode)) return;
+    const cpx<T>* Yn = tile_ptr(jn, t);
+    sfor<0, KS>([&](auto K) {
+      constexpr int k = decltype(K)::value;
+      const uint32_t e = tid + k * NT, qq = e / (RB * TB), w2 = e % (RB * TB);
+      pf[k] = gld(Yn, qq * N * TB + w2);
+    });
+  };
+  prefetch(blockIdx.x, tid);
+  for (int t = blockIdx.x; t < total; t += G) {
+    const uint32_t tid = opaque_tid();
+    const Job& jb = jobs[t / TPI];
+    const int mode = jb.mode;
+    if (mode == CM_NONE || mode == CM_SIM) {
+      prefetch(t + G, tid);
+      continue;
     }
-    __syncthreads();
-    // complex-to-real pre-processing into the first stage's registers (see k_row)
-    constexpr int R0 = PQI, NQ0 = H / R0, K0 = E / R0;
-    sfor<0, K0>([&](auto KK) {
-      constexpr int kk = decltype(KK)::value;
-      const int u = tid + kk * NT, b = u / NQ0, j = u % NQ0;
-      sfor<0, R0>([&](auto RR) {
-        constexpr int r = decltype(RR)::value;
-        const int k = j + r * NQ0;
-        const cpx<T> X = data[lio(b, k)];
-        cpx<T> z;
-        if (k == 0) {
-          z = mk(X.x, X.x);
-        } else {
-          const cpx<T> Xm = conj(data[lio(b, H - k)]);
-          const cpx<T> t = mulc(sub(X, Xm), twg[k]);
-          const cpx<T> s = add(X, Xm);
-          z = mk(s.x - t.y, s.y + t.x);
-        }
-        v[kk * R0 + r] = z;
+    const int c = (t % TPI) / TPC, tile = (t % TPI) % TPC, y0 = tile * RB;
+    const bool adjIn = (mode == CM_ADJ || mode == CM_ADJ_GRAD);
+    cpx<T>* Y = tile_ptr(jb, t);
+    cpx<T> v[E];
+    double acc = 0.0;
+    __syncthreads();   // the previous tile's readers of data are done
+    if (!adjIn) {
+      sfor<0, KS>([&](auto K) {
+        constexpr int k = decltype(K)::value;
+        const uint32_t e = tid + k * NT, w2 = e % (RB * TB);
+        data[lio(w2 / TB, (e / (RB * TB)) * TB + w2 % TB)] = pf[k];
       });
-    });
-    rs_fft<T, H, RB, E, true, true, false>(v, data, stI, lxi);
-  }
-  {
-    // pixel step in the inverse's last-stage layout, which is the forward's first-stage one
-    constexpr int RL = rs_radix(H, E, false, NST - 1), NQL = H / RL, KL = E / RL;
-    sfor<0, KL>([&](auto KK) {
-      constexpr int kk = decltype(KK)::value;
-      const int u = tid + kk * NT, b = u / NQL, j = u % NQL;
-      sfor<0, RL>([&](auto RR) {
-        constexpr int r = decltype(RR)::value;
-        row_pixel<T, N, C, false>(jb, mode, adjIn, c, y0 + b, j + r * NQL, v[kk * RL + r], acc);
+    }
+    prefetch(t + G, tid);
+    if (!adjIn) {
+      __syncthreads();
+      // complex-to-real pre-processing into the first stage's registers (see k_row)
+      constexpr int R0 = PQI, NQ0 = H / R0, K0 = E / R0;
+      sfor<0, K0>([&](auto KK) {
+        constexpr int kk = decltype(KK)::value;
+        const uint32_t u = tid + kk * NT, b = u / NQ0, j = u % NQ0;
+        sfor<0, R0>([&](auto RR) {
+          constexpr int r = decltype(RR)::value;
+          const uint32_t k = j + r * NQ0;
+          const cpx<T> X = data[lio(b, k)];
+          cpx<T> z;
+          if (k == 0) {
+            z = mk(X.x, X.x);
+          } else {
+            const cpx<T> Xm = conj(data[lio(b, H - k)]);
+            const cpx<T> tw = mulc(sub(X, Xm), gld(twg, k));
+            const cpx<T> sm = add(X, Xm);
+            z = mk(sm.x - tw.y, sm.y + tw.x);
+          }
+          v[kk * R0 + r] = z;
+        });
       });
-    });
-  }
-  if (mode == CM_FWD) return;
-  rs_fft<T, H, RB, E, true, false, true>(v, data, stF, lxf);
-  {
-    // outputs are in the inverse's first-stage layout: to LDS in natural order for the
-    // real-to-complex untangle, which pairs k with H - k
-    constexpr int R0 = PQI, NQ0 = H / R0, K0 = E / R0;
-    __syncthreads();
-    sfor<0, K0>([&](auto KK) {
-      constexpr int kk = decltype(KK)::value;
-      const int u = tid + kk * NT, b = u / NQ0, j = u % NQ0;
-      sfor<0, R0>([&](auto RR) {
-        constexpr int r = decltype(RR)::value;
-        data[lio(b, j + r * NQ0)] = v[kk * R0 + r];
+      rs_fft<T, H, RB, E, true, true, false>(v, data, stI, lxi, tid);
+    }
+    {
+      // pixel step in the inverse's last-stage layout, which is the forward's first-stage one
+      constexpr int RL = rs_radix(H, E, false, NST - 1), NQL = H / RL, KL = E / RL;
+      sfor<0, KL>([&](auto KK) {
+        constexpr int kk = decltype(KK)::value;
+        const uint32_t u = tid + kk * NT, b = u / NQL, j = u % NQL;
+        sfor<0, RL>([&](auto RR) {
+          constexpr int r = decltype(RR)::value;
+          row_pixel<T, N, C, false>(jb, mode, adjIn, c, y0 + b, j + r * NQL, v[kk * RL + r], acc);
+        });
       });
+    }
+    if (mode == CM_FWD) continue;
+    rs_fft<T, H, RB, E, true, false, true>(v, data, stF, lxf, tid);
+    {
+      // outputs are in the inverse's first-stage layout: to LDS in natural order for the
+      // real-to-complex untangle, which pairs k with H - k
+      constexpr int R0 = PQI, NQ0 = H / R0, K0 = E / R0;
+      __syncthreads();
+      sfor<0, K0>([&](auto KK) {
+        constexpr int kk = decltype(KK)::value;
+        const uint32_t u = tid + kk * NT, b = u / NQ0, j = u % NQ0;
+        sfor<0, R0>([&](auto RR) {
+          constexpr int r = decltype(RR)::value;
+          data[lio(b, j + r * NQ0)] = v[kk * R0 + r];
+        });
+      });
+      __syncthreads();
+    }
+    sfor<0, KS>([&](auto K) {
+      constexpr int kq = decltype(K)::value;
+      const uint32_t e = tid + kq * NT, qq = e / (RB * TB), w2 = e % (RB * TB);
+      const uint32_t b = w2 / TB, k = qq * TB + w2 % TB;
+      const cpx<T> Zk = data[lio(b, k)];
+      const cpx<T> Zm = conj(data[lio(b, k == 0 ? 0 : H - k)]);
+      const cpx<T> A = add(Zk, Zm);
+      const cpx<T> tw = mul(gld(twg, k), sub(Zk, Zm));
+      gst(Y, qq * N * TB + w2, mk(T(0.5) * (A.x + tw.y), T(0.5) * (A.y - tw.x)));
     });
-    __syncthreads();
-  }
-  for (int e = tid; e < NE; e += NT) {
-    const int qq = e / (RB * TB), w2 = e % (RB * TB);
-    const int b = w2 / TB, k = qq * TB + w2 % TB;
-    const cpx<T> Zk = data[lio(b, k)];
-    const cpx<T> Zm = conj(data[lio(b, k == 0 ? 0 : H - k)]);
-    const cpx<T> A = add(Zk, Zm);
-    const cpx<T> t = mul(twg[k], sub(Zk, Zm));
-    Y[(int64_t)qq * N * TB + w2] = mk(T(0.5) * (A.x + t.y), T(0.5) * (A.y - t.x));
-  }
-  if (mode == CM_GRAD || mode == CM_RAW_GRAD) {
-    const double t = block_sum(acc, red);
-    constexpr int PR = RB / RB_MIN;
-    if (tid < PR) jb.part[PK_RES * jb.pstride + c * (N / RB_MIN) + tile * PR + tid] = tid == 0 ? t : 0.0;
+    if (mode == CM_GRAD || mode == CM_RAW_GRAD) {
+      const double tsum = block_sum(acc, red);
+      constexpr int PR = RB / RB_MIN;
+      if (tid < PR) jb.part[PK_RES * jb.pstride + c * (N / RB_MIN) + tile * PR + tid] = tid == 0 ? tsum : 0.0;
+    }
   }
 }
 
@@ -736,8 +774,8 @@ __global__ __launch_bounds__(NT) void k_colfwdr(const Job* __restrict__ jobs, co
     const cpx<T>* g = twg + tw_col_off(N, E);
     for (int i = tid; i < N; i += NT) st[i] = g[i];
   }
-  auto lx = [](int b, int i) { return (i + i / PQ) * NB + b; };
-  const int b = tid % NB;
+  auto lx = [](uint32_t b, uint32_t i) { return (i + i / PQ) * NB + b; };
+  const uint32_t b = (uint32_t)tid % NB;
   const int col = b % TB, c = (b / TB) % C, cb = b / (TB * C);
   const int qb = q * CPB + cb, kx = qb * TB + col;
   const int64_t bs = fidx(N, c, 0, qb * TB);
@@ -748,19 +786,19 @@ __global__ __launch_bounds__(NT) void k_colfwdr(const Job* __restrict__ jobs, co
     constexpr int R0 = PQ, NQ0 = N / R0, K0 = E / R0;
     sfor<0, K0>([&](auto KK) {
       constexpr int kk = decltype(KK)::value;
-      const int j = (tid + kk * NT) / NB;
+      const uint32_t j = ((uint32_t)tid + kk * NT) / NB;
       sfor<0, R0>([&](auto RR) {
         constexpr int r = decltype(RR)::value;
-        v[kk * R0 + r] = Y[bs + (j + r * NQ0) * TB + col];
+        v[kk * R0 + r] = gld(Y, (uint32_t)bs + (j + r * NQ0) * TB + col);
       });
     });
   }
-  rs_fft<T, N, NB, E, false, false, false>(v, data, st, lx);
+  rs_fft<T, N, NB, E, false, false, false>(v, data, st, lx, tid);
   constexpr int RL = rs_radix(N, E, false, NST - 1), NQL = N / RL, KL = E / RL;
   double avo = 0.0, aoo = 0.0;
   sfor<0, KL>([&](auto KK) {
     constexpr int kk = decltype(KK)::value;
-    const int j = (tid + kk * NT) / NB;
+    const uint32_t j = ((uint32_t)tid + kk * NT) / NB;
     sfor<0, RL>([&](auto RR) {
       constexpr int r = decltype(RR)::value;
       const int ky = j + r * NQL;
@@ -793,10 +831,10 @@ __global__ __launch_bounds__(NT) void k_colfwdr(const Job* __restrict__ jobs, co
     double a = 0.0;
     sfor<0, KL>([&](auto KK) {
       constexpr int kk = decltype(KK)::value;
-      const int j = (tid + kk * NT) / NB;
+      const uint32_t j = ((uint32_t)tid + kk * NT) / NB;
       sfor<0, RL>([&](auto RR) {
         constexpr int r = decltype(RR)::value;
-        const cpx<T> w = u[bs + (j + r * NQL) * TB + col + dvc];
+        const cpx<T> w = gld(u, (uint32_t)(bs + dvc) + (j + r * NQL) * TB + col);
         a += (double)w.x * v[kk * RL + r].x + (double)w.y * v[kk * RL + r].y;
       });
     });

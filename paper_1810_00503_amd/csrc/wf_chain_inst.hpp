@@ -1,6 +1,7 @@
 // Instantiation of the transform-chain kernels for one element type and a list of grid
 // sides.  Included by the wf_chain_*.hip units with WF_T, WF_SIZES, WF_VARIANTS and the
 // entry-point names defined.
+#include <algorithm>
 #include <type_traits>
 #include "wf_chain.hpp"
 #include "wf_launch.hpp"
@@ -25,6 +26,18 @@ template <typename T, int N, int C, int RBV, bool SIMK = false>
 static hipError_t prep_row() {
   return hipFuncSetAttribute((const void*)k_row<T, N, C, RBV, SIMK>, hipFuncAttributeMaxDynamicSharedMemorySize,
                              (int)lds_rowpass<T, N, C, RBV>());
+}
+
+// work-groups of a persistent register-staged row pass: 6 per CU of the device
+static int rowr_grid() {
+  static int g = 0;
+  if (g == 0) {
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+      cus = 256;
+    g = 6 * cus;
+  }
+  return g;
 }
 
 // register-staged passes: float32, power-of-two n >= 128
@@ -114,7 +127,10 @@ static hipError_t launch_t(int which, const ChainCfg& cfg, const Job* jobs, int 
   if constexpr (reg_ok<T, N>()) {
     const cpx<float>* tf = reinterpret_cast<const cpx<float>*>(tw);
     if (which == CH_ROW && (cfg.reg & 1)) {
-      k_rowr<N, C><<<dim3(C * (N / rowr_rb(N)), batch), dim3(NT), lds_rowr<N>(), st>>>(jobs, tf);
+      // persistent tiles: about as many work-groups as fit on the device at once
+      const int total = batch * C * (N / rowr_rb(N));
+      const int G = std::min(total, rowr_grid());
+      k_rowr<N, C><<<dim3(G), dim3(NT), lds_rowr<N>(), st>>>(jobs, tf, batch);
       return hipGetLastError();
     }
     if ((which == CH_COLINV && (cfg.reg & 2)) || (which == CH_COLFWD && (cfg.reg & 4))) {

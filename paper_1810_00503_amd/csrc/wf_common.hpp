@@ -37,6 +37,57 @@ __device__ __forceinline__ cpx<T> conj(cpx<T> a) { return mk(a.x, -a.y); }
 template <typename T>
 __device__ __forceinline__ cpx<T> scale(cpx<T> a, T s) { return mk(a.x * s, a.y * s); }
 
+// ------------------------------------------------------------------------ global accesses
+// Device pointers taken from job descriptors are generic pointers, which compile to flat
+// accesses with 64-bit per-lane addresses.  gld / gst address global memory explicitly from
+// a work-group-uniform base with a 32-bit byte offset (the base stays in scalar registers,
+// the offset takes one vector register); i * sizeof(T) must stay below 4 GiB.
+template <typename T>
+using gptr = __attribute__((address_space(1))) T*;
+typedef float gf32x2 __attribute__((ext_vector_type(2)));
+typedef float gf32x4 __attribute__((ext_vector_type(4)));
+typedef double gf64x2 __attribute__((ext_vector_type(2)));
+// the builtin type a T moves as (class types cannot be copied out of a qualified address space)
+template <typename T>
+struct GStore {
+  using type = T;
+};
+template <>
+struct GStore<cpx<float>> {
+  using type = gf32x2;
+};
+template <>
+struct GStore<cpx<double>> {
+  using type = gf64x2;
+};
+template <>
+struct GStore<float2> {
+  using type = gf32x2;
+};
+template <>
+struct GStore<float4> {
+  using type = gf32x4;
+};
+template <>
+struct GStore<double2> {
+  using type = gf64x2;
+};
+template <typename T>
+__device__ __forceinline__ T gld(const T* base, uint32_t i) {
+  using S = typename GStore<T>::type;
+  const S v = *(gptr<const S>)((gptr<const char>)(const char*)base + i * (uint32_t)sizeof(T));
+  T r;
+  __builtin_memcpy(&r, &v, sizeof(T));
+  return r;
+}
+template <typename T>
+__device__ __forceinline__ void gst(T* base, uint32_t i, const T& x) {
+  using S = typename GStore<T>::type;
+  S v;
+  __builtin_memcpy(&v, &x, sizeof(T));
+  *(gptr<S>)((gptr<char>)(char*)base + i * (uint32_t)sizeof(T)) = v;
+}
+
 // ------------------------------------------------------------------------ layout
 // Internal storage of a harmonic field: column blocks of TB columns, each block a
 // contiguous [n][TB] array, so a column pass reads contiguous memory and a row pass

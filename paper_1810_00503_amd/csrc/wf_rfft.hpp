@@ -149,16 +149,16 @@ __device__ __forceinline__ void rdft(cpx<T>* v) {
 
 // ------------------------------------------------------------------------ transform
 // v: on entry stage 0's inputs, on exit the last stage's outputs (see above).  lds: exchange
-// buffer addressed by lid(b, i); stw: this schedule's stage-twiddle table (LDS or global).
+// buffer addressed by lid(b, i); stw: this schedule's stage-twiddle table (LDS or global);
+// tid: the thread's index in the work-group.
 // Starts every exchange with a barrier, so the caller may still have LDS reads in flight
 // from the previous use of the buffer; returns without a trailing barrier.
 template <typename T, int N, int NB, int E, bool JFAST, bool INV, bool REV, typename LID>
 __device__ __forceinline__ void rs_fft(cpx<T> (&v)[E], cpx<T>* __restrict__ lds, const cpx<T>* __restrict__ stw,
-                                       LID lid) {
+                                       LID lid, uint32_t tid) {
   static_assert(NB * N == E * NT, "E elements per thread");
   constexpr int NST = rs_nst(N, E);
   constexpr int R0 = rs_radix(N, E, REV, 0);
-  const int tid = threadIdx.x;
   sfor<0, NST>([&](auto S_) {
     constexpr int s = decltype(S_)::value;
     constexpr int R = rs_radix(N, E, REV, s), NS = rs_ns(N, E, REV, s), NQ = N / R, K = E / R;
@@ -166,9 +166,9 @@ __device__ __forceinline__ void rs_fft(cpx<T> (&v)[E], cpx<T>* __restrict__ lds,
       constexpr int off = NS - R0;
       sfor<0, K>([&](auto KK) {
         constexpr int kk = decltype(KK)::value;
-        const int u = tid + kk * NT;
-        const int j = JFAST ? u % NQ : u / NB;
-        const int k = j % NS;
+        const uint32_t u = tid + kk * NT;
+        const uint32_t j = JFAST ? u % NQ : u / NB;
+        const uint32_t k = j % NS;
         sfor<1, R>([&](auto RR) {
           constexpr int r = decltype(RR)::value;
           const cpx<T> w = stw[off + (r - 1) * NS + k];
@@ -181,9 +181,9 @@ __device__ __forceinline__ void rs_fft(cpx<T> (&v)[E], cpx<T>* __restrict__ lds,
       __syncthreads();
       sfor<0, K>([&](auto KK) {
         constexpr int kk = decltype(KK)::value;
-        const int u = tid + kk * NT;
-        const int b = JFAST ? u / NQ : u % NB, j = JFAST ? u % NQ : u / NB;
-        const int base = (j / NS) * NS * R + (j % NS);
+        const uint32_t u = tid + kk * NT;
+        const uint32_t b = JFAST ? u / NQ : u % NB, j = JFAST ? u % NQ : u / NB;
+        const uint32_t base = (j / NS) * NS * R + (j % NS);
         sfor<0, R>([&](auto RR) {
           constexpr int r = decltype(RR)::value;
           lds[lid(b, base + r * NS)] = v[kk * R + r];
@@ -193,8 +193,8 @@ __device__ __forceinline__ void rs_fft(cpx<T> (&v)[E], cpx<T>* __restrict__ lds,
       constexpr int R2 = rs_radix(N, E, REV, s + 1), NQ2 = N / R2, K2 = E / R2;
       sfor<0, K2>([&](auto KK) {
         constexpr int kk = decltype(KK)::value;
-        const int u = tid + kk * NT;
-        const int b = JFAST ? u / NQ2 : u % NB, j = JFAST ? u % NQ2 : u / NB;
+        const uint32_t u = tid + kk * NT;
+        const uint32_t b = JFAST ? u / NQ2 : u % NB, j = JFAST ? u % NQ2 : u / NB;
         sfor<0, R2>([&](auto RR) {
           constexpr int r = decltype(RR)::value;
           v[kk * R2 + r] = lds[lid(b, j + r * NQ2)];
@@ -202,6 +202,14 @@ __device__ __forceinline__ void rs_fft(cpx<T> (&v)[E], cpx<T>* __restrict__ lds,
       });
     }
   });
+}
+
+// the thread index through an opaque move: index arithmetic derived from it inside a loop
+// is not hoisted out of the loop (which would keep every address of every tile in registers)
+__device__ __forceinline__ uint32_t opaque_tid() {
+  uint32_t t;
+  asm volatile("v_mov_b32 %0, %1" : "=v"(t) : "v"((uint32_t)threadIdx.x));
+  return t;
 }
 
 // value of the lane whose index differs in bit 1 (partner component of a column pair);

@@ -40,12 +40,12 @@ __device__ __forceinline__ double2 vaxpy(double a, const double2& x, const doubl
 __device__ __forceinline__ float4 vscale(float a, const float4& x) { return make_float4(a * x.x, a * x.y, a * x.z, a * x.w); }
 // |g|^2 in the whitened norm of a preconditioned solve: sum over the complex elements of the
 // vector element e of |g_k|^2 / P_k (ainv = 1 / P)
-__device__ __forceinline__ double wnorm2(const float4& g, const float* ainv, int64_t e) {
-  const float2 a = reinterpret_cast<const float2*>(ainv)[e];
+__device__ __forceinline__ double wnorm2(const float4& g, const float* ainv, uint32_t e) {
+  const float2 a = gld(reinterpret_cast<const float2*>(ainv), e);
   return (double)a.x * ((double)g.x * g.x + (double)g.y * g.y) + (double)a.y * ((double)g.z * g.z + (double)g.w * g.w);
 }
-__device__ __forceinline__ double wnorm2(const double2& g, const double* ainv, int64_t e) {
-  return ainv[e] * (g.x * g.x + g.y * g.y);
+__device__ __forceinline__ double wnorm2(const double2& g, const double* ainv, uint32_t e) {
+  return gld(ainv, e) * (g.x * g.x + g.y * g.y);
 }
 __device__ __forceinline__ double2 vscale(double a, const double2& x) { return make_double2(a * x.x, a * x.y); }
 
@@ -166,13 +166,12 @@ __global__ __launch_bounds__(NT) void k_passA(const InstDesc* __restrict__ desc,
   constexpr int VW = VecT<T>::W;
   __shared__ double red[NT / 64][NDOT];
   const int nh = S.nhist, head = S.head;
-  const int64_t nvec = D.L * 2 / VW;
-  const int64_t vs = D.vstride * 2 / VW;
-  const int64_t e0 = (int64_t)blockIdx.x * PASS_CV + threadIdx.x;
+  // element offsets (units of V) from the instance's vector block, 32-bit
+  const uint32_t nvec = (uint32_t)(D.L * 2 / VW);
+  const uint32_t vs = (uint32_t)(D.vstride * 2 / VW);
+  const uint32_t e0 = blockIdx.x * (uint32_t)PASS_CV + threadIdx.x;
   const V* X = reinterpret_cast<const V*>(D.X);
-  const V* g = X + vs;
-  const V* P = X + 2 * vs;
-  const V* Dp = X + (2 + M) * vs;
+  const uint32_t og = vs, oP = 2 * vs, oD = (2 + M) * vs;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   bool ok[PASS_U];
   V gv[PASS_U];
@@ -180,10 +179,11 @@ __global__ __launch_bounds__(NT) void k_passA(const InstDesc* __restrict__ desc,
   const T* ainv = reinterpret_cast<const T*>(D.ainv);
 #pragma unroll
   for (int u = 0; u < PASS_U; ++u) {
-    ok[u] = e0 + (int64_t)u * NT < nvec;
+    const uint32_t e = e0 + (uint32_t)u * NT;
+    ok[u] = e < nvec;
     if (ok[u]) {
-      gv[u] = g[e0 + (int64_t)u * NT];
-      gg += ainv ? wnorm2(gv[u], ainv, e0 + (int64_t)u * NT) : vdot(gv[u], gv[u]);
+      gv[u] = gld(X, og + e);
+      gg += ainv ? wnorm2(gv[u], ainv, e) : vdot(gv[u], gv[u]);
     }
   }
   {
@@ -195,14 +195,14 @@ __global__ __launch_bounds__(NT) void k_passA(const InstDesc* __restrict__ desc,
     stream_fence();
     double a0 = 0.0, a1 = 0.0;
     if (j < nh) {
-      const int64_t sp = (int64_t)slot_of(head, j, M) * vs;
+      const uint32_t sp = (uint32_t)slot_of(head, j, M) * vs;
       V pv[PASS_U], dv[PASS_U];
 #pragma unroll
       for (int u = 0; u < PASS_U; ++u)
-        if (ok[u]) pv[u] = P[sp + e0 + (int64_t)u * NT];
+        if (ok[u]) pv[u] = gld(X, oP + sp + e0 + (uint32_t)u * NT);
 #pragma unroll
       for (int u = 0; u < PASS_U; ++u)
-        if (ok[u]) dv[u] = Dp[sp + e0 + (int64_t)u * NT];
+        if (ok[u]) dv[u] = gld(X, oD + sp + e0 + (uint32_t)u * NT);
 #pragma unroll
       for (int u = 0; u < PASS_U; ++u) {
         if (ok[u]) {
@@ -437,32 +437,31 @@ __global__ __launch_bounds__(NT) void k_passB(const InstDesc* __restrict__ desc,
     cD[j] = T(S.coef[MMAX + sj]);
   }
   const T cg = T(S.coef[2 * MMAX]);
-  const int64_t nvec = D.L * 2 / VW;
-  const int64_t vs = D.vstride * 2 / VW;
-  const int64_t e0 = (int64_t)blockIdx.x * PASS_CV + threadIdx.x;
+  // element offsets (units of V) from the instance's vector block, 32-bit
+  const uint32_t nvec = (uint32_t)(D.L * 2 / VW);
+  const uint32_t vs = (uint32_t)(D.vstride * 2 / VW);
+  const uint32_t e0 = blockIdx.x * (uint32_t)PASS_CV + threadIdx.x;
   V* X = reinterpret_cast<V*>(D.X);
-  V* w = X;
-  V* g = X + vs;
-  V* P = X + 2 * vs;
-  const V* Dp = X + (2 + M) * vs;
+  const uint32_t ow = 0, og = vs, oP = 2 * vs, oD = (2 + M) * vs;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   bool ok[PASS_U];
   V gv[PASS_U], acc[PASS_U];
 #pragma unroll
   for (int u = 0; u < PASS_U; ++u) {
-    ok[u] = e0 + (int64_t)u * NT < nvec;
-    if (ok[u]) gv[u] = g[e0 + (int64_t)u * NT];
+    const uint32_t e = e0 + (uint32_t)u * NT;
+    ok[u] = e < nvec;
+    if (ok[u]) gv[u] = gld(X, og + e);
   }
   if (pend) {   // the step of the newest pair: w += alpha p, g += alpha Dp
-    const int64_t sh = (int64_t)head * vs;
+    const uint32_t sh = (uint32_t)head * vs;
 #pragma unroll
     for (int u = 0; u < PASS_U; ++u) {
-      const int64_t e = e0 + (int64_t)u * NT;
+      const uint32_t e = e0 + (uint32_t)u * NT;
       if (ok[u]) {
-        const V ph = P[sh + e], dh = Dp[sh + e];
-        w[e] = vaxpy(al, ph, w[e]);
+        const V ph = gld(X, oP + sh + e), dh = gld(X, oD + sh + e);
+        gst(X, ow + e, vaxpy(al, ph, gld(X, ow + e)));
         gv[u] = vaxpy(al, dh, gv[u]);
-        g[e] = gv[u];
+        gst(X, og + e, gv[u]);
       }
     }
   }
@@ -471,7 +470,7 @@ __global__ __launch_bounds__(NT) void k_passB(const InstDesc* __restrict__ desc,
 #pragma unroll
   for (int u = 0; u < PASS_U; ++u) {
     if (ok[u]) {
-      gg += ainv ? wnorm2(gv[u], ainv, e0 + (int64_t)u * NT) : vdot(gv[u], gv[u]);
+      gg += ainv ? wnorm2(gv[u], ainv, e0 + (uint32_t)u * NT) : vdot(gv[u], gv[u]);
       acc[u] = vscale(cg, gv[u]);
     }
   }
@@ -485,14 +484,14 @@ __global__ __launch_bounds__(NT) void k_passB(const InstDesc* __restrict__ desc,
     stream_fence();
     double a0 = 0.0, a1 = 0.0;
     if (j < nh) {
-      const int64_t sp = (int64_t)slot_of(head, j, M) * vs;
+      const uint32_t sp = (uint32_t)slot_of(head, j, M) * vs;
       V pv[PASS_U], dv[PASS_U];
 #pragma unroll
       for (int u = 0; u < PASS_U; ++u)
-        if (ok[u]) pv[u] = P[sp + e0 + (int64_t)u * NT];
+        if (ok[u]) pv[u] = gld(X, oP + sp + e0 + (uint32_t)u * NT);
 #pragma unroll
       for (int u = 0; u < PASS_U; ++u)
-        if (ok[u]) dv[u] = Dp[sp + e0 + (int64_t)u * NT];
+        if (ok[u]) dv[u] = gld(X, oD + sp + e0 + (uint32_t)u * NT);
 #pragma unroll
       for (int u = 0; u < PASS_U; ++u) {
         if (ok[u]) {
@@ -515,7 +514,7 @@ __global__ __launch_bounds__(NT) void k_passB(const InstDesc* __restrict__ desc,
 #pragma unroll
   for (int u = 0; u < PASS_U; ++u) {
     if (ok[u]) {
-      P[(int64_t)ns * vs + e0 + (int64_t)u * NT] = acc[u];
+      gst(X, oP + (uint32_t)ns * vs + e0 + (uint32_t)u * NT, acc[u]);
       gp += vdot(gv[u], acc[u]);
     }
   }
