@@ -130,25 +130,35 @@ def cmb_pshape(n: int, theta_pix_arcmin: float = 1.7, A: float = 2.0 * math.pi *
 
 # ----------------------------------------------------------------------------- masks
 
+def _cut_disc(m: np.ndarray, cy: float, cx: float, r: float) -> None:
+    """m &= (pixel outside the disc), evaluated only inside the disc's bounding box (every
+    pixel outside the box is farther than r from the centre)."""
+    n = m.shape[0]
+    y0, y1 = max(0, int(np.ceil(cy - r))), min(n - 1, int(np.floor(cy + r)))
+    x0, x1 = max(0, int(np.ceil(cx - r))), min(n - 1, int(np.floor(cx + r)))
+    if y0 > y1 or x0 > x1:
+        return
+    yy, xx = np.mgrid[y0:y1 + 1, x0:x1 + 1]
+    m[y0:y1 + 1, x0:x1 + 1] &= (yy - cy) ** 2 + (xx - cx) ** 2 > r * r
+
+
 def circle_holes(n: int, rng: np.random.Generator, count: int, rmin: float, rmax: float,
                  mask: np.ndarray | None = None) -> np.ndarray:
     """Cut `count` discs of radius U(rmin, rmax) at uniform centres (True = observed)."""
     m = np.ones((n, n), bool) if mask is None else mask.copy()
-    yy, xx = np.mgrid[0:n, 0:n]
     for _ in range(count):
         cy, cx = rng.uniform(0, n, 2)
         r = rng.uniform(rmin, rmax)
-        m &= (yy - cy) ** 2 + (xx - cx) ** 2 > r * r
+        _cut_disc(m, cy, cx, r)
     return m
 
 
 def _holes_until(n, rng, mask, target, rmin, rmax):
     """Add discs one at a time until the masked fraction reaches `target`."""
-    yy, xx = np.mgrid[0:n, 0:n]
     while 1.0 - mask.mean() < target:
         cy, cx = rng.uniform(0, n, 2)
         r = rng.uniform(rmin, rmax)
-        mask &= (yy - cy) ** 2 + (xx - cx) ** 2 > r * r
+        _cut_disc(mask, cy, cx, r)
     return mask
 
 
