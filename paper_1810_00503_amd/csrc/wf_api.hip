@@ -624,6 +624,8 @@ int solve_core(wf_ctx* ctx, const wf_problem* probs, int B, const wf_lbfgs_opts&
         Timed t(ctx, KK_PASSB);
         HIPCHK(lbfgs_launch(dt, m, LB_PASSB, dim3(k.nchunk, cnt), ddesc + k.first, dst + k.first, djobs + k.first, cnt,
                             ctx->cs));
+        HIPCHK(lbfgs_launch(dt, m, LB_PASSBF, dim3(k.nchunk, cnt), ddesc + k.first, dst + k.first, djobs + k.first,
+                            cnt, ctx->cs));
       }
       {
         Timed t(ctx, KK_POST);

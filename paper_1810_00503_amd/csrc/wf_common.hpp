@@ -128,7 +128,8 @@ enum ChainMode : int {
   CM_ADJ_GRAD = 5,  // out = 2 R^T x on free entries
   CM_RAW_GRAD = 6,  // out = 4 (S^-1 v + R^T W (R v - d)), chi^2 partials (raw field)
   CM_RAW_HV = 7,    // out = 4 (S^-1 v + R^T W R v)
-  CM_SIM = 8        // x = M (R (sIn . boost . z / sqrt 2) + noise)     (simulation)
+  CM_SIM = 8,       // x = M (R (sIn . boost . z / sqrt 2) + noise)     (simulation)
+  CM_FLUSH = 9      // solver only: no transform this iteration, pass B brings w up to date
 };
 
 // partial-sum kinds written per block
@@ -192,7 +193,14 @@ struct LbState {
   int iter;
   int nhist;         // kept pairs: slots head, head-1, ..., head-nhist+1 (mod m)
   int head;
-  int pending;       // the newest pair's step is not yet applied to w and g
+  int pending;       // the newest pair's step is not yet applied to g
+  int npend;         // the newest npend pairs' steps are not yet applied to w:
+                     // the iterate is w + sum alpha_i p_i over them
+  int npendB;        // npend when pass B ran (for post B)
+  int flushB;        // pass B applies the pending steps to w
+  int dirB;          // pass B forms a direction
+  int after;         // decision waiting for a flush of w: 0 none, 1 exact-gradient refresh,
+                     // 2 + status: stop with that status
   int chainMode;     // mode of the chain enqueued in this iteration
   int lastWasGrad;   // g currently holds an exact gradient
   int ngrad;

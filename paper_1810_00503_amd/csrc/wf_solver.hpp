@@ -3,18 +3,26 @@
 // One iteration of an instance (every kernel skips instances that have stopped):
 //   chain    curvature product Dp = D p of the new direction, or the exact gradient
 //            (transform passes, wf_chain.hpp); in curvature mode it also returns the dots
-//            of Dp with g and with the kept Dp_j;
+//            of Dp with the stored g and with the kept Dp_j;
 //   passA    only after an exact-gradient evaluation: dots of the new g with the kept
 //            pairs (otherwise these come from the previous pass B and a one-step update);
 //   coef     step length alpha = -g.p / p.Dp of the exact line search of a quadratic
 //            (eq. eq_chib), Gram entries of the new pair, stop test after an exact gradient,
 //            and the two-loop recursion run on coefficients: the direction is a combination
 //            of the kept p_i, Dp_i and g (s_i = alpha_i p_i, y_i = alpha_i Dp_i);
-//   passB    applies the pending step (w += alpha p, g += alpha Dp), forms the direction in
-//            the next history slot and measures g.g, g.p and the dots of g with the pairs;
+//   passB    applies the pending step to g (g += alpha Dp), forms the direction in the next
+//            history slot and measures g.g, g.p and the dots of g with the pairs; when told
+//            to, brings w up to date;
 //   postB    stop test on the measured g, choice of the next chain (curvature product,
-//            exact-gradient refresh, or none) and the remaining Gram entries.
-// Per iteration the vector traffic is about 3m + 13 field vectors (m kept pairs).
+//            exact-gradient refresh, a flush-only iteration, or none) and the remaining Gram
+//            entries.
+// The iterate is updated lazily: w is stored at the last flush and the current iterate is
+// w + sum alpha_i p_i over the pending pairs, whose vectors are the newest kept ones.  Pass B
+// flushes when the direction it writes would overwrite a pending pair (every m iterations)
+// and before an exact-gradient refresh or a stop.  (g is not deferred: forming the direction
+// from a stale g plus pending Dp terms that cancel it would lose the direction's accuracy in
+// float32.)  Per iteration the vector traffic is about 3m + 11 field vectors (m kept pairs),
+// plus 2 at a flush.
 #pragma once
 #include "wf_chain.hpp"
 
@@ -48,6 +56,9 @@ __device__ __forceinline__ double wnorm2(const double2& g, const double* ainv, u
   return gld(ainv, e) * (g.x * g.x + g.y * g.y);
 }
 __device__ __forceinline__ double2 vscale(double a, const double2& x) { return make_double2(a * x.x, a * x.y); }
+template <typename V> __device__ __forceinline__ V vzero();
+template <> __device__ __forceinline__ float4 vzero<float4>() { return make_float4(0.f, 0.f, 0.f, 0.f); }
+template <> __device__ __forceinline__ double2 vzero<double2>() { return make_double2(0.0, 0.0); }
 
 constexpr int NDOT = 5 * MMAX + 1;          // partials per block of k_passA
 
@@ -136,6 +147,11 @@ __global__ void k_init(InstDesc* desc, LbState* st, Job* jobs, int batch) {
   S.head = D.m - 1;
   S.newslot = 0;
   S.pending = 0;
+  S.npend = 0;
+  S.npendB = 0;
+  S.flushB = 0;
+  S.dirB = 0;
+  S.after = 0;
   S.chainMode = CM_GRAD;
   S.lastWasGrad = 0;
   S.ngrad = 0;
@@ -265,6 +281,16 @@ __global__ __launch_bounds__(256) void k_coef(const InstDesc* __restrict__ desc,
   if (S.status != ST_RUNNING) return;
   const InstDesc& D = desc[i];
   const int mode = S.chainMode;
+  if (mode == CM_FLUSH) {   // no transform this iteration: pass B only brings w up to date
+    if (threadIdx.x == 0) {
+      S.doB = 1;
+      S.dirB = 0;
+      S.flushB = 1;
+      S.npendB = S.npend;
+      S.bytes[KK_PASSB] += D.vbytes * (2.0 * S.nhist + 1.0 + 2.0);
+    }
+    return;
+  }
   __shared__ double sums[NDOT];
   __shared__ double part4[4][NDOT];
   __shared__ double chs[3 + MMAX + 2];
@@ -333,6 +359,7 @@ __global__ __launch_bounds__(256) void k_coef(const InstDesc* __restrict__ desc,
     S.nhist = nh;
     S.alpha[ns] = alpha;
     S.pending = 1;
+    S.npend += 1;
     S.pDp = pDp;
     S.dchi2 = 4.0 * (alpha * S.gdotp + 0.5 * alpha * alpha * pDp);
     S.chi2 += S.dchi2;
@@ -353,6 +380,7 @@ __global__ __launch_bounds__(256) void k_coef(const InstDesc* __restrict__ desc,
     S.ngrad += 1;
     S.lastGradIter = S.iter;
     S.pending = 0;
+    S.npend = 0;   // an exact gradient is only taken at a flushed iterate
     S.lastWasGrad = 1;
     S.bytes[KK_PASSA] += D.vbytes * (1.0 + 2.0 * nh);
     for (int j = 0; j < nh; ++j) {
@@ -414,29 +442,36 @@ __global__ __launch_bounds__(256) void k_coef(const InstDesc* __restrict__ desc,
   S.coef[2 * MMAX] = -c[2 * M];
   S.newslot = (head + 1) % M;
   S.doB = 1;
-  S.bytes[KK_PASSB] += D.vbytes * (2.0 * nh + 2.0 + (S.pending ? 3.0 : 0.0));
+  S.dirB = 1;
+  // bring w up to date in this pass B when the direction would overwrite a pending pair
+  S.flushB = (nh == M && S.npend == M) ? 1 : 0;
+  S.npendB = S.npend;
+  S.bytes[KK_PASSB] += D.vbytes * (2.0 * nh + 2.0 + (S.pending ? 1.0 : 0.0) + (S.flushB ? 2.0 : 0.0));
 }
 
 // ------------------------------------------------------------------------ pass B
-template <typename T, int M>
+// FLUSH: the variant for instances whose pass B brings w up to date (launched as a second
+// kernel, so the streaming pass of the others keeps its register budget).
+template <typename T, int M, bool FLUSH>
 __global__ __launch_bounds__(NT) void k_passB(const InstDesc* __restrict__ desc, const LbState* __restrict__ st) {
   const int i = blockIdx.y;
   const LbState& S = st[i];
-  if (S.status != ST_RUNNING || !S.doB) return;
+  if (S.status != ST_RUNNING || !S.doB || (S.flushB != 0) != FLUSH) return;
   const InstDesc& D = desc[i];
   using V = typename VecT<T>::type;
   constexpr int VW = VecT<T>::W;
   __shared__ double red[NT / 64][NDOT];
-  const int nh = S.nhist, head = S.head, ns = S.newslot, pend = S.pending;
-  const T al = pend ? T(S.alpha[head]) : T(0);
-  T cP[M], cD[M];
+  const int nh = S.nhist, head = S.head, ns = S.newslot, pend = S.pending, np = S.npendB, dir = S.dirB;
+  const T alh = pend ? T(S.alpha[head]) : T(0);
+  T cP[M], cD[M], al[M];
 #pragma unroll
   for (int j = 0; j < M; ++j) {
     const int sj = slot_of(head, j, M);
-    cP[j] = T(S.coef[sj]);
-    cD[j] = T(S.coef[MMAX + sj]);
+    al[j] = j < np ? T(S.alpha[sj]) : T(0);
+    cP[j] = dir ? T(S.coef[sj]) : T(0);
+    cD[j] = dir ? T(S.coef[MMAX + sj]) : T(0);
   }
-  const T cg = T(S.coef[2 * MMAX]);
+  const T cg = dir ? T(S.coef[2 * MMAX]) : T(0);
   // element offsets (units of V) from the instance's vector block, 32-bit
   const uint32_t nvec = (uint32_t)(D.L * 2 / VW);
   const uint32_t vs = (uint32_t)(D.vstride * 2 / VW);
@@ -446,21 +481,21 @@ __global__ __launch_bounds__(NT) void k_passB(const InstDesc* __restrict__ desc,
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   bool ok[PASS_U];
   V gv[PASS_U], acc[PASS_U];
+  V wa[FLUSH ? PASS_U : 1];
 #pragma unroll
   for (int u = 0; u < PASS_U; ++u) {
     const uint32_t e = e0 + (uint32_t)u * NT;
     ok[u] = e < nvec;
     if (ok[u]) gv[u] = gld(X, og + e);
+    if constexpr (FLUSH) wa[u] = vzero<V>();
   }
-  if (pend) {   // the step of the newest pair: w += alpha p, g += alpha Dp
+  if (pend) {   // the step of the newest pair on g: g += alpha Dp
     const uint32_t sh = (uint32_t)head * vs;
 #pragma unroll
     for (int u = 0; u < PASS_U; ++u) {
       const uint32_t e = e0 + (uint32_t)u * NT;
       if (ok[u]) {
-        const V ph = gld(X, oP + sh + e), dh = gld(X, oD + sh + e);
-        gst(X, ow + e, vaxpy(al, ph, gld(X, ow + e)));
-        gv[u] = vaxpy(al, dh, gv[u]);
+        gv[u] = vaxpy(alh, gld(X, oD + sh + e), gv[u]);
         gst(X, og + e, gv[u]);
       }
     }
@@ -478,7 +513,8 @@ __global__ __launch_bounds__(NT) void k_passB(const InstDesc* __restrict__ desc,
     const double a = wave_sum(gg);
     if (lane == 0) red[wv][2 * M] = a;
   }
-  // one kept pair at a time: accumulate the direction and the dots of g with the pair
+  // one kept pair at a time: accumulate the direction (and the pending steps of w), dots of
+  // g with the pair
 #pragma unroll
   for (int j = 0; j < M; ++j) {
     stream_fence();
@@ -499,6 +535,9 @@ __global__ __launch_bounds__(NT) void k_passB(const InstDesc* __restrict__ desc,
           a1 += vdot(gv[u], dv[u]);
           acc[u] = vaxpy(cP[j], pv[u], acc[u]);
           acc[u] = vaxpy(cD[j], dv[u], acc[u]);
+          if constexpr (FLUSH) {
+            if (j < np) wa[u] = vaxpy(al[j], pv[u], wa[u]);
+          }
         }
       }
     }
@@ -510,12 +549,21 @@ __global__ __launch_bounds__(NT) void k_passB(const InstDesc* __restrict__ desc,
     }
   }
   stream_fence();
-  double gp = 0.0;
+  if constexpr (FLUSH) {   // w += sum alpha p over the pending pairs
 #pragma unroll
-  for (int u = 0; u < PASS_U; ++u) {
-    if (ok[u]) {
-      gst(X, oP + (uint32_t)ns * vs + e0 + (uint32_t)u * NT, acc[u]);
-      gp += vdot(gv[u], acc[u]);
+    for (int u = 0; u < PASS_U; ++u) {
+      const uint32_t e = e0 + (uint32_t)u * NT;
+      if (ok[u]) gst(X, ow + e, vaxpy(T(1), wa[u], gld(X, ow + e)));
+    }
+  }
+  double gp = 0.0;
+  if (dir) {
+#pragma unroll
+    for (int u = 0; u < PASS_U; ++u) {
+      if (ok[u]) {
+        gst(X, oP + (uint32_t)ns * vs + e0 + (uint32_t)u * NT, acc[u]);
+        gp += vdot(gv[u], acc[u]);
+      }
     }
   }
   {
@@ -542,33 +590,47 @@ __global__ __launch_bounds__(256) void k_postB(const InstDesc* __restrict__ desc
   __shared__ double part4[4][NDOT];
   reduce_columns(D.partA, D.nchunk, NDOT, 2 * M + 2, sums, part4);
   if (threadIdx.x != 0) return;
-  const int nh = S.nhist, head = S.head, ns = S.newslot;
-  S.pending = 0;
+  const int nh = S.nhist, head = S.head, ns = S.newslot, dir = S.dirB;
   S.doB = 0;
+  S.pending = 0;
+  if (S.flushB) S.npend = 0;
+  int sl[M];
+  for (int j = 0; j < M; ++j) sl[j] = slot_of(head, j, M);
   // the measured dots of the current gradient replace the one-step updates
   for (int j = 0; j < nh; ++j) {
-    const int sj = slot_of(head, j, M);
-    S.gP[sj] = sums[j];
-    S.gD[sj] = sums[M + j];
+    S.gP[sl[j]] = sums[j];
+    S.gD[sl[j]] = sums[M + j];
   }
-  const double gg = sums[2 * M], gp = sums[2 * M + 1];
+  const double gg = sums[2 * M], gp = dir ? sums[2 * M + 1] : 0.0;
   S.gg = gg;
-  S.gdotp = gp;
+  if (dir) S.gdotp = gp;
   const double g0 = S.g0norm;
   const double rel = g0 > 0.0 ? sqrt(gg) / g0 : 0.0;
   int next = CM_HV, status = ST_RUNNING;
-  if (!isfinite(gg) || !isfinite(gp)) {
-    status = 2;
-  } else if (rel <= D.tol) {
-    next = CM_GRAD;                 // confirm with the exact gradient
-  } else if (S.iter >= D.maxIter) {
-    status = 1;
-  } else if (D.dchi2Tol > 0.0 && S.iter > 0 && fabs(S.dchi2) < D.dchi2Tol) {
-    status = 0;
-  } else if (!(gp < 0.0)) {
-    next = CM_GRAD;                 // not a descent direction (round-off): refresh
-  } else if (D.refreshEvery > 0 && S.iter - S.lastGradIter >= D.refreshEvery) {
-    next = CM_GRAD;
+  if (S.after != 0) {   // a flush-only iteration carrying an earlier decision
+    if (S.after == 1) next = CM_GRAD;
+    else status = S.after - 2;
+    S.after = 0;
+  } else {
+    if (!isfinite(gg) || !isfinite(gp)) {
+      status = 2;
+    } else if (rel <= D.tol) {
+      next = CM_GRAD;                 // confirm with the exact gradient
+    } else if (S.iter >= D.maxIter) {
+      status = 1;
+    } else if (D.dchi2Tol > 0.0 && S.iter > 0 && fabs(S.dchi2) < D.dchi2Tol) {
+      status = 0;
+    } else if (!(gp < 0.0)) {
+      next = CM_GRAD;                 // not a descent direction (round-off): refresh
+    } else if (D.refreshEvery > 0 && S.iter - S.lastGradIter >= D.refreshEvery) {
+      next = CM_GRAD;
+    }
+    // a refresh or a stop needs the current iterate in w: apply the pending steps first
+    if (S.npend > 0 && (next == CM_GRAD || status == 0 || status == 1)) {
+      S.after = next == CM_GRAD ? 1 : 2 + status;
+      next = CM_FLUSH;
+      status = ST_RUNNING;
+    }
   }
   if (status != ST_RUNNING) {
     S.status = status;
@@ -581,22 +643,27 @@ __global__ __launch_bounds__(256) void k_postB(const InstDesc* __restrict__ desc
   if (next == CM_HV) {
     // p . Dp_j of the new direction from its coefficients: p = sum c b, b in {p_i, Dp_i, g}
     for (int j = 0; j < nh; ++j) {
-      const int sj = slot_of(head, j, M);
+      const int sj = sl[j];
       double v = S.coef[2 * MMAX] * S.gD[sj];
       for (int t = 0; t < nh; ++t) {
-        const int st2 = slot_of(head, t, M);
+        const int st2 = sl[t];
         v += S.coef[st2] * S.PD[st2][sj] + S.coef[MMAX + st2] * S.DD[st2][sj];
       }
       S.pkD[sj] = v;
       if (sj != ns) mask |= 1u << sj;
     }
     add_chain_bytes(S, D, CM_HV, 1 + __popc(mask));
+    make_job(jobs[i], D, CM_HV, ns, mask);
   } else {
-    // the direction just formed overwrote slot ns: if that slot held the oldest pair, drop it
-    if (nh == M) S.nhist = M - 1;
-    add_chain_bytes(S, D, CM_GRAD, 0);
+    // a direction just formed overwrote slot ns: if that slot held the oldest pair, drop it
+    if (dir && nh == M) S.nhist = M - 1;
+    if (next == CM_GRAD) {
+      add_chain_bytes(S, D, CM_GRAD, 0);
+      make_job(jobs[i], D, CM_GRAD, ns, 0u);
+    } else {
+      jobs[i].mode = CM_NONE;   // flush-only iteration: no transform
+    }
   }
-  make_job(jobs[i], D, next, ns, mask);
   S.chainMode = next;
   D.statusOut[0] = ST_RUNNING;
 }
