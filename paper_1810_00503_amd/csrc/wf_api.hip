@@ -31,7 +31,7 @@ constexpr int kMaxChunk = 256;
 // offset modulo a large power of two.
 constexpr size_t kVecPadBytes = 4096 + 256;
 
-const char* kKindNames[KK_COUNT] = {"colinv", "row", "colfwd", "passA", "passB", "post", "coef", "misc"};
+const char* kKindNames[KK_COUNT] = {"colinv", "row", "colfwd", "passA", "passB", "post", "coef", "misc", "passB_flush"};
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
@@ -624,6 +624,9 @@ int solve_core(wf_ctx* ctx, const wf_problem* probs, int B, const wf_lbfgs_opts&
         Timed t(ctx, KK_PASSB);
         HIPCHK(lbfgs_launch(dt, m, LB_PASSB, dim3(k.nchunk, cnt), ddesc + k.first, dst + k.first, djobs + k.first, cnt,
                             ctx->cs));
+      }
+      {
+        Timed t(ctx, KK_PASSBF);
         HIPCHK(lbfgs_launch(dt, m, LB_PASSBF, dim3(k.nchunk, cnt), ddesc + k.first, dst + k.first, djobs + k.first,
                             cnt, ctx->cs));
       }
@@ -681,6 +684,7 @@ int solve_core(wf_ctx* ctx, const wf_problem* probs, int B, const wf_lbfgs_opts&
         ctx->launches[KK_PASSA] += K;
         ctx->launches[KK_COEF] += K;
         ctx->launches[KK_PASSB] += K;
+        ctx->launches[KK_PASSBF] += K;
       }
     } else {
       for (int r = 0; r < K; ++r) {

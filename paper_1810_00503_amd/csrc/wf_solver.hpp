@@ -287,7 +287,7 @@ __global__ __launch_bounds__(256) void k_coef(const InstDesc* __restrict__ desc,
       S.dirB = 0;
       S.flushB = 1;
       S.npendB = S.npend;
-      S.bytes[KK_PASSB] += D.vbytes * (2.0 * S.nhist + 1.0 + 2.0);
+      S.bytes[KK_PASSBF] += D.vbytes * (2.0 * S.nhist + 1.0 + 2.0);
     }
     return;
   }
@@ -446,7 +446,7 @@ __global__ __launch_bounds__(256) void k_coef(const InstDesc* __restrict__ desc,
   // bring w up to date in this pass B when the direction would overwrite a pending pair
   S.flushB = (nh == M && S.npend == M) ? 1 : 0;
   S.npendB = S.npend;
-  S.bytes[KK_PASSB] += D.vbytes * (2.0 * nh + 2.0 + (S.pending ? 1.0 : 0.0) + (S.flushB ? 2.0 : 0.0));
+  S.bytes[S.flushB ? KK_PASSBF : KK_PASSB] += D.vbytes * (2.0 * nh + 2.0 + (S.pending ? 1.0 : 0.0) + (S.flushB ? 2.0 : 0.0));
 }
 
 // ------------------------------------------------------------------------ pass B

@@ -37,7 +37,8 @@ def test_binding_matches_exports():
     names = _declared()
     assert sorted(_lib.EXPORTS) == names
     lib = _lib.load()
-    assert lib.wf_kernel_kinds() == 8
+    assert lib.wf_kernel_kinds() == 9
+    assert lib.wf_kernel_kind_name(8) == b"passB_flush"
     assert lib.wf_kernel_kind_name(3) == b"passA"
     o = _lib.WfLbfgsOpts()
     lib.wf_lbfgs_default(ctypes.byref(o))
