@@ -614,16 +614,17 @@ __global__ __launch_bounds__(NT) void k_colinvr(const Job* __restrict__ jobs, co
   }
 }
 
-// Persistent: work-group w takes tiles t = w, w + G, ... (G = gridDim.x) of the flattened
-// (instance, component, row tile) list and loads the next tile's input into registers while
-// it transforms the current one.
+// One tile (RB rows of one component) per work-group: blockIdx.x = component * (N / RB) + row
+// tile, blockIdx.y = instance.
 template <int N, int C>
-__global__ __launch_bounds__(NT) void k_rowr(const Job* __restrict__ jobs, const cpx<float>* __restrict__ twg,
-                                             int batch) {
+__global__ __launch_bounds__(NT) void k_rowr(const Job* __restrict__ jobs, const cpx<float>* __restrict__ twg) {
   using T = float;
+  const Job& jb = jobs[blockIdx.y];
+  const int mode = jb.mode;
+  if (mode == CM_NONE || mode == CM_SIM) return;
   constexpr int H = N / 2, E = rowr_e(N), RB = rowr_rb(N), NE = RB * H, KS = NE / NT;
   static_assert(RB % RB_MIN == 0 && N % RB == 0 && NE % NT == 0, "row tile");
-  constexpr int TPC = N / RB, TPI = C * TPC;   // tiles per component and per instance
+  constexpr int TPC = N / RB;   // tiles per component
   constexpr int NST = rs_nst(H, E);
   constexpr int PQI = rs_radix(H, E, false, 0), PQF = rs_radix(H, E, true, 0);
   constexpr int SBIO = rowr_io_stride(H), SBXI = rowr_x_stride(H, E, false), SBXF = rowr_x_stride(H, E, true);
@@ -632,129 +633,103 @@ __global__ __launch_bounds__(NT) void k_rowr(const Job* __restrict__ jobs, const
   cpx<T>* stI = data + RB * rowr_data_stride(H, E);
   cpx<T>* stF = stI + H;
   __shared__ double red[NT / 64];
-  const int tid = threadIdx.x;
-  const int total = batch * TPI, G = gridDim.x;
+  const uint32_t tid = threadIdx.x;
+  const int c = blockIdx.x / TPC, tile = blockIdx.x % TPC, y0 = tile * RB;
   {
     const cpx<T>* gI = twg + tw_row_off(N, E, false);
     const cpx<T>* gF = twg + tw_row_off(N, E, true);
-    for (int i = tid; i < H; i += NT) {
-      stI[i] = gI[i];
-      stF[i] = gF[i];
+    for (uint32_t i = tid; i < H; i += NT) {
+      stI[i] = gld(gI, i);
+      stF[i] = gld(gF, i);
     }
   }
   auto lio = [](uint32_t b, uint32_t i) { return b * SBIO + i; };
   auto lxi = [](uint32_t b, uint32_t i) { return b * SBXI + i + i / PQI; };
   auto lxf = [](uint32_t b, uint32_t i) { return b * SBXF + i + i / PQF; };
-  auto staged = [](int mode) { return mode != CM_NONE && mode != CM_SIM && mode != CM_ADJ && mode != CM_ADJ_GRAD; };
-  // this thread's staging elements e = tid + k NT of a tile: column block qq, offset w2
-  auto tile_ptr = [&](const Job& jb, int t) {
-    const int r = t % TPI;
-    return reinterpret_cast<cpx<T>*>(jb.y) + fidx(N, r / TPC, (r % TPC) * RB, 0);
-  };
-  cpx<T> pf[KS];
-  auto prefetch = [&](int t, uint32_t tid) {
-    if (t >= total) return;
-    const Job& jn = jobs[t / TPI];
-    if (!staged(jn.mode)) return;
-    const cpx<T>* Yn = tile_ptr(jn, t);
+  const bool adjIn = (mode == CM_ADJ || mode == CM_ADJ_GRAD);
+  cpx<T>* Y = reinterpret_cast<cpx<T>*>(jb.y) + fidx(N, c, y0, 0);   // column block 0 of this tile
+  cpx<T> v[E];
+  double acc = 0.0;
+  if (!adjIn) {
+    // staging: the tile's RB x TB runs of every column block, coalesced
+    cpx<T> pf[KS];
     sfor<0, KS>([&](auto K) {
       constexpr int k = decltype(K)::value;
-      const uint32_t e = tid + k * NT, qq = e / (RB * TB), w2 = e % (RB * TB);
-      pf[k] = gld(Yn, qq * N * TB + w2);
+      const uint32_t e = tid + k * NT;
+      pf[k] = gld(Y, (e / (RB * TB)) * N * TB + e % (RB * TB));
     });
-  };
-  prefetch(blockIdx.x, tid);
-  for (int t = blockIdx.x; t < total; t += G) {
-    const uint32_t tid = opaque_tid();
-    const Job& jb = jobs[t / TPI];
-    const int mode = jb.mode;
-    if (mode == CM_NONE || mode == CM_SIM) {
-      prefetch(t + G, tid);
-      continue;
-    }
-    const int c = (t % TPI) / TPC, tile = (t % TPI) % TPC, y0 = tile * RB;
-    const bool adjIn = (mode == CM_ADJ || mode == CM_ADJ_GRAD);
-    cpx<T>* Y = tile_ptr(jb, t);
-    cpx<T> v[E];
-    double acc = 0.0;
-    __syncthreads();   // the previous tile's readers of data are done
-    if (!adjIn) {
-      sfor<0, KS>([&](auto K) {
-        constexpr int k = decltype(K)::value;
-        const uint32_t e = tid + k * NT, w2 = e % (RB * TB);
-        data[lio(w2 / TB, (e / (RB * TB)) * TB + w2 % TB)] = pf[k];
-      });
-    }
-    prefetch(t + G, tid);
-    if (!adjIn) {
-      __syncthreads();
-      // complex-to-real pre-processing into the first stage's registers (see k_row)
-      constexpr int R0 = PQI, NQ0 = H / R0, K0 = E / R0;
-      sfor<0, K0>([&](auto KK) {
-        constexpr int kk = decltype(KK)::value;
-        const uint32_t u = tid + kk * NT, b = u / NQ0, j = u % NQ0;
-        sfor<0, R0>([&](auto RR) {
-          constexpr int r = decltype(RR)::value;
-          const uint32_t k = j + r * NQ0;
-          const cpx<T> X = data[lio(b, k)];
-          cpx<T> z;
-          if (k == 0) {
-            z = mk(X.x, X.x);
-          } else {
-            const cpx<T> Xm = conj(data[lio(b, H - k)]);
-            const cpx<T> tw = mulc(sub(X, Xm), gld(twg, k));
-            const cpx<T> sm = add(X, Xm);
-            z = mk(sm.x - tw.y, sm.y + tw.x);
-          }
-          v[kk * R0 + r] = z;
-        });
-      });
-      rs_fft<T, H, RB, E, true, true, false>(v, data, stI, lxi, tid);
-    }
-    {
-      // pixel step in the inverse's last-stage layout, which is the forward's first-stage one
-      constexpr int RL = rs_radix(H, E, false, NST - 1), NQL = H / RL, KL = E / RL;
-      sfor<0, KL>([&](auto KK) {
-        constexpr int kk = decltype(KK)::value;
-        const uint32_t u = tid + kk * NT, b = u / NQL, j = u % NQL;
-        sfor<0, RL>([&](auto RR) {
-          constexpr int r = decltype(RR)::value;
-          row_pixel<T, N, C, false>(jb, mode, adjIn, c, y0 + b, j + r * NQL, v[kk * RL + r], acc);
-        });
-      });
-    }
-    if (mode == CM_FWD) continue;
-    rs_fft<T, H, RB, E, true, false, true>(v, data, stF, lxf, tid);
-    {
-      // outputs are in the inverse's first-stage layout: to LDS in natural order for the
-      // real-to-complex untangle, which pairs k with H - k
-      constexpr int R0 = PQI, NQ0 = H / R0, K0 = E / R0;
-      __syncthreads();
-      sfor<0, K0>([&](auto KK) {
-        constexpr int kk = decltype(KK)::value;
-        const uint32_t u = tid + kk * NT, b = u / NQ0, j = u % NQ0;
-        sfor<0, R0>([&](auto RR) {
-          constexpr int r = decltype(RR)::value;
-          data[lio(b, j + r * NQ0)] = v[kk * R0 + r];
-        });
-      });
-      __syncthreads();
-    }
     sfor<0, KS>([&](auto K) {
-      constexpr int kq = decltype(K)::value;
-      const uint32_t e = tid + kq * NT, qq = e / (RB * TB), w2 = e % (RB * TB);
-      const uint32_t b = w2 / TB, k = qq * TB + w2 % TB;
-      const cpx<T> Zk = data[lio(b, k)];
-      const cpx<T> Zm = conj(data[lio(b, k == 0 ? 0 : H - k)]);
-      const cpx<T> A = add(Zk, Zm);
-      const cpx<T> tw = mul(gld(twg, k), sub(Zk, Zm));
-      gst(Y, qq * N * TB + w2, mk(T(0.5) * (A.x + tw.y), T(0.5) * (A.y - tw.x)));
+      constexpr int k = decltype(K)::value;
+      const uint32_t e = tid + k * NT, w2 = e % (RB * TB);
+      data[lio(w2 / TB, (e / (RB * TB)) * TB + w2 % TB)] = pf[k];
     });
-    if (mode == CM_GRAD || mode == CM_RAW_GRAD) {
-      const double tsum = block_sum(acc, red);
-      constexpr int PR = RB / RB_MIN;
-      if (tid < PR) jb.part[PK_RES * jb.pstride + c * (N / RB_MIN) + tile * PR + tid] = tid == 0 ? tsum : 0.0;
-    }
+    __syncthreads();
+    // complex-to-real pre-processing into the first stage's registers (see k_row)
+    constexpr int R0 = PQI, NQ0 = H / R0, K0 = E / R0;
+    sfor<0, K0>([&](auto KK) {
+      constexpr int kk = decltype(KK)::value;
+      const uint32_t u = tid + kk * NT, b = u / NQ0, j = u % NQ0;
+      sfor<0, R0>([&](auto RR) {
+        constexpr int r = decltype(RR)::value;
+        const uint32_t k = j + r * NQ0;
+        const cpx<T> X = data[lio(b, k)];
+        cpx<T> z;
+        if (k == 0) {
+          z = mk(X.x, X.x);
+        } else {
+          const cpx<T> Xm = conj(data[lio(b, H - k)]);
+          const cpx<T> tw = mulc(sub(X, Xm), gld(twg, k));
+          const cpx<T> sm = add(X, Xm);
+          z = mk(sm.x - tw.y, sm.y + tw.x);
+        }
+        v[kk * R0 + r] = z;
+      });
+    });
+    rs_fft<T, H, RB, E, true, true, false>(v, data, stI, lxi, tid);
+  }
+  {
+    // pixel step in the inverse's last-stage layout, which is the forward's first-stage one
+    constexpr int RL = rs_radix(H, E, false, NST - 1), NQL = H / RL, KL = E / RL;
+    sfor<0, KL>([&](auto KK) {
+      constexpr int kk = decltype(KK)::value;
+      const uint32_t u = tid + kk * NT, b = u / NQL, j = u % NQL;
+      sfor<0, RL>([&](auto RR) {
+        constexpr int r = decltype(RR)::value;
+        row_pixel<T, N, C, false>(jb, mode, adjIn, c, y0 + b, j + r * NQL, v[kk * RL + r], acc);
+      });
+    });
+  }
+  if (mode == CM_FWD) return;
+  rs_fft<T, H, RB, E, true, false, true>(v, data, stF, lxf, tid);
+  {
+    // outputs are in the inverse's first-stage layout: to LDS in natural order for the
+    // real-to-complex untangle, which pairs k with H - k
+    constexpr int R0 = PQI, NQ0 = H / R0, K0 = E / R0;
+    __syncthreads();
+    sfor<0, K0>([&](auto KK) {
+      constexpr int kk = decltype(KK)::value;
+      const uint32_t u = tid + kk * NT, b = u / NQ0, j = u % NQ0;
+      sfor<0, R0>([&](auto RR) {
+        constexpr int r = decltype(RR)::value;
+        data[lio(b, j + r * NQ0)] = v[kk * R0 + r];
+      });
+    });
+    __syncthreads();
+  }
+  sfor<0, KS>([&](auto K) {
+    constexpr int kq = decltype(K)::value;
+    const uint32_t e = tid + kq * NT, qq = e / (RB * TB), w2 = e % (RB * TB);
+    const uint32_t b = w2 / TB, k = qq * TB + w2 % TB;
+    const cpx<T> Zk = data[lio(b, k)];
+    const cpx<T> Zm = conj(data[lio(b, k == 0 ? 0 : H - k)]);
+    const cpx<T> A = add(Zk, Zm);
+    const cpx<T> tw = mul(gld(twg, k), sub(Zk, Zm));
+    gst(Y, qq * N * TB + w2, mk(T(0.5) * (A.x + tw.y), T(0.5) * (A.y - tw.x)));
+  });
+  if (mode == CM_GRAD || mode == CM_RAW_GRAD) {
+    const double tsum = block_sum(acc, red);
+    constexpr int PR = RB / RB_MIN;
+    if (tid < PR) jb.part[PK_RES * jb.pstride + c * (N / RB_MIN) + tile * PR + tid] = tid == 0 ? tsum : 0.0;
   }
 }
 

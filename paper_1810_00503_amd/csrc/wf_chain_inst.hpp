@@ -28,18 +28,6 @@ static hipError_t prep_row() {
                              (int)lds_rowpass<T, N, C, RBV>());
 }
 
-// work-groups of a persistent register-staged row pass: 6 per CU of the device
-static int rowr_grid() {
-  static int g = 0;
-  if (g == 0) {
-    int dev = 0, cus = 0;
-    if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
-      cus = 256;
-    g = 6 * cus;
-  }
-  return g;
-}
-
 // register-staged passes: float32, power-of-two n >= 128
 template <typename T, int N>
 constexpr bool reg_ok() {
@@ -127,10 +115,7 @@ static hipError_t launch_t(int which, const ChainCfg& cfg, const Job* jobs, int 
   if constexpr (reg_ok<T, N>()) {
     const cpx<float>* tf = reinterpret_cast<const cpx<float>*>(tw);
     if (which == CH_ROW && (cfg.reg & 1)) {
-      // persistent tiles: about as many work-groups as fit on the device at once
-      const int total = batch * C * (N / rowr_rb(N));
-      const int G = std::min(total, rowr_grid());
-      k_rowr<N, C><<<dim3(G), dim3(NT), lds_rowr<N>(), st>>>(jobs, tf, batch);
+      k_rowr<N, C><<<dim3(C * (N / rowr_rb(N)), batch), dim3(NT), lds_rowr<N>(), st>>>(jobs, tf);
       return hipGetLastError();
     }
     if ((which == CH_COLINV && (cfg.reg & 2)) || (which == CH_COLFWD && (cfg.reg & 4))) {

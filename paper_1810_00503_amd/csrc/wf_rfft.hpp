@@ -204,14 +204,6 @@ __device__ __forceinline__ void rs_fft(cpx<T> (&v)[E], cpx<T>* __restrict__ lds,
   });
 }
 
-// the thread index through an opaque move: index arithmetic derived from it inside a loop
-// is not hoisted out of the loop (which would keep every address of every tile in registers)
-__device__ __forceinline__ uint32_t opaque_tid() {
-  uint32_t t;
-  asm volatile("v_mov_b32 %0, %1" : "=v"(t) : "v"((uint32_t)threadIdx.x));
-  return t;
-}
-
 // value of the lane whose index differs in bit 1 (partner component of a column pair);
 // every lane of the wave must be active
 __device__ __forceinline__ float lane_xor2(float x) {
