@@ -272,6 +272,16 @@ def main():
             "avg_launch_us": round(1e3 * kd["ms"] / max(kd["launches"], 1), 2),
             "bytes_per_launch": kd["bytes"] / max(kd["launches"], 1)}
 
+    # the fused transform chain of one gradient / curvature product (column inverse, row pass with
+    # the mask and noise weights, column forward with the prior scale and the solver's dots)
+    chain_k = ("colinv", "row", "colfwd")
+    cb = sum(ks[k]["bytes"] for k in chain_k)
+    cm = sum(ks[k]["ms"] for k in chain_k)
+    ca = cb / (cm * 1e-3) / 1e9 if cm > 0 else 0.0
+    roof_chain = {"bound": "hbm", "kernels": "+".join(chain_k), "achieved": round(ca, 1), "peak": HBM_PEAK_GBS,
+                  "unit": "GB/s", "frac": round(ca / HBM_PEAK_GBS, 4), "ms_per_step": round(cm, 3),
+                  "bytes_per_step": cb}
+
     # measured copy ceiling (context for the roofline): device-to-device copy of 2 GiB
     src = torch.empty(512 * 1024 * 1024, dtype=torch.float32, device=dev)
     dst = torch.empty_like(src)
@@ -298,6 +308,7 @@ def main():
                    "n": args.n, "ncomp": 2, "batch": nsolve, "nsim": args.nsim, "nbands": nb,
                    "rel_grad_tol": args.tol, "m": args.m},
         "roofline": roof,
+        "roofline_gradient_chain": roof_chain,
         "cpu_baseline": cpu,
         "batched_solve_only_solves_per_s": round(len(sims) / t_batch, 2),
         "plain_solves_per_s": None if plain is None else round(plain, 2),

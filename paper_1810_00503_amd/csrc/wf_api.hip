@@ -31,7 +31,8 @@ constexpr int kMaxChunk = 256;
 // offset modulo a large power of two.
 constexpr size_t kVecPadBytes = 4096 + 256;
 
-const char* kKindNames[KK_COUNT] = {"colinv", "row", "colfwd", "passA", "passB", "post", "coef", "misc", "passB_flush"};
+const char* kKindNames[KK_COUNT] = {"colinv", "row", "colfwd", "passA", "passB", "post", "coef", "misc", "passB_flush",
+                                     "simulate"};
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
@@ -250,7 +251,7 @@ ChainCfg op_cfg(const wf_ctx* ctx, int dtype, int n, int c) {
 
 hipError_t chain(wf_ctx* ctx, int dtype, int n, int c, int which, const Job* jobs, int batch, const void* tw,
                  const ChainCfg* cfgp = nullptr) {
-  Timed t(ctx, which == CH_COLINV ? KK_COLINV : (which == CH_ROW ? KK_ROW : KK_COLFWD));
+  Timed t(ctx, (cfgp && cfgp->sim) ? KK_SIM : (which == CH_COLINV ? KK_COLINV : (which == CH_ROW ? KK_ROW : KK_COLFWD)));
   const ChainCfg cfg = cfgp ? *cfgp : op_cfg(ctx, dtype, n, c);
   return chain_launch(dtype, n, c, which, cfg, jobs, batch, tw, ctx->cs);
 }

@@ -265,61 +265,89 @@ __device__ __forceinline__ void reduce_columns(const double* part, int nblk, int
   __syncthreads();
 }
 
-// sum over the `nb` blocks of chain partial kind k (a row of stride pstride)
-__device__ __forceinline__ double chain_sum(const InstDesc& D, int kind, int nb) {
-  double a = 0.0;
-  for (int b = 0; b < nb; ++b) a += D.partChain[kind * D.pstride + b];
-  return a;
+// whole-state copy between global memory and LDS by every thread of the work-group
+__device__ __forceinline__ void copy_state(LbState* dst, const LbState* src) {
+  static_assert(sizeof(LbState) % 8 == 0, "state size");
+  const uint64_t* s = reinterpret_cast<const uint64_t*>(src);
+  uint64_t* d = reinterpret_cast<uint64_t*>(dst);
+  for (int k = threadIdx.x; k < (int)(sizeof(LbState) / 8); k += blockDim.x) d[k] = s[k];
 }
 
 // ------------------------------------------------------------------------ coefficients
 // 256 threads per instance; thread 0 runs the scalar part out of LDS.
 template <int M>
+__device__ __forceinline__ void coef_scalar(const InstDesc& D, LbState& S, Job& job, int mode, const double* chs,
+                                            const double* sums, double (*sPD)[M], double (*sDD)[M], double* sal,
+                                            double* sgP, double* sgD);
+
+template <int M>
 __global__ __launch_bounds__(256) void k_coef(const InstDesc* __restrict__ desc, LbState* st, Job* jobs) {
   const int i = blockIdx.x;
-  LbState& S = st[i];
-  if (S.status != ST_RUNNING) return;
+  LbState& Sg = st[i];
+  if (Sg.status != ST_RUNNING) return;
   const InstDesc& D = desc[i];
-  const int mode = S.chainMode;
+  const int mode = Sg.chainMode;
   if (mode == CM_FLUSH) {   // no transform this iteration: pass B only brings w up to date
     if (threadIdx.x == 0) {
-      S.doB = 1;
-      S.dirB = 0;
-      S.flushB = 1;
-      S.npendB = S.npend;
-      S.bytes[KK_PASSBF] += D.vbytes * (2.0 * S.nhist + 1.0 + 2.0);
+      Sg.doB = 1;
+      Sg.dirB = 0;
+      Sg.flushB = 1;
+      Sg.npendB = Sg.npend;
+      Sg.bytes[KK_PASSBF] += D.vbytes * (2.0 * Sg.nhist + 1.0 + 2.0);
     }
     return;
   }
+  // the scalar part runs in one thread on an LDS copy of the state
+  __shared__ __align__(16) LbState S;
+  copy_state(&S, &Sg);
+  __syncthreads();
   __shared__ double sums[NDOT];
   __shared__ double part4[4][NDOT];
   __shared__ double chs[3 + MMAX + 2];
   __shared__ double sPD[M][M], sDD[M][M], sal[M], sgP[M], sgD[M];
   const int ncol = (D.n / 2) / TB, nrow = D.c * D.n / RB_MIN;
   if (mode == CM_GRAD) reduce_columns(D.partA, D.nchunk, NDOT, 2 * M + 1, sums, part4);
-  // chain partial sums (fixed order, one thread per kind)
-  if (threadIdx.x < 3 + M + 2) {
-    const int t = threadIdx.x;
-    double a = 0.0;
-    if (t < 3 + M) {
-      if (mode == CM_HV && (t < 3 || t - 3 < M)) a = chain_sum(D, PK_VO + t, ncol);
-    } else if (mode == CM_GRAD) {
-      a = (t == 3 + M) ? chain_sum(D, PK_PRIOR, ncol) : chain_sum(D, PK_RES, nrow);
+  // chain partial sums: one wave per kind, fixed-order lane sums and a fixed shuffle tree
+  {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    for (int t = wv; t < 3 + M + 2; t += (int)(blockDim.x >> 6)) {
+      int kind = -1, nb = 0;
+      if (t < 3 + M) {
+        if (mode == CM_HV) {
+          kind = PK_VO + t;
+          nb = ncol;
+        }
+      } else if (mode == CM_GRAD) {
+        kind = (t == 3 + M) ? PK_PRIOR : PK_RES;
+        nb = (t == 3 + M) ? ncol : nrow;
+      }
+      double a = 0.0;
+      if (kind >= 0)
+        for (int b = lane; b < nb; b += 64) a += D.partChain[kind * D.pstride + b];
+      a = wave_sum(a);
+      if (lane == 0) chs[t] = a;
     }
-    chs[t] = a;
   }
   for (int t = threadIdx.x; t < M * M; t += blockDim.x) {
     sPD[t / M][t % M] = S.PD[t / M][t % M];
     sDD[t / M][t % M] = S.DD[t / M][t % M];
   }
+  __syncthreads();
   for (int t = threadIdx.x; t < M; t += blockDim.x) {
     sal[t] = S.alpha[t];
     sgP[t] = S.gP[t];
     sgD[t] = S.gD[t];
   }
   __syncthreads();
-  if (threadIdx.x != 0) return;
+  if (threadIdx.x == 0) coef_scalar<M>(D, S, jobs[i], mode, chs, sums, sPD, sDD, sal, sgP, sgD);
+  __syncthreads();
+  copy_state(&Sg, &S);
+}
 
+template <int M>
+__device__ __forceinline__ void coef_scalar(const InstDesc& D, LbState& S, Job& job, int mode, const double* chs,
+                                            const double* sums, double (*sPD)[M], double (*sDD)[M], double* sal,
+                                            double* sgP, double* sgD) {
   int status = ST_RUNNING;
   int nh = S.nhist, head = S.head;
   if (mode == CM_HV) {
@@ -327,7 +355,7 @@ __global__ __launch_bounds__(256) void k_coef(const InstDesc* __restrict__ desc,
     if (!(pDp > 0.0) || !isfinite(pDp) || !isfinite(DpDp)) {
       S.status = 2;
       D.statusOut[0] = 2;
-      jobs[i].mode = CM_NONE;
+      job.mode = CM_NONE;
       S.chainMode = CM_NONE;
       S.doB = 0;
       return;
@@ -402,7 +430,7 @@ __global__ __launch_bounds__(256) void k_coef(const InstDesc* __restrict__ desc,
   if (status != ST_RUNNING) {
     S.status = status;
     D.statusOut[0] = status;
-    jobs[i].mode = CM_NONE;
+    job.mode = CM_NONE;
     S.chainMode = CM_NONE;
     S.doB = 0;
     return;
@@ -581,15 +609,27 @@ __global__ __launch_bounds__(NT) void k_passB(const InstDesc* __restrict__ desc,
 
 // ------------------------------------------------------------------------ post B
 template <int M>
+__device__ __forceinline__ void postB_scalar(const InstDesc& D, LbState& S, Job& job, const double* sums);
+
+template <int M>
 __global__ __launch_bounds__(256) void k_postB(const InstDesc* __restrict__ desc, LbState* st, Job* jobs) {
   const int i = blockIdx.x;
-  LbState& S = st[i];
-  if (S.status != ST_RUNNING || !S.doB) return;
+  LbState& Sg = st[i];
+  if (Sg.status != ST_RUNNING || !Sg.doB) return;
   const InstDesc& D = desc[i];
+  // the scalar part runs in one thread on an LDS copy of the state
+  __shared__ __align__(16) LbState S;
+  copy_state(&S, &Sg);
   __shared__ double sums[NDOT];
   __shared__ double part4[4][NDOT];
-  reduce_columns(D.partA, D.nchunk, NDOT, 2 * M + 2, sums, part4);
-  if (threadIdx.x != 0) return;
+  reduce_columns(D.partA, D.nchunk, NDOT, 2 * M + 2, sums, part4);   // (synchronises)
+  if (threadIdx.x == 0) postB_scalar<M>(D, S, jobs[i], sums);
+  __syncthreads();
+  copy_state(&Sg, &S);
+}
+
+template <int M>
+__device__ __forceinline__ void postB_scalar(const InstDesc& D, LbState& S, Job& job, const double* sums) {
   const int nh = S.nhist, head = S.head, ns = S.newslot, dir = S.dirB;
   S.doB = 0;
   S.pending = 0;
@@ -635,7 +675,7 @@ __global__ __launch_bounds__(256) void k_postB(const InstDesc* __restrict__ desc
   if (status != ST_RUNNING) {
     S.status = status;
     D.statusOut[0] = status;
-    jobs[i].mode = CM_NONE;
+    job.mode = CM_NONE;
     S.chainMode = CM_NONE;
     return;
   }
@@ -653,15 +693,15 @@ __global__ __launch_bounds__(256) void k_postB(const InstDesc* __restrict__ desc
       if (sj != ns) mask |= 1u << sj;
     }
     add_chain_bytes(S, D, CM_HV, 1 + __popc(mask));
-    make_job(jobs[i], D, CM_HV, ns, mask);
+    make_job(job, D, CM_HV, ns, mask);
   } else {
     // a direction just formed overwrote slot ns: if that slot held the oldest pair, drop it
     if (dir && nh == M) S.nhist = M - 1;
     if (next == CM_GRAD) {
       add_chain_bytes(S, D, CM_GRAD, 0);
-      make_job(jobs[i], D, CM_GRAD, ns, 0u);
+      make_job(job, D, CM_GRAD, ns, 0u);
     } else {
-      jobs[i].mode = CM_NONE;   // flush-only iteration: no transform
+      job.mode = CM_NONE;   // flush-only iteration: no transform
     }
   }
   S.chainMode = next;
