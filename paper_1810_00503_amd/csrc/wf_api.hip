@@ -342,8 +342,7 @@ struct Klass {
 };
 
 struct SolveOut {
-  std::vector<void*> w;         // per user index: whitened solution (chunk-interleaved view)
-  std::vector<int64_t> vcs, vcstr;   // its view
+  std::vector<void*> w;         // per user index: whitened solution
   std::vector<void*> y;         // per user index: intermediate buffer
   std::vector<PriorTab> prior;  // per user index
   std::vector<LbState> st;      // per user index
@@ -391,7 +390,6 @@ int tune_chain(wf_ctx* ctx, Klass& k, const std::vector<InstDesc>& hd, Job* djob
     jb.aTab = D.aTab;
     jb.part = D.partChain;
     jb.pstride = D.pstride;
-    jb.vcs = jb.vcstr = D.L;
     // the solver's curvature products also read g and the m - 1 other kept Dp_j
     jb.gvec = (char*)D.X + vb;
     jb.dpBase = (char*)D.X + (2 + (size_t)m) * vb;
@@ -533,8 +531,6 @@ int solve_core(wf_ctx* ctx, const wf_problem* probs, int B, const wf_lbfgs_opts&
   }
   std::vector<InstDesc> hd(B);
   out.w.assign(B, nullptr);
-  out.vcs.assign(B, 0);
-  out.vcstr.assign(B, 0);
   out.y.assign(B, nullptr);
   out.prior.assign(B, PriorTab());
   out.order.assign(B, 0);
@@ -571,8 +567,6 @@ int solve_core(wf_ctx* ctx, const wf_problem* probs, int B, const wf_lbfgs_opts&
       D.dchi2Tol = o.dchi2_tol;
       D.vbytes = (double)k.L * eb;
       out.w[ui] = D.X;
-      out.vcs[ui] = k.L;
-      out.vcstr[ui] = k.L;
       out.y[ui] = D.y;
       out.prior[ui] = ptabs[pidx[ui]];
       out.order[ui] = gi;
@@ -743,8 +737,6 @@ int maps_from_solution(wf_ctx* ctx, const wf_problem* probs, int B, const SolveO
       jb.mode = CM_FWD;
       jb.boost_band = -1;
       jb.vin = so.w[mem[j]];
-      jb.vcs = so.vcs[mem[j]];
-      jb.vcstr = so.vcstr[mem[j]];
       jb.y = so.y[mem[j]];
       jb.sIn = so.prior[mem[j]].sq;
       jb.xout = map_out[mem[j]];
@@ -814,8 +806,6 @@ int band_E_solved(wf_ctx* ctx, const wf_problem* probs, int B, const SolveOut& s
     hj[i].part = part + (size_t)i * nblk * nb;
     hj[i].E = dE + (size_t)i * nb;
     hj[i].L = L;
-    hj[i].vcs = so.vcs[i];
-    hj[i].vcstr = so.vcstr[i];
     hj[i].nbands = nb;
     hj[i].raw = 0;
   }
@@ -1066,7 +1056,7 @@ int map_wf_solve(wf_ctx* ctx, const wf_problem* probs, int32_t batch, const wf_l
   // s = sqrt(S) w with partners filled, into the caller's buffers
   for (int i = 0; i < batch; ++i) {
     const wf_problem* p = &probs[i];
-    HIPCHK(pack_launch(p->dtype, p->n, p->ncomp, 1, so.w[i], 0, so.vcs[i], so.vcstr[i], so.prior[i].sq, 1, nullptr,
+    HIPCHK(pack_launch(p->dtype, p->n, p->ncomp, 1, so.w[i], 0, so.prior[i].sq, 1, nullptr,
                        s_out[i], ctx->cs));
   }
   rc = maps_from_solution(ctx, probs, batch, so, map_out);
@@ -1172,7 +1162,6 @@ int wf_forward(wf_ctx* ctx, const wf_problem* p, int32_t batch, const void* s, v
   std::vector<Job> hj(batch);
   for (int i = 0; i < batch; ++i) {
     std::memset(&hj[i], 0, sizeof(Job));
-    hj[i].vcs = hj[i].vcstr = L;
     hj[i].mode = CM_FWD;
     hj[i].boost_band = -1;
     hj[i].W = (flags & WF_MASK) ? p->w : nullptr;
@@ -1205,7 +1194,6 @@ int wf_adjoint(wf_ctx* ctx, const wf_problem* p, int32_t batch, const void* x, v
   std::vector<Job> hj(batch);
   for (int i = 0; i < batch; ++i) {
     std::memset(&hj[i], 0, sizeof(Job));
-    hj[i].vcs = hj[i].vcstr = L;
     hj[i].mode = (flags & WF_ADJ_GRAD) ? CM_ADJ_GRAD : CM_ADJ;
     hj[i].boost_band = -1;
     hj[i].W = (flags & WF_MASK) ? p->w : nullptr;
@@ -1216,7 +1204,7 @@ int wf_adjoint(wf_ctx* ctx, const wf_problem* p, int32_t batch, const void* x, v
   HIPCHK(hipMemcpyAsync(dj, hj.data(), sizeof(Job) * batch, hipMemcpyHostToDevice, ctx->cs));
   HIPCHK(chain(ctx, dt, n, c, CH_ROW, dj, batch, tw));
   HIPCHK(chain(ctx, dt, n, c, CH_COLFWD, dj, batch, tw));
-  HIPCHK(pack_launch(dt, n, c, batch, vout, L, L, L, nullptr, 0, nullptr, s, ctx->cs));
+  HIPCHK(pack_launch(dt, n, c, batch, vout, L, nullptr, 0, nullptr, s, ctx->cs));
   HIPCHK(hipStreamSynchronize(ctx->cs));
   return WF_OK;
 }
@@ -1239,7 +1227,6 @@ static int raw_chain(wf_ctx* ctx, const wf_problem* p, int batch, const void* s,
   std::vector<Job> hj(batch);
   for (int i = 0; i < batch; ++i) {
     std::memset(&hj[i], 0, sizeof(Job));
-    hj[i].vcs = hj[i].vcstr = L;
     hj[i].mode = mode;
     hj[i].boost_band = -1;
     hj[i].vin = (char*)vin + (size_t)i * L * eb;
@@ -1254,7 +1241,7 @@ static int raw_chain(wf_ctx* ctx, const wf_problem* p, int batch, const void* s,
   }
   HIPCHK(hipMemcpyAsync(dj, hj.data(), sizeof(Job) * batch, hipMemcpyHostToDevice, ctx->cs));
   for (int w = 0; w < 3; ++w) HIPCHK(chain(ctx, dt, n, c, w, dj, batch, tw));
-  if (out) HIPCHK(pack_launch(dt, n, c, batch, vout, L, L, L, nullptr, 0, nullptr, out, ctx->cs));
+  if (out) HIPCHK(pack_launch(dt, n, c, batch, vout, L, nullptr, 0, nullptr, out, ctx->cs));
   if (chi2) {
     std::vector<double> hp((size_t)PK_COUNT * pstride * batch);
     HIPCHK(hipMemcpyAsync(hp.data(), part, sizeof(double) * hp.size(), hipMemcpyDeviceToHost, ctx->cs));
@@ -1324,8 +1311,6 @@ int wf_band_E(wf_ctx* ctx, const wf_problem* p, int32_t batch, const void* s, do
     hj[i].part = bpart + (size_t)i * nblk * nb;
     hj[i].E = dE + (size_t)i * nb;
     hj[i].L = L;
-    hj[i].vcs = L;
-    hj[i].vcstr = L;
     hj[i].nbands = nb;
     hj[i].raw = 1;
   }

@@ -97,11 +97,11 @@ __device__ __forceinline__ size_t chain_lds_col(int N, int C) { return (size_t)(
 // Column-inverse input of component c at (ky, kx): scale (sqrt S, simulation amplitude),
 // liveness, prior partial (gradient modes).  Returns the value before the spin-2 rotation;
 // part/kyr tell whether (ky, kx) is a kx = 0 conjugate partner and which stored row holds its
-// free entry.  dvc: offset of the input view of this column block.  SIMK: the simulation mode
+// free entry.  SIMK: the simulation mode
 // (normals from draws or Philox, in float64) is compiled in; it costs registers, so only the
 // kernels that simulation launches use it.
 template <typename T, int N, bool SIMK>
-__device__ __forceinline__ cpx<T> colinv_in(const Job& jb, int mode, int c, int ky, int kx, int64_t dvc, bool& part,
+__device__ __forceinline__ cpx<T> colinv_in(const Job& jb, int mode, int c, int ky, int kx, bool& part,
                                             int& kyr, double& acc) {
   cpx<T> a = mk(T(0), T(0));
   part = false;
@@ -126,7 +126,7 @@ __device__ __forceinline__ cpx<T> colinv_in(const Job& jb, int mode, int c, int 
     sc = gld(sIn, src) * T(0.70710678118654752440084436210485);
     if (jb.band && jb.boost_band >= 0 && gld(jb.band, src) == jb.boost_band) sc *= T(jb.boost_factor);
   } else {
-    v = gld(reinterpret_cast<const cpx<T>*>(jb.vin), src + (uint32_t)dvc);
+    v = gld(reinterpret_cast<const cpx<T>*>(jb.vin), src);
     if (sIn) sc = gld(sIn, src);
     if (mode == CM_RAW_GRAD || mode == CM_RAW_HV) {
       const T sq = gld(reinterpret_cast<const T*>(jb.sOut), src);
@@ -214,15 +214,15 @@ __device__ __forceinline__ void row_pixel(const Job& jb, int mode, bool adjIn, i
 // transform after the inverse rotation): prior scale, added term, the v.out and out.out
 // partials; writes and returns the output.
 template <typename T, int N>
-__device__ __forceinline__ cpx<T> colfwd_val(const Job& jb, int mode, int ky, int kx, int64_t o, int64_t dvc,
+__device__ __forceinline__ cpx<T> colfwd_val(const Job& jb, int mode, int ky, int kx, int64_t o,
                                              cpx<T> t, double& avo, double& aoo) {
   const bool fr = is_free(N, ky, kx);
-  const uint32_t oi = (uint32_t)o, ov = (uint32_t)(o + dvc);
+  const uint32_t oi = (uint32_t)o;
   cpx<T> out = mk(T(0), T(0));
   if (mode == CM_HV || mode == CM_GRAD) {
     const T sq = gld(reinterpret_cast<const T*>(jb.sOut), oi);
     if (fr && sq != T(0)) {
-      const cpx<T> v = gld(reinterpret_cast<const cpx<T>*>(jb.vadd), ov);
+      const cpx<T> v = gld(reinterpret_cast<const cpx<T>*>(jb.vadd), oi);
       const T wa = jb.aTab ? gld(reinterpret_cast<const T*>(jb.aTab), oi) : T(1);
       out = mk(wa * v.x + sq * t.x, wa * v.y + sq * t.y);
       avo += (double)v.x * out.x + (double)v.y * out.y;
@@ -231,7 +231,7 @@ __device__ __forceinline__ cpx<T> colfwd_val(const Job& jb, int mode, int ky, in
   } else if (mode == CM_RAW_GRAD || mode == CM_RAW_HV) {
     const T sq = gld(reinterpret_cast<const T*>(jb.sOut), oi);
     if (fr && sq != T(0)) {
-      const cpx<T> v = gld(reinterpret_cast<const cpx<T>*>(jb.vadd), ov);
+      const cpx<T> v = gld(reinterpret_cast<const cpx<T>*>(jb.vadd), oi);
       const T is = T(1) / (sq * sq);
       out = mk(T(4) * (v.x * is + t.x), T(4) * (v.y * is + t.y));
     }
@@ -240,7 +240,7 @@ __device__ __forceinline__ cpx<T> colfwd_val(const Job& jb, int mode, int ky, in
   } else {  // CM_ADJ_GRAD
     if (fr) out = scale(t, T(2));
   }
-  gst(reinterpret_cast<cpx<T>*>(jb.vout), ov, out);
+  gst(reinterpret_cast<cpx<T>*>(jb.vout), oi, out);
   return out;
 }
 
@@ -248,17 +248,17 @@ __device__ __forceinline__ cpx<T> colfwd_val(const Job& jb, int mode, int ky, in
 // with g and with the kept Dp_j.
 template <typename T, int N>
 __device__ __forceinline__ void colfwd_out(const Job& jb, int mode, bool extras, int ky, int kx, int64_t o,
-                                           int64_t dvc, cpx<T> t, double& avo, double& aoo, double& adg,
+                                           cpx<T> t, double& avo, double& aoo, double& adg,
                                            double (&add)[MMAX]) {
-  const cpx<T> out = colfwd_val<T, N>(jb, mode, ky, kx, o, dvc, t, avo, aoo);
+  const cpx<T> out = colfwd_val<T, N>(jb, mode, ky, kx, o, t, avo, aoo);
   if (extras) {
-    const cpx<T> gv = reinterpret_cast<const cpx<T>*>(jb.gvec)[o + dvc];
+    const cpx<T> gv = reinterpret_cast<const cpx<T>*>(jb.gvec)[o];
     adg += (double)gv.x * out.x + (double)gv.y * out.y;
     const cpx<T>* dpb = reinterpret_cast<const cpx<T>*>(jb.dpBase);
 #pragma unroll
     for (int j = 0; j < MMAX; ++j) {
       if ((jb.dpMask >> j) & 1u) {
-        const cpx<T> dj = dpb[(int64_t)j * jb.dpStride + o + dvc];
+        const cpx<T> dj = dpb[(int64_t)j * jb.dpStride + o];
         add[j] += (double)dj.x * out.x + (double)dj.y * out.y;
       }
     }
@@ -328,9 +328,7 @@ __global__ __launch_bounds__(NT) void k_colinv(const Job* __restrict__ jobs, con
     int kyr = ky;
 #pragma unroll
     for (int c = 0; c < C; ++c) {
-      const int64_t bs = fidx(N, c, 0, qb * TB);
-      const int64_t dvc = jb.vcs > 0 ? vview(bs, jb.vcs, jb.vcstr) - bs : 0;
-      a[c] = colinv_in<T, N, SIMK>(jb, mode, c, ky, kx, dvc, part, kyr, acc);
+      a[c] = colinv_in<T, N, SIMK>(jb, mode, c, ky, kx, part, kyr, acc);
     }
     if constexpr (C == 2) {
       T c2, s2;
@@ -513,8 +511,7 @@ __global__ __launch_bounds__(NT) void k_colfwd(const Job* __restrict__ jobs, con
 #pragma unroll
     for (int c = 0; c < C; ++c) {
       const int64_t bs = fidx(N, c, 0, qb * TB);
-      const int64_t dvc = jb.vcs > 0 ? vview(bs, jb.vcs, jb.vcstr) - bs : 0;
-      colfwd_out<T, N>(jb, mode, extras, ky, kx, bs + e, dvc, t[c], avo, aoo, adg, add);
+      colfwd_out<T, N>(jb, mode, extras, ky, kx, bs + e, t[c], avo, aoo, adg, add);
     }
   }
   colfwd_reduce(jb, mode, extras, avo, aoo, adg, add, q, CPB);
@@ -571,7 +568,6 @@ __global__ __launch_bounds__(NT) void k_colinvr(const Job* __restrict__ jobs, co
   const int col = b % TB, c = (b / TB) % C, cb = b / (TB * C);
   const int qb = q * CPB + cb, kx = qb * TB + col;
   const int64_t bs = fidx(N, c, 0, qb * TB);
-  const int64_t dvc = jb.vcs > 0 ? vview(bs, jb.vcs, jb.vcstr) - bs : 0;
   double acc = 0.0;
   cpx<T> v[E];
   {
@@ -584,7 +580,7 @@ __global__ __launch_bounds__(NT) void k_colinvr(const Job* __restrict__ jobs, co
         const int ky = j + r * NQ0;
         bool part;
         int kyr;
-        cpx<T> a = colinv_in<T, N, false>(jb, mode, c, ky, kx, dvc, part, kyr, acc);
+        cpx<T> a = colinv_in<T, N, false>(jb, mode, c, ky, kx, part, kyr, acc);
         if constexpr (C == 2) {
           const T ox = lane_xor2(a.x), oy = lane_xor2(a.y);   // the other component
           T c2, s2;
@@ -754,7 +750,6 @@ __global__ __launch_bounds__(NT) void k_colfwdr(const Job* __restrict__ jobs, co
   const int col = b % TB, c = (b / TB) % C, cb = b / (TB * C);
   const int qb = q * CPB + cb, kx = qb * TB + col;
   const int64_t bs = fidx(N, c, 0, qb * TB);
-  const int64_t dvc = jb.vcs > 0 ? vview(bs, jb.vcs, jb.vcstr) - bs : 0;
   const cpx<T>* Y = reinterpret_cast<const cpx<T>*>(jb.y);
   cpx<T> v[E];
   {
@@ -784,7 +779,7 @@ __global__ __launch_bounds__(NT) void k_colfwdr(const Job* __restrict__ jobs, co
         rot2<T>(kx, ky < N / 2 ? ky : ky - N, c2, s2);
         t = (c == 0) ? mk(c2 * t.x + s2 * ox, c2 * t.y + s2 * oy) : mk(-s2 * ox + c2 * t.x, -s2 * oy + c2 * t.y);
       }
-      v[kk * RL + r] = colfwd_val<T, N>(jb, mode, ky, kx, bs + ky * TB + col, dvc, t, avo, aoo);
+      v[kk * RL + r] = colfwd_val<T, N>(jb, mode, ky, kx, bs + ky * TB + col, t, avo, aoo);
     });
   });
   if (!(mode == CM_HV || mode == CM_GRAD)) return;
@@ -809,7 +804,7 @@ __global__ __launch_bounds__(NT) void k_colfwdr(const Job* __restrict__ jobs, co
       const uint32_t j = ((uint32_t)tid + kk * NT) / NB;
       sfor<0, RL>([&](auto RR) {
         constexpr int r = decltype(RR)::value;
-        const cpx<T> w = gld(u, (uint32_t)(bs + dvc) + (j + r * NQL) * TB + col);
+        const cpx<T> w = gld(u, (uint32_t)bs + (j + r * NQL) * TB + col);
         a += (double)w.x * v[kk * RL + r].x + (double)w.y * v[kk * RL + r].y;
       });
     });

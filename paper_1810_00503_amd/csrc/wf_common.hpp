@@ -159,24 +159,14 @@ struct Job {
   double* part;         // [PK_COUNT][pstride] partial sums
   int pstride;
   int pad1;
-  // vin, vadd and vout are chunk-interleaved views: element e of such a vector lives at
-  // ptr + (e / vcs) * vcstr + e % vcs (vcs = vcstr = L for a plain contiguous vector).
-  // Chunks are whole column blocks, so a column tile is contiguous.
-  int64_t vcs;
-  int64_t vcstr;
   // curvature mode inside the solver: also accumulate out . g (gvec) and out . Dp_j for the
-  // history slots j set in dpMask (Dp_j at dpBase + j * dpStride), all in the same view
+  // history slots j set in dpMask (Dp_j at dpBase + j * dpStride)
   const void* gvec;
   const void* dpBase;
   int64_t dpStride;
   uint32_t dpMask;
   int pad2;
 };
-
-// element offset of e in a chunk-interleaved vector view
-__host__ __device__ __forceinline__ int64_t vview(int64_t e, int64_t vcs, int64_t vcstr) {
-  return (e / vcs) * vcstr + (e % vcs);
-}
 
 // ------------------------------------------------------------------------ solver state
 
@@ -234,8 +224,6 @@ struct BandJob {
   double* part;           // [nblk][nbands]
   double* E;              // [nbands] output (device)
   int64_t L;
-  int64_t vcs;            // view of f (see Job)
-  int64_t vcstr;
   int nbands;
   int raw;
 };

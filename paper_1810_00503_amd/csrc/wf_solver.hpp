@@ -107,8 +107,6 @@ __device__ __forceinline__ void make_job(Job& jb, const InstDesc& D, int mode, i
   jb.xout = nullptr;
   jb.part = D.partChain;
   jb.pstride = D.pstride;
-  jb.vcs = D.L;
-  jb.vcstr = D.L;
   jb.gvec = nullptr;
   jb.dpBase = nullptr;
   jb.dpStride = D.vstride;
@@ -779,8 +777,8 @@ __global__ void k_unpack(int n, int C, int batch, const cpx<T>* __restrict__ ext
 // conjugates of their free entries, dead entries 0.  fill = 0: copy every stored entry
 // (live ones; dead entries 0).
 template <typename T>
-__global__ void k_pack(int n, int C, int batch, const cpx<T>* __restrict__ in, int64_t inStride, int64_t vcs,
-                       int64_t vcstr, const T* __restrict__ sq, int fill, cpx<T>* const* __restrict__ outs,
+__global__ void k_pack(int n, int C, int batch, const cpx<T>* __restrict__ in, int64_t inStride,
+                       const T* __restrict__ sq, int fill, cpx<T>* const* __restrict__ outs,
                        cpx<T>* __restrict__ out0) {
   const int h = n / 2;
   const int64_t per = (int64_t)C * n * (h + 1);
@@ -795,7 +793,7 @@ __global__ void k_pack(int n, int C, int batch, const cpx<T>* __restrict__ in, i
       const bool part = is_partner(n, ky, kx);
       const int kyr = (fill && part) ? n - ky : ky;
       const int64_t src = fidx(n, c, kyr, kx);
-      v = in[i * inStride + vview(src, vcs, vcstr)];
+      v = in[i * inStride + src];
       if (sq) v = scale(v, sq[src]);
       if (fill && part) v = conj(v);
     }
@@ -827,7 +825,7 @@ __global__ __launch_bounds__(NT) void k_band_part(const BandJob* __restrict__ jo
     if (e < jb.L) {
       bl[k] = jb.bandI[e];
       if (bl[k] >= 0) {
-        const cpx<T> a = f[vview(e, jb.vcs, jb.vcstr)];
+        const cpx<T> a = f[e];
         double t = (double)a.x * a.x + (double)a.y * a.y;
         if (jb.aw) t *= (double)reinterpret_cast<const T*>(jb.aw)[e];
         if (jb.raw) {

@@ -79,14 +79,14 @@ hipError_t unpack_launch(int dtype, int n, int c, int batch, const void* ext, vo
   return hipGetLastError();
 }
 
-hipError_t pack_launch(int dtype, int n, int c, int batch, const void* in, int64_t inStride, int64_t vcs,
-                       int64_t vcstr, const void* sq, int fill, void* const* outs, void* out0, hipStream_t s) {
+hipError_t pack_launch(int dtype, int n, int c, int batch, const void* in, int64_t inStride,
+                       const void* sq, int fill, void* const* outs, void* out0, hipStream_t s) {
   const dim3 g = flat_grid((int64_t)batch * c * n * (n / 2 + 1));
   if (dtype == 0)
-    k_pack<float><<<g, 256, 0, s>>>(n, c, batch, (const cpx<float>*)in, inStride, vcs, vcstr, (const float*)sq, fill,
+    k_pack<float><<<g, 256, 0, s>>>(n, c, batch, (const cpx<float>*)in, inStride, (const float*)sq, fill,
                                     (cpx<float>* const*)outs, (cpx<float>*)out0);
   else
-    k_pack<double><<<g, 256, 0, s>>>(n, c, batch, (const cpx<double>*)in, inStride, vcs, vcstr, (const double*)sq, fill,
+    k_pack<double><<<g, 256, 0, s>>>(n, c, batch, (const cpx<double>*)in, inStride, (const double*)sq, fill,
                                      (cpx<double>* const*)outs, (cpx<double>*)out0);
   return hipGetLastError();
 }
