@@ -143,6 +143,40 @@ __device__ __forceinline__ cpx<T> colinv_in(const Job& jb, int mode, int c, int 
   return scale(v, sc);
 }
 
+// The same for the curvature and gradient modes, whitened or raw (CM_HV, CM_GRAD,
+// CM_RAW_HV, CM_RAW_GRAD), split in two so that a thread issues the global loads of all its
+// elements (colinv_ld) before the arithmetic of the first (colinv_fin): a load behind a
+// data-dependent branch waits for the loads before it, so the one-call form costs a memory
+// round trip per element.  wa is the solver weight (whitened) or the sqrt S of sOut (raw).
+__device__ __forceinline__ bool colinv_hot(int mode) {
+  return mode == CM_HV || mode == CM_GRAD || mode == CM_RAW_HV || mode == CM_RAW_GRAD;
+}
+template <typename T, int N>
+__device__ __forceinline__ void colinv_ld(const Job& jb, bool grad, bool raw, int c, int ky, int kx, cpx<T>& v,
+                                          T& sc, T& wa) {
+  const uint32_t src = (uint32_t)fidx(N, c, is_partner(N, ky, kx) ? N - ky : ky, kx);
+  v = gld(reinterpret_cast<const cpx<T>*>(jb.vin), src);
+  sc = jb.sIn ? gld(reinterpret_cast<const T*>(jb.sIn), src) : T(1);
+  if (raw) wa = gld(reinterpret_cast<const T*>(jb.sOut), src);
+  else wa = (grad && jb.aTab) ? gld(reinterpret_cast<const T*>(jb.aTab), src) : T(1);
+}
+template <typename T, int N>
+__device__ __forceinline__ cpx<T> colinv_fin(bool grad, bool raw, int ky, int kx, cpx<T> v, T sc, T wa, bool& part,
+                                             int& kyr, double& acc) {
+  part = false;
+  kyr = ky;
+  if (!is_live(N, ky, kx)) return mk(T(0), T(0));
+  part = is_partner(N, ky, kx);
+  kyr = part ? N - ky : ky;
+  if (raw) {
+    if (wa == T(0)) v = mk(T(0), T(0));
+    else if (grad && !part) acc += ((double)v.x * v.x + (double)v.y * v.y) / ((double)wa * wa);
+  } else if (grad && !part) {
+    acc += (double)wa * ((double)v.x * v.x + (double)v.y * v.y);
+  }
+  return scale(v, sc);
+}
+
 // Pixel step of the row pass for complex element j of image row y of component c (pixels
 // 2j, 2j + 1).  Adjoint modes read the pixels into z; otherwise z holds the unnormalised
 // inverse transform and becomes the input of the forward transform (or is written to xout
@@ -210,6 +244,27 @@ __device__ __forceinline__ void row_pixel(const Job& jb, int mode, bool adjIn, i
   z = mk(r0 * invn, r1 * invn);
 }
 
+// row_pixel's curvature and gradient branches (whitened or raw) on a preloaded pixel pair of
+// W (and of d), so that a thread can issue the loads of all its elements first
+template <typename T, int N, typename T2>
+__device__ __forceinline__ void row_pixel_hot(bool grad, T2 w, T2 d, cpx<T>& z, double& acc) {
+  const T invn = T(1) / T(N);
+  const T x0 = z.x * invn, x1 = z.y * invn;
+  T r0, r1;
+  if (!grad) {
+    r0 = w.x * x0;
+    r1 = w.y * x1;
+  } else {   // masked pixels contribute nothing
+    const T e0 = x0 - d.x, e1 = x1 - d.y;
+    const bool m0 = w.x > T(0), m1 = w.y > T(0);
+    r0 = m0 ? w.x * e0 : T(0);
+    r1 = m1 ? w.y * e1 : T(0);
+    acc += m0 ? (double)r0 * e0 : 0.0;
+    acc += m1 ? (double)r1 * e1 : 0.0;
+  }
+  z = mk(r0 * invn, r1 * invn);
+}
+
 // Column-forward output of component c at (ky, kx) = internal index o (t: forward
 // transform after the inverse rotation): prior scale, added term, the v.out and out.out
 // partials; writes and returns the output.
@@ -242,6 +297,46 @@ __device__ __forceinline__ cpx<T> colfwd_val(const Job& jb, int mode, int ky, in
   }
   gst(reinterpret_cast<cpx<T>*>(jb.vout), oi, out);
   return out;
+}
+
+// colfwd_val's curvature and gradient branches (CM_HV, CM_GRAD; raw: CM_RAW_HV,
+// CM_RAW_GRAD) split like colinv_ld / colinv_fin: the loads of all of a thread's elements
+// first, then the arithmetic; the caller stores the returned output.
+template <typename T>
+__device__ __forceinline__ void colfwd_ld(const Job& jb, uint32_t o, T& sq, cpx<T>& a, T& wa) {
+  sq = gld(reinterpret_cast<const T*>(jb.sOut), o);
+  a = gld(reinterpret_cast<const cpx<T>*>(jb.vadd), o);
+  wa = jb.aTab ? gld(reinterpret_cast<const T*>(jb.aTab), o) : T(1);
+}
+template <typename T, int N>
+__device__ __forceinline__ cpx<T> colfwd_fin(bool raw, int ky, int kx, cpx<T> t, T sq, cpx<T> a, T wa, double& avo,
+                                             double& aoo) {
+  const bool keep = is_free(N, ky, kx) && sq != T(0);
+  if (raw) {
+    const T is = keep ? T(1) / (sq * sq) : T(0);
+    return keep ? mk(T(4) * (a.x * is + t.x), T(4) * (a.y * is + t.y)) : mk(T(0), T(0));
+  }
+  const cpx<T> out = keep ? mk(wa * a.x + sq * t.x, wa * a.y + sq * t.y) : mk(T(0), T(0));
+  const double dvo = (double)a.x * out.x + (double)a.y * out.y;
+  avo += keep ? dvo : 0.0;
+  aoo += (double)out.x * out.x + (double)out.y * out.y;
+  return out;
+}
+
+// For curvature products inside the solver (extras): the dots of the output at o with g and
+// with the kept Dp_j.
+template <typename T>
+__device__ __forceinline__ void colfwd_extras(const Job& jb, int64_t o, cpx<T> out, double& adg, double (&add)[MMAX]) {
+  const cpx<T> gv = reinterpret_cast<const cpx<T>*>(jb.gvec)[o];
+  adg += (double)gv.x * out.x + (double)gv.y * out.y;
+  const cpx<T>* dpb = reinterpret_cast<const cpx<T>*>(jb.dpBase);
+#pragma unroll
+  for (int j = 0; j < MMAX; ++j) {
+    if ((jb.dpMask >> j) & 1u) {
+      const cpx<T> dj = dpb[(int64_t)j * jb.dpStride + o];
+      add[j] += (double)dj.x * out.x + (double)dj.y * out.y;
+    }
+  }
 }
 
 // The same plus, for curvature products inside the solver (extras), the dots of the output
@@ -319,30 +414,51 @@ __global__ __launch_bounds__(NT) void k_colinv(const Job* __restrict__ jobs, con
   for (int i = tid; i < N; i += NT) tw[i] = twg[i];
 
   double acc = 0.0;
-  for (int ee = tid; ee < CPB * N * TB; ee += NT) {
-    const int cb = ee / (N * TB), e = ee % (N * TB);
-    const int qb = q * CPB + cb;                     // column block
-    const int ky = e / TB, col = e % TB, kx = qb * TB + col;
-    cpx<T> a[C];
-    bool part = false;
-    int kyr = ky;
+  // elements ee = tid + k NT, in chunks of KCH whose loads are all issued first (hot modes)
+  constexpr int NEL = CPB * N * TB, KI = (NEL + NT - 1) / NT, KCH = KI < 4 ? KI : 4;
+  const bool hot = colinv_hot(mode), grad = (mode == CM_GRAD || mode == CM_RAW_GRAD);
+  const bool raw = (mode == CM_RAW_HV || mode == CM_RAW_GRAD);
+  for (int k0 = 0; k0 < KI; k0 += KCH) {
+    cpx<T> av[KCH][C];
+    T sc[KCH][C], wa[KCH][C];
+    if (hot) {
 #pragma unroll
-    for (int c = 0; c < C; ++c) {
-      a[c] = colinv_in<T, N, SIMK>(jb, mode, c, ky, kx, part, kyr, acc);
-    }
-    if constexpr (C == 2) {
-      T c2, s2;
-      rot2<T>(kx, kyr < N / 2 ? kyr : kyr - N, c2, s2);
-      const cpx<T> e0 = a[0], b0 = a[1];
-      a[0] = mk(c2 * e0.x - s2 * b0.x, c2 * e0.y - s2 * b0.y);
-      a[1] = mk(s2 * e0.x + c2 * b0.x, s2 * e0.y + c2 * b0.y);
-    }
-    if (part) {
+      for (int k = 0; k < KCH; ++k) {
+        const int ee = min(tid + (k0 + k) * NT, NEL - 1);   // past the end: any valid entry
+        const int e = ee % (N * TB), kx = (q * CPB + ee / (N * TB)) * TB + e % TB;
 #pragma unroll
-      for (int c = 0; c < C; ++c) a[c] = conj(a[c]);
+        for (int c = 0; c < C; ++c) colinv_ld<T, N>(jb, grad, raw, c, e / TB, kx, av[k][c], sc[k][c], wa[k][c]);
+      }
     }
 #pragma unroll
-    for (int c = 0; c < C; ++c) buf[ky * NB + (cb * C + c) * TB + col] = a[c];
+    for (int k = 0; k < KCH; ++k) {
+      const int ee = tid + (k0 + k) * NT;
+      if (k0 + k >= KI || ee >= NEL) break;
+      const int cb = ee / (N * TB), e = ee % (N * TB);
+      const int qb = q * CPB + cb;                     // column block
+      const int ky = e / TB, col = e % TB, kx = qb * TB + col;
+      cpx<T> a[C];
+      bool part = false;
+      int kyr = ky;
+#pragma unroll
+      for (int c = 0; c < C; ++c) {
+        a[c] = hot ? colinv_fin<T, N>(grad, raw, ky, kx, av[k][c], sc[k][c], wa[k][c], part, kyr, acc)
+                   : colinv_in<T, N, SIMK>(jb, mode, c, ky, kx, part, kyr, acc);
+      }
+      if constexpr (C == 2) {
+        T c2, s2;
+        rot2<T>(kx, kyr < N / 2 ? kyr : kyr - N, c2, s2);
+        const cpx<T> e0 = a[0], b0 = a[1];
+        a[0] = mk(c2 * e0.x - s2 * b0.x, c2 * e0.y - s2 * b0.y);
+        a[1] = mk(s2 * e0.x + c2 * b0.x, s2 * e0.y + c2 * b0.y);
+      }
+      if (part) {
+#pragma unroll
+        for (int c = 0; c < C; ++c) a[c] = conj(a[c]);
+      }
+#pragma unroll
+      for (int c = 0; c < C; ++c) buf[ky * NB + (cb * C + c) * TB + col] = a[c];
+    }
   }
   __syncthreads();
   lds_fft<T, N, NB, 1, NB, 1, false, true>(buf, tw);
@@ -419,11 +535,41 @@ __global__ __launch_bounds__(NT) void k_row(const Job* __restrict__ jobs, const 
 
   // pixel operation: element j of row b holds pixels (2j, 2j+1)
   double acc = 0.0;
-  for (int e = tid; e < NE; e += NT) {
-    const int b = e / H, j = e % H;
-    cpx<T> zf = buf[b * SBR + j];
-    row_pixel<T, N, C, SIMK>(jb, mode, adjIn, b / RB, y0 + b % RB, j, zf, acc);
-    if (mode != CM_FWD && mode != CM_SIM) buf[b * SBR + j] = zf;
+  if (colinv_hot(mode)) {
+    // W (and d) pixel pairs of a chunk of elements loaded first, then row_pixel_hot
+    using T2 = typename std::conditional<std::is_same<T, float>::value, float2, double2>::type;
+    const bool grad = (mode == CM_GRAD || mode == CM_RAW_GRAD);
+    const T2* W2 = reinterpret_cast<const T2*>(jb.W);
+    const T2* D2 = grad ? reinterpret_cast<const T2*>(jb.d) : nullptr;
+    constexpr int KCH = KP < 8 ? KP : 8;
+    for (int k0 = 0; k0 < KP; k0 += KCH) {
+      T2 wv[KCH], dv[KCH];
+#pragma unroll
+      for (int k = 0; k < KCH; ++k) {
+        const int e = min(tid + (k0 + k) * NT, NE - 1);   // past the end: any valid element
+        const int b = e / H;
+        const uint32_t p2 = (uint32_t)(y0 + b % RB) * (N / 2) + e % H;
+        wv[k] = gld(W2, p2);
+        if (grad) dv[k] = gld(D2, (uint32_t)(b / RB) * (N * N / 2) + p2);
+        else dv[k] = T2{T(0), T(0)};
+      }
+#pragma unroll
+      for (int k = 0; k < KCH; ++k) {
+        const int e = tid + (k0 + k) * NT;
+        if (k0 + k >= KP || e >= NE) break;
+        const int b = e / H, j = e % H;
+        cpx<T> zf = buf[b * SBR + j];
+        row_pixel_hot<T, N>(grad, wv[k], dv[k], zf, acc);
+        buf[b * SBR + j] = zf;
+      }
+    }
+  } else {
+    for (int e = tid; e < NE; e += NT) {
+      const int b = e / H, j = e % H;
+      cpx<T> zf = buf[b * SBR + j];
+      row_pixel<T, N, C, SIMK>(jb, mode, adjIn, b / RB, y0 + b % RB, j, zf, acc);
+      if (mode != CM_FWD && mode != CM_SIM) buf[b * SBR + j] = zf;
+    }
   }
   if (mode == CM_FWD || mode == CM_SIM) return;
   __syncthreads();
@@ -494,24 +640,53 @@ __global__ __launch_bounds__(NT) void k_colfwd(const Job* __restrict__ jobs, con
   for (int j = 0; j < MMAX; ++j) add[j] = 0.0;
   // curvature products inside the solver also dot the new Dp with g and the kept Dp_j
   const bool extras = (mode == CM_HV) && jb.dpBase != nullptr;
-  for (int ee = tid; ee < CPB * N * TB; ee += NT) {
-    const int cb = ee / (N * TB), e = ee % (N * TB);
-    const int qb = q * CPB + cb;
-    const int ky = e / TB, col = e % TB, kx = qb * TB + col;
-    cpx<T> t[C];
+  // elements ee = tid + k NT, in chunks of KCH whose epilogue loads are all issued first
+  // (curvature and gradient modes)
+  constexpr int NEL = CPB * N * TB, KI = (NEL + NT - 1) / NT, KCH = KI < 4 ? KI : 4;
+  const bool hot = colinv_hot(mode), raw = (mode == CM_RAW_HV || mode == CM_RAW_GRAD);
+  cpx<T>* vo = reinterpret_cast<cpx<T>*>(jb.vout);
+  for (int k0 = 0; k0 < KI; k0 += KCH) {
+    T sqv[KCH][C], wav[KCH][C];
+    cpx<T> vav[KCH][C];
+    if (hot) {
 #pragma unroll
-    for (int c = 0; c < C; ++c) t[c] = buf[ky * NB + (cb * C + c) * TB + col];
-    if constexpr (C == 2) {
-      T c2, s2;
-      rot2<T>(kx, ky < N / 2 ? ky : ky - N, c2, s2);
-      const cpx<T> g1 = t[0], g2 = t[1];
-      t[0] = mk(c2 * g1.x + s2 * g2.x, c2 * g1.y + s2 * g2.y);
-      t[1] = mk(-s2 * g1.x + c2 * g2.x, -s2 * g1.y + c2 * g2.y);
+      for (int k = 0; k < KCH; ++k) {
+        const int ee = min(tid + (k0 + k) * NT, NEL - 1);   // past the end: any valid entry
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+          const uint32_t o = (uint32_t)(fidx(N, c, 0, (q * CPB + ee / (N * TB)) * TB) + ee % (N * TB));
+          colfwd_ld<T>(jb, o, sqv[k][c], vav[k][c], wav[k][c]);
+        }
+      }
     }
 #pragma unroll
-    for (int c = 0; c < C; ++c) {
-      const int64_t bs = fidx(N, c, 0, qb * TB);
-      colfwd_out<T, N>(jb, mode, extras, ky, kx, bs + e, t[c], avo, aoo, adg, add);
+    for (int k = 0; k < KCH; ++k) {
+      const int ee = tid + (k0 + k) * NT;
+      if (k0 + k >= KI || ee >= NEL) break;
+      const int cb = ee / (N * TB), e = ee % (N * TB);
+      const int qb = q * CPB + cb;
+      const int ky = e / TB, col = e % TB, kx = qb * TB + col;
+      cpx<T> t[C];
+#pragma unroll
+      for (int c = 0; c < C; ++c) t[c] = buf[ky * NB + (cb * C + c) * TB + col];
+      if constexpr (C == 2) {
+        T c2, s2;
+        rot2<T>(kx, ky < N / 2 ? ky : ky - N, c2, s2);
+        const cpx<T> g1 = t[0], g2 = t[1];
+        t[0] = mk(c2 * g1.x + s2 * g2.x, c2 * g1.y + s2 * g2.y);
+        t[1] = mk(-s2 * g1.x + c2 * g2.x, -s2 * g1.y + c2 * g2.y);
+      }
+#pragma unroll
+      for (int c = 0; c < C; ++c) {
+        const int64_t o = fidx(N, c, 0, qb * TB) + e;
+        if (hot) {
+          const cpx<T> out = colfwd_fin<T, N>(raw, ky, kx, t[c], sqv[k][c], vav[k][c], wav[k][c], avo, aoo);
+          gst(vo, (uint32_t)o, out);
+          if (extras) colfwd_extras<T>(jb, o, out, adg, add);
+        } else {
+          colfwd_out<T, N>(jb, mode, extras, ky, kx, o, t[c], avo, aoo, adg, add);
+        }
+      }
     }
   }
   colfwd_reduce(jb, mode, extras, avo, aoo, adg, add, q, CPB);
@@ -572,6 +747,16 @@ __global__ __launch_bounds__(NT) void k_colinvr(const Job* __restrict__ jobs, co
   cpx<T> v[E];
   {
     constexpr int R0 = PQ, NQ0 = N / R0, K0 = E / R0;
+    const bool hot = colinv_hot(mode), grad = (mode == CM_GRAD || mode == CM_RAW_GRAD);
+    const bool raw = (mode == CM_RAW_HV || mode == CM_RAW_GRAD);
+    T sc[E], wa[E];
+    if (hot) {
+      sfor<0, E>([&](auto I) {
+        constexpr int i = decltype(I)::value;
+        const int ky = (int)(((uint32_t)tid + (i / R0) * NT) / NB) + (i % R0) * NQ0;
+        colinv_ld<T, N>(jb, grad, raw, c, ky, kx, v[i], sc[i], wa[i]);
+      });
+    }
     sfor<0, K0>([&](auto KK) {
       constexpr int kk = decltype(KK)::value;
       const int j = ((uint32_t)tid + kk * NT) / NB;
@@ -580,7 +765,9 @@ __global__ __launch_bounds__(NT) void k_colinvr(const Job* __restrict__ jobs, co
         const int ky = j + r * NQ0;
         bool part;
         int kyr;
-        cpx<T> a = colinv_in<T, N, false>(jb, mode, c, ky, kx, part, kyr, acc);
+        cpx<T> a = hot ? colinv_fin<T, N>(grad, raw, ky, kx, v[kk * R0 + r], sc[kk * R0 + r], wa[kk * R0 + r], part,
+                                          kyr, acc)
+                       : colinv_in<T, N, false>(jb, mode, c, ky, kx, part, kyr, acc);
         if constexpr (C == 2) {
           const T ox = lane_xor2(a.x), oy = lane_xor2(a.y);   // the other component
           T c2, s2;
@@ -686,14 +873,31 @@ __global__ __launch_bounds__(NT) void k_rowr(const Job* __restrict__ jobs, const
   {
     // pixel step in the inverse's last-stage layout, which is the forward's first-stage one
     constexpr int RL = rs_radix(H, E, false, NST - 1), NQL = H / RL, KL = E / RL;
-    sfor<0, KL>([&](auto KK) {
-      constexpr int kk = decltype(KK)::value;
-      const uint32_t u = tid + kk * NT, b = u / NQL, j = u % NQL;
-      sfor<0, RL>([&](auto RR) {
-        constexpr int r = decltype(RR)::value;
-        row_pixel<T, N, C, false>(jb, mode, adjIn, c, y0 + b, j + r * NQL, v[kk * RL + r], acc);
+    if (colinv_hot(mode)) {
+      // row_pixel's curvature and gradient branches with the W (and d) pixel pairs of all E
+      // elements loaded first
+      const bool grad = (mode == CM_GRAD || mode == CM_RAW_GRAD);
+      const float2* W2 = reinterpret_cast<const float2*>(jb.W);
+      const float2* D2 = grad ? reinterpret_cast<const float2*>(jb.d) + (uint32_t)c * (N * N / 2) : nullptr;
+      float2 wv[E], dv[E];
+      sfor<0, E>([&](auto I) {
+        constexpr int i = decltype(I)::value;
+        const uint32_t u = tid + (i / RL) * NT;
+        const uint32_t p2 = (uint32_t)(y0 + u / NQL) * (N / 2) + u % NQL + (i % RL) * NQL;
+        wv[i] = gld(W2, p2);
+        dv[i] = grad ? gld(D2, p2) : make_float2(0.f, 0.f);
       });
-    });
+      sfor<0, E>([&](auto I) { row_pixel_hot<T, N>(grad, wv[decltype(I)::value], dv[decltype(I)::value], v[decltype(I)::value], acc); });
+    } else {
+      sfor<0, KL>([&](auto KK) {
+        constexpr int kk = decltype(KK)::value;
+        const uint32_t u = tid + kk * NT, b = u / NQL, j = u % NQL;
+        sfor<0, RL>([&](auto RR) {
+          constexpr int r = decltype(RR)::value;
+          row_pixel<T, N, C, false>(jb, mode, adjIn, c, y0 + b, j + r * NQL, v[kk * RL + r], acc);
+        });
+      });
+    }
   }
   if (mode == CM_FWD) return;
   rs_fft<T, H, RB, E, true, false, true>(v, data, stF, lxf, tid);
@@ -766,20 +970,41 @@ __global__ __launch_bounds__(NT) void k_colfwdr(const Job* __restrict__ jobs, co
   rs_fft<T, N, NB, E, false, false, false>(v, data, st, lx, tid);
   constexpr int RL = rs_radix(N, E, false, NST - 1), NQL = N / RL, KL = E / RL;
   double avo = 0.0, aoo = 0.0;
+  // curvature and gradient modes: the epilogue's loads (prior scale, added term, solver
+  // weight) of all E elements are issued before the first use
+  const bool hot = colinv_hot(mode), raw = (mode == CM_RAW_HV || mode == CM_RAW_GRAD);
+  T sqv[E], wav[E];
+  cpx<T> vav[E];
+  if (hot) {
+    sfor<0, E>([&](auto I) {
+      constexpr int i = decltype(I)::value;
+      const uint32_t o = (uint32_t)bs + (((uint32_t)tid + (i / RL) * NT) / NB + (i % RL) * NQL) * TB + col;
+      colfwd_ld<T>(jb, o, sqv[i], vav[i], wav[i]);
+    });
+  }
+  cpx<T>* vo = reinterpret_cast<cpx<T>*>(jb.vout);
   sfor<0, KL>([&](auto KK) {
     constexpr int kk = decltype(KK)::value;
     const uint32_t j = ((uint32_t)tid + kk * NT) / NB;
     sfor<0, RL>([&](auto RR) {
       constexpr int r = decltype(RR)::value;
+      constexpr int i = kk * RL + r;
       const int ky = j + r * NQL;
-      cpx<T> t = v[kk * RL + r];
+      cpx<T> t = v[i];
       if constexpr (C == 2) {
         const T ox = lane_xor2(t.x), oy = lane_xor2(t.y);   // the other component
         T c2, s2;
         rot2<T>(kx, ky < N / 2 ? ky : ky - N, c2, s2);
         t = (c == 0) ? mk(c2 * t.x + s2 * ox, c2 * t.y + s2 * oy) : mk(-s2 * ox + c2 * t.x, -s2 * oy + c2 * t.y);
       }
-      v[kk * RL + r] = colfwd_val<T, N>(jb, mode, ky, kx, bs + ky * TB + col, t, avo, aoo);
+      const uint32_t o = (uint32_t)bs + ky * TB + col;
+      if (hot) {
+        const cpx<T> out = colfwd_fin<T, N>(raw, ky, kx, t, sqv[i], vav[i], wav[i], avo, aoo);
+        gst(vo, o, out);
+        v[i] = out;
+      } else {
+        v[i] = colfwd_val<T, N>(jb, mode, ky, kx, o, t, avo, aoo);
+      }
     });
   });
   if (!(mode == CM_HV || mode == CM_GRAD)) return;
