@@ -705,7 +705,9 @@ __global__ __launch_bounds__(NT) void k_colfwd(const Job* __restrict__ jobs, con
 __host__ __device__ constexpr int rowr_e(int n) { return n <= 512 ? 8 : 16; }
 __host__ __device__ constexpr int rowr_rb(int n) { return rowr_e(n) * NT / (n / 2); }
 __host__ __device__ constexpr int rowr_io_stride(int H) { return H + (H == 64 ? 6 : (H == 512 ? 4 : 2)); }
-__host__ __device__ constexpr int rowr_x_stride(int H, int E, bool rev) { return H + H / rs_radix(H, E, rev, 0); }
+// exchange layouts: row b at b * rowr_x_stride, index i at i + i / rowr_xpad
+__host__ __device__ constexpr int rowr_xpad(int H) { return H <= 128 ? 8 : 16; }
+__host__ __device__ constexpr int rowr_x_stride(int H, int E, bool rev) { return H + H / rowr_xpad(H); }
 __host__ __device__ constexpr int rowr_data_stride(int H, int E) {
   const int a = rowr_io_stride(H), b = rowr_x_stride(H, E, false), c = rowr_x_stride(H, E, true);
   return a > b ? (a > c ? a : c) : (b > c ? b : c);
@@ -809,7 +811,7 @@ __global__ __launch_bounds__(NT) void k_rowr(const Job* __restrict__ jobs, const
   static_assert(RB % RB_MIN == 0 && N % RB == 0 && NE % NT == 0, "row tile");
   constexpr int TPC = N / RB;   // tiles per component
   constexpr int NST = rs_nst(H, E);
-  constexpr int PQI = rs_radix(H, E, false, 0), PQF = rs_radix(H, E, true, 0);
+  constexpr int PQI = rs_radix(H, E, false, 0);
   constexpr int SBIO = rowr_io_stride(H), SBXI = rowr_x_stride(H, E, false), SBXF = rowr_x_stride(H, E, true);
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cpx<T>* data = reinterpret_cast<cpx<T>*>(smem_raw);
@@ -818,6 +820,29 @@ __global__ __launch_bounds__(NT) void k_rowr(const Job* __restrict__ jobs, const
   __shared__ double red[NT / 64];
   const uint32_t tid = threadIdx.x;
   const int c = blockIdx.x / TPC, tile = blockIdx.x % TPC, y0 = tile * RB;
+  auto lio = [](uint32_t b, uint32_t i) { return b * SBIO + i; };
+  constexpr int XP = rowr_xpad(H);
+  auto lxi = [](uint32_t b, uint32_t i) { return b * SBXI + i + i / XP; };
+  auto lxf = [](uint32_t b, uint32_t i) { return b * SBXF + i + i / XP; };
+  const bool adjIn = (mode == CM_ADJ || mode == CM_ADJ_GRAD);
+  cpx<T>* Y = reinterpret_cast<cpx<T>*>(jb.y) + fidx(N, c, y0, 0);   // column block 0 of this tile
+  cpx<T> v[E];
+  double acc = 0.0;
+  // the tile's RB x TB runs of every column block, coalesced, and the twiddles w^k of the
+  // complex-to-real pre-processing, issued before the (L2-resident) stage twiddles are staged
+  constexpr int R0 = PQI, NQ0 = H / R0, K0 = E / R0;
+  cpx<T> pf[KS], wpre[E];
+  if (!adjIn) {
+    sfor<0, KS>([&](auto K) {
+      constexpr int k = decltype(K)::value;
+      const uint32_t e = tid + k * NT;
+      pf[k] = gld(Y, (e / (RB * TB)) * N * TB + e % (RB * TB));
+    });
+    sfor<0, E>([&](auto I) {
+      constexpr int i = decltype(I)::value;
+      wpre[i] = gld(twg, (tid + (i / R0) * NT) % NQ0 + (i % R0) * NQ0);
+    });
+  }
   {
     const cpx<T>* gI = twg + tw_row_off(N, E, false);
     const cpx<T>* gF = twg + tw_row_off(N, E, true);
@@ -826,21 +851,7 @@ __global__ __launch_bounds__(NT) void k_rowr(const Job* __restrict__ jobs, const
       stF[i] = gld(gF, i);
     }
   }
-  auto lio = [](uint32_t b, uint32_t i) { return b * SBIO + i; };
-  auto lxi = [](uint32_t b, uint32_t i) { return b * SBXI + i + i / PQI; };
-  auto lxf = [](uint32_t b, uint32_t i) { return b * SBXF + i + i / PQF; };
-  const bool adjIn = (mode == CM_ADJ || mode == CM_ADJ_GRAD);
-  cpx<T>* Y = reinterpret_cast<cpx<T>*>(jb.y) + fidx(N, c, y0, 0);   // column block 0 of this tile
-  cpx<T> v[E];
-  double acc = 0.0;
   if (!adjIn) {
-    // staging: the tile's RB x TB runs of every column block, coalesced
-    cpx<T> pf[KS];
-    sfor<0, KS>([&](auto K) {
-      constexpr int k = decltype(K)::value;
-      const uint32_t e = tid + k * NT;
-      pf[k] = gld(Y, (e / (RB * TB)) * N * TB + e % (RB * TB));
-    });
     sfor<0, KS>([&](auto K) {
       constexpr int k = decltype(K)::value;
       const uint32_t e = tid + k * NT, w2 = e % (RB * TB);
@@ -848,7 +859,6 @@ __global__ __launch_bounds__(NT) void k_rowr(const Job* __restrict__ jobs, const
     });
     __syncthreads();
     // complex-to-real pre-processing into the first stage's registers (see k_row)
-    constexpr int R0 = PQI, NQ0 = H / R0, K0 = E / R0;
     sfor<0, K0>([&](auto KK) {
       constexpr int kk = decltype(KK)::value;
       const uint32_t u = tid + kk * NT, b = u / NQ0, j = u % NQ0;
@@ -861,7 +871,7 @@ __global__ __launch_bounds__(NT) void k_rowr(const Job* __restrict__ jobs, const
           z = mk(X.x, X.x);
         } else {
           const cpx<T> Xm = conj(data[lio(b, H - k)]);
-          const cpx<T> tw = mulc(sub(X, Xm), gld(twg, k));
+          const cpx<T> tw = mulc(sub(X, Xm), wpre[kk * R0 + r]);
           const cpx<T> sm = add(X, Xm);
           z = mk(sm.x - tw.y, sm.y + tw.x);
         }
@@ -901,10 +911,15 @@ __global__ __launch_bounds__(NT) void k_rowr(const Job* __restrict__ jobs, const
   }
   if (mode == CM_FWD) return;
   rs_fft<T, H, RB, E, true, false, true>(v, data, stF, lxf, tid);
+  cpx<T> wpost[KS];
   {
     // outputs are in the inverse's first-stage layout: to LDS in natural order for the
-    // real-to-complex untangle, which pairs k with H - k
-    constexpr int R0 = PQI, NQ0 = H / R0, K0 = E / R0;
+    // real-to-complex untangle, which pairs k with H - k; its twiddles are loaded first
+    sfor<0, KS>([&](auto K) {
+      constexpr int kq = decltype(K)::value;
+      const uint32_t e = tid + kq * NT;
+      wpost[kq] = gld(twg, (e / (RB * TB)) * TB + e % TB);
+    });
     __syncthreads();
     sfor<0, K0>([&](auto KK) {
       constexpr int kk = decltype(KK)::value;
@@ -923,7 +938,7 @@ __global__ __launch_bounds__(NT) void k_rowr(const Job* __restrict__ jobs, const
     const cpx<T> Zk = data[lio(b, k)];
     const cpx<T> Zm = conj(data[lio(b, k == 0 ? 0 : H - k)]);
     const cpx<T> A = add(Zk, Zm);
-    const cpx<T> tw = mul(gld(twg, k), sub(Zk, Zm));
+    const cpx<T> tw = mul(wpost[kq], sub(Zk, Zm));
     gst(Y, qq * N * TB + w2, mk(T(0.5) * (A.x + tw.y), T(0.5) * (A.y - tw.x)));
   });
   if (mode == CM_GRAD || mode == CM_RAW_GRAD) {
