@@ -416,7 +416,7 @@ int tune_chain(wf_ctx* ctx, Klass& k, const std::vector<InstDesc>& hd, Job* djob
         }
     }
   hipEvent_t e0 = ev_get(ctx), e1 = ev_get(ctx);
-  float best = 1e30f;
+  std::vector<float> times;
   for (const ChainCfg& c : cands) {
     auto run = [&]() -> hipError_t {
       const int G = c.group > 0 ? std::min(c.group, cnt) : cnt;
@@ -438,11 +438,17 @@ int tune_chain(wf_ctx* ctx, Klass& k, const std::vector<InstDesc>& hd, Job* djob
       HIPCHK(hipEventElapsedTime(&t, e0, e1));
       tmin = std::min(tmin, t);
     }
-    if (tmin < best) {
-      best = tmin;
-      k.cfg = c;
-    }
+    times.push_back(tmin);
   }
+  // fastest candidate; one that launches each pass once for the whole class wins unless a
+  // grouped one is more than 3 % faster (the timing noise is about 1-2 %, and grouping
+  // multiplies the launches)
+  size_t bi = 0, bu = cands.size();
+  for (size_t i = 0; i < cands.size(); ++i) {
+    if (times[i] < times[bi]) bi = i;
+    if (cands[i].group == 0 && (bu == cands.size() || times[i] < times[bu])) bu = i;
+  }
+  if (!cands.empty()) k.cfg = (bu < cands.size() && times[bu] <= 1.03f * times[bi]) ? cands[bu] : cands[bi];
   ctx->evPool.push_back(e0);
   ctx->evPool.push_back(e1);
   ctx->tuned[key] = k.cfg;
