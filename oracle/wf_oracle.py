@@ -39,7 +39,8 @@ __all__ = [
     "forward", "adjoint", "inner_half", "chi2", "grad_chi2", "whitened_grad", "whitened_hvp",
     "lbfgs_solve", "wiener_dense", "band_E", "dchi2_dtheta", "simulate", "sim_fisher",
     "bandpower_qe", "dense_bias_fisher", "newton_update", "homogeneous_wiener",
-    "homogeneous_band_moments",
+    "homogeneous_band_moments", "band_groups", "fisher_from_columns", "sim_fisher_rows",
+    "fiducial_iteration", "bandpower_iterate",
 ]
 
 
@@ -446,6 +447,130 @@ def bandpower_qe(d, W, pshape, band, theta_fid, nbands, draws, m=10, tol=1e-8, m
     E = band_E(sh, S_fid, band, theta_fid, nbands)
     b, F, _ = sim_fisher(W, pshape, band, theta_fid, nbands, draws, m, tol, max_iter)
     return newton_update(theta_fid, F, E, b), E, b, F
+
+
+# ----------------------------------------------------------------------------- sampled Fisher rows
+# The Fisher matrix is smooth and close to translation invariant along its diagonals, so
+# only a few of its rows need their own simulations and the rest can be interpolated
+# (sec. 3.1, discussion of the iteration count against box size).  The paper gives no
+# interpolation rule; the one used here: bands form groups of consecutive indices (one
+# group per spectrum, e.g. E and B); a column l2 of the unsymmetrised response
+# Fr[l, l2] that has no simulations of its own is taken from the nearest simulated columns
+# a < l2 < b of its group at the same diagonal offset (row l + (a - l2) of column a, row
+# l + (b - l2) of column b, each row shift kept inside the row's own group), linearly
+# in the band index; with one of the two rows outside its group the other is used; beyond
+# the first or last simulated column of a group the one neighbour is used with the row
+# clamped into its group.  F is symmetrised afterwards, as in the full estimate.
+
+def band_groups(nbands, groups=None):
+    """[(start, stop)] of the band groups (consecutive indices with equal group id)."""
+    g = np.zeros(nbands, np.int64) if groups is None else np.asarray(groups, np.int64)
+    out = []
+    start = 0
+    for l in range(1, nbands + 1):
+        if l == nbands or g[l] != g[start]:
+            out.append((start, l))
+            start = l
+    return out
+
+
+def fisher_from_columns(Fcols, rows, nbands, groups=None):
+    """Symmetrised F from the simulated columns Fcols[:, j] = Fr[:, rows[j]] (see above)."""
+    rows = [int(r) for r in rows]
+    Fr = np.zeros((nbands, nbands))
+    for j, r in enumerate(rows):
+        Fr[:, r] = Fcols[:, j]
+    grp = band_groups(nbands, groups)
+    gof = {}
+    for gi, (g0, g1) in enumerate(grp):
+        for l in range(g0, g1):
+            gof[l] = (g0, g1)
+    for l2 in range(nbands):
+        if l2 in rows:
+            continue
+        g0, g1 = gof[l2]
+        below = [r for r in rows if g0 <= r < l2]
+        above = [r for r in rows if l2 < r < g1]
+        if not below and not above:
+            raise ValueError(f"band group [{g0}, {g1}) has no simulated column")
+        a = max(below) if below else None
+        b = min(above) if above else None
+        for l in range(nbands):
+            h0, h1 = gof[l]
+            va = vb = None
+            if a is not None and h0 <= l + (a - l2) < h1:
+                va = Fr[l + (a - l2), a]
+            if b is not None and h0 <= l + (b - l2) < h1:
+                vb = Fr[l + (b - l2), b]
+            if va is not None and vb is not None:
+                Fr[l, l2] = va + (vb - va) * (l2 - a) / (b - a)
+            elif va is not None:
+                Fr[l, l2] = va
+            elif vb is not None:
+                Fr[l, l2] = vb
+            else:
+                s_ = a if a is not None else b
+                Fr[l, l2] = Fr[min(max(l + (s_ - l2), h0), h1 - 1), s_]
+    return 0.5 * (Fr + Fr.T)
+
+
+def sim_fisher_rows(W, pshape, band, theta_fid, nbands, draws, rows, groups=None, m=10, tol=1e-8,
+                    max_iter=20000):
+    """sim_fisher with simulations for the boosted bands in `rows` only, the other columns
+    interpolated (fisher_from_columns).  Returns (b, F, E_sims)."""
+    theta_fid = np.asarray(theta_fid, np.float64)
+    S_fid = prior_S(pshape, band, theta_fid)
+    nsim = draws.shape[0]
+    Es = np.zeros((nsim, nbands))
+    Fc = np.zeros((nsim, nbands, len(rows)))
+    for i in range(nsim):
+        d0 = simulate(draws[i], S_fid, W)
+        E0 = band_E(lbfgs_solve(d0, W, S_fid, m, tol, max_iter)["s"], S_fid, band, theta_fid, nbands)
+        Es[i] = E0
+        for j, l2 in enumerate(rows):
+            S2 = _boosted_S(pshape, band, theta_fid, int(l2), 2.0)
+            d2 = simulate(draws[i], S2, W)
+            E2 = band_E(lbfgs_solve(d2, W, S_fid, m, tol, max_iter)["s"], S_fid, band, theta_fid, nbands)
+            Fc[i, :, j] = (E2 - E0) / theta_fid[int(l2)]
+    return Es.mean(0), fisher_from_columns(Fc.mean(0), rows, nbands, groups), Es
+
+
+# ----------------------------------------------------------------------------- fiducial iteration
+# The fiducial spectrum is itself updated from the estimate and the estimate repeated
+# (sec. 2.3, after eq. pilin): a band power must not reach zero, which would remove its
+# projection; the update keeps each band at or above `floor` times its previous value.
+
+def fiducial_iteration(estimate, theta0, max_iter, rel_tol, floor):
+    """Theta_fid,0 = theta0; theta_hat_t = estimate(Theta_fid,t-1); Theta_fid,t =
+    max(theta_hat_t, floor * Theta_fid,t-1); stop after max_iter estimates or once
+    max_l |Theta_fid,t - Theta_fid,t-1| / Theta_fid,t-1 <= rel_tol.  Returns
+    (theta_hat of the last estimate, [Theta_fid,0 .. Theta_fid,T])."""
+    hist = [np.asarray(theta0, np.float64).copy()]
+    th = None
+    for _ in range(max_iter):
+        prev = hist[-1]
+        th = np.asarray(estimate(prev), np.float64)
+        nxt = np.maximum(th, floor * prev)
+        hist.append(nxt)
+        if np.max(np.abs(nxt - prev) / prev) <= rel_tol:
+            break
+    return th, hist
+
+
+def bandpower_iterate(d, W, pshape, band, theta0, nbands, draws, max_iter, rel_tol, floor, rows=None, groups=None,
+                      m=10, tol=1e-8, solve_max_iter=20000):
+    """fiducial_iteration of the quadratic estimate (bandpower_qe, with the Fisher matrix
+    from all rows or from the sampled `rows`).  Returns (theta_hat, history)."""
+    def est(th_fid):
+        S_fid = prior_S(pshape, band, th_fid)
+        sh = lbfgs_solve(d, W, S_fid, m, tol, solve_max_iter)["s"]
+        E = band_E(sh, S_fid, band, th_fid, nbands)
+        if rows is None:
+            b, F, _ = sim_fisher(W, pshape, band, th_fid, nbands, draws, m, tol, solve_max_iter)
+        else:
+            b, F, _ = sim_fisher_rows(W, pshape, band, th_fid, nbands, draws, rows, groups, m, tol, solve_max_iter)
+        return newton_update(th_fid, F, E, b)
+    return fiducial_iteration(est, theta0, max_iter, rel_tol, floor)
 
 
 # ----------------------------------------------------------------------------- closed forms
