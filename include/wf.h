@@ -159,6 +159,37 @@ int bandpower_qe(wf_ctx* ctx, const wf_problem* prob, int32_t nsim, uint64_t see
                  const wf_lbfgs_opts* opts, double* theta_hat, double* E, double* b, double* F,
                  void* stream);
 
+/* sim_fisher with simulations for a subset of the Fisher rows only (the matrix is smooth
+ * and nearly translation invariant, sec. 3.1): nsim * (1 + nrows) MAP solves.
+ *   rows     HOST [nrows] strictly increasing band indices whose boosted simulations
+ *            are run (NULL = all bands, then nrows is ignored);
+ *   groups   nullable HOST [nbands] group id per band; a group is a run of consecutive
+ *            bands with equal ids (e.g. the E and the B bands), NULL = one group.  Every
+ *            group needs at least one simulated row.
+ * A column l' without simulations is interpolated along the diagonals from the nearest
+ * simulated columns a < l' < b of its group: entry l reads entry l + (a - l') of column a
+ * and l + (b - l') of column b, each kept inside the group of row l, linearly in the band
+ * index; with one of the two outside, the other; beyond the group's first or last
+ * simulated column, the one neighbour with the row clamped into the group.  F is then
+ * symmetrised.  Outputs as sim_fisher; WF_EINVAL for bad rows or groups.               */
+int sim_fisher_rows(wf_ctx* ctx, const wf_problem* prob, int32_t nsim, uint64_t seed, const void* draws,
+                    const wf_lbfgs_opts* opts, const int32_t* rows, int32_t nrows, const int32_t* groups,
+                    double* F, double* b, double* E_sims, void* stream);
+
+/* Fiducial iteration of the band-power estimate (sec. 2.3, after eq. pilin): starting from
+ * prob->theta, repeat the quadratic estimate (Fisher rows as in sim_fisher_rows; rows NULL
+ * = all) with the fiducial set to max(theta_hat, floor_frac * previous fiducial) until
+ * max_l |change| / previous <= rel_tol or max_iter estimates.  The same seed (or draws)
+ * is used by every estimate.
+ *   theta_hat, E, b  HOST [nbands]: the last estimate and its E, b; F nullable [nb*nb];
+ *   theta_hist       nullable HOST [(max_iter + 1) * nbands]: fiducials 0 .. n_iter;
+ *   n_iter           nullable: estimates made.
+ * Needs max_iter >= 1, rel_tol >= 0, 0 < floor_frac <= 1.                              */
+int bandpower_iterate(wf_ctx* ctx, const wf_problem* prob, int32_t nsim, uint64_t seed, const void* draws,
+                      const wf_lbfgs_opts* opts, const int32_t* rows, int32_t nrows, const int32_t* groups,
+                      int32_t max_iter, double rel_tol, double floor_frac, double* theta_hat, double* theta_hist,
+                      int32_t* n_iter, double* E, double* b, double* F, void* stream);
+
 /* operator-level calls: `batch` fields sharing prob's geometry, packed contiguously -- */
 
 /* x = R s (eq. ddecomp), or M R s with flags WF_MASK:

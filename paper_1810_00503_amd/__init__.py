@@ -23,7 +23,8 @@ from ._lib import (WF_ADJ_GRAD, WF_ADJ_METRIC, WF_F32, WF_F64, WF_MASK, WF_NOT_C
 
 __all__ = [
     "load", "Context", "Problem", "LbfgsOpts", "SolveStats", "context", "map_wf_solve", "wf_simulate",
-    "sim_fisher", "bandpower_qe", "wf_forward", "wf_adjoint", "wf_chi2_grad", "wf_hvp", "wf_band_E",
+    "sim_fisher", "sim_fisher_rows", "bandpower_qe", "bandpower_iterate", "wf_forward", "wf_adjoint",
+    "wf_chi2_grad", "wf_hvp", "wf_band_E",
     "WFError", "kernel_stats", "reset_kernel_stats", "set_profiling", "autograd", "set_chain_tiles",
     "get_chain_tiles",
 ]
@@ -286,6 +287,70 @@ def bandpower_qe(problem: Problem, nsim: int, seed: int, draws=None, opts: Lbfgs
     cx.check(rc)
     del keep
     return th, E, b, F, rc
+
+
+def _rows_groups(problem, rows, groups):
+    """int32 host arrays (or None) for the sampled-row calls."""
+    nb = problem.nbands
+    r = None if rows is None else np.ascontiguousarray(rows, dtype=np.int32)
+    if r is not None and r.size == 0:
+        raise ValueError("rows must name at least one band")
+    g = None if groups is None else np.ascontiguousarray(groups, dtype=np.int32)
+    if g is not None and g.shape != (nb,):
+        raise ValueError("groups must have one id per band")
+    ip = lambda a: None if a is None else a.ctypes.data_as(C.POINTER(C.c_int32))  # noqa: E731
+    return r, g, ip(r), (0 if r is None else int(r.size)), ip(g)
+
+
+def sim_fisher_rows(problem: Problem, nsim: int, seed: int, rows=None, groups=None, draws=None,
+                    opts: LbfgsOpts | None = None, ctx: Context | None = None):
+    """sim_fisher with boosted simulations for the Fisher rows `rows` only, the others
+    interpolated along the diagonals within band groups (sec. 3.1).
+    Returns (F [nb][nb], b [nb], E_sims [nsim][nb], rc) as numpy arrays."""
+    dev = problem.device_index()
+    cx = ctx or context(dev)
+    nb = problem.nbands
+    F = np.zeros((nb, nb))
+    b = np.zeros(nb)
+    Es = np.zeros((nsim, nb))
+    keep, dp = _draws_ptr(problem, draws, nsim)
+    r, g, rp, nr, gp = _rows_groups(problem, rows, groups)
+    cp = problem.c()
+    o = _opts(opts)
+    ptr = lambda a: a.ctypes.data_as(C.POINTER(C.c_double))  # noqa: E731
+    rc = cx.lib.sim_fisher_rows(cx.h, C.byref(cp), nsim, C.c_uint64(seed), dp, C.byref(o), rp, nr, gp, ptr(F),
+                                ptr(b), ptr(Es), _stream(dev))
+    cx.check(rc)
+    del keep, r, g
+    return F, b, Es, rc
+
+
+def bandpower_iterate(problem: Problem, nsim: int, seed: int, max_iter: int = 3, rel_tol: float = 0.01,
+                      floor: float = 0.01, rows=None, groups=None, draws=None, opts: LbfgsOpts | None = None,
+                      ctx: Context | None = None):
+    """Fiducial iteration of the band-power estimate (sec. 2.3): the fiducial is reset to
+    max(theta_hat, floor * previous) and the estimate repeated.  Returns (theta_hat,
+    history [n_iter + 1][nb] of fiducials, E, b, F, rc) as numpy arrays."""
+    dev = problem.device_index()
+    cx = ctx or context(dev)
+    nb = problem.nbands
+    th = np.zeros(nb)
+    hist = np.zeros((max_iter + 1, nb))
+    E = np.zeros(nb)
+    b = np.zeros(nb)
+    F = np.zeros((nb, nb))
+    nit = C.c_int32(0)
+    keep, dp = _draws_ptr(problem, draws, nsim)
+    r, g, rp, nr, gp = _rows_groups(problem, rows, groups)
+    cp = problem.c()
+    o = _opts(opts)
+    ptr = lambda a: a.ctypes.data_as(C.POINTER(C.c_double))  # noqa: E731
+    rc = cx.lib.bandpower_iterate(cx.h, C.byref(cp), nsim, C.c_uint64(seed), dp, C.byref(o), rp, nr, gp, max_iter,
+                                  rel_tol, floor, ptr(th), ptr(hist), C.byref(nit), ptr(E), ptr(b), ptr(F),
+                                  _stream(dev))
+    cx.check(rc)
+    del keep, r, g
+    return th, hist[:nit.value + 1], E, b, F, rc
 
 
 def _batch_shape(problem, t, kind):

@@ -829,6 +829,7 @@ struct SimEntry {
   int kind;   // 0 data, 1 fiducial simulation, 2 boosted simulation
   int sim;
   int band;
+  int col;    // boosted simulations: index of `band` in the list of simulated columns
 };
 
 // Simulate the data of a list of simulation entries into dbuf (d of entry j at dbuf + j * c n^2).
@@ -876,20 +877,24 @@ int simulate_entries(wf_ctx* ctx, const wf_problem* p, const std::vector<SimEntr
 
 // The quadratic estimator's solves (sec. 2.3-2.4): optional data map, nsim fiducial
 // simulations and nsim * nbands boosted ones, in chunks of one batched solve each.
+// The solves of one band-power estimate: the data map (with_data), nsim fiducial
+// simulations and, per simulation, one with each band of `cols` boosted.  E0 [nsim][nb],
+// E2 [nsim][cols.size()][nb].
 int run_qe(wf_ctx* ctx, const wf_problem* p, bool with_data, int nsim, uint64_t seed, const void* draws,
-           const wf_lbfgs_opts& o, std::vector<double>& Edata, std::vector<double>& E0, std::vector<double>& E2,
-           int& notConverged) {
+           const wf_lbfgs_opts& o, const std::vector<int>& cols, std::vector<double>& Edata, std::vector<double>& E0,
+           std::vector<double>& E2, int& notConverged) {
   const int nb = p->nbands;
+  const int nc = (int)cols.size();
   const int n = p->n, c = p->ncomp, dt = p->dtype;
   std::vector<SimEntry> all;
-  if (with_data) all.push_back({0, 0, -1});
+  if (with_data) all.push_back({0, 0, -1, -1});
   for (int i = 0; i < nsim; ++i) {
-    all.push_back({1, i, -1});
-    for (int l = 0; l < nb; ++l) all.push_back({2, i, l});
+    all.push_back({1, i, -1, -1});
+    for (int j = 0; j < nc; ++j) all.push_back({2, i, cols[j], j});
   }
   Edata.assign(nb, 0.0);
   E0.assign((size_t)nsim * nb, 0.0);
-  E2.assign((size_t)nsim * nb * nb, 0.0);
+  E2.assign((size_t)nsim * nc * nb, 0.0);
   notConverged = 0;
   const size_t rs = rsize_of(dt), eb = esize_of(dt);
   const int64_t L = (int64_t)c * n * (n / 2);
@@ -927,28 +932,128 @@ int run_qe(wf_ctx* ctx, const wf_problem* p, bool with_data, int nsim, uint64_t 
       else if (ents[j].kind == 1)
         std::copy(e, e + nb, E0.begin() + (size_t)ents[j].sim * nb);
       else
-        for (int l = 0; l < nb; ++l) E2[((size_t)ents[j].sim * nb + ents[j].band) * nb + l] = e[l];
+        for (int l = 0; l < nb; ++l) E2[((size_t)ents[j].sim * nc + ents[j].col) * nb + l] = e[l];
     }
   }
   return WF_OK;
 }
 
-void bias_fisher(const double* theta, int nsim, int nb, const std::vector<double>& E0, const std::vector<double>& E2,
-                 double* b, double* F) {
+// Bias b_l = <E0_l> and the symmetrised Fisher matrix from the simulated columns `cols`
+// (F_ll' from the boosted minus fiducial E of column l', eq. fisher with Delta_l' =
+// theta_l').  The other columns are interpolated along the diagonals between the nearest
+// simulated columns of the same band group (bands with equal consecutive ids in grp), the
+// row shift kept inside the row's group; linear in the band index when both neighbours'
+// rows exist, else the one that does, and beyond a group's last (first) simulated column
+// the one neighbour with the row clamped into the group.
+void bias_fisher(const double* theta, int nsim, int nb, const std::vector<int>& cols, const std::vector<int>& grp,
+                 const std::vector<double>& E0, const std::vector<double>& E2, double* b, double* F) {
+  const int nc = (int)cols.size();
   for (int l = 0; l < nb; ++l) {
     double s = 0.0;
     for (int i = 0; i < nsim; ++i) s += E0[(size_t)i * nb + l];
     b[l] = nsim > 0 ? s / nsim : 0.0;
   }
-  std::vector<double> Fr((size_t)nb * nb, 0.0);
-  for (int l = 0; l < nb; ++l)          // row of E
-    for (int l2 = 0; l2 < nb; ++l2) {   // boosted band
+  std::vector<double> Fr((size_t)nb * nb, 0.0);   // Fr[l][l2]: response of E_l to band l2
+  std::vector<char> have(nb, 0);
+  for (int j = 0; j < nc; ++j) {
+    const int l2 = cols[j];
+    have[l2] = 1;
+    for (int l = 0; l < nb; ++l) {
       double s = 0.0;
-      for (int i = 0; i < nsim; ++i) s += E2[((size_t)i * nb + l2) * nb + l] - E0[(size_t)i * nb + l];
+      for (int i = 0; i < nsim; ++i) s += E2[((size_t)i * nc + j) * nb + l] - E0[(size_t)i * nb + l];
       Fr[(size_t)l * nb + l2] = nsim > 0 ? s / nsim / theta[l2] : 0.0;
     }
+  }
+  // group extents [lo, hi) of every band
+  std::vector<int> lo(nb), hi(nb);
+  for (int l = 0; l < nb;) {
+    int e = l + 1;
+    while (e < nb && grp[e] == grp[l]) ++e;
+    for (int k = l; k < e; ++k) {
+      lo[k] = l;
+      hi[k] = e;
+    }
+    l = e;
+  }
+  for (int l2 = 0; l2 < nb; ++l2) {
+    if (have[l2]) continue;
+    int a = -1, bb = -1;
+    for (int k = lo[l2]; k < l2; ++k)
+      if (have[k]) a = k;
+    for (int k = hi[l2] - 1; k > l2; --k)
+      if (have[k]) bb = k;
+    for (int l = 0; l < nb; ++l) {
+      const int ra = l + (a - l2), rb = l + (bb - l2);
+      const bool okA = a >= 0 && ra >= lo[l] && ra < hi[l];
+      const bool okB = bb >= 0 && rb >= lo[l] && rb < hi[l];
+      double v;
+      if (okA && okB) {
+        const double va = Fr[(size_t)ra * nb + a], vb = Fr[(size_t)rb * nb + bb];
+        v = va + (vb - va) * (double)(l2 - a) / (double)(bb - a);
+      } else if (okA) {
+        v = Fr[(size_t)ra * nb + a];
+      } else if (okB) {
+        v = Fr[(size_t)rb * nb + bb];
+      } else {
+        const int sc = a >= 0 ? a : bb;
+        const int r = std::min(std::max(l + (sc - l2), lo[l]), hi[l] - 1);
+        v = Fr[(size_t)r * nb + sc];
+      }
+      Fr[(size_t)l * nb + l2] = v;
+    }
+  }
   for (int l = 0; l < nb; ++l)
     for (int l2 = 0; l2 < nb; ++l2) F[(size_t)l * nb + l2] = 0.5 * (Fr[(size_t)l * nb + l2] + Fr[(size_t)l2 * nb + l]);
+}
+
+// Simulated columns and band groups of a sampled-Fisher call: rows strictly increasing in
+// [0, nb), groups nullable (one group) or [nb] ids, every group with a simulated column.
+int parse_rows(wf_ctx* ctx, int nb, const int32_t* rows, int32_t nrows, const int32_t* groups, std::vector<int>& cols,
+               std::vector<int>& grp) {
+  cols.clear();
+  grp.assign(nb, 0);
+  if (!rows) {
+    for (int l = 0; l < nb; ++l) cols.push_back(l);
+  } else {
+    if (nrows < 1 || nrows > nb) return fail(ctx, WF_EINVAL, "need 1 <= nrows <= nbands");
+    for (int j = 0; j < nrows; ++j) {
+      if (rows[j] < 0 || rows[j] >= nb || (j > 0 && rows[j] <= rows[j - 1]))
+        return fail(ctx, WF_EINVAL, "rows must be strictly increasing band indices");
+      cols.push_back(rows[j]);
+    }
+  }
+  if (groups)
+    for (int l = 0; l < nb; ++l) grp[l] = groups[l];
+  for (int l = 0; l < nb;) {
+    int e = l + 1;
+    while (e < nb && grp[e] == grp[l]) ++e;
+    bool any = false;
+    for (int c : cols) any = any || (c >= l && c < e);
+    if (!any) return fail(ctx, WF_EINVAL, "every band group needs a simulated row");
+    l = e;
+  }
+  return WF_OK;
+}
+
+// One quadratic band-power estimate around p->theta (MAP of the data, E, b, F, Newton step);
+// with_data = false: b and F only.
+int qe_estimate(wf_ctx* ctx, const wf_problem* p, bool with_data, int nsim, uint64_t seed, const void* draws,
+                const wf_lbfgs_opts& o, const std::vector<int>& cols, const std::vector<int>& grp, double* theta_hat,
+                std::vector<double>& E, std::vector<double>& hb, std::vector<double>& hF, std::vector<double>& E0,
+                int& nc) {
+  const int nb = p->nbands;
+  std::vector<double> E2;
+  int rc = run_qe(ctx, p, with_data, nsim, seed, draws, o, cols, E, E0, E2, nc);
+  if (rc) return rc;
+  hb.assign(nb, 0.0);
+  hF.assign((size_t)nb * nb, 0.0);
+  bias_fisher(p->theta, nsim, nb, cols, grp, E0, E2, hb.data(), hF.data());
+  if (!with_data) return WF_OK;
+  std::vector<double> x(nb);
+  for (int l = 0; l < nb; ++l) x[l] = E[l] - hb[l];
+  if (!dense_solve(hF, x, nb)) return fail(ctx, WF_ENONFINITE, "singular Fisher matrix");
+  for (int l = 0; l < nb; ++l) theta_hat[l] = p->theta[l] + x[l];
+  return WF_OK;
 }
 
 // ---------------------------------------------------------------------------- operator jobs
@@ -1100,24 +1205,81 @@ int wf_simulate(wf_ctx* ctx, const wf_problem* p, int32_t nsim, uint64_t seed, i
   return WF_OK;
 }
 
-int sim_fisher(wf_ctx* ctx, const wf_problem* p, int32_t nsim, uint64_t seed, const void* draws,
-               const wf_lbfgs_opts* opts, double* F, double* b, double* E_sims, void* stream) {
+int sim_fisher_rows(wf_ctx* ctx, const wf_problem* p, int32_t nsim, uint64_t seed, const void* draws,
+                    const wf_lbfgs_opts* opts, const int32_t* rows, int32_t nrows, const int32_t* groups, double* F,
+                    double* b, double* E_sims, void* stream) {
   if (!ctx) return WF_EINVAL;
   int rc = check_problem(ctx, p, false);
   if (rc) return rc;
   if (nsim < 1 || !F || !b) return fail(ctx, WF_EINVAL, "need nsim >= 1 and F, b");
   for (int l = 0; l < p->nbands; ++l)
     if (!(p->theta[l] > 0)) return fail(ctx, WF_EINVAL, "fiducial band amplitudes must be > 0");
+  std::vector<int> cols, grp;
+  rc = parse_rows(ctx, p->nbands, rows, nrows, groups, cols, grp);
+  if (rc) return rc;
   wf_lbfgs_opts o;
   fill_opts(opts, o);
   StreamScope ss(ctx, stream);
-  std::vector<double> Ed, E0, E2;
+  std::vector<double> E, hb, hF, E0;
   int nc = 0;
-  rc = run_qe(ctx, p, false, nsim, seed, draws, o, Ed, E0, E2, nc);
+  rc = qe_estimate(ctx, p, false, nsim, seed, draws, o, cols, grp, nullptr, E, hb, hF, E0, nc);
   if (rc) return rc;
-  bias_fisher(p->theta, nsim, p->nbands, E0, E2, b, F);
+  std::copy(hb.begin(), hb.end(), b);
+  std::copy(hF.begin(), hF.end(), F);
   if (E_sims) std::copy(E0.begin(), E0.end(), E_sims);
   return nc ? WF_NOT_CONVERGED : WF_OK;
+}
+
+int sim_fisher(wf_ctx* ctx, const wf_problem* p, int32_t nsim, uint64_t seed, const void* draws,
+               const wf_lbfgs_opts* opts, double* F, double* b, double* E_sims, void* stream) {
+  return sim_fisher_rows(ctx, p, nsim, seed, draws, opts, nullptr, 0, nullptr, F, b, E_sims, stream);
+}
+
+int bandpower_iterate(wf_ctx* ctx, const wf_problem* p, int32_t nsim, uint64_t seed, const void* draws,
+                      const wf_lbfgs_opts* opts, const int32_t* rows, int32_t nrows, const int32_t* groups,
+                      int32_t max_iter, double rel_tol, double floor_frac, double* theta_hat, double* theta_hist,
+                      int32_t* n_iter, double* E, double* b, double* F, void* stream) {
+  if (!ctx) return WF_EINVAL;
+  int rc = check_problem(ctx, p, true);
+  if (rc) return rc;
+  if (nsim < 1 || !theta_hat) return fail(ctx, WF_EINVAL, "need nsim >= 1 and theta_hat");
+  if (max_iter < 1 || !(rel_tol >= 0) || !(floor_frac > 0 && floor_frac <= 1))
+    return fail(ctx, WF_EINVAL, "need max_iter >= 1, rel_tol >= 0 and 0 < floor_frac <= 1");
+  const int nb = p->nbands;
+  for (int l = 0; l < nb; ++l)
+    if (!(p->theta[l] > 0)) return fail(ctx, WF_EINVAL, "fiducial band amplitudes must be > 0");
+  std::vector<int> cols, grp;
+  rc = parse_rows(ctx, nb, rows, nrows, groups, cols, grp);
+  if (rc) return rc;
+  wf_lbfgs_opts o;
+  fill_opts(opts, o);
+  StreamScope ss(ctx, stream);
+  std::vector<double> fid(p->theta, p->theta + nb), th(nb), hE, hb, hF, E0;
+  if (theta_hist) std::copy(fid.begin(), fid.end(), theta_hist);
+  int done = 0, ncTot = 0;
+  while (done < max_iter) {
+    wf_problem q = *p;
+    q.theta = fid.data();
+    int nc = 0;
+    rc = qe_estimate(ctx, &q, true, nsim, seed, draws, o, cols, grp, th.data(), hE, hb, hF, E0, nc);
+    if (rc) return rc;
+    ncTot += nc;
+    ++done;
+    double rel = 0.0;
+    for (int l = 0; l < nb; ++l) {
+      const double nx = std::max(th[l], floor_frac * fid[l]);
+      rel = std::max(rel, std::fabs(nx - fid[l]) / fid[l]);
+      fid[l] = nx;
+    }
+    if (theta_hist) std::copy(fid.begin(), fid.end(), theta_hist + (size_t)done * nb);
+    if (rel <= rel_tol) break;
+  }
+  std::copy(th.begin(), th.end(), theta_hat);
+  if (n_iter) *n_iter = done;
+  if (E) std::copy(hE.begin(), hE.end(), E);
+  if (b) std::copy(hb.begin(), hb.end(), b);
+  if (F) std::copy(hF.begin(), hF.end(), F);
+  return ncTot ? WF_NOT_CONVERGED : WF_OK;
 }
 
 int bandpower_qe(wf_ctx* ctx, const wf_problem* p, int32_t nsim, uint64_t seed, const void* draws,
@@ -1128,21 +1290,17 @@ int bandpower_qe(wf_ctx* ctx, const wf_problem* p, int32_t nsim, uint64_t seed, 
   if (nsim < 1 || !theta_hat) return fail(ctx, WF_EINVAL, "need nsim >= 1 and theta_hat");
   for (int l = 0; l < p->nbands; ++l)
     if (!(p->theta[l] > 0)) return fail(ctx, WF_EINVAL, "fiducial band amplitudes must be > 0");
+  std::vector<int> cols, grp;
+  rc = parse_rows(ctx, p->nbands, nullptr, 0, nullptr, cols, grp);
+  if (rc) return rc;
   wf_lbfgs_opts o;
   fill_opts(opts, o);
   StreamScope ss(ctx, stream);
-  const int nb = p->nbands;
-  std::vector<double> Ed, E0, E2;
+  std::vector<double> hE, hb, hF, E0;
   int nc = 0;
-  rc = run_qe(ctx, p, true, nsim, seed, draws, o, Ed, E0, E2, nc);
+  rc = qe_estimate(ctx, p, true, nsim, seed, draws, o, cols, grp, theta_hat, hE, hb, hF, E0, nc);
   if (rc) return rc;
-  std::vector<double> hb(nb), hF((size_t)nb * nb);
-  bias_fisher(p->theta, nsim, nb, E0, E2, hb.data(), hF.data());
-  std::vector<double> x(nb);
-  for (int l = 0; l < nb; ++l) x[l] = Ed[l] - hb[l];
-  if (!dense_solve(hF, x, nb)) return fail(ctx, WF_ENONFINITE, "singular Fisher matrix");
-  for (int l = 0; l < nb; ++l) theta_hat[l] = p->theta[l] + x[l];
-  if (E) std::copy(Ed.begin(), Ed.end(), E);
+  if (E) std::copy(hE.begin(), hE.end(), E);
   if (b) std::copy(hb.begin(), hb.end(), b);
   if (F) std::copy(hF.begin(), hF.end(), F);
   return nc ? WF_NOT_CONVERGED : WF_OK;
