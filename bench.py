@@ -104,7 +104,8 @@ def cpu_child(args):
 
 def secondary_workloads(args):
     """The other workloads, one timed call each after one untimed call (inputs resident):
-    256^2 density band powers (128 simulations, 1665 solves per estimate), the scalar
+    256^2 density band powers (128 simulations, 1665 solves per estimate; then with 5 of the
+    12 Fisher rows simulated, and two steps of the fiducial iteration with those), the scalar
     512^2 density variant (127 maps), 1024^2 CMB maps (preconditioned, 16 maps) and the
     96-map uneven batch (preconditioned) against its plain one-map-at-a-time path."""
     import numpy as np
@@ -140,12 +141,33 @@ def secondary_workloads(args):
     prob = base.with_data(wf.wf_simulate(base, 1, 2000, theta_true=wl.theta_true)[0])
     nsim = 128
     opts = wf.LbfgsOpts(m=args.m, rel_grad_tol=args.tol)
-    _, dt = timed(lambda: wf.bandpower_qe(prob, nsim, 2001, opts=opts))
+    (th_all, _, _, F_all, _), dt = timed(lambda: wf.bandpower_qe(prob, nsim, 2001, opts=opts))
     ns = 1 + nsim * (1 + wl.nbands)
     out["density256_bandpowers"] = {"workload": f"256^2 density, {wl.nbands} bands, {nsim} simulations "
                                                 f"({ns} MAP solves per estimate)",
                                     "bandpower_estimates_per_s": round(1.0 / dt, 3),
                                     "solves_per_s": round(ns / dt, 1)}
+    # the same estimate with a subset of the Fisher rows simulated (the rest interpolated
+    # along the diagonals), and two steps of the fiducial iteration with it
+    rows = [0, 3, 6, 9, 11]
+    (th_r, _, _, _, F_r, _), dt_r = timed(lambda: wf.bandpower_iterate(prob, nsim, 2001, max_iter=1, rows=rows,
+                                                                       opts=opts))
+    (th_i, hist_i, _, _, _, _), dt_i = timed(lambda: wf.bandpower_iterate(prob, nsim, 2001, max_iter=2, rel_tol=0.0,
+                                                                          rows=rows, opts=opts))
+    ns_r = 1 + nsim * (1 + len(rows))
+    sig = np.diag(F_all) > 1e-6 * np.diag(F_all).max()
+    out["density256_sampled_rows"] = {
+        "workload": f"256^2 density, {wl.nbands} bands, {nsim} simulations, Fisher rows {rows} simulated "
+                    f"({ns_r} MAP solves per estimate)",
+        "bandpower_estimates_per_s": round(1.0 / dt_r, 3), "solves_per_s": round(ns_r / dt_r, 1),
+        "F_rel_frobenius_diff_vs_all_rows": round(float(np.linalg.norm(F_r - F_all) / np.linalg.norm(F_all)), 5),
+        # bands whose F_ll is below 1e-6 of the largest carry no signal (the spectrum's damping
+        # tail): their Theta_hat is undetermined in either estimate and is left out
+        "signal_bands": int(sig.sum()),
+        "theta_max_rel_diff_vs_all_rows": round(float(np.max(np.abs(th_r - th_all)[sig] / np.abs(th_all)[sig])), 5),
+        "fiducial_iteration_2_estimates_s": round(dt_i, 4),
+        "fiducial_iteration_2nd_step_rel_change": round(float(np.max((np.abs(hist_i[2] - hist_i[1]) /
+                                                                       hist_i[1])[sig])), 5)}
     # scalar 512^2 density variant
     wl = WL.config2(512)
     base = base_of(wl)

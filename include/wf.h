@@ -167,11 +167,13 @@ int bandpower_qe(wf_ctx* ctx, const wf_problem* prob, int32_t nsim, uint64_t see
  *            bands with equal ids (e.g. the E and the B bands), NULL = one group.  Every
  *            group needs at least one simulated row.
  * A column l' without simulations is interpolated along the diagonals from the nearest
- * simulated columns a < l' < b of its group: entry l reads entry l + (a - l') of column a
- * and l + (b - l') of column b, each kept inside the group of row l, linearly in the band
- * index; with one of the two outside, the other; beyond the group's first or last
- * simulated column, the one neighbour with the row clamped into the group.  F is then
- * symmetrised.  Outputs as sim_fisher; WF_EINVAL for bad rows or groups.               */
+ * simulated columns a < l' < b of its group, in units of D_l = the variance of E_l over
+ * the fiducial simulations (F_ll' / sqrt(D_l D_l') is interpolated): entry l reads entry
+ * l + (a - l') of column a and l + (b - l') of column b, each kept inside the group of row
+ * l, linearly in the band index; with one of the two outside, the other; beyond the
+ * group's first or last simulated column, the one neighbour with the row clamped into the
+ * group.  F is then symmetrised.  Outputs as sim_fisher; WF_EINVAL for bad rows or
+ * groups.                                                                               */
 int sim_fisher_rows(wf_ctx* ctx, const wf_problem* prob, int32_t nsim, uint64_t seed, const void* draws,
                     const wf_lbfgs_opts* opts, const int32_t* rows, int32_t nrows, const int32_t* groups,
                     double* F, double* b, double* E_sims, void* stream);

@@ -40,7 +40,7 @@ __all__ = [
     "lbfgs_solve", "wiener_dense", "band_E", "dchi2_dtheta", "simulate", "sim_fisher",
     "bandpower_qe", "dense_bias_fisher", "newton_update", "homogeneous_wiener",
     "homogeneous_band_moments", "band_groups", "fisher_from_columns", "sim_fisher_rows",
-    "fiducial_iteration", "bandpower_iterate",
+    "fiducial_iteration", "bandpower_iterate", "fisher_scale",
 ]
 
 
@@ -454,13 +454,17 @@ def bandpower_qe(d, W, pshape, band, theta_fid, nbands, draws, m=10, tol=1e-8, m
 # only a few of its rows need their own simulations and the rest can be interpolated
 # (sec. 3.1, discussion of the iteration count against box size).  The paper gives no
 # interpolation rule; the one used here: bands form groups of consecutive indices (one
-# group per spectrum, e.g. E and B); a column l2 of the unsymmetrised response
-# Fr[l, l2] that has no simulations of its own is taken from the nearest simulated columns
-# a < l2 < b of its group at the same diagonal offset (row l + (a - l2) of column a, row
-# l + (b - l2) of column b, each row shift kept inside the row's own group), linearly
-# in the band index; with one of the two rows outside its group the other is used; beyond
-# the first or last simulated column of a group the one neighbour is used with the row
-# clamped into its group.  F is symmetrised afterwards, as in the full estimate.
+# group per spectrum, e.g. E and B).  The response is interpolated in units of a per-band
+# scale D (the variance of E_l over the fiducial simulations, which estimates F_ll for
+# the optimal quadratic estimator, so the interpolated quantity is close to a correlation
+# and varies slowly even where F_ll spans orders of magnitude):
+# r[l, l2] = Fr[l, l2] / sqrt(D_l D_l2).  A column l2 of r that has no simulations of its
+# own is taken from the nearest simulated columns a < l2 < b of its group at the same
+# diagonal offset (row l + (a - l2) of column a, row l + (b - l2) of column b, each row
+# shift kept inside the row's own group), linearly in the band index; with one of the
+# two rows outside its group the other is used; beyond the first or last simulated
+# column of a group the one neighbour is used with the row clamped into its group.
+# Fr = sqrt(D_l D_l2) r, and F is symmetrised afterwards, as in the full estimate.
 
 def band_groups(nbands, groups=None):
     """[(start, stop)] of the band groups (consecutive indices with equal group id)."""
@@ -474,12 +478,26 @@ def band_groups(nbands, groups=None):
     return out
 
 
-def fisher_from_columns(Fcols, rows, nbands, groups=None):
-    """Symmetrised F from the simulated columns Fcols[:, j] = Fr[:, rows[j]] (see above)."""
+def fisher_scale(Es):
+    """Per-band scale D_l: the sample variance of E_l over the simulations (1 where it is
+    not positive or there is a single simulation)."""
+    Es = np.asarray(Es, np.float64)
+    if Es.shape[0] < 2:
+        return np.ones(Es.shape[1])
+    v = Es.var(0, ddof=1)
+    return np.where(v > 0, v, 1.0)
+
+
+def fisher_from_columns(Fcols, rows, nbands, groups=None, scale=None):
+    """Symmetrised F from the simulated columns Fcols[:, j] = Fr[:, rows[j]] (see above);
+    scale = D (None: all ones)."""
     rows = [int(r) for r in rows]
+    D = np.ones(nbands) if scale is None else np.asarray(scale, np.float64)
+    sq = np.sqrt(D)
     Fr = np.zeros((nbands, nbands))
     for j, r in enumerate(rows):
         Fr[:, r] = Fcols[:, j]
+    rn = Fr / np.outer(sq, sq)
     grp = band_groups(nbands, groups)
     gof = {}
     for gi, (g0, g1) in enumerate(grp):
@@ -499,18 +517,19 @@ def fisher_from_columns(Fcols, rows, nbands, groups=None):
             h0, h1 = gof[l]
             va = vb = None
             if a is not None and h0 <= l + (a - l2) < h1:
-                va = Fr[l + (a - l2), a]
+                va = rn[l + (a - l2), a]
             if b is not None and h0 <= l + (b - l2) < h1:
-                vb = Fr[l + (b - l2), b]
+                vb = rn[l + (b - l2), b]
             if va is not None and vb is not None:
-                Fr[l, l2] = va + (vb - va) * (l2 - a) / (b - a)
+                v = va + (vb - va) * (l2 - a) / (b - a)
             elif va is not None:
-                Fr[l, l2] = va
+                v = va
             elif vb is not None:
-                Fr[l, l2] = vb
+                v = vb
             else:
                 s_ = a if a is not None else b
-                Fr[l, l2] = Fr[min(max(l + (s_ - l2), h0), h1 - 1), s_]
+                v = rn[min(max(l + (s_ - l2), h0), h1 - 1), s_]
+            Fr[l, l2] = sq[l] * sq[l2] * v
     return 0.5 * (Fr + Fr.T)
 
 
@@ -532,7 +551,7 @@ def sim_fisher_rows(W, pshape, band, theta_fid, nbands, draws, rows, groups=None
             d2 = simulate(draws[i], S2, W)
             E2 = band_E(lbfgs_solve(d2, W, S_fid, m, tol, max_iter)["s"], S_fid, band, theta_fid, nbands)
             Fc[i, :, j] = (E2 - E0) / theta_fid[int(l2)]
-    return Es.mean(0), fisher_from_columns(Fc.mean(0), rows, nbands, groups), Es
+    return Es.mean(0), fisher_from_columns(Fc.mean(0), rows, nbands, groups, fisher_scale(Es)), Es
 
 
 # ----------------------------------------------------------------------------- fiducial iteration

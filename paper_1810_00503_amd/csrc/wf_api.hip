@@ -940,11 +940,13 @@ int run_qe(wf_ctx* ctx, const wf_problem* p, bool with_data, int nsim, uint64_t 
 
 // Bias b_l = <E0_l> and the symmetrised Fisher matrix from the simulated columns `cols`
 // (F_ll' from the boosted minus fiducial E of column l', eq. fisher with Delta_l' =
-// theta_l').  The other columns are interpolated along the diagonals between the nearest
-// simulated columns of the same band group (bands with equal consecutive ids in grp), the
-// row shift kept inside the row's group; linear in the band index when both neighbours'
-// rows exist, else the one that does, and beyond a group's last (first) simulated column
-// the one neighbour with the row clamped into the group.
+// theta_l').  The other columns are interpolated in units of D_l, the variance of E0_l
+// over the simulations (an estimate of F_ll for the optimal quadratic estimator): the
+// normalised response Fr_ll' / sqrt(D_l D_l') is taken along the diagonals from the
+// nearest simulated columns of the same band group (bands with equal consecutive ids in
+// grp), the row shift kept inside the row's group; linear in the band index when both
+// neighbours' rows exist, else the one that does, and beyond a group's last (first)
+// simulated column the one neighbour with the row clamped into the group.
 void bias_fisher(const double* theta, int nsim, int nb, const std::vector<int>& cols, const std::vector<int>& grp,
                  const std::vector<double>& E0, const std::vector<double>& E2, double* b, double* F) {
   const int nc = (int)cols.size();
@@ -964,6 +966,20 @@ void bias_fisher(const double* theta, int nsim, int nb, const std::vector<int>& 
       Fr[(size_t)l * nb + l2] = nsim > 0 ? s / nsim / theta[l2] : 0.0;
     }
   }
+  // per-band scale: sample variance of E0 (1 if not positive or a single simulation)
+  std::vector<double> sq(nb, 1.0);
+  if (nsim > 1)
+    for (int l = 0; l < nb; ++l) {
+      const double m = b[l];
+      double v = 0.0;
+      for (int i = 0; i < nsim; ++i) {
+        const double e = E0[(size_t)i * nb + l] - m;
+        v += e * e;
+      }
+      v /= (nsim - 1);
+      sq[l] = v > 0 ? std::sqrt(v) : 1.0;
+    }
+  auto rn = [&](int l, int l2) { return Fr[(size_t)l * nb + l2] / (sq[l] * sq[l2]); };
   // group extents [lo, hi) of every band
   std::vector<int> lo(nb), hi(nb);
   for (int l = 0; l < nb;) {
@@ -988,18 +1004,17 @@ void bias_fisher(const double* theta, int nsim, int nb, const std::vector<int>& 
       const bool okB = bb >= 0 && rb >= lo[l] && rb < hi[l];
       double v;
       if (okA && okB) {
-        const double va = Fr[(size_t)ra * nb + a], vb = Fr[(size_t)rb * nb + bb];
+        const double va = rn(ra, a), vb = rn(rb, bb);
         v = va + (vb - va) * (double)(l2 - a) / (double)(bb - a);
       } else if (okA) {
-        v = Fr[(size_t)ra * nb + a];
+        v = rn(ra, a);
       } else if (okB) {
-        v = Fr[(size_t)rb * nb + bb];
+        v = rn(rb, bb);
       } else {
         const int sc = a >= 0 ? a : bb;
-        const int r = std::min(std::max(l + (sc - l2), lo[l]), hi[l] - 1);
-        v = Fr[(size_t)r * nb + sc];
+        v = rn(std::min(std::max(l + (sc - l2), lo[l]), hi[l] - 1), sc);
       }
-      Fr[(size_t)l * nb + l2] = v;
+      Fr[(size_t)l * nb + l2] = sq[l] * sq[l2] * v;
     }
   }
   for (int l = 0; l < nb; ++l)

@@ -131,3 +131,27 @@ def test_fiducial_iteration_floor():
     th, hist = O.fiducial_iteration(lambda t: -t, t0, 3, 0.0, 0.1)
     np.testing.assert_allclose(np.array(hist), [t0, 0.1 * t0, 0.01 * t0, 0.001 * t0], rtol=1e-15)
     np.testing.assert_allclose(th, -0.01 * t0, rtol=1e-15)
+
+
+def test_scaled_toeplitz_is_reproduced_exactly_with_its_scale():
+    """Fr = diag(sqrt D) T diag(sqrt D) with T depending only on the diagonal offset (a
+    correlation-like response whose diagonal spans orders of magnitude) is reproduced
+    exactly when the interpolation works in units of D."""
+    nb = 10
+    T = _toeplitz(nb, lambda d: math.exp(-abs(d) / 1.5) * (1.0 - 0.05 * d))
+    D = np.geomspace(1e3, 1e-6, nb)
+    sq = np.sqrt(D)
+    Fr = sq[:, None] * T * sq[None, :]
+    rows = [0, 3, 4, 9]
+    got = O.fisher_from_columns(Fr[:, rows], rows, nb, None, D)
+    want = 0.5 * (Fr + Fr.T)
+    np.testing.assert_allclose(got, want, rtol=1e-13, atol=0)
+    # without the scale the interpolation of such a matrix is far off
+    raw = O.fisher_from_columns(Fr[:, rows], rows, nb)
+    assert np.abs(raw - want).max() > 1e-3 * np.abs(want).max()
+
+
+def test_fisher_scale_is_the_sample_variance():
+    Es = np.array([[1.0, 2.0, 5.0], [3.0, 2.0, 1.0], [2.0, 2.0, 3.0]])
+    np.testing.assert_allclose(O.fisher_scale(Es), [1.0, 1.0, 4.0], rtol=1e-15)
+    np.testing.assert_array_equal(O.fisher_scale(Es[:1]), np.ones(3))
