@@ -40,7 +40,8 @@ __all__ = [
     "lbfgs_solve", "wiener_dense", "band_E", "dchi2_dtheta", "simulate", "sim_fisher",
     "bandpower_qe", "dense_bias_fisher", "newton_update", "homogeneous_wiener",
     "homogeneous_band_moments", "band_groups", "fisher_from_columns", "sim_fisher_rows",
-    "fiducial_iteration", "bandpower_iterate", "fisher_scale",
+    "fiducial_iteration", "bandpower_iterate", "fisher_scale", "sim_signal", "posterior_error",
+    "dense_posterior_variance",
 ]
 
 
@@ -382,20 +383,26 @@ def dchi2_dtheta(s, pshape, band, theta, nbands) -> np.ndarray:
     return -2.0 * band_E(s, S, band, np.asarray(theta, np.float64), nbands)
 
 
-def simulate(draw, S_true, W):
-    """One simulated data map (sec. 2.4 and the procedure summary): a Gaussian random
-    field with spectrum S_true, s_k = (S_true,k / 2)^1/2 (z_re + i z_im) on the free
-    entries, x = R s, plus pixel noise of variance 1/W, zero on masked pixels.
-    draw: [2][ncomp][n][n] standard normals (part 0 signal, part 1 noise)."""
-    ncomp, n = S_true.shape[0], S_true.shape[1]
+def sim_signal(draw, S_true):
+    """The signal of a simulation (sec. 2.4): s_k = (S_true,k / 2)^1/2 (z_re + i z_im) on
+    the free entries from part 0 of draw, partners their conjugates, dead entries 0."""
+    n = S_true.shape[1]
     h = n // 2
     fr = _free_with_prior(S_true)
     zr = draw[0][:, :, 0:2 * h:2][:, :, :h]
     zi = draw[0][:, :, 1:2 * h:2][:, :, :h]
     z = np.zeros(S_true.shape, np.complex128)
     z[:, :, :h] = zr + 1j * zi
-    s = np.where(fr, np.sqrt(0.5 * S_true) * z, 0)
-    x = forward(s, fr)
+    return _fill_partners(np.where(fr, np.sqrt(0.5 * S_true) * z, 0))
+
+
+def simulate(draw, S_true, W):
+    """One simulated data map (sec. 2.4 and the procedure summary): a Gaussian random
+    field with spectrum S_true (sim_signal), x = R s, plus pixel noise of variance 1/W,
+    zero on masked pixels.
+    draw: [2][ncomp][n][n] standard normals (part 0 signal, part 1 noise)."""
+    fr = _free_with_prior(S_true)
+    x = forward(sim_signal(draw, S_true), fr)
     with np.errstate(divide="ignore"):
         sig = np.where(W > 0, 1.0 / np.sqrt(np.where(W > 0, W, 1.0)), 0.0)
     return np.where(W[None] > 0, x + sig[None] * draw[1], 0.0)
@@ -590,6 +597,50 @@ def bandpower_iterate(d, W, pshape, band, theta0, nbands, draws, max_iter, rel_t
             b, F, _ = sim_fisher_rows(W, pshape, band, th_fid, nbands, draws, rows, groups, m, tol, solve_max_iter)
         return newton_update(th_fid, F, E, b)
     return fiducial_iteration(est, theta0, max_iter, rel_tol, floor)
+
+
+# ----------------------------------------------------------------------------- posterior errors
+# The Wiener filter's residual s - s_hat has covariance S - S R^dag C^-1 R S (appendix A,
+# after eq. eq:wiener).  Its diagonal, per harmonic entry and per pixel (x = R (s - s_hat)),
+# is estimated from simulations drawn with the solve's own prior: signal and data of each
+# simulation, the MAP of the data, the residual.
+
+def posterior_error(W, pshape, band, theta, draws, m=10, tol=1e-10, max_iter=20000):
+    """Simulation estimate of the posterior variance: var_modes [ncomp][n][n/2+1] =
+    mean |s - s_hat|^2 per stored entry (partners mirror their free entries, dead 0),
+    var_pix [ncomp][n][n] = mean (R (s - s_hat))^2."""
+    S = prior_S(pshape, band, theta)
+    vm = np.zeros(S.shape)
+    vp = None
+    for dr in draws:
+        s = sim_signal(dr, S)
+        sh = lbfgs_solve(simulate(dr, S, W), W, S, m, tol, max_iter)["s"]
+        r = s - sh
+        x = forward(r, _free_with_prior(S))
+        vm += np.abs(r) ** 2
+        vp = x ** 2 if vp is None else vp + x ** 2
+    return vm / len(draws), vp / len(draws)
+
+
+def dense_posterior_variance(W, S):
+    """Exact diagonal of S - S R^dag C^-1 R S (dense, n <= 16): per stored entry the sum of
+    the posterior variances of its real and imaginary coordinates (var - var^2 G_jj with
+    G = A^T C^-1 A over the observed pixels), and per pixel the diagonal of
+    A (V - V G V) A^T."""
+    A, (comp, yy, xx, part) = _response_matrix(S)
+    var = 0.5 * S[comp, yy, xx]
+    ncomp, n = S.shape[0], S.shape[1]
+    obs = np.broadcast_to(W[None] > 0, (ncomp, n, n)).reshape(-1)
+    Ao = A[obs]
+    C = (Ao * var[None, :]) @ Ao.T
+    C[np.diag_indices_from(C)] += 1.0 / np.broadcast_to(W[None], (ncomp, n, n)).reshape(-1)[obs]
+    G = Ao.T @ np.linalg.solve(C, Ao)
+    P = np.diag(var) - (var[:, None] * G) * var[None, :]
+    vm = np.zeros(S.shape)
+    np.add.at(vm, (comp, yy, xx), np.diag(P))
+    vm = _fill_partners(vm.astype(np.complex128)).real
+    vp = np.einsum("pj,jk,pk->p", A, P, A).reshape(ncomp, n, n)
+    return vm, vp
 
 
 # ----------------------------------------------------------------------------- closed forms
