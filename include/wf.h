@@ -192,6 +192,18 @@ int bandpower_iterate(wf_ctx* ctx, const wf_problem* prob, int32_t nsim, uint64_
                       int32_t max_iter, double rel_tol, double floor_frac, double* theta_hat, double* theta_hist,
                       int32_t* n_iter, double* E, double* b, double* F, void* stream);
 
+/* Posterior error of the Wiener filter (appendix A after eq. eq:wiener: the residual
+ * s - s_hat has covariance S - S R^T C^-1 R S), estimated from nsim simulations drawn
+ * with prob's own prior (theta): signal s_i and data d_i as in wf_simulate (same draws or
+ * Philox stream, simulations 0 .. nsim - 1), s_hat_i the MAP of d_i, then
+ *   var_modes  nullable, device [ncomp][n][n/2+1] (dtype): mean_i |s_i - s_hat_i|^2 per
+ *              stored entry (kx = 0 partners mirror their free entries, dead entries 0);
+ *   var_pix    nullable, device [ncomp][n][n] (dtype): mean_i (R (s_i - s_hat_i))^2.
+ * Sums in float64.  At least one output; prob->d is not used.  WF_NOT_CONVERGED if a
+ * simulation's solve did not converge.                                                  */
+int posterior_error(wf_ctx* ctx, const wf_problem* prob, int32_t nsim, uint64_t seed, const void* draws,
+                    const wf_lbfgs_opts* opts, void* var_modes, void* var_pix, void* stream);
+
 /* operator-level calls: `batch` fields sharing prob's geometry, packed contiguously -- */
 
 /* x = R s (eq. ddecomp), or M R s with flags WF_MASK:

@@ -23,7 +23,8 @@ from ._lib import (WF_ADJ_GRAD, WF_ADJ_METRIC, WF_F32, WF_F64, WF_MASK, WF_NOT_C
 
 __all__ = [
     "load", "Context", "Problem", "LbfgsOpts", "SolveStats", "context", "map_wf_solve", "wf_simulate",
-    "sim_fisher", "sim_fisher_rows", "bandpower_qe", "bandpower_iterate", "wf_forward", "wf_adjoint",
+    "sim_fisher", "sim_fisher_rows", "bandpower_qe", "bandpower_iterate", "posterior_error", "wf_forward",
+    "wf_adjoint",
     "wf_chi2_grad", "wf_hvp", "wf_band_E",
     "WFError", "kernel_stats", "reset_kernel_stats", "set_profiling", "autograd", "set_chain_tiles",
     "get_chain_tiles",
@@ -351,6 +352,28 @@ def bandpower_iterate(problem: Problem, nsim: int, seed: int, max_iter: int = 3,
     cx.check(rc)
     del keep, r, g
     return th, hist[:nit.value + 1], E, b, F, rc
+
+
+def posterior_error(problem: Problem, nsim: int, seed: int, draws=None, opts: LbfgsOpts | None = None,
+                    want_modes: bool = True, want_pixels: bool = True, ctx: Context | None = None):
+    """Posterior error of the Wiener filter from simulations with the problem's prior
+    (residual covariance S - S R^T C^-1 R S, appendix A).  Returns (var_modes
+    [ncomp][n][n/2+1] or None, var_pix [ncomp][n][n] or None, rc) as device tensors."""
+    torch = _torch()
+    dev = problem.device_index()
+    cx = ctx or context(dev)
+    n, c = problem.n, problem.ncomp
+    vm = torch.empty((c, n, n // 2 + 1), dtype=problem.rdtype, device=problem.w.device) if want_modes else None
+    vp = torch.empty((c, n, n), dtype=problem.rdtype, device=problem.w.device) if want_pixels else None
+    keep, dp = _draws_ptr(problem, draws, nsim)
+    cp = problem.c()
+    o = _opts(opts)
+    rc = cx.lib.posterior_error(cx.h, C.byref(cp), nsim, C.c_uint64(seed), dp, C.byref(o),
+                                None if vm is None else vm.data_ptr(), None if vp is None else vp.data_ptr(),
+                                _stream(dev))
+    cx.check(rc)
+    del keep
+    return vm, vp, rc
 
 
 def _batch_shape(problem, t, kind):

@@ -52,7 +52,7 @@ struct wf_ctx {
   hipEvent_t evIn = nullptr, evOut = nullptr;
   std::map<std::pair<int, int>, void*> tw;   // (n, dtype) -> twiddles
   std::map<std::tuple<int, int, int>, bool> prepared;
-  Arena solveA, simA, opA;
+  Arena solveA, simA, opA, accA;
   int* hstat = nullptr;
   size_t hstatCap = 0;
   // instrumentation
@@ -1149,7 +1149,7 @@ void wf_destroy(wf_ctx* c) {
   if (c->cs) (void)hipStreamSynchronize(c->cs);
   if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
   for (auto& kv : c->tw) (void)hipFree(kv.second);
-  for (Arena* a : {&c->solveA, &c->simA, &c->opA})
+  for (Arena* a : {&c->solveA, &c->simA, &c->opA, &c->accA})
     if (a->base) (void)hipFree(a->base);
   if (c->hstat) (void)hipHostFree(c->hstat);
   for (auto& pe : c->pendingEv) {
@@ -1445,6 +1445,72 @@ int wf_chi2_grad(wf_ctx* ctx, const wf_problem* p, int32_t batch, const void* s,
   rc = check_problem(ctx, p, true);
   if (rc) return rc;
   return raw_chain(ctx, p, batch, s, chi2, grad_s, CM_RAW_GRAD, stream);
+}
+
+int posterior_error(wf_ctx* ctx, const wf_problem* p, int32_t nsim, uint64_t seed, const void* draws,
+                    const wf_lbfgs_opts* opts, void* var_modes, void* var_pix, void* stream) {
+  if (!ctx) return WF_EINVAL;
+  int rc = check_problem(ctx, p, false);
+  if (rc) return rc;
+  if (nsim < 1 || (!var_modes && !var_pix)) return fail(ctx, WF_EINVAL, "need nsim >= 1 and an output");
+  wf_lbfgs_opts o;
+  fill_opts(opts, o);
+  StreamScope ss(ctx, stream);
+  const int n = p->n, c = p->ncomp, dt = p->dtype;
+  const size_t rs = rsize_of(dt), eb = esize_of(dt);
+  const int64_t L = (int64_t)c * n * (n / 2), npix = (int64_t)c * n * n, next = (int64_t)c * n * (n / 2 + 1);
+  // float64 sums over all simulations, kept across the chunks
+  rc = arena_reserve(ctx, ctx->accA, align_up(sizeof(double) * next) + align_up(sizeof(double) * npix));
+  if (rc) return rc;
+  double* accM = (double*)arena_take(ctx->accA, sizeof(double) * next);
+  double* accP = (double*)arena_take(ctx->accA, sizeof(double) * npix);
+  HIPCHK(hipMemsetAsync(accM, 0, sizeof(double) * next, ctx->cs));
+  HIPCHK(hipMemsetAsync(accP, 0, sizeof(double) * npix, ctx->cs));
+  const double perInst = (double)(3 + 2 * o.m) * L * eb + 2.0 * npix * rs + 2.0 * next * eb;
+  const int chunk = (int)std::max(1.0, std::min((double)kMaxChunk, kSimBudgetBytes / perInst));
+  int notConv = 0;
+  for (int off = 0; off < nsim; off += chunk) {
+    const int cnt = std::min(nsim - off, chunk);
+    std::vector<SimEntry> ents;
+    for (int j = 0; j < cnt; ++j) ents.push_back({1, off + j, -1, -1});
+    const size_t need = prior_bytes(p) + align_up(sizeof(Job) * cnt) + align_up((size_t)npix * rs * cnt) +
+                        align_up((size_t)L * eb * cnt) + 2 * align_up((size_t)next * eb * cnt);
+    rc = arena_reserve(ctx, ctx->simA, need);
+    if (rc) return rc;
+    PriorTab pt;
+    rc = build_prior(ctx, ctx->simA, p, p->theta, pt);
+    if (rc) return rc;
+    void* dbuf = arena_take(ctx->simA, (size_t)npix * rs * cnt);
+    void* ybuf = arena_take(ctx->simA, (size_t)L * eb * cnt);   // L eb = npix rs: also a pixel batch
+    void* sbuf = arena_take(ctx->simA, (size_t)next * eb * cnt);
+    void* shbuf = arena_take(ctx->simA, (size_t)next * eb * cnt);
+    // data, MAP, signal coefficients of the simulations (same normals)
+    rc = simulate_entries(ctx, p, ents, seed, draws, 0, pt, dbuf, ybuf, 2.0);
+    if (rc) return rc;
+    std::vector<wf_problem> probs(cnt, *p);
+    for (int j = 0; j < cnt; ++j) probs[j].d = (const char*)dbuf + (size_t)j * npix * rs;
+    SolveOut so;
+    rc = solve_core(ctx, probs.data(), cnt, o, so);
+    if (rc) return rc;
+    for (int j = 0; j < cnt; ++j) {
+      notConv += so.st[j].status != WF_SOLVE_CONVERGED;
+      HIPCHK(pack_launch(dt, n, c, 1, so.w[j], 0, so.prior[j].sq, 1, nullptr, (char*)shbuf + (size_t)j * next * eb,
+                         ctx->cs));
+    }
+    HIPCHK(sim_coeffs_launch(dt, n, c, cnt, off, seed, draws ? (const char*)draws + (size_t)off * 2 * npix * rs : nullptr,
+                             pt.sq, sbuf, ctx->cs));
+    if (var_modes) HIPCHK(sqdiff_acc_launch(dt, next, 2, cnt, sbuf, shbuf, accM, ctx->cs));
+    if (var_pix) {   // R s - R s_hat = R (s - s_hat)
+      rc = wf_forward(ctx, p, cnt, sbuf, dbuf, 0, ctx->cs);
+      if (rc) return rc;
+      rc = wf_forward(ctx, p, cnt, shbuf, ybuf, 0, ctx->cs);
+      if (rc) return rc;
+      HIPCHK(sqdiff_acc_launch(dt, npix, 1, cnt, dbuf, ybuf, accP, ctx->cs));
+    }
+  }
+  if (var_modes) HIPCHK(acc_out_launch(dt, next, accM, 1.0 / nsim, var_modes, ctx->cs));
+  if (var_pix) HIPCHK(acc_out_launch(dt, npix, accP, 1.0 / nsim, var_pix, ctx->cs));
+  return notConv ? WF_NOT_CONVERGED : WF_OK;
 }
 
 int wf_hvp(wf_ctx* ctx, const wf_problem* p, int32_t batch, const void* pv, void* Dp, void* stream) {

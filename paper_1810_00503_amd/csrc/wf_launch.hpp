@@ -74,6 +74,12 @@ hipError_t unpack_launch(int dtype, int n, int c, int batch, const void* ext, vo
 hipError_t pack_launch(int dtype, int n, int c, int batch, const void* in, int64_t inStride,
                        const void* sq, int fill, void* const* outs, void* out0, hipStream_t s);
 hipError_t band_launch(int dtype, const BandJob* jobs, int count, int64_t L, hipStream_t s);
+// simulation signal coefficients (external layout), squared-difference accumulation, output
+hipError_t sim_coeffs_launch(int dtype, int n, int c, int nsim, int sim0, uint64_t seed, const void* draws,
+                             const void* sq, void* out, hipStream_t s);
+hipError_t sqdiff_acc_launch(int dtype, int64_t len, int P, int count, const void* a, const void* b, double* acc,
+                             hipStream_t s);
+hipError_t acc_out_launch(int dtype, int64_t len, const double* acc, double scale, void* out, hipStream_t s);
 int band_nblk(int64_t L);
 
 }  // namespace wf

@@ -802,6 +802,69 @@ __global__ void k_pack(int n, int C, int batch, const cpx<T>* __restrict__ in, i
   }
 }
 
+// Signal coefficients of simulations sim0 .. sim0 + nsim - 1 (sec. 2.4) in the external
+// layout [nsim][C][n][n/2+1]: s = sqrt S (z_re, z_im) / sqrt 2 on the free entries with the
+// simulation pass's normals and rounding (draws, or the Philox stream when draws is null),
+// kx = 0 partners the conjugates of their free entries, dead entries 0.  sq: internal
+// sqrt S table.
+template <typename T>
+__global__ void k_sim_coeffs(int n, int C, int nsim, int sim0, uint64_t seed, const T* __restrict__ draws,
+                             const T* __restrict__ sq, cpx<T>* __restrict__ out) {
+  const int h = n / 2;
+  const int64_t plane = (int64_t)n * (h + 1), per = (int64_t)C * plane, tot = per * nsim;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < tot; e += (int64_t)gridDim.x * blockDim.x) {
+    const int i = (int)(e / per);
+    const int64_t r0 = e % per;
+    const int c = (int)(r0 / plane);
+    const int r = (int)(r0 % plane);
+    const int ky = r / (h + 1), kx = r % (h + 1);
+    cpx<T> v = mk(T(0), T(0));
+    if (kx < h && is_live(n, ky, kx)) {
+      const bool part = is_partner(n, ky, kx);
+      const int kyr = part ? n - ky : ky;
+      const int64_t qn = ((int64_t)c * n + kyr) * n + 2 * kx;
+      cpx<T> z;
+      if (draws) {
+        const T* dr = draws + (int64_t)i * 2 * C * n * n;
+        z = mk(dr[qn], dr[qn + 1]);
+      } else {
+        double z0, z1;
+        philox_normal_pair(seed, sim0 + i, qn, z0, z1);
+        z = mk(T(z0), T(z1));
+      }
+      const T sc = sq[fidx(n, c, kyr, kx)] * T(0.70710678118654752440084436210485);
+      v = scale(z, sc);
+      if (part) v = conj(v);
+    }
+    out[e] = v;
+  }
+}
+
+// acc[e] += sum_i sum_{p < P} (a[i][e P + p] - b[i][e P + p])^2 over the count arrays of
+// len * P reals (b nullable: 0), in float64; one thread per e, fixed order in i.
+template <typename T>
+__global__ void k_sqdiff_acc(int64_t len, int P, int count, const T* __restrict__ a, const T* __restrict__ b,
+                             double* __restrict__ acc) {
+  const int64_t stride = len * P;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < len; e += (int64_t)gridDim.x * blockDim.x) {
+    double s = acc[e];
+    for (int i = 0; i < count; ++i)
+      for (int p = 0; p < P; ++p) {
+        const int64_t o = (int64_t)i * stride + e * P + p;
+        const double d = (double)a[o] - (b ? (double)b[o] : 0.0);
+        s += d * d;
+      }
+    acc[e] = s;
+  }
+}
+
+// out[e] = T(acc[e] * scale)
+template <typename T>
+__global__ void k_acc_out(int64_t len, const double* __restrict__ acc, double scale, T* __restrict__ out) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < len; e += (int64_t)gridDim.x * blockDim.x)
+    out[e] = T(acc[e] * scale);
+}
+
 // Band statistic E_l = Theta_l^-1 sum_{free k in l} |w_k|^2 for a whitened field, or
 // sum |s_k|^2 / (Theta_l S_k) for a raw one (sec. 2.3, eq. el; the free half-plane sum
 // is half the full-plane sum).  Deterministic two-stage reduction: per-block partials

@@ -91,6 +91,37 @@ hipError_t pack_launch(int dtype, int n, int c, int batch, const void* in, int64
   return hipGetLastError();
 }
 
+hipError_t sim_coeffs_launch(int dtype, int n, int c, int nsim, int sim0, uint64_t seed, const void* draws,
+                             const void* sq, void* out, hipStream_t s) {
+  const dim3 g = flat_grid((int64_t)nsim * c * n * (n / 2 + 1));
+  if (dtype == 0)
+    k_sim_coeffs<float><<<g, 256, 0, s>>>(n, c, nsim, sim0, seed, (const float*)draws, (const float*)sq,
+                                          (cpx<float>*)out);
+  else
+    k_sim_coeffs<double><<<g, 256, 0, s>>>(n, c, nsim, sim0, seed, (const double*)draws, (const double*)sq,
+                                           (cpx<double>*)out);
+  return hipGetLastError();
+}
+
+hipError_t sqdiff_acc_launch(int dtype, int64_t len, int P, int count, const void* a, const void* b, double* acc,
+                             hipStream_t s) {
+  const dim3 g = flat_grid(len);
+  if (dtype == 0)
+    k_sqdiff_acc<float><<<g, 256, 0, s>>>(len, P, count, (const float*)a, (const float*)b, acc);
+  else
+    k_sqdiff_acc<double><<<g, 256, 0, s>>>(len, P, count, (const double*)a, (const double*)b, acc);
+  return hipGetLastError();
+}
+
+hipError_t acc_out_launch(int dtype, int64_t len, const double* acc, double scale, void* out, hipStream_t s) {
+  const dim3 g = flat_grid(len);
+  if (dtype == 0)
+    k_acc_out<float><<<g, 256, 0, s>>>(len, acc, scale, (float*)out);
+  else
+    k_acc_out<double><<<g, 256, 0, s>>>(len, acc, scale, (double*)out);
+  return hipGetLastError();
+}
+
 int band_nblk(int64_t L) { return (int)((L + (int64_t)NT * BAND_EPT - 1) / ((int64_t)NT * BAND_EPT)); }
 
 hipError_t band_launch(int dtype, const BandJob* jobs, int count, int64_t L, hipStream_t s) {
