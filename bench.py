@@ -168,6 +168,15 @@ def secondary_workloads(args):
         "fiducial_iteration_2_estimates_s": round(dt_i, 4),
         "fiducial_iteration_2nd_step_rel_change": round(float(np.max((np.abs(hist_i[2] - hist_i[1]) /
                                                                        hist_i[1])[sig])), 5)}
+    # posterior error maps of the 512^2 shear workload: 127 simulations in one batched solve
+    wl = WL.config3()
+    base = base_of(wl)
+    (vm, vp, _), dt_pe = timed(lambda: wf.posterior_error(base, 127, 2200, opts=opts))
+    out["shear512_posterior_error"] = {"workload": "512^2 E/B shear, residual variance per mode and per pixel from 127 "
+                                                   "simulations (127 MAP solves)",
+                                       "estimates_per_s": round(1.0 / dt_pe, 3), "solves_per_s": round(127 / dt_pe, 1),
+                                       "mean_pixel_variance": float(vp.double().mean().item())}
+    del vm, vp
     # scalar 512^2 density variant
     wl = WL.config2(512)
     base = base_of(wl)

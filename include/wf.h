@@ -204,6 +204,22 @@ int bandpower_iterate(wf_ctx* ctx, const wf_problem* prob, int32_t nsim, uint64_
 int posterior_error(wf_ctx* ctx, const wf_problem* prob, int32_t nsim, uint64_t seed, const void* draws,
                     const wf_lbfgs_opts* opts, void* var_modes, void* var_pix, void* stream);
 
+/* Convergence as a function of scale (appendix B): the MAP of prob->d solved to the
+ * reference tolerance opts->rel_grad_tol and to each of tols[0 .. ntol-1] (one batched
+ * solve, per-instance tolerances), compared band by band:
+ *   power      HOST [ntol + 1][nbands]: band power sum_{free k in l} |s_k|^2 of the
+ *              reference (row 0) and of each looser solution;
+ *   err_power  nullable HOST [ntol][nbands]: band power of (solution t - reference);
+ *   cv         nullable HOST [nbands]: the cosmic-variance scale sqrt(2 / N_l), N_l the
+ *              full-plane modes of band l;
+ *   iters      nullable HOST [ntol + 1]: L-BFGS iterations of each solve;
+ *   s_out      nullable HOST [ntol + 1] of device pointers (entries may be NULL): the
+ *              solutions, [ncomp][n][n/2+1] complex.
+ * 1 <= ntol <= 64, tols > 0.  WF_NOT_CONVERGED if the reference did not converge.       */
+int convergence_by_band(wf_ctx* ctx, const wf_problem* prob, int32_t ntol, const double* tols,
+                        const wf_lbfgs_opts* opts, double* power, double* err_power, double* cv, int32_t* iters,
+                        void* const* s_out, void* stream);
+
 /* operator-level calls: `batch` fields sharing prob's geometry, packed contiguously -- */
 
 /* x = R s (eq. ddecomp), or M R s with flags WF_MASK:

@@ -41,7 +41,7 @@ __all__ = [
     "bandpower_qe", "dense_bias_fisher", "newton_update", "homogeneous_wiener",
     "homogeneous_band_moments", "band_groups", "fisher_from_columns", "sim_fisher_rows",
     "fiducial_iteration", "bandpower_iterate", "fisher_scale", "sim_signal", "posterior_error",
-    "dense_posterior_variance",
+    "dense_posterior_variance", "band_power", "cosmic_variance",
 ]
 
 
@@ -641,6 +641,31 @@ def dense_posterior_variance(W, S):
     vm = _fill_partners(vm.astype(np.complex128)).real
     vp = np.einsum("pj,jk,pk->p", A, P, A).reshape(ncomp, n, n)
     return vm, vp
+
+
+# ----------------------------------------------------------------------------- convergence by scale
+# Appendix B compares a map solved to a loose tolerance with a tightly converged one scale by
+# scale, against the cosmic-variance limit: here per band, by the band power of the map and
+# of its difference from the reference.
+
+def band_power(s, S, band, nbands) -> np.ndarray:
+    """sum over the free entries k of band l with S_k > 0 of |s_k|^2."""
+    fr = _free_with_prior(S)
+    out = np.zeros(nbands)
+    for l in range(nbands):
+        sel = fr & (band == l)
+        out[l] = np.sum(np.abs(s[sel]) ** 2)
+    return out
+
+
+def cosmic_variance(S, band, nbands) -> np.ndarray:
+    """sqrt(2 / N_l), N_l the full-plane modes of band l (two per free entry with S > 0)."""
+    fr = _free_with_prior(S)
+    out = np.zeros(nbands)
+    for l in range(nbands):
+        N = 2 * int(np.sum(fr & (band == l)))
+        out[l] = math.sqrt(2.0 / N) if N > 0 else 0.0
+    return out
 
 
 # ----------------------------------------------------------------------------- closed forms

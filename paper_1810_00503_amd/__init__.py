@@ -23,7 +23,8 @@ from ._lib import (WF_ADJ_GRAD, WF_ADJ_METRIC, WF_F32, WF_F64, WF_MASK, WF_NOT_C
 
 __all__ = [
     "load", "Context", "Problem", "LbfgsOpts", "SolveStats", "context", "map_wf_solve", "wf_simulate",
-    "sim_fisher", "sim_fisher_rows", "bandpower_qe", "bandpower_iterate", "posterior_error", "wf_forward",
+    "sim_fisher", "sim_fisher_rows", "bandpower_qe", "bandpower_iterate", "posterior_error", "convergence_by_band",
+    "wf_forward",
     "wf_adjoint",
     "wf_chi2_grad", "wf_hvp", "wf_band_E",
     "WFError", "kernel_stats", "reset_kernel_stats", "set_profiling", "autograd", "set_chain_tiles",
@@ -374,6 +375,37 @@ def posterior_error(problem: Problem, nsim: int, seed: int, draws=None, opts: Lb
     cx.check(rc)
     del keep
     return vm, vp, rc
+
+
+def convergence_by_band(problem: Problem, tols, opts: LbfgsOpts | None = None, want_fields: bool = False,
+                        ctx: Context | None = None):
+    """Convergence as a function of scale (appendix B): the MAP of problem.d at the
+    reference tolerance (opts.rel_grad_tol) and at each of `tols`, in one batched solve.
+    Returns (power [ntol + 1][nb], err_power [ntol][nb], cv [nb], iters [ntol + 1],
+    fields (list of ntol + 1 tensors, reference first) or None, rc)."""
+    torch = _torch()
+    dev = problem.device_index()
+    cx = ctx or context(dev)
+    t = np.ascontiguousarray(tols, dtype=np.float64)
+    nt, nb = int(t.size), problem.nbands
+    power = np.zeros((nt + 1, nb))
+    err = np.zeros((nt, nb))
+    cv = np.zeros(nb)
+    its = np.zeros(nt + 1, np.int32)
+    fields = None
+    outs = None
+    if want_fields:
+        cdt = torch.complex64 if problem.rdtype == torch.float32 else torch.complex128
+        fields = [torch.empty((problem.ncomp, problem.n, problem.n // 2 + 1), dtype=cdt, device=problem.w.device)
+                  for _ in range(nt + 1)]
+        outs = (C.c_void_p * (nt + 1))(*[f.data_ptr() for f in fields])
+    cp = problem.c()
+    o = _opts(opts)
+    ptr = lambda a: a.ctypes.data_as(C.POINTER(C.c_double))  # noqa: E731
+    rc = cx.lib.convergence_by_band(cx.h, C.byref(cp), nt, ptr(t), C.byref(o), ptr(power), ptr(err), ptr(cv),
+                                    its.ctypes.data_as(C.POINTER(C.c_int32)), outs, _stream(dev))
+    cx.check(rc)
+    return power, err, cv, its, fields, rc
 
 
 def _batch_shape(problem, t, kind):

@@ -15,7 +15,7 @@ WF_ADJ_METRIC, WF_ADJ_GRAD, WF_MASK = 0, 1, 2
 
 EXPORTS = [
     "wf_create", "wf_destroy", "wf_last_error", "wf_lbfgs_default", "map_wf_solve", "wf_simulate",
-    "sim_fisher", "sim_fisher_rows", "bandpower_qe", "bandpower_iterate", "posterior_error", "wf_forward", "wf_adjoint", "wf_chi2_grad", "wf_hvp", "wf_band_E",
+    "sim_fisher", "sim_fisher_rows", "bandpower_qe", "bandpower_iterate", "posterior_error", "convergence_by_band", "wf_forward", "wf_adjoint", "wf_chi2_grad", "wf_hvp", "wf_band_E",
     "wf_set_profiling", "wf_kernel_kinds", "wf_kernel_kind_name", "wf_get_kernel_stats",
     "wf_reset_kernel_stats", "wf_set_chain_tiles", "wf_get_chain_tiles",
 ]
@@ -76,6 +76,8 @@ def load(path: str | None = None):
     L.bandpower_iterate.argtypes = [vp, C.POINTER(WfProblem), i32, C.c_uint64, vp, C.POINTER(WfLbfgsOpts), ip, i32,
                                     ip, i32, C.c_double, C.c_double, dp, dp, ip, dp, dp, dp, vp]
     L.posterior_error.argtypes = [vp, C.POINTER(WfProblem), i32, C.c_uint64, vp, C.POINTER(WfLbfgsOpts), vp, vp, vp]
+    L.convergence_by_band.argtypes = [vp, C.POINTER(WfProblem), i32, dp, C.POINTER(WfLbfgsOpts), dp, dp, dp,
+                                      C.POINTER(i32), C.POINTER(vp), vp]
     L.wf_forward.argtypes = [vp, C.POINTER(WfProblem), i32, vp, vp, i32, vp]
     L.wf_adjoint.argtypes = [vp, C.POINTER(WfProblem), i32, vp, vp, i32, vp]
     L.wf_chi2_grad.argtypes = [vp, C.POINTER(WfProblem), i32, vp, dp, vp, vp]

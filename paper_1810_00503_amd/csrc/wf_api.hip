@@ -455,7 +455,9 @@ int tune_chain(wf_ctx* ctx, Klass& k, const std::vector<InstDesc>& hd, Job* djob
   return WF_OK;
 }
 
-int solve_core(wf_ctx* ctx, const wf_problem* probs, int B, const wf_lbfgs_opts& o, SolveOut& out) {
+// tols: nullable per-instance relative-gradient tolerances (user index), else o's
+int solve_core(wf_ctx* ctx, const wf_problem* probs, int B, const wf_lbfgs_opts& o, SolveOut& out,
+               const double* tols = nullptr) {
   const int m = o.m;
   if (m < 1 || m > MMAX) return fail(ctx, WF_EINVAL, "m must be in [1, 16]");
   // group into classes of equal (n, ncomp, dtype)
@@ -569,7 +571,7 @@ int solve_core(wf_ctx* ctx, const wf_problem* probs, int B, const wf_lbfgs_opts&
       D.esize = (int)eb;
       D.maxIter = o.max_iter;
       D.refreshEvery = o.refresh_every;
-      D.tol = o.rel_grad_tol;
+      D.tol = tols ? tols[ui] : o.rel_grad_tol;
       D.dchi2Tol = o.dchi2_tol;
       D.vbytes = (double)k.L * eb;
       out.w[ui] = D.X;
@@ -1511,6 +1513,77 @@ int posterior_error(wf_ctx* ctx, const wf_problem* p, int32_t nsim, uint64_t see
   if (var_modes) HIPCHK(acc_out_launch(dt, next, accM, 1.0 / nsim, var_modes, ctx->cs));
   if (var_pix) HIPCHK(acc_out_launch(dt, npix, accP, 1.0 / nsim, var_pix, ctx->cs));
   return notConv ? WF_NOT_CONVERGED : WF_OK;
+}
+
+int convergence_by_band(wf_ctx* ctx, const wf_problem* p, int32_t ntol, const double* tols, const wf_lbfgs_opts* opts,
+                        double* power, double* err_power, double* cv, int32_t* iters, void* const* s_out,
+                        void* stream) {
+  if (!ctx) return WF_EINVAL;
+  int rc = check_problem(ctx, p, true);
+  if (rc) return rc;
+  if (ntol < 1 || ntol > 64 || !tols || !power) return fail(ctx, WF_EINVAL, "need 1 <= ntol <= 64, tols and power");
+  for (int t = 0; t < ntol; ++t)
+    if (!(tols[t] > 0)) return fail(ctx, WF_EINVAL, "tolerances must be > 0");
+  wf_lbfgs_opts o;
+  fill_opts(opts, o);
+  StreamScope ss(ctx, stream);
+  const int B = ntol + 1, nb = p->nbands, n = p->n, c = p->ncomp, dt = p->dtype;
+  // one batched solve: the reference (opts->rel_grad_tol) and one copy per tolerance
+  std::vector<wf_problem> probs(B, *p);
+  std::vector<double> tv(B);
+  tv[0] = o.rel_grad_tol;
+  for (int t = 0; t < ntol; ++t) tv[t + 1] = tols[t];
+  SolveOut so;
+  rc = solve_core(ctx, probs.data(), B, o, so, tv.data());
+  if (rc) return rc;
+  const int64_t L = (int64_t)c * n * (n / 2);
+  if (nb > 0) {
+    const int nj = 2 * B - 1, nblk = band_nblk(L);
+    const size_t need = align_up(sizeof(BandJob) * nj) + align_up(sizeof(double) * (size_t)nj * nblk * nb) +
+                        align_up(sizeof(double) * (size_t)nj * nb);
+    rc = arena_reserve(ctx, ctx->opA, need);
+    if (rc) return rc;
+    BandJob* dj = (BandJob*)arena_take(ctx->opA, sizeof(BandJob) * nj);
+    double* part = (double*)arena_take(ctx->opA, sizeof(double) * (size_t)nj * nblk * nb);
+    double* dE = (double*)arena_take(ctx->opA, sizeof(double) * (size_t)nj * nb);
+    std::vector<BandJob> hj(nj);
+    for (int j = 0; j < nj; ++j) {
+      const int i = j < B ? j : j - B + 1;   // jobs B.. are the differences to the reference
+      hj[j].f = so.w[i];
+      hj[j].f2 = j < B ? nullptr : so.w[0];
+      hj[j].sq = so.prior[i].sq;
+      hj[j].aw = so.prior[i].a;
+      hj[j].bandI = so.prior[i].bandI;
+      hj[j].theta = so.prior[i].theta;
+      hj[j].part = part + (size_t)j * nblk * nb;
+      hj[j].E = dE + (size_t)j * nb;
+      hj[j].L = L;
+      hj[j].nbands = nb;
+      hj[j].raw = 2;
+    }
+    HIPCHK(hipMemcpyAsync(dj, hj.data(), sizeof(BandJob) * nj, hipMemcpyHostToDevice, ctx->cs));
+    HIPCHK(band_launch(dt, dj, nj, L, ctx->cs));
+    std::vector<double> hE((size_t)nj * nb);
+    HIPCHK(hipMemcpyAsync(hE.data(), dE, sizeof(double) * hE.size(), hipMemcpyDeviceToHost, ctx->cs));
+    std::vector<int32_t> bI(L);
+    HIPCHK(hipMemcpyAsync(bI.data(), so.prior[0].bandI, sizeof(int32_t) * L, hipMemcpyDeviceToHost, ctx->cs));
+    HIPCHK(hipStreamSynchronize(ctx->cs));
+    std::copy(hE.begin(), hE.begin() + (size_t)B * nb, power);
+    if (err_power) std::copy(hE.begin() + (size_t)B * nb, hE.end(), err_power);
+    if (cv) {   // sqrt(2 / N_l), N_l = full-plane modes of band l (two per free entry)
+      std::vector<int64_t> cnt(nb, 0);
+      for (int64_t e = 0; e < L; ++e)
+        if (bI[e] >= 0 && bI[e] < nb) ++cnt[bI[e]];
+      for (int l = 0; l < nb; ++l) cv[l] = cnt[l] > 0 ? std::sqrt(2.0 / (2.0 * cnt[l])) : 0.0;
+    }
+  }
+  if (iters)
+    for (int i = 0; i < B; ++i) iters[i] = so.st[i].iter;
+  if (s_out)
+    for (int i = 0; i < B; ++i)
+      if (s_out[i])
+        HIPCHK(pack_launch(dt, n, c, 1, so.w[i], 0, so.prior[i].sq, 1, nullptr, s_out[i], ctx->cs));
+  return so.st[0].status == WF_SOLVE_CONVERGED ? WF_OK : WF_NOT_CONVERGED;
 }
 
 int wf_hvp(wf_ctx* ctx, const wf_problem* p, int32_t batch, const void* pv, void* Dp, void* stream) {

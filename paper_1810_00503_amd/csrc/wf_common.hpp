@@ -217,6 +217,7 @@ struct LbState {
 // One field's band-statistic job.
 struct BandJob {
   const void* f;          // field, internal layout
+  const void* f2;         // nullable: the statistic is taken of f - f2
   const void* sq;         // sqrt S table (raw fields)
   const void* aw;         // solver-variable weight P_k (preconditioned solution), nullable
   const int32_t* bandI;   // internal band table (-1 = none / not free)
@@ -225,7 +226,7 @@ struct BandJob {
   double* E;              // [nbands] output (device)
   int64_t L;
   int nbands;
-  int raw;
+  int raw;                // 0: whitened field, E_l; 1: raw field, E_l; 2: whitened field, band power sum S |w|^2
 };
 
 // Static per-instance description of a solve.

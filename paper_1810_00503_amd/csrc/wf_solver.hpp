@@ -867,7 +867,8 @@ __global__ void k_acc_out(int64_t len, const double* __restrict__ acc, double sc
 
 // Band statistic E_l = Theta_l^-1 sum_{free k in l} |w_k|^2 for a whitened field, or
 // sum |s_k|^2 / (Theta_l S_k) for a raw one (sec. 2.3, eq. el; the free half-plane sum
-// is half the full-plane sum).  Deterministic two-stage reduction: per-block partials
+// is half the full-plane sum); or the band power sum_{free k in l} |s_k|^2 of a whitened
+// field (raw == 2).  With f2 the field is f - f2.  Deterministic two-stage reduction: per-block partials
 // for every band, then a fixed-order sum over blocks.
 constexpr int BAND_EPT = 16;
 
@@ -888,12 +889,16 @@ __global__ __launch_bounds__(NT) void k_band_part(const BandJob* __restrict__ jo
     if (e < jb.L) {
       bl[k] = jb.bandI[e];
       if (bl[k] >= 0) {
-        const cpx<T> a = f[e];
+        cpx<T> a = f[e];
+        if (jb.f2) a = sub(a, reinterpret_cast<const cpx<T>*>(jb.f2)[e]);
         double t = (double)a.x * a.x + (double)a.y * a.y;
         if (jb.aw) t *= (double)reinterpret_cast<const T*>(jb.aw)[e];
-        if (jb.raw) {
+        if (jb.raw == 1) {
           const double s = (double)sq[e];
           t /= s * s;
+        } else if (jb.raw == 2) {
+          const double s = (double)sq[e];
+          t *= s * s;
         }
         v[k] = t;
       }
@@ -913,7 +918,7 @@ __global__ void k_band_final(const BandJob* __restrict__ jobs, int nblk) {
   for (int l = threadIdx.x; l < jb.nbands; l += blockDim.x) {
     double a = 0.0;
     for (int b = 0; b < nblk; ++b) a += jb.part[(int64_t)b * jb.nbands + l];
-    jb.E[l] = a / jb.theta[l];
+    jb.E[l] = jb.raw == 2 ? a : a / jb.theta[l];
   }
 }
 

@@ -70,3 +70,35 @@ def test_posterior_error_simulations_match_dense_diagonal():
     # band-summed and map-summed: Monte Carlo errors average down
     assert abs(vm.sum() / dm.sum() - 1.0) < 3.0 / math.sqrt(nsim)
     assert abs(vp.sum() / dp.sum() - 1.0) < 3.0 / math.sqrt(nsim)
+
+
+def test_band_power_single_entries():
+    """Brute force on fields with one nonzero stored entry: a free entry with S > 0 adds
+    |v|^2 to its band only; a partner, a dead entry or an entry with S = 0 adds nothing."""
+    n = 8
+    pshape, band, theta, _ = _setup(n, 6, False)
+    S = O.prior_S(pshape, band, theta)
+    cases = [((0, 1, 2), True), ((0, 3, 0), True), ((0, 6, 0), False), ((0, 4, 1), False), ((0, 0, 0), False),
+             ((0, 2, 4), False)]
+    for (c, ky, kx), counts in cases:
+        s = np.zeros(S.shape, np.complex128)
+        s[c, ky, kx] = 3.0 - 4.0j
+        got = O.band_power(s, S, band, 2)
+        want = np.zeros(2)
+        if counts and S[c, ky, kx] > 0 and band[c, ky, kx] >= 0:
+            want[band[c, ky, kx]] = 25.0
+        np.testing.assert_array_equal(got, want, err_msg=str((ky, kx)))
+
+
+def test_cosmic_variance_counts_modes():
+    n = 12
+    pshape, band, theta, _ = _setup(n, 7, False)
+    S = O.prior_S(pshape, band, theta)
+    cv = O.cosmic_variance(S, band, 2)
+    for l in range(2):
+        N = 0
+        for ky in range(n):
+            for kx in range(n // 2 + 1):
+                free = (kx > 0 and kx < n // 2 and ky != n // 2) or (kx == 0 and 0 < ky < n // 2)
+                N += 2 * int(free and S[0, ky, kx] > 0 and band[0, ky, kx] == l)
+        assert cv[l] == math.sqrt(2.0 / N)
