@@ -105,7 +105,15 @@ typedef struct {
                              noise-aware H0 = gamma diag(1 / (1 + S_k <W>)), <W> the pixel
                              mean of w, for very red spectra.  The stop test always uses
                              the whitened gradient norm; the solution is the same MAP.   */
+  int32_t method;         /* WF_METHOD_LBFGS (0, default) or WF_METHOD_CG (1): conjugate
+                             gradients on the same operator and variable (with precond = 1
+                             the split-preconditioned CG), the same stop test, exact
+                             gradient at the start, to confirm the stop and every
+                             refresh_every iterations (then restarted); m is ignored      */
+  int32_t reserved;
 } wf_lbfgs_opts;
+
+enum { WF_METHOD_LBFGS = 0, WF_METHOD_CG = 1 };
 
 typedef struct {
   int32_t iters;          /* L-BFGS directions taken                                      */

@@ -19,7 +19,7 @@ import numpy as np
 
 from . import _lib as L
 from ._lib import (WF_ADJ_GRAD, WF_ADJ_METRIC, WF_F32, WF_F64, WF_MASK, WF_NOT_CONVERGED, WF_OK,  # noqa: F401
-                   WF_SOLVE_CONVERGED, WF_SOLVE_MAXITER, WF_SOLVE_NONFINITE)
+                   WF_SOLVE_CONVERGED, WF_SOLVE_MAXITER, WF_SOLVE_NONFINITE, WF_METHOD_LBFGS, WF_METHOD_CG)
 
 __all__ = [
     "load", "Context", "Problem", "LbfgsOpts", "SolveStats", "context", "map_wf_solve", "wf_simulate",
@@ -98,10 +98,11 @@ class LbfgsOpts:
     iters_per_poll: int = 0
     use_graph: int = 1
     precond: int = 0
+    method: int = 0   # WF_METHOD_LBFGS or WF_METHOD_CG
 
     def c(self) -> L.WfLbfgsOpts:
         return L.WfLbfgsOpts(self.m, self.max_iter, self.rel_grad_tol, self.dchi2_tol, self.refresh_every,
-                             self.iters_per_poll, self.use_graph, self.precond)
+                             self.iters_per_poll, self.use_graph, self.precond, self.method, 0)
 
 
 @dataclasses.dataclass

@@ -12,6 +12,7 @@ WF_EINVAL, WF_ESHAPE, WF_ENOMEM, WF_EHIP, WF_ENONFINITE = -1, -2, -3, -4, -5
 WF_F32, WF_F64 = 0, 1
 WF_SOLVE_CONVERGED, WF_SOLVE_MAXITER, WF_SOLVE_NONFINITE = 0, 1, 2
 WF_ADJ_METRIC, WF_ADJ_GRAD, WF_MASK = 0, 1, 2
+WF_METHOD_LBFGS, WF_METHOD_CG = 0, 1
 
 EXPORTS = [
     "wf_create", "wf_destroy", "wf_last_error", "wf_lbfgs_default", "map_wf_solve", "wf_simulate",
@@ -33,7 +34,7 @@ class WfLbfgsOpts(C.Structure):
     _fields_ = [
         ("m", C.c_int32), ("max_iter", C.c_int32), ("rel_grad_tol", C.c_double), ("dchi2_tol", C.c_double),
         ("refresh_every", C.c_int32), ("iters_per_poll", C.c_int32), ("use_graph", C.c_int32),
-        ("precond", C.c_int32),
+        ("precond", C.c_int32), ("method", C.c_int32), ("reserved", C.c_int32),
     ]
 
 

@@ -281,6 +281,8 @@ void fill_opts(const wf_lbfgs_opts* o, wf_lbfgs_opts& r) {
   if (r.max_iter <= 0) r.max_iter = 20000;
   if (!(r.rel_grad_tol > 0)) r.rel_grad_tol = 1e-6;
   if (r.precond != 0) r.precond = 1;
+  if (r.method != WF_METHOD_CG) r.method = WF_METHOD_LBFGS;
+  if (r.method == WF_METHOD_CG) r.m = 1;   // CG keeps w, g, p and Dp: one pair of the vector block
 }
 
 // ---------------------------------------------------------------------------- prior tables
@@ -611,7 +613,32 @@ int solve_core(wf_ctx* ctx, const wf_problem* probs, int B, const wf_lbfgs_opts&
         for (int w = 0; w < 3; ++w) HIPCHK(chain(ctx, k.dtype, k.n, k.c, w, djobs + k.first + g0, gc, k.tw, &k.cfg));
       }
     }
+    const bool cg = o.method == WF_METHOD_CG;
     for (auto& k : ks) {
+      if (!cg) continue;
+      const int cnt = (int)k.members.size();
+      const int dt = k.dtype == WF_F64;
+      {
+        Timed t(ctx, KK_COEF);
+        HIPCHK(lbfgs_launch(dt, m, LB_CGSTEP, dim3(cnt), ddesc + k.first, dst + k.first, djobs + k.first, cnt, ctx->cs));
+      }
+      {
+        Timed t(ctx, KK_PASSB);
+        HIPCHK(lbfgs_launch(dt, m, LB_CGPASS, dim3(k.nchunk, cnt), ddesc + k.first, dst + k.first, djobs + k.first,
+                            cnt, ctx->cs));
+      }
+      {
+        Timed t(ctx, KK_POST);
+        HIPCHK(lbfgs_launch(dt, m, LB_CGPOST, dim3(cnt), ddesc + k.first, dst + k.first, djobs + k.first, cnt, ctx->cs));
+      }
+      {
+        Timed t(ctx, KK_PASSBF);
+        HIPCHK(lbfgs_launch(dt, m, LB_CGDIR, dim3(k.nchunk, cnt), ddesc + k.first, dst + k.first, djobs + k.first, cnt,
+                            ctx->cs));
+      }
+    }
+    for (auto& k : ks) {
+      if (cg) continue;
       const int cnt = (int)k.members.size();
       const int dt = k.dtype == WF_F64;
       {
@@ -647,7 +674,7 @@ int solve_core(wf_ctx* ctx, const wf_problem* probs, int B, const wf_lbfgs_opts&
   std::string key;
   if (graph) {
     char buf[128];
-    snprintf(buf, sizeof buf, "%p/%d/%d/%d/%d|", (void*)A.base, A.gen, B, m, K);
+    snprintf(buf, sizeof buf, "%p/%d/%d/%d/%d/%d|", (void*)A.base, A.gen, B, m, K, o.method);
     key = buf;
     for (auto& k : ks) key += std::to_string(k.n) + "," + std::to_string(k.c) + "," + std::to_string(k.dtype) + "," +
                               std::to_string(k.members.size()) + "," + std::to_string(k.cfg.rbv) + "," +
@@ -684,7 +711,7 @@ int solve_core(wf_ctx* ctx, const wf_problem* probs, int B, const wf_lbfgs_opts&
         ctx->launches[KK_ROW] += K;
         ctx->launches[KK_COLFWD] += K;
         ctx->launches[KK_POST] += K;
-        ctx->launches[KK_PASSA] += K;
+        if (o.method != WF_METHOD_CG) ctx->launches[KK_PASSA] += K;
         ctx->launches[KK_COEF] += K;
         ctx->launches[KK_PASSB] += K;
         ctx->launches[KK_PASSBF] += K;
@@ -1126,6 +1153,8 @@ void wf_lbfgs_default(wf_lbfgs_opts* o) {
   o->iters_per_poll = 0;
   o->use_graph = 1;
   o->precond = 0;
+  o->method = WF_METHOD_LBFGS;
+  o->reserved = 0;
 }
 
 int wf_create(wf_ctx** out, int hip_device) {

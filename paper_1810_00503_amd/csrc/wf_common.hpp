@@ -212,6 +212,11 @@ struct LbState {
   double pkD[MMAX];        // p . Dp_j of the current direction (from the Gram entries)
   double coef[2 * MMAX + 1];   // direction on (p_0..p_{m-1}, Dp_0..Dp_{m-1}, g)
   double bytes[KK_COUNT];      // algorithmic bytes moved for this instance
+  // conjugate gradients: rho = g.g of the current gradient, beta of the next direction
+  double rho;
+  double beta;
+  int doDir;                   // the direction pass runs in this iteration
+  int pad3;
 };
 
 // One field's band-statistic job.

@@ -161,6 +161,9 @@ __global__ void k_init(InstDesc* desc, LbState* st, Job* jobs, int batch) {
   S.dchi2 = 0.0;
   S.gdotp = 0.0;
   S.pDp = 0.0;
+  S.rho = 0.0;
+  S.beta = 0.0;
+  S.doDir = 0;
   for (int k = 0; k < KK_COUNT; ++k) S.bytes[k] = 0.0;
   S.bytes[KK_MISC] += D.vbytes;   // zeroing w
   add_chain_bytes(S, D, CM_GRAD, 0);
@@ -704,6 +707,216 @@ __device__ __forceinline__ void postB_scalar(const InstDesc& D, LbState& S, Job&
   }
   S.chainMode = next;
   D.statusOut[0] = ST_RUNNING;
+}
+
+// ======================================================================== conjugate gradients
+// CG on the same quadratic, operator and variable as the L-BFGS solve (the whitened
+// variable, or the split-preconditioned one: the chain applies P^1/2 D P^1/2), an
+// alternative optimiser in the same batched engine (sec. 4 lists CG among the standard
+// choices for this problem).  Per iteration: the curvature product Dp (chain, no extra
+// dots), alpha = rho / p.Dp, w += alpha p, g += alpha Dp, rho' = g.g, beta = rho' / rho,
+// p = -g + beta p.  The exact gradient is taken at the start, to confirm the stop (the
+// same relative whitened-gradient test as L-BFGS) and every refreshEvery iterations;
+// after it the recursion restarts (beta = 0).  Vectors: w, g, p = slot 0 of the p block,
+// Dp = slot 0 of the Dp block.
+
+__device__ __forceinline__ void cg_job(Job& jb, const InstDesc& D, int mode) {
+  make_job(jb, D, mode, 0, 0u);
+  jb.gvec = nullptr;
+  jb.dpBase = nullptr;   // no solver dots in the curvature product
+}
+
+__device__ __forceinline__ void cg_stop(const InstDesc& D, LbState& S, Job& job, int status) {
+  S.status = status;
+  D.statusOut[0] = status;
+  S.chainMode = CM_NONE;
+  S.doB = 0;
+  S.doDir = 0;
+  job.mode = CM_NONE;
+}
+
+// after the chain: alpha (curvature product) or the chi^2 of an exact gradient
+__global__ __launch_bounds__(256) void k_cg_step(const InstDesc* __restrict__ desc, LbState* st, Job* jobs) {
+  const int i = blockIdx.x;
+  LbState& S = st[i];
+  if (S.status != ST_RUNNING) return;
+  const InstDesc& D = desc[i];
+  const int mode = S.chainMode;
+  const int ncol = (D.n / 2) / TB, nrow = D.c * D.n / RB_MIN;
+  __shared__ double chs[2];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  if (wv < 2) {   // one wave per partial kind, fixed-order sums
+    int kind = -1, nb = 0;
+    if (mode == CM_HV) {
+      if (wv == 0) {
+        kind = PK_VO;   // p . Dp
+        nb = ncol;
+      }
+    } else {
+      kind = wv == 0 ? PK_PRIOR : PK_RES;
+      nb = wv == 0 ? ncol : nrow;
+    }
+    double a = 0.0;
+    if (kind >= 0)
+      for (int b = lane; b < nb; b += 64) a += D.partChain[kind * D.pstride + b];
+    a = wave_sum(a);
+    if (lane == 0) chs[wv] = a;
+  }
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  if (mode == CM_HV) {
+    const double pDp = chs[0];
+    if (!(pDp > 0.0) || !isfinite(pDp)) {
+      cg_stop(D, S, jobs[i], 2);
+      return;
+    }
+    const double alpha = S.rho / pDp;
+    S.alpha[0] = alpha;
+    S.pDp = pDp;
+    S.dchi2 = 4.0 * (alpha * S.gdotp + 0.5 * alpha * alpha * pDp);
+    S.chi2 += S.dchi2;
+    S.iter += 1;
+    S.lastWasGrad = 0;
+    S.doB = 1;
+    S.bytes[KK_PASSB] += 6.0 * D.vbytes;   // w, p, g, Dp read; w, g written
+  } else {
+    S.chi2 = 2.0 * chs[0] + chs[1];
+    S.ngrad += 1;
+    S.lastGradIter = S.iter;
+    S.lastWasGrad = 1;
+    S.doB = 2;
+    S.bytes[KK_PASSB] += D.vbytes;         // g read
+  }
+}
+
+// vector pass: w += alpha p, g += alpha Dp (after a curvature product); partial sums of g.g
+// and of the whitened |g|^2 (kinds 0 and 1 of partA)
+template <typename T>
+__global__ __launch_bounds__(NT) void k_cg_pass(const InstDesc* __restrict__ desc, const LbState* __restrict__ st) {
+  const int i = blockIdx.y;
+  const LbState& S = st[i];
+  if (S.status != ST_RUNNING || !S.doB) return;
+  const InstDesc& D = desc[i];
+  using V = typename VecT<T>::type;
+  constexpr int VW = VecT<T>::W;
+  __shared__ double red[NT / 64][2];
+  const uint32_t nvec = (uint32_t)(D.L * 2 / VW);
+  const uint32_t vs = (uint32_t)(D.vstride * 2 / VW);
+  const uint32_t e0 = blockIdx.x * (uint32_t)PASS_CV + threadIdx.x;
+  V* X = reinterpret_cast<V*>(D.X);
+  const uint32_t ow = 0, og = vs, op = 2 * vs, od = (uint32_t)(2 + D.m) * vs;
+  const bool upd = S.doB == 1;
+  const T al = T(S.alpha[0]);
+  const T* ainv = reinterpret_cast<const T*>(D.ainv);
+  double gg = 0.0, gw = 0.0;
+#pragma unroll
+  for (int u = 0; u < PASS_U; ++u) {
+    const uint32_t e = e0 + (uint32_t)u * NT;
+    if (e < nvec) {
+      V g = gld(X, og + e);
+      if (upd) {
+        const V p = gld(X, op + e), dp = gld(X, od + e), w = gld(X, ow + e);
+        g = vaxpy(al, dp, g);
+        gst(X, og + e, g);
+        gst(X, ow + e, vaxpy(al, p, w));
+      }
+      const double t = vdot(g, g);
+      gg += t;
+      gw += ainv ? wnorm2(g, ainv, e) : t;
+    }
+  }
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  gg = wave_sum(gg);
+  gw = wave_sum(gw);
+  if (lane == 0) {
+    red[wv][0] = gg;
+    red[wv][1] = gw;
+  }
+  __syncthreads();
+  if (threadIdx.x < 2) {
+    double t = 0.0;
+#pragma unroll
+    for (int k = 0; k < NT / 64; ++k) t += red[k][threadIdx.x];
+    D.partA[(int64_t)blockIdx.x * NDOT + threadIdx.x] = t;
+  }
+}
+
+// after the pass: stop test, beta and the next chain
+__global__ __launch_bounds__(256) void k_cg_post(const InstDesc* __restrict__ desc, LbState* st, Job* jobs) {
+  const int i = blockIdx.x;
+  LbState& S = st[i];
+  if (S.status != ST_RUNNING || !S.doB) return;
+  const InstDesc& D = desc[i];
+  __shared__ double sums[NDOT];
+  __shared__ double part4[4][NDOT];
+  reduce_columns(D.partA, D.nchunk, NDOT, 2, sums, part4);   // (synchronises)
+  if (threadIdx.x != 0) return;
+  const double rho = sums[0], gw = sums[1];
+  const bool exact = S.doB == 2;
+  S.doB = 0;
+  S.gg = gw;
+  if (exact && S.g0norm < 0.0) S.g0norm = sqrt(gw);
+  const double g0 = S.g0norm;
+  const double rel = g0 > 0.0 ? sqrt(gw) / g0 : 0.0;
+  int status = ST_RUNNING, next = CM_HV;
+  bool restart = exact;
+  if (!isfinite(rho) || !isfinite(gw) || !isfinite(S.chi2)) {
+    status = 2;
+  } else if (rel <= D.tol || g0 == 0.0) {
+    if (exact) status = 0;
+    else next = CM_GRAD;              // confirm with the exact gradient
+  } else if (S.iter >= D.maxIter) {
+    status = 1;
+  } else if (!exact && D.dchi2Tol > 0.0 && S.iter > 0 && fabs(S.dchi2) < D.dchi2Tol) {
+    status = 0;
+  } else if (!exact && D.refreshEvery > 0 && S.iter - S.lastGradIter >= D.refreshEvery) {
+    next = CM_GRAD;
+  }
+  if (status != ST_RUNNING) {
+    cg_stop(D, S, jobs[i], status);
+    return;
+  }
+  if (next == CM_GRAD) {
+    S.doDir = 0;
+    S.chainMode = CM_GRAD;
+    cg_job(jobs[i], D, CM_GRAD);
+    add_chain_bytes(S, D, CM_GRAD, 0);
+    return;
+  }
+  S.beta = restart ? 0.0 : rho / S.rho;
+  S.rho = rho;
+  S.gdotp = -rho;   // g . p of the new direction: g is orthogonal to the previous one
+  S.doDir = 1;
+  S.bytes[KK_PASSBF] += (restart ? 2.0 : 3.0) * D.vbytes;
+  S.chainMode = CM_HV;
+  cg_job(jobs[i], D, CM_HV);
+  add_chain_bytes(S, D, CM_HV, 0);
+}
+
+// direction pass: p = -g + beta p (p = -g after an exact gradient)
+template <typename T>
+__global__ __launch_bounds__(NT) void k_cg_dir(const InstDesc* __restrict__ desc, const LbState* __restrict__ st) {
+  const int i = blockIdx.y;
+  const LbState& S = st[i];
+  if (S.status != ST_RUNNING || !S.doDir) return;
+  const InstDesc& D = desc[i];
+  using V = typename VecT<T>::type;
+  constexpr int VW = VecT<T>::W;
+  const uint32_t nvec = (uint32_t)(D.L * 2 / VW);
+  const uint32_t vs = (uint32_t)(D.vstride * 2 / VW);
+  const uint32_t e0 = blockIdx.x * (uint32_t)PASS_CV + threadIdx.x;
+  V* X = reinterpret_cast<V*>(D.X);
+  const uint32_t og = vs, op = 2 * vs;
+  const T be = T(S.beta);
+#pragma unroll
+  for (int u = 0; u < PASS_U; ++u) {
+    const uint32_t e = e0 + (uint32_t)u * NT;
+    if (e < nvec) {
+      const V g = gld(X, og + e);
+      const V p = be != T(0) ? vscale(be, gld(X, op + e)) : vscale(T(0), g);
+      gst(X, op + e, vaxpy(T(-1), g, p));
+    }
+  }
 }
 
 // ------------------------------------------------------------------------ tables and packing
