@@ -281,6 +281,21 @@ def main():
         tb.append(time.perf_counter() - t0)
     t_batch = float(np.median(tb))
     iters = [s.iters for s in st_b]
+    # the same batch with conjugate gradients (same operator, tolerance and stop test)
+    copts = wf.LbfgsOpts(m=args.m, rel_grad_tol=args.tol, method=wf.WF_METHOD_CG)
+    wf.map_wf_solve(sims, copts)
+    torch.cuda.synchronize()
+    tc = []
+    for _ in range(3):
+        t0 = time.perf_counter()
+        _, _, st_c, _ = wf.map_wf_solve(sims, copts)
+        torch.cuda.synchronize()
+        tc.append(time.perf_counter() - t0)
+    cg_line = {"solves_per_s": round(nsolve / float(np.median(tc)), 2),
+               "iters_mean": round(float(np.mean([x.iters for x in st_c])), 1),
+               "iters_max": int(max(x.iters for x in st_c)),
+               "exact_gradients_mean": round(float(np.mean([x.ngrad for x in st_c])), 1),
+               "converged": f"{sum(x.status == wf.WF_SOLVE_CONVERGED for x in st_c)}/{nsolve}"}
     tiles = wf.get_chain_tiles(args.n, 2, wf.WF_F32, nsolve)
     conv = sum(s.status == wf.WF_SOLVE_CONVERGED for s in st_b)
 
@@ -353,6 +368,7 @@ def main():
         "roofline_gradient_chain": roof_chain,
         "cpu_baseline": cpu,
         "batched_solve_only_solves_per_s": round(len(sims) / t_batch, 2),
+        "batched_solve_only_cg": cg_line,
         "plain_solves_per_s": None if plain is None else round(plain, 2),
         "speedup_batched_vs_plain": None if plain is None else round(len(sims) / t_batch / plain, 2),
         "bandpower_estimates_per_s": round(args.steps / elapsed, 3),
