@@ -41,7 +41,7 @@ __all__ = [
     "bandpower_qe", "dense_bias_fisher", "newton_update", "homogeneous_wiener",
     "homogeneous_band_moments", "band_groups", "fisher_from_columns", "sim_fisher_rows",
     "fiducial_iteration", "bandpower_iterate", "fisher_scale", "sim_signal", "posterior_error",
-    "dense_posterior_variance", "band_power", "cosmic_variance",
+    "dense_posterior_variance", "band_power", "cosmic_variance", "bmode_leakage_qe",
 ]
 
 
@@ -597,6 +597,42 @@ def bandpower_iterate(d, W, pshape, band, theta0, nbands, draws, max_iter, rel_t
             b, F, _ = sim_fisher_rows(W, pshape, band, th_fid, nbands, draws, rows, groups, m, tol, solve_max_iter)
         return newton_update(th_fid, F, E, b)
     return fiducial_iteration(est, theta0, max_iter, rel_tol, floor)
+
+
+# ----------------------------------------------------------------------------- B-mode leakage bias
+# Appendix C: instead of the full Fisher analysis for the B bands, realisations of the E->B
+# leakage are averaged into a bias, like the noise bias.  Reading used here: simulations
+# drawn with the fiducial E power and no B power, solved with the fiducial prior, give
+# b_B = <E_B> = noise bias + leakage; the B block of the Fisher matrix comes from boosted B
+# bands only (eq. fisher); with <E> linear in the true amplitudes,
+# Theta_hat_B = F_BB^-1 (E_B(d) - b_B).
+
+def bmode_leakage_qe(d, W, pshape, band, theta_fid, nbands, draws, b_bands, m=10, tol=1e-8, max_iter=20000):
+    """Returns (theta_hat_B, E_B of the data, b_B, F_BB) over the bands b_bands."""
+    theta_fid = np.asarray(theta_fid, np.float64)
+    B = [int(l) for l in b_bands]
+    th_leak = theta_fid.copy()
+    th_leak[B] = 0.0
+    S_fid = prior_S(pshape, band, theta_fid)
+    S_leak = prior_S(pshape, band, th_leak)
+    E = band_E(lbfgs_solve(d, W, S_fid, m, tol, max_iter)["s"], S_fid, band, theta_fid, nbands)
+    Eleak = np.zeros((len(draws), nbands))
+    Fr = np.zeros((nbands, len(B)))
+    for i, dr in enumerate(draws):
+        Eleak[i] = band_E(lbfgs_solve(simulate(dr, S_leak, W), W, S_fid, m, tol, max_iter)["s"], S_fid, band,
+                          theta_fid, nbands)
+        E0 = band_E(lbfgs_solve(simulate(dr, S_fid, W), W, S_fid, m, tol, max_iter)["s"], S_fid, band, theta_fid,
+                    nbands)
+        for j, l2 in enumerate(B):
+            S2 = _boosted_S(pshape, band, theta_fid, l2, 2.0)
+            E2 = band_E(lbfgs_solve(simulate(dr, S2, W), W, S_fid, m, tol, max_iter)["s"], S_fid, band, theta_fid,
+                        nbands)
+            Fr[:, j] += (E2 - E0) / theta_fid[l2]
+    Fr /= len(draws)
+    FBB = Fr[B, :]
+    FBB = 0.5 * (FBB + FBB.T)
+    bB = Eleak.mean(0)[B]
+    return np.linalg.solve(FBB, E[B] - bB), E[B], bB, FBB
 
 
 # ----------------------------------------------------------------------------- posterior errors
