@@ -167,6 +167,19 @@ int bandpower_qe(wf_ctx* ctx, const wf_problem* prob, int32_t nsim, uint64_t see
                  const wf_lbfgs_opts* opts, double* theta_hat, double* E, double* b, double* F,
                  void* stream);
 
+/* B-mode band powers with the E->B leakage treated as a bias (appendix C): nsim
+ * simulations drawn with the fiducial amplitudes except the bands b_bands (the B bands),
+ * which are set to 0, give b_B = <E_B> (noise bias plus leakage); the B block F_BB of the
+ * Fisher matrix comes from nsim fiducial and nsim * nbb boosted-B simulations (eq. fisher,
+ * symmetrised); every solve uses the fiducial prior; theta_B = F_BB^-1 (E_B(d) - b_B), which
+ * holds because <E> is linear in the true amplitudes.  nsim (2 + nbb) + 1 MAP solves
+ * against nsim (1 + nbands) + 1 for the full estimate.  Same seed / draws for both sets.
+ *   b_bands  HOST [nbb] strictly increasing band indices;
+ *   theta_b  HOST [nbb]; E_b, bias_b nullable HOST [nbb]; F_bb nullable HOST [nbb*nbb].  */
+int bmode_leakage_qe(wf_ctx* ctx, const wf_problem* prob, int32_t nsim, uint64_t seed, const void* draws,
+                     const wf_lbfgs_opts* opts, const int32_t* b_bands, int32_t nbb, double* theta_b, double* E_b,
+                     double* bias_b, double* F_bb, void* stream);
+
 /* sim_fisher with simulations for a subset of the Fisher rows only (the matrix is smooth
  * and nearly translation invariant, sec. 3.1): nsim * (1 + nrows) MAP solves.
  *   rows     HOST [nrows] strictly increasing band indices whose boosted simulations

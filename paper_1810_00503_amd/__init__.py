@@ -23,7 +23,8 @@ from ._lib import (WF_ADJ_GRAD, WF_ADJ_METRIC, WF_F32, WF_F64, WF_MASK, WF_NOT_C
 
 __all__ = [
     "load", "Context", "Problem", "LbfgsOpts", "SolveStats", "context", "map_wf_solve", "wf_simulate",
-    "sim_fisher", "sim_fisher_rows", "bandpower_qe", "bandpower_iterate", "posterior_error", "convergence_by_band",
+    "sim_fisher", "sim_fisher_rows", "bandpower_qe", "bandpower_iterate", "bmode_leakage_qe", "posterior_error",
+    "convergence_by_band",
     "wf_forward",
     "wf_adjoint",
     "wf_chi2_grad", "wf_hvp", "wf_band_E",
@@ -354,6 +355,30 @@ def bandpower_iterate(problem: Problem, nsim: int, seed: int, max_iter: int = 3,
     cx.check(rc)
     del keep, r, g
     return th, hist[:nit.value + 1], E, b, F, rc
+
+
+def bmode_leakage_qe(problem: Problem, nsim: int, seed: int, b_bands, draws=None, opts: LbfgsOpts | None = None,
+                     ctx: Context | None = None):
+    """B-mode band powers with the E->B leakage as a bias (appendix C).  Returns (theta_B,
+    E_B, b_B, F_BB, rc) as numpy arrays over the bands b_bands."""
+    dev = problem.device_index()
+    cx = ctx or context(dev)
+    bb = np.ascontiguousarray(b_bands, dtype=np.int32)
+    k = int(bb.size)
+    if k == 0:
+        raise ValueError("b_bands must name at least one band")
+    th, E, b = np.zeros(k), np.zeros(k), np.zeros(k)
+    F = np.zeros((k, k))
+    keep, dp = _draws_ptr(problem, draws, nsim)
+    cp = problem.c()
+    o = _opts(opts)
+    ptr = lambda a: a.ctypes.data_as(C.POINTER(C.c_double))  # noqa: E731
+    rc = cx.lib.bmode_leakage_qe(cx.h, C.byref(cp), nsim, C.c_uint64(seed), dp, C.byref(o),
+                                 bb.ctypes.data_as(C.POINTER(C.c_int32)), k, ptr(th), ptr(E), ptr(b), ptr(F),
+                                 _stream(dev))
+    cx.check(rc)
+    del keep
+    return th, E, b, F, rc
 
 
 def posterior_error(problem: Problem, nsim: int, seed: int, draws=None, opts: LbfgsOpts | None = None,

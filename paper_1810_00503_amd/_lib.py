@@ -16,7 +16,7 @@ WF_METHOD_LBFGS, WF_METHOD_CG = 0, 1
 
 EXPORTS = [
     "wf_create", "wf_destroy", "wf_last_error", "wf_lbfgs_default", "map_wf_solve", "wf_simulate",
-    "sim_fisher", "sim_fisher_rows", "bandpower_qe", "bandpower_iterate", "posterior_error", "convergence_by_band", "wf_forward", "wf_adjoint", "wf_chi2_grad", "wf_hvp", "wf_band_E",
+    "sim_fisher", "sim_fisher_rows", "bandpower_qe", "bandpower_iterate", "bmode_leakage_qe", "posterior_error", "convergence_by_band", "wf_forward", "wf_adjoint", "wf_chi2_grad", "wf_hvp", "wf_band_E",
     "wf_set_profiling", "wf_kernel_kinds", "wf_kernel_kind_name", "wf_get_kernel_stats",
     "wf_reset_kernel_stats", "wf_set_chain_tiles", "wf_get_chain_tiles",
 ]
@@ -76,6 +76,8 @@ def load(path: str | None = None):
                                   dp, dp, dp, vp]
     L.bandpower_iterate.argtypes = [vp, C.POINTER(WfProblem), i32, C.c_uint64, vp, C.POINTER(WfLbfgsOpts), ip, i32,
                                     ip, i32, C.c_double, C.c_double, dp, dp, ip, dp, dp, dp, vp]
+    L.bmode_leakage_qe.argtypes = [vp, C.POINTER(WfProblem), i32, C.c_uint64, vp, C.POINTER(WfLbfgsOpts),
+                                   C.POINTER(i32), i32, dp, dp, dp, dp, vp]
     L.posterior_error.argtypes = [vp, C.POINTER(WfProblem), i32, C.c_uint64, vp, C.POINTER(WfLbfgsOpts), vp, vp, vp]
     L.convergence_by_band.argtypes = [vp, C.POINTER(WfProblem), i32, dp, C.POINTER(WfLbfgsOpts), dp, dp, dp,
                                       C.POINTER(i32), C.POINTER(vp), vp]

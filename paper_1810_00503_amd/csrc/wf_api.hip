@@ -909,9 +909,11 @@ int simulate_entries(wf_ctx* ctx, const wf_problem* p, const std::vector<SimEntr
 // The solves of one band-power estimate: the data map (with_data), nsim fiducial
 // simulations and, per simulation, one with each band of `cols` boosted.  E0 [nsim][nb],
 // E2 [nsim][cols.size()][nb].
+// theta_sim: nullable amplitudes the simulations are drawn with (the solves always use
+// p->theta)
 int run_qe(wf_ctx* ctx, const wf_problem* p, bool with_data, int nsim, uint64_t seed, const void* draws,
            const wf_lbfgs_opts& o, const std::vector<int>& cols, std::vector<double>& Edata, std::vector<double>& E0,
-           std::vector<double>& E2, int& notConverged) {
+           std::vector<double>& E2, int& notConverged, const double* theta_sim = nullptr) {
   const int nb = p->nbands;
   const int nc = (int)cols.size();
   const int n = p->n, c = p->ncomp, dt = p->dtype;
@@ -938,7 +940,7 @@ int run_qe(wf_ctx* ctx, const wf_problem* p, bool with_data, int nsim, uint64_t 
     int rc = arena_reserve(ctx, ctx->simA, need);
     if (rc) return rc;
     PriorTab ptrue;
-    rc = build_prior(ctx, ctx->simA, p, p->theta, ptrue);
+    rc = build_prior(ctx, ctx->simA, p, theta_sim ? theta_sim : p->theta, ptrue);
     if (rc) return rc;
     void* dbuf = arena_take(ctx->simA, (size_t)npix * rs * cnt);
     void* ybuf = arena_take(ctx->simA, (size_t)L * eb * cnt);
@@ -1326,6 +1328,58 @@ int bandpower_iterate(wf_ctx* ctx, const wf_problem* p, int32_t nsim, uint64_t s
   if (b) std::copy(hb.begin(), hb.end(), b);
   if (F) std::copy(hF.begin(), hF.end(), F);
   return ncTot ? WF_NOT_CONVERGED : WF_OK;
+}
+
+int bmode_leakage_qe(wf_ctx* ctx, const wf_problem* p, int32_t nsim, uint64_t seed, const void* draws,
+                     const wf_lbfgs_opts* opts, const int32_t* b_bands, int32_t nbb, double* theta_b, double* E_b,
+                     double* bias_b, double* F_bb, void* stream) {
+  if (!ctx) return WF_EINVAL;
+  int rc = check_problem(ctx, p, true);
+  if (rc) return rc;
+  const int nb = p->nbands;
+  if (nsim < 1 || !theta_b || !b_bands || nbb < 1 || nbb > nb)
+    return fail(ctx, WF_EINVAL, "need nsim >= 1, theta_b and 1 <= nbb <= nbands B bands");
+  for (int j = 0; j < nbb; ++j)
+    if (b_bands[j] < 0 || b_bands[j] >= nb || (j > 0 && b_bands[j] <= b_bands[j - 1]))
+      return fail(ctx, WF_EINVAL, "b_bands must be strictly increasing band indices");
+  for (int l = 0; l < nb; ++l)
+    if (!(p->theta[l] > 0)) return fail(ctx, WF_EINVAL, "fiducial band amplitudes must be > 0");
+  wf_lbfgs_opts o;
+  fill_opts(opts, o);
+  StreamScope ss(ctx, stream);
+  const std::vector<int> cols(b_bands, b_bands + nbb);
+  // the data and simulations without B power (noise plus E->B leakage)
+  std::vector<double> thl(p->theta, p->theta + nb);
+  for (int l : cols) thl[l] = 0.0;
+  std::vector<double> Ed, El, E2u, Ed2, E0, E2;
+  int nc1 = 0, nc2 = 0;
+  rc = run_qe(ctx, p, true, nsim, seed, draws, o, std::vector<int>(), Ed, El, E2u, nc1, thl.data());
+  if (rc) return rc;
+  // fiducial simulations and boosted B bands: the B block of the Fisher matrix
+  rc = run_qe(ctx, p, false, nsim, seed, draws, o, cols, Ed2, E0, E2, nc2);
+  if (rc) return rc;
+  std::vector<double> Fbb((size_t)nbb * nbb), Fr((size_t)nbb * nbb), bb(nbb), x(nbb);
+  for (int j = 0; j < nbb; ++j) {
+    double s = 0.0;
+    for (int i = 0; i < nsim; ++i) s += El[(size_t)i * nb + cols[j]];
+    bb[j] = s / nsim;
+    for (int j2 = 0; j2 < nbb; ++j2) {   // row: band cols[j]; column: boosted band cols[j2]
+      double t = 0.0;
+      for (int i = 0; i < nsim; ++i) t += E2[((size_t)i * nbb + j2) * nb + cols[j]] - E0[(size_t)i * nb + cols[j]];
+      Fr[(size_t)j * nbb + j2] = t / nsim / p->theta[cols[j2]];
+    }
+  }
+  for (int j = 0; j < nbb; ++j)
+    for (int j2 = 0; j2 < nbb; ++j2)
+      Fbb[(size_t)j * nbb + j2] = 0.5 * (Fr[(size_t)j * nbb + j2] + Fr[(size_t)j2 * nbb + j]);
+  for (int j = 0; j < nbb; ++j) x[j] = Ed[cols[j]] - bb[j];
+  if (!dense_solve(Fbb, x, nbb)) return fail(ctx, WF_ENONFINITE, "singular B-band Fisher block");
+  std::copy(x.begin(), x.end(), theta_b);
+  if (E_b)
+    for (int j = 0; j < nbb; ++j) E_b[j] = Ed[cols[j]];
+  if (bias_b) std::copy(bb.begin(), bb.end(), bias_b);
+  if (F_bb) std::copy(Fbb.begin(), Fbb.end(), F_bb);
+  return (nc1 || nc2) ? WF_NOT_CONVERGED : WF_OK;
 }
 
 int bandpower_qe(wf_ctx* ctx, const wf_problem* p, int32_t nsim, uint64_t seed, const void* draws,

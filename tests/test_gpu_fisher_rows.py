@@ -101,3 +101,26 @@ def test_bad_rows_and_groups_are_rejected(lib):
         lib.bandpower_iterate(prob, 1, 0, max_iter=0)
     with pytest.raises(lib.WFError):
         lib.bandpower_iterate(prob, 1, 0, floor=0.0)
+
+
+def test_bmode_leakage_matches_oracle(lib):
+    """B-mode leakage bias (appendix C), identical draws: theta_B, E_B, b_B, F_BB to 1e-4."""
+    import torch
+    print("[bmode_leakage_qe]", flush=True)
+    wl = WL.shear_workload(16, 93, nbands_e=2, nbands_b=2, b_ratio=0.3)
+    nsim = 3
+    draws = WL.white_draws(wl.n, 2, nsim, 444)
+    d = oracle_data(wl, 45)
+    prob = make_problem(lib, torch, wl, "f32", d=d)
+    dt = torch.tensor(draws, dtype=torch.float32, device="cuda:0")
+    B = [2, 3]
+    th, E, b, F, rc = lib.bmode_leakage_qe(prob, nsim, 0, B, draws=dt, opts=lib.LbfgsOpts(rel_grad_tol=1e-7))
+    assert rc == 0
+    tho, Eo, bo, Fo = O.bmode_leakage_qe(d, wl.W, wl.pshape, wl.band, wl.theta_fid, wl.nbands, draws, B, tol=1e-11)
+    np.testing.assert_allclose(E, Eo, rtol=1e-4)
+    np.testing.assert_allclose(b, bo, rtol=1e-4)
+    np.testing.assert_allclose(F, Fo, rtol=1e-4, atol=1e-4 * np.abs(Fo).max())
+    np.testing.assert_allclose(th, tho, rtol=2e-4, atol=1e-4 * np.abs(tho).max())
+    for bad in ([3, 2], [0, 4]):
+        with pytest.raises(lib.WFError):
+            lib.bmode_leakage_qe(prob, 1, 0, bad)
