@@ -172,6 +172,19 @@ def secondary_workloads(args):
     # posterior error maps of the 512^2 shear workload: 127 simulations in one batched solve
     wl = WL.config3()
     base = base_of(wl)
+    # B-mode band powers with the leakage as a bias against the full estimate (6 simulations)
+    nb_e = wl.nbands // 2
+    bband = list(range(nb_e, wl.nbands))
+    dsh = wf.wf_simulate(base, 1, 2300, theta_true=wl.theta_true)[0]
+    pdat = base.with_data(dsh)
+    (thl, _, _, Fbb, _), dt_l = timed(lambda: wf.bmode_leakage_qe(pdat, 6, 2301, bband, opts=opts))
+    (thf, _, _, Ff, _), dt_f = timed(lambda: wf.bandpower_qe(pdat, 6, 2301, opts=opts))
+    sdf = np.sqrt(np.abs(np.diag(np.linalg.inv(Ff))))[bband]
+    out["shear512_bmode_leakage"] = {
+        "workload": f"512^2 E/B shear, {len(bband)} B bands, 6 simulations: leakage bias "
+                    f"({6 * (2 + len(bband)) + 1} solves) vs the full estimate ({6 * (1 + wl.nbands) + 1})",
+        "leakage_seconds": round(dt_l, 4), "full_seconds": round(dt_f, 4),
+        "theta_B_max_diff_over_sigma_full": round(float(np.max(np.abs(thl - thf[bband]) / sdf)), 4)}
     (vm, vp, _), dt_pe = timed(lambda: wf.posterior_error(base, 127, 2200, opts=opts))
     out["shear512_posterior_error"] = {"workload": "512^2 E/B shear, residual variance per mode and per pixel from 127 "
                                                    "simulations (127 MAP solves)",
