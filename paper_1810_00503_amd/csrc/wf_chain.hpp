@@ -93,6 +93,13 @@ __device__ __forceinline__ void rot2(int kx, int kys, T& c2, T& s2) {
 template <typename T>
 __device__ __forceinline__ size_t chain_lds_col(int N, int C) { return (size_t)(N + N * C * TB) * sizeof(cpx<T>); }
 
+// ------------------------------------------------------------------------ traversal order
+// Consecutive passes over a batch walk the instances in opposite orders (column passes and
+// the solver's direction pass forward, the row pass and the passes after the column-forward
+// one in reverse), so each pass starts on the instances whose vectors the previous pass
+// wrote last, which a batch the size of the memory-side cache still holds there.
+__device__ __forceinline__ int rev_instance() { return (int)(gridDim.y - 1 - blockIdx.y); }
+
 // ------------------------------------------------------------------------ per-element steps
 // Column-inverse input of component c at (ky, kx): scale (sqrt S, simulation amplitude),
 // liveness, prior partial (gradient modes).  Returns the value before the spin-2 rotation;
@@ -479,7 +486,7 @@ __global__ __launch_bounds__(NT) void k_colinv(const Job* __restrict__ jobs, con
 // ------------------------------------------------------------------------ row pass
 template <typename T, int N, int C, int RBV, bool SIMK>
 __global__ __launch_bounds__(NT) void k_row(const Job* __restrict__ jobs, const cpx<T>* __restrict__ twg) {
-  const Job& jb = jobs[blockIdx.y];
+  const Job& jb = jobs[rev_instance()];
   const int mode = jb.mode;
   if (mode == CM_NONE || (!SIMK && mode == CM_SIM)) return;
   constexpr int RB = RBV;
@@ -702,7 +709,7 @@ __global__ __launch_bounds__(NT) void k_colfwd(const Job* __restrict__ jobs, con
 // Register-staged row pass: a work-group owns RB rows of one component, E elements per
 // thread.  LDS row strides of the staging tile and of the exchange layouts (index
 // i + i / R_0 in a row) were chosen for at most 2-way bank conflicts of every access pattern.
-__host__ __device__ constexpr int rowr_e(int n) { return n <= 512 ? 8 : 16; }
+__host__ __device__ constexpr int rowr_e(int n) { return n <= 256 ? 8 : 16; }
 __host__ __device__ constexpr int rowr_rb(int n) { return rowr_e(n) * NT / (n / 2); }
 __host__ __device__ constexpr int rowr_io_stride(int H) { return H + (H == 64 ? 6 : (H == 512 ? 4 : 2)); }
 // exchange layouts: row b at b * rowr_x_stride, index i at i + i / rowr_xpad
@@ -800,11 +807,11 @@ __global__ __launch_bounds__(NT) void k_colinvr(const Job* __restrict__ jobs, co
 }
 
 // One tile (RB rows of one component) per work-group: blockIdx.x = component * (N / RB) + row
-// tile, blockIdx.y = instance.
+// tile, blockIdx.y = instance (in reverse order, see rev_instance).
 template <int N, int C>
 __global__ __launch_bounds__(NT) void k_rowr(const Job* __restrict__ jobs, const cpx<float>* __restrict__ twg) {
   using T = float;
-  const Job& jb = jobs[blockIdx.y];
+  const Job& jb = jobs[rev_instance()];
   const int mode = jb.mode;
   if (mode == CM_NONE || mode == CM_SIM) return;
   constexpr int H = N / 2, E = rowr_e(N), RB = rowr_rb(N), NE = RB * H, KS = NE / NT;

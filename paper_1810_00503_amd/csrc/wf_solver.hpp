@@ -175,7 +175,7 @@ __global__ void k_init(InstDesc* desc, LbState* st, Job* jobs, int batch) {
 // After an exact gradient: g.g, g.p_j, g.Dp_j for the kept pairs, one slot at a time.
 template <typename T, int M>
 __global__ __launch_bounds__(NT) void k_passA(const InstDesc* __restrict__ desc, const LbState* __restrict__ st) {
-  const int i = blockIdx.y;
+  const int i = rev_instance();
   const LbState& S = st[i];
   if (S.status != ST_RUNNING || S.chainMode != CM_GRAD) return;
   const InstDesc& D = desc[i];
@@ -483,7 +483,7 @@ __device__ __forceinline__ void coef_scalar(const InstDesc& D, LbState& S, Job& 
 // kernel, so the streaming pass of the others keeps its register budget).
 template <typename T, int M, bool FLUSH>
 __global__ __launch_bounds__(NT) void k_passB(const InstDesc* __restrict__ desc, const LbState* __restrict__ st) {
-  const int i = blockIdx.y;
+  const int i = rev_instance();
   const LbState& S = st[i];
   if (S.status != ST_RUNNING || !S.doB || (S.flushB != 0) != FLUSH) return;
   const InstDesc& D = desc[i];
@@ -793,7 +793,7 @@ __global__ __launch_bounds__(256) void k_cg_step(const InstDesc* __restrict__ de
 // and of the whitened |g|^2 (kinds 0 and 1 of partA)
 template <typename T>
 __global__ __launch_bounds__(NT) void k_cg_pass(const InstDesc* __restrict__ desc, const LbState* __restrict__ st) {
-  const int i = blockIdx.y;
+  const int i = rev_instance();
   const LbState& S = st[i];
   if (S.status != ST_RUNNING || !S.doB) return;
   const InstDesc& D = desc[i];
