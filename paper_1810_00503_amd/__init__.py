@@ -195,17 +195,36 @@ def _dptr(t):
     return C.cast(C.c_void_p(t.data_ptr()), C.POINTER(C.c_double))
 
 
+def _out_buffers(torch, given, problems, shape_of, dtype_of, what):
+    """Caller-supplied output tensors, checked against the problems, or new ones."""
+    if given is None:
+        return [torch.empty(shape_of(p), dtype=dtype_of(p), device=p.w.device) for p in problems]
+    given = list(given)
+    if len(given) != len(problems):
+        raise ValueError(f"{what}: {len(given)} tensors for {len(problems)} problems")
+    for i, (t, p) in enumerate(zip(given, problems)):
+        if (tuple(t.shape) != shape_of(p) or t.dtype != dtype_of(p) or t.device != p.w.device
+                or not t.is_contiguous()):
+            raise ValueError(f"{what}[{i}] must be a contiguous {dtype_of(p)} tensor of shape {shape_of(p)} "
+                             f"on {p.w.device}")
+    return given
+
+
 def map_wf_solve(problems: Sequence[Problem], opts: LbfgsOpts | None = None, want_maps: bool = False,
-                 ctx: Context | None = None):
+                 ctx: Context | None = None, out=None, maps_out=None):
     """MAP fields of a batch of problems (uneven sizes allowed).
-    Returns (s list of complex [ncomp][n][n/2+1], maps list or None, stats list, rc)."""
+    Returns (s list of complex [ncomp][n][n/2+1], maps list or None, stats list, rc).
+    `out` (and `maps_out`, which implies want_maps) are optional preallocated output tensors,
+    one per problem; a loop that passes the same ones every call allocates nothing per call."""
     torch = _torch()
     problems = list(problems)
     B = len(problems)
     dev = problems[0].device_index() if B else 0
     cx = ctx or context(dev)
-    outs = [torch.empty((p.ncomp, p.n, p.n // 2 + 1), dtype=p.cdtype, device=p.w.device) for p in problems]
-    maps = [torch.empty((p.ncomp, p.n, p.n), dtype=p.rdtype, device=p.w.device) for p in problems] if want_maps else None
+    outs = _out_buffers(torch, out, problems, lambda p: (p.ncomp, p.n, p.n // 2 + 1), lambda p: p.cdtype, "out")
+    want_maps = want_maps or maps_out is not None
+    maps = _out_buffers(torch, maps_out, problems, lambda p: (p.ncomp, p.n, p.n), lambda p: p.rdtype,
+                        "maps_out") if want_maps else None
     cps = (L.WfProblem * max(B, 1))(*[p.c() for p in problems])
     s_arr = (C.c_void_p * max(B, 1))(*[o.data_ptr() for o in outs])
     m_arr = (C.c_void_p * max(B, 1))(*[m.data_ptr() for m in maps]) if maps else None

@@ -275,11 +275,17 @@ __device__ __forceinline__ void copy_state(LbState* dst, const LbState* src) {
 }
 
 // ------------------------------------------------------------------------ coefficients
-// 256 threads per instance; thread 0 runs the scalar part out of LDS.
+// 256 threads per instance.  Thread 0 folds the new pair into the Gram blocks (or takes the
+// exact-gradient dots) and runs the stop test; all threads then copy the Gram blocks in
+// history order (position 0 = newest pair) into LDS, and thread 0 runs the two-loop recursion
+// on those with every index known at compile time, so its coefficient arrays stay in registers.
 template <int M>
-__device__ __forceinline__ void coef_scalar(const InstDesc& D, LbState& S, Job& job, int mode, const double* chs,
-                                            const double* sums, double (*sPD)[M], double (*sDD)[M], double* sal,
-                                            double* sgP, double* sgD);
+__device__ __forceinline__ int coef_update(const InstDesc& D, LbState& S, Job& job, int mode, const double* chs,
+                                           const double* sums);
+template <int M>
+__device__ __forceinline__ void coef_twoloop(const InstDesc& D, LbState& S, const double (*qPD)[M],
+                                             const double (*qDD)[M], const double* qgP, const double* qgD,
+                                             const double* qal);
 
 template <int M>
 __global__ __launch_bounds__(256) void k_coef(const InstDesc* __restrict__ desc, LbState* st, Job* jobs) {
@@ -298,14 +304,13 @@ __global__ __launch_bounds__(256) void k_coef(const InstDesc* __restrict__ desc,
     }
     return;
   }
-  // the scalar part runs in one thread on an LDS copy of the state
   __shared__ __align__(16) LbState S;
   copy_state(&S, &Sg);
-  __syncthreads();
   __shared__ double sums[NDOT];
   __shared__ double part4[4][NDOT];
   __shared__ double chs[3 + MMAX + 2];
-  __shared__ double sPD[M][M], sDD[M][M], sal[M], sgP[M], sgD[M];
+  __shared__ double qPD[M][M], qDD[M][M], qgP[M], qgD[M], qal[M];
+  __shared__ int run;
   const int ncol = (D.n / 2) / TB, nrow = D.c * D.n / RB_MIN;
   if (mode == CM_GRAD) reduce_columns(D.partA, D.nchunk, NDOT, 2 * M + 1, sums, part4);
   // chain partial sums: one wave per kind, fixed-order lane sums and a fixed shuffle tree
@@ -329,28 +334,38 @@ __global__ __launch_bounds__(256) void k_coef(const InstDesc* __restrict__ desc,
       if (lane == 0) chs[t] = a;
     }
   }
-  for (int t = threadIdx.x; t < M * M; t += blockDim.x) {
-    sPD[t / M][t % M] = S.PD[t / M][t % M];
-    sDD[t / M][t % M] = S.DD[t / M][t % M];
-  }
   __syncthreads();
-  for (int t = threadIdx.x; t < M; t += blockDim.x) {
-    sal[t] = S.alpha[t];
-    sgP[t] = S.gP[t];
-    sgD[t] = S.gD[t];
-  }
+  if (threadIdx.x == 0) run = coef_update<M>(D, S, jobs[i], mode, chs, sums);
   __syncthreads();
-  if (threadIdx.x == 0) coef_scalar<M>(D, S, jobs[i], mode, chs, sums, sPD, sDD, sal, sgP, sgD);
+  if (run) {   // (uniform: read from LDS after the barrier)
+    const int nh = S.nhist, head = S.head;
+    for (int t = threadIdx.x; t < M * M; t += blockDim.x) {
+      const int j = t / M, u = t % M;
+      const bool in = j < nh && u < nh;
+      const int sj = slot_of(head, j, M), su = slot_of(head, u, M);
+      qPD[j][u] = in ? S.PD[sj][su] : 0.0;
+      qDD[j][u] = in ? S.DD[sj][su] : 0.0;
+    }
+    for (int t = threadIdx.x; t < M; t += blockDim.x) {
+      const bool in = t < nh;
+      const int sj = slot_of(head, t, M);
+      qgP[t] = in ? S.gP[sj] : 0.0;
+      qgD[t] = in ? S.gD[sj] : 0.0;
+      qal[t] = in ? S.alpha[sj] : 0.0;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) coef_twoloop<M>(D, S, qPD, qDD, qgP, qgD, qal);
+  }
   __syncthreads();
   copy_state(&Sg, &S);
 }
 
+// Folds the last curvature product into the state (CM_HV) or takes the exact gradient's
+// dots (CM_GRAD); returns 1 when a new direction is to be formed.
 template <int M>
-__device__ __forceinline__ void coef_scalar(const InstDesc& D, LbState& S, Job& job, int mode, const double* chs,
-                                            const double* sums, double (*sPD)[M], double (*sDD)[M], double* sal,
-                                            double* sgP, double* sgD) {
+__device__ __forceinline__ int coef_update(const InstDesc& D, LbState& S, Job& job, int mode, const double* chs,
+                                           const double* sums) {
   int status = ST_RUNNING;
-  int nh = S.nhist, head = S.head;
   if (mode == CM_HV) {
     const double pDp = chs[0], DpDp = chs[1], DpG = chs[2];
     if (!(pDp > 0.0) || !isfinite(pDp) || !isfinite(DpDp)) {
@@ -359,9 +374,9 @@ __device__ __forceinline__ void coef_scalar(const InstDesc& D, LbState& S, Job& 
       job.mode = CM_NONE;
       S.chainMode = CM_NONE;
       S.doB = 0;
-      return;
+      return 0;
     }
-    const int ns = S.newslot;
+    const int nh = S.nhist, head = S.head, ns = S.newslot;
     const double alpha = -S.gdotp / pDp;
     // Gram entries of the new pair (p_k, Dp_k) in slot ns against the kept pairs: p_k . Dp_j
     // from the previous pass B, p_j . Dp_k = p_k . Dp_j (D is symmetric), Dp_k . Dp_j
@@ -369,24 +384,22 @@ __device__ __forceinline__ void coef_scalar(const InstDesc& D, LbState& S, Job& 
     for (int j = 0; j < nh; ++j) {
       const int sj = slot_of(head, j, M);
       if (sj == ns) continue;
-      sPD[ns][sj] = S.pkD[sj];
-      sPD[sj][ns] = S.pkD[sj];
-      sDD[ns][sj] = chs[3 + sj];
-      sDD[sj][ns] = chs[3 + sj];
+      const double pd = S.pkD[sj], dd = chs[3 + sj];
+      S.PD[ns][sj] = pd;
+      S.PD[sj][ns] = pd;
+      S.DD[ns][sj] = dd;
+      S.DD[sj][ns] = dd;
       // one-step update of the dots of g_{k+1} = g_k + alpha Dp_k with the kept pairs
-      sgP[sj] += alpha * sPD[sj][ns];
-      sgD[sj] += alpha * sDD[ns][sj];
+      S.gP[sj] += alpha * pd;
+      S.gD[sj] += alpha * dd;
     }
-    sPD[ns][ns] = pDp;
-    sDD[ns][ns] = DpDp;
-    sgP[ns] = S.gdotp + alpha * pDp;
-    sgD[ns] = DpG + alpha * DpDp;
-    sal[ns] = alpha;
-    head = ns;
-    nh = nh + 1 < M ? nh + 1 : M;
-    S.head = head;
-    S.nhist = nh;
+    S.PD[ns][ns] = pDp;
+    S.DD[ns][ns] = DpDp;
+    S.gP[ns] = S.gdotp + alpha * pDp;
+    S.gD[ns] = DpG + alpha * DpDp;
     S.alpha[ns] = alpha;
+    S.head = ns;
+    S.nhist = nh + 1 < M ? nh + 1 : M;
     S.pending = 1;
     S.npend += 1;
     S.pDp = pDp;
@@ -394,17 +407,8 @@ __device__ __forceinline__ void coef_scalar(const InstDesc& D, LbState& S, Job& 
     S.chi2 += S.dchi2;
     S.iter += 1;
     S.lastWasGrad = 0;
-    for (int j = 0; j < nh; ++j) {
-      const int sj = slot_of(head, j, M);
-      for (int t = 0; t < nh; ++t) {
-        const int st2 = slot_of(head, t, M);
-        S.PD[sj][st2] = sPD[sj][st2];
-        S.DD[sj][st2] = sDD[sj][st2];
-      }
-      S.gP[sj] = sgP[sj];
-      S.gD[sj] = sgD[sj];
-    }
   } else if (mode == CM_GRAD) {
+    const int nh = S.nhist, head = S.head;
     S.chi2 = 2.0 * chs[3 + M] + chs[4 + M];
     S.ngrad += 1;
     S.lastGradIter = S.iter;
@@ -414,8 +418,6 @@ __device__ __forceinline__ void coef_scalar(const InstDesc& D, LbState& S, Job& 
     S.bytes[KK_PASSA] += D.vbytes * (1.0 + 2.0 * nh);
     for (int j = 0; j < nh; ++j) {
       const int sj = slot_of(head, j, M);
-      sgP[sj] = sums[j];
-      sgD[sj] = sums[M + j];
       S.gP[sj] = sums[j];
       S.gD[sj] = sums[M + j];
     }
@@ -434,41 +436,63 @@ __device__ __forceinline__ void coef_scalar(const InstDesc& D, LbState& S, Job& 
     job.mode = CM_NONE;
     S.chainMode = CM_NONE;
     S.doB = 0;
-    return;
+    return 0;
   }
-  // two-loop recursion in the coefficients of (p_0..p_{M-1}, Dp_0..Dp_{M-1}, g)
-  double c[2 * M + 1];
-  for (int k = 0; k < 2 * M + 1; ++k) c[k] = 0.0;
-  c[2 * M] = 1.0;
-  double a[M], rho[M];
-  int sl[M];
-  for (int j = 0; j < M; ++j) sl[j] = slot_of(head, j, M);
-  for (int j = 0; j < nh; ++j) {           // newest to oldest
-    const int s = sl[j];
-    const double al = sal[s];
-    rho[j] = 1.0 / (al * al * sPD[s][s]);
-    double sq = c[2 * M] * sgP[s];
-    for (int t = 0; t < nh; ++t) sq += c[M + sl[t]] * sPD[s][sl[t]];
-    a[j] = rho[j] * al * sq;
-    c[M + s] -= a[j] * al;
+  return 1;
+}
+
+// Two-loop recursion in the coefficients of (p_0..p_{M-1}, Dp_0..Dp_{M-1}, g) by history
+// position; entries at positions >= nhist are zero in the LDS copies.
+template <int M>
+__device__ __forceinline__ void coef_twoloop(const InstDesc& D, LbState& S, const double (*qPD)[M],
+                                             const double (*qDD)[M], const double* qgP, const double* qgD,
+                                             const double* qal) {
+  const int nh = S.nhist, head = S.head;
+  double cP[M], cD[M], a[M], rho[M];
+  double cg = 1.0;
+#pragma unroll
+  for (int j = 0; j < M; ++j) {
+    cP[j] = 0.0;
+    cD[j] = 0.0;
+    a[j] = 0.0;
+    rho[j] = 0.0;
+  }
+#pragma unroll
+  for (int j = 0; j < M; ++j) {   // newest to oldest
+    if (j < nh) {
+      const double al = qal[j];
+      rho[j] = 1.0 / (al * al * qPD[j][j]);
+      double sq = cg * qgP[j];
+#pragma unroll
+      for (int t = 0; t < j; ++t) sq += cD[t] * qPD[j][t];
+      a[j] = rho[j] * al * sq;
+      cD[j] -= a[j] * al;
+    }
   }
   if (nh > 0) {
-    const double gam = sPD[head][head] / sDD[head][head];
-    for (int k = 0; k < 2 * M + 1; ++k) c[k] *= gam;
+    const double gam = qPD[0][0] / qDD[0][0];
+    cg *= gam;
+#pragma unroll
+    for (int t = 0; t < M; ++t) cD[t] *= gam;
   }
-  for (int j = nh - 1; j >= 0; --j) {      // oldest to newest
-    const int s = sl[j];
-    const double al = sal[s];
-    double yr = c[2 * M] * sgD[s];
-    for (int t = 0; t < nh; ++t) yr += c[M + sl[t]] * sDD[s][sl[t]] + c[sl[t]] * sPD[sl[t]][s];
-    const double beta = rho[j] * al * yr;
-    c[s] += al * (a[j] - beta);
+#pragma unroll
+  for (int j = M - 1; j >= 0; --j) {   // oldest to newest
+    if (j < nh) {
+      const double al = qal[j];
+      double yr = cg * qgD[j];
+#pragma unroll
+      for (int t = 0; t < M; ++t) yr += cD[t] * qDD[j][t] + cP[t] * qPD[t][j];
+      const double beta = rho[j] * al * yr;
+      cP[j] += al * (a[j] - beta);
+    }
   }
-  for (int k = 0; k < M; ++k) {
-    S.coef[k] = -c[k];
-    S.coef[MMAX + k] = -c[M + k];
+#pragma unroll
+  for (int j = 0; j < M; ++j) {   // every slot: the kept pairs' coefficients, zero for the others
+    const int sj = slot_of(head, j, M);
+    S.coef[sj] = j < nh ? -cP[j] : 0.0;
+    S.coef[MMAX + sj] = j < nh ? -cD[j] : 0.0;
   }
-  S.coef[2 * MMAX] = -c[2 * M];
+  S.coef[2 * MMAX] = -cg;
   S.newslot = (head + 1) % M;
   S.doB = 1;
   S.dirB = 1;
@@ -610,7 +634,7 @@ __global__ __launch_bounds__(NT) void k_passB(const InstDesc* __restrict__ desc,
 
 // ------------------------------------------------------------------------ post B
 template <int M>
-__device__ __forceinline__ void postB_scalar(const InstDesc& D, LbState& S, Job& job, const double* sums);
+__device__ __forceinline__ int postB_scalar(const InstDesc& D, LbState& S, Job& job, const double* sums);
 
 template <int M>
 __global__ __launch_bounds__(256) void k_postB(const InstDesc* __restrict__ desc, LbState* st, Job* jobs) {
@@ -623,14 +647,31 @@ __global__ __launch_bounds__(256) void k_postB(const InstDesc* __restrict__ desc
   copy_state(&S, &Sg);
   __shared__ double sums[NDOT];
   __shared__ double part4[4][NDOT];
+  __shared__ int next;
   reduce_columns(D.partA, D.nchunk, NDOT, 2 * M + 2, sums, part4);   // (synchronises)
-  if (threadIdx.x == 0) postB_scalar<M>(D, S, jobs[i], sums);
+  if (threadIdx.x == 0) next = postB_scalar<M>(D, S, jobs[i], sums);
+  __syncthreads();
+  if (next == CM_HV) {   // (uniform) p . Dp_j of the new direction, one kept pair per thread
+    const int nh = S.nhist, head = S.head;
+    if ((int)threadIdx.x < nh) {
+      const int sj = slot_of(head, threadIdx.x, M);
+      // from its coefficients: p = sum c b, b in {p_i, Dp_i, g}
+      double v = S.coef[2 * MMAX] * S.gD[sj];
+      for (int t = 0; t < nh; ++t) {
+        const int st2 = slot_of(head, t, M);
+        v += S.coef[st2] * S.PD[st2][sj] + S.coef[MMAX + st2] * S.DD[st2][sj];
+      }
+      S.pkD[sj] = v;
+    }
+  }
   __syncthreads();
   copy_state(&Sg, &S);
 }
 
+// Stop test and next chain mode; returns that mode (CM_NONE once stopped).  For CM_HV the
+// caller fills pkD with the new direction's dots with the kept Dp.
 template <int M>
-__device__ __forceinline__ void postB_scalar(const InstDesc& D, LbState& S, Job& job, const double* sums) {
+__device__ __forceinline__ int postB_scalar(const InstDesc& D, LbState& S, Job& job, const double* sums) {
   const int nh = S.nhist, head = S.head, ns = S.newslot, dir = S.dirB;
   S.doB = 0;
   S.pending = 0;
@@ -678,21 +719,12 @@ __device__ __forceinline__ void postB_scalar(const InstDesc& D, LbState& S, Job&
     D.statusOut[0] = status;
     job.mode = CM_NONE;
     S.chainMode = CM_NONE;
-    return;
+    return CM_NONE;
   }
-  uint32_t mask = 0u;
   if (next == CM_HV) {
-    // p . Dp_j of the new direction from its coefficients: p = sum c b, b in {p_i, Dp_i, g}
-    for (int j = 0; j < nh; ++j) {
-      const int sj = sl[j];
-      double v = S.coef[2 * MMAX] * S.gD[sj];
-      for (int t = 0; t < nh; ++t) {
-        const int st2 = sl[t];
-        v += S.coef[st2] * S.PD[st2][sj] + S.coef[MMAX + st2] * S.DD[st2][sj];
-      }
-      S.pkD[sj] = v;
-      if (sj != ns) mask |= 1u << sj;
-    }
+    uint32_t mask = 0u;
+    for (int j = 0; j < nh; ++j)
+      if (sl[j] != ns) mask |= 1u << sl[j];
     add_chain_bytes(S, D, CM_HV, 1 + __popc(mask));
     make_job(job, D, CM_HV, ns, mask);
   } else {
@@ -707,6 +739,7 @@ __device__ __forceinline__ void postB_scalar(const InstDesc& D, LbState& S, Job&
   }
   S.chainMode = next;
   D.statusOut[0] = ST_RUNNING;
+  return next;
 }
 
 // ======================================================================== conjugate gradients
@@ -913,8 +946,7 @@ __global__ __launch_bounds__(NT) void k_cg_dir(const InstDesc* __restrict__ desc
     const uint32_t e = e0 + (uint32_t)u * NT;
     if (e < nvec) {
       const V g = gld(X, og + e);
-      const V p = be != T(0) ? vscale(be, gld(X, op + e)) : vscale(T(0), g);
-      gst(X, op + e, vaxpy(T(-1), g, p));
+      gst(X, op + e, be != T(0) ? vaxpy(T(-1), g, vscale(be, gld(X, op + e))) : vscale(T(-1), g));
     }
   }
 }

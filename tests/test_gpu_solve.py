@@ -280,3 +280,36 @@ def test_preconditioned_solve_same_map(lib, kind, n):
     # band statistic of the preconditioned solution equals the oracle's
     E = lib.wf_band_E(prob, torch.tensor(s1[0], dtype=prob.cdtype, device="cuda:0"))
     np.testing.assert_allclose(E, O.band_E(ref["s"], S, wl.band, wl.theta_fid, wl.nbands), rtol=3e-5)
+
+
+def test_map_solve_into_caller_buffers(lib):
+    """Preallocated outputs (reused across calls, uneven batch) hold the same fields and maps as
+    fresh ones; wrong shapes, dtypes or counts are rejected before any launch."""
+    import torch
+    print("[solve into caller buffers]", flush=True)
+    wls = [WL.density_workload(32, 61, nbands=3, holes=2, target_mask=0.2),
+           WL.shear_workload(64, 62, nbands_e=3, nbands_b=3), WL.density_workload(48, 63, nbands=4)]
+    ds = [oracle_data(wl, 70 + i) for i, wl in enumerate(wls)]
+    probs = [make_problem(lib, torch, wl, "f32", d=d) for wl, d in zip(wls, ds)]
+    opts = lib.LbfgsOpts(rel_grad_tol=1e-7)
+    s0, m0, st0, rc0 = lib.map_wf_solve(probs, opts, want_maps=True)
+    assert rc0 == 0
+    out = [torch.full_like(x, float("nan")) for x in s0]
+    mout = [torch.full_like(x, float("nan")) for x in m0]
+    for call in range(2):
+        s1, m1, st1, rc1 = lib.map_wf_solve(probs, opts, out=out, maps_out=mout)
+        assert rc1 == 0 and all(a is b for a, b in zip(s1, out)) and all(a is b for a, b in zip(m1, mout))
+        for i, (wl, d) in enumerate(zip(wls, ds)):
+            a, b = s1[i].cpu().numpy(), s0[i].cpu().numpy()
+            assert np.all(np.isfinite(a)) and rel_l2(a, b) < 1e-6, (call, i)
+            assert rel_l2(m1[i].cpu().numpy(), m0[i].cpu().numpy()) < 1e-6
+            S = O.prior_S(wl.pshape, wl.band, wl.theta_fid)
+            ref = O.lbfgs_solve(d, wl.W, S, tol=1e-11, max_iter=50000)["s"] if call == 0 else None
+            if ref is not None:
+                assert rel_l2(a, ref) < 1e-5
+    with pytest.raises(ValueError):
+        lib.map_wf_solve(probs, opts, out=out[:2])
+    with pytest.raises(ValueError):
+        lib.map_wf_solve(probs, opts, out=[out[1], out[0], out[2]])
+    with pytest.raises(ValueError):
+        lib.map_wf_solve(probs, opts, out=[x.to(torch.complex128) for x in out])
