@@ -129,7 +129,9 @@ enum ChainMode : int {
   CM_RAW_GRAD = 6,  // out = 4 (S^-1 v + R^T W (R v - d)), chi^2 partials (raw field)
   CM_RAW_HV = 7,    // out = 4 (S^-1 v + R^T W R v)
   CM_SIM = 8,       // x = M (R (sIn . boost . z / sqrt 2) + noise)     (simulation)
-  CM_FLUSH = 9      // solver only: no transform this iteration, pass B brings w up to date
+  CM_FLUSH = 9,     // solver only: no transform this iteration, pass B brings w up to date
+  CM_DOTS = 10      // solver only: no transform, pass A takes the dots of the exact gradient that
+                    // a failed stop confirmation left out
 };
 
 // partial-sum kinds written per block
@@ -216,7 +218,7 @@ struct LbState {
   double rho;
   double beta;
   int doDir;                   // the direction pass runs in this iteration
-  int pad3;
+  int confirm;                 // the pending exact gradient confirms a stop: pass A takes g.g only
 };
 
 // One field's band-statistic job.

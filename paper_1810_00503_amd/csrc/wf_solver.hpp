@@ -164,6 +164,7 @@ __global__ void k_init(InstDesc* desc, LbState* st, Job* jobs, int batch) {
   S.rho = 0.0;
   S.beta = 0.0;
   S.doDir = 0;
+  S.confirm = 0;
   for (int k = 0; k < KK_COUNT; ++k) S.bytes[k] = 0.0;
   S.bytes[KK_MISC] += D.vbytes;   // zeroing w
   add_chain_bytes(S, D, CM_GRAD, 0);
@@ -172,17 +173,19 @@ __global__ void k_init(InstDesc* desc, LbState* st, Job* jobs, int batch) {
 }
 
 // ------------------------------------------------------------------------ pass A (dots only)
-// After an exact gradient: g.g, g.p_j, g.Dp_j for the kept pairs, one slot at a time.
+// After an exact gradient: g.g, g.p_j, g.Dp_j for the kept pairs, one slot at a time.  An
+// exact gradient that confirms a stop needs g.g only; the dots follow in a CM_DOTS
+// iteration if the confirmation fails.
 template <typename T, int M>
 __global__ __launch_bounds__(NT) void k_passA(const InstDesc* __restrict__ desc, const LbState* __restrict__ st) {
   const int i = rev_instance();
   const LbState& S = st[i];
-  if (S.status != ST_RUNNING || S.chainMode != CM_GRAD) return;
+  if (S.status != ST_RUNNING || !(S.chainMode == CM_GRAD || S.chainMode == CM_DOTS)) return;
   const InstDesc& D = desc[i];
   using V = typename VecT<T>::type;
   constexpr int VW = VecT<T>::W;
   __shared__ double red[NT / 64][NDOT];
-  const int nh = S.nhist, head = S.head;
+  const int nh = (S.chainMode == CM_GRAD && S.confirm) ? 0 : S.nhist, head = S.head;
   // element offsets (units of V) from the instance's vector block, 32-bit
   const uint32_t nvec = (uint32_t)(D.L * 2 / VW);
   const uint32_t vs = (uint32_t)(D.vstride * 2 / VW);
@@ -312,7 +315,7 @@ __global__ __launch_bounds__(256) void k_coef(const InstDesc* __restrict__ desc,
   __shared__ double qPD[M][M], qDD[M][M], qgP[M], qgD[M], qal[M];
   __shared__ int run;
   const int ncol = (D.n / 2) / TB, nrow = D.c * D.n / RB_MIN;
-  if (mode == CM_GRAD) reduce_columns(D.partA, D.nchunk, NDOT, 2 * M + 1, sums, part4);
+  if (mode == CM_GRAD || mode == CM_DOTS) reduce_columns(D.partA, D.nchunk, NDOT, 2 * M + 1, sums, part4);
   // chain partial sums: one wave per kind, fixed-order lane sums and a fixed shuffle tree
   {
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -407,28 +410,43 @@ __device__ __forceinline__ int coef_update(const InstDesc& D, LbState& S, Job& j
     S.chi2 += S.dchi2;
     S.iter += 1;
     S.lastWasGrad = 0;
-  } else if (mode == CM_GRAD) {
+  } else if (mode == CM_GRAD || mode == CM_DOTS) {
     const int nh = S.nhist, head = S.head;
-    S.chi2 = 2.0 * chs[3 + M] + chs[4 + M];
-    S.ngrad += 1;
-    S.lastGradIter = S.iter;
-    S.pending = 0;
-    S.npend = 0;   // an exact gradient is only taken at a flushed iterate
-    S.lastWasGrad = 1;
-    S.bytes[KK_PASSA] += D.vbytes * (1.0 + 2.0 * nh);
-    for (int j = 0; j < nh; ++j) {
-      const int sj = slot_of(head, j, M);
-      S.gP[sj] = sums[j];
-      S.gD[sj] = sums[M + j];
+    const bool dots = mode == CM_DOTS || !S.confirm;   // pass A took the dots with the kept pairs
+    if (mode == CM_GRAD) {
+      S.chi2 = 2.0 * chs[3 + M] + chs[4 + M];
+      S.ngrad += 1;
+      S.lastGradIter = S.iter;
+      S.pending = 0;
+      S.npend = 0;   // an exact gradient is only taken at a flushed iterate
+      S.lastWasGrad = 1;
+    }
+    S.bytes[KK_PASSA] += D.vbytes * (1.0 + (dots ? 2.0 * nh : 0.0));
+    if (dots) {
+      for (int j = 0; j < nh; ++j) {
+        const int sj = slot_of(head, j, M);
+        S.gP[sj] = sums[j];
+        S.gD[sj] = sums[M + j];
+      }
     }
     const double gg = sums[2 * M];
     S.gg = gg;
-    if (S.g0norm < 0.0) S.g0norm = sqrt(gg);
-    const double g0 = S.g0norm;
-    const double rel = g0 > 0.0 ? sqrt(gg) / g0 : 0.0;
-    if (!isfinite(gg) || !isfinite(S.chi2)) status = 2;
-    else if (g0 == 0.0 || rel <= D.tol) status = 0;
-    else if (S.iter >= D.maxIter) status = 1;
+    if (mode == CM_GRAD) {
+      if (S.g0norm < 0.0) S.g0norm = sqrt(gg);
+      const double g0 = S.g0norm;
+      const double rel = g0 > 0.0 ? sqrt(gg) / g0 : 0.0;
+      if (!isfinite(gg) || !isfinite(S.chi2)) status = 2;
+      else if (g0 == 0.0 || rel <= D.tol) status = 0;
+      else if (S.iter >= D.maxIter) status = 1;
+      if (status == ST_RUNNING && !dots) {   // the confirmation failed: take the dots first
+        S.confirm = 0;
+        S.chainMode = CM_DOTS;
+        job.mode = CM_NONE;
+        S.doB = 0;
+        return 0;
+      }
+    }
+    S.confirm = 0;
   }
   if (status != ST_RUNNING) {
     S.status = status;
@@ -694,10 +712,12 @@ __device__ __forceinline__ int postB_scalar(const InstDesc& D, LbState& S, Job& 
     else status = S.after - 2;
     S.after = 0;
   } else {
+    S.confirm = 0;
     if (!isfinite(gg) || !isfinite(gp)) {
       status = 2;
     } else if (rel <= D.tol) {
       next = CM_GRAD;                 // confirm with the exact gradient
+      S.confirm = 1;
     } else if (S.iter >= D.maxIter) {
       status = 1;
     } else if (D.dchi2Tol > 0.0 && S.iter > 0 && fabs(S.dchi2) < D.dchi2Tol) {

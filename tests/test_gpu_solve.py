@@ -313,3 +313,32 @@ def test_map_solve_into_caller_buffers(lib):
         lib.map_wf_solve(probs, opts, out=[out[1], out[0], out[2]])
     with pytest.raises(ValueError):
         lib.map_wf_solve(probs, opts, out=[x.to(torch.complex128) for x in out])
+
+
+def test_failed_stop_confirmations(lib):
+    """Solves whose running gradient meets the tolerance before the exact one does: the exact
+    gradient taken to confirm the stop reads only g, and when it fails its dots with the kept
+    pairs follow in an iteration without a transform before the recursion goes on.  The results
+    still meet the bars (fixed tiles make the sequence of confirmations reproducible)."""
+    import torch
+    print("[failed stop confirmations]", flush=True)
+    lib.set_chain_tiles(4, 1, 0, 0)
+    try:
+        for kind, precond in (("density", 0), ("shear", 1)):
+            wl = (WL.density_workload(64, 21, nbands=4, holes=4, target_mask=0.25) if kind == "density"
+                  else WL.shear_workload(64, 22, nbands_e=3, nbands_b=3))
+            d = oracle_data(wl, 5)
+            S = O.prior_S(wl.pshape, wl.band, wl.theta_fid)
+            ref = O.lbfgs_solve(d, wl.W, S, tol=1e-11, max_iter=50000)
+            prob = make_problem(lib, torch, wl, "f32", d=d)
+            s, _, st, rc = lib.map_wf_solve([prob], lib.LbfgsOpts(rel_grad_tol=1e-7, precond=precond))
+            print(f"   {kind} precond={precond}: iters {st[0].iters}, exact gradients {st[0].ngrad}", flush=True)
+            assert rc == 0 and st[0].status == lib.WF_SOLVE_CONVERGED and st[0].rel_grad <= 1e-7
+            assert st[0].ngrad >= 3   # at least one confirmation failed (or a refresh) before the stop
+            got = s[0].cpu().numpy()
+            assert rel_l2(got, ref["s"]) < 1e-5
+            g = np.sqrt(S) * O.grad_chi2(got, d, wl.W, S)
+            g0 = np.sqrt(S) * O.grad_chi2(np.zeros_like(got), d, wl.W, S)
+            assert np.linalg.norm(g) <= 3e-6 * np.linalg.norm(g0)
+    finally:
+        lib.set_chain_tiles(0)
