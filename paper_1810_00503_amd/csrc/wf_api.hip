@@ -30,6 +30,7 @@ constexpr int kMaxChunk = 256;
 // them (an odd multiple of 256 B), so the 2m + 3 streams of a pass do not start at the same
 // offset modulo a large power of two.
 constexpr size_t kVecPadBytes = 4096 + 256;
+constexpr int kMaxStreams = 4;   // the context stream plus up to 3 more for the classes of an uneven batch
 
 const char* kKindNames[KK_COUNT] = {"colinv", "row", "colfwd", "passA", "passB", "post", "coef", "misc", "passB_flush",
                                      "simulate"};
@@ -62,9 +63,12 @@ struct wf_ctx {
   double bytes[KK_COUNT] = {};
   std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> pendingEv;
   std::vector<hipEvent_t> evPool;
-  // graph cache
-  hipGraphExec_t gexec = nullptr;
-  std::string gkey;
+  // graph cache: one captured graph per class of the current batch (key: arena, shapes, options)
+  std::map<std::string, hipGraphExec_t> gexecs;
+  // streams beside cs that run classes of an uneven batch concurrently, with their fork/join events
+  std::vector<hipStream_t> xs;
+  std::vector<hipEvent_t> xev;
+  hipEvent_t evFork = nullptr;
   // chain tile choices: fixed by the caller (rbv > 0) or tuned per shape and batch size
   ChainCfg fixedCfg;
   bool fixedSet = false;
@@ -113,10 +117,9 @@ int arena_reserve(wf_ctx* ctx, Arena& a, size_t bytes) {
   a.cap = want;
   a.used = 0;
   a.gen++;
-  if (&a == &ctx->solveA && ctx->gexec) {
-    (void)hipGraphExecDestroy(ctx->gexec);
-    ctx->gexec = nullptr;
-    ctx->gkey.clear();
+  if (&a == &ctx->solveA) {
+    for (auto& kv : ctx->gexecs) (void)hipGraphExecDestroy(kv.second);
+    ctx->gexecs.clear();
   }
   return WF_OK;
 }
@@ -603,67 +606,33 @@ int solve_core(wf_ctx* ctx, const wf_problem* probs, int B, const wf_lbfgs_opts&
                           ctx->cs));
     }
   }
-  // one iteration for every class
-  auto body = [&](void) -> int {
-    for (auto& k : ks) {
-      const int cnt = (int)k.members.size();
-      const int G = k.cfg.group > 0 ? std::min(k.cfg.group, cnt) : cnt;
-      for (int g0 = 0; g0 < cnt; g0 += G) {
-        const int gc = std::min(G, cnt - g0);
-        for (int w = 0; w < 3; ++w) HIPCHK(chain(ctx, k.dtype, k.n, k.c, w, djobs + k.first + g0, gc, k.tw, &k.cfg));
-      }
+  // one iteration of one class (classes share no buffers, so their iterations are independent)
+  const bool cg = o.method == WF_METHOD_CG;
+  auto body = [&](const Klass& k) -> int {
+    const int cnt = (int)k.members.size();
+    const int dt = k.dtype == WF_F64;
+    const int G = k.cfg.group > 0 ? std::min(k.cfg.group, cnt) : cnt;
+    for (int g0 = 0; g0 < cnt; g0 += G) {
+      const int gc = std::min(G, cnt - g0);
+      for (int w = 0; w < 3; ++w) HIPCHK(chain(ctx, k.dtype, k.n, k.c, w, djobs + k.first + g0, gc, k.tw, &k.cfg));
     }
-    const bool cg = o.method == WF_METHOD_CG;
-    for (auto& k : ks) {
-      if (!cg) continue;
-      const int cnt = (int)k.members.size();
-      const int dt = k.dtype == WF_F64;
-      {
-        Timed t(ctx, KK_COEF);
-        HIPCHK(lbfgs_launch(dt, m, LB_CGSTEP, dim3(cnt), ddesc + k.first, dst + k.first, djobs + k.first, cnt, ctx->cs));
-      }
-      {
-        Timed t(ctx, KK_PASSB);
-        HIPCHK(lbfgs_launch(dt, m, LB_CGPASS, dim3(k.nchunk, cnt), ddesc + k.first, dst + k.first, djobs + k.first,
-                            cnt, ctx->cs));
-      }
-      {
-        Timed t(ctx, KK_POST);
-        HIPCHK(lbfgs_launch(dt, m, LB_CGPOST, dim3(cnt), ddesc + k.first, dst + k.first, djobs + k.first, cnt, ctx->cs));
-      }
-      {
-        Timed t(ctx, KK_PASSBF);
-        HIPCHK(lbfgs_launch(dt, m, LB_CGDIR, dim3(k.nchunk, cnt), ddesc + k.first, dst + k.first, djobs + k.first, cnt,
-                            ctx->cs));
-      }
-    }
-    for (auto& k : ks) {
-      if (cg) continue;
-      const int cnt = (int)k.members.size();
-      const int dt = k.dtype == WF_F64;
-      {
-        Timed t(ctx, KK_PASSA);
-        HIPCHK(lbfgs_launch(dt, m, LB_PASSA, dim3(k.nchunk, cnt), ddesc + k.first, dst + k.first, djobs + k.first, cnt,
-                            ctx->cs));
-      }
-      {
-        Timed t(ctx, KK_COEF);
-        HIPCHK(lbfgs_launch(dt, m, LB_COEF, dim3(cnt), ddesc + k.first, dst + k.first, djobs + k.first, cnt, ctx->cs));
-      }
-      {
-        Timed t(ctx, KK_PASSB);
-        HIPCHK(lbfgs_launch(dt, m, LB_PASSB, dim3(k.nchunk, cnt), ddesc + k.first, dst + k.first, djobs + k.first, cnt,
-                            ctx->cs));
-      }
-      {
-        Timed t(ctx, KK_PASSBF);
-        HIPCHK(lbfgs_launch(dt, m, LB_PASSBF, dim3(k.nchunk, cnt), ddesc + k.first, dst + k.first, djobs + k.first,
-                            cnt, ctx->cs));
-      }
-      {
-        Timed t(ctx, KK_POST);
-        HIPCHK(lbfgs_launch(dt, m, LB_POSTB, dim3(cnt), ddesc + k.first, dst + k.first, djobs + k.first, cnt, ctx->cs));
-      }
+    auto launch = [&](int kk, int which, dim3 grid) -> int {
+      Timed t(ctx, kk);
+      HIPCHK(lbfgs_launch(dt, m, which, grid, ddesc + k.first, dst + k.first, djobs + k.first, cnt, ctx->cs));
+      return WF_OK;
+    };
+    int rc;
+    if (cg) {
+      if ((rc = launch(KK_COEF, LB_CGSTEP, dim3(cnt)))) return rc;
+      if ((rc = launch(KK_PASSB, LB_CGPASS, dim3(k.nchunk, cnt)))) return rc;
+      if ((rc = launch(KK_POST, LB_CGPOST, dim3(cnt)))) return rc;
+      if ((rc = launch(KK_PASSBF, LB_CGDIR, dim3(k.nchunk, cnt)))) return rc;
+    } else {
+      if ((rc = launch(KK_PASSA, LB_PASSA, dim3(k.nchunk, cnt)))) return rc;
+      if ((rc = launch(KK_COEF, LB_COEF, dim3(cnt)))) return rc;
+      if ((rc = launch(KK_PASSB, LB_PASSB, dim3(k.nchunk, cnt)))) return rc;
+      if ((rc = launch(KK_PASSBF, LB_PASSBF, dim3(k.nchunk, cnt)))) return rc;
+      if ((rc = launch(KK_POST, LB_POSTB, dim3(cnt)))) return rc;
     }
     return WF_OK;
   };
@@ -671,56 +640,96 @@ int solve_core(wf_ctx* ctx, const wf_problem* probs, int B, const wf_lbfgs_opts&
   if (rc) return rc;
   int K = o.iters_per_poll > 0 ? o.iters_per_poll : (B > 1 ? 8 : 1);
   const bool graph = o.use_graph != 0 && !ctx->prof && K > 0;
-  std::string key;
+  const int nk = (int)ks.size();
+  std::vector<hipGraphExec_t> gx(nk, nullptr);
   if (graph) {
-    char buf[128];
-    snprintf(buf, sizeof buf, "%p/%d/%d/%d/%d/%d|", (void*)A.base, A.gen, B, m, K, o.method);
-    key = buf;
-    for (auto& k : ks) key += std::to_string(k.n) + "," + std::to_string(k.c) + "," + std::to_string(k.dtype) + "," +
-                              std::to_string(k.members.size()) + "," + std::to_string(k.cfg.rbv) + "," +
-                              std::to_string(k.cfg.cpb) + "," + std::to_string(k.cfg.group) + "," + std::to_string(k.cfg.reg) + ";";
-    if (key != ctx->gkey) {
-      if (ctx->gexec) (void)hipGraphExecDestroy(ctx->gexec);
-      ctx->gexec = nullptr;
-      ctx->gkey.clear();
+    // K iterations of each class captured once per (arena, batch shape, options); graphs of
+    // earlier batch shapes are dropped
+    std::vector<std::string> keys(nk);
+    for (int c = 0; c < nk; ++c) {
+      const Klass& k = ks[c];
+      char buf[160];
+      snprintf(buf, sizeof buf, "%p/%d/%d/%d/%d/%d|%d,%d,%d,%d,%zu,%d,%d,%d,%d", (void*)A.base, A.gen, B, m, K,
+               o.method, k.first, k.n, k.c, k.dtype, k.members.size(), k.cfg.rbv, k.cfg.cpb, k.cfg.group, k.cfg.reg);
+      keys[c] = buf;
+    }
+    for (auto it = ctx->gexecs.begin(); it != ctx->gexecs.end();) {
+      if (std::find(keys.begin(), keys.end(), it->first) == keys.end()) {
+        (void)hipGraphExecDestroy(it->second);
+        it = ctx->gexecs.erase(it);
+      } else {
+        ++it;
+      }
+    }
+    for (int c = 0; c < nk; ++c) {
+      auto it = ctx->gexecs.find(keys[c]);
+      if (it != ctx->gexecs.end()) {
+        gx[c] = it->second;
+        continue;
+      }
       hipGraph_t g = nullptr;
       HIPCHK(hipStreamBeginCapture(ctx->cs, hipStreamCaptureModeRelaxed));
       int brc = WF_OK;
       int64_t saved[KK_COUNT];
       std::memcpy(saved, ctx->launches, sizeof saved);
-      for (int r = 0; r < K && brc == WF_OK; ++r) brc = body();
+      for (int r = 0; r < K && brc == WF_OK; ++r) brc = body(ks[c]);
       std::memcpy(ctx->launches, saved, sizeof saved);
       hipError_t e = hipStreamEndCapture(ctx->cs, &g);
       if (brc) return brc;
       if (e != hipSuccess) return fail(ctx, WF_EHIP, std::string("graph capture: ") + hipGetErrorString(e));
-      e = hipGraphInstantiate(&ctx->gexec, g, nullptr, nullptr, 0);
+      e = hipGraphInstantiate(&gx[c], g, nullptr, nullptr, 0);
       (void)hipGraphDestroy(g);
       if (e != hipSuccess) return fail(ctx, WF_EHIP, std::string("graph instantiate: ") + hipGetErrorString(e));
-      ctx->gkey = key;
+      ctx->gexecs[keys[c]] = gx[c];
+    }
+    // concurrent streams for the classes of an uneven batch (default priority)
+    const int nx = std::min(nk, kMaxStreams) - 1;
+    if (!ctx->evFork && nx > 0) HIPCHK(hipEventCreateWithFlags(&ctx->evFork, hipEventDisableTiming));
+    while ((int)ctx->xs.size() < nx) {
+      hipStream_t x = nullptr;
+      hipEvent_t ev = nullptr;
+      HIPCHK(hipStreamCreateWithFlags(&x, hipStreamNonBlocking));
+      ctx->xs.push_back(x);
+      HIPCHK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+      ctx->xev.push_back(ev);
     }
   }
+  // classes with running instances: all at the start, then as the host polls find them
+  std::vector<char> active(nk, 1);
   const int64_t maxBodies = 2LL * o.max_iter + 64;
   int64_t bodies = 0;
   while (true) {
     if (graph) {
-      HIPCHK(hipGraphLaunch(ctx->gexec, ctx->cs));
-      // count launches as if enqueued one by one
-      for (auto& k : ks) {
-        (void)k;
+      std::vector<int> act;
+      for (int c = 0; c < nk; ++c)
+        if (active[c]) act.push_back(c);
+      const int ns = std::min((int)act.size(), kMaxStreams);
+      if (ns > 1) HIPCHK(hipEventRecord(ctx->evFork, ctx->cs));
+      for (int s = 1; s < ns; ++s) HIPCHK(hipStreamWaitEvent(ctx->xs[s - 1], ctx->evFork, 0));
+      for (size_t a = 0; a < act.size(); ++a) {
+        const int s = (int)(a % ns);
+        HIPCHK(hipGraphLaunch(gx[act[a]], s == 0 ? ctx->cs : ctx->xs[s - 1]));
+        // count launches as if enqueued one by one
         ctx->launches[KK_COLINV] += K;
         ctx->launches[KK_ROW] += K;
         ctx->launches[KK_COLFWD] += K;
         ctx->launches[KK_POST] += K;
-        if (o.method != WF_METHOD_CG) ctx->launches[KK_PASSA] += K;
+        if (!cg) ctx->launches[KK_PASSA] += K;
         ctx->launches[KK_COEF] += K;
         ctx->launches[KK_PASSB] += K;
         ctx->launches[KK_PASSBF] += K;
       }
-    } else {
-      for (int r = 0; r < K; ++r) {
-        rc = body();
-        if (rc) return rc;
+      for (int s = 1; s < ns; ++s) {
+        HIPCHK(hipEventRecord(ctx->xev[s - 1], ctx->xs[s - 1]));
+        HIPCHK(hipStreamWaitEvent(ctx->cs, ctx->xev[s - 1], 0));
       }
+    } else {
+      for (int r = 0; r < K; ++r)
+        for (int c = 0; c < nk; ++c) {
+          if (!active[c]) continue;
+          rc = body(ks[c]);
+          if (rc) return rc;
+        }
     }
     bodies += K;
     HIPCHK(hipMemcpyAsync(ctx->hstat, dstat, sizeof(int) * B, hipMemcpyDeviceToHost, ctx->cs));
@@ -728,7 +737,12 @@ int solve_core(wf_ctx* ctx, const wf_problem* probs, int B, const wf_lbfgs_opts&
     rc = drain_events(ctx);
     if (rc) return rc;
     int running = 0;
-    for (int i = 0; i < B; ++i) running += (ctx->hstat[i] == ST_RUNNING);
+    for (int c = 0; c < nk; ++c) {
+      int r = 0;
+      for (size_t j = 0; j < ks[c].members.size(); ++j) r += (ctx->hstat[ks[c].first + (int)j] == ST_RUNNING);
+      active[c] = r > 0;
+      running += r;
+    }
     if (running == 0 || bodies >= maxBodies) break;
   }
   std::vector<LbState> hs(B);
@@ -1180,7 +1194,13 @@ void wf_destroy(wf_ctx* c) {
   if (!c) return;
   (void)hipSetDevice(c->dev);
   if (c->cs) (void)hipStreamSynchronize(c->cs);
-  if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+  for (auto& kv : c->gexecs) (void)hipGraphExecDestroy(kv.second);
+  for (auto x : c->xs) {
+    (void)hipStreamSynchronize(x);
+    (void)hipStreamDestroy(x);
+  }
+  for (auto e : c->xev) (void)hipEventDestroy(e);
+  if (c->evFork) (void)hipEventDestroy(c->evFork);
   for (auto& kv : c->tw) (void)hipFree(kv.second);
   for (Arena* a : {&c->solveA, &c->simA, &c->opA, &c->accA})
     if (a->base) (void)hipFree(a->base);
