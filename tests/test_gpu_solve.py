@@ -368,3 +368,25 @@ def test_uneven_batch_graphs_match_sequential(lib):
             assert np.array_equal(sg[i].cpu().numpy(), ss[i].cpu().numpy()), i
             assert (stg[i].iters, stg[i].ngrad, stg[i].status) == (sts[i].iters, sts[i].ngrad, sts[i].status)
             assert stg[i].chi2 == sts[i].chi2 and stg[i].rel_grad == sts[i].rel_grad
+
+
+@pytest.mark.parametrize("m", [1, 2, 5, 16])
+def test_history_lengths(lib, m):
+    """Every history length the library instantiates reaches the same MAP (m = 1 flushes the lazy
+    iterate every iteration, m = 16 is the largest history), in float32 against the oracle's MAP and
+    in float64 against it at 1e-9 (both from the exact stop test)."""
+    import torch
+    print(f"[history m={m}]", flush=True)
+    cases = [("density", WL.density_workload(48, 31, nbands=4, holes=3, target_mask=0.2), 0),
+             ("shear", WL.shear_workload(64, 32, nbands_e=3, nbands_b=3), 1)]
+    for kind, wl, precond in cases:
+        d = oracle_data(wl, 6)
+        S = O.prior_S(wl.pshape, wl.band, wl.theta_fid)
+        ref = O.lbfgs_solve(d, wl.W, S, tol=1e-12, max_iter=50000)
+        for dt, tol, bar in (("f32", 1e-7, 1e-5), ("f64", 1e-12, 1e-9)):
+            prob = make_problem(lib, torch, wl, dt, d=d)
+            s, maps, st, rc = _solve(lib, [prob], m=m, rel_grad_tol=tol, max_iter=20000, precond=precond)
+            print(f"   {kind} {dt}: iters {st[0].iters}, exact gradients {st[0].ngrad}", flush=True)
+            assert rc == 0 and st[0].status == lib.WF_SOLVE_CONVERGED and st[0].rel_grad <= tol
+            assert rel_l2(s[0], ref["s"]) < bar
+            assert rel_l2(maps[0], O.forward(ref["s"])) < bar
