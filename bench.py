@@ -312,20 +312,23 @@ def main():
                "converged": f"{sum(x.status == wf.WF_SOLVE_CONVERGED for x in st_c)}/{nsolve}"}
     # the same batch with the optional diagonal noise-aware preconditioner (off by default: the method
     # solves without one); the stop test stays the exact whitened relative gradient
-    pcopts = wf.LbfgsOpts(m=args.m, rel_grad_tol=args.tol, precond=1)
-    wf.map_wf_solve(sims, pcopts)
-    torch.cuda.synchronize()
-    tp = []
-    for _ in range(3):
-        t0 = time.perf_counter()
-        _, _, st_p, _ = wf.map_wf_solve(sims, pcopts)
+    # (with the secondary lines: it would mix shorter-history pass-B launches into a profile of the step)
+    pc_line = None
+    if not args.no_secondary:
+        pcopts = wf.LbfgsOpts(m=args.m, rel_grad_tol=args.tol, precond=1)
+        wf.map_wf_solve(sims, pcopts)
         torch.cuda.synchronize()
-        tp.append(time.perf_counter() - t0)
-    pc_line = {"solves_per_s": round(nsolve / float(np.median(tp)), 2),
-               "iters_mean": round(float(np.mean([x.iters for x in st_p])), 1),
-               "iters_max": int(max(x.iters for x in st_p)),
-               "rel_grad_max": float(max(x.rel_grad for x in st_p)),
-               "converged": f"{sum(x.status == wf.WF_SOLVE_CONVERGED for x in st_p)}/{nsolve}"}
+        tp = []
+        for _ in range(3):
+            t0 = time.perf_counter()
+            _, _, st_p, _ = wf.map_wf_solve(sims, pcopts)
+            torch.cuda.synchronize()
+            tp.append(time.perf_counter() - t0)
+        pc_line = {"solves_per_s": round(nsolve / float(np.median(tp)), 2),
+                   "iters_mean": round(float(np.mean([x.iters for x in st_p])), 1),
+                   "iters_max": int(max(x.iters for x in st_p)),
+                   "rel_grad_max": float(max(x.rel_grad for x in st_p)),
+                   "converged": f"{sum(x.status == wf.WF_SOLVE_CONVERGED for x in st_p)}/{nsolve}"}
     tiles = wf.get_chain_tiles(args.n, 2, wf.WF_F32, nsolve)
     conv = sum(s.status == wf.WF_SOLVE_CONVERGED for s in st_b)
 
