@@ -137,6 +137,9 @@ void wf_lbfgs_default(wf_lbfgs_opts* opts);
  *   map_out  nullable; HOST [batch] of device pointers (entries may be NULL), each
  *            [ncomp][n][n] real: the map R s_hat;
  *   stats    HOST [batch] (nullable).
+ * Instances of equal (n, ncomp, dtype) form a class; the classes of an uneven batch may run
+ * on up to three more streams of the context, forked from and joined back to `stream`
+ * inside the call (the call returns with all of its work finished).
  * Returns WF_OK if every instance converged, WF_NOT_CONVERGED otherwise.             */
 int map_wf_solve(wf_ctx* ctx, const wf_problem* probs, int32_t batch, const wf_lbfgs_opts* opts,
                  void* const* s_out, void* const* map_out, wf_solve_stats* stats, void* stream);
