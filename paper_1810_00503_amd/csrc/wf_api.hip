@@ -98,7 +98,9 @@ int arena_reserve(wf_ctx* ctx, Arena& a, size_t bytes) {
     return WF_OK;
   }
   if (a.base) {
+    // work of an earlier call (on any of the context's streams) may still use the old block
     HIPCHK(hipStreamSynchronize(ctx->cs));
+    for (auto x : ctx->xs) HIPCHK(hipStreamSynchronize(x));
     HIPCHK(hipFree(a.base));
     a.base = nullptr;
     a.cap = 0;
