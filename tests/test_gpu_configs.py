@@ -4,7 +4,8 @@ by one and on properties that hold at any size:
 * 256^2 density band powers (12 bands, 128 simulations, 1665 solves in one call): the
   simulation statistic E_l of sampled simulations against the oracle's own simulation,
   solve and E_l from the same Philox draws; F symmetric with a positive diagonal, b > 0.
-* 512^2 joint E/B shear (the benchmark's maps): a sampled MAP against the oracle's MAP.
+* 512^2 joint E/B shear (the benchmark's maps): a sampled MAP against the oracle's MAP (L-BFGS, and the
+  bench's conjugate-gradient and preconditioned comparisons).
 * 1024^2 CMB patch (preconditioned solve): the oracle's FP64 exact gradient at the GPU's
   MAP, and the E_l of the GPU's MAP against the oracle's E_l of the same field.
 * 96-map uneven batch (sides 128..1024, three kinds): every map converges in one batched
@@ -84,6 +85,15 @@ def test_config3_shear_map_full_size(lib):
     err = rel_l2(got, ref)
     print(f"  map rel L2 vs oracle {err:.2e}", flush=True)
     assert err < 1e-5
+    # the bench's comparison solvers on the same maps: conjugate gradients and the preconditioned
+    # L-BFGS, same stop test
+    for name, opts in (("cg", lib.LbfgsOpts(rel_grad_tol=1e-6, method=lib.WF_METHOD_CG)),
+                       ("precond", lib.LbfgsOpts(rel_grad_tol=1e-6, precond=1))):
+        s2, _, st2, rc2 = lib.map_wf_solve(probs, opts)
+        assert rc2 == 0 and all(x.status == lib.WF_SOLVE_CONVERGED and x.rel_grad <= 1e-6 for x in st2)
+        err2 = rel_l2(s2[2].cpu().numpy(), ref)
+        print(f"  {name}: iterations {[x.iters for x in st2]}, map rel L2 vs oracle {err2:.2e}", flush=True)
+        assert err2 < 1e-5
 
 
 def test_config4_cmb_full_size(lib):
