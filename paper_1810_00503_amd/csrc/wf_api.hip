@@ -696,20 +696,28 @@ int solve_core(wf_ctx* ctx, const wf_problem* probs, int B, const wf_lbfgs_opts&
       ctx->xev.push_back(ev);
     }
   }
-  // classes with running instances: all at the start, then as the host polls find them
-  std::vector<char> active(nk, 1);
+  // running instances per class: all at the start, then as the host polls find them
+  std::vector<int64_t> nrun(nk);
+  for (int c = 0; c < nk; ++c) nrun[c] = (int64_t)ks[c].members.size();
   const int64_t maxBodies = 2LL * o.max_iter + 64;
   int64_t bodies = 0;
   while (true) {
     if (graph) {
+      // classes with running instances, heaviest first (running instances x vector length),
+      // each onto the stream with the least load so far: the long classes of an uneven batch
+      // get streams of their own
       std::vector<int> act;
       for (int c = 0; c < nk; ++c)
-        if (active[c]) act.push_back(c);
+        if (nrun[c] > 0) act.push_back(c);
+      std::stable_sort(act.begin(), act.end(),
+                       [&](int x, int y) { return nrun[x] * ks[x].L > nrun[y] * ks[y].L; });
       const int ns = std::min((int)act.size(), kMaxStreams);
+      std::vector<int64_t> sload(ns, 0);
       if (ns > 1) HIPCHK(hipEventRecord(ctx->evFork, ctx->cs));
       for (int s = 1; s < ns; ++s) HIPCHK(hipStreamWaitEvent(ctx->xs[s - 1], ctx->evFork, 0));
       for (size_t a = 0; a < act.size(); ++a) {
-        const int s = (int)(a % ns);
+        const int s = (int)(std::min_element(sload.begin(), sload.end()) - sload.begin());
+        sload[s] += nrun[act[a]] * ks[act[a]].L;
         HIPCHK(hipGraphLaunch(gx[act[a]], s == 0 ? ctx->cs : ctx->xs[s - 1]));
         // count launches as if enqueued one by one
         ctx->launches[KK_COLINV] += K;
@@ -728,7 +736,7 @@ int solve_core(wf_ctx* ctx, const wf_problem* probs, int B, const wf_lbfgs_opts&
     } else {
       for (int r = 0; r < K; ++r)
         for (int c = 0; c < nk; ++c) {
-          if (!active[c]) continue;
+          if (nrun[c] == 0) continue;
           rc = body(ks[c]);
           if (rc) return rc;
         }
@@ -738,11 +746,11 @@ int solve_core(wf_ctx* ctx, const wf_problem* probs, int B, const wf_lbfgs_opts&
     HIPCHK(hipStreamSynchronize(ctx->cs));
     rc = drain_events(ctx);
     if (rc) return rc;
-    int running = 0;
+    int64_t running = 0;
     for (int c = 0; c < nk; ++c) {
-      int r = 0;
+      int64_t r = 0;
       for (size_t j = 0; j < ks[c].members.size(); ++j) r += (ctx->hstat[ks[c].first + (int)j] == ST_RUNNING);
-      active[c] = r > 0;
+      nrun[c] = r;
       running += r;
     }
     if (running == 0 || bodies >= maxBodies) break;
