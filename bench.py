@@ -86,7 +86,7 @@ def cpu_child(args):
 
     import oracle as O
     from paper_1810_00503_amd import workloads as WL
-    wl = WL.config3(args.n)
+    wl = WL.shear_eb(args.n)
     S_true = O.prior_S(wl.pshape, wl.band, wl.theta_true)
     S = O.prior_S(wl.pshape, wl.band, wl.theta_fid)
     # the data map (Philox stream 0 of the data seed) and the first two fiducial simulations
@@ -136,7 +136,7 @@ def secondary_workloads(args):
 
     out = {}
     # 256^2 density band powers: one estimate = data + 128 simulations x (1 + 12 bands)
-    wl = WL.config2()
+    wl = WL.density_bands()
     base = base_of(wl)
     prob = base.with_data(wf.wf_simulate(base, 1, 2000, theta_true=wl.theta_true)[0])
     nsim = 128
@@ -170,7 +170,7 @@ def secondary_workloads(args):
         "fiducial_iteration_2nd_step_change_over_sigma": round(float(np.max(np.abs(hist_i[2] - hist_i[1])[sig] /
                                                                            sd[sig])), 4)}
     # posterior error maps of the 512^2 shear workload: 127 simulations in one batched solve
-    wl = WL.config3()
+    wl = WL.shear_eb()
     base = base_of(wl)
     # B-mode band powers with the leakage as a bias against the full estimate (6 simulations)
     nb_e = wl.nbands // 2
@@ -192,14 +192,14 @@ def secondary_workloads(args):
                                        "mean_pixel_variance": float(vp.double().mean().item())}
     del vm, vp
     # scalar 512^2 density variant
-    wl = WL.config2(512)
+    wl = WL.density_bands(512)
     base = base_of(wl)
     d = wf.wf_simulate(base, 127, 2100, theta_true=wl.theta_true)
-    out["density512_maps"] = solve_line("512^2 density (config-2 generator at 512^2)",
+    out["density512_maps"] = solve_line("512^2 density (the 256^2 band-power generator at 512^2)",
                                         [base.with_data(d[i]) for i in range(127)], opts)
     del d
     # 1024^2 CMB patch (the diagonal preconditioner: unpreconditioned L-BFGS needs > 4000 iterations)
-    wl = WL.config4()
+    wl = WL.cmb_patch()
     base = base_of(wl)
     d = wf.wf_simulate(base, 16, 4100, theta_true=wl.theta_true)
     popts = wf.LbfgsOpts(m=args.m, rel_grad_tol=args.tol, max_iter=4000, precond=1)
@@ -217,7 +217,7 @@ def secondary_workloads(args):
                                      for t in range(len(ctols))]}
     del d
     # 96-map uneven batch
-    wls = WL.config5(96)
+    wls = WL.uneven_batch(96)
     probs = []
     for i, w in enumerate(wls):
         b0 = base_of(w)
@@ -251,7 +251,7 @@ def main():
 
     wf.load()
     dev = "cuda:0"
-    wl = WL.config3(args.n)
+    wl = WL.shear_eb(args.n)
     W = torch.tensor(wl.W, dtype=torch.float32, device=dev)
     base = wf.Problem(W, wl.pshape, wl.band, wl.theta_fid)
     # the observed map: a simulation from the truth (Theta = 1), Philox stream 0
@@ -392,7 +392,7 @@ def main():
         "metric": METRIC, "value": round(value, 2), "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(ms_step, 2), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": f"{args.n}^2 joint E/B shear (config-3 generator), {nb} bands; one bandpower_qe "
+        "config": {"workload": f"{args.n}^2 joint E/B shear (shear_eb generator), {nb} bands; one bandpower_qe "
                                f"step = {nsolve} MAP solves (1 data + {args.nsim} sims x (1 + {nb} bands)) in one "
                                f"batch to {args.tol:g} rel. grad, L-BFGS m={args.m}",
                    "n": args.n, "ncomp": 2, "batch": nsolve, "nsim": args.nsim, "nbands": nb,

@@ -33,7 +33,7 @@ import numpy as np
 __all__ = [
     "Workload", "kmag_half", "log_band_map", "linear_band_map",
     "density_pshape", "shear_pshape", "cmb_pshape", "circle_holes",
-    "white_draws", "config1", "config2", "config3", "config4", "config5",
+    "white_draws", "density64", "density_bands", "shear_eb", "cmb_patch", "uneven_batch",
     "density_workload", "shear_workload", "cmb_workload",
 ]
 
@@ -240,7 +240,7 @@ def cmb_workload(n: int, seed: int, nbands: int = 40, holes: int = 300, gal_frac
                     _theta_fid(rng, nbands, randomize_fid), var, m, seed)
 
 
-def config1(n: int = 64) -> Workload:
+def density64(n: int = 64) -> Workload:
     """64^2 density, P = (k/k0)^-2 exp(-(k/20)^2), 8 discs r 4-8 px + 4-px border,
     sigma^2 = 0.1 U(0.5, 2); compared against the dense Wiener filter."""
     seed = 1000
@@ -255,23 +255,29 @@ def config1(n: int = 64) -> Workload:
     var = 0.1 * rng.uniform(0.5, 2.0, (n, n))
     nb = 8
     band = log_band_map(n, nb)[None]
-    return Workload("config1-density64", n, 1, density_pshape(n), band, nb, np.ones(nb),
+    return Workload("density64", n, 1, density_pshape(n), band, nb, np.ones(nb),
                     np.ones(nb), var, m, seed)
 
 
-def config2(n: int = 256) -> Workload:
-    return density_workload(n, 2000, nbands=12, name=f"config2-density{n}")
+def density_bands(n: int = 256) -> Workload:
+    """The density band-power workload: 12 log bands, 40 holes plus a stripe (~30 % masked),
+    log-normal per-pixel noise 0.05 lognormal(0, 0.5); 256^2 by default."""
+    return density_workload(n, 2000, nbands=12, name=f"density{n}-bands")
 
 
-def config3(n: int = 512) -> Workload:
-    return shear_workload(n, 3000, name=f"config3-shear{n}")
+def shear_eb(n: int = 512) -> Workload:
+    """The joint E/B shear workload: 10 E and 10 B bands, P_B = 0.01 P_E, sigma_e = 0.3 with
+    n_gal ~ Poisson(10), ~15 % masked; 512^2 by default."""
+    return shear_workload(n, 3000, name=f"shear{n}-eb")
 
 
-def config4(n: int = 1024) -> Workload:
-    return cmb_workload(n, 4000, name=f"config4-cmb{n}")
+def cmb_patch(n: int = 1024) -> Workload:
+    """The flat-sky CMB temperature patch: 40 linear bands, 300 point-source holes plus a 10 %
+    galactic cut, scan-striped noise at 6 uK-arcmin mean depth; 1024^2 by default."""
+    return cmb_workload(n, 4000, name=f"cmb{n}-patch")
 
 
-def config5(count: int = 96, sizes=(128, 192, 256, 384, 512, 768, 1024)) -> list[Workload]:
+def uneven_batch(count: int = 96, sizes=(128, 192, 256, 384, 512, 768, 1024)) -> list[Workload]:
     """Uneven-size batch: maps of the three kinds with sides drawn from `sizes`."""
     rng = np.random.Generator(np.random.PCG64(5000))
     out = []
@@ -281,9 +287,9 @@ def config5(count: int = 96, sizes=(128, 192, 256, 384, 512, 768, 1024)) -> list
         frac = float(rng.uniform(0.10, 0.40))
         s = 5000 + 1 + i
         if kind == 0:
-            out.append(density_workload(n, s, target_mask=frac, name=f"config5-density{n}"))
+            out.append(density_workload(n, s, target_mask=frac, name=f"uneven-density{n}"))
         elif kind == 1:
-            out.append(shear_workload(n, s, target_mask=frac, name=f"config5-shear{n}"))
+            out.append(shear_workload(n, s, target_mask=frac, name=f"uneven-shear{n}"))
         else:
-            out.append(cmb_workload(n, s, name=f"config5-cmb{n}"))
+            out.append(cmb_workload(n, s, name=f"uneven-cmb{n}"))
     return out

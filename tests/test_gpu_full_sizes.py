@@ -44,10 +44,10 @@ def _rel_exact_grad(s, d, W, S):
     return float(np.linalg.norm(g) / np.linalg.norm(g0))
 
 
-def test_config2_density_bandpowers_full_size(lib):
+def test_density256_bandpowers_full_size(lib):
     import torch
-    print("[config2 256^2 density, 128 sims]", flush=True)
-    wl = WL.config2()
+    print("[256^2 density, 128 sims]", flush=True)
+    wl = WL.density_bands()
     prob = _problem(lib, torch, wl)
     nsim, seed = 128, 2024
     opts = lib.LbfgsOpts(rel_grad_tol=1e-6)
@@ -69,10 +69,10 @@ def test_config2_density_bandpowers_full_size(lib):
         np.testing.assert_allclose(Es[i], E0, rtol=1e-4, atol=1e-9 * E0.sum(), err_msg=f"simulation {i}")
 
 
-def test_config3_shear_map_full_size(lib):
+def test_shear512_map_full_size(lib):
     import torch
-    print("[config3 512^2 shear]", flush=True)
-    wl = WL.config3()
+    print("[512^2 shear]", flush=True)
+    wl = WL.shear_eb()
     base = _problem(lib, torch, wl)
     d = lib.wf_simulate(base, 4, 3000, sim0=0, theta_true=wl.theta_true)
     probs = [base.with_data(d[i]) for i in range(4)]
@@ -96,10 +96,10 @@ def test_config3_shear_map_full_size(lib):
         assert err2 < 1e-5
 
 
-def test_config4_cmb_full_size(lib):
+def test_cmb1024_full_size(lib):
     import torch
-    print("[config4 1024^2 cmb, preconditioned]", flush=True)
-    wl = WL.config4()
+    print("[1024^2 cmb, preconditioned]", flush=True)
+    wl = WL.cmb_patch()
     base = _problem(lib, torch, wl)
     d = lib.wf_simulate(base, 2, 4000, sim0=0, theta_true=wl.theta_true)
     probs = [base.with_data(d[i]) for i in range(2)]
@@ -117,10 +117,10 @@ def test_config4_cmb_full_size(lib):
     np.testing.assert_allclose(E, Eo, rtol=1e-4)
 
 
-def test_config5_uneven_batch_full_size(lib):
+def test_uneven96_batch_full_size(lib):
     import torch
-    print("[config5 96 uneven maps]", flush=True)
-    wls = WL.config5(96)
+    print("[96 uneven maps]", flush=True)
+    wls = WL.uneven_batch(96)
     probs = []
     for i, wl in enumerate(wls):
         base = _problem(lib, torch, wl)

@@ -66,7 +66,7 @@ def test_posterior_error_shear512_full_size(lib):
     """The 512^2 E/B shear workload (two simulations, Philox path) against the oracle."""
     import torch
     print("[posterior_error 512^2 shear]", flush=True)
-    wl = WL.config3()
+    wl = WL.shear_eb()
     prob = make_problem(lib, torch, wl, "f32")
     nsim, seed = 2, 99
     vm, vp, rc = lib.posterior_error(prob, nsim, seed, opts=lib.LbfgsOpts(rel_grad_tol=1e-6))   # the workload's tolerance

@@ -52,11 +52,11 @@ def test_map_matches_oracle_f32(lib, kind, n):
     assert np.linalg.norm(w_g) <= 3e-6 * np.linalg.norm(w_g0)
 
 
-def test_config1_f64_matches_dense_wiener_filter(lib):
+def test_density64_f64_matches_dense_wiener_filter(lib):
     """64^2 density in float64, m = 10, tol 1e-8, against the 4096 x 4096 direct inversion."""
     import torch
-    print("[config1 f64]", flush=True)
-    wl = WL.config1()
+    print("[density64 f64]", flush=True)
+    wl = WL.density64()
     d = oracle_data(wl, 1)
     S = O.prior_S(wl.pshape, wl.band, wl.theta_fid)
     wf_ref = O.wiener_dense(d, wl.W, S)

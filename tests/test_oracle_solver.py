@@ -49,9 +49,9 @@ def test_map_equals_dense_wiener_filter(ncomp, n):
     assert np.linalg.norm(g) <= 1e-9 * np.linalg.norm(g0)
 
 
-def test_config1_map_vs_dense_wiener_filter():
+def test_density64_map_vs_dense_wiener_filter():
     """64^2 density case (m = 10, tol 1e-8) against the 4096 x 4096 direct inversion."""
-    wl = WL.config1()
+    wl = WL.density64()
     S = O.prior_S(wl.pshape, wl.band, wl.theta_fid)
     draws = WL.white_draws(wl.n, 1, 1, wl.seed)
     d = O.simulate(draws[0], O.prior_S(wl.pshape, wl.band, wl.theta_true), wl.W)
