@@ -241,7 +241,7 @@ def main():
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the simulation batches would shard "
-              f"across GPUs with one all-reduce of E and F, which this build does not implement.", file=sys.stderr)
+              f"across GPUs with one all-reduce of E and F, which is not implemented.", file=sys.stderr)
         sys.exit(2)
     import numpy as np
     import torch
