@@ -390,3 +390,26 @@ def test_history_lengths(lib, m):
             assert rc == 0 and st[0].status == lib.WF_SOLVE_CONVERGED and st[0].rel_grad <= tol
             assert rel_l2(s[0], ref["s"]) < bar
             assert rel_l2(maps[0], O.forward(ref["s"])) < bar
+
+
+def test_mixed_precision_batch(lib):
+    """float32 and float64 instances of the same problems in one batch (separate classes, run on
+    concurrent streams): each meets the oracle's MAP, and the batch equals its sequential path
+    bit for bit."""
+    import torch
+    print("[mixed float32 / float64 batch]", flush=True)
+    wls = [WL.density_workload(48, 71, nbands=4, holes=3, target_mask=0.2), WL.shear_workload(32, 72, nbands_e=3, nbands_b=3)]
+    ds = [oracle_data(wl, 80 + i) for i, wl in enumerate(wls)]
+    probs = [make_problem(lib, torch, wl, dt, d=d) for dt in ("f32", "f64") for wl, d in zip(wls, ds)]
+    opts = dict(rel_grad_tol=1e-7, max_iter=20000)
+    s, _, st, rc = lib.map_wf_solve(probs, lib.LbfgsOpts(**opts))
+    sq, _, stq, rcq = lib.map_wf_solve(probs, lib.LbfgsOpts(use_graph=0, **opts))
+    assert rc == rcq == 0
+    for i, p in enumerate(probs):
+        wl, d = wls[i % 2], ds[i % 2]
+        assert st[i].status == lib.WF_SOLVE_CONVERGED and st[i].rel_grad <= 1e-7
+        assert s[i].dtype == (torch.complex64 if i < 2 else torch.complex128)
+        assert np.array_equal(s[i].cpu().numpy(), sq[i].cpu().numpy()) and st[i].iters == stq[i].iters
+        S = O.prior_S(wl.pshape, wl.band, wl.theta_fid)
+        ref = O.lbfgs_solve(d, wl.W, S, tol=1e-12, max_iter=50000)["s"]
+        assert rel_l2(s[i].cpu().numpy(), ref) < 1e-5, i
