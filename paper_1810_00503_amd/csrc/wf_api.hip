@@ -32,7 +32,7 @@ constexpr int kMaxChunk = 256;
 constexpr size_t kVecPadBytes = 4096 + 256;
 constexpr int kMaxStreams = 4;   // the context stream plus up to 3 more for the classes of an uneven batch
 
-const char* kKindNames[KK_COUNT] = {"colinv", "row", "colfwd", "passA", "passB", "post", "coef", "misc", "passB_flush",
+const char* kKindNames[KK_COUNT] = {"colinv", "row", "colfwd", "passA", "passB", "post", "coef", "misc", "cg_dir",
                                      "simulate"};
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
@@ -628,12 +628,11 @@ int solve_core(wf_ctx* ctx, const wf_problem* probs, int B, const wf_lbfgs_opts&
       if ((rc = launch(KK_COEF, LB_CGSTEP, dim3(cnt)))) return rc;
       if ((rc = launch(KK_PASSB, LB_CGPASS, dim3(k.nchunk, cnt)))) return rc;
       if ((rc = launch(KK_POST, LB_CGPOST, dim3(cnt)))) return rc;
-      if ((rc = launch(KK_PASSBF, LB_CGDIR, dim3(k.nchunk, cnt)))) return rc;
+      if ((rc = launch(KK_DIR, LB_CGDIR, dim3(k.nchunk, cnt)))) return rc;
     } else {
       if ((rc = launch(KK_PASSA, LB_PASSA, dim3(k.nchunk, cnt)))) return rc;
       if ((rc = launch(KK_COEF, LB_COEF, dim3(cnt)))) return rc;
       if ((rc = launch(KK_PASSB, LB_PASSB, dim3(k.nchunk, cnt)))) return rc;
-      if ((rc = launch(KK_PASSBF, LB_PASSBF, dim3(k.nchunk, cnt)))) return rc;
       if ((rc = launch(KK_POST, LB_POSTB, dim3(cnt)))) return rc;
     }
     return WF_OK;
@@ -727,7 +726,7 @@ int solve_core(wf_ctx* ctx, const wf_problem* probs, int B, const wf_lbfgs_opts&
         if (!cg) ctx->launches[KK_PASSA] += K;
         ctx->launches[KK_COEF] += K;
         ctx->launches[KK_PASSB] += K;
-        ctx->launches[KK_PASSBF] += K;
+        if (cg) ctx->launches[KK_DIR] += K;
       }
       for (int s = 1; s < ns; ++s) {
         HIPCHK(hipEventRecord(ctx->xev[s - 1], ctx->xs[s - 1]));

@@ -177,7 +177,7 @@ enum { ST_RUNNING = -1 };   // otherwise WF_SOLVE_* values
 // kernel kinds for instrumentation
 enum {
   KK_COLINV = 0, KK_ROW = 1, KK_COLFWD = 2, KK_PASSA = 3, KK_PASSB = 4, KK_POST = 5, KK_COEF = 6,
-  KK_MISC = 7, KK_PASSBF = 8, KK_SIM = 9, KK_COUNT = 10
+  KK_MISC = 7, KK_DIR = 8, KK_SIM = 9, KK_COUNT = 10
 };
 
 struct LbState {

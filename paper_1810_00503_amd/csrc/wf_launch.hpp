@@ -62,7 +62,7 @@ inline bool chain_cfg_supported(int dtype, int n, int c, const ChainCfg& cfg) {
          ncb % cfg.cpb == 0;
 }
 
-enum { LB_ZERO = 0, LB_INIT = 1, LB_POSTB = 2, LB_PASSA = 3, LB_COEF = 4, LB_PASSB = 5, LB_PASSBF = 6,
+enum { LB_ZERO = 0, LB_INIT = 1, LB_POSTB = 2, LB_PASSA = 3, LB_COEF = 4, LB_PASSB = 5,
        LB_CGSTEP = 7, LB_CGPASS = 8, LB_CGPOST = 9, LB_CGDIR = 10 };
 hipError_t lbfgs_launch(int dtype, int m, int which, dim3 grid, InstDesc* desc, LbState* st, Job* jobs, int count,
                         hipStream_t s);

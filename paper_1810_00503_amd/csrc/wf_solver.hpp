@@ -303,7 +303,7 @@ __global__ __launch_bounds__(256) void k_coef(const InstDesc* __restrict__ desc,
       Sg.dirB = 0;
       Sg.flushB = 1;
       Sg.npendB = Sg.npend;
-      Sg.bytes[KK_PASSBF] += D.vbytes * (2.0 * Sg.nhist + 1.0 + 2.0);
+      Sg.bytes[KK_PASSB] += D.vbytes * (2.0 * Sg.nhist + 1.0 + 2.0);
     }
     return;
   }
@@ -517,17 +517,19 @@ __device__ __forceinline__ void coef_twoloop(const InstDesc& D, LbState& S, cons
   // bring w up to date in this pass B when the direction would overwrite a pending pair
   S.flushB = (nh == M && S.npend == M) ? 1 : 0;
   S.npendB = S.npend;
-  S.bytes[S.flushB ? KK_PASSBF : KK_PASSB] += D.vbytes * (2.0 * nh + 2.0 + (S.pending ? 1.0 : 0.0) + (S.flushB ? 2.0 : 0.0));
+  S.bytes[KK_PASSB] += D.vbytes * (2.0 * nh + 2.0 + (S.pending ? 1.0 : 0.0) + (S.flushB ? 2.0 : 0.0));
 }
 
 // ------------------------------------------------------------------------ pass B
-// FLUSH: the variant for instances whose pass B brings w up to date (launched as a second
-// kernel, so the streaming pass of the others keeps its register budget).
-template <typename T, int M, bool FLUSH>
+// One kernel for the streaming pass and, when the history wraps or before a refresh or a stop,
+// the flush of the pending steps into w (a run-time branch: a second launch per iteration for
+// the flushing instances cost more than the extra registers, 136 instead of 110 VGPRs).
+template <typename T, int M>
 __global__ __launch_bounds__(NT) void k_passB(const InstDesc* __restrict__ desc, const LbState* __restrict__ st) {
   const int i = rev_instance();
   const LbState& S = st[i];
-  if (S.status != ST_RUNNING || !S.doB || (S.flushB != 0) != FLUSH) return;
+  if (S.status != ST_RUNNING || !S.doB) return;
+  const bool flush = S.flushB != 0;
   const InstDesc& D = desc[i];
   using V = typename VecT<T>::type;
   constexpr int VW = VecT<T>::W;
@@ -552,13 +554,13 @@ __global__ __launch_bounds__(NT) void k_passB(const InstDesc* __restrict__ desc,
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   bool ok[PASS_U];
   V gv[PASS_U], acc[PASS_U];
-  V wa[FLUSH ? PASS_U : 1];
+  V wa[PASS_U];
 #pragma unroll
   for (int u = 0; u < PASS_U; ++u) {
     const uint32_t e = e0 + (uint32_t)u * NT;
     ok[u] = e < nvec;
     if (ok[u]) gv[u] = gld(X, og + e);
-    if constexpr (FLUSH) wa[u] = vzero<V>();
+    wa[u] = vzero<V>();
   }
   if (pend) {   // the step of the newest pair on g: g += alpha Dp
     const uint32_t sh = (uint32_t)head * vs;
@@ -606,9 +608,7 @@ __global__ __launch_bounds__(NT) void k_passB(const InstDesc* __restrict__ desc,
           a1 += vdot(gv[u], dv[u]);
           acc[u] = vaxpy(cP[j], pv[u], acc[u]);
           acc[u] = vaxpy(cD[j], dv[u], acc[u]);
-          if constexpr (FLUSH) {
-            if (j < np) wa[u] = vaxpy(al[j], pv[u], wa[u]);
-          }
+          if (flush && j < np) wa[u] = vaxpy(al[j], pv[u], wa[u]);
         }
       }
     }
@@ -620,7 +620,7 @@ __global__ __launch_bounds__(NT) void k_passB(const InstDesc* __restrict__ desc,
     }
   }
   stream_fence();
-  if constexpr (FLUSH) {   // w += sum alpha p over the pending pairs
+  if (flush) {   // w += sum alpha p over the pending pairs
 #pragma unroll
     for (int u = 0; u < PASS_U; ++u) {
       const uint32_t e = e0 + (uint32_t)u * NT;
@@ -940,7 +940,7 @@ __global__ __launch_bounds__(256) void k_cg_post(const InstDesc* __restrict__ de
   S.rho = rho;
   S.gdotp = -rho;   // g . p of the new direction: g is orthogonal to the previous one
   S.doDir = 1;
-  S.bytes[KK_PASSBF] += (restart ? 2.0 : 3.0) * D.vbytes;
+  S.bytes[KK_DIR] += (restart ? 2.0 : 3.0) * D.vbytes;
   S.chainMode = CM_HV;
   cg_job(jobs[i], D, CM_HV);
   add_chain_bytes(S, D, CM_HV, 0);

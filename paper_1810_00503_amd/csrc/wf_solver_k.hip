@@ -19,8 +19,7 @@ static hipError_t lb_t(int which, dim3 grid, InstDesc* desc, LbState* st, Job* j
     case LB_POSTB: k_postB<M><<<dim3(count), dim3(256), 0, s>>>(desc, st, jobs); break;
     case LB_PASSA: k_passA<T, M><<<grid, dim3(NT), 0, s>>>(desc, st); break;
     case LB_COEF: k_coef<M><<<dim3(count), dim3(256), 0, s>>>(desc, st, jobs); break;
-    case LB_PASSB: k_passB<T, M, false><<<grid, dim3(NT), 0, s>>>(desc, st); break;
-    case LB_PASSBF: k_passB<T, M, true><<<grid, dim3(NT), 0, s>>>(desc, st); break;
+    case LB_PASSB: k_passB<T, M><<<grid, dim3(NT), 0, s>>>(desc, st); break;
     case LB_CGSTEP: k_cg_step<<<dim3(count), dim3(256), 0, s>>>(desc, st, jobs); break;
     case LB_CGPASS: k_cg_pass<T><<<grid, dim3(NT), 0, s>>>(desc, st); break;
     case LB_CGPOST: k_cg_post<<<dim3(count), dim3(256), 0, s>>>(desc, st, jobs); break;

@@ -39,7 +39,7 @@ def test_binding_matches_exports():
     lib = _lib.load()
     assert lib.wf_kernel_kinds() == 10
     assert lib.wf_kernel_kind_name(9) == b"simulate"
-    assert lib.wf_kernel_kind_name(8) == b"passB_flush"
+    assert lib.wf_kernel_kind_name(8) == b"cg_dir"
     assert lib.wf_kernel_kind_name(3) == b"passA"
     o = _lib.WfLbfgsOpts()
     lib.wf_lbfgs_default(ctypes.byref(o))
