@@ -344,6 +344,7 @@ struct Klass {
   int first = 0;              // position in the class-ordered arrays
   int64_t L = 0;
   int nchunk = 0, pstride = 0;
+  int pu = PASS_U_FEW;   // vector loads per thread per stream of the class's vector passes
   ChainCfg cfg;    // tile choice of the transform chain
   const void* tw = nullptr;
 };
@@ -519,7 +520,9 @@ int solve_core(wf_ctx* ctx, const wf_problem* probs, int B, const wf_lbfgs_opts&
     k.L = (int64_t)k.c * k.n * (k.n / 2);
     const size_t eb = esize_of(k.dtype);
     const int64_t nvec = k.L * 2 / (k.dtype == WF_F64 ? 2 : 4);
-    k.nchunk = (int)((nvec + PASS_CV - 1) / PASS_CV);
+    const int64_t many = (nvec + NT * PASS_U_MANY - 1) / (NT * PASS_U_MANY);
+    k.pu = many * (int64_t)k.members.size() >= PASS_MANY_MIN_GROUPS ? PASS_U_MANY : PASS_U_FEW;
+    k.nchunk = (int)((nvec + NT * k.pu - 1) / (NT * k.pu));
     k.pstride = k.c * k.n / RB_MIN;   // row partials per component and RB_MIN rows
     const size_t vsb = (size_t)k.L * eb + kVecPadBytes;
     const size_t per = align_up((size_t)(2 + 2 * m) * vsb) + align_up(vsb) +
@@ -599,12 +602,12 @@ int solve_core(wf_ctx* ctx, const wf_problem* probs, int B, const wf_lbfgs_opts&
       Timed t(ctx, KK_MISC);
       const int64_t nvec = k.L * 2 / (k.dtype == WF_F64 ? 2 : 4);
       const unsigned bx = (unsigned)std::min<int64_t>((nvec + 255) / 256, 1024);
-      HIPCHK(lbfgs_launch(k.dtype == WF_F64, m, LB_ZERO, dim3(bx, cnt), ddesc + k.first, dst + k.first,
+      HIPCHK(lbfgs_launch(k.dtype == WF_F64, m, k.pu, LB_ZERO, dim3(bx, cnt), ddesc + k.first, dst + k.first,
                           djobs + k.first, cnt, ctx->cs));
     }
     {
       Timed t(ctx, KK_MISC);
-      HIPCHK(lbfgs_launch(k.dtype == WF_F64, m, LB_INIT, dim3(1), ddesc + k.first, dst + k.first, djobs + k.first, cnt,
+      HIPCHK(lbfgs_launch(k.dtype == WF_F64, m, k.pu, LB_INIT, dim3(1), ddesc + k.first, dst + k.first, djobs + k.first, cnt,
                           ctx->cs));
     }
   }
@@ -620,7 +623,7 @@ int solve_core(wf_ctx* ctx, const wf_problem* probs, int B, const wf_lbfgs_opts&
     }
     auto launch = [&](int kk, int which, dim3 grid) -> int {
       Timed t(ctx, kk);
-      HIPCHK(lbfgs_launch(dt, m, which, grid, ddesc + k.first, dst + k.first, djobs + k.first, cnt, ctx->cs));
+      HIPCHK(lbfgs_launch(dt, m, k.pu, which, grid, ddesc + k.first, dst + k.first, djobs + k.first, cnt, ctx->cs));
       return WF_OK;
     };
     int rc;

@@ -96,8 +96,11 @@ __device__ __forceinline__ void gst(T* base, uint32_t i, const T& x) {
 constexpr int TB = 2;
 constexpr int RB_MIN = 2;  // granularity of the row pass's partial sums (rows)
 constexpr int NT = 256;    // threads per work-group of the transform and vector passes
-constexpr int PASS_U = 4;                // vector loads per thread per stream in a vector pass
-constexpr int PASS_CV = NT * PASS_U;     // vector elements of one stream per work-group
+// vector loads per thread per stream in a vector pass (a template parameter of the passes): 8
+// (longer runs per stream) for a class with enough work-groups to fill the GPU, else 4 (twice the
+// work-groups, for the few-instance classes of an uneven batch and their tails)
+constexpr int PASS_U_FEW = 4, PASS_U_MANY = 8;
+constexpr int64_t PASS_MANY_MIN_GROUPS = 4096;   // work-groups per pass launch needed for PASS_U_MANY
 
 __host__ __device__ __forceinline__ int64_t fidx(int n, int c, int ky, int kx) {
   const int h = n >> 1;

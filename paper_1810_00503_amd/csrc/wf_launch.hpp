@@ -64,8 +64,10 @@ inline bool chain_cfg_supported(int dtype, int n, int c, const ChainCfg& cfg) {
 
 enum { LB_ZERO = 0, LB_INIT = 1, LB_POSTB = 2, LB_PASSA = 3, LB_COEF = 4, LB_PASSB = 5,
        LB_CGSTEP = 7, LB_CGPASS = 8, LB_CGPOST = 9, LB_CGDIR = 10 };
-hipError_t lbfgs_launch(int dtype, int m, int which, dim3 grid, InstDesc* desc, LbState* st, Job* jobs, int count,
-                        hipStream_t s);
+// pu: vector loads per thread per stream of the vector passes (PASS_U_FEW or PASS_U_MANY); the
+// grid of a vector pass is (ceil(vector elements / (NT pu)), instances)
+hipError_t lbfgs_launch(int dtype, int m, int pu, int which, dim3 grid, InstDesc* desc, LbState* st, Job* jobs,
+                        int count, hipStream_t s);
 
 // prior tables; with W non-null also the preconditioner (mean of W into meanW, a, ainv)
 hipError_t prior_table_launch(int dtype, int n, int c, const double* pshape, const int32_t* band, const double* theta,

@@ -176,7 +176,7 @@ __global__ void k_init(InstDesc* desc, LbState* st, Job* jobs, int batch) {
 // After an exact gradient: g.g, g.p_j, g.Dp_j for the kept pairs, one slot at a time.  An
 // exact gradient that confirms a stop needs g.g only; the dots follow in a CM_DOTS
 // iteration if the confirmation fails.
-template <typename T, int M>
+template <typename T, int M, int PASS_U>
 __global__ __launch_bounds__(NT) void k_passA(const InstDesc* __restrict__ desc, const LbState* __restrict__ st) {
   const int i = rev_instance();
   const LbState& S = st[i];
@@ -189,7 +189,7 @@ __global__ __launch_bounds__(NT) void k_passA(const InstDesc* __restrict__ desc,
   // element offsets (units of V) from the instance's vector block, 32-bit
   const uint32_t nvec = (uint32_t)(D.L * 2 / VW);
   const uint32_t vs = (uint32_t)(D.vstride * 2 / VW);
-  const uint32_t e0 = blockIdx.x * (uint32_t)PASS_CV + threadIdx.x;
+  const uint32_t e0 = blockIdx.x * (uint32_t)(NT * PASS_U) + threadIdx.x;
   const V* X = reinterpret_cast<const V*>(D.X);
   const uint32_t og = vs, oP = 2 * vs, oD = (2 + M) * vs;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -524,7 +524,7 @@ __device__ __forceinline__ void coef_twoloop(const InstDesc& D, LbState& S, cons
 // One kernel for the streaming pass and, when the history wraps or before a refresh or a stop,
 // the flush of the pending steps into w (a run-time branch: a second launch per iteration for
 // the flushing instances cost more than the extra registers, 136 instead of 110 VGPRs).
-template <typename T, int M>
+template <typename T, int M, int PASS_U>
 __global__ __launch_bounds__(NT) void k_passB(const InstDesc* __restrict__ desc, const LbState* __restrict__ st) {
   const int i = rev_instance();
   const LbState& S = st[i];
@@ -548,7 +548,7 @@ __global__ __launch_bounds__(NT) void k_passB(const InstDesc* __restrict__ desc,
   // element offsets (units of V) from the instance's vector block, 32-bit
   const uint32_t nvec = (uint32_t)(D.L * 2 / VW);
   const uint32_t vs = (uint32_t)(D.vstride * 2 / VW);
-  const uint32_t e0 = blockIdx.x * (uint32_t)PASS_CV + threadIdx.x;
+  const uint32_t e0 = blockIdx.x * (uint32_t)(NT * PASS_U) + threadIdx.x;
   V* X = reinterpret_cast<V*>(D.X);
   const uint32_t ow = 0, og = vs, oP = 2 * vs, oD = (2 + M) * vs;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -844,7 +844,7 @@ __global__ __launch_bounds__(256) void k_cg_step(const InstDesc* __restrict__ de
 
 // vector pass: w += alpha p, g += alpha Dp (after a curvature product); partial sums of g.g
 // and of the whitened |g|^2 (kinds 0 and 1 of partA)
-template <typename T>
+template <typename T, int PASS_U>
 __global__ __launch_bounds__(NT) void k_cg_pass(const InstDesc* __restrict__ desc, const LbState* __restrict__ st) {
   const int i = rev_instance();
   const LbState& S = st[i];
@@ -855,7 +855,7 @@ __global__ __launch_bounds__(NT) void k_cg_pass(const InstDesc* __restrict__ des
   __shared__ double red[NT / 64][2];
   const uint32_t nvec = (uint32_t)(D.L * 2 / VW);
   const uint32_t vs = (uint32_t)(D.vstride * 2 / VW);
-  const uint32_t e0 = blockIdx.x * (uint32_t)PASS_CV + threadIdx.x;
+  const uint32_t e0 = blockIdx.x * (uint32_t)(NT * PASS_U) + threadIdx.x;
   V* X = reinterpret_cast<V*>(D.X);
   const uint32_t ow = 0, og = vs, op = 2 * vs, od = (uint32_t)(2 + D.m) * vs;
   const bool upd = S.doB == 1;
@@ -947,7 +947,7 @@ __global__ __launch_bounds__(256) void k_cg_post(const InstDesc* __restrict__ de
 }
 
 // direction pass: p = -g + beta p (p = -g after an exact gradient)
-template <typename T>
+template <typename T, int PASS_U>
 __global__ __launch_bounds__(NT) void k_cg_dir(const InstDesc* __restrict__ desc, const LbState* __restrict__ st) {
   const int i = blockIdx.y;
   const LbState& S = st[i];
@@ -957,7 +957,7 @@ __global__ __launch_bounds__(NT) void k_cg_dir(const InstDesc* __restrict__ desc
   constexpr int VW = VecT<T>::W;
   const uint32_t nvec = (uint32_t)(D.L * 2 / VW);
   const uint32_t vs = (uint32_t)(D.vstride * 2 / VW);
-  const uint32_t e0 = blockIdx.x * (uint32_t)PASS_CV + threadIdx.x;
+  const uint32_t e0 = blockIdx.x * (uint32_t)(NT * PASS_U) + threadIdx.x;
   V* X = reinterpret_cast<V*>(D.X);
   const uint32_t og = vs, op = 2 * vs;
   const T be = T(S.beta);

@@ -12,27 +12,41 @@ bool chain_supported(int n) {
 }
 
 template <typename T, int M>
-static hipError_t lb_t(int which, dim3 grid, InstDesc* desc, LbState* st, Job* jobs, int count, hipStream_t s) {
+static hipError_t lb_t(int which, int pu, dim3 grid, InstDesc* desc, LbState* st, Job* jobs, int count, hipStream_t s) {
+  const bool many = pu == PASS_U_MANY;
   switch (which) {
     case LB_ZERO: k_zero<T><<<grid, dim3(256), 0, s>>>(desc, count); break;
     case LB_INIT: k_init<<<dim3((count + 63) / 64), dim3(64), 0, s>>>(desc, st, jobs, count); break;
     case LB_POSTB: k_postB<M><<<dim3(count), dim3(256), 0, s>>>(desc, st, jobs); break;
-    case LB_PASSA: k_passA<T, M><<<grid, dim3(NT), 0, s>>>(desc, st); break;
+    case LB_PASSA:
+      if (many) k_passA<T, M, PASS_U_MANY><<<grid, dim3(NT), 0, s>>>(desc, st);
+      else k_passA<T, M, PASS_U_FEW><<<grid, dim3(NT), 0, s>>>(desc, st);
+      break;
     case LB_COEF: k_coef<M><<<dim3(count), dim3(256), 0, s>>>(desc, st, jobs); break;
-    case LB_PASSB: k_passB<T, M><<<grid, dim3(NT), 0, s>>>(desc, st); break;
+    case LB_PASSB:
+      if (many) k_passB<T, M, PASS_U_MANY><<<grid, dim3(NT), 0, s>>>(desc, st);
+      else k_passB<T, M, PASS_U_FEW><<<grid, dim3(NT), 0, s>>>(desc, st);
+      break;
     case LB_CGSTEP: k_cg_step<<<dim3(count), dim3(256), 0, s>>>(desc, st, jobs); break;
-    case LB_CGPASS: k_cg_pass<T><<<grid, dim3(NT), 0, s>>>(desc, st); break;
+    case LB_CGPASS:
+      if (many) k_cg_pass<T, PASS_U_MANY><<<grid, dim3(NT), 0, s>>>(desc, st);
+      else k_cg_pass<T, PASS_U_FEW><<<grid, dim3(NT), 0, s>>>(desc, st);
+      break;
     case LB_CGPOST: k_cg_post<<<dim3(count), dim3(256), 0, s>>>(desc, st, jobs); break;
-    case LB_CGDIR: k_cg_dir<T><<<grid, dim3(NT), 0, s>>>(desc, st); break;
+    case LB_CGDIR:
+      if (many) k_cg_dir<T, PASS_U_MANY><<<grid, dim3(NT), 0, s>>>(desc, st);
+      else k_cg_dir<T, PASS_U_FEW><<<grid, dim3(NT), 0, s>>>(desc, st);
+      break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
 
 template <typename T>
-static hipError_t lb_m(int m, int which, dim3 grid, InstDesc* desc, LbState* st, Job* jobs, int count, hipStream_t s) {
+static hipError_t lb_m(int m, int which, int pu, dim3 grid, InstDesc* desc, LbState* st, Job* jobs, int count,
+                       hipStream_t s) {
   switch (m) {
-#define WF_M(M) case M: return lb_t<T, M>(which, grid, desc, st, jobs, count, s);
+#define WF_M(M) case M: return lb_t<T, M>(which, pu, grid, desc, st, jobs, count, s);
     WF_M(1) WF_M(2) WF_M(3) WF_M(4) WF_M(5) WF_M(6) WF_M(7) WF_M(8)
     WF_M(9) WF_M(10) WF_M(11) WF_M(12) WF_M(13) WF_M(14) WF_M(15) WF_M(16)
 #undef WF_M
@@ -40,10 +54,11 @@ static hipError_t lb_m(int m, int which, dim3 grid, InstDesc* desc, LbState* st,
   }
 }
 
-hipError_t lbfgs_launch(int dtype, int m, int which, dim3 grid, InstDesc* desc, LbState* st, Job* jobs, int count,
-                        hipStream_t s) {
-  return dtype == 0 ? lb_m<float>(m, which, grid, desc, st, jobs, count, s)
-                    : lb_m<double>(m, which, grid, desc, st, jobs, count, s);
+hipError_t lbfgs_launch(int dtype, int m, int pu, int which, dim3 grid, InstDesc* desc, LbState* st, Job* jobs,
+                        int count, hipStream_t s) {
+  if (pu != PASS_U_FEW && pu != PASS_U_MANY) return hipErrorInvalidValue;
+  return dtype == 0 ? lb_m<float>(m, which, pu, grid, desc, st, jobs, count, s)
+                    : lb_m<double>(m, which, pu, grid, desc, st, jobs, count, s);
 }
 
 static dim3 flat_grid(int64_t tot) {
