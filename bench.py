@@ -332,7 +332,7 @@ def main():
     tiles = wf.get_chain_tiles(args.n, 2, wf.WF_F32, nsolve)
     conv = sum(s.status == wf.WF_SOLVE_CONVERGED for s in st_b)
 
-    plain = None
+    plain = plain_graph = None
     if not args.no_plain:
         npl = len(sims) if args.plain_solves <= 0 else min(args.plain_solves, len(sims))
         popts = wf.LbfgsOpts(m=args.m, rel_grad_tol=args.tol, use_graph=0, iters_per_poll=1)
@@ -343,6 +343,16 @@ def main():
             wf.map_wf_solve([p], popts)
         torch.cuda.synchronize()
         plain = npl / (time.perf_counter() - t0)
+        # one map at a time, but with the batch's graph replay (8 iterations between host polls):
+        # separates what batching gains from what the captured iterations gain
+        gopts = wf.LbfgsOpts(m=args.m, rel_grad_tol=args.tol, iters_per_poll=8)
+        wf.map_wf_solve(sims[:1], gopts)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for p in sims[:npl]:
+            wf.map_wf_solve([p], gopts)
+        torch.cuda.synchronize()
+        plain_graph = npl / (time.perf_counter() - t0)
 
     # one instrumented step: events around every launch, device-counted algorithmic bytes
     wf.reset_kernel_stats()
@@ -404,6 +414,7 @@ def main():
         "batched_solve_only_cg": cg_line,
         "batched_solve_only_precond": pc_line,
         "plain_solves_per_s": None if plain is None else round(plain, 2),
+        "plain_graph_solves_per_s": None if plain_graph is None else round(plain_graph, 2),
         "speedup_batched_vs_plain": None if plain is None else round(len(sims) / t_batch / plain, 2),
         "bandpower_estimates_per_s": round(args.steps / elapsed, 3),
         "iters_mean": round(float(np.mean(iters)), 1), "iters_max": int(np.max(iters)),
