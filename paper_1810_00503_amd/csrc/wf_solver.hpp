@@ -6,6 +6,8 @@
 //            of Dp with the stored g and with the kept Dp_j;
 //   passA    only after an exact-gradient evaluation: dots of the new g with the kept
 //            pairs (otherwise these come from the previous pass B and a one-step update);
+//            g.g alone when the gradient confirms a stop, the dots following in a
+//            transform-free iteration if the confirmation fails;
 //   coef     step length alpha = -g.p / p.Dp of the exact line search of a quadratic
 //            (eq. eq_chib), Gram entries of the new pair, stop test after an exact gradient,
 //            and the two-loop recursion run on coefficients: the direction is a combination
