@@ -39,18 +39,31 @@ __device__ __forceinline__ void philox4x32_10(uint32_t& c0, uint32_t& c1, uint32
 }
 
 // Normals q and q + 1 (q even) of simulation `sim`: Box-Muller of the Philox pair that
-// holds them, in float64.
-__device__ __forceinline__ void philox_normal_pair(uint64_t seed, int sim, int64_t q, double& z0, double& z1) {
+// holds them, u = (x + 1/2) 2^-32.  R = double for float64 fields; float32 fields take the
+// transform in float32 (the hardware log, square root and sine/cosine), whose few-ulp
+// differences from the float64 transform are below the fields' own rounding.
+template <typename R>
+__device__ __forceinline__ void philox_normal_pair(uint64_t seed, int sim, int64_t q, R& z0, R& z1) {
   uint32_t c0 = (uint32_t)(q >> 2), c1 = (uint32_t)sim, c2 = 0u, c3 = 0u;
   philox4x32_10(c0, c1, c2, c3, (uint32_t)(seed & 0xffffffffu), (uint32_t)(seed >> 32));
   const bool hi = (q & 2) != 0;
   const uint32_t xa = hi ? c2 : c0, xb = hi ? c3 : c1;
-  const double u0 = ((double)xa + 0.5) * 2.3283064365386963e-10;
-  const double u1 = ((double)xb + 0.5) * 2.3283064365386963e-10;
-  const double r = sqrt(-2.0 * log(u0));
-  const double ang = 6.283185307179586 * u1;
-  z0 = r * cos(ang);
-  z1 = r * sin(ang);
+  if constexpr (sizeof(R) == 8) {
+    const double u0 = ((double)xa + 0.5) * 2.3283064365386963e-10;
+    const double u1 = ((double)xb + 0.5) * 2.3283064365386963e-10;
+    const double r = sqrt(-2.0 * log(u0));
+    const double ang = 6.283185307179586 * u1;
+    z0 = r * cos(ang);
+    z1 = r * sin(ang);
+  } else {
+    const float u0 = ((float)xa + 0.5f) * 2.3283064365386963e-10f;
+    const float u1 = ((float)xb + 0.5f) * 2.3283064365386963e-10f;
+    const float r = sqrtf(-2.0f * logf(u0));
+    float sn, cs;
+    sincosf(6.2831853071795865f * u1, &sn, &cs);
+    z0 = r * cs;
+    z1 = r * sn;
+  }
 }
 
 // ------------------------------------------------------------------------ reductions
@@ -105,7 +118,7 @@ __device__ __forceinline__ int rev_instance() { return (int)(gridDim.y - 1 - blo
 // liveness, prior partial (gradient modes).  Returns the value before the spin-2 rotation;
 // part/kyr tell whether (ky, kx) is a kx = 0 conjugate partner and which stored row holds its
 // free entry.  SIMK: the simulation mode
-// (normals from draws or Philox, in float64) is compiled in; it costs registers, so only the
+// (normals from draws or Philox) is compiled in; it costs registers, so only the
 // kernels that simulation launches use it.
 template <typename T, int N, bool SIMK>
 __device__ __forceinline__ cpx<T> colinv_in(const Job& jb, int mode, int c, int ky, int kx, bool& part,
@@ -126,9 +139,9 @@ __device__ __forceinline__ cpx<T> colinv_in(const Job& jb, int mode, int c, int 
     if (draws) {
       v = mk(draws[qn], draws[qn + 1]);
     } else {
-      double z0, z1;
-      philox_normal_pair(jb.seed, jb.sim, qn, z0, z1);
-      v = mk(T(z0), T(z1));
+      T z0, z1;
+      philox_normal_pair<T>(jb.seed, jb.sim, qn, z0, z1);
+      v = mk(z0, z1);
     }
     sc = gld(sIn, src) * T(0.70710678118654752440084436210485);
     if (jb.band && jb.boost_band >= 0 && gld(jb.band, src) == jb.boost_band) sc *= T(jb.boost_factor);
@@ -221,10 +234,7 @@ __device__ __forceinline__ void row_pixel(const Job& jb, int mode, bool adjIn, i
       n0 = draws[qn];
       n1 = draws[qn + 1];
     } else {
-      double z0, z1;
-      philox_normal_pair(jb.seed, jb.sim, qn, z0, z1);
-      n0 = T(z0);
-      n1 = T(z1);
+      philox_normal_pair<T>(jb.seed, jb.sim, qn, n0, n1);
     }
     xout[cp] = W0 > T(0) ? x0 + n0 / sqrt(W0) : T(0);
     xout[cp + 1] = W1 > T(0) ? x1 + n1 / sqrt(W1) : T(0);

@@ -1094,10 +1094,10 @@ __global__ void k_sim_coeffs(int n, int C, int nsim, int sim0, uint64_t seed, co
       if (draws) {
         const T* dr = draws + (int64_t)i * 2 * C * n * n;
         z = mk(dr[qn], dr[qn + 1]);
-      } else {
-        double z0, z1;
-        philox_normal_pair(seed, sim0 + i, qn, z0, z1);
-        z = mk(T(z0), T(z1));
+      } else {   // the same normals as the simulation pass draws for this field type
+        T z0, z1;
+        philox_normal_pair<T>(seed, sim0 + i, qn, z0, z1);
+        z = mk(z0, z1);
       }
       const T sc = sq[fidx(n, c, kyr, kx)] * T(0.70710678118654752440084436210485);
       v = scale(z, sc);
