@@ -783,6 +783,31 @@ void fill_stats(const SolveOut& so, int B, wf_solve_stats* stats) {
 }
 
 // forward map of solved fields into caller buffers (mode CM_FWD on the whitened w)
+// s = sqrt(S) w with partners filled, into the caller's buffers: one launch per class of
+// equal (n, ncomp, dtype), from a device table of per-instance pointers
+int pack_solutions(wf_ctx* ctx, const wf_problem* probs, int B, const SolveOut& so, void* const* s_out) {
+  std::map<std::tuple<int, int, int>, std::vector<int>> cls;
+  for (int i = 0; i < B; ++i) cls[std::make_tuple(probs[i].n, probs[i].ncomp, probs[i].dtype)].push_back(i);
+  std::vector<PackEntry> tab;
+  tab.reserve(B);
+  for (auto& kv : cls)
+    for (int i : kv.second) tab.push_back(PackEntry{so.w[i], so.prior[i].sq, s_out[i]});
+  int rc = arena_reserve(ctx, ctx->opA, align_up(sizeof(PackEntry) * tab.size()));
+  if (rc) return rc;
+  PackEntry* dt = (PackEntry*)arena_take(ctx->opA, sizeof(PackEntry) * tab.size());
+  HIPCHK(hipMemcpyAsync(dt, tab.data(), sizeof(PackEntry) * tab.size(), hipMemcpyHostToDevice, ctx->cs));
+  size_t off = 0;
+  for (auto& kv : cls) {
+    const int cnt = (int)kv.second.size();
+    HIPCHK(pack_tab_launch(std::get<2>(kv.first), std::get<0>(kv.first), std::get<1>(kv.first), cnt, dt + off,
+                           ctx->cs));
+    off += (size_t)cnt;
+  }
+  // the table is reused by the next call on this arena
+  HIPCHK(hipStreamSynchronize(ctx->cs));
+  return WF_OK;
+}
+
 int maps_from_solution(wf_ctx* ctx, const wf_problem* probs, int B, const SolveOut& so, void* const* map_out) {
   if (!map_out) return WF_OK;
   std::map<std::tuple<int, int, int>, std::vector<int>> cls;
@@ -1244,12 +1269,8 @@ int map_wf_solve(wf_ctx* ctx, const wf_problem* probs, int32_t batch, const wf_l
   SolveOut so;
   int rc = solve_core(ctx, probs, batch, o, so);
   if (rc) return rc;
-  // s = sqrt(S) w with partners filled, into the caller's buffers
-  for (int i = 0; i < batch; ++i) {
-    const wf_problem* p = &probs[i];
-    HIPCHK(pack_launch(p->dtype, p->n, p->ncomp, 1, so.w[i], 0, so.prior[i].sq, 1, nullptr,
-                       s_out[i], ctx->cs));
-  }
+  rc = pack_solutions(ctx, probs, batch, so, s_out);
+  if (rc) return rc;
   rc = maps_from_solution(ctx, probs, batch, so, map_out);
   if (rc) return rc;
   HIPCHK(hipStreamSynchronize(ctx->cs));

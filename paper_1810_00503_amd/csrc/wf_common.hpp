@@ -224,6 +224,13 @@ struct LbState {
   int confirm;                 // the pending exact gradient confirms a stop: pass A takes g.g only
 };
 
+// One instance of a batched pack (internal whitened field -> caller's external field).
+struct PackEntry {
+  const void* in;   // internal field
+  const void* sq;   // sqrt S table (internal layout), nullable
+  void* out;        // [C][n][n/2+1] external field
+};
+
 // One field's band-statistic job.
 struct BandJob {
   const void* f;          // field, internal layout

@@ -74,6 +74,8 @@ hipError_t prior_table_launch(int dtype, int n, int c, const double* pshape, con
                               int nbands, const void* W, double* meanW, void* sq, int32_t* bandI, void* aT, void* ainvT,
                               hipStream_t s);
 hipError_t unpack_launch(int dtype, int n, int c, int batch, const void* ext, void* in, hipStream_t s);
+// tab: device [batch] of per-instance (internal field, sqrt S table, external output)
+hipError_t pack_tab_launch(int dtype, int n, int c, int batch, const PackEntry* tab, hipStream_t s);
 hipError_t pack_launch(int dtype, int n, int c, int batch, const void* in, int64_t inStride,
                        const void* sq, int fill, void* const* outs, void* out0, hipStream_t s);
 hipError_t band_launch(int dtype, const BandJob* jobs, int count, int64_t L, hipStream_t s);

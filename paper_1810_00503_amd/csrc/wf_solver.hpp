@@ -1069,6 +1069,31 @@ __global__ void k_pack(int n, int C, int batch, const cpx<T>* __restrict__ in, i
   }
 }
 
+// k_pack with fill = 1 over a batch whose inputs, prior tables and outputs are given per
+// instance (one launch for a class of solved fields that need not share a prior).
+template <typename T>
+__global__ void k_pack_tab(int n, int C, int batch, const PackEntry* __restrict__ tab) {
+  const int h = n / 2;
+  const int64_t per = (int64_t)C * n * (h + 1);
+  const int64_t tot = per * batch;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < tot; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = e / per, r0 = e % per;
+    const PackEntry pe = tab[i];
+    const int c = (int)(r0 / ((int64_t)n * (h + 1)));
+    const int r = (int)(r0 % ((int64_t)n * (h + 1)));
+    const int ky = r / (h + 1), kx = r % (h + 1);
+    cpx<T> v = mk(T(0), T(0));
+    if (kx < h && is_live(n, ky, kx)) {
+      const bool part = is_partner(n, ky, kx);
+      const int64_t src = fidx(n, c, part ? n - ky : ky, kx);
+      v = reinterpret_cast<const cpx<T>*>(pe.in)[src];
+      if (pe.sq) v = scale(v, reinterpret_cast<const T*>(pe.sq)[src]);
+      if (part) v = conj(v);
+    }
+    reinterpret_cast<cpx<T>*>(pe.out)[r0] = v;
+  }
+}
+
 // Signal coefficients of simulations sim0 .. sim0 + nsim - 1 (sec. 2.4) in the external
 // layout [nsim][C][n][n/2+1]: s = sqrt S (z_re, z_im) / sqrt 2 on the free entries with the
 // simulation pass's normals and rounding (draws, or the Philox stream when draws is null),

@@ -109,6 +109,15 @@ hipError_t pack_launch(int dtype, int n, int c, int batch, const void* in, int64
   return hipGetLastError();
 }
 
+hipError_t pack_tab_launch(int dtype, int n, int c, int batch, const PackEntry* tab, hipStream_t s) {
+  const dim3 g = flat_grid((int64_t)batch * c * n * (n / 2 + 1));
+  if (dtype == 0)
+    k_pack_tab<float><<<g, 256, 0, s>>>(n, c, batch, tab);
+  else
+    k_pack_tab<double><<<g, 256, 0, s>>>(n, c, batch, tab);
+  return hipGetLastError();
+}
+
 hipError_t sim_coeffs_launch(int dtype, int n, int c, int nsim, int sim0, uint64_t seed, const void* draws,
                              const void* sq, void* out, hipStream_t s) {
   const dim3 g = flat_grid((int64_t)nsim * c * n * (n / 2 + 1));
