@@ -49,6 +49,7 @@ def parse():
     ap.add_argument("--plain-solves", type=int, default=0, help="plain-path solves to time (0 = all)")
     ap.add_argument("--no-secondary", action="store_true", help="skip the other workloads' lines")
     ap.add_argument("--cpu-child", action="store_true", help=argparse.SUPPRESS)
+    ap.add_argument("--cpu-out", default="", help=argparse.SUPPRESS)
     return ap.parse_args()
 
 
@@ -70,15 +71,42 @@ def measured_traffic(kernel: str):
     return None if k is None else k["traffic_bytes_per_launch"]
 
 
-def cpu_baseline(args):
-    """The oracle (float64 numpy, one thread) solving the data map of the workload."""
+def cpu_baseline(args, gpu_solve=None):
+    """The oracle (float64 numpy, one thread) solving the data map of the workload and two
+    simulations, timed at the benchmark's tolerance.  The child also writes those maps with the
+    oracle's MAP at 1e-10 (untimed); gpu_solve(maps) -> (fields, maps, stats) solves the same
+    data on the GPU at the benchmark's tolerance, and the accuracy beside the throughput is the
+    GPU against that reference (field relative L2; per-pixel map error on observed and on
+    masked pixels, relative to the largest reference pixel)."""
+    import tempfile
+
+    import numpy as np
     env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
-    cmd = [sys.executable, os.path.abspath(__file__), "--cpu-child", "--n", str(args.n), "--tol", str(args.tol),
-           "--m", str(args.m), "--seed", str(args.seed)]
-    r = subprocess.run(cmd, capture_output=True, text=True, env=env, timeout=600)
-    if r.returncode != 0:
-        return {"error": r.stderr[-400:]}
-    return json.loads(r.stdout.strip().splitlines()[-1])
+    with tempfile.TemporaryDirectory() as tmp:
+        out = os.path.join(tmp, "ref.npz")
+        cmd = [sys.executable, os.path.abspath(__file__), "--cpu-child", "--n", str(args.n), "--tol", str(args.tol),
+               "--m", str(args.m), "--seed", str(args.seed), "--cpu-out", out]
+        r = subprocess.run(cmd, capture_output=True, text=True, env=env, timeout=900)
+        if r.returncode != 0:
+            return {"error": r.stderr[-400:]}
+        res = json.loads(r.stdout.strip().splitlines()[-1])
+        if gpu_solve is not None and os.path.exists(out):
+            ref = np.load(out)
+            k = int(ref["count"])
+            s, x, st = gpu_solve([ref[f"d{i}"] for i in range(k)])
+            obs = ref["observed"]
+            el2, eo, em = [], [], []
+            for i in range(k):
+                sr, xr = ref[f"s{i}"], ref[f"x{i}"]
+                el2.append(float(np.linalg.norm(s[i] - sr) / np.linalg.norm(sr)))
+                dx = np.abs(x[i] - xr) / np.abs(xr).max()
+                eo.append(float(dx[:, obs].max()))
+                em.append(float(dx[:, ~obs].max()))
+            res["accuracy"] = {"maps": k, "reference": "oracle float64 MAP to 1e-10 of the same data",
+                               "field_rel_l2_max": max(el2), "map_max_abs_observed_rel": max(eo),
+                               "map_max_abs_masked_rel": max(em),
+                               "gpu_rel_grad_max": max(float(x_.rel_grad) for x_ in st)}
+    return res
 
 
 def cpu_child(args):
@@ -96,6 +124,12 @@ def cpu_child(args):
     t0 = time.perf_counter()
     its = [O.lbfgs_solve(d, wl.W, S, m=args.m, tol=args.tol)["iters"] for d in maps]
     dt = time.perf_counter() - t0
+    if args.cpu_out:   # the reference for the accuracy line (untimed)
+        ref = {"count": len(maps), "observed": wl.W > 0}
+        for i, d in enumerate(maps):
+            sr = O.lbfgs_solve(d, wl.W, S, m=args.m, tol=1e-10, max_iter=50000)["s"]
+            ref[f"d{i}"], ref[f"s{i}"], ref[f"x{i}"] = d, sr, O.forward(sr)
+        np.savez(args.cpu_out, **ref)
     print(json.dumps({"value": len(maps) / dt, "unit": "solves/s", "cores": 1, "kind": "oracle",
                       "sample": f"{len(maps)} MAP solves (the {args.n}^2 E/B shear data map and 2 fiducial "
                                 f"simulations) to {args.tol:g} rel. grad, float64 numpy on 1 thread, "
@@ -396,7 +430,13 @@ def main():
     del src, dst
     roof["copy_ceiling_GBps"] = round(copy_gbs, 1)
 
-    cpu = None if args.no_cpu else cpu_baseline(args)
+    def gpu_solve(ds):
+        probs = [base.with_data(torch.tensor(np.asarray(d), dtype=torch.float32, device=dev)) for d in ds]
+        s_, x_, st_, _ = wf.map_wf_solve(probs, opts, want_maps=True)
+        return [t.cpu().numpy() for t in s_], [t.cpu().numpy() for t in x_], st_
+
+    cpu = None if args.no_cpu else cpu_baseline(args, gpu_solve)
+    accuracy = cpu.pop("accuracy", None) if isinstance(cpu, dict) else None
     secondary = None if args.no_secondary else secondary_workloads(args)
     out = {
         "metric": METRIC, "value": round(value, 2), "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
@@ -410,6 +450,7 @@ def main():
         "roofline": roof,
         "roofline_gradient_chain": roof_chain,
         "cpu_baseline": cpu,
+        "accuracy": accuracy,
         "batched_solve_only_solves_per_s": round(len(sims) / t_batch, 2),
         "batched_solve_only_cg": cg_line,
         "batched_solve_only_precond": pc_line,
