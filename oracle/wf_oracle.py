@@ -23,10 +23,18 @@ Conventions the paper leaves open (fixed identically for the HIP library):
   the Euclidean inner product of their real and imaginary parts; f = chi^2 / 4.
 
 Parity status: every function below is pinned by the not-gpu tests in
-tests/test_oracle_*.py (brute-force DFT, plane-wave derivatives, finite
-differences, the dense Wiener filter, closed forms of the homogeneous unmasked
-case, Philox known answers).  Iteration counts of the solver are not pinned
+tests/test_oracle_*.py: brute-force DFT, plane-wave derivatives, finite
+differences of chi^2 in s and in Theta, the dense Wiener filter (also for the
+preconditioned solve), closed forms of the homogeneous unmasked case, Philox known
+answers; the dense noise bias and Fisher matrix by derivatives of ln det C of an
+independently built pixel covariance (masked, off-diagonals included); the
+simulation b and F, every entry, within their own Monte Carlo error of the dense
+ones; the full estimate with simulation b and F unbiased over data realisations;
+the sampled-row Fisher matrix and the fiducial iteration by reduction to the full
+estimate and closed-form histories.  Iteration counts of the solver are not pinned
 (the paper prints none).
+This module is test infrastructure: only the tests, the smoke check and the
+benchmark's CPU-baseline leg use it; the library never does.
 """
 from __future__ import annotations
 
@@ -38,7 +46,7 @@ __all__ = [
     "signed_k", "live_mask", "free_mask", "partner_mask", "prior_S", "full_plane",
     "forward", "adjoint", "inner_half", "chi2", "grad_chi2", "whitened_grad", "whitened_hvp",
     "lbfgs_solve", "wiener_dense", "band_E", "dchi2_dtheta", "simulate", "sim_fisher",
-    "bandpower_qe", "dense_bias_fisher", "newton_update", "homogeneous_wiener",
+    "bandpower_qe", "dense_bias_fisher", "newton_update", "precond_diag",
     "homogeneous_band_moments", "band_groups", "fisher_from_columns", "sim_fisher_rows",
     "fiducial_iteration", "bandpower_iterate", "fisher_scale", "sim_signal", "posterior_error",
     "dense_posterior_variance", "band_power", "cosmic_variance", "bmode_leakage_qe",
@@ -205,19 +213,31 @@ def _dot(a, b) -> float:
     return float(np.vdot(a, b).real)
 
 
+def precond_diag(W, S) -> np.ndarray:
+    """Diagonal of the optional noise-aware initial inverse Hessian in the whitened
+    variable: P_k = 1 / (1 + S_k <W>), <W> the pixel mean of W (masked pixels count as 0).
+    It approximates the inverse of D = I + S^1/2 R^T W R S^1/2 when W is replaced by its
+    mean (R is an isometry), which makes very red spectra tractable; the paper itself
+    solves without a preconditioner (sec. 3)."""
+    return 1.0 / (1.0 + S * float(np.mean(W)))
+
+
 def lbfgs_solve(d, W, S, m: int = 10, tol: float = 1e-10, max_iter: int = 20000,
-                dchi2_tol: float = 0.0, x0=None):
+                dchi2_tol: float = 0.0, x0=None, precond: bool = False):
     """MAP field by L-BFGS (sec. 2.2): textbook two-loop recursion (Nocedal & Wright,
     Numerical Optimization, 2nd ed., algorithms 7.4/7.5) in the whitened variable,
     H0 = gamma I with gamma = s.y / y.y of the newest pair, and the exact line search of
     a quadratic, alpha = -g.p / p.D p (eq. eq_chib).  Starts from w = 0 unless given
     (the start does not matter for a convex problem).  Stops when
     |g| <= tol |g(0)|, or |delta chi^2| < dchi2_tol (sec. 3), or after max_iter.
+    precond: H0 = gamma diag(P) with P = precond_diag(W, S) and gamma = s.y / y.P y (same
+    stop test, same minimum).
 
     Returns dict(s, w, iters, rel_grad, chi2, status) with s on the free entries and
     its conjugate partners filled."""
     fr = _free_with_prior(S)
     sq = np.sqrt(S)
+    P = np.where(fr, precond_diag(W, S), 0.0) if precond else None
     w = np.zeros_like(S, dtype=np.complex128) if x0 is None else np.where(fr, x0, 0).astype(np.complex128)
     g = whitened_grad(np.zeros_like(w), d, W, S)
     g0 = math.sqrt(_dot(g, g))
@@ -243,7 +263,12 @@ def lbfgs_solve(d, W, S, m: int = 10, tol: float = 1e-10, max_iter: int = 20000,
             alph.append(a)
         if pairs:
             sv, yv, _ = pairs[-1]
-            q = (_dot(sv, yv) / _dot(yv, yv)) * q
+            if P is None:
+                q = (_dot(sv, yv) / _dot(yv, yv)) * q
+            else:
+                q = (_dot(sv, yv) / _dot(yv, P * yv)) * (P * q)
+        elif P is not None:
+            q = P * q
         for (sv, yv, rho), a in zip(pairs, reversed(alph)):
             b = rho * _dot(yv, q)
             q = q + sv * (a - b)
@@ -415,12 +440,15 @@ def _boosted_S(pshape, band, theta_fid, lb, factor):
     return prior_S(pshape, band, th)
 
 
-def sim_fisher(W, pshape, band, theta_fid, nbands, draws, m=10, tol=1e-8, max_iter=20000):
+def sim_fisher(W, pshape, band, theta_fid, nbands, draws, m=10, tol=1e-8, max_iter=20000, return_var=False):
     """Simulation noise bias and Fisher matrix (sec. 2.4):
     b_l = < E_l(Theta_fid, s_hat[d_sim]) > over sims drawn at Theta_fid (eq. blmv);
     F_ll' Delta_l' = < E_l(s_hat[d_sim at Theta_fid + Delta_l' e_l']) - E_l(s_hat[d_sim]) >
     (eq. fisher) with common random numbers, Delta_l' = Theta_fid,l' and every solve
-    using the fiducial prior; F is symmetrised.  Returns (b, F, E_sims[nsim][nbands])."""
+    using the fiducial prior; F is symmetrised.  Returns (b, F, E_sims[nsim][nbands]),
+    and with return_var also F_var: per entry the variance of the mean, i.e. the sample
+    variance over the simulations of each one's symmetrised estimate divided by nsim
+    (zero with a single simulation)."""
     theta_fid = np.asarray(theta_fid, np.float64)
     S_fid = prior_S(pshape, band, theta_fid)
     nsim = draws.shape[0]
@@ -437,7 +465,11 @@ def sim_fisher(W, pshape, band, theta_fid, nbands, draws, m=10, tol=1e-8, max_it
             Fs[i, :, l2] = (E2 - E0) / theta_fid[l2]
     b = Es.mean(0)
     F = Fs.mean(0)
-    return b, 0.5 * (F + F.T), Es
+    if not return_var:
+        return b, 0.5 * (F + F.T), Es
+    Fsym = 0.5 * (Fs + Fs.transpose(0, 2, 1))
+    Fvar = Fsym.var(0, ddof=1) / nsim if nsim > 1 else np.zeros((nbands, nbands))
+    return b, 0.5 * (F + F.T), Es, Fvar
 
 
 def newton_update(theta_fid, F, E, b):
@@ -705,15 +737,6 @@ def cosmic_variance(S, band, nbands) -> np.ndarray:
 
 
 # ----------------------------------------------------------------------------- closed forms
-
-def homogeneous_wiener(d, sigma2, S):
-    """Unmasked, homogeneous white noise: the filter is diagonal in Fourier space,
-    s_k = S_k / (S_k + sigma^2) (F d)_k (appendix A with R unitary, N = sigma^2 I).
-    Spin-0 only (the spin-2 case rotates first, still diagonal)."""
-    t = adjoint(d)
-    with np.errstate(invalid="ignore"):
-        return np.where(S > 0, S / (S + sigma2) * t, 0)
-
 
 def homogeneous_band_moments(pshape, band, theta_fid, theta_true, nbands, sigma2):
     """Unmasked homogeneous noise, full-plane sums per band (diagonal C in Fourier space):
