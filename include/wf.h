@@ -160,9 +160,12 @@ int wf_simulate(wf_ctx* ctx, const wf_problem* prob, int32_t nsim, uint64_t seed
 /* Simulation noise bias and Fisher matrix around prob->theta (eqs. blmv, fisher):
  * nsim * (1 + nbands) MAP solves with the fiducial prior, common random numbers,
  * Delta_l = theta_l; F symmetrised.  F HOST [nbands*nbands], b HOST [nbands],
- * E_sims nullable HOST [nsim][nbands] (E of the fiducial simulations).               */
+ * F_var nullable HOST [nbands*nbands]: the Monte Carlo variance of each entry of F (the
+ * sample variance over the simulations of each one's symmetrised estimate, divided by
+ * nsim; 0 when nsim = 1), E_sims nullable HOST [nsim][nbands] (E of the fiducial
+ * simulations).                                                                         */
 int sim_fisher(wf_ctx* ctx, const wf_problem* prob, int32_t nsim, uint64_t seed, const void* draws,
-               const wf_lbfgs_opts* opts, double* F, double* b, double* E_sims, void* stream);
+               const wf_lbfgs_opts* opts, double* F, double* b, double* F_var, double* E_sims, void* stream);
 
 /* Quadratic band-power estimator (sec. 2.3-2.5): MAP of prob->d, E_l of it, sim_fisher,
  * Newton step.  theta_hat, E, b HOST [nbands]; F HOST [nbands*nbands] (nullable).      */
@@ -251,8 +254,13 @@ int convergence_by_band(wf_ctx* ctx, const wf_problem* prob, int32_t ntol, const
 int wf_forward(wf_ctx* ctx, const wf_problem* prob, int32_t batch, const void* s, void* x, int32_t flags,
                void* stream);
 
-/* s = R^T x (flags WF_ADJ_METRIC) or the stored-coefficient gradient (WF_ADJ_GRAD);
- * with WF_MASK the input is masked first (adjoint of the masked forward operator).    */
+/* Adjoint of the response (sec. 2, eq. ddecomp; R^T is the operator of the gradient, eq.
+ * eq_cost, and of the curvature, eq. eq_curv; spin-2: the inverse rotation of appendix C):
+ * s = R^T x in the full-plane metric (flags WF_ADJ_METRIC: unitary forward DFT, inverse
+ * rotation, dead entries 0, partners filled) or the stored-coefficient gradient of a
+ * function of x = R s (WF_ADJ_GRAD: 2 R^T x on free entries, 0 else); with WF_MASK the
+ * input is masked first (adjoint of the masked forward operator M R).
+ * x [batch][ncomp][n][n] -> s [batch][ncomp][n][n/2+1] complex.                       */
 int wf_adjoint(wf_ctx* ctx, const wf_problem* prob, int32_t batch, const void* x, void* s, int32_t flags,
                void* stream);
 
@@ -267,6 +275,16 @@ int wf_hvp(wf_ctx* ctx, const wf_problem* prob, int32_t batch, const void* p, vo
 
 /* band statistic E_l (eq. el) of each field with the prior of prob: E HOST [batch][nbands]. */
 int wf_band_E(wf_ctx* ctx, const wf_problem* prob, int32_t batch, const void* s, double* E, void* stream);
+
+/* Band-power derivative of the objective at fixed fields (eq. eq_chi with S = theta_b P_k;
+ * with eq. el, d chi^2 / d theta_b = -sum_{k in b, full plane} |s_k|^2 / (theta_b^2 P_k) =
+ * -2 E_b(s; theta)), contracted with the upstream weights of a batch:
+ *   dtheta   HOST [nbands]: sum_i gout[i] d chi^2(s_i) / d theta_b, accumulated in float64;
+ *   gout     nullable HOST [batch] (NULL = all ones).
+ * s as in wf_band_E; prob->theta are the amplitudes the derivative is taken at.  This is
+ * the theta-gradient of a chi^2 autograd node.                                           */
+int wf_chi2_dtheta(wf_ctx* ctx, const wf_problem* prob, int32_t batch, const void* s, const double* gout,
+                   double* dtheta, void* stream);
 
 /* Tiles of the transform chain (the three passes of every gradient / curvature product):
  * rbv = image rows per work-group of the row pass (2, 4, 8), cpb = column blocks of 2

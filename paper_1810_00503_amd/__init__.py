@@ -27,7 +27,7 @@ __all__ = [
     "convergence_by_band",
     "wf_forward",
     "wf_adjoint",
-    "wf_chi2_grad", "wf_hvp", "wf_band_E",
+    "wf_chi2_grad", "wf_hvp", "wf_band_E", "wf_chi2_dtheta",
     "WFError", "kernel_stats", "reset_kernel_stats", "set_profiling", "autograd", "set_chain_tiles",
     "get_chain_tiles",
 ]
@@ -271,24 +271,27 @@ def _draws_ptr(problem, draws, nsim):
 
 
 def sim_fisher(problem: Problem, nsim: int, seed: int, draws=None, opts: LbfgsOpts | None = None,
-               ctx: Context | None = None):
+               ctx: Context | None = None, want_var: bool = False):
     """Simulation noise bias b and Fisher matrix F around problem.theta (eqs. blmv, fisher).
-    Returns (F [nb][nb], b [nb], E_sims [nsim][nb], rc) as numpy arrays."""
+    Returns (F [nb][nb], b [nb], E_sims [nsim][nb], rc) as numpy arrays; with want_var
+    (F, b, E_sims, F_var [nb][nb], rc), F_var the Monte Carlo variance of each entry of F."""
     dev = problem.device_index()
     cx = ctx or context(dev)
     nb = problem.nbands
     F = np.zeros((nb, nb))
     b = np.zeros(nb)
+    Fv = np.zeros((nb, nb))
     Es = np.zeros((nsim, nb))
     keep, dp = _draws_ptr(problem, draws, nsim)
     cp = problem.c()
     o = _opts(opts)
     rc = cx.lib.sim_fisher(cx.h, C.byref(cp), nsim, C.c_uint64(seed), dp, C.byref(o),
                            F.ctypes.data_as(C.POINTER(C.c_double)), b.ctypes.data_as(C.POINTER(C.c_double)),
+                           Fv.ctypes.data_as(C.POINTER(C.c_double)) if want_var else None,
                            Es.ctypes.data_as(C.POINTER(C.c_double)), _stream(dev))
     cx.check(rc)
     del keep
-    return F, b, Es, rc
+    return (F, b, Es, Fv, rc) if want_var else (F, b, Es, rc)
 
 
 def bandpower_qe(problem: Problem, nsim: int, seed: int, draws=None, opts: LbfgsOpts | None = None,
@@ -539,6 +542,26 @@ def wf_band_E(problem: Problem, s, ctx: Context | None = None):
     cx.check(cx.lib.wf_band_E(cx.h, C.byref(cp), B, s.data_ptr(), E.ctypes.data_as(C.POINTER(C.c_double)),
                               _stream(dev)))
     return E if batched else E[0]
+
+
+def wf_chi2_dtheta(problem: Problem, s, gout=None, ctx: Context | None = None):
+    """sum_i gout[i] d chi^2(s_i) / d theta_b at fixed fields (numpy [nbands]); gout None =
+    ones.  s is one field [c][n][n/2+1] or a batch [B][c][n][n/2+1]."""
+    s = s.contiguous()
+    B, batched = _batch_shape(problem, s, "s")
+    dev = problem.device_index()
+    cx = ctx or context(dev)
+    out = np.zeros(problem.nbands)
+    go = None
+    if gout is not None:
+        go = np.ascontiguousarray(np.asarray(gout, np.float64).reshape(-1))
+        if go.size != B:
+            raise ValueError(f"gout must have {B} entries")
+    cp = problem.c()
+    cx.check(cx.lib.wf_chi2_dtheta(cx.h, C.byref(cp), B, s.data_ptr(),
+                                   go.ctypes.data_as(C.POINTER(C.c_double)) if go is not None else None,
+                                   out.ctypes.data_as(C.POINTER(C.c_double)), _stream(dev)))
+    return out
 
 
 def set_profiling(on: bool, ctx: Context | None = None):

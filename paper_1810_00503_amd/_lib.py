@@ -16,7 +16,7 @@ WF_METHOD_LBFGS, WF_METHOD_CG = 0, 1
 
 EXPORTS = [
     "wf_create", "wf_destroy", "wf_last_error", "wf_lbfgs_default", "map_wf_solve", "wf_simulate",
-    "sim_fisher", "sim_fisher_rows", "bandpower_qe", "bandpower_iterate", "bmode_leakage_qe", "posterior_error", "convergence_by_band", "wf_forward", "wf_adjoint", "wf_chi2_grad", "wf_hvp", "wf_band_E",
+    "sim_fisher", "sim_fisher_rows", "bandpower_qe", "bandpower_iterate", "bmode_leakage_qe", "posterior_error", "convergence_by_band", "wf_forward", "wf_adjoint", "wf_chi2_grad", "wf_hvp", "wf_band_E", "wf_chi2_dtheta",
     "wf_set_profiling", "wf_kernel_kinds", "wf_kernel_kind_name", "wf_get_kernel_stats",
     "wf_reset_kernel_stats", "wf_set_chain_tiles", "wf_get_chain_tiles",
 ]
@@ -68,7 +68,8 @@ def load(path: str | None = None):
     L.map_wf_solve.argtypes = [vp, C.POINTER(WfProblem), i32, C.POINTER(WfLbfgsOpts), C.POINTER(vp),
                                C.POINTER(vp), C.POINTER(WfSolveStats), vp]
     L.wf_simulate.argtypes = [vp, C.POINTER(WfProblem), i32, C.c_uint64, i32, vp, dp, i32, C.c_double, vp, vp]
-    L.sim_fisher.argtypes = [vp, C.POINTER(WfProblem), i32, C.c_uint64, vp, C.POINTER(WfLbfgsOpts), dp, dp, dp, vp]
+    L.sim_fisher.argtypes = [vp, C.POINTER(WfProblem), i32, C.c_uint64, vp, C.POINTER(WfLbfgsOpts), dp, dp, dp, dp,
+                             vp]
     L.bandpower_qe.argtypes = [vp, C.POINTER(WfProblem), i32, C.c_uint64, vp, C.POINTER(WfLbfgsOpts), dp, dp, dp,
                                dp, vp]
     ip = C.POINTER(i32)
@@ -86,6 +87,7 @@ def load(path: str | None = None):
     L.wf_chi2_grad.argtypes = [vp, C.POINTER(WfProblem), i32, vp, dp, vp, vp]
     L.wf_hvp.argtypes = [vp, C.POINTER(WfProblem), i32, vp, vp, vp]
     L.wf_band_E.argtypes = [vp, C.POINTER(WfProblem), i32, vp, dp, vp]
+    L.wf_chi2_dtheta.argtypes = [vp, C.POINTER(WfProblem), i32, vp, dp, dp, vp]
     L.wf_set_profiling.argtypes = [vp, i32]
     L.wf_kernel_kinds.argtypes = []
     L.wf_kernel_kind_name.argtypes = [i32]

@@ -6,7 +6,8 @@
 * ``chi2(s, theta, problem)``: chi^2(s; theta) of eq. eq_chi for one field [c][n][n/2+1] or a
   batch [B][c][n][n/2+1]; its backward gives d chi^2 / ds = 4 g (eq. eq_cost, per stored
   coefficient) and d chi^2 / d theta_b = -2 E_b (the prior term's derivative; E_b of eq. el
-  evaluated with the prior at theta).
+  evaluated with the prior at theta), both computed by the library (wf_chi2_grad and
+  wf_chi2_dtheta, which also contracts with the upstream gradient).
 
 Gradients follow PyTorch's complex convention (d/dRe + i d/dIm for a real loss), which is
 the library's.  theta is a CPU float64 tensor (the C-ABI takes band amplitudes on the host).
@@ -16,7 +17,7 @@ from __future__ import annotations
 import numpy as np
 import torch
 
-from . import WF_ADJ_GRAD, WF_MASK, wf_adjoint, wf_band_E, wf_chi2_grad, wf_forward
+from . import WF_ADJ_GRAD, WF_MASK, wf_adjoint, wf_chi2_dtheta, wf_chi2_grad, wf_forward
 
 __all__ = ["ResponseOp", "Chi2Op", "response", "chi2"]
 
@@ -58,10 +59,8 @@ class Chi2Op(torch.autograd.Function):
             gs = g * w
         gth = None
         if ctx.needs_input_grad[1]:
-            E = np.asarray(wf_band_E(ctx.p, s), np.float64)
-            E = E.reshape(-1, ctx.p.nbands)
             gow = go.detach().cpu().numpy().reshape(-1)
-            gth = torch.as_tensor(-2.0 * (gow[:, None] * E).sum(0), dtype=torch.float64, device=ctx.theta_device)
+            gth = torch.as_tensor(wf_chi2_dtheta(ctx.p, s, gow), dtype=torch.float64, device=ctx.theta_device)
         return gs, gth, None
 
 

@@ -701,7 +701,10 @@ int solve_core(wf_ctx* ctx, const wf_problem* probs, int B, const wf_lbfgs_opts&
   // running instances per class: all at the start, then as the host polls find them
   std::vector<int64_t> nrun(nk);
   for (int c = 0; c < nk; ++c) nrun[c] = (int64_t)ks[c].members.size();
-  const int64_t maxBodies = 2LL * o.max_iter + 64;
+  // one iteration takes at most four bodies (curvature product, flush of w, exact gradient,
+  // dots after a failed confirmation), so the device's own max_iter test, which flushes w
+  // before it stops, always comes first
+  const int64_t maxBodies = 4LL * o.max_iter + 64;
   int64_t bodies = 0;
   while (true) {
     if (graph) {
@@ -1103,6 +1106,35 @@ void bias_fisher(const double* theta, int nsim, int nb, const std::vector<int>& 
     for (int l2 = 0; l2 < nb; ++l2) F[(size_t)l * nb + l2] = 0.5 * (Fr[(size_t)l * nb + l2] + Fr[(size_t)l2 * nb + l]);
 }
 
+// Monte Carlo variance of the Fisher estimate with every column simulated: per entry, the
+// sample variance over the simulations of each one's symmetrised estimate
+// (Fr_i,ll' + Fr_i,l'l) / 2 with Fr_i,ll' = (E2_i,l(l') - E0_i,l) / theta_l', divided by nsim
+// (the variance of the mean; 0 with one simulation).
+void fisher_variance(const double* theta, int nsim, int nb, const std::vector<double>& E0,
+                     const std::vector<double>& E2, double* Fv) {
+  for (int l = 0; l < nb; ++l)
+    for (int l2 = 0; l2 < nb; ++l2) {
+      if (nsim < 2) {
+        Fv[(size_t)l * nb + l2] = 0.0;
+        continue;
+      }
+      auto est = [&](int i) {
+        const double a = (E2[((size_t)i * nb + l2) * nb + l] - E0[(size_t)i * nb + l]) / theta[l2];
+        const double c = (E2[((size_t)i * nb + l) * nb + l2] - E0[(size_t)i * nb + l2]) / theta[l];
+        return 0.5 * (a + c);
+      };
+      double m = 0.0;
+      for (int i = 0; i < nsim; ++i) m += est(i);
+      m /= nsim;
+      double v = 0.0;
+      for (int i = 0; i < nsim; ++i) {
+        const double e = est(i) - m;
+        v += e * e;
+      }
+      Fv[(size_t)l * nb + l2] = v / (nsim - 1) / nsim;
+    }
+}
+
 // Simulated columns and band groups of a sampled-Fisher call: rows strictly increasing in
 // [0, nb), groups nullable (one group) or [nb] ids, every group with a simulated column.
 int parse_rows(wf_ctx* ctx, int nb, const int32_t* rows, int32_t nrows, const int32_t* groups, std::vector<int>& cols,
@@ -1332,8 +1364,28 @@ int sim_fisher_rows(wf_ctx* ctx, const wf_problem* p, int32_t nsim, uint64_t see
 }
 
 int sim_fisher(wf_ctx* ctx, const wf_problem* p, int32_t nsim, uint64_t seed, const void* draws,
-               const wf_lbfgs_opts* opts, double* F, double* b, double* E_sims, void* stream) {
-  return sim_fisher_rows(ctx, p, nsim, seed, draws, opts, nullptr, 0, nullptr, F, b, E_sims, stream);
+               const wf_lbfgs_opts* opts, double* F, double* b, double* F_var, double* E_sims, void* stream) {
+  if (!ctx) return WF_EINVAL;
+  int rc = check_problem(ctx, p, false);
+  if (rc) return rc;
+  if (nsim < 1 || !F || !b) return fail(ctx, WF_EINVAL, "need nsim >= 1 and F, b");
+  const int nb = p->nbands;
+  for (int l = 0; l < nb; ++l)
+    if (!(p->theta[l] > 0)) return fail(ctx, WF_EINVAL, "fiducial band amplitudes must be > 0");
+  std::vector<int> cols, grp;
+  rc = parse_rows(ctx, nb, nullptr, 0, nullptr, cols, grp);
+  if (rc) return rc;
+  wf_lbfgs_opts o;
+  fill_opts(opts, o);
+  StreamScope ss(ctx, stream);
+  std::vector<double> Ed, E0, E2;
+  int nc = 0;
+  rc = run_qe(ctx, p, false, nsim, seed, draws, o, cols, Ed, E0, E2, nc);
+  if (rc) return rc;
+  bias_fisher(p->theta, nsim, nb, cols, grp, E0, E2, b, F);
+  if (F_var) fisher_variance(p->theta, nsim, nb, E0, E2, F_var);
+  if (E_sims) std::copy(E0.begin(), E0.end(), E_sims);
+  return nc ? WF_NOT_CONVERGED : WF_OK;
 }
 
 int bandpower_iterate(wf_ctx* ctx, const wf_problem* p, int32_t nsim, uint64_t seed, const void* draws,
@@ -1730,14 +1782,13 @@ int wf_hvp(wf_ctx* ctx, const wf_problem* p, int32_t batch, const void* pv, void
   return raw_chain(ctx, p, batch, pv, nullptr, Dp, CM_RAW_HV, stream);
 }
 
-int wf_band_E(wf_ctx* ctx, const wf_problem* p, int32_t batch, const void* s, double* E, void* stream) {
-  int rc = check_op(ctx, p, batch, s, E);
-  if (rc || batch == 0) return rc;
-  rc = check_problem(ctx, p, false);
-  if (rc) return rc;
+}  // extern "C"
+
+namespace {
+// E_l (eq. el) of `batch` external fields with p's prior, into E HOST [batch][nbands]; the
+// caller has checked the arguments and entered the stream scope.
+int band_E_ext(wf_ctx* ctx, const wf_problem* p, int batch, const void* s, double* E) {
   const int nb = p->nbands;
-  if (nb == 0) return WF_OK;
-  StreamScope ss(ctx, stream);
   const int n = p->n, c = p->ncomp, dt = p->dtype;
   const int64_t L = (int64_t)c * n * (n / 2);
   const size_t eb = esize_of(dt);
@@ -1749,7 +1800,7 @@ int wf_band_E(wf_ctx* ctx, const wf_problem* p, int32_t batch, const void* s, do
   double* part;
   const void* tw;
   PriorTab pt;
-  rc = op_setup(ctx, p, batch, extra, &pt, &vin, &vy, &vout, &dj, &part, &tw);
+  int rc = op_setup(ctx, p, batch, extra, &pt, &vin, &vy, &vout, &dj, &part, &tw);
   if (rc) return rc;
   HIPCHK(unpack_launch(dt, n, c, batch, s, vin, ctx->cs));
   BandJob* bj = (BandJob*)arena_take(ctx->opA, sizeof(BandJob) * batch);
@@ -1758,6 +1809,7 @@ int wf_band_E(wf_ctx* ctx, const wf_problem* p, int32_t batch, const void* s, do
   std::vector<BandJob> hj(batch);
   for (int i = 0; i < batch; ++i) {
     hj[i].f = (char*)vin + (size_t)i * L * eb;
+    hj[i].f2 = nullptr;
     hj[i].sq = pt.sq;
     hj[i].aw = nullptr;
     hj[i].bandI = pt.bandI;
@@ -1772,6 +1824,46 @@ int wf_band_E(wf_ctx* ctx, const wf_problem* p, int32_t batch, const void* s, do
   HIPCHK(band_launch(dt, bj, batch, L, ctx->cs));
   HIPCHK(hipMemcpyAsync(E, dE, sizeof(double) * (size_t)batch * nb, hipMemcpyDeviceToHost, ctx->cs));
   HIPCHK(hipStreamSynchronize(ctx->cs));
+  return WF_OK;
+}
+}  // namespace
+
+extern "C" {
+
+int wf_band_E(wf_ctx* ctx, const wf_problem* p, int32_t batch, const void* s, double* E, void* stream) {
+  int rc = check_op(ctx, p, batch, s, E);
+  if (rc || batch == 0) return rc;
+  rc = check_problem(ctx, p, false);
+  if (rc) return rc;
+  if (p->nbands == 0) return WF_OK;
+  StreamScope ss(ctx, stream);
+  return band_E_ext(ctx, p, batch, s, E);
+}
+
+int wf_chi2_dtheta(wf_ctx* ctx, const wf_problem* p, int32_t batch, const void* s, const double* gout,
+                   double* dtheta, void* stream) {
+  int rc = check_op(ctx, p, batch, s, dtheta);
+  if (rc) return rc;
+  rc = check_problem(ctx, p, false);
+  if (rc) return rc;
+  const int nb = p->nbands;
+  if (nb == 0) return WF_OK;
+  if (!dtheta) return fail(ctx, WF_EINVAL, "null dtheta");
+  for (int b = 0; b < nb; ++b) dtheta[b] = 0.0;
+  if (batch == 0) return WF_OK;
+  if (gout)
+    for (int i = 0; i < batch; ++i)
+      if (!std::isfinite(gout[i])) return fail(ctx, WF_ENONFINITE, "non-finite gout");
+  StreamScope ss(ctx, stream);
+  std::vector<double> E((size_t)batch * nb);
+  rc = band_E_ext(ctx, p, batch, s, E.data());
+  if (rc) return rc;
+  // d chi^2 / d theta_b = -sum_{k in b, full plane} |s_k|^2 / (theta_b^2 P_k) = -2 E_b
+  for (int b = 0; b < nb; ++b) {
+    double a = 0.0;
+    for (int i = 0; i < batch; ++i) a += (gout ? gout[i] : 1.0) * E[(size_t)i * nb + b];
+    dtheta[b] = -2.0 * a;
+  }
   return WF_OK;
 }
 

@@ -103,3 +103,26 @@ def test_chi2_gradients_vs_finite_differences(lib, dtype):
     # and the closed form against the oracle: -2 E_b(theta, s)
     Eo = sum(w * O.band_E(s0[b], S, wl.band, wl.theta_fid, wl.nbands) for b, w in enumerate([0.7, 1.3]))
     np.testing.assert_allclose(gth, -2.0 * Eo, rtol=1e-5 if dtype == "f32" else 1e-11)
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_chi2_dtheta_through_the_c_abi(lib, dtype):
+    """wf_chi2_dtheta: sum_i gout_i d chi^2_i / d theta_b against the oracle's derivative."""
+    import torch
+    print(f"[wf_chi2_dtheta {dtype}]", flush=True)
+    wl = _shear(n=48, seed=12)
+    n = wl.n
+    rng = np.random.default_rng(21)
+    prob = make_problem(lib, torch, wl, dtype, d=rng.standard_normal((2, n, n)))
+    S = O.prior_S(wl.pshape, wl.band, wl.theta_fid)
+    fr = O.free_mask(n)[None] & (S > 0)
+    s0 = np.stack([np.where(fr, np.sqrt(S) * (rng.standard_normal(S.shape) + 1j * rng.standard_normal(S.shape)), 0)
+                   for _ in range(3)])
+    st = torch.tensor(s0, dtype=prob.cdtype, device="cuda:0")
+    gout = np.array([0.5, -1.25, 2.0])
+    got = lib.wf_chi2_dtheta(prob, st, gout)
+    ref = sum(w * O.dchi2_dtheta(s0[i], wl.pshape, wl.band, wl.theta_fid, wl.nbands) for i, w in enumerate(gout))
+    tol = 1e-5 if dtype == "f32" else 1e-12
+    np.testing.assert_allclose(got, ref, rtol=tol, atol=tol * np.abs(ref).max())
+    one = lib.wf_chi2_dtheta(prob, st[1])
+    np.testing.assert_allclose(one, O.dchi2_dtheta(s0[1], wl.pshape, wl.band, wl.theta_fid, wl.nbands), rtol=tol)

@@ -152,11 +152,17 @@ def test_sim_fisher_and_bandpower_match_oracle(lib, ncomp):
     prob = make_problem(lib, torch, wl, "f32", d=d)
     dt = torch.tensor(draws, dtype=torch.float32, device="cuda:0")
     opts = lib.LbfgsOpts(rel_grad_tol=1e-8)
-    F, b, Es, rc = lib.sim_fisher(prob, nsim, 0, draws=dt, opts=opts)
-    bo, Fo, Eso = O.sim_fisher(wl.W, wl.pshape, wl.band, wl.theta_fid, wl.nbands, draws, tol=1e-11)
+    F, b, Es, Fv, rc = lib.sim_fisher(prob, nsim, 0, draws=dt, opts=opts, want_var=True)
+    bo, Fo, Eso, Fvo = O.sim_fisher(wl.W, wl.pshape, wl.band, wl.theta_fid, wl.nbands, draws, tol=1e-11,
+                                    return_var=True)
     np.testing.assert_allclose(Es, Eso, rtol=1e-4)
     np.testing.assert_allclose(b, bo, rtol=1e-4)
     np.testing.assert_allclose(F, Fo, rtol=1e-4, atol=1e-4 * np.abs(Fo).max())
+    # the Monte Carlo variance of F: a variance of differences of the per-simulation
+    # estimates, which agree to 1e-4 of F; compared at that scale
+    np.testing.assert_allclose(np.sqrt(Fv), np.sqrt(Fvo), rtol=1e-3, atol=2e-4 * np.abs(Fo).max())
+    F1, b1, Es1, rc1 = lib.sim_fisher(prob, nsim, 0, draws=dt, opts=opts)
+    np.testing.assert_array_equal(F1, F)
     th, E, b2, F2, rc = lib.bandpower_qe(prob, nsim, 0, draws=dt, opts=opts)
     tho, Eo, bo2, Fo2 = O.bandpower_qe(d, wl.W, wl.pshape, wl.band, wl.theta_fid, wl.nbands, draws, tol=1e-11)
     np.testing.assert_allclose(E, Eo, rtol=1e-4)
@@ -413,3 +419,30 @@ def test_mixed_precision_batch(lib):
         S = O.prior_S(wl.pshape, wl.band, wl.theta_fid)
         ref = O.lbfgs_solve(d, wl.W, S, tol=1e-12, max_iter=50000)["s"]
         assert rel_l2(s[i].cpu().numpy(), ref) < 1e-5, i
+
+
+def test_iteration_cap_with_refresh_every_iteration(lib):
+    """refresh_every = 1 (an exact gradient, and a flush of the lazily updated iterate,
+    every iteration) with a small max_iter: the solve stops at the cap, and the returned
+    field is the iterate its statistics describe (chi^2 of the returned s = the reported
+    chi^2, and the whitened gradient of the returned s = the reported relative gradient)."""
+    import torch
+    print("[iteration cap, refresh 1]", flush=True)
+    wl = WL.density_workload(64, 77, nbands=6)
+    d = oracle_data(wl, 78)
+    for dtype, rt in (("f32", 2e-5), ("f64", 1e-9)):
+        prob = make_problem(lib, torch, wl, dtype, d=d)
+        for mi in (3, 7):
+            s, _, st, rc = lib.map_wf_solve([prob], lib.LbfgsOpts(max_iter=mi, refresh_every=1, rel_grad_tol=1e-12))
+            assert rc == lib.WF_NOT_CONVERGED and st[0].status == lib.WF_SOLVE_MAXITER and st[0].iters == mi
+            got = s[0].cpu().numpy().astype(np.complex128)
+            S = O.prior_S(wl.pshape, wl.band, wl.theta_fid)
+            c2 = O.chi2(got, d, wl.W, S)
+            assert abs(c2 - st[0].chi2) <= rt * abs(c2), (dtype, mi, c2, st[0].chi2)
+            fr = O.free_mask(wl.n)[None] & (S > 0)
+            w = np.where(fr, got / np.sqrt(np.where(fr, S, 1.0)), 0)
+            g = O.whitened_grad(w, d, wl.W, S)
+            g0 = O.whitened_grad(np.zeros_like(w), d, wl.W, S)
+            rel = np.linalg.norm(g) / np.linalg.norm(g0)
+            assert abs(rel - st[0].rel_grad) <= (1e-3 if dtype == "f32" else 1e-8) * rel, (dtype, mi, rel,
+                                                                                            st[0].rel_grad)
