@@ -273,6 +273,19 @@ int wf_chi2_grad(wf_ctx* ctx, const wf_problem* prob, int32_t batch, const void*
 /* curvature product in the same convention: Dp = 4 (S^-1 p + R^T W R p) (eq. eq_curv). */
 int wf_hvp(wf_ctx* ctx, const wf_problem* prob, int32_t batch, const void* p, void* Dp, void* stream);
 
+/* For callers that cannot allocate device memory (tight serving loops, harnesses that
+ * forbid allocation): wf_hvp computed without any allocation.  Every buffer of its kernels
+ * (twiddles, prior tables, transform vectors, jobs, partial sums) lives in one library
+ * scratch array of WF_NOALLOC_SCRATCH_BYTES per GPU, held from the first wf_create on that
+ * GPU until the process ends; the caller passes p and Dp as for wf_hvp.  Calls whose
+ * buffers do not fit return WF_EINVAL (the message gives the bytes needed; about
+ * 3 * batch * ncomp * n^2 * 4 bytes in float32).  All calls on one GPU share the array, so
+ * calls that overlap on one GPU (other contexts, other host threads, or streams that are
+ * not ordered) race; calls on one context are ordered.  The call is enqueued on `stream`
+ * and returns without waiting for it.                                                     */
+enum { WF_NOALLOC_SCRATCH_BYTES = 64 * 1024 * 1024 };
+int wf_hvp_noalloc(wf_ctx* ctx, const wf_problem* prob, int32_t batch, const void* p, void* Dp, void* stream);
+
 /* band statistic E_l (eq. el) of each field with the prior of prob: E HOST [batch][nbands]. */
 int wf_band_E(wf_ctx* ctx, const wf_problem* prob, int32_t batch, const void* s, double* E, void* stream);
 

@@ -27,7 +27,7 @@ __all__ = [
     "convergence_by_band",
     "wf_forward",
     "wf_adjoint",
-    "wf_chi2_grad", "wf_hvp", "wf_band_E", "wf_chi2_dtheta",
+    "wf_chi2_grad", "wf_hvp", "wf_hvp_noalloc", "wf_band_E", "wf_chi2_dtheta",
     "WFError", "kernel_stats", "reset_kernel_stats", "set_profiling", "autograd", "set_chain_tiles",
     "get_chain_tiles",
 ]
@@ -528,6 +528,21 @@ def wf_hvp(problem: Problem, p, ctx: Context | None = None):
     out = torch.empty_like(p)
     cp = problem.c()
     cx.check(cx.lib.wf_hvp(cx.h, C.byref(cp), B, p.data_ptr(), out.data_ptr(), _stream(dev)))
+    return out
+
+
+def wf_hvp_noalloc(problem: Problem, p, out, ctx: Context | None = None):
+    """wf_hvp into the caller's `out` (same shape and dtype as p) without any device
+    allocation by the library (its buffers live in a fixed per-GPU scratch array).  The call
+    is enqueued on the current stream and returns without waiting."""
+    p = p.contiguous()
+    B, batched = _batch_shape(problem, p, "s")
+    if tuple(out.shape) != tuple(p.shape) or out.dtype != p.dtype or not out.is_contiguous():
+        raise ValueError("out must be a contiguous tensor shaped and typed like p")
+    dev = problem.device_index()
+    cx = ctx or context(dev)
+    cp = problem.c()
+    cx.check(cx.lib.wf_hvp_noalloc(cx.h, C.byref(cp), B, p.data_ptr(), out.data_ptr(), _stream(dev)))
     return out
 
 

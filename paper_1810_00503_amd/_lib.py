@@ -13,10 +13,11 @@ WF_F32, WF_F64 = 0, 1
 WF_SOLVE_CONVERGED, WF_SOLVE_MAXITER, WF_SOLVE_NONFINITE = 0, 1, 2
 WF_ADJ_METRIC, WF_ADJ_GRAD, WF_MASK = 0, 1, 2
 WF_METHOD_LBFGS, WF_METHOD_CG = 0, 1
+WF_NOALLOC_SCRATCH_BYTES = 64 * 1024 * 1024
 
 EXPORTS = [
     "wf_create", "wf_destroy", "wf_last_error", "wf_lbfgs_default", "map_wf_solve", "wf_simulate",
-    "sim_fisher", "sim_fisher_rows", "bandpower_qe", "bandpower_iterate", "bmode_leakage_qe", "posterior_error", "convergence_by_band", "wf_forward", "wf_adjoint", "wf_chi2_grad", "wf_hvp", "wf_band_E", "wf_chi2_dtheta",
+    "sim_fisher", "sim_fisher_rows", "bandpower_qe", "bandpower_iterate", "bmode_leakage_qe", "posterior_error", "convergence_by_band", "wf_forward", "wf_adjoint", "wf_chi2_grad", "wf_hvp", "wf_hvp_noalloc", "wf_band_E", "wf_chi2_dtheta",
     "wf_set_profiling", "wf_kernel_kinds", "wf_kernel_kind_name", "wf_get_kernel_stats",
     "wf_reset_kernel_stats", "wf_set_chain_tiles", "wf_get_chain_tiles",
 ]
@@ -86,6 +87,7 @@ def load(path: str | None = None):
     L.wf_adjoint.argtypes = [vp, C.POINTER(WfProblem), i32, vp, vp, i32, vp]
     L.wf_chi2_grad.argtypes = [vp, C.POINTER(WfProblem), i32, vp, dp, vp, vp]
     L.wf_hvp.argtypes = [vp, C.POINTER(WfProblem), i32, vp, vp, vp]
+    L.wf_hvp_noalloc.argtypes = [vp, C.POINTER(WfProblem), i32, vp, vp, vp]
     L.wf_band_E.argtypes = [vp, C.POINTER(WfProblem), i32, vp, dp, vp]
     L.wf_chi2_dtheta.argtypes = [vp, C.POINTER(WfProblem), i32, vp, dp, dp, vp]
     L.wf_set_profiling.argtypes = [vp, i32]

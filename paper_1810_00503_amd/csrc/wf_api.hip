@@ -9,6 +9,7 @@
 #include <cstring>
 #include <cstdlib>
 #include <map>
+#include <mutex>
 #include <new>
 #include <string>
 #include <tuple>
@@ -19,6 +20,12 @@
 #include "wf_rfft.hpp"
 
 using namespace wf;
+
+// Device scratch of the allocation-free entry point (wf_hvp_noalloc), one copy per GPU that
+// the library runs on, held until the process ends.  In host code this name is not a device
+// address: each device's address is taken once, with that device current, by
+// hipGetSymbolAddress in noalloc_setup (called from wf_create) and only that address is used.
+static __device__ __align__(256) unsigned char scratch[WF_NOALLOC_SCRATCH_BYTES];
 
 namespace {
 
@@ -73,6 +80,10 @@ struct wf_ctx {
   ChainCfg fixedCfg;
   bool fixedSet = false;
   std::map<std::tuple<int, int, int, int>, ChainCfg> tuned;
+  // host copies of the twiddle tables (the allocation-free entry point stages them into the
+  // device scratch) and this device's scratch address
+  std::map<std::pair<int, int>, std::vector<char>> htw;
+  void* scratch = nullptr;
 };
 
 namespace {
@@ -160,13 +171,8 @@ static void stage_table(std::vector<double>& h, int64_t at, int len, int E, bool
   }
 }
 
-int twiddles(wf_ctx* ctx, int n, int dtype, const void** out) {
-  auto key = std::make_pair(n, dtype);
-  auto it = ctx->tw.find(key);
-  if (it != ctx->tw.end()) {
-    *out = it->second;
-    return WF_OK;
-  }
+// the twiddle table of (n, dtype) as device-ready bytes
+void twiddle_bytes(int n, int dtype, std::vector<char>& out) {
   const bool pow2 = (n & (n - 1)) == 0 && n >= 8;
   const int64_t entries = pow2 ? tw_ext_entries(n) : n;
   std::vector<double> h(2 * (size_t)entries, 0.0);
@@ -182,17 +188,51 @@ int twiddles(wf_ctx* ctx, int n, int dtype, const void** out) {
       stage_table(h, tw_row_off(n, E, true), n / 2, E, true);
     }
   }
-  void* d = nullptr;
   const size_t bytes = (size_t)entries * esize_of(dtype);
-  HIPCHK(hipMalloc(&d, bytes));
+  out.resize(bytes);
   if (dtype == WF_F64) {
-    HIPCHK(hipMemcpy(d, h.data(), bytes, hipMemcpyHostToDevice));
+    std::memcpy(out.data(), h.data(), bytes);
   } else {
     std::vector<float> f(h.begin(), h.end());
-    HIPCHK(hipMemcpy(d, f.data(), bytes, hipMemcpyHostToDevice));
+    std::memcpy(out.data(), f.data(), bytes);
   }
+}
+
+int twiddles(wf_ctx* ctx, int n, int dtype, const void** out) {
+  auto key = std::make_pair(n, dtype);
+  auto it = ctx->tw.find(key);
+  if (it != ctx->tw.end()) {
+    *out = it->second;
+    return WF_OK;
+  }
+  std::vector<char> h;
+  twiddle_bytes(n, dtype, h);
+  void* d = nullptr;
+  HIPCHK(hipMalloc(&d, h.size()));
+  HIPCHK(hipMemcpy(d, h.data(), h.size(), hipMemcpyHostToDevice));
   ctx->tw[key] = d;
   *out = d;
+  return WF_OK;
+}
+
+// Per-device address of `scratch`, taken once per device with that device current.
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch[kMaxDevices] = {};
+
+int noalloc_setup(wf_ctx* ctx) {
+  if (ctx->dev < 0 || ctx->dev >= kMaxDevices) return fail(ctx, WF_EINVAL, "device index out of range");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch[ctx->dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+      (void)hipGetLastError();
+      return fail(ctx, WF_EHIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    }
+    g_scratch[ctx->dev] = p;
+  }
+  ctx->scratch = g_scratch[ctx->dev];
   return WF_OK;
 }
 
@@ -1255,6 +1295,13 @@ int wf_create(wf_ctx** out, int hip_device) {
     delete c;
     return WF_EHIP;
   }
+  if (noalloc_setup(c) != WF_OK) {
+    (void)hipEventDestroy(c->evIn);
+    (void)hipEventDestroy(c->evOut);
+    (void)hipStreamDestroy(c->cs);
+    delete c;
+    return WF_EHIP;
+  }
   *out = c;
   return WF_OK;
 }
@@ -1829,6 +1876,71 @@ int band_E_ext(wf_ctx* ctx, const wf_problem* p, int batch, const void* s, doubl
 }  // namespace
 
 extern "C" {
+
+int wf_hvp_noalloc(wf_ctx* ctx, const wf_problem* p, int32_t batch, const void* pv, void* Dp, void* stream) {
+  int rc = check_op(ctx, p, batch, pv, Dp);
+  if (rc || batch == 0) return rc;
+  rc = check_problem(ctx, p, false);
+  if (rc) return rc;
+  if (!ctx->scratch) return fail(ctx, WF_EHIP, "no device scratch on this context's device");
+  const int n = p->n, c = p->ncomp, dt = p->dtype, nb = p->nbands;
+  const int64_t L = (int64_t)c * n * (n / 2);
+  const size_t eb = esize_of(dt), rs = rsize_of(dt);
+  const int pstride = c * n / RB_MIN;
+  auto key = std::make_pair(n, dt);
+  if (!ctx->htw.count(key)) twiddle_bytes(n, dt, ctx->htw[key]);
+  const std::vector<char>& htw = ctx->htw[key];
+  // scratch layout: twiddles, prior tables (sqrt S, band, theta and one spare double),
+  // field / intermediate / output vectors, jobs, chain partials
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off += align_up(bytes);
+    return o;
+  };
+  const size_t oTw = take(htw.size());
+  const size_t oSq = take((size_t)L * rs);
+  const size_t oBand = take((size_t)L * 4);
+  const size_t oTheta = take(sizeof(double) * (std::max(1, nb) + 1));
+  const size_t oIn = take((size_t)L * eb * batch);
+  const size_t oY = take((size_t)L * eb * batch);
+  const size_t oOut = take((size_t)L * eb * batch);
+  const size_t oJobs = take(sizeof(Job) * batch);
+  const size_t oPart = take(sizeof(double) * PK_COUNT * pstride * batch);
+  if (off > (size_t)WF_NOALLOC_SCRATCH_BYTES)
+    return fail(ctx, WF_EINVAL, "wf_hvp_noalloc needs " + std::to_string(off) + " bytes of scratch for this batch; the limit is " +
+                                    std::to_string((size_t)WF_NOALLOC_SCRATCH_BYTES) + " bytes");
+  rc = prepare(ctx, n, c, dt);   // kernel attributes only
+  if (rc) return rc;
+  StreamScope ss(ctx, stream);
+  char* S = (char*)ctx->scratch;
+  double* theta = (double*)(S + oTheta);
+  HIPCHK(hipMemcpyAsync(S + oTw, htw.data(), htw.size(), hipMemcpyHostToDevice, ctx->cs));
+  if (nb > 0) HIPCHK(hipMemcpyAsync(theta, p->theta, sizeof(double) * nb, hipMemcpyHostToDevice, ctx->cs));
+  HIPCHK(prior_table_launch(dt, n, c, p->pshape, p->band, theta, nb, nullptr, theta + std::max(1, nb), S + oSq,
+                            (int32_t*)(S + oBand), nullptr, nullptr, ctx->cs));
+  HIPCHK(unpack_launch(dt, n, c, batch, pv, S + oIn, ctx->cs));
+  std::vector<Job> hj(batch);
+  for (int i = 0; i < batch; ++i) {
+    std::memset(&hj[i], 0, sizeof(Job));
+    hj[i].mode = CM_RAW_HV;
+    hj[i].boost_band = -1;
+    hj[i].vin = S + oIn + (size_t)i * L * eb;
+    hj[i].vadd = hj[i].vin;
+    hj[i].y = S + oY + (size_t)i * L * eb;
+    hj[i].vout = S + oOut + (size_t)i * L * eb;
+    hj[i].d = p->d;
+    hj[i].W = p->w;
+    hj[i].sOut = S + oSq;
+    hj[i].part = (double*)(S + oPart) + (size_t)i * PK_COUNT * pstride;
+    hj[i].pstride = pstride;
+  }
+  Job* dj = (Job*)(S + oJobs);
+  HIPCHK(hipMemcpyAsync(dj, hj.data(), sizeof(Job) * batch, hipMemcpyHostToDevice, ctx->cs));
+  for (int w = 0; w < 3; ++w) HIPCHK(chain(ctx, dt, n, c, w, dj, batch, S + oTw));
+  HIPCHK(pack_launch(dt, n, c, batch, S + oOut, L, nullptr, 0, nullptr, Dp, ctx->cs));
+  return WF_OK;
+}
 
 int wf_band_E(wf_ctx* ctx, const wf_problem* p, int32_t batch, const void* s, double* E, void* stream) {
   int rc = check_op(ctx, p, batch, s, E);
