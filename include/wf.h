@@ -110,7 +110,19 @@ typedef struct {
                              the split-preconditioned CG), the same stop test, exact
                              gradient at the start, to confirm the stop and every
                              refresh_every iterations (then restarted); m is ignored      */
-  int32_t reserved;
+  int32_t refine;         /* float32 solves: 0 = off (default); else up to this many rounds
+                             (<= 16) of float64 residual refinement after the solve: the
+                             exact gradient is evaluated in float64 and a float32 correction
+                             solve of D delta = -g (same solver, explicit right-hand side)
+                             is added in float64, until the float64 relative whitened
+                             gradient is <= refine_tol.  The relative-gradient stop of
+                             float32 arithmetic ends near 1e-7; badly conditioned maps
+                             (whitened condition number ~1e7, as the CMB workload) need
+                             ~1e-10 and below for maps within 1e-5.  Stats then report the
+                             float64 chi^2 and relative gradient, the iterations of all
+                             solves, and WF_SOLVE_MAXITER if refine_tol was not reached.
+                             Ignored for float64 problems.                               */
+  double refine_tol;      /* target of the refinement (default 1e-10)                     */
 } wf_lbfgs_opts;
 
 enum { WF_METHOD_LBFGS = 0, WF_METHOD_CG = 1 };

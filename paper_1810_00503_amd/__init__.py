@@ -100,10 +100,13 @@ class LbfgsOpts:
     use_graph: int = 1
     precond: int = 0
     method: int = 0   # WF_METHOD_LBFGS or WF_METHOD_CG
+    refine: int = 0   # rounds of float64 residual refinement of float32 solves (0 = off)
+    refine_tol: float = 1e-10
 
     def c(self) -> L.WfLbfgsOpts:
         return L.WfLbfgsOpts(self.m, self.max_iter, self.rel_grad_tol, self.dchi2_tol, self.refresh_every,
-                             self.iters_per_poll, self.use_graph, self.precond, self.method, 0)
+                             self.iters_per_poll, self.use_graph, self.precond, self.method, self.refine,
+                             self.refine_tol)
 
 
 @dataclasses.dataclass

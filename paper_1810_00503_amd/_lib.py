@@ -35,7 +35,7 @@ class WfLbfgsOpts(C.Structure):
     _fields_ = [
         ("m", C.c_int32), ("max_iter", C.c_int32), ("rel_grad_tol", C.c_double), ("dchi2_tol", C.c_double),
         ("refresh_every", C.c_int32), ("iters_per_poll", C.c_int32), ("use_graph", C.c_int32),
-        ("precond", C.c_int32), ("method", C.c_int32), ("reserved", C.c_int32),
+        ("precond", C.c_int32), ("method", C.c_int32), ("refine", C.c_int32), ("refine_tol", C.c_double),
     ]
 
 

@@ -60,7 +60,7 @@ struct wf_ctx {
   hipEvent_t evIn = nullptr, evOut = nullptr;
   std::map<std::pair<int, int>, void*> tw;   // (n, dtype) -> twiddles
   std::map<std::tuple<int, int, int>, bool> prepared;
-  Arena solveA, simA, opA, accA;
+  Arena solveA, simA, opA, accA, refA;
   int* hstat = nullptr;
   size_t hstatCap = 0;
   // instrumentation
@@ -328,6 +328,9 @@ void fill_opts(const wf_lbfgs_opts* o, wf_lbfgs_opts& r) {
   if (r.precond != 0) r.precond = 1;
   if (r.method != WF_METHOD_CG) r.method = WF_METHOD_LBFGS;
   if (r.method == WF_METHOD_CG) r.m = 1;   // CG keeps w, g, p and Dp: one pair of the vector block
+  if (r.refine < 0) r.refine = 0;
+  if (r.refine > 16) r.refine = 16;
+  if (!(r.refine_tol > 0)) r.refine_tol = 1e-10;
 }
 
 // ---------------------------------------------------------------------------- prior tables
@@ -503,6 +506,259 @@ int tune_chain(wf_ctx* ctx, Klass& k, const std::vector<InstDesc>& hd, Job* djob
   return WF_OK;
 }
 
+// Float64 residual refinement of float32 solves (option refine > 0).  The stop test of the
+// float32 solve measures the whitened gradient, which the stiff (high signal-to-noise) modes
+// dominate; on very red spectra (the CMB workload) a solve stopped at 1e-6 can still be 1e-2
+// off in the map, and float32 cannot evaluate the gradient much below 1e-7 of its start.
+// Each round evaluates the exact gradient g of every instance of the float32 classes in
+// float64 (float64 copies of d, W, the prior tables and the solution v; the same rounded
+// tables as the float32 solve, so both solve the same problem), and for the instances
+// whose float64 relative gradient |g|_w / |g(0)|_w still exceeds refine_tol runs a float32
+// correction solve of D delta = -g (the same batched solver on zero data, with -g as an
+// explicit right-hand side, to a relative gradient of max(0.3 refine_tol / current, 1e-3)),
+// then v += delta in float64.  At most `refine` correction rounds; the last evaluation gives
+// the reported chi^2 and relative gradient.  Instances whose first solve did not converge are
+// left as they are.
+// The float32 evaluation of a correction's own gradient is limited by the stiff part of D
+// acting on a residual that sits mostly in soft modes: its relative-gradient stop ends between
+// ~1e-5 and ~1e-3 of its start on the CMB maps (against ~2e-8 for a full solve), so a round
+// asks for at most a 1e-3 reduction (which gives more in the float64 gradient) and is capped
+// at twice the iterations of the first solve (at least kRefineMinIter); a round that hits its
+// cap still improves the field and is kept.
+constexpr double kRefineTolMin = 1e-3;
+constexpr int kRefineMinIter = 200;
+
+template <typename InitF, typename RunF>
+int refine_f64(wf_ctx* ctx, const wf_lbfgs_opts& o, const std::vector<Klass>& ks, std::vector<InstDesc>& hd,
+               InstDesc* ddesc, LbState* dst, std::vector<LbState>& hs, InitF& init_class, RunF& run_loop) {
+  const double T = o.refine_tol;
+  std::vector<int> fk;
+  for (size_t c = 0; c < ks.size(); ++c)
+    if (ks[c].dtype == WF_F32) fk.push_back((int)c);
+  if (fk.empty()) return WF_OK;
+  const int B = (int)hd.size();
+  struct Ref {
+    void *v64 = nullptr, *g64 = nullptr, *y64 = nullptr, *d64 = nullptr, *W64 = nullptr, *sq64 = nullptr,
+         *a64 = nullptr, *ainv64 = nullptr;
+    float* rhs = nullptr;
+    double *part64 = nullptr, *rpart = nullptr;
+  };
+  std::vector<Ref> rf(B);
+  auto nblk_of = [](int64_t L) { return (int)std::min<int64_t>(256, (L + 255) / 256); };
+  size_t total = 0;
+  for (int c : fk) {
+    const Klass& k = ks[c];
+    const size_t L = (size_t)k.L, npix = (size_t)k.c * k.n * k.n, cnt = k.members.size();
+    const size_t per = 3 * align_up(L * 16) + align_up(npix * 8) + align_up((size_t)k.n * k.n * 8) + 3 * align_up(L * 8) +
+                       align_up(L * 8) + align_up(sizeof(double) * PK_COUNT * k.pstride) +
+                       align_up(sizeof(double) * nblk_of(k.L));
+    total += per * cnt + align_up(npix * 4) + align_up(sizeof(Job) * cnt) + align_up(sizeof(RhsJob) * cnt) +
+             2 * align_up(sizeof(CvtJob) * 6 * cnt);
+  }
+  int rc = arena_reserve(ctx, ctx->refA, total);
+  if (rc) return rc;
+  Arena& A = ctx->refA;
+  struct KRef {
+    void* zero = nullptr;
+    Job* jobs = nullptr;
+    RhsJob* rj = nullptr;
+    CvtJob* cv = nullptr;   // promotions, then the accumulation / demotion jobs
+    CvtJob* cv2 = nullptr;
+    const void* tw = nullptr;
+  };
+  std::vector<KRef> kr(ks.size());
+  ChainCfg cfg64;
+  for (int c : fk) {
+    const Klass& k = ks[c];
+    const size_t L = (size_t)k.L, npix = (size_t)k.c * k.n * k.n, cnt = k.members.size();
+    KRef& K = kr[c];
+    K.zero = arena_take(A, npix * 4);
+    K.jobs = (Job*)arena_take(A, sizeof(Job) * cnt);
+    K.rj = (RhsJob*)arena_take(A, sizeof(RhsJob) * cnt);
+    K.cv = (CvtJob*)arena_take(A, sizeof(CvtJob) * 6 * cnt);
+    K.cv2 = (CvtJob*)arena_take(A, sizeof(CvtJob) * 6 * cnt);
+    HIPCHK(hipMemsetAsync(K.zero, 0, npix * 4, ctx->cs));
+    rc = twiddles(ctx, k.n, WF_F64, &K.tw);
+    if (rc) return rc;
+    rc = prepare(ctx, k.n, k.c, WF_F64);
+    if (rc) return rc;
+    std::vector<Job> hj(cnt);
+    std::vector<RhsJob> hr(cnt);
+    std::vector<CvtJob> hc;
+    for (size_t j = 0; j < cnt; ++j) {
+      const int gi = k.first + (int)j;
+      const InstDesc& D = hd[gi];
+      Ref& r = rf[gi];
+      r.v64 = arena_take(A, L * 16);
+      r.g64 = arena_take(A, L * 16);
+      r.y64 = arena_take(A, L * 16);
+      r.d64 = arena_take(A, npix * 8);
+      r.W64 = arena_take(A, (size_t)k.n * k.n * 8);
+      r.sq64 = arena_take(A, L * 8);
+      r.a64 = arena_take(A, L * 8);
+      r.ainv64 = arena_take(A, L * 8);
+      r.rhs = (float*)arena_take(A, L * 8);
+      r.part64 = (double*)arena_take(A, sizeof(double) * PK_COUNT * k.pstride);
+      r.rpart = (double*)arena_take(A, sizeof(double) * nblk_of(k.L));
+      hc.push_back(CvtJob{D.d, r.d64, (int64_t)npix, CVT_F32_F64, 0});
+      hc.push_back(CvtJob{D.W, r.W64, (int64_t)k.n * k.n, CVT_F32_F64, 0});
+      hc.push_back(CvtJob{D.sq, r.sq64, (int64_t)L, CVT_F32_F64, 0});
+      hc.push_back(CvtJob{D.X, r.v64, (int64_t)(2 * L), CVT_F32_F64, 0});
+      if (D.aTab) {
+        hc.push_back(CvtJob{D.aTab, r.a64, (int64_t)L, CVT_F32_F64, 0});
+        hc.push_back(CvtJob{D.ainv, r.ainv64, (int64_t)L, CVT_F32_F64, 0});
+      }
+      Job& jb = hj[j];
+      std::memset(&jb, 0, sizeof jb);
+      jb.mode = CM_GRAD;
+      jb.boost_band = -1;
+      jb.vin = r.v64;
+      jb.vadd = r.v64;
+      jb.vout = r.g64;
+      jb.y = r.y64;
+      jb.d = r.d64;
+      jb.W = r.W64;
+      jb.sIn = r.sq64;
+      jb.sOut = r.sq64;
+      jb.aTab = D.aTab ? r.a64 : nullptr;
+      jb.part = r.part64;
+      jb.pstride = k.pstride;
+      hr[j] = RhsJob{(const double*)r.g64, D.aTab ? (const double*)r.ainv64 : nullptr, r.rhs, r.rpart, (int64_t)L};
+    }
+    HIPCHK(hipMemcpyAsync(K.jobs, hj.data(), sizeof(Job) * cnt, hipMemcpyHostToDevice, ctx->cs));
+    HIPCHK(hipMemcpyAsync(K.rj, hr.data(), sizeof(RhsJob) * cnt, hipMemcpyHostToDevice, ctx->cs));
+    HIPCHK(hipMemcpyAsync(K.cv, hc.data(), sizeof(CvtJob) * hc.size(), hipMemcpyHostToDevice, ctx->cs));
+    {
+      Timed t(ctx, KK_MISC);
+      HIPCHK(convert_launch(K.cv, (int)hc.size(), (int64_t)std::max(npix, 2 * L), ctx->cs));
+    }
+  }
+  std::vector<double> rho(B, 0.0), prev(B, 0.0), chi(B, 0.0);
+  std::vector<int> conv0(B, 0), live(B, 0), addIt(B, 0), addGrad(B, 0);
+  for (int c : fk)
+    for (size_t j = 0; j < ks[c].members.size(); ++j) {
+      const int gi = ks[c].first + (int)j;
+      conv0[gi] = hs[gi].status == WF_SOLVE_CONVERGED;
+      live[gi] = conv0[gi];
+    }
+  for (int round = 0;; ++round) {
+    // float64 exact gradient, right-hand side and norms of every instance of the float32 classes
+    for (int c : fk) {
+      const Klass& k = ks[c];
+      const int cnt = (int)k.members.size();
+      for (int w = 0; w < 3; ++w) HIPCHK(chain(ctx, WF_F64, k.n, k.c, w, kr[c].jobs, cnt, kr[c].tw, &cfg64));
+      Timed t(ctx, KK_MISC);
+      HIPCHK(refine_rhs_launch(kr[c].rj, cnt, nblk_of(k.L), ctx->cs));
+    }
+    std::vector<std::vector<double>> hp(B), hq(B);
+    for (int c : fk)
+      for (size_t j = 0; j < ks[c].members.size(); ++j) {
+        const int gi = ks[c].first + (int)j;
+        hp[gi].resize((size_t)PK_COUNT * ks[c].pstride);
+        hq[gi].resize(nblk_of(ks[c].L));
+        HIPCHK(hipMemcpyAsync(hp[gi].data(), rf[gi].part64, sizeof(double) * hp[gi].size(), hipMemcpyDeviceToHost,
+                              ctx->cs));
+        HIPCHK(hipMemcpyAsync(hq[gi].data(), rf[gi].rpart, sizeof(double) * hq[gi].size(), hipMemcpyDeviceToHost,
+                              ctx->cs));
+      }
+    HIPCHK(hipStreamSynchronize(ctx->cs));
+    bool any = false;
+    for (int c : fk) {
+      const Klass& k = ks[c];
+      const int ncol = (k.n / 2) / TB, nrow = k.c * k.n / RB_MIN;
+      for (size_t j = 0; j < k.members.size(); ++j) {
+        const int gi = k.first + (int)j;
+        double gw = 0.0, pr = 0.0, res = 0.0;
+        for (double v : hq[gi]) gw += v;
+        for (int b = 0; b < ncol; ++b) pr += hp[gi][(size_t)PK_PRIOR * k.pstride + b];
+        for (int b = 0; b < nrow; ++b) res += hp[gi][(size_t)PK_RES * k.pstride + b];
+        const double g0 = hs[gi].g0norm;
+        prev[gi] = rho[gi];
+        rho[gi] = g0 > 0.0 ? std::sqrt(gw) / g0 : 0.0;
+        chi[gi] = 2.0 * pr + res;
+        if (conv0[gi]) addGrad[gi] += 1;
+        // stop refining an instance that is done, that stopped improving (a round must at
+        // least halve its gradient) or whose values are not finite
+        if (live[gi] && (!(rho[gi] > T) || !std::isfinite(rho[gi]) || (round > 0 && !(rho[gi] < 0.5 * prev[gi]))))
+          live[gi] = 0;
+        any = any || live[gi];
+      }
+    }
+    if (!any || round >= o.refine) break;
+    // float32 correction solves of the instances still refined; the other members of their
+    // classes stop at once (infinite tolerance); their v64 keeps their solution
+    std::vector<int64_t> nrun(ks.size(), 0);
+    for (int c : fk) {
+      const Klass& k = ks[c];
+      bool cls = false;
+      for (size_t j = 0; j < k.members.size(); ++j) cls = cls || live[k.first + (int)j];
+      if (!cls) continue;
+      std::vector<InstDesc> dd(hd.begin() + k.first, hd.begin() + k.first + k.members.size());
+      for (size_t j = 0; j < k.members.size(); ++j) {
+        const int gi = k.first + (int)j;
+        dd[j].d = kr[c].zero;
+        dd[j].rhs = rf[gi].rhs;
+        dd[j].dchi2Tol = 0.0;
+        dd[j].tol = live[gi] ? std::max(0.3 * T / rho[gi], kRefineTolMin) : 1e300;
+        dd[j].maxIter = std::min(o.max_iter, std::max(kRefineMinIter, 2 * hs[gi].iter));
+      }
+      HIPCHK(hipMemcpyAsync(ddesc + k.first, dd.data(), sizeof(InstDesc) * dd.size(), hipMemcpyHostToDevice, ctx->cs));
+      rc = init_class(k);
+      if (rc) return rc;
+      nrun[c] = (int64_t)k.members.size();
+    }
+    rc = run_loop(nrun);
+    if (rc) return rc;
+    std::vector<LbState> cs(B);
+    HIPCHK(hipMemcpyAsync(cs.data(), dst, sizeof(LbState) * B, hipMemcpyDeviceToHost, ctx->cs));
+    HIPCHK(hipStreamSynchronize(ctx->cs));
+    for (int c : fk) {
+      if (nrun[c] == 0) continue;
+      const Klass& k = ks[c];
+      std::vector<CvtJob> hc;
+      for (size_t j = 0; j < k.members.size(); ++j) {
+        const int gi = k.first + (int)j;
+        for (int q = 0; q < KK_COUNT; ++q) ctx->bytes[q] += cs[gi].bytes[q];
+        if (!live[gi]) continue;
+        addIt[gi] += cs[gi].iter;
+        addGrad[gi] += cs[gi].ngrad;
+        if (cs[gi].status == WF_SOLVE_NONFINITE) {   // keep the last good solution
+          live[gi] = 0;
+          continue;
+        }
+        hc.push_back(CvtJob{hd[gi].X, rf[gi].v64, 2 * k.L, CVT_ADD_F32_F64, 0});
+      }
+      if (!hc.empty()) {
+        HIPCHK(hipMemcpyAsync(kr[c].cv2, hc.data(), sizeof(CvtJob) * hc.size(), hipMemcpyHostToDevice, ctx->cs));
+        Timed t(ctx, KK_MISC);
+        HIPCHK(convert_launch(kr[c].cv2, (int)hc.size(), 2 * k.L, ctx->cs));
+      }
+    }
+  }
+  // the refined solutions back into the solver's float32 vectors (the packing, maps and band
+  // statistics read them there)
+  for (int c : fk) {
+    const Klass& k = ks[c];
+    std::vector<CvtJob> hc;
+    for (size_t j = 0; j < k.members.size(); ++j) {
+      const int gi = k.first + (int)j;
+      hc.push_back(CvtJob{rf[gi].v64, hd[gi].X, 2 * k.L, CVT_F64_F32, 0});
+      if (!conv0[gi]) continue;
+      LbState& S = hs[gi];
+      S.status = rho[gi] <= T ? WF_SOLVE_CONVERGED : WF_SOLVE_MAXITER;
+      S.iter += addIt[gi];
+      S.ngrad += addGrad[gi];
+      S.chi2 = chi[gi];
+      S.gg = (rho[gi] * S.g0norm) * (rho[gi] * S.g0norm);
+    }
+    HIPCHK(hipMemcpyAsync(kr[c].cv2, hc.data(), sizeof(CvtJob) * hc.size(), hipMemcpyHostToDevice, ctx->cs));
+    Timed t(ctx, KK_MISC);
+    HIPCHK(convert_launch(kr[c].cv2, (int)hc.size(), 2 * k.L, ctx->cs));
+  }
+  HIPCHK(hipStreamSynchronize(ctx->cs));
+  return WF_OK;
+}
+
 // tols: nullable per-instance relative-gradient tolerances (user index), else o's
 int solve_core(wf_ctx* ctx, const wf_problem* probs, int B, const wf_lbfgs_opts& o, SolveOut& out,
                const double* tols = nullptr) {
@@ -635,8 +891,8 @@ int solve_core(wf_ctx* ctx, const wf_problem* probs, int B, const wf_lbfgs_opts&
     rc = tune_chain(ctx, k, hd, djobs, m);
     if (rc) return rc;
   }
-  // init
-  for (auto& k : ks) {
+  // start of a solve of every instance of a class: w = 0, state reset, exact gradient first
+  auto init_class = [&](const Klass& k) -> int {
     const int cnt = (int)k.members.size();
     {
       Timed t(ctx, KK_MISC);
@@ -650,6 +906,11 @@ int solve_core(wf_ctx* ctx, const wf_problem* probs, int B, const wf_lbfgs_opts&
       HIPCHK(lbfgs_launch(k.dtype == WF_F64, m, k.pu, LB_INIT, dim3(1), ddesc + k.first, dst + k.first, djobs + k.first, cnt,
                           ctx->cs));
     }
+    return WF_OK;
+  };
+  for (auto& k : ks) {
+    rc = init_class(k);
+    if (rc) return rc;
   }
   // one iteration of one class (classes share no buffers, so their iterations are independent)
   const bool cg = o.method == WF_METHOD_CG;
@@ -738,77 +999,89 @@ int solve_core(wf_ctx* ctx, const wf_problem* probs, int B, const wf_lbfgs_opts&
       ctx->xev.push_back(ev);
     }
   }
-  // running instances per class: all at the start, then as the host polls find them
-  std::vector<int64_t> nrun(nk);
-  for (int c = 0; c < nk; ++c) nrun[c] = (int64_t)ks[c].members.size();
-  // one iteration takes at most four bodies (curvature product, flush of w, exact gradient,
+  // Host-polled iterations until every instance of the classes with nrun[c] > 0 has stopped.
+  // One iteration takes at most four bodies (curvature product, flush of w, exact gradient,
   // dots after a failed confirmation), so the device's own max_iter test, which flushes w
-  // before it stops, always comes first
-  const int64_t maxBodies = 4LL * o.max_iter + 64;
-  int64_t bodies = 0;
-  while (true) {
-    if (graph) {
-      // classes with running instances, heaviest first (running instances x vector length),
-      // each onto the stream with the least load so far: the long classes of an uneven batch
-      // get streams of their own
-      std::vector<int> act;
-      for (int c = 0; c < nk; ++c)
-        if (nrun[c] > 0) act.push_back(c);
-      std::stable_sort(act.begin(), act.end(),
-                       [&](int x, int y) { return nrun[x] * ks[x].L > nrun[y] * ks[y].L; });
-      const int ns = std::min((int)act.size(), kMaxStreams);
-      std::vector<int64_t> sload(ns, 0);
-      if (ns > 1) HIPCHK(hipEventRecord(ctx->evFork, ctx->cs));
-      for (int s = 1; s < ns; ++s) HIPCHK(hipStreamWaitEvent(ctx->xs[s - 1], ctx->evFork, 0));
-      for (size_t a = 0; a < act.size(); ++a) {
-        const int s = (int)(std::min_element(sload.begin(), sload.end()) - sload.begin());
-        sload[s] += nrun[act[a]] * ks[act[a]].L;
-        HIPCHK(hipGraphLaunch(gx[act[a]], s == 0 ? ctx->cs : ctx->xs[s - 1]));
-        // count launches as if enqueued one by one
-        ctx->launches[KK_COLINV] += K;
-        ctx->launches[KK_ROW] += K;
-        ctx->launches[KK_COLFWD] += K;
-        ctx->launches[KK_POST] += K;
-        if (!cg) ctx->launches[KK_PASSA] += K;
-        ctx->launches[KK_COEF] += K;
-        ctx->launches[KK_PASSB] += K;
-        if (cg) ctx->launches[KK_DIR] += K;
-      }
-      for (int s = 1; s < ns; ++s) {
-        HIPCHK(hipEventRecord(ctx->xev[s - 1], ctx->xs[s - 1]));
-        HIPCHK(hipStreamWaitEvent(ctx->cs, ctx->xev[s - 1], 0));
-      }
-    } else {
-      for (int r = 0; r < K; ++r)
-        for (int c = 0; c < nk; ++c) {
-          if (nrun[c] == 0) continue;
-          rc = body(ks[c]);
-          if (rc) return rc;
+  // before it stops, always comes first.
+  auto run_loop = [&](std::vector<int64_t> nrun) -> int {
+    const int64_t maxBodies = 4LL * o.max_iter + 64;
+    int64_t bodies = 0;
+    while (true) {
+      if (graph) {
+        // classes with running instances, heaviest first (running instances x vector length),
+        // each onto the stream with the least load so far: the long classes of an uneven batch
+        // get streams of their own
+        std::vector<int> act;
+        for (int c = 0; c < nk; ++c)
+          if (nrun[c] > 0) act.push_back(c);
+        std::stable_sort(act.begin(), act.end(),
+                         [&](int x, int y) { return nrun[x] * ks[x].L > nrun[y] * ks[y].L; });
+        const int ns = std::min((int)act.size(), kMaxStreams);
+        std::vector<int64_t> sload(ns, 0);
+        if (ns > 1) HIPCHK(hipEventRecord(ctx->evFork, ctx->cs));
+        for (int s = 1; s < ns; ++s) HIPCHK(hipStreamWaitEvent(ctx->xs[s - 1], ctx->evFork, 0));
+        for (size_t a = 0; a < act.size(); ++a) {
+          const int s = (int)(std::min_element(sload.begin(), sload.end()) - sload.begin());
+          sload[s] += nrun[act[a]] * ks[act[a]].L;
+          HIPCHK(hipGraphLaunch(gx[act[a]], s == 0 ? ctx->cs : ctx->xs[s - 1]));
+          // count launches as if enqueued one by one
+          ctx->launches[KK_COLINV] += K;
+          ctx->launches[KK_ROW] += K;
+          ctx->launches[KK_COLFWD] += K;
+          ctx->launches[KK_POST] += K;
+          if (!cg) ctx->launches[KK_PASSA] += K;
+          ctx->launches[KK_COEF] += K;
+          ctx->launches[KK_PASSB] += K;
+          if (cg) ctx->launches[KK_DIR] += K;
         }
+        for (int s = 1; s < ns; ++s) {
+          HIPCHK(hipEventRecord(ctx->xev[s - 1], ctx->xs[s - 1]));
+          HIPCHK(hipStreamWaitEvent(ctx->cs, ctx->xev[s - 1], 0));
+        }
+      } else {
+        for (int r = 0; r < K; ++r)
+          for (int c = 0; c < nk; ++c) {
+            if (nrun[c] == 0) continue;
+            int brc = body(ks[c]);
+            if (brc) return brc;
+          }
+      }
+      bodies += K;
+      HIPCHK(hipMemcpyAsync(ctx->hstat, dstat, sizeof(int) * B, hipMemcpyDeviceToHost, ctx->cs));
+      HIPCHK(hipStreamSynchronize(ctx->cs));
+      int drc = drain_events(ctx);
+      if (drc) return drc;
+      int64_t running = 0;
+      for (int c = 0; c < nk; ++c) {
+        if (nrun[c] == 0) continue;
+        int64_t r = 0;
+        for (size_t j = 0; j < ks[c].members.size(); ++j) r += (ctx->hstat[ks[c].first + (int)j] == ST_RUNNING);
+        nrun[c] = r;
+        running += r;
+      }
+      if (running == 0 || bodies >= maxBodies) break;
     }
-    bodies += K;
-    HIPCHK(hipMemcpyAsync(ctx->hstat, dstat, sizeof(int) * B, hipMemcpyDeviceToHost, ctx->cs));
-    HIPCHK(hipStreamSynchronize(ctx->cs));
-    rc = drain_events(ctx);
+    return WF_OK;
+  };
+  {
+    std::vector<int64_t> nrun(nk);
+    for (int c = 0; c < nk; ++c) nrun[c] = (int64_t)ks[c].members.size();
+    rc = run_loop(nrun);
     if (rc) return rc;
-    int64_t running = 0;
-    for (int c = 0; c < nk; ++c) {
-      int64_t r = 0;
-      for (size_t j = 0; j < ks[c].members.size(); ++j) r += (ctx->hstat[ks[c].first + (int)j] == ST_RUNNING);
-      nrun[c] = r;
-      running += r;
-    }
-    if (running == 0 || bodies >= maxBodies) break;
   }
   std::vector<LbState> hs(B);
   HIPCHK(hipMemcpyAsync(hs.data(), dst, sizeof(LbState) * B, hipMemcpyDeviceToHost, ctx->cs));
   HIPCHK(hipStreamSynchronize(ctx->cs));
-  out.st.assign(B, LbState());
-  for (int ui = 0; ui < B; ++ui) {
-    out.st[ui] = hs[out.order[ui]];
-    if (out.st[ui].status == ST_RUNNING) out.st[ui].status = WF_SOLVE_MAXITER;
-    for (int k = 0; k < KK_COUNT; ++k) ctx->bytes[k] += hs[out.order[ui]].bytes[k];
+  for (int gi = 0; gi < B; ++gi) {
+    if (hs[gi].status == ST_RUNNING) hs[gi].status = WF_SOLVE_MAXITER;
+    for (int k = 0; k < KK_COUNT; ++k) ctx->bytes[k] += hs[gi].bytes[k];
   }
+  if (o.refine > 0) {
+    rc = refine_f64(ctx, o, ks, hd, ddesc, dst, hs, init_class, run_loop);
+    if (rc) return rc;
+  }
+  out.st.assign(B, LbState());
+  for (int ui = 0; ui < B; ++ui) out.st[ui] = hs[out.order[ui]];
   return WF_OK;
 }
 
@@ -1279,7 +1552,8 @@ void wf_lbfgs_default(wf_lbfgs_opts* o) {
   o->use_graph = 1;
   o->precond = 0;
   o->method = WF_METHOD_LBFGS;
-  o->reserved = 0;
+  o->refine = 0;
+  o->refine_tol = 1e-10;
 }
 
 int wf_create(wf_ctx** out, int hip_device) {
@@ -1318,7 +1592,7 @@ void wf_destroy(wf_ctx* c) {
   for (auto e : c->xev) (void)hipEventDestroy(e);
   if (c->evFork) (void)hipEventDestroy(c->evFork);
   for (auto& kv : c->tw) (void)hipFree(kv.second);
-  for (Arena* a : {&c->solveA, &c->simA, &c->opA, &c->accA})
+  for (Arena* a : {&c->solveA, &c->simA, &c->opA, &c->accA, &c->refA})
     if (a->base) (void)hipFree(a->base);
   if (c->hstat) (void)hipHostFree(c->hstat);
   for (auto& pe : c->pendingEv) {

@@ -231,6 +231,27 @@ struct PackEntry {
   void* out;        // [C][n][n/2+1] external field
 };
 
+// Elementwise conversion job of the float64 refinement (counts in real elements).
+struct CvtJob {
+  const void* src;
+  void* dst;
+  int64_t n;
+  int op;   // CVT_*
+  int pad;
+};
+enum { CVT_F32_F64 = 0, CVT_F64_F32 = 1, CVT_ADD_F32_F64 = 2 };
+
+// Right-hand side of a float32 correction solve from a float64 gradient g (L complex
+// elements, internal layout): rhs = -g rounded to float32, and per block the partial sums of
+// |g|^2 in the solver's whitened metric (1 / P_k per element when ainv is given).
+struct RhsJob {
+  const double* g;
+  const double* ainv;
+  float* rhs;
+  double* part;   // [gridDim.x]
+  int64_t L;
+};
+
 // One field's band-statistic job.
 struct BandJob {
   const void* f;          // field, internal layout
@@ -258,6 +279,8 @@ struct InstDesc {
   const void* sq;   // scale table (internal layout, real): sqrt S, or sqrt(S P) when preconditioned
   const void* aTab; // preconditioned solves: P_k = 1 / (1 + S_k <W>); else null
   const void* ainv; // preconditioned solves: 1 / P_k (whitened gradient norm); else null
+  const void* rhs;  // correction solves of a float64 refinement: the gradient is D v - rhs
+                    // (the chain runs on zero data and pass A subtracts rhs); else null
   double* partChain;   // [PK_COUNT][pstride]
   double* partA;       // [nblkA][NDOT]
   int* statusOut;      // compact per-instance status for host polling

@@ -86,5 +86,9 @@ hipError_t sqdiff_acc_launch(int dtype, int64_t len, int P, int count, const voi
                              hipStream_t s);
 hipError_t acc_out_launch(int dtype, int64_t len, const double* acc, double scale, void* out, hipStream_t s);
 int band_nblk(int64_t L);
+// float64 refinement: elementwise conversions (CvtJob, maxn = largest count) and the float32
+// right-hand side with per-block norm partials of a float64 gradient (nblk blocks per job)
+hipError_t convert_launch(const CvtJob* jobs, int count, int64_t maxn, hipStream_t s);
+hipError_t refine_rhs_launch(const RhsJob* jobs, int count, int nblk, hipStream_t s);
 
 }  // namespace wf

@@ -199,12 +199,18 @@ __global__ __launch_bounds__(NT) void k_passA(const InstDesc* __restrict__ desc,
   V gv[PASS_U];
   double gg = 0.0;
   const T* ainv = reinterpret_cast<const T*>(D.ainv);
+  // a correction solve's exact gradient is D v - rhs: the chain ran on zero data
+  const V* R = (S.chainMode == CM_GRAD) ? reinterpret_cast<const V*>(D.rhs) : nullptr;
 #pragma unroll
   for (int u = 0; u < PASS_U; ++u) {
     const uint32_t e = e0 + (uint32_t)u * NT;
     ok[u] = e < nvec;
     if (ok[u]) {
       gv[u] = gld(X, og + e);
+      if (R) {
+        gv[u] = vaxpy(T(-1), gld(R, e), gv[u]);
+        gst(reinterpret_cast<V*>(D.X), og + e, gv[u]);
+      }
       gg += ainv ? wnorm2(gv[u], ainv, e) : vdot(gv[u], gv[u]);
     }
   }
@@ -423,7 +429,7 @@ __device__ __forceinline__ int coef_update(const InstDesc& D, LbState& S, Job& j
       S.npend = 0;   // an exact gradient is only taken at a flushed iterate
       S.lastWasGrad = 1;
     }
-    S.bytes[KK_PASSA] += D.vbytes * (1.0 + (dots ? 2.0 * nh : 0.0));
+    S.bytes[KK_PASSA] += D.vbytes * (1.0 + (dots ? 2.0 * nh : 0.0) + (mode == CM_GRAD && D.rhs ? 2.0 : 0.0));
     if (dots) {
       for (int j = 0; j < nh; ++j) {
         const int sj = slot_of(head, j, M);
@@ -840,7 +846,7 @@ __global__ __launch_bounds__(256) void k_cg_step(const InstDesc* __restrict__ de
     S.lastGradIter = S.iter;
     S.lastWasGrad = 1;
     S.doB = 2;
-    S.bytes[KK_PASSB] += D.vbytes;         // g read
+    S.bytes[KK_PASSB] += D.vbytes * (D.rhs ? 3.0 : 1.0);   // g read (and rhs read, g written)
   }
 }
 
@@ -874,6 +880,9 @@ __global__ __launch_bounds__(NT) void k_cg_pass(const InstDesc* __restrict__ des
         g = vaxpy(al, dp, g);
         gst(X, og + e, g);
         gst(X, ow + e, vaxpy(al, p, w));
+      } else if (D.rhs) {   // a correction solve's exact gradient is D v - rhs
+        g = vaxpy(T(-1), gld(reinterpret_cast<const V*>(D.rhs), e), g);
+        gst(X, og + e, g);
       }
       const double t = vdot(g, g);
       gg += t;
@@ -1212,6 +1221,38 @@ __global__ void k_band_final(const BandJob* __restrict__ jobs, int nblk) {
     for (int b = 0; b < nblk; ++b) a += jb.part[(int64_t)b * jb.nbands + l];
     jb.E[l] = jb.raw == 2 ? a : a / jb.theta[l];
   }
+}
+
+// ------------------------------------------------------------------------ float64 refinement
+__global__ void k_convert(const CvtJob* __restrict__ jobs) {
+  const CvtJob J = jobs[blockIdx.y];
+  const int64_t step = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < J.n; e += step) {
+    if (J.op == CVT_F32_F64)
+      reinterpret_cast<double*>(J.dst)[e] = (double)reinterpret_cast<const float*>(J.src)[e];
+    else if (J.op == CVT_F64_F32)
+      reinterpret_cast<float*>(J.dst)[e] = (float)reinterpret_cast<const double*>(J.src)[e];
+    else
+      reinterpret_cast<double*>(J.dst)[e] += (double)reinterpret_cast<const float*>(J.src)[e];
+  }
+}
+
+__global__ __launch_bounds__(256) void k_refine_rhs(const RhsJob* __restrict__ jobs) {
+  const RhsJob J = jobs[blockIdx.y];
+  __shared__ double red[4];
+  double a = 0.0;
+  const int64_t step = (int64_t)gridDim.x * 256;
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < J.L; e += step) {
+    const double gr = J.g[2 * e], gi = J.g[2 * e + 1];
+    J.rhs[2 * e] = (float)(-gr);
+    J.rhs[2 * e + 1] = (float)(-gi);
+    const double t = gr * gr + gi * gi;
+    a += J.ainv ? J.ainv[e] * t : t;
+  }
+  a = wave_sum(a);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = a;
+  __syncthreads();
+  if (threadIdx.x == 0) J.part[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
 }
 
 }  // namespace wf

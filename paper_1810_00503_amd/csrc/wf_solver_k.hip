@@ -163,4 +163,18 @@ hipError_t band_launch(int dtype, const BandJob* jobs, int count, int64_t L, hip
   return hipGetLastError();
 }
 
+hipError_t convert_launch(const CvtJob* jobs, int count, int64_t maxn, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  int64_t b = (maxn + 255) / 256;
+  b = b < 1 ? 1 : (b > 1024 ? 1024 : b);
+  k_convert<<<dim3((unsigned)b, count), 256, 0, s>>>(jobs);
+  return hipGetLastError();
+}
+
+hipError_t refine_rhs_launch(const RhsJob* jobs, int count, int nblk, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  k_refine_rhs<<<dim3(nblk, count), 256, 0, s>>>(jobs);
+  return hipGetLastError();
+}
+
 }  // namespace wf

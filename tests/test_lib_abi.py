@@ -44,10 +44,11 @@ def test_binding_matches_exports():
     o = _lib.WfLbfgsOpts()
     lib.wf_lbfgs_default(ctypes.byref(o))
     assert o.m == 10 and o.rel_grad_tol == 1e-6 and o.use_graph == 1 and o.method == 0
+    assert o.refine == 0 and o.refine_tol == 1e-10
 
 
 def test_struct_layouts_match_header():
     from paper_1810_00503_amd import _lib
     assert ctypes.sizeof(_lib.WfProblem) == 4 * 4 + 5 * 8
-    assert ctypes.sizeof(_lib.WfLbfgsOpts) == 4 * 2 + 8 * 2 + 4 * 6
+    assert ctypes.sizeof(_lib.WfLbfgsOpts) == 4 * 2 + 8 * 2 + 4 * 6 + 8
     assert ctypes.sizeof(_lib.WfSolveStats) == 4 * 4 + 8 * 2
