@@ -50,6 +50,7 @@ def parse():
     ap.add_argument("--no-secondary", action="store_true", help="skip the other workloads' lines")
     ap.add_argument("--cpu-child", action="store_true", help=argparse.SUPPRESS)
     ap.add_argument("--cpu-out", default="", help=argparse.SUPPRESS)
+    ap.add_argument("--cpu-cores", type=int, default=1, help=argparse.SUPPRESS)
     return ap.parse_args()
 
 
@@ -71,13 +72,36 @@ def measured_traffic(kernel: str):
     return None if k is None else k["traffic_bytes_per_launch"]
 
 
+def host_cores() -> int:
+    """Cores this process may use: its CPU affinity, capped by OMP_NUM_THREADS where the host
+    sets it (the GPU machine gives each GPU a share of its cores that way)."""
+    n = len(os.sched_getaffinity(0))
+    try:
+        n = min(n, int(os.environ.get("OMP_NUM_THREADS", n)))
+    except ValueError:
+        pass
+    return max(1, n)
+
+
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(args, gpu_solve=None):
-    """The oracle (float64 numpy, one thread) solving the data map of the workload and two
-    simulations, timed at the benchmark's tolerance.  The child also writes those maps with the
-    oracle's MAP at 1e-10 (untimed); gpu_solve(maps) -> (fields, maps, stats) solves the same
-    data on the GPU at the benchmark's tolerance, and the accuracy beside the throughput is the
-    GPU against that reference (field relative L2; per-pixel map error on observed and on
-    masked pixels, relative to the largest reference pixel)."""
+    """The oracle (float64 numpy, one thread per process) on the host: solves of the data map
+    and fiducial simulations of the workload at the benchmark's tolerance, on every core this
+    process may use (one independent solve per process, all started together) and on one core.
+    The child also writes three maps with the oracle's MAP at 1e-10 (untimed);
+    gpu_solve(maps) -> (fields, maps, stats) solves the same data on the GPU at the benchmark's
+    tolerance, and the accuracy beside the throughput is the GPU against that reference (field
+    relative L2; per-pixel map error on observed and on masked pixels, relative to the largest
+    reference pixel)."""
     import tempfile
 
     import numpy as np
@@ -85,7 +109,7 @@ def cpu_baseline(args, gpu_solve=None):
     with tempfile.TemporaryDirectory() as tmp:
         out = os.path.join(tmp, "ref.npz")
         cmd = [sys.executable, os.path.abspath(__file__), "--cpu-child", "--n", str(args.n), "--tol", str(args.tol),
-               "--m", str(args.m), "--seed", str(args.seed), "--cpu-out", out]
+               "--m", str(args.m), "--seed", str(args.seed), "--cpu-out", out, "--cpu-cores", str(host_cores())]
         r = subprocess.run(cmd, capture_output=True, text=True, env=env, timeout=900)
         if r.returncode != 0:
             return {"error": r.stderr[-400:]}
@@ -109,31 +133,70 @@ def cpu_baseline(args, gpu_solve=None):
     return res
 
 
-def cpu_child(args):
-    import numpy as np
-
+def _cpu_maps(args, idx):
+    """Map idx of the CPU sample: 0 the data map, i > 0 fiducial simulation i - 1 (Philox)."""
     import oracle as O
     from paper_1810_00503_amd import workloads as WL
     wl = WL.shear_eb(args.n)
     S_true = O.prior_S(wl.pshape, wl.band, wl.theta_true)
     S = O.prior_S(wl.pshape, wl.band, wl.theta_fid)
-    # the data map (Philox stream 0 of the data seed) and the first two fiducial simulations
-    maps = [O.simulate(O.philox.draws_for_sims(args.seed, [0], wl.n, wl.ncomp)[0], S_true, wl.W)]
-    for i in range(2):
-        maps.append(O.simulate(O.philox.draws_for_sims(args.seed + 1, [i], wl.n, wl.ncomp)[0], S, wl.W))
+    if idx == 0:
+        d = O.simulate(O.philox.draws_for_sims(args.seed, [0], wl.n, wl.ncomp)[0], S_true, wl.W)
+    else:
+        d = O.simulate(O.philox.draws_for_sims(args.seed + 1, [idx - 1], wl.n, wl.ncomp)[0], S, wl.W)
+    return wl, S, d
+
+
+def _cpu_worker(args, idx, barrier, q):
+    import oracle as O
+    wl, S, d = _cpu_maps(args, idx)
+    barrier.wait()
     t0 = time.perf_counter()
-    its = [O.lbfgs_solve(d, wl.W, S, m=args.m, tol=args.tol)["iters"] for d in maps]
+    r = O.lbfgs_solve(d, wl.W, S, m=args.m, tol=args.tol)
+    q.put((idx, t0, time.perf_counter(), r["iters"]))
+
+
+def cpu_child(args):
+    import multiprocessing as mp
+
+    import numpy as np
+
+    import oracle as O
+    # all cores: one independent solve per process, started together (fork: this process never
+    # touches the GPU)
+    P = max(1, args.cpu_cores)
+    ctxm = mp.get_context("fork")
+    barrier = ctxm.Barrier(P)
+    q = ctxm.Queue()
+    procs = [ctxm.Process(target=_cpu_worker, args=(args, i, barrier, q)) for i in range(P)]
+    for p in procs:
+        p.start()
+    res = [q.get() for _ in range(P)]
+    for p in procs:
+        p.join()
+    t_start = min(r[1] for r in res)
+    t_end = max(r[2] for r in res)
+    par = P / (t_end - t_start)
+    # one core: the data map and the first two fiducial simulations one after another
+    maps = [_cpu_maps(args, i) for i in range(3)]
+    t0 = time.perf_counter()
+    its = [O.lbfgs_solve(d, wl.W, S, m=args.m, tol=args.tol)["iters"] for wl, S, d in maps]
     dt = time.perf_counter() - t0
     if args.cpu_out:   # the reference for the accuracy line (untimed)
+        wl = maps[0][0]
         ref = {"count": len(maps), "observed": wl.W > 0}
-        for i, d in enumerate(maps):
+        for i, (wl, S, d) in enumerate(maps):
             sr = O.lbfgs_solve(d, wl.W, S, m=args.m, tol=1e-10, max_iter=50000)["s"]
             ref[f"d{i}"], ref[f"s{i}"], ref[f"x{i}"] = d, sr, O.forward(sr)
         np.savez(args.cpu_out, **ref)
-    print(json.dumps({"value": len(maps) / dt, "unit": "solves/s", "cores": 1, "kind": "oracle",
-                      "sample": f"{len(maps)} MAP solves (the {args.n}^2 E/B shear data map and 2 fiducial "
-                                f"simulations) to {args.tol:g} rel. grad, float64 numpy on 1 thread, "
-                                f"iterations {its}, {dt:.1f} s"}))
+    print(json.dumps({"value": round(par, 4), "unit": "solves/s", "cores": P, "kind": "oracle",
+                      "cpu_model": cpu_model(), "nproc": os.cpu_count(),
+                      "one_core_solves_per_s": round(len(maps) / dt, 4),
+                      "sample": f"{P} independent {args.n}^2 E/B shear MAP solves (the data map and "
+                                f"{P - 1} fiducial simulations) to {args.tol:g} rel. grad, float64 numpy, one "
+                                f"process per core started together, {t_end - t_start:.1f} s wall, iterations "
+                                f"{sorted(r[3] for r in res)}; one core: 3 of them in {dt:.1f} s "
+                                f"(iterations {its})"}))
 
 
 def secondary_workloads(args):
@@ -239,6 +302,49 @@ def secondary_workloads(args):
     popts = wf.LbfgsOpts(m=args.m, rel_grad_tol=args.tol, max_iter=4000, precond=1)
     out["cmb1024_maps"] = solve_line("1024^2 CMB, preconditioned L-BFGS", [base.with_data(d[i]) for i in range(16)],
                                      popts)
+    # the paper's method on the same maps: no preconditioner (same stop test)
+    uopts = wf.LbfgsOpts(m=args.m, rel_grad_tol=args.tol, max_iter=20000)
+    out["cmb1024_maps_unpreconditioned"] = solve_line("1024^2 CMB, L-BFGS without preconditioner",
+                                                      [base.with_data(d[i]) for i in range(16)], uopts)
+    # 1024^2 CMB band powers (40 linear bands): N_sim = 6 at the 1e-6 stop (247 solves per
+    # estimate), and N_sim = 1 with float64 refinement to 3e-11 (42 solves; the stop that gives
+    # maps within 1e-5 on this spectrum); both extrapolated to N_sim = 256 (10497 solves, in
+    # chunks of 256) by solve count
+    prob4 = base.with_data(d[0])
+    nsim4 = 6
+    ns4 = 1 + nsim4 * (1 + wl.nbands)
+    (_, _, _, _, rc4), dt4 = timed(lambda: wf.bandpower_qe(prob4, nsim4, 4201, opts=popts))
+    ropts = wf.LbfgsOpts(m=args.m, rel_grad_tol=args.tol, max_iter=4000, precond=1, refine=4, refine_tol=3e-11)
+    ns4r = 1 + 1 * (1 + wl.nbands)
+    wf.bandpower_qe(prob4, 1, 4201, opts=popts)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, _, _, _, rc4r = wf.bandpower_qe(prob4, 1, 4201, opts=ropts)
+    torch.cuda.synchronize()
+    dt4r = time.perf_counter() - t0
+    n256 = 1 + 256 * (1 + wl.nbands)
+    line4 = {"workload": f"1024^2 CMB, {wl.nbands} linear bands, preconditioned L-BFGS",
+             "nsim": nsim4, "solves_per_estimate": ns4, "seconds": round(dt4, 3), "solves_per_s": round(ns4 / dt4, 1),
+             "all_converged": rc4 == wf.WF_OK,
+             "refined": {"nsim": 1, "refine_tol": 3e-11, "solves_per_estimate": ns4r, "seconds": round(dt4r, 3),
+                         "solves_per_s": round(ns4r / dt4r, 1), "all_converged": rc4r == wf.WF_OK},
+             "extrapolated_nsim256": {"solves": n256, "estimates_per_s_1e-6": round(ns4 / dt4 / n256, 5),
+                                      "estimates_per_s_refined": round(ns4r / dt4r / n256, 5)}}
+    # the refined solve of the committed oracle reference's data map (the same white normals,
+    # simulated here in float32) against that reference
+    gpath = os.path.join(ROOT, "tests", "golden", "cmb1024_map.npy")
+    if os.path.exists(gpath):
+        gmeta = json.load(open(gpath.replace(".npy", ".json")))
+        seed_g = int(gmeta["data"].split("white_draws(1024, 1, 1, ")[1].split(")")[0])
+        dr = torch.tensor(WL.white_draws(1024, 1, 1, seed_g), dtype=torch.float32, device=dev)
+        dg = wf.wf_simulate(base, 1, 0, draws=dr, theta_true=wl.theta_true)[0]
+        sg, _, stg, _ = wf.map_wf_solve([base.with_data(dg)], ropts)
+        ref = np.load(gpath).astype(np.complex128)
+        got = sg[0].cpu().numpy().astype(np.complex128)
+        line4["refined_map_vs_oracle"] = {"field_rel_l2": float(np.linalg.norm(got - ref) / np.linalg.norm(ref)),
+                                          "iters": stg[0].iters, "rel_grad": stg[0].rel_grad,
+                                          "reference": "tests/golden/cmb1024_map.npy (oracle MAP to 1e-11)"}
+    out["cmb1024_bandpowers"] = line4
     # convergence by scale of one CMB map (appendix B): reference 1e-6, looser 1e-2 .. 1e-4
     ctols = [1e-2, 1e-3, 1e-4]
     (cpow, cerr, ccv, cits, _, _), dt_c = timed(lambda: wf.convergence_by_band(base.with_data(d[0]), ctols, popts))
@@ -264,6 +370,32 @@ def secondary_workloads(args):
     line["plain_solves_per_s"] = round(len(probs) / dtp, 2)
     line["plain_converged"] = f"{sum(r[2][0].status == wf.WF_SOLVE_CONVERGED for r in res)}/{len(probs)}"
     line["speedup_batched_vs_plain"] = round(line["solves_per_s"] / line["plain_solves_per_s"], 2)
+    # band-power estimates of the same 96 maps (one simulation each, every Fisher column): all
+    # estimates' solves shared among batched solves, against one bandpower_qe call per map
+    nsol = sum(2 + w.nbands for w in wls)
+    # untimed first calls: the tiles of every (side, components, batch-size bucket) class are
+    # tuned on a context's first solve of it, once for the shared batch and once per map kind
+    # and side for the per-map path
+    wf.bandpower_qe_batch(probs, 1, 5300, opts=popts)
+    seen = set()
+    for i, (w, p) in enumerate(zip(wls, probs)):
+        if (w.n, w.ncomp, w.nbands) not in seen:
+            seen.add((w.n, w.ncomp, w.nbands))
+            wf.bandpower_qe(p, 1, 5300 + i, opts=popts)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, _, _, _, rcb = wf.bandpower_qe_batch(probs, 1, 5300, opts=popts)
+    torch.cuda.synchronize()
+    dtb = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    rcs = [wf.bandpower_qe(p, 1, 5300 + i, opts=popts)[4] for i, p in enumerate(probs)]
+    torch.cuda.synchronize()
+    dtm = time.perf_counter() - t0
+    line["bandpower_estimates"] = {"nsim": 1, "solves": nsol, "batched_estimates_per_s": round(len(probs) / dtb, 3),
+                                   "per_map_estimates_per_s": round(len(probs) / dtm, 3),
+                                   "batched_solves_per_s": round(nsol / dtb, 1),
+                                   "speedup_batched_vs_per_map": round(dtm / dtb, 2),
+                                   "all_converged": rcb == wf.WF_OK and all(r == wf.WF_OK for r in rcs)}
     out["uneven96"] = line
     return out
 
@@ -415,20 +547,26 @@ def main():
     roof_chain = {"bound": "hbm", "kernels": "+".join(chain_k), "achieved": round(ca, 1), "peak": HBM_PEAK_GBS,
                   "unit": "GB/s", "frac": round(ca / HBM_PEAK_GBS, 4), "ms_per_step": round(cm, 3),
                   "bytes_per_step": cb}
+    # the same chain against its algorithmic minimum: per curvature product read p and write Dp
+    # (2 vectors), per exact gradient read w and d and write g (3 vectors); W and the prior tables
+    # are shared by the batch (one field vector = ncomp n^2 float32 = the [ncomp][n][n/2] complex field)
+    vb = 2 * args.n * args.n * 4
+    alg = sum((2.0 * x.iters + 3.0 * x.ngrad) * vb for x in st_b)
+    aa = alg / (cm * 1e-3) / 1e9 if cm > 0 else 0.0
+    roof_chain["algorithmic_bytes_per_step"] = alg
+    roof_chain["algorithmic_GBps"] = round(aa, 1)
+    roof_chain["algorithmic_frac"] = round(aa / HBM_PEAK_GBS, 4)
+    # counting as algorithmic also the L-BFGS Gram reads that the column-forward pass does for
+    # the solver (g and the other kept Dp_j: min(k, m) vectors at iteration k), which the
+    # vector algebra would otherwise need in a pass of its own
+    gram = sum(sum(min(k, args.m) for k in range(x.iters)) * vb for x in st_b)
+    ag = (alg + gram) / (cm * 1e-3) / 1e9 if cm > 0 else 0.0
+    roof_chain["algorithmic_with_gram_bytes_per_step"] = alg + gram
+    roof_chain["algorithmic_with_gram_frac"] = round(ag / HBM_PEAK_GBS, 4)
 
-    # measured copy ceiling (context for the roofline): device-to-device copy of 2 GiB
-    src = torch.empty(512 * 1024 * 1024, dtype=torch.float32, device=dev)
-    dst = torch.empty_like(src)
-    dst.copy_(src)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(5):
-        dst.copy_(src)
-    e1.record()
-    torch.cuda.synchronize()
-    copy_gbs = 5 * 2 * src.numel() * 4 / (e0.elapsed_time(e1) * 1e-3) / 1e9
-    del src, dst
-    roof["copy_ceiling_GBps"] = round(copy_gbs, 1)
+    # measured copy ceiling (context for the roofline): the library's streaming copy of 2 GiB
+    roof["copy_ceiling_GBps"] = round(wf.copy_bandwidth(2 * 1024 ** 3, 5), 1)
+    roof_chain["copy_ceiling_GBps"] = roof["copy_ceiling_GBps"]
 
     def gpu_solve(ds):
         probs = [base.with_data(torch.tensor(np.asarray(d), dtype=torch.float32, device=dev)) for d in ds]

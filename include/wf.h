@@ -185,6 +185,19 @@ int bandpower_qe(wf_ctx* ctx, const wf_problem* prob, int32_t nsim, uint64_t see
                  const wf_lbfgs_opts* opts, double* theta_hat, double* E, double* b, double* F,
                  void* stream);
 
+/* The quadratic estimate of each of nprob maps (sec. 2.3-2.5, as bandpower_qe with every
+ * Fisher column simulated), all of their solves shared among batched solves: per map the
+ * data map, nsim fiducial and nsim * nbands_i boosted simulations, map after map, in chunks
+ * of at most 256 solves, each chunk one batched solve (maps of different n, ncomp or dtype
+ * form classes of an uneven batch).  Map i draws its simulations from the Philox key
+ * seed + i (the stream of bandpower_qe(probs[i], nsim, seed + i)); external draws are not
+ * taken.  Results per map equal bandpower_qe's up to the rounding of the transforms.
+ *   theta_hat  HOST [nprob] of HOST [nbands_i] outputs;
+ *   E, b, F    nullable HOST [nprob] of nullable HOST [nbands_i] ([nbands_i^2] for F).  */
+int bandpower_qe_batch(wf_ctx* ctx, const wf_problem* probs, int32_t nprob, int32_t nsim, uint64_t seed,
+                       const wf_lbfgs_opts* opts, double* const* theta_hat, double* const* E, double* const* b,
+                       double* const* F, void* stream);
+
 /* B-mode band powers with the E->B leakage treated as a bias (appendix C): nsim
  * simulations drawn with the fiducial amplitudes except the bands b_bands (the B bands),
  * which are set to 0, give b_B = <E_B> (noise bias plus leakage); the B block F_BB of the
@@ -333,6 +346,13 @@ int wf_get_chain_tiles(wf_ctx* ctx, int32_t n, int32_t ncomp, int32_t dtype, int
  * algorithmic bytes (counted on the device for every launch).  Kinds are named by
  * wf_kernel_kind_name(k) for k in [0, wf_kernel_kinds()).                            */
 int wf_set_profiling(wf_ctx* ctx, int32_t on);
+
+/* instrumentation: the HBM streaming-copy reference.  Copies `bytes` (a positive multiple of
+ * 16; device buffers src, dst) reps times with a hand-written copy kernel (16-byte vector
+ * loads, each thread's loads issued before its stores) on the context's stream after one
+ * untimed copy, timed with HIP events; *gbps = 2 * bytes * reps / time (read + write),
+ * in 1e9 bytes per second.                                                                */
+int wf_copy_bandwidth(wf_ctx* ctx, const void* src, void* dst, uint64_t bytes, int32_t reps, double* gbps);
 int wf_kernel_kinds(void);
 const char* wf_kernel_kind_name(int32_t kind);
 int wf_get_kernel_stats(wf_ctx* ctx, int64_t* launches, double* ms, double* bytes);

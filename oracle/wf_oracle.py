@@ -440,7 +440,8 @@ def _boosted_S(pshape, band, theta_fid, lb, factor):
     return prior_S(pshape, band, th)
 
 
-def sim_fisher(W, pshape, band, theta_fid, nbands, draws, m=10, tol=1e-8, max_iter=20000, return_var=False):
+def sim_fisher(W, pshape, band, theta_fid, nbands, draws, m=10, tol=1e-8, max_iter=20000, return_var=False,
+               precond=False):
     """Simulation noise bias and Fisher matrix (sec. 2.4):
     b_l = < E_l(Theta_fid, s_hat[d_sim]) > over sims drawn at Theta_fid (eq. blmv);
     F_ll' Delta_l' = < E_l(s_hat[d_sim at Theta_fid + Delta_l' e_l']) - E_l(s_hat[d_sim]) >
@@ -448,7 +449,8 @@ def sim_fisher(W, pshape, band, theta_fid, nbands, draws, m=10, tol=1e-8, max_it
     using the fiducial prior; F is symmetrised.  Returns (b, F, E_sims[nsim][nbands]),
     and with return_var also F_var: per entry the variance of the mean, i.e. the sample
     variance over the simulations of each one's symmetrised estimate divided by nsim
-    (zero with a single simulation)."""
+    (zero with a single simulation).  precond: the solves use the diagonal preconditioner
+    (same minima)."""
     theta_fid = np.asarray(theta_fid, np.float64)
     S_fid = prior_S(pshape, band, theta_fid)
     nsim = draws.shape[0]
@@ -456,12 +458,14 @@ def sim_fisher(W, pshape, band, theta_fid, nbands, draws, m=10, tol=1e-8, max_it
     Fs = np.zeros((nsim, nbands, nbands))
     for i in range(nsim):
         d0 = simulate(draws[i], S_fid, W)
-        E0 = band_E(lbfgs_solve(d0, W, S_fid, m, tol, max_iter)["s"], S_fid, band, theta_fid, nbands)
+        E0 = band_E(lbfgs_solve(d0, W, S_fid, m, tol, max_iter, precond=precond)["s"], S_fid, band, theta_fid,
+                    nbands)
         Es[i] = E0
         for l2 in range(nbands):
             S2 = _boosted_S(pshape, band, theta_fid, l2, 2.0)
             d2 = simulate(draws[i], S2, W)
-            E2 = band_E(lbfgs_solve(d2, W, S_fid, m, tol, max_iter)["s"], S_fid, band, theta_fid, nbands)
+            E2 = band_E(lbfgs_solve(d2, W, S_fid, m, tol, max_iter, precond=precond)["s"], S_fid, band, theta_fid,
+                        nbands)
             Fs[i, :, l2] = (E2 - E0) / theta_fid[l2]
     b = Es.mean(0)
     F = Fs.mean(0)
@@ -472,19 +476,31 @@ def sim_fisher(W, pshape, band, theta_fid, nbands, draws, m=10, tol=1e-8, max_it
     return b, 0.5 * (F + F.T), Es, Fvar
 
 
+FISHER_FLOOR = 1e-9
+
+
 def newton_update(theta_fid, F, E, b):
-    """Theta_hat = Theta_fid + F^-1 (E - b) (sec. 2.3, eq. eq:wfmv)."""
-    return np.asarray(theta_fid, np.float64) + np.linalg.solve(F, E - b)
+    """Theta_hat = Theta_fid + F^-1 (E - b) (sec. 2.3, eq. eq:wfmv), on the bands that carry
+    information: a band whose Fisher diagonal is not positive or is below FISHER_FLOOR of the
+    largest (its E does not respond to its amplitude, e.g. beyond a spectrum's cut-off) keeps
+    its fiducial amplitude and the step is solved on the other bands."""
+    theta_fid = np.asarray(theta_fid, np.float64)
+    d = np.diag(F)
+    use = np.nonzero(d > FISHER_FLOOR * max(d.max(), 0.0))[0]
+    out = theta_fid.copy()
+    if use.size:
+        out[use] = theta_fid[use] + np.linalg.solve(F[np.ix_(use, use)], (E - b)[use])
+    return out
 
 
-def bandpower_qe(d, W, pshape, band, theta_fid, nbands, draws, m=10, tol=1e-8, max_iter=20000):
+def bandpower_qe(d, W, pshape, band, theta_fid, nbands, draws, m=10, tol=1e-8, max_iter=20000, precond=False):
     """Quadratic band-power estimate (procedure summary, sec. 2.5): MAP of the data,
     E_l of it, simulation b and F, Newton step.  Returns (theta_hat, E, b, F)."""
     theta_fid = np.asarray(theta_fid, np.float64)
     S_fid = prior_S(pshape, band, theta_fid)
-    sh = lbfgs_solve(d, W, S_fid, m, tol, max_iter)["s"]
+    sh = lbfgs_solve(d, W, S_fid, m, tol, max_iter, precond=precond)["s"]
     E = band_E(sh, S_fid, band, theta_fid, nbands)
-    b, F, _ = sim_fisher(W, pshape, band, theta_fid, nbands, draws, m, tol, max_iter)
+    b, F, _ = sim_fisher(W, pshape, band, theta_fid, nbands, draws, m, tol, max_iter, precond=precond)
     return newton_update(theta_fid, F, E, b), E, b, F
 
 

@@ -23,12 +23,12 @@ from ._lib import (WF_ADJ_GRAD, WF_ADJ_METRIC, WF_F32, WF_F64, WF_MASK, WF_NOT_C
 
 __all__ = [
     "load", "Context", "Problem", "LbfgsOpts", "SolveStats", "context", "map_wf_solve", "wf_simulate",
-    "sim_fisher", "sim_fisher_rows", "bandpower_qe", "bandpower_iterate", "bmode_leakage_qe", "posterior_error",
+    "sim_fisher", "sim_fisher_rows", "bandpower_qe", "bandpower_qe_batch", "bandpower_iterate", "bmode_leakage_qe", "posterior_error",
     "convergence_by_band",
     "wf_forward",
     "wf_adjoint",
     "wf_chi2_grad", "wf_hvp", "wf_hvp_noalloc", "wf_band_E", "wf_chi2_dtheta",
-    "WFError", "kernel_stats", "reset_kernel_stats", "set_profiling", "autograd", "set_chain_tiles",
+    "WFError", "kernel_stats", "reset_kernel_stats", "set_profiling", "autograd", "set_chain_tiles", "copy_bandwidth",
     "get_chain_tiles",
 ]
 
@@ -318,6 +318,32 @@ def bandpower_qe(problem: Problem, nsim: int, seed: int, draws=None, opts: Lbfgs
     return th, E, b, F, rc
 
 
+def bandpower_qe_batch(problems: Sequence[Problem], nsim: int, seed: int, opts: LbfgsOpts | None = None,
+                       ctx: Context | None = None):
+    """Quadratic band-power estimates of several maps (uneven sizes allowed) with all of their
+    solves shared among batched solves; map i draws its simulations from Philox key seed + i.
+    Returns (theta_hat list, E list, b list, F list, rc) of numpy arrays."""
+    problems = list(problems)
+    P = len(problems)
+    dev = problems[0].device_index() if P else 0
+    cx = ctx or context(dev)
+    th = [np.zeros(p.nbands) for p in problems]
+    Es = [np.zeros(p.nbands) for p in problems]
+    bs = [np.zeros(p.nbands) for p in problems]
+    Fs = [np.zeros((p.nbands, p.nbands)) for p in problems]
+    dpp = C.POINTER(C.c_double)
+
+    def arr(xs):
+        return (dpp * max(P, 1))(*[x.ctypes.data_as(dpp) for x in xs])
+
+    cps = (L.WfProblem * max(P, 1))(*[p.c() for p in problems])
+    o = _opts(opts)
+    rc = cx.lib.bandpower_qe_batch(cx.h, cps, P, nsim, C.c_uint64(seed), C.byref(o), arr(th), arr(Es), arr(bs),
+                                   arr(Fs), _stream(dev))
+    cx.check(rc)
+    return th, Es, bs, Fs, rc
+
+
 def _rows_groups(problem, rows, groups):
     """int32 host arrays (or None) for the sampled-row calls."""
     nb = problem.nbands
@@ -580,6 +606,20 @@ def wf_chi2_dtheta(problem: Problem, s, gout=None, ctx: Context | None = None):
                                    go.ctypes.data_as(C.POINTER(C.c_double)) if go is not None else None,
                                    out.ctypes.data_as(C.POINTER(C.c_double)), _stream(dev)))
     return out
+
+
+def copy_bandwidth(nbytes: int = 2 * 1024 ** 3, reps: int = 5, device: int = 0, ctx: Context | None = None) -> float:
+    """HBM streaming-copy reference in GB/s (read + write) of the library's copy kernel."""
+    torch = _torch()
+    cx = ctx or context(device)
+    n = nbytes // 16 * 4
+    src = torch.empty(n, dtype=torch.float32, device=f"cuda:{device}")
+    dst = torch.empty_like(src)
+    out = C.c_double()
+    torch.cuda.synchronize()
+    cx.check(cx.lib.wf_copy_bandwidth(cx.h, src.data_ptr(), dst.data_ptr(), C.c_uint64(n * 4), int(reps),
+                                      C.byref(out)))
+    return float(out.value)
 
 
 def set_profiling(on: bool, ctx: Context | None = None):

@@ -17,9 +17,9 @@ WF_NOALLOC_SCRATCH_BYTES = 64 * 1024 * 1024
 
 EXPORTS = [
     "wf_create", "wf_destroy", "wf_last_error", "wf_lbfgs_default", "map_wf_solve", "wf_simulate",
-    "sim_fisher", "sim_fisher_rows", "bandpower_qe", "bandpower_iterate", "bmode_leakage_qe", "posterior_error", "convergence_by_band", "wf_forward", "wf_adjoint", "wf_chi2_grad", "wf_hvp", "wf_hvp_noalloc", "wf_band_E", "wf_chi2_dtheta",
+    "sim_fisher", "sim_fisher_rows", "bandpower_qe", "bandpower_qe_batch", "bandpower_iterate", "bmode_leakage_qe", "posterior_error", "convergence_by_band", "wf_forward", "wf_adjoint", "wf_chi2_grad", "wf_hvp", "wf_hvp_noalloc", "wf_band_E", "wf_chi2_dtheta",
     "wf_set_profiling", "wf_kernel_kinds", "wf_kernel_kind_name", "wf_get_kernel_stats",
-    "wf_reset_kernel_stats", "wf_set_chain_tiles", "wf_get_chain_tiles",
+    "wf_reset_kernel_stats", "wf_set_chain_tiles", "wf_get_chain_tiles", "wf_copy_bandwidth",
 ]
 
 
@@ -74,6 +74,9 @@ def load(path: str | None = None):
     L.bandpower_qe.argtypes = [vp, C.POINTER(WfProblem), i32, C.c_uint64, vp, C.POINTER(WfLbfgsOpts), dp, dp, dp,
                                dp, vp]
     ip = C.POINTER(i32)
+    L.bandpower_qe_batch.argtypes = [vp, C.POINTER(WfProblem), i32, i32, C.c_uint64, C.POINTER(WfLbfgsOpts),
+                                     C.POINTER(dp), C.POINTER(dp), C.POINTER(dp), C.POINTER(dp), vp]
+    L.wf_copy_bandwidth.argtypes = [vp, vp, vp, C.c_uint64, i32, dp]
     L.sim_fisher_rows.argtypes = [vp, C.POINTER(WfProblem), i32, C.c_uint64, vp, C.POINTER(WfLbfgsOpts), ip, i32, ip,
                                   dp, dp, dp, vp]
     L.bandpower_iterate.argtypes = [vp, C.POINTER(WfProblem), i32, C.c_uint64, vp, C.POINTER(WfLbfgsOpts), ip, i32,

@@ -33,6 +33,10 @@ constexpr size_t kAlign = 256;
 constexpr int kNdot = 5 * MMAX + 1;
 constexpr double kSimBudgetBytes = 48.0 * 1024 * 1024 * 1024;   // workspace cap of a sim chunk
 constexpr int kMaxChunk = 256;
+// the band-power estimates of several maps: one uneven batch of up to this many solves and bytes
+// (classes of equal shape then run independently, so no solve waits for a slower map's)
+constexpr double kMultiBudgetBytes = 96.0 * 1024 * 1024 * 1024;
+constexpr int kMaxChunkMulti = 8192;
 // Vectors of one instance are laid out back to back with this many extra bytes between
 // them (an odd multiple of 256 B), so the 2m + 3 streams of a pass do not start at the same
 // offset modulo a large power of two.
@@ -523,9 +527,17 @@ int tune_chain(wf_ctx* ctx, Klass& k, const std::vector<InstDesc>& hd, Job* djob
 // acting on a residual that sits mostly in soft modes: its relative-gradient stop ends between
 // ~1e-5 and ~1e-3 of its start on the CMB maps (against ~2e-8 for a full solve), so a round
 // asks for at most a 1e-3 reduction (which gives more in the float64 gradient) and is capped
-// at twice the iterations of the first solve (at least kRefineMinIter); a round that hits its
-// cap still improves the field and is kept.
-constexpr double kRefineTolMin = 1e-3;
+// at six times the iterations of the first solve (at least kRefineMinIter; each round starts a
+// new history, and on the 1024^2 CMB map a round needs several times the first solve's
+// iterations); a round that hits its cap still improves the field and is kept.
+#ifndef WF_REFINE_TOL_MIN
+#define WF_REFINE_TOL_MIN 1e-3
+#endif
+#ifndef WF_REFINE_ITER_FACTOR
+#define WF_REFINE_ITER_FACTOR 6
+#endif
+constexpr double kRefineTolMin = WF_REFINE_TOL_MIN;
+constexpr int kRefineIterFactor = WF_REFINE_ITER_FACTOR;
 constexpr int kRefineMinIter = 200;
 
 template <typename InitF, typename RunF>
@@ -700,7 +712,7 @@ int refine_f64(wf_ctx* ctx, const wf_lbfgs_opts& o, const std::vector<Klass>& ks
         dd[j].rhs = rf[gi].rhs;
         dd[j].dchi2Tol = 0.0;
         dd[j].tol = live[gi] ? std::max(0.3 * T / rho[gi], kRefineTolMin) : 1e300;
-        dd[j].maxIter = std::min(o.max_iter, std::max(kRefineMinIter, 2 * hs[gi].iter));
+        dd[j].maxIter = std::min(o.max_iter, std::max(kRefineMinIter, kRefineIterFactor * hs[gi].iter));
       }
       HIPCHK(hipMemcpyAsync(ddesc + k.first, dd.data(), sizeof(InstDesc) * dd.size(), hipMemcpyHostToDevice, ctx->cs));
       rc = init_class(k);
@@ -1336,6 +1348,133 @@ int run_qe(wf_ctx* ctx, const wf_problem* p, bool with_data, int nsim, uint64_t 
   return WF_OK;
 }
 
+// The solves of the band-power estimates of several maps (all Fisher columns simulated),
+// shared among batched solves: per map the data map, nsim fiducial simulations and nsim *
+// nbands boosted ones, the maps ordered by size (largest first), cut into chunks of at most
+// kMaxChunkMulti solves and kMultiBudgetBytes of workspace; each chunk is one batched
+// (uneven) solve whose classes of equal shape run independently.  Map i's simulations use
+// the Philox key seed + i.  Edata[i] [nb_i], E0[i] [nsim][nb_i],
+// E2[i] [nsim][nb_i][nb_i]; notConverged counts solves that did not converge.
+int run_qe_multi(wf_ctx* ctx, const wf_problem* probs, int np, int nsim, uint64_t seed, const wf_lbfgs_opts& o,
+                 std::vector<std::vector<double>>& Edata, std::vector<std::vector<double>>& E0,
+                 std::vector<std::vector<double>>& E2, int& notConverged) {
+  struct MEnt {
+    int prob;
+    SimEntry e;
+  };
+  std::vector<MEnt> all;
+  Edata.assign(np, {});
+  E0.assign(np, {});
+  E2.assign(np, {});
+  std::vector<int> order(np);
+  for (int i = 0; i < np; ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+    return (int64_t)probs[a].ncomp * probs[a].n * probs[a].n > (int64_t)probs[b].ncomp * probs[b].n * probs[b].n;
+  });
+  for (int i : order) {
+    const int nb = probs[i].nbands;
+    Edata[i].assign(nb, 0.0);
+    E0[i].assign((size_t)nsim * nb, 0.0);
+    E2[i].assign((size_t)nsim * nb * nb, 0.0);
+    all.push_back({i, {0, 0, -1, -1}});
+    for (int s = 0; s < nsim; ++s) {
+      all.push_back({i, {1, s, -1, -1}});
+      for (int l = 0; l < nb; ++l) all.push_back({i, {2, s, l, l}});
+    }
+  }
+  notConverged = 0;
+  auto shape = [&](int i, int64_t& L, int64_t& npix, size_t& rs, size_t& eb) {
+    const wf_problem& p = probs[i];
+    L = (int64_t)p.ncomp * p.n * (p.n / 2);
+    npix = (int64_t)p.ncomp * p.n * p.n;
+    rs = rsize_of(p.dtype);
+    eb = esize_of(p.dtype);
+  };
+  size_t off = 0;
+  while (off < all.size()) {
+    // the chunk: as many entries as the instance and workspace caps allow
+    size_t cnt = 0;
+    double bytes = 0.0;
+    while (off + cnt < all.size() && cnt < (size_t)kMaxChunkMulti) {
+      int64_t L, npix;
+      size_t rs, eb;
+      shape(all[off + cnt].prob, L, npix, rs, eb);
+      const double per = (double)(3 + 2 * o.m) * L * eb + (double)npix * rs + (double)L * eb;
+      if (cnt > 0 && bytes + per > kMultiBudgetBytes) break;
+      bytes += per;
+      ++cnt;
+    }
+    // workspace of the simulations: prior tables of each map in the chunk, jobs, data, intermediates
+    size_t need = 0;
+    for (size_t j = 0; j < cnt;) {
+      const int pi = all[off + j].prob;
+      size_t e = j;
+      while (e < cnt && all[off + e].prob == pi) ++e;
+      int64_t L, npix;
+      size_t rs, eb;
+      shape(pi, L, npix, rs, eb);
+      need += prior_bytes(&probs[pi]) + align_up(sizeof(Job) * (e - j)) + align_up((size_t)npix * rs * (e - j)) +
+              align_up((size_t)L * eb * (e - j));
+      j = e;
+    }
+    int rc = arena_reserve(ctx, ctx->simA, need);
+    if (rc) return rc;
+    std::vector<wf_problem> cp(cnt);
+    for (size_t j = 0; j < cnt;) {
+      const int pi = all[off + j].prob;
+      size_t e = j;
+      while (e < cnt && all[off + e].prob == pi) ++e;
+      int64_t L, npix;
+      size_t rs, eb;
+      shape(pi, L, npix, rs, eb);
+      PriorTab ptrue;
+      rc = build_prior(ctx, ctx->simA, &probs[pi], probs[pi].theta, ptrue);
+      if (rc) return rc;
+      void* dbuf = arena_take(ctx->simA, (size_t)npix * rs * (e - j));
+      void* ybuf = arena_take(ctx->simA, (size_t)L * eb * (e - j));
+      std::vector<SimEntry> ents;
+      for (size_t q = j; q < e; ++q) ents.push_back(all[off + q].e);
+      rc = simulate_entries(ctx, &probs[pi], ents, seed + (uint64_t)pi, nullptr, 0, ptrue, dbuf, ybuf, 2.0);
+      if (rc) return rc;
+      for (size_t q = j; q < e; ++q) {
+        cp[q] = probs[pi];
+        if (all[off + q].e.kind != 0) cp[q].d = (const char*)dbuf + (q - j) * npix * rs;
+      }
+      j = e;
+    }
+    SolveOut so;
+    rc = solve_core(ctx, cp.data(), (int)cnt, o, so);
+    if (rc) return rc;
+    for (size_t j = 0; j < cnt; ++j) notConverged += so.st[j].status != WF_SOLVE_CONVERGED;
+    // band statistics map by map (band_E_solved takes one shape)
+    for (size_t j = 0; j < cnt;) {
+      const int pi = all[off + j].prob;
+      size_t e = j;
+      while (e < cnt && all[off + e].prob == pi) ++e;
+      SolveOut sub;
+      sub.w.assign(so.w.begin() + j, so.w.begin() + e);
+      sub.prior.assign(so.prior.begin() + j, so.prior.begin() + e);
+      std::vector<double> E;
+      rc = band_E_solved(ctx, cp.data() + j, (int)(e - j), sub, E);
+      if (rc) return rc;
+      const int nb = probs[pi].nbands;
+      for (size_t q = j; q < e; ++q) {
+        const double* v = &E[(q - j) * nb];
+        const SimEntry& en = all[off + q].e;
+        if (en.kind == 0)
+          std::copy(v, v + nb, Edata[pi].begin());
+        else if (en.kind == 1)
+          std::copy(v, v + nb, E0[pi].begin() + (size_t)en.sim * nb);
+        else
+          std::copy(v, v + nb, E2[pi].begin() + ((size_t)en.sim * nb + en.col) * nb);
+      }
+      j = e;
+    }
+    off += cnt;
+  }
+  return WF_OK;
+}
+
 // Bias b_l = <E0_l> and the symmetrised Fisher matrix from the simulated columns `cols`
 // (F_ll' from the boosted minus fiducial E of column l', eq. fisher with Delta_l' =
 // theta_l').  The other columns are interpolated in units of D_l, the variance of E0_l
@@ -1448,6 +1587,32 @@ void fisher_variance(const double* theta, int nsim, int nb, const std::vector<do
     }
 }
 
+// Newton step Theta_hat = Theta_fid + F^-1 (E - b) (eq. eq:wfmv) on the bands that carry
+// information: a band whose Fisher diagonal is not positive or is below kFisherFloor of the
+// largest (its E does not respond to its amplitude above the rounding of E, e.g. bands beyond
+// a spectrum's cut-off, whose modes have no signal) keeps its fiducial amplitude, and the step
+// is solved on the others.  Returns false if that system is singular.
+constexpr double kFisherFloor = 1e-9;
+bool newton_step(const double* theta, const std::vector<double>& F, const std::vector<double>& E,
+                 const std::vector<double>& b, int nb, double* out) {
+  double fmax = 0.0;
+  for (int l = 0; l < nb; ++l) fmax = std::max(fmax, F[(size_t)l * nb + l]);
+  std::vector<int> use;
+  for (int l = 0; l < nb; ++l)
+    if (F[(size_t)l * nb + l] > kFisherFloor * fmax) use.push_back(l);
+  for (int l = 0; l < nb; ++l) out[l] = theta[l];
+  const int k = (int)use.size();
+  if (k == 0) return nb == 0;
+  std::vector<double> A((size_t)k * k), x(k);
+  for (int i = 0; i < k; ++i) {
+    x[i] = E[use[i]] - b[use[i]];
+    for (int j = 0; j < k; ++j) A[(size_t)i * k + j] = F[(size_t)use[i] * nb + use[j]];
+  }
+  if (!dense_solve(A, x, k)) return false;
+  for (int i = 0; i < k; ++i) out[use[i]] = theta[use[i]] + x[i];
+  return true;
+}
+
 // Simulated columns and band groups of a sampled-Fisher call: rows strictly increasing in
 // [0, nb), groups nullable (one group) or [nb] ids, every group with a simulated column.
 int parse_rows(wf_ctx* ctx, int nb, const int32_t* rows, int32_t nrows, const int32_t* groups, std::vector<int>& cols,
@@ -1491,10 +1656,7 @@ int qe_estimate(wf_ctx* ctx, const wf_problem* p, bool with_data, int nsim, uint
   hF.assign((size_t)nb * nb, 0.0);
   bias_fisher(p->theta, nsim, nb, cols, grp, E0, E2, hb.data(), hF.data());
   if (!with_data) return WF_OK;
-  std::vector<double> x(nb);
-  for (int l = 0; l < nb; ++l) x[l] = E[l] - hb[l];
-  if (!dense_solve(hF, x, nb)) return fail(ctx, WF_ENONFINITE, "singular Fisher matrix");
-  for (int l = 0; l < nb; ++l) theta_hat[l] = p->theta[l] + x[l];
+  if (!newton_step(p->theta, hF, E, hb, nb, theta_hat)) return fail(ctx, WF_ENONFINITE, "singular Fisher matrix");
   return WF_OK;
 }
 
@@ -1830,6 +1992,62 @@ int bandpower_qe(wf_ctx* ctx, const wf_problem* p, int32_t nsim, uint64_t seed, 
   if (b) std::copy(hb.begin(), hb.end(), b);
   if (F) std::copy(hF.begin(), hF.end(), F);
   return nc ? WF_NOT_CONVERGED : WF_OK;
+}
+
+int bandpower_qe_batch(wf_ctx* ctx, const wf_problem* probs, int32_t nprob, int32_t nsim, uint64_t seed,
+                       const wf_lbfgs_opts* opts, double* const* theta_hat, double* const* E, double* const* b,
+                       double* const* F, void* stream) {
+  if (!ctx) return WF_EINVAL;
+  if (nprob < 0 || nprob > 4096 || (nprob > 0 && (!probs || !theta_hat)))
+    return fail(ctx, WF_EINVAL, "bad nprob / null arrays");
+  if (nsim < 1) return fail(ctx, WF_EINVAL, "need nsim >= 1");
+  for (int i = 0; i < nprob; ++i) {
+    int rc = check_problem(ctx, &probs[i], true);
+    if (rc) return rc;
+    if (!theta_hat[i]) return fail(ctx, WF_EINVAL, "null theta_hat entry");
+    for (int l = 0; l < probs[i].nbands; ++l)
+      if (!(probs[i].theta[l] > 0)) return fail(ctx, WF_EINVAL, "fiducial band amplitudes must be > 0");
+  }
+  if (nprob == 0) return WF_OK;
+  wf_lbfgs_opts o;
+  fill_opts(opts, o);
+  StreamScope ss(ctx, stream);
+  std::vector<std::vector<double>> Ed, E0, E2;
+  int nc = 0;
+  int rc = run_qe_multi(ctx, probs, nprob, nsim, seed, o, Ed, E0, E2, nc);
+  if (rc) return rc;
+  for (int i = 0; i < nprob; ++i) {
+    const int nb = probs[i].nbands;
+    std::vector<int> cols(nb), grp(nb, 0);
+    for (int l = 0; l < nb; ++l) cols[l] = l;
+    std::vector<double> hb(nb), hF((size_t)nb * nb);
+    bias_fisher(probs[i].theta, nsim, nb, cols, grp, E0[i], E2[i], hb.data(), hF.data());
+    if (!newton_step(probs[i].theta, hF, Ed[i], hb, nb, theta_hat[i]))
+      return fail(ctx, WF_ENONFINITE, "singular Fisher matrix of map " + std::to_string(i));
+    if (E && E[i]) std::copy(Ed[i].begin(), Ed[i].end(), E[i]);
+    if (b && b[i]) std::copy(hb.begin(), hb.end(), b[i]);
+    if (F && F[i]) std::copy(hF.begin(), hF.end(), F[i]);
+  }
+  return nc ? WF_NOT_CONVERGED : WF_OK;
+}
+
+int wf_copy_bandwidth(wf_ctx* ctx, const void* src, void* dst, uint64_t bytes, int32_t reps, double* gbps) {
+  if (!ctx) return WF_EINVAL;
+  if (!src || !dst || !gbps || bytes == 0 || bytes % 16 != 0 || reps < 1)
+    return fail(ctx, WF_EINVAL, "need src, dst, gbps, bytes a positive multiple of 16 and reps >= 1");
+  (void)hipSetDevice(ctx->dev);
+  hipEvent_t e0 = ev_get(ctx), e1 = ev_get(ctx);
+  HIPCHK(stream_copy_launch(src, dst, bytes, ctx->cs));   // warm-up
+  HIPCHK(hipEventRecord(e0, ctx->cs));
+  for (int r = 0; r < reps; ++r) HIPCHK(stream_copy_launch(src, dst, bytes, ctx->cs));
+  HIPCHK(hipEventRecord(e1, ctx->cs));
+  HIPCHK(hipEventSynchronize(e1));
+  float ms = 0.f;
+  HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+  ctx->evPool.push_back(e0);
+  ctx->evPool.push_back(e1);
+  *gbps = ms > 0.f ? 2.0 * (double)bytes * reps / (ms * 1e-3) / 1e9 : 0.0;
+  return WF_OK;
 }
 
 int wf_forward(wf_ctx* ctx, const wf_problem* p, int32_t batch, const void* s, void* x, int32_t flags,

@@ -80,6 +80,16 @@ __device__ __forceinline__ T gld(const T* base, uint32_t i) {
   __builtin_memcpy(&r, &v, sizeof(T));
   return r;
 }
+// the same load with the non-temporal hint, for streams that a pass reads once and that no
+// cache can hold until they are read again (the solver's history vectors)
+template <typename T>
+__device__ __forceinline__ T gldnt(const T* base, uint32_t i) {
+  using S = typename GStore<T>::type;
+  const S v = __builtin_nontemporal_load((gptr<const S>)((gptr<const char>)(const char*)base + i * (uint32_t)sizeof(T)));
+  T r;
+  __builtin_memcpy(&r, &v, sizeof(T));
+  return r;
+}
 template <typename T>
 __device__ __forceinline__ void gst(T* base, uint32_t i, const T& x) {
   using S = typename GStore<T>::type;

@@ -90,5 +90,7 @@ int band_nblk(int64_t L);
 // right-hand side with per-block norm partials of a float64 gradient (nblk blocks per job)
 hipError_t convert_launch(const CvtJob* jobs, int count, int64_t maxn, hipStream_t s);
 hipError_t refine_rhs_launch(const RhsJob* jobs, int count, int nblk, hipStream_t s);
+// streaming copy of `bytes` (a multiple of 16) for the bandwidth reference
+hipError_t stream_copy_launch(const void* src, void* dst, uint64_t bytes, hipStream_t s);
 
 }  // namespace wf

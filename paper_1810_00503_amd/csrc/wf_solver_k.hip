@@ -177,4 +177,12 @@ hipError_t refine_rhs_launch(const RhsJob* jobs, int count, int nblk, hipStream_
   return hipGetLastError();
 }
 
+hipError_t stream_copy_launch(const void* src, void* dst, uint64_t bytes, hipStream_t s) {
+  const uint64_t n = bytes / 16;
+  const uint64_t blocks = (n + 256 * COPY_U - 1) / (256 * COPY_U);
+  if (blocks == 0 || blocks > 0x7fffffffull) return hipErrorInvalidValue;
+  k_stream_copy<<<dim3((unsigned)blocks), 256, 0, s>>>((const float4*)src, (float4*)dst, n);
+  return hipGetLastError();
+}
+
 }  // namespace wf

@@ -221,10 +221,11 @@ def shear_workload(n: int, seed: int, nbands_e: int = 10, nbands_b: int = 10, si
 
 def cmb_workload(n: int, seed: int, nbands: int = 40, holes: int = 300, gal_frac: float = 0.10,
                  depth_uk_arcmin: float = 6.0, theta_pix_arcmin: float = 1.7,
-                 randomize_fid: bool = True, name="cmb") -> Workload:
+                 randomize_fid: bool = True, name="cmb", target_mask: float | None = None) -> Workload:
     """Flat-sky CMB temperature: point-source holes (r 3-10 px, scaled below 1024),
     a galactic-cut band of gal_frac of the rows, scan-striped noise
-    sigma^2 = (depth/theta_pix)^2 <hits>/hits with hits = 1 + |sin(x/50)| Poisson(20)."""
+    sigma^2 = (depth/theta_pix)^2 <hits>/hits with hits = 1 + |sin(x/50)| Poisson(20).
+    target_mask: further holes until that masked fraction (- 2 %) is reached."""
     rng = np.random.Generator(np.random.PCG64(seed))
     sc = min(1.0, n / 1024.0)
     nh = max(1, int(round(holes * (n / 1024.0) ** 2)))
@@ -232,6 +233,8 @@ def cmb_workload(n: int, seed: int, nbands: int = 40, holes: int = 300, gal_frac
     w = max(1, int(round(gal_frac * n)))
     y0 = int(rng.integers(0, n - w + 1))
     m[y0:y0 + w, :] = False
+    if target_mask is not None:
+        m = _holes_until(n, rng, m, target_mask - 0.02, max(1.0, 3.0 * sc), max(1.5, 10.0 * sc))
     xx = np.arange(n, dtype=np.float64)[None, :]
     hits = 1.0 + np.abs(np.sin(xx / 50.0)) * rng.poisson(20.0, (n, n))
     var = (depth_uk_arcmin / theta_pix_arcmin) ** 2 * hits.mean() / hits
@@ -291,5 +294,5 @@ def uneven_batch(count: int = 96, sizes=(128, 192, 256, 384, 512, 768, 1024)) ->
         elif kind == 1:
             out.append(shear_workload(n, s, target_mask=frac, name=f"uneven-shear{n}"))
         else:
-            out.append(cmb_workload(n, s, name=f"uneven-cmb{n}"))
+            out.append(cmb_workload(n, s, target_mask=frac, name=f"uneven-cmb{n}"))
     return out

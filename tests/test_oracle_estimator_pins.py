@@ -247,3 +247,26 @@ def test_preconditioned_lbfgs_reaches_the_dense_wiener_filter(ncomp, n):
     assert np.linalg.norm(a["s"] - b["s"]) <= 1e-9 * np.linalg.norm(ref["s"])
     P = O.precond_diag(W, S)
     assert np.all((P > 0) & (P <= 1))
+
+
+def test_newton_step_leaves_uninformative_bands_at_the_fiducial():
+    """A band with no Fisher information (a zero or negative diagonal, or one below 1e-9 of
+    the largest) keeps its fiducial amplitude; the others get the Newton step of the reduced
+    system, which is the full step when F decouples them."""
+    rng = np.random.default_rng(2)
+    A = rng.standard_normal((3, 3))
+    Fi = A @ A.T + 3 * np.eye(3)
+    th = np.array([0.5, 0.8, 1.2, 0.3, 0.9])
+    E, b = rng.uniform(1, 2, 5), rng.uniform(0.5, 1, 5)
+    F = np.zeros((5, 5))
+    keep = [0, 2, 4]
+    F[np.ix_(keep, keep)] = Fi
+    F[1, 1] = -1e-5
+    F[3, 3] = 1e-12 * Fi.max()
+    out = O.newton_update(th, F, E, b)
+    np.testing.assert_allclose(out[[1, 3]], th[[1, 3]], rtol=0, atol=0)
+    np.testing.assert_allclose(out[keep], th[keep] + np.linalg.solve(Fi, (E - b)[keep]), rtol=1e-13)
+    # informative everywhere: the plain step
+    G = Fi.copy()
+    np.testing.assert_allclose(O.newton_update(th[:3], G, E[:3], b[:3]), th[:3] + np.linalg.solve(G, E[:3] - b[:3]),
+                               rtol=1e-13)
