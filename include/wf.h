@@ -334,6 +334,9 @@ int wf_chi2_dtheta(wf_ctx* ctx, const wf_problem* prob, int32_t batch, const voi
  * first float32 solve of a batch of >= 4 maps of a given (n, ncomp, batch-size bucket) it
  * times every supported choice on that batch and keeps the fastest for the context.
  * float64 uses (4, 1, 0, 0), as does a fixed choice that the shape does not support.
+ * Tuned choices persist on disk, keyed by device architecture and compute-unit count: in the
+ * file WF_TUNE_CACHE names (empty: none), else $XDG_CACHE_HOME/libwf/tiles.txt or
+ * ~/.cache/libwf/tiles.txt; wf_create reads it and every new tuning appends a line.
  * Every choice computes the same result up to the rounding of the transforms and the
  * order of the FP64 partial sums.  wf_get_chain_tiles reports the choice in use (WF_OK)
  * or the default if none was tuned yet (WF_NOT_CONVERGED).                             */

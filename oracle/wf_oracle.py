@@ -50,6 +50,8 @@ __all__ = [
     "homogeneous_band_moments", "band_groups", "fisher_from_columns", "sim_fisher_rows",
     "fiducial_iteration", "bandpower_iterate", "fisher_scale", "sim_signal", "posterior_error",
     "dense_posterior_variance", "band_power", "cosmic_variance", "bmode_leakage_qe",
+    "catalog_forward", "catalog_adjoint", "catalog_chi2", "catalog_whitened_grad", "catalog_whitened_hvp",
+    "catalog_lbfgs_solve", "catalog_wiener_dense", "catalog_simulate",
 ]
 
 
@@ -235,18 +237,25 @@ def lbfgs_solve(d, W, S, m: int = 10, tol: float = 1e-10, max_iter: int = 20000,
 
     Returns dict(s, w, iters, rel_grad, chi2, status) with s on the free entries and
     its conjugate partners filled."""
+    return _lbfgs(lambda w: whitened_grad(w, d, W, S), lambda p: whitened_hvp(p, W, S),
+                  lambda s_: chi2(s_, d, W, S), S, precond_diag(W, S) if precond else None, m, tol, max_iter,
+                  dchi2_tol, x0)
+
+
+def _lbfgs(grad, hvp, chi2_of, S, Pdiag, m, tol, max_iter, dchi2_tol, x0):
+    """The L-BFGS iteration of lbfgs_solve for a whitened gradient grad(w) and curvature
+    product hvp(p) of any linear response."""
     fr = _free_with_prior(S)
     sq = np.sqrt(S)
-    P = np.where(fr, precond_diag(W, S), 0.0) if precond else None
+    P = np.where(fr, Pdiag, 0.0) if Pdiag is not None else None
     w = np.zeros_like(S, dtype=np.complex128) if x0 is None else np.where(fr, x0, 0).astype(np.complex128)
-    g = whitened_grad(np.zeros_like(w), d, W, S)
+    g = grad(np.zeros_like(w))
     g0 = math.sqrt(_dot(g, g))
     if w.any():
-        g = whitened_grad(w, d, W, S)
+        g = grad(w)
     pairs: list[tuple[np.ndarray, np.ndarray, float]] = []
     it = 0
     status = 0
-    f_prev = None
     rel = math.sqrt(_dot(g, g)) / g0 if g0 > 0 else 0.0
     while True:
         rel = math.sqrt(_dot(g, g)) / g0 if g0 > 0 else 0.0
@@ -273,14 +282,14 @@ def lbfgs_solve(d, W, S, m: int = 10, tol: float = 1e-10, max_iter: int = 20000,
             b = rho * _dot(yv, q)
             q = q + sv * (a - b)
         p = -q
-        Dp = whitened_hvp(p, W, S)
+        Dp = hvp(p)
         pDp = _dot(p, Dp)
         if not (pDp > 0):
             status = 2
             break
         alpha = -_dot(g, p) / pDp
         w_new = w + alpha * p
-        g_new = whitened_grad(w_new, d, W, S)
+        g_new = grad(w_new)
         sv, yv = w_new - w, g_new - g
         sy = _dot(sv, yv)
         if sy > 1e-12 * math.sqrt(_dot(sv, sv) * _dot(yv, yv)):
@@ -292,9 +301,9 @@ def lbfgs_solve(d, W, S, m: int = 10, tol: float = 1e-10, max_iter: int = 20000,
         it += 1
         if dchi2_tol > 0 and abs(dchi) < dchi2_tol:
             break
-    s = np.where(fr, sq * w, 0)
-    s = _fill_partners(s)
-    return dict(s=s, w=w, iters=it, rel_grad=rel, chi2=chi2(s, d, W, S), status=status)
+    s_ = np.where(fr, sq * w, 0)
+    s_ = _fill_partners(s_)
+    return dict(s=s_, w=w, iters=it, rel_grad=rel, chi2=chi2_of(s_), status=status)
 
 
 def _fill_partners(s):
@@ -750,6 +759,119 @@ def cosmic_variance(S, band, nbands) -> np.ndarray:
         N = 2 * int(np.sum(fr & (band == l)))
         out[l] = math.sqrt(2.0 / N) if N > 0 else 0.0
     return out
+
+
+# ----------------------------------------------------------------------------- catalog response
+# Sec. 3.4: instead of binned shear maps, the likelihood of the measured ellipticities of a
+# catalog of galaxies at their own positions.  The field is the band-limited Fourier series of
+# the harmonic coefficients (the same modes, rotation and unitary normalisation as R),
+# evaluated exactly at each galaxy position r_g in pixel units (a non-uniform DFT):
+# gamma_a(r_g) = n^-1 sum_{k live, full plane} gamma~_a,k exp(2 pi i k.r_g / n); at integer
+# positions this is R s.  chi^2 = s^dag S^-1 s + sum_{a,g} wgt_g (e_a,g - gamma_a(r_g))^2.
+
+def _catalog_phases(pos, n):
+    """exp(2 pi i k.r_g / n) for every galaxy (rows) and full-plane mode (columns, [ky][kx])."""
+    k = np.fft.fftfreq(n, 1.0 / n)
+    ky = np.repeat(k, n)
+    kx = np.tile(k, n)
+    ph = 2.0 * math.pi * (np.outer(pos[:, 0], ky) + np.outer(pos[:, 1], kx)) / n
+    return np.exp(1j * ph)
+
+
+def catalog_forward(s, pos, free=None) -> np.ndarray:
+    """gamma [ncomp][ngal] at the positions pos [ngal][2] (y, x) of the field s
+    [ncomp][n][n/2+1] (free entries read; spin-2 rotated as in forward)."""
+    ncomp, n = s.shape[0], s.shape[1]
+    fr = free_mask(n) if free is None else free
+    full = [full_plane(s[c], fr if fr.ndim == 2 else fr[c]) for c in range(ncomp)]
+    if ncomp == 2:
+        c2, s2 = _rotation_full(n)
+        full = [c2 * full[0] - s2 * full[1], s2 * full[0] + c2 * full[1]]
+    E = _catalog_phases(np.asarray(pos, np.float64), n)
+    out = np.empty((ncomp, len(pos)))
+    for c in range(ncomp):
+        z = E @ full[c].reshape(-1) / n
+        assert np.max(np.abs(z.imag)) <= 1e-9 * (np.max(np.abs(z.real)) + 1e-300)
+        out[c] = z.real
+    return out
+
+
+def catalog_adjoint(r, pos, n) -> np.ndarray:
+    """R_cat^T r in the full-plane metric for r [ncomp][ngal]: per full-plane mode
+    n^-1 sum_g r_g exp(-2 pi i k.r_g / n), inverse rotation, dead entries zeroed."""
+    ncomp = r.shape[0]
+    E = _catalog_phases(np.asarray(pos, np.float64), n)
+    t = [(np.conj(E).T @ r[c]).reshape(n, n) / n for c in range(ncomp)]
+    if ncomp == 2:
+        c2, s2 = _rotation_full(n)
+        t = [c2 * t[0] + s2 * t[1], -s2 * t[0] + c2 * t[1]]
+    live = live_mask(n)
+    return np.stack([np.where(live, tc[:, : n // 2 + 1], 0.0) for tc in t])
+
+
+def catalog_chi2(s, e, wgt, pos, S) -> float:
+    """chi^2 of a catalog (eq. eq_chi with the catalog response)."""
+    fr = _free_with_prior(S)
+    prior = 0.0
+    for c in range(S.shape[0]):
+        Fs = full_plane(s[c], fr[c])
+        Sf = full_plane(S[c].astype(np.complex128), fr[c]).real
+        nz = Sf > 0
+        prior += float(np.sum(np.abs(Fs[nz]) ** 2 / Sf[nz]))
+    r = e - catalog_forward(np.where(fr, s, 0), pos, fr)
+    return prior + float(np.sum(wgt[None] * r * r))
+
+
+def catalog_whitened_grad(w, e, wgt, pos, S) -> np.ndarray:
+    fr = _free_with_prior(S)
+    sq = np.sqrt(S)
+    g = catalog_forward(np.where(fr, sq * w, 0), pos, fr)
+    return np.where(fr, w - sq * catalog_adjoint(wgt[None] * (e - g), pos, S.shape[1]), 0)
+
+
+def catalog_whitened_hvp(p, wgt, pos, S) -> np.ndarray:
+    fr = _free_with_prior(S)
+    sq = np.sqrt(S)
+    g = catalog_forward(np.where(fr, sq * p, 0), pos, fr)
+    return np.where(fr, p + sq * catalog_adjoint(wgt[None] * g, pos, S.shape[1]), 0)
+
+
+def catalog_lbfgs_solve(e, wgt, pos, S, m: int = 10, tol: float = 1e-10, max_iter: int = 20000):
+    """MAP field of a catalog by the L-BFGS of lbfgs_solve (same recursion and line search)."""
+    return _lbfgs(lambda w: catalog_whitened_grad(w, e, wgt, pos, S),
+                  lambda p: catalog_whitened_hvp(p, wgt, pos, S),
+                  lambda s_: catalog_chi2(s_, e, wgt, pos, S), S, None, m, tol, max_iter, 0.0, None)
+
+
+def catalog_wiener_dense(e, wgt, pos, S):
+    """Exact Wiener filter of a catalog (appendix A, eq. eq:wiener, with the catalog response):
+    s = S R^dag C^-1 e, C = R S R^dag + diag(1 / wgt) per component.  Small cases only."""
+    comp, yy, xx, part = _coords(S)
+    fr = _free_with_prior(S)
+    ng = len(pos)
+    A = np.empty((S.shape[0] * ng, comp.size))
+    for j in range(comp.size):
+        u = np.zeros(S.shape, np.complex128)
+        u[comp[j], yy[j], xx[j]] = 1.0 if part[j] == 0 else 1.0j
+        A[:, j] = catalog_forward(u, pos, fr).reshape(-1)
+    var = 0.5 * S[comp, yy, xx]
+    C = (A * var[None, :]) @ A.T
+    C[np.diag_indices_from(C)] += 1.0 / np.tile(wgt, S.shape[0])
+    L = np.linalg.cholesky(C)
+    u_ = np.linalg.solve(L.T, np.linalg.solve(L, e.reshape(-1)))
+    theta = var * (A.T @ u_)
+    s_ = np.zeros(S.shape, np.complex128)
+    np.add.at(s_, (comp[part == 0], yy[part == 0], xx[part == 0]), theta[part == 0])
+    np.add.at(s_, (comp[part == 1], yy[part == 1], xx[part == 1]), 1j * theta[part == 1])
+    return dict(s=_fill_partners(s_), chi2_min=float(e.reshape(-1) @ u_))
+
+
+def catalog_simulate(draw_signal, draw_noise, S_true, wgt, pos):
+    """A simulated catalog: the signal of sim_signal (normals draw_signal [ncomp][n][n], as part
+    0 of a grid draw) at the galaxy positions plus noise of variance 1 / wgt_g
+    (normals draw_noise [ncomp][ngal])."""
+    s_ = sim_signal(np.stack([draw_signal, np.zeros_like(draw_signal)]), S_true)
+    return catalog_forward(s_, pos, _free_with_prior(S_true)) + draw_noise / np.sqrt(wgt)[None]
 
 
 # ----------------------------------------------------------------------------- closed forms

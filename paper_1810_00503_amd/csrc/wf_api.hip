@@ -12,6 +12,7 @@
 #include <mutex>
 #include <new>
 #include <string>
+#include <sys/stat.h>
 #include <tuple>
 #include <vector>
 
@@ -88,6 +89,8 @@ struct wf_ctx {
   // device scratch) and this device's scratch address
   std::map<std::pair<int, int>, std::vector<char>> htw;
   void* scratch = nullptr;
+  // on-disk cache of tuned tiles (empty path: none) and the device it is keyed by
+  std::string tunePath, tuneDev;
 };
 
 namespace {
@@ -404,6 +407,62 @@ struct SolveOut {
   std::vector<int> order;       // class-ordered position of each user index
 };
 
+// On-disk cache of the tuned tiles: one line per (device, n, ncomp, dtype, batch-size bucket)
+// with the choice, "<version> <device> <n> <c> <dtype> <bucket> <rbv> <cpb> <group> <reg>",
+// where device is the architecture name and compute-unit count.  The path is WF_TUNE_CACHE
+// if set (empty: no cache), else $XDG_CACHE_HOME/libwf/tiles.txt or ~/.cache/libwf/tiles.txt.
+// Lines of another version or device, and choices the shape does not support, are ignored;
+// every choice computes the same result, so a stale line costs speed at most.
+constexpr int kTuneVersion = 1;
+
+void tune_cache_open(wf_ctx* ctx) {
+  const char* env = std::getenv("WF_TUNE_CACHE");
+  std::string path;
+  if (env) {
+    path = env;
+  } else if (const char* x = std::getenv("XDG_CACHE_HOME"); x && *x) {
+    path = std::string(x) + "/libwf/tiles.txt";
+  } else if (const char* h = std::getenv("HOME"); h && *h) {
+    path = std::string(h) + "/.cache/libwf/tiles.txt";
+  }
+  hipDeviceProp_t prop;
+  if (path.empty() || hipGetDeviceProperties(&prop, ctx->dev) != hipSuccess) {
+    (void)hipGetLastError();
+    return;
+  }
+  std::string arch = prop.gcnArchName;
+  const size_t colon = arch.find(':');
+  if (colon != std::string::npos) arch = arch.substr(0, colon);
+  ctx->tunePath = path;
+  ctx->tuneDev = arch + "/" + std::to_string(prop.multiProcessorCount);
+  FILE* f = std::fopen(path.c_str(), "r");
+  if (!f) return;
+  char dev[128];
+  int v, n, c, dt, bucket;
+  ChainCfg cfg;
+  while (std::fscanf(f, "%d %127s %d %d %d %d %d %d %d %d", &v, dev, &n, &c, &dt, &bucket, &cfg.rbv, &cfg.cpb, &cfg.group,
+                     &cfg.reg) == 10) {
+    if (v == kTuneVersion && ctx->tuneDev == dev && chain_supported(n) && (c == 1 || c == 2) &&
+        (dt == WF_F32 || dt == WF_F64) && cfg.group >= 0 && chain_cfg_supported(dt, n, c, cfg))
+      ctx->tuned[std::make_tuple(n, c, dt, bucket)] = cfg;
+  }
+  std::fclose(f);
+}
+
+void tune_cache_add(wf_ctx* ctx, const std::tuple<int, int, int, int>& key, const ChainCfg& cfg) {
+  if (ctx->tunePath.empty()) return;
+  const size_t slash = ctx->tunePath.rfind('/');
+  if (slash != std::string::npos && slash > 0) {   // create the directories
+    for (size_t i = 1; i <= slash; ++i)
+      if (ctx->tunePath[i] == '/' || i == slash) (void)mkdir(ctx->tunePath.substr(0, i).c_str(), 0755);
+  }
+  FILE* f = std::fopen(ctx->tunePath.c_str(), "a");
+  if (!f) return;
+  std::fprintf(f, "%d %s %d %d %d %d %d %d %d %d\n", kTuneVersion, ctx->tuneDev.c_str(), std::get<0>(key),
+               std::get<1>(key), std::get<2>(key), std::get<3>(key), cfg.rbv, cfg.cpb, cfg.group, cfg.reg);
+  std::fclose(f);
+}
+
 // Autotuner of the transform chain's tiles: times the curvature product of this class's own
 // instances as the solver runs it (zero direction, real W and prior tables, the extra dots
 // with g and m - 1 kept Dp_j) for every supported tile choice, best of 5, and keeps the
@@ -507,6 +566,7 @@ int tune_chain(wf_ctx* ctx, Klass& k, const std::vector<InstDesc>& hd, Job* djob
   ctx->evPool.push_back(e0);
   ctx->evPool.push_back(e1);
   ctx->tuned[key] = k.cfg;
+  tune_cache_add(ctx, key, k.cfg);
   return WF_OK;
 }
 
@@ -1731,6 +1791,7 @@ int wf_create(wf_ctx** out, int hip_device) {
     delete c;
     return WF_EHIP;
   }
+  tune_cache_open(c);
   if (noalloc_setup(c) != WF_OK) {
     (void)hipEventDestroy(c->evIn);
     (void)hipEventDestroy(c->evOut);

@@ -243,6 +243,57 @@ def cmb_workload(n: int, seed: int, nbands: int = 40, holes: int = 300, gal_frac
                     _theta_fid(rng, nbands, randomize_fid), var, m, seed)
 
 
+@dataclasses.dataclass
+class Catalog:
+    """A galaxy catalog over an n x n patch: positions (y, x) in pixel units, per-galaxy
+    inverse noise variance, and the E/B shear prior of the shear workload."""
+    name: str
+    n: int
+    pos: np.ndarray        # [ngal][2] float64 in [0, n)
+    wgt: np.ndarray        # [ngal] 1 / sigma_e^2
+    mask: np.ndarray       # [n][n] observed pixels (galaxies only there)
+    pshape: np.ndarray
+    band: np.ndarray
+    nbands: int
+    theta_true: np.ndarray
+    theta_fid: np.ndarray
+    seed: int
+    ncomp: int = 2
+
+    @property
+    def ngal(self) -> int:
+        return int(self.pos.shape[0])
+
+
+def shear_catalog(n: int, seed: int, ngal_mean: float = 10.0, sigma_e: float = 0.3, target_mask: float = 0.15,
+                  nbands_e: int = 10, nbands_b: int = 10, b_ratio: float = 0.01, name="shear-catalog") -> Catalog:
+    """Galaxy catalog for the E/B shear workload: Poisson(ngal_mean) galaxies per observed
+    pixel, each at a uniform random position inside its pixel; discs (radius 4-12 px, scaled
+    below 512) masked until target_mask; per-component shape noise sigma_e per galaxy."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    sc = min(1.0, n / 512.0)
+    m = _holes_until(n, rng, np.ones((n, n), bool), target_mask, max(1.0, 4.0 * sc), max(1.5, 12.0 * sc))
+    counts = np.where(m, rng.poisson(ngal_mean, (n, n)), 0)
+    iy, ix = np.nonzero(counts)
+    reps = counts[iy, ix]
+    py = np.repeat(iy, reps).astype(np.float64) + rng.uniform(0.0, 1.0, reps.sum())
+    px = np.repeat(ix, reps).astype(np.float64) + rng.uniform(0.0, 1.0, reps.sum())
+    pos = np.stack([py, px], 1)
+    wgt = np.full(pos.shape[0], 1.0 / sigma_e ** 2)
+    be = log_band_map(n, nbands_e)
+    bb = np.where(log_band_map(n, nbands_b) >= 0, log_band_map(n, nbands_b) + nbands_e, -1)
+    band = np.stack([be, bb]).astype(np.int32)
+    nb = nbands_e + nbands_b
+    return Catalog(name, n, pos, wgt, m, shear_pshape(n, b_ratio=b_ratio), band, nb, np.ones(nb),
+                   _theta_fid(rng, nb, True), seed)
+
+
+def catalog_draws(n: int, ncomp: int, ngal: int, seed: int, dtype=np.float64):
+    """(signal normals [ncomp][n][n], noise normals [ncomp][ngal]) of one simulated catalog."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return (rng.standard_normal((ncomp, n, n)).astype(dtype), rng.standard_normal((ncomp, ngal)).astype(dtype))
+
+
 def density64(n: int = 64) -> Workload:
     """64^2 density, P = (k/k0)^-2 exp(-(k/20)^2), 8 discs r 4-8 px + 4-px border,
     sigma^2 = 0.1 U(0.5, 2); compared against the dense Wiener filter."""
