@@ -324,6 +324,45 @@ int wf_band_E(wf_ctx* ctx, const wf_problem* prob, int32_t batch, const void* s,
 int wf_chi2_dtheta(wf_ctx* ctx, const wf_problem* prob, int32_t batch, const void* s, const double* gout,
                    double* dtheta, void* stream);
 
+/* catalog-level response (sec. 3.4: instead of binned shear maps, the likelihood of each
+ * galaxy's measured ellipticity, so the field is evaluated at every galaxy's own position) --
+ *
+ * A catalog replaces the pixel data of a problem: the response maps the field s to its
+ * values at the galaxies, gamma_a(r_g) = n^-1 sum_k (R~ s)_a,k exp(2 pi i k.r_g / n) (full
+ * plane, the spin-2 rotation of appendix C for ncomp = 2), and the data term of chi^2 (eq.
+ * eq_chi) is sum_g wgt_g sum_a (e_a,g - gamma_a(r_g))^2.  Evaluated as a non-uniform FFT: the
+ * field's modes, deconvolved by the kernel's Fourier transform, on a grid of N = 2n points
+ * per side, the transform chain at N, and a separable exponential-of-semicircle kernel of
+ * 8 x 8 fine points per galaxy (interpolation; its adjoint, deterministic spreading, for
+ * R^T), about 1e-6 relative to the exact sums in float32.  float32 only; n <= 512. */
+typedef struct {
+  int32_t ngal;           /* galaxies, 1 .. 2^27                                          */
+  const double* pos;      /* [ngal][2] positions (y, x) in pixel units: pixel (iy, ix) is at
+                             (iy, ix); periodic, any finite value (wrapped into [0, n))    */
+  const float* e;         /* [ncomp][ngal] measured values (spin-2: e1, e2); solves only   */
+  const float* wgt;       /* [ngal] inverse noise variance of each component, > 0; solves  */
+} wf_catalog;
+
+/* MAP solve of catalogs (sec. 2.2 with the catalog response): as map_wf_solve, with
+ * cats[i] (HOST array, device pointers inside) in place of probs[i].d and .w (not read);
+ * probs[i] gives n, ncomp, dtype = WF_F32, the prior and theta.  opts->precond and
+ * opts->refine must be 0.  The galaxies of each catalog are binned on the host (positions
+ * copied back once per call).  Catalogs of equal (n, ncomp) form one class of the batch.  */
+int map_wf_solve_catalog(wf_ctx* ctx, const wf_problem* probs, const wf_catalog* cats, int32_t batch,
+                         const wf_lbfgs_opts* opts, void* const* s_out, wf_solve_stats* stats, void* stream);
+
+/* gamma [ncomp][ngal] = the field s [ncomp][n][n/2+1] (complex float, free entries read) at
+ * the catalog's positions; prob gives n and ncomp (dtype WF_F32), cat->e and ->wgt unused. */
+int wf_catalog_forward(wf_ctx* ctx, const wf_problem* prob, const wf_catalog* cat, const void* s, float* gamma,
+                       void* stream);
+
+/* Adjoint of wf_catalog_forward: s = R_cat^T r for r [ncomp][ngal] in the full-plane metric
+ * (flags WF_ADJ_METRIC: per live mode n^-1 sum_g r_g exp(-2 pi i k.r_g / n), inverse
+ * rotation, dead entries 0, partners filled) or the stored-coefficient gradient
+ * (WF_ADJ_GRAD: twice that on free entries, 0 else); s [ncomp][n][n/2+1] complex float.    */
+int wf_catalog_adjoint(wf_ctx* ctx, const wf_problem* prob, const wf_catalog* cat, const float* r, void* s,
+                       int32_t flags, void* stream);
+
 /* Tiles of the transform chain (the three passes of every gradient / curvature product):
  * rbv = image rows per work-group of the row pass (2, 4, 8), cpb = column blocks of 2
  * columns per work-group of the column passes (1, 2, 4; must divide n/4), group =

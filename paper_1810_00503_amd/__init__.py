@@ -29,7 +29,7 @@ __all__ = [
     "wf_adjoint",
     "wf_chi2_grad", "wf_hvp", "wf_hvp_noalloc", "wf_band_E", "wf_chi2_dtheta",
     "WFError", "kernel_stats", "reset_kernel_stats", "set_profiling", "autograd", "set_chain_tiles", "copy_bandwidth",
-    "get_chain_tiles",
+    "get_chain_tiles", "GalaxyCatalog", "map_wf_solve_catalog", "catalog_forward", "catalog_adjoint",
 ]
 
 
@@ -139,9 +139,31 @@ class Problem:
         self.d = None if d is None else torch.as_tensor(d, dtype=self.rdtype, device=dev).contiguous()
         self._check()
 
+    @classmethod
+    def for_catalog(cls, n: int, pshape, band, theta, device=None) -> "Problem":
+        """A float32 problem whose data is a galaxy catalog (sec. 3.4): prior and grid only,
+        no pixel data or weights (map_wf_solve_catalog, catalog_forward / catalog_adjoint)."""
+        torch = _torch()
+        p = object.__new__(cls)
+        dev = device if device is not None else (pshape.device if isinstance(pshape, torch.Tensor) else "cuda:0")
+        p.w = None
+        p.d = None
+        p.rdtype = torch.float32
+        p.n = int(n)
+        p.pshape = torch.as_tensor(pshape, dtype=torch.float64, device=dev).contiguous()
+        p.ncomp = int(p.pshape.shape[0])
+        p.band = torch.as_tensor(band, dtype=torch.int32, device=dev).contiguous()
+        p.theta = np.ascontiguousarray(np.asarray(theta, dtype=np.float64).reshape(-1))
+        p._check()
+        return p
+
+    @property
+    def device(self):
+        return self.pshape.device
+
     def _check(self):
         n, c = self.n, self.ncomp
-        if tuple(self.w.shape) != (n, n):
+        if self.w is not None and tuple(self.w.shape) != (n, n):
             raise ValueError(f"w must be [{n}][{n}]")
         if tuple(self.pshape.shape) != (c, n, n // 2 + 1) or tuple(self.band.shape) != (c, n, n // 2 + 1):
             raise ValueError("pshape and band must be [ncomp][n][n/2+1]")
@@ -152,7 +174,7 @@ class Problem:
         p = object.__new__(Problem)
         p.__dict__.update(self.__dict__)
         torch = _torch()
-        p.d = torch.as_tensor(d, dtype=self.rdtype, device=self.w.device).contiguous()
+        p.d = torch.as_tensor(d, dtype=self.rdtype, device=self.device).contiguous()
         p._check()
         return p
 
@@ -178,11 +200,12 @@ class Problem:
     def c(self) -> L.WfProblem:
         th = self.theta.ctypes.data_as(C.POINTER(C.c_double)) if self.theta.size else None
         return L.WfProblem(self.n, self.ncomp, self.dtype_code, self.theta.size,
-                           self.d.data_ptr() if self.d is not None else None, self.w.data_ptr(),
+                           self.d.data_ptr() if self.d is not None else None,
+                           self.w.data_ptr() if self.w is not None else None,
                            self.pshape.data_ptr(), self.band.data_ptr(), th)
 
     def device_index(self) -> int:
-        return self.w.device.index or 0
+        return self.device.index or 0
 
 
 def _stream(dev: int):
@@ -201,15 +224,15 @@ def _dptr(t):
 def _out_buffers(torch, given, problems, shape_of, dtype_of, what):
     """Caller-supplied output tensors, checked against the problems, or new ones."""
     if given is None:
-        return [torch.empty(shape_of(p), dtype=dtype_of(p), device=p.w.device) for p in problems]
+        return [torch.empty(shape_of(p), dtype=dtype_of(p), device=p.device) for p in problems]
     given = list(given)
     if len(given) != len(problems):
         raise ValueError(f"{what}: {len(given)} tensors for {len(problems)} problems")
     for i, (t, p) in enumerate(zip(given, problems)):
-        if (tuple(t.shape) != shape_of(p) or t.dtype != dtype_of(p) or t.device != p.w.device
+        if (tuple(t.shape) != shape_of(p) or t.dtype != dtype_of(p) or t.device != p.device
                 or not t.is_contiguous()):
             raise ValueError(f"{what}[{i}] must be a contiguous {dtype_of(p)} tensor of shape {shape_of(p)} "
-                             f"on {p.w.device}")
+                             f"on {p.device}")
     return given
 
 
@@ -239,16 +262,93 @@ def map_wf_solve(problems: Sequence[Problem], opts: LbfgsOpts | None = None, wan
     return outs, maps, stats, rc
 
 
+class GalaxyCatalog:
+    """A galaxy catalog on the device (sec. 3.4): positions pos [ngal][2] (y, x) in pixel units
+    (float64, periodic), measured values e [ncomp][ngal] and inverse noise variances
+    wgt [ngal] (float32; needed by solves only)."""
+
+    def __init__(self, pos, e=None, wgt=None, device=None):
+        torch = _torch()
+        dev = device if device is not None else (pos.device if isinstance(pos, torch.Tensor) else "cuda:0")
+        self.pos = torch.as_tensor(pos, dtype=torch.float64, device=dev).contiguous()
+        if self.pos.dim() != 2 or self.pos.shape[1] != 2:
+            raise ValueError("pos must be [ngal][2]")
+        self.ngal = int(self.pos.shape[0])
+        self.e = None if e is None else torch.as_tensor(e, dtype=torch.float32, device=dev).contiguous()
+        self.wgt = None if wgt is None else torch.as_tensor(wgt, dtype=torch.float32, device=dev).contiguous()
+        if self.e is not None and (self.e.dim() != 2 or self.e.shape[1] != self.ngal):
+            raise ValueError("e must be [ncomp][ngal]")
+        if self.wgt is not None and tuple(self.wgt.shape) != (self.ngal,):
+            raise ValueError("wgt must be [ngal]")
+
+    def c(self) -> L.WfCatalog:
+        return L.WfCatalog(self.ngal, self.pos.data_ptr(), self.e.data_ptr() if self.e is not None else None,
+                           self.wgt.data_ptr() if self.wgt is not None else None)
+
+
+def map_wf_solve_catalog(problems: Sequence[Problem], catalogs: Sequence[GalaxyCatalog],
+                         opts: LbfgsOpts | None = None, ctx: Context | None = None, out=None):
+    """MAP fields of a batch of catalogs (problems from Problem.for_catalog give the grid and
+    prior).  Returns (s list of complex64 [ncomp][n][n/2+1], stats list, rc)."""
+    torch = _torch()
+    problems, catalogs = list(problems), list(catalogs)
+    if len(problems) != len(catalogs):
+        raise ValueError("one catalog per problem")
+    B = len(problems)
+    dev = problems[0].device_index() if B else 0
+    cx = ctx or context(dev)
+    outs = _out_buffers(torch, out, problems, lambda p: (p.ncomp, p.n, p.n // 2 + 1), lambda p: p.cdtype, "out")
+    cps = (L.WfProblem * max(B, 1))(*[p.c() for p in problems])
+    cats = (L.WfCatalog * max(B, 1))(*[g.c() for g in catalogs])
+    s_arr = (C.c_void_p * max(B, 1))(*[o.data_ptr() for o in outs])
+    st = (L.WfSolveStats * max(B, 1))()
+    o = _opts(opts)
+    rc = cx.lib.map_wf_solve_catalog(cx.h, cps, cats, B, C.byref(o), s_arr, st, _stream(dev))
+    cx.check(rc)
+    stats = [SolveStats(st[i].iters, st[i].status, st[i].ngrad, st[i].chi2, st[i].rel_grad) for i in range(B)]
+    return outs, stats, rc
+
+
+def catalog_forward(problem: Problem, catalog: GalaxyCatalog, s, ctx: Context | None = None):
+    """The field s [ncomp][n][n/2+1] (complex64) at the catalog's positions: [ncomp][ngal]."""
+    torch = _torch()
+    s = s.contiguous()
+    if s.dtype != torch.complex64 or tuple(s.shape) != (problem.ncomp, problem.n, problem.n // 2 + 1):
+        raise ValueError("s must be complex64 [ncomp][n][n/2+1]")
+    dev = problem.device_index()
+    cx = ctx or context(dev)
+    g = torch.empty((problem.ncomp, catalog.ngal), dtype=torch.float32, device=s.device)
+    cp, cc = problem.c(), catalog.c()
+    cx.check(cx.lib.wf_catalog_forward(cx.h, C.byref(cp), C.byref(cc), s.data_ptr(), g.data_ptr(), _stream(dev)))
+    return g
+
+
+def catalog_adjoint(problem: Problem, catalog: GalaxyCatalog, r, flags: int = WF_ADJ_METRIC,
+                    ctx: Context | None = None):
+    """Adjoint of catalog_forward for r [ncomp][ngal] (float32): complex64 [ncomp][n][n/2+1]."""
+    torch = _torch()
+    r = r.contiguous()
+    if r.dtype != torch.float32 or tuple(r.shape) != (problem.ncomp, catalog.ngal):
+        raise ValueError("r must be float32 [ncomp][ngal]")
+    dev = problem.device_index()
+    cx = ctx or context(dev)
+    s = torch.empty((problem.ncomp, problem.n, problem.n // 2 + 1), dtype=torch.complex64, device=r.device)
+    cp, cc = problem.c(), catalog.c()
+    cx.check(cx.lib.wf_catalog_adjoint(cx.h, C.byref(cp), C.byref(cc), r.data_ptr(), s.data_ptr(), int(flags),
+                                       _stream(dev)))
+    return s
+
+
 def wf_simulate(problem: Problem, nsim: int, seed: int, sim0: int = 0, draws=None, theta_true=None,
                 boost_band: int = -1, boost_factor: float = 1.0, ctx: Context | None = None):
     """Simulated data maps [nsim][ncomp][n][n] (sec. 2.4)."""
     torch = _torch()
     dev = problem.device_index()
     cx = ctx or context(dev)
-    out = torch.empty((nsim, problem.ncomp, problem.n, problem.n), dtype=problem.rdtype, device=problem.w.device)
+    out = torch.empty((nsim, problem.ncomp, problem.n, problem.n), dtype=problem.rdtype, device=problem.device)
     dr = None
     if draws is not None:
-        draws = torch.as_tensor(draws, dtype=problem.rdtype, device=problem.w.device).contiguous()
+        draws = torch.as_tensor(draws, dtype=problem.rdtype, device=problem.device).contiguous()
         if tuple(draws.shape) != (nsim, 2, problem.ncomp, problem.n, problem.n):
             raise ValueError("draws must be [nsim][2][ncomp][n][n]")
         dr = draws.data_ptr()
@@ -267,7 +367,7 @@ def _draws_ptr(problem, draws, nsim):
     if draws is None:
         return None, None
     torch = _torch()
-    t = torch.as_tensor(draws, dtype=problem.rdtype, device=problem.w.device).contiguous()
+    t = torch.as_tensor(draws, dtype=problem.rdtype, device=problem.device).contiguous()
     if tuple(t.shape) != (nsim, 2, problem.ncomp, problem.n, problem.n):
         raise ValueError("draws must be [nsim][2][ncomp][n][n]")
     return t, t.data_ptr()
@@ -441,8 +541,8 @@ def posterior_error(problem: Problem, nsim: int, seed: int, draws=None, opts: Lb
     dev = problem.device_index()
     cx = ctx or context(dev)
     n, c = problem.n, problem.ncomp
-    vm = torch.empty((c, n, n // 2 + 1), dtype=problem.rdtype, device=problem.w.device) if want_modes else None
-    vp = torch.empty((c, n, n), dtype=problem.rdtype, device=problem.w.device) if want_pixels else None
+    vm = torch.empty((c, n, n // 2 + 1), dtype=problem.rdtype, device=problem.device) if want_modes else None
+    vp = torch.empty((c, n, n), dtype=problem.rdtype, device=problem.device) if want_pixels else None
     keep, dp = _draws_ptr(problem, draws, nsim)
     cp = problem.c()
     o = _opts(opts)
@@ -473,7 +573,7 @@ def convergence_by_band(problem: Problem, tols, opts: LbfgsOpts | None = None, w
     outs = None
     if want_fields:
         cdt = torch.complex64 if problem.rdtype == torch.float32 else torch.complex128
-        fields = [torch.empty((problem.ncomp, problem.n, problem.n // 2 + 1), dtype=cdt, device=problem.w.device)
+        fields = [torch.empty((problem.ncomp, problem.n, problem.n // 2 + 1), dtype=cdt, device=problem.device)
                   for _ in range(nt + 1)]
         outs = (C.c_void_p * (nt + 1))(*[f.data_ptr() for f in fields])
     cp = problem.c()

@@ -20,6 +20,7 @@ EXPORTS = [
     "sim_fisher", "sim_fisher_rows", "bandpower_qe", "bandpower_qe_batch", "bandpower_iterate", "bmode_leakage_qe", "posterior_error", "convergence_by_band", "wf_forward", "wf_adjoint", "wf_chi2_grad", "wf_hvp", "wf_hvp_noalloc", "wf_band_E", "wf_chi2_dtheta",
     "wf_set_profiling", "wf_kernel_kinds", "wf_kernel_kind_name", "wf_get_kernel_stats",
     "wf_reset_kernel_stats", "wf_set_chain_tiles", "wf_get_chain_tiles", "wf_copy_bandwidth",
+    "map_wf_solve_catalog", "wf_catalog_forward", "wf_catalog_adjoint",
 ]
 
 
@@ -29,6 +30,10 @@ class WfProblem(C.Structure):
         ("d", C.c_void_p), ("w", C.c_void_p), ("pshape", C.c_void_p), ("band", C.c_void_p),
         ("theta", C.POINTER(C.c_double)),
     ]
+
+
+class WfCatalog(C.Structure):
+    _fields_ = [("ngal", C.c_int32), ("pos", C.c_void_p), ("e", C.c_void_p), ("wgt", C.c_void_p)]
 
 
 class WfLbfgsOpts(C.Structure):
@@ -68,6 +73,10 @@ def load(path: str | None = None):
     L.wf_lbfgs_default.restype = None
     L.map_wf_solve.argtypes = [vp, C.POINTER(WfProblem), i32, C.POINTER(WfLbfgsOpts), C.POINTER(vp),
                                C.POINTER(vp), C.POINTER(WfSolveStats), vp]
+    L.map_wf_solve_catalog.argtypes = [vp, C.POINTER(WfProblem), C.POINTER(WfCatalog), i32, C.POINTER(WfLbfgsOpts),
+                                       C.POINTER(vp), C.POINTER(WfSolveStats), vp]
+    L.wf_catalog_forward.argtypes = [vp, C.POINTER(WfProblem), C.POINTER(WfCatalog), vp, vp, vp]
+    L.wf_catalog_adjoint.argtypes = [vp, C.POINTER(WfProblem), C.POINTER(WfCatalog), vp, vp, i32, vp]
     L.wf_simulate.argtypes = [vp, C.POINTER(WfProblem), i32, C.c_uint64, i32, vp, dp, i32, C.c_double, vp, vp]
     L.sim_fisher.argtypes = [vp, C.POINTER(WfProblem), i32, C.c_uint64, vp, C.POINTER(WfLbfgsOpts), dp, dp, dp, dp,
                              vp]

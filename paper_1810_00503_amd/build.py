@@ -19,7 +19,8 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libwf.so")
-UNITS = ["wf_chain_f32l.hip", "wf_chain_f32s.hip", "wf_chain_f64.hip", "wf_solver_k.hip", "wf_api.hip"]
+UNITS = ["wf_chain_f32l.hip", "wf_chain_f32s.hip", "wf_chain_f64.hip", "wf_solver_k.hip", "wf_catalog_k.hip",
+         "wf_api.hip"]
 ARCH = os.environ.get("WF_OFFLOAD_ARCH", "gfx950")
 
 

@@ -45,7 +45,7 @@ constexpr size_t kVecPadBytes = 4096 + 256;
 constexpr int kMaxStreams = 4;   // the context stream plus up to 3 more for the classes of an uneven batch
 
 const char* kKindNames[KK_COUNT] = {"colinv", "row", "colfwd", "passA", "passB", "post", "coef", "misc", "cg_dir",
-                                     "simulate"};
+                                     "simulate", "catalog"};
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
@@ -387,6 +387,186 @@ struct StreamScope {
   }
 };
 
+// ---------------------------------------------------------------------------- catalogs
+// The catalog-level response (sec. 3.4) as a non-uniform FFT on the fine grid of N = 2n
+// points per side.  Positions are binned on the host: fine coordinate rho = 2 r wrapped into
+// [0, N), its cell floor(rho) and fraction, and a stable counting sort of the galaxies by
+// CAT_TS x CAT_TS tile, so each tile keeps the input order and the spreading sums are the
+// same on every call.
+struct CatHost {
+  int n = 0, N = 0, c = 0, ngal = 0, tiles = 0;
+  std::vector<GalPos> pos;     // sorted
+  std::vector<int> perm;       // sorted position -> input index
+  std::vector<int> tileStart;  // [tiles^2 + 1]
+  const wf_catalog* src = nullptr;
+  int* dperm = nullptr;        // device copy of perm (after cat_fill)
+};
+
+constexpr int kCatMaxGal = 1 << 27;
+
+int check_catalog(wf_ctx* ctx, const wf_problem* p, const wf_catalog* cat, bool solve) {
+  if (!p || !cat) return fail(ctx, WF_EINVAL, "null problem / catalog");
+  if (!chain_supported(p->n) || !chain_supported(2 * p->n))
+    return fail(ctx, WF_EINVAL, "unsupported n=" + std::to_string(p->n) +
+                                    " for a catalog (need n % 8 == 0, 8 <= n <= 512, n = 2^a or 3*2^a)");
+  if (p->ncomp != 1 && p->ncomp != 2) return fail(ctx, WF_EINVAL, "ncomp must be 1 or 2");
+  if (p->dtype != WF_F32) return fail(ctx, WF_EINVAL, "catalogs are float32 only");
+  if (cat->ngal < 1 || cat->ngal > kCatMaxGal) return fail(ctx, WF_EINVAL, "ngal out of range");
+  if (!cat->pos) return fail(ctx, WF_EINVAL, "null catalog positions");
+  if (!solve) return WF_OK;
+  if (!cat->e || !cat->wgt) return fail(ctx, WF_EINVAL, "null catalog e / wgt");
+  if (p->nbands < 0 || p->nbands > 4096) return fail(ctx, WF_EINVAL, "nbands out of range");
+  if (!p->pshape || !p->band) return fail(ctx, WF_EINVAL, "null pshape / band");
+  if (p->nbands > 0 && !p->theta) return fail(ctx, WF_EINVAL, "null theta");
+  for (int b = 0; b < p->nbands; ++b)
+    if (!std::isfinite(p->theta[b])) return fail(ctx, WF_ENONFINITE, "non-finite theta");
+  return WF_OK;
+}
+
+int cat_bin(wf_ctx* ctx, const wf_catalog* cat, int n, int c, CatHost& h) {
+  h.n = n;
+  h.N = 2 * n;
+  h.c = c;
+  h.ngal = cat->ngal;
+  h.tiles = h.N / CAT_TS;
+  h.src = cat;
+  std::vector<double> hp((size_t)2 * h.ngal);
+  HIPCHK(hipMemcpyAsync(hp.data(), cat->pos, sizeof(double) * hp.size(), hipMemcpyDeviceToHost, ctx->cs));
+  HIPCHK(hipStreamSynchronize(ctx->cs));
+  const int nt = h.tiles * h.tiles;
+  std::vector<GalPos> gp(h.ngal);
+  std::vector<int> key(h.ngal);
+  h.tileStart.assign(nt + 1, 0);
+  for (int g = 0; g < h.ngal; ++g) {
+    int cell[2];
+    float frac[2];
+    for (int a = 0; a < 2; ++a) {
+      const double x = hp[2 * (size_t)g + a];
+      if (!std::isfinite(x)) return fail(ctx, WF_ENONFINITE, "non-finite galaxy position");
+      double r = std::fmod(2.0 * x, (double)h.N);
+      if (r < 0.0) r += h.N;
+      const double fl = std::floor(r);
+      int ci = (int)fl;
+      float fr = (float)(r - fl);
+      if (fr >= 1.0f) {   // rounded up to the next cell
+        fr = 0.0f;
+        ++ci;
+      }
+      if (ci >= h.N) ci -= h.N;   // r == N after the wrap of a tiny negative value
+      cell[a] = ci;
+      frac[a] = fr;
+    }
+    gp[g] = GalPos{cell[0], cell[1], frac[0], frac[1]};
+    key[g] = (cell[0] / CAT_TS) * h.tiles + cell[1] / CAT_TS;
+    ++h.tileStart[key[g] + 1];
+  }
+  for (int t = 0; t < nt; ++t) h.tileStart[t + 1] += h.tileStart[t];
+  std::vector<int> at(h.tileStart.begin(), h.tileStart.end() - 1);
+  h.perm.resize(h.ngal);
+  h.pos.resize(h.ngal);
+  for (int g = 0; g < h.ngal; ++g) {
+    const int q = at[key[g]]++;
+    h.perm[q] = g;
+    h.pos[q] = gp[g];
+  }
+  return WF_OK;
+}
+
+// 1 / phi^(k / N) for k = 0 .. n/2, phi the spreading kernel exp(beta (sqrt(1 - (2z/W)^2) - 1))
+// on |z| <= W/2 (the device's beta, W): phi^(xi) = int phi(z) cos(2 pi xi z) dz
+// = W int_0^{pi/2} exp(beta (cos t - 1)) cos(pi xi W sin t) cos t dt  (z = W/2 sin t), whose
+// integrand is smooth, by composite Simpson in float64.
+void cat_deconv(int n, int N, std::vector<double>& dk) {
+  constexpr int M = 2048;
+  const double W = CAT_W, beta = (double)CAT_BETA, hq = 0.5 * M_PI / M;
+  dk.assign(n / 2 + 1, 0.0);
+  for (int k = 0; k <= n / 2; ++k) {
+    const double xi = (double)k / N;
+    double s = 0.0;
+    for (int q = 0; q <= M; ++q) {
+      const double t = q * hq;
+      const double f = std::exp(beta * (std::cos(t) - 1.0)) * std::cos(M_PI * xi * W * std::sin(t)) * std::cos(t);
+      s += f * ((q == 0 || q == M) ? 1.0 : (q % 2 ? 4.0 : 2.0));
+    }
+    dk[k] = 1.0 / (W * s * hq / 3.0);
+  }
+}
+
+size_t cat_bytes(int n, int c, int ngal) {
+  const size_t N = 2 * (size_t)n, tiles = N / CAT_TS, g = (size_t)ngal, C = (size_t)c;
+  return align_up(sizeof(GalPos) * g) + align_up(4 * g) + align_up(4 * (tiles * tiles + 1)) + 2 * align_up(4 * C * g) +
+         align_up(4 * g) + align_up(4 * C * n * (n / 2)) + align_up(8 * ((g + NT - 1) / NT)) +
+         align_up(8 * ((size_t)n / 2 + 1)) + 2 * align_up(8 * C * N * (N / 2)) + align_up(4 * C * N * N);
+}
+
+// Device copy of one binned catalog: the descriptor (host copy cd; jfwd / jadj are set by the
+// caller), its fine-grid forward and adjoint jobs (host copies jf, ja, switched off), the table
+// T from the scale table sq (nullptr: the unscaled operator) and, for solves, the measurements
+// and weights gathered into the sorted order.
+int cat_fill(wf_ctx* ctx, Arena& A, CatHost& h, const void* sq, bool solve, CatDesc& cd, Job& jf, Job& ja) {
+  const int n = h.n, N = h.N, c = h.c, g = h.ngal;
+  GalPos* dpos = (GalPos*)arena_take(A, sizeof(GalPos) * g);
+  int* dperm = (int*)arena_take(A, 4 * (size_t)g);
+  int* dts = (int*)arena_take(A, 4 * h.tileStart.size());
+  float* de = (float*)arena_take(A, 4 * (size_t)c * g);
+  float* dr = (float*)arena_take(A, 4 * (size_t)c * g);
+  float* dw = (float*)arena_take(A, 4 * (size_t)g);
+  float* dT = (float*)arena_take(A, 4 * (size_t)c * n * (n / 2));
+  double* dpart = (double*)arena_take(A, 8 * (size_t)((g + NT - 1) / NT));
+  double* ddk = (double*)arena_take(A, 8 * (size_t)(n / 2 + 1));
+  void* y2 = arena_take(A, 8 * (size_t)c * N * (N / 2));
+  void* yN = arena_take(A, 8 * (size_t)c * N * (N / 2));
+  float* map = (float*)arena_take(A, 4 * (size_t)c * N * N);
+  if (A.used > A.cap) return fail(ctx, WF_ENOMEM, "internal: catalog workspace overflow");
+  std::vector<double> dk;
+  cat_deconv(n, N, dk);
+  HIPCHK(hipMemcpyAsync(dpos, h.pos.data(), sizeof(GalPos) * g, hipMemcpyHostToDevice, ctx->cs));
+  HIPCHK(hipMemcpyAsync(dperm, h.perm.data(), 4 * (size_t)g, hipMemcpyHostToDevice, ctx->cs));
+  HIPCHK(hipMemcpyAsync(dts, h.tileStart.data(), 4 * h.tileStart.size(), hipMemcpyHostToDevice, ctx->cs));
+  HIPCHK(hipMemcpyAsync(ddk, dk.data(), 8 * dk.size(), hipMemcpyHostToDevice, ctx->cs));
+  HIPCHK(hipStreamSynchronize(ctx->cs));   // dk is local
+  HIPCHK(cat_table_launch(n, N, c, (const float*)sq, ddk, dT, ctx->cs));
+  if (solve) {
+    HIPCHK(cat_permute_launch(h.src->e, dperm, de, g, c, 1, ctx->cs));
+    HIPCHK(cat_permute_launch(h.src->wgt, dperm, dw, g, 1, 1, ctx->cs));
+  }
+  h.dperm = dperm;
+  std::memset(&cd, 0, sizeof cd);
+  cd.n = n;
+  cd.N = N;
+  cd.c = c;
+  cd.ngal = g;
+  cd.tiles = h.tiles;
+  cd.nrowPart = c * n / RB_MIN;
+  cd.pos = dpos;
+  cd.tileStart = dts;
+  cd.e = de;
+  cd.wgt = dw;
+  cd.T = dT;
+  cd.aTab = nullptr;
+  cd.y2 = y2;
+  cd.u = map;
+  cd.v = map;
+  cd.r = dr;
+  cd.partI = dpart;
+  std::memset(&jf, 0, sizeof jf);
+  std::memset(&ja, 0, sizeof ja);
+  jf.mode = ja.mode = CM_NONE;
+  jf.boost_band = ja.boost_band = -1;
+  jf.vin = y2;
+  jf.y = yN;
+  jf.xout = map;
+  ja.d = map;
+  ja.y = yN;
+  ja.vout = y2;
+  return WF_OK;
+}
+
+hipError_t cat_step(wf_ctx* ctx, int which, int c, int blocks, const Job* jobs, CatDesc* cats, int count) {
+  Timed t(ctx, KK_CAT);
+  return cat_launch(which, c, blocks, jobs, cats, count, ctx->cs);
+}
+
 // ---------------------------------------------------------------------------- solve core
 struct Klass {
   int n, c, dtype;
@@ -397,6 +577,15 @@ struct Klass {
   int pu = PASS_U_FEW;   // vector loads per thread per stream of the class's vector passes
   ChainCfg cfg;    // tile choice of the transform chain
   const void* tw = nullptr;
+  // catalog classes (sec. 3.4): fine grid N = 2n, its tiles per side, interpolation blocks of
+  // the largest catalog, and the class's descriptors and fine-grid forward / adjoint jobs
+  bool cat = false;
+  int N = 0, tiles = 0, nblkI = 0;
+  ChainCfg cfgN;
+  const void* twN = nullptr;
+  CatDesc* dcats = nullptr;
+  Job* fjobs = nullptr;
+  Job* ajobs = nullptr;
 };
 
 struct SolveOut {
@@ -606,7 +795,7 @@ int refine_f64(wf_ctx* ctx, const wf_lbfgs_opts& o, const std::vector<Klass>& ks
   const double T = o.refine_tol;
   std::vector<int> fk;
   for (size_t c = 0; c < ks.size(); ++c)
-    if (ks[c].dtype == WF_F32) fk.push_back((int)c);
+    if (ks[c].dtype == WF_F32 && !ks[c].cat) fk.push_back((int)c);
   if (fk.empty()) return WF_OK;
   const int B = (int)hd.size();
   struct Ref {
@@ -832,19 +1021,23 @@ int refine_f64(wf_ctx* ctx, const wf_lbfgs_opts& o, const std::vector<Klass>& ks
 }
 
 // tols: nullable per-instance relative-gradient tolerances (user index), else o's
+// cats (nullable): catalogs [B] in place of the problems' pixel data (every instance then
+// uses the catalog response; no preconditioner, no refinement)
 int solve_core(wf_ctx* ctx, const wf_problem* probs, int B, const wf_lbfgs_opts& o, SolveOut& out,
-               const double* tols = nullptr) {
+               const double* tols = nullptr, const wf_catalog* cats = nullptr) {
   const int m = o.m;
   if (m < 1 || m > MMAX) return fail(ctx, WF_EINVAL, "m must be in [1, 16]");
-  // group into classes of equal (n, ncomp, dtype)
+  if (cats && (o.precond || o.refine > 0)) return fail(ctx, WF_EINVAL, "catalog solves take no precond / refine");
+  // group into classes of equal (n, ncomp, dtype) and response
+  const bool isCat = cats != nullptr;
   std::vector<Klass> ks;
   for (int i = 0; i < B; ++i) {
     const wf_problem* p = &probs[i];
-    int rc = check_problem(ctx, p, true);
+    int rc = isCat ? check_catalog(ctx, p, &cats[i], true) : check_problem(ctx, p, true);
     if (rc) return rc;
     bool found = false;
     for (auto& k : ks)
-      if (k.n == p->n && k.c == p->ncomp && k.dtype == p->dtype) {
+      if (k.n == p->n && k.c == p->ncomp && k.dtype == p->dtype && k.cat == isCat) {
         k.members.push_back(i);
         found = true;
         break;
@@ -854,9 +1047,16 @@ int solve_core(wf_ctx* ctx, const wf_problem* probs, int B, const wf_lbfgs_opts&
       k.n = p->n;
       k.c = p->ncomp;
       k.dtype = p->dtype;
+      k.cat = isCat;
       k.members.push_back(i);
       ks.push_back(k);
     }
+  }
+  // catalogs binned on the fine grid (host)
+  std::vector<CatHost> ch(isCat ? B : 0);
+  for (int i = 0; i < (int)ch.size(); ++i) {
+    int rc = cat_bin(ctx, &cats[i], probs[i].n, probs[i].ncomp, ch[i]);
+    if (rc) return rc;
   }
   // distinct priors within the call
   std::map<std::tuple<const void*, const void*, int, int, int, std::vector<double>>, int> pmap;
@@ -900,6 +1100,21 @@ int solve_core(wf_ctx* ctx, const wf_problem* probs, int B, const wf_lbfgs_opts&
     if (rc) return rc;
     rc = prepare(ctx, k.n, k.c, k.dtype);
     if (rc) return rc;
+    if (k.cat) {
+      k.N = 2 * k.n;
+      k.tiles = k.N / CAT_TS;
+      k.nblkI = 1;
+      for (int ui : k.members) {
+        k.nblkI = std::max(k.nblkI, (ch[ui].ngal + NT - 1) / NT);
+        total += cat_bytes(k.n, k.c, ch[ui].ngal);
+      }
+      total += 2 * align_up(sizeof(Job) * k.members.size()) + align_up(sizeof(CatDesc) * k.members.size());
+      k.cfgN = op_cfg(ctx, WF_F32, k.N, k.c);
+      rc = twiddles(ctx, k.N, WF_F32, &k.twN);
+      if (rc) return rc;
+      rc = prepare(ctx, k.N, k.c, WF_F32);
+      if (rc) return rc;
+    }
   }
   total += align_up(sizeof(InstDesc) * B) + align_up(sizeof(LbState) * B) + align_up(sizeof(Job) * B) +
            align_up(sizeof(int) * B);
@@ -910,6 +1125,14 @@ int solve_core(wf_ctx* ctx, const wf_problem* probs, int B, const wf_lbfgs_opts&
   LbState* dst = (LbState*)arena_take(A, sizeof(LbState) * B);
   Job* djobs = (Job*)arena_take(A, sizeof(Job) * B);
   int* dstat = (int*)arena_take(A, sizeof(int) * B);
+  // the catalog classes' descriptor and job arrays next, at offsets fixed by the batch shape
+  // (captured graphs take them as kernel arguments)
+  for (auto& k : ks) {
+    if (!k.cat) continue;
+    k.dcats = (CatDesc*)arena_take(A, sizeof(CatDesc) * k.members.size());
+    k.fjobs = (Job*)arena_take(A, sizeof(Job) * k.members.size());
+    k.ajobs = (Job*)arena_take(A, sizeof(Job) * k.members.size());
+  }
   std::vector<PriorTab> ptabs(prepIdx.size());
   for (size_t id = 0; id < prepIdx.size(); ++id) {
     rc = build_prior(ctx, A, &probs[prepIdx[id]], probs[prepIdx[id]].theta, ptabs[id], o.precond != 0);
@@ -922,6 +1145,8 @@ int solve_core(wf_ctx* ctx, const wf_problem* probs, int B, const wf_lbfgs_opts&
   out.order.assign(B, 0);
   for (auto& k : ks) {
     const size_t eb = esize_of(k.dtype);
+    std::vector<CatDesc> hcd(k.cat ? k.members.size() : 0);
+    std::vector<Job> hjf(hcd.size()), hja(hcd.size());
     for (size_t j = 0; j < k.members.size(); ++j) {
       const int ui = k.members[j];
       const int gi = k.first + (int)j;
@@ -933,8 +1158,8 @@ int solve_core(wf_ctx* ctx, const wf_problem* probs, int B, const wf_lbfgs_opts&
       D.vstride = (int64_t)(vsb / eb);
       D.NV = 2 + 2 * m;
       D.nchunk = k.nchunk;
-      D.d = p->d;
-      D.W = p->w;
+      D.d = k.cat ? nullptr : p->d;
+      D.W = k.cat ? nullptr : p->w;
       D.sq = ptabs[pidx[ui]].sq;
       D.aTab = ptabs[pidx[ui]].a;
       D.ainv = ptabs[pidx[ui]].ainv;
@@ -956,10 +1181,23 @@ int solve_core(wf_ctx* ctx, const wf_problem* probs, int B, const wf_lbfgs_opts&
       out.y[ui] = D.y;
       out.prior[ui] = ptabs[pidx[ui]];
       out.order[ui] = gi;
+      if (k.cat) {
+        rc = cat_fill(ctx, A, ch[ui], D.sq, true, hcd[j], hjf[j], hja[j]);
+        if (rc) return rc;
+        hcd[j].jfwd = k.fjobs + j;
+        hcd[j].jadj = k.ajobs + j;
+      }
+    }
+    if (k.cat) {
+      HIPCHK(hipMemcpyAsync(k.dcats, hcd.data(), sizeof(CatDesc) * hcd.size(), hipMemcpyHostToDevice, ctx->cs));
+      HIPCHK(hipMemcpyAsync(k.fjobs, hjf.data(), sizeof(Job) * hjf.size(), hipMemcpyHostToDevice, ctx->cs));
+      HIPCHK(hipMemcpyAsync(k.ajobs, hja.data(), sizeof(Job) * hja.size(), hipMemcpyHostToDevice, ctx->cs));
+      HIPCHK(hipStreamSynchronize(ctx->cs));   // host copies are local
     }
   }
   HIPCHK(hipMemcpyAsync(ddesc, hd.data(), sizeof(InstDesc) * B, hipMemcpyHostToDevice, ctx->cs));
   for (auto& k : ks) {
+    if (k.cat) continue;   // the coarse chain does not run for catalogs
     rc = tune_chain(ctx, k, hd, djobs, m);
     if (rc) return rc;
   }
@@ -989,10 +1227,24 @@ int solve_core(wf_ctx* ctx, const wf_problem* probs, int B, const wf_lbfgs_opts&
   auto body = [&](const Klass& k) -> int {
     const int cnt = (int)k.members.size();
     const int dt = k.dtype == WF_F64;
-    const int G = k.cfg.group > 0 ? std::min(k.cfg.group, cnt) : cnt;
-    for (int g0 = 0; g0 < cnt; g0 += G) {
-      const int gc = std::min(G, cnt - g0);
-      for (int w = 0; w < 3; ++w) HIPCHK(chain(ctx, k.dtype, k.n, k.c, w, djobs + k.first + g0, gc, k.tw, &k.cfg));
+    if (k.cat) {
+      // the catalog response in place of the coarse chain: pad to the fine grid, forward
+      // transform, interpolation at the galaxies, spreading, adjoint transform, unpad
+      Job* jc = djobs + k.first;
+      HIPCHK(cat_step(ctx, CAT_PAD, k.c, k.N / 4, jc, k.dcats, cnt));
+      HIPCHK(chain(ctx, WF_F32, k.N, k.c, CH_COLINV, k.fjobs, cnt, k.twN, &k.cfgN));
+      HIPCHK(chain(ctx, WF_F32, k.N, k.c, CH_ROW, k.fjobs, cnt, k.twN, &k.cfgN));
+      HIPCHK(cat_step(ctx, CAT_INTERP, k.c, k.nblkI, jc, k.dcats, cnt));
+      HIPCHK(cat_step(ctx, CAT_SPREAD, k.c, k.tiles * k.tiles, jc, k.dcats, cnt));
+      HIPCHK(chain(ctx, WF_F32, k.N, k.c, CH_ROW, k.ajobs, cnt, k.twN, &k.cfgN));
+      HIPCHK(chain(ctx, WF_F32, k.N, k.c, CH_COLFWD, k.ajobs, cnt, k.twN, &k.cfgN));
+      HIPCHK(cat_step(ctx, CAT_UNPAD, k.c, k.n / 4, jc, k.dcats, cnt));
+    } else {
+      const int G = k.cfg.group > 0 ? std::min(k.cfg.group, cnt) : cnt;
+      for (int g0 = 0; g0 < cnt; g0 += G) {
+        const int gc = std::min(G, cnt - g0);
+        for (int w = 0; w < 3; ++w) HIPCHK(chain(ctx, k.dtype, k.n, k.c, w, djobs + k.first + g0, gc, k.tw, &k.cfg));
+      }
     }
     auto launch = [&](int kk, int which, dim3 grid) -> int {
       Timed t(ctx, kk);
@@ -1026,8 +1278,9 @@ int solve_core(wf_ctx* ctx, const wf_problem* probs, int B, const wf_lbfgs_opts&
     for (int c = 0; c < nk; ++c) {
       const Klass& k = ks[c];
       char buf[160];
-      snprintf(buf, sizeof buf, "%p/%d/%d/%d/%d/%d|%d,%d,%d,%d,%zu,%d,%d,%d,%d", (void*)A.base, A.gen, B, m, K,
-               o.method, k.first, k.n, k.c, k.dtype, k.members.size(), k.cfg.rbv, k.cfg.cpb, k.cfg.group, k.cfg.reg);
+      snprintf(buf, sizeof buf, "%p/%d/%d/%d/%d/%d|%d,%d,%d,%d,%zu,%d,%d,%d,%d|%d,%d", (void*)A.base, A.gen, B, m, K,
+               o.method, k.first, k.n, k.c, k.dtype, k.members.size(), k.cfg.rbv, k.cfg.cpb, k.cfg.group, k.cfg.reg,
+               (int)k.cat, k.nblkI);
       keys[c] = buf;
     }
     for (auto it = ctx->gexecs.begin(); it != ctx->gexecs.end();) {
@@ -1098,8 +1351,9 @@ int solve_core(wf_ctx* ctx, const wf_problem* probs, int B, const wf_lbfgs_opts&
           HIPCHK(hipGraphLaunch(gx[act[a]], s == 0 ? ctx->cs : ctx->xs[s - 1]));
           // count launches as if enqueued one by one
           ctx->launches[KK_COLINV] += K;
-          ctx->launches[KK_ROW] += K;
+          ctx->launches[KK_ROW] += ks[act[a]].cat ? 2 * K : K;
           ctx->launches[KK_COLFWD] += K;
+          if (ks[act[a]].cat) ctx->launches[KK_CAT] += 4 * K;
           ctx->launches[KK_POST] += K;
           if (!cg) ctx->launches[KK_PASSA] += K;
           ctx->launches[KK_COEF] += K;
@@ -1758,6 +2012,69 @@ int check_op(wf_ctx* ctx, const wf_problem* p, int batch, const void* a, const v
   return WF_OK;
 }
 
+// One catalog's response operator: forward (s -> values at the galaxies, CM_FWD) or adjoint
+// (residuals -> field, CM_ADJ / CM_ADJ_GRAD), unscaled, on the fine grid.
+int cat_operator(wf_ctx* ctx, const wf_problem* p, const wf_catalog* cat, const void* in, void* out, int mode,
+                 void* stream) {
+  if (!ctx) return WF_EINVAL;
+  int rc = check_catalog(ctx, p, cat, false);
+  if (rc) return rc;
+  if (!in || !out) return fail(ctx, WF_EINVAL, "null array");
+  StreamScope ss(ctx, stream);
+  const int n = p->n, c = p->ncomp, N = 2 * n;
+  CatHost h;
+  rc = cat_bin(ctx, cat, n, c, h);
+  if (rc) return rc;
+  const int64_t L = (int64_t)c * n * (n / 2);
+  rc = arena_reserve(ctx, ctx->opA,
+                     cat_bytes(n, c, h.ngal) + align_up((size_t)L * 8) + align_up(3 * sizeof(Job)) + align_up(sizeof(CatDesc)));
+  if (rc) return rc;
+  Job* dj = (Job*)arena_take(ctx->opA, 3 * sizeof(Job));   // coarse job, fine forward, fine adjoint
+  CatDesc* dc = (CatDesc*)arena_take(ctx->opA, sizeof(CatDesc));
+  void* vc = arena_take(ctx->opA, (size_t)L * 8);
+  const void* twN = nullptr;
+  rc = twiddles(ctx, N, WF_F32, &twN);
+  if (rc) return rc;
+  rc = prepare(ctx, N, c, WF_F32);
+  if (rc) return rc;
+  CatDesc hc;
+  Job hj[3];
+  rc = cat_fill(ctx, ctx->opA, h, nullptr, false, hc, hj[1], hj[2]);
+  if (rc) return rc;
+  hc.jfwd = dj + 1;
+  hc.jadj = dj + 2;
+  std::memset(&hj[0], 0, sizeof(Job));
+  hj[0].mode = mode;
+  hj[0].boost_band = -1;
+  if (mode == CM_FWD) {
+    HIPCHK(unpack_launch(WF_F32, n, c, 1, in, vc, ctx->cs));
+    hj[0].vin = vc;
+    hj[1].mode = CM_FWD;
+  } else {
+    HIPCHK(cat_permute_launch((const float*)in, h.dperm, hc.r, h.ngal, c, 1, ctx->cs));
+    hj[0].vout = vc;
+    hj[2].mode = CM_ADJ;
+  }
+  HIPCHK(hipMemcpyAsync(dc, &hc, sizeof hc, hipMemcpyHostToDevice, ctx->cs));
+  HIPCHK(hipMemcpyAsync(dj, hj, sizeof hj, hipMemcpyHostToDevice, ctx->cs));
+  const ChainCfg cfg = op_cfg(ctx, WF_F32, N, c);
+  if (mode == CM_FWD) {
+    HIPCHK(cat_step(ctx, CAT_PAD, c, N / 4, dj, dc, 1));
+    HIPCHK(chain(ctx, WF_F32, N, c, CH_COLINV, dj + 1, 1, twN, &cfg));
+    HIPCHK(chain(ctx, WF_F32, N, c, CH_ROW, dj + 1, 1, twN, &cfg));
+    HIPCHK(cat_step(ctx, CAT_INTERP, c, (h.ngal + NT - 1) / NT, dj, dc, 1));
+    HIPCHK(cat_permute_launch(hc.r, h.dperm, (float*)out, h.ngal, c, 0, ctx->cs));
+  } else {
+    HIPCHK(cat_step(ctx, CAT_SPREAD, c, h.tiles * h.tiles, dj, dc, 1));
+    HIPCHK(chain(ctx, WF_F32, N, c, CH_ROW, dj + 2, 1, twN, &cfg));
+    HIPCHK(chain(ctx, WF_F32, N, c, CH_COLFWD, dj + 2, 1, twN, &cfg));
+    HIPCHK(cat_step(ctx, CAT_UNPAD, c, n / 4, dj, dc, 1));
+    HIPCHK(pack_launch(WF_F32, n, c, 1, vc, L, nullptr, 0, nullptr, out, ctx->cs));
+  }
+  HIPCHK(hipStreamSynchronize(ctx->cs));
+  return WF_OK;
+}
+
 }  // namespace
 
 // ============================================================================ C-ABI
@@ -1854,6 +2171,41 @@ int map_wf_solve(wf_ctx* ctx, const wf_problem* probs, int32_t batch, const wf_l
   for (int i = 0; i < batch; ++i)
     if (so.st[i].status != WF_SOLVE_CONVERGED) return WF_NOT_CONVERGED;
   return WF_OK;
+}
+
+int map_wf_solve_catalog(wf_ctx* ctx, const wf_problem* probs, const wf_catalog* cats, int32_t batch,
+                         const wf_lbfgs_opts* opts, void* const* s_out, wf_solve_stats* stats, void* stream) {
+  if (!ctx) return WF_EINVAL;
+  if (batch < 0 || batch > 65535 || (batch > 0 && (!probs || !cats || !s_out)))
+    return fail(ctx, WF_EINVAL, "bad batch / null arrays");
+  if (batch == 0) return WF_OK;
+  for (int i = 0; i < batch; ++i)
+    if (!s_out[i]) return fail(ctx, WF_EINVAL, "null s_out entry");
+  wf_lbfgs_opts o;
+  fill_opts(opts, o);
+  StreamScope ss(ctx, stream);
+  SolveOut so;
+  int rc = solve_core(ctx, probs, batch, o, so, nullptr, cats);
+  if (rc) return rc;
+  rc = pack_solutions(ctx, probs, batch, so, s_out);
+  if (rc) return rc;
+  HIPCHK(hipStreamSynchronize(ctx->cs));
+  fill_stats(so, batch, stats);
+  for (int i = 0; i < batch; ++i)
+    if (so.st[i].status != WF_SOLVE_CONVERGED) return WF_NOT_CONVERGED;
+  return WF_OK;
+}
+
+int wf_catalog_forward(wf_ctx* ctx, const wf_problem* prob, const wf_catalog* cat, const void* s, float* gamma,
+                       void* stream) {
+  return cat_operator(ctx, prob, cat, s, gamma, CM_FWD, stream);
+}
+
+int wf_catalog_adjoint(wf_ctx* ctx, const wf_problem* prob, const wf_catalog* cat, const float* r, void* s,
+                       int32_t flags, void* stream) {
+  if (!ctx) return WF_EINVAL;
+  if (flags & ~WF_ADJ_GRAD) return fail(ctx, WF_EINVAL, "bad flags");
+  return cat_operator(ctx, prob, cat, r, s, (flags & WF_ADJ_GRAD) ? CM_ADJ_GRAD : CM_ADJ, stream);
 }
 
 int wf_simulate(wf_ctx* ctx, const wf_problem* p, int32_t nsim, uint64_t seed, int32_t sim0, const void* draws,

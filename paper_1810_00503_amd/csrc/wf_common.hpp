@@ -190,7 +190,7 @@ enum { ST_RUNNING = -1 };   // otherwise WF_SOLVE_* values
 // kernel kinds for instrumentation
 enum {
   KK_COLINV = 0, KK_ROW = 1, KK_COLFWD = 2, KK_PASSA = 3, KK_PASSB = 4, KK_POST = 5, KK_COEF = 6,
-  KK_MISC = 7, KK_DIR = 8, KK_SIM = 9, KK_COUNT = 10
+  KK_MISC = 7, KK_DIR = 8, KK_SIM = 9, KK_CAT = 10, KK_COUNT = 11
 };
 
 struct LbState {
@@ -260,6 +260,37 @@ struct RhsJob {
   float* rhs;
   double* part;   // [gridDim.x]
   int64_t L;
+};
+
+// ------------------------------------------------------------------------ catalog response
+// A galaxy of a catalog in fine-grid coordinates rho = 2 r (the fine grid has N = 2n points per
+// side): integer cell and fraction, so that kernel offsets keep full float32 precision.
+struct GalPos {
+  int cy, cx;
+  float fy, fx;
+};
+constexpr int CAT_W = 8;      // interpolation kernel width in fine-grid points
+constexpr int CAT_TS = 16;    // fine-grid tile side of the spreading pass (256 points, one per thread)
+constexpr float CAT_BETA = 2.30f * CAT_W;   // exponential-of-semicircle shape for oversampling 2
+
+// One catalog instance: sorted galaxies, tables and the buffers of its fine-grid passes.
+struct CatDesc {
+  int n, N, c, ngal;
+  int tiles;              // fine-grid tiles per side (N / CAT_TS)
+  int nrowPart;           // row-partial slots of the coarse grid (c n / RB_MIN)
+  const GalPos* pos;      // [ngal], sorted by tile
+  const int* tileStart;   // [tiles * tiles + 1]
+  const float* e;         // [c][ngal] measurements (sorted), solver gradients only
+  const float* wgt;       // [ngal] inverse noise variance (sorted)
+  const float* T;         // [c][n][n/2] coarse internal layout: prior (or 1) x (N/n) / deconvolution
+  const float* aTab;      // prior weight of the solver variable, nullable -> 1
+  void* y2;               // fine-grid half-plane field, internal layout (complex float)
+  float* u;               // [c][N][N] fine-grid map
+  float* v;               // [c][N][N] spread residuals (may be u: interpolation is done first)
+  float* r;               // [c][ngal] residuals or field values (sorted)
+  double* partI;          // [ceil(ngal / NT)] chi^2 partials of the interpolation
+  Job* jfwd;              // this instance's fine-grid forward and adjoint jobs
+  Job* jadj;
 };
 
 // One field's band-statistic job.

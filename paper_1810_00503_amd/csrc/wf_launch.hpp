@@ -90,6 +90,14 @@ int band_nblk(int64_t L);
 // right-hand side with per-block norm partials of a float64 gradient (nblk blocks per job)
 hipError_t convert_launch(const CvtJob* jobs, int count, int64_t maxn, hipStream_t s);
 hipError_t refine_rhs_launch(const RhsJob* jobs, int count, int nblk, hipStream_t s);
+// catalog response (wf_catalog.hpp): pad (blocks = N / 4), interpolation (blocks of NT
+// galaxies of the largest catalog), spreading (blocks = tiles^2), unpad (blocks = n / 4);
+// one launch for `count` instances of equal (n, c)
+enum { CAT_PAD = 0, CAT_INTERP = 1, CAT_SPREAD = 2, CAT_UNPAD = 3 };
+hipError_t cat_launch(int which, int c, int blocks, const Job* jobs, CatDesc* cats, int count, hipStream_t s);
+hipError_t cat_table_launch(int n, int N, int c, const float* sq, const double* dk, float* T, hipStream_t s);
+hipError_t cat_permute_launch(const float* src, const int* perm, float* dst, int ngal, int c, int gather,
+                              hipStream_t s);
 // streaming copy of `bytes` (a multiple of 16) for the bandwidth reference
 hipError_t stream_copy_launch(const void* src, void* dst, uint64_t bytes, hipStream_t s);
 

@@ -37,7 +37,8 @@ def test_binding_matches_exports():
     names = _declared()
     assert sorted(_lib.EXPORTS) == names
     lib = _lib.load()
-    assert lib.wf_kernel_kinds() == 10
+    assert lib.wf_kernel_kinds() == 11
+    assert lib.wf_kernel_kind_name(10) == b"catalog"
     assert lib.wf_kernel_kind_name(9) == b"simulate"
     assert lib.wf_kernel_kind_name(8) == b"cg_dir"
     assert lib.wf_kernel_kind_name(3) == b"passA"
