@@ -389,17 +389,14 @@ struct StreamScope {
 
 // ---------------------------------------------------------------------------- catalogs
 // The catalog-level response (sec. 3.4) as a non-uniform FFT on the fine grid of N = 2n
-// points per side.  Positions are binned on the host: fine coordinate rho = 2 r wrapped into
-// [0, N), its cell floor(rho) and fraction, and a stable counting sort of the galaxies by
-// CAT_TS x CAT_TS tile, so each tile keeps the input order and the spreading sums are the
-// same on every call.
-struct CatHost {
+// points per side.  Set-up on the device, once per call and catalog: each galaxy's fine cell
+// (rho = 2 r wrapped into [0, N)), a stable radix sort of the galaxies by cell (a cell keeps
+// the input order, so every sum over galaxies has the same order on every call), and in the
+// sorted order each galaxy's cell and kernel weights and the first galaxy of every cell.
+struct CatPlan {
   int n = 0, N = 0, c = 0, ngal = 0, tiles = 0;
-  std::vector<GalPos> pos;     // sorted
-  std::vector<int> perm;       // sorted position -> input index
-  std::vector<int> tileStart;  // [tiles^2 + 1]
   const wf_catalog* src = nullptr;
-  int* dperm = nullptr;        // device copy of perm (after cat_fill)
+  uint32_t* perm = nullptr;   // device: sorted position -> input index (after cat_fill)
 };
 
 constexpr int kCatMaxGal = 1 << 27;
@@ -423,53 +420,19 @@ int check_catalog(wf_ctx* ctx, const wf_problem* p, const wf_catalog* cat, bool 
   return WF_OK;
 }
 
-int cat_bin(wf_ctx* ctx, const wf_catalog* cat, int n, int c, CatHost& h) {
+void cat_plan(const wf_catalog* cat, int n, int c, CatPlan& h) {
   h.n = n;
   h.N = 2 * n;
   h.c = c;
   h.ngal = cat->ngal;
   h.tiles = h.N / CAT_TS;
   h.src = cat;
-  std::vector<double> hp((size_t)2 * h.ngal);
-  HIPCHK(hipMemcpyAsync(hp.data(), cat->pos, sizeof(double) * hp.size(), hipMemcpyDeviceToHost, ctx->cs));
-  HIPCHK(hipStreamSynchronize(ctx->cs));
-  const int nt = h.tiles * h.tiles;
-  std::vector<GalPos> gp(h.ngal);
-  std::vector<int> key(h.ngal);
-  h.tileStart.assign(nt + 1, 0);
-  for (int g = 0; g < h.ngal; ++g) {
-    int cell[2];
-    float frac[2];
-    for (int a = 0; a < 2; ++a) {
-      const double x = hp[2 * (size_t)g + a];
-      if (!std::isfinite(x)) return fail(ctx, WF_ENONFINITE, "non-finite galaxy position");
-      double r = std::fmod(2.0 * x, (double)h.N);
-      if (r < 0.0) r += h.N;
-      const double fl = std::floor(r);
-      int ci = (int)fl;
-      float fr = (float)(r - fl);
-      if (fr >= 1.0f) {   // rounded up to the next cell
-        fr = 0.0f;
-        ++ci;
-      }
-      if (ci >= h.N) ci -= h.N;   // r == N after the wrap of a tiny negative value
-      cell[a] = ci;
-      frac[a] = fr;
-    }
-    gp[g] = GalPos{cell[0], cell[1], frac[0], frac[1]};
-    key[g] = (cell[0] / CAT_TS) * h.tiles + cell[1] / CAT_TS;
-    ++h.tileStart[key[g] + 1];
-  }
-  for (int t = 0; t < nt; ++t) h.tileStart[t + 1] += h.tileStart[t];
-  std::vector<int> at(h.tileStart.begin(), h.tileStart.end() - 1);
-  h.perm.resize(h.ngal);
-  h.pos.resize(h.ngal);
-  for (int g = 0; g < h.ngal; ++g) {
-    const int q = at[key[g]]++;
-    h.perm[q] = g;
-    h.pos[q] = gp[g];
-  }
-  return WF_OK;
+}
+
+int cat_key_bits(int N) {
+  int b = 1;
+  while ((1ull << b) < (unsigned long long)N * N) ++b;
+  return b;
 }
 
 // 1 / phi^(k / N) for k = 0 .. n/2, phi the spreading kernel exp(beta (sqrt(1 - (2z/W)^2) - 1))
@@ -492,22 +455,36 @@ void cat_deconv(int n, int N, std::vector<double>& dk) {
   }
 }
 
-size_t cat_bytes(int n, int c, int ngal) {
-  const size_t N = 2 * (size_t)n, tiles = N / CAT_TS, g = (size_t)ngal, C = (size_t)c;
-  return align_up(sizeof(GalPos) * g) + align_up(4 * g) + align_up(4 * (tiles * tiles + 1)) + 2 * align_up(4 * C * g) +
-         align_up(4 * g) + align_up(4 * C * n * (n / 2)) + align_up(8 * ((g + NT - 1) / NT)) +
-         align_up(8 * ((size_t)n / 2 + 1)) + 2 * align_up(8 * C * N * (N / 2)) + align_up(4 * C * N * N);
+int cat_sort_bytes(wf_ctx* ctx, int N, int ngal, size_t& bytes) {
+  bytes = 0;
+  HIPCHK(cat_sort_launch(nullptr, &bytes, nullptr, nullptr, nullptr, nullptr, ngal, cat_key_bits(N), ctx->cs));
+  return WF_OK;
 }
 
-// Device copy of one binned catalog: the descriptor (host copy cd; jfwd / jadj are set by the
-// caller), its fine-grid forward and adjoint jobs (host copies jf, ja, switched off), the table
-// T from the scale table sq (nullptr: the unscaled operator) and, for solves, the measurements
-// and weights gathered into the sorted order.
-int cat_fill(wf_ctx* ctx, Arena& A, CatHost& h, const void* sq, bool solve, CatDesc& cd, Job& jf, Job& ja) {
+size_t cat_bytes(int n, int c, int ngal, size_t sortBytes) {
+  const size_t N = 2 * (size_t)n, g = (size_t)ngal, C = (size_t)c;
+  return 4 * align_up(4 * g) + align_up(sortBytes) + align_up(sizeof(int)) + align_up(8 * g) +
+         align_up(4 * CAT_REC * g) + align_up(4 * (N * N + 1)) + 2 * align_up(4 * C * g) + align_up(4 * g) +
+         align_up(4 * C * n * (n / 2)) + align_up(8 * ((g + NT - 1) / NT)) + align_up(8 * ((size_t)n / 2 + 1)) +
+         2 * align_up(8 * C * N * (N / 2)) + align_up(4 * C * N * N);
+}
+
+// Device set-up of one catalog: keys, sort, windows and cell table; the descriptor (host copy
+// cd; jfwd / jadj are set by the caller), its fine-grid forward and adjoint jobs (host copies
+// jf, ja, switched off), the table T from the scale table sq (nullptr: the unscaled operator)
+// and, for solves, the measurements and weights gathered into the sorted order.
+int cat_fill(wf_ctx* ctx, Arena& A, CatPlan& h, size_t sortBytes, const void* sq, bool solve, CatDesc& cd, Job& jf,
+             Job& ja) {
   const int n = h.n, N = h.N, c = h.c, g = h.ngal;
-  GalPos* dpos = (GalPos*)arena_take(A, sizeof(GalPos) * g);
-  int* dperm = (int*)arena_take(A, 4 * (size_t)g);
-  int* dts = (int*)arena_take(A, 4 * h.tileStart.size());
+  uint32_t* kin = (uint32_t*)arena_take(A, 4 * (size_t)g);
+  uint32_t* kout = (uint32_t*)arena_take(A, 4 * (size_t)g);
+  uint32_t* vin = (uint32_t*)arena_take(A, 4 * (size_t)g);
+  uint32_t* perm = (uint32_t*)arena_take(A, 4 * (size_t)g);
+  void* temp = arena_take(A, sortBytes);
+  int* bad = (int*)arena_take(A, sizeof(int));
+  int2* cell = (int2*)arena_take(A, 8 * (size_t)g);
+  float4* rec = (float4*)arena_take(A, 4 * CAT_REC * (size_t)g);
+  int* cellStart = (int*)arena_take(A, 4 * ((size_t)N * N + 1));
   float* de = (float*)arena_take(A, 4 * (size_t)c * g);
   float* dr = (float*)arena_take(A, 4 * (size_t)c * g);
   float* dw = (float*)arena_take(A, 4 * (size_t)g);
@@ -520,17 +497,22 @@ int cat_fill(wf_ctx* ctx, Arena& A, CatHost& h, const void* sq, bool solve, CatD
   if (A.used > A.cap) return fail(ctx, WF_ENOMEM, "internal: catalog workspace overflow");
   std::vector<double> dk;
   cat_deconv(n, N, dk);
-  HIPCHK(hipMemcpyAsync(dpos, h.pos.data(), sizeof(GalPos) * g, hipMemcpyHostToDevice, ctx->cs));
-  HIPCHK(hipMemcpyAsync(dperm, h.perm.data(), 4 * (size_t)g, hipMemcpyHostToDevice, ctx->cs));
-  HIPCHK(hipMemcpyAsync(dts, h.tileStart.data(), 4 * h.tileStart.size(), hipMemcpyHostToDevice, ctx->cs));
+  int hbad = 0;
+  HIPCHK(hipMemcpyAsync(bad, &hbad, sizeof(int), hipMemcpyHostToDevice, ctx->cs));
   HIPCHK(hipMemcpyAsync(ddk, dk.data(), 8 * dk.size(), hipMemcpyHostToDevice, ctx->cs));
-  HIPCHK(hipStreamSynchronize(ctx->cs));   // dk is local
+  HIPCHK(cat_keys_launch(h.src->pos, g, N, kin, vin, bad, ctx->cs));
+  size_t tb = sortBytes;
+  HIPCHK(cat_sort_launch(temp, &tb, kin, kout, vin, perm, g, cat_key_bits(N), ctx->cs));
+  HIPCHK(cat_prep_launch(h.src->pos, kout, perm, g, N, cell, rec, cellStart, ctx->cs));
+  HIPCHK(hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, ctx->cs));
+  HIPCHK(hipStreamSynchronize(ctx->cs));   // hbad, dk are local
+  if (hbad) return fail(ctx, WF_ENONFINITE, "non-finite galaxy position");
   HIPCHK(cat_table_launch(n, N, c, (const float*)sq, ddk, dT, ctx->cs));
   if (solve) {
-    HIPCHK(cat_permute_launch(h.src->e, dperm, de, g, c, 1, ctx->cs));
-    HIPCHK(cat_permute_launch(h.src->wgt, dperm, dw, g, 1, 1, ctx->cs));
+    HIPCHK(cat_permute_launch(h.src->e, (const int*)perm, de, g, c, 1, 0, ctx->cs));
+    HIPCHK(cat_permute_launch(h.src->wgt, (const int*)perm, dw, g, 1, 1, 0, ctx->cs));
   }
-  h.dperm = dperm;
+  h.perm = perm;
   std::memset(&cd, 0, sizeof cd);
   cd.n = n;
   cd.N = N;
@@ -538,8 +520,9 @@ int cat_fill(wf_ctx* ctx, Arena& A, CatHost& h, const void* sq, bool solve, CatD
   cd.ngal = g;
   cd.tiles = h.tiles;
   cd.nrowPart = c * n / RB_MIN;
-  cd.pos = dpos;
-  cd.tileStart = dts;
+  cd.cell = cell;
+  cd.rec = rec;
+  cd.cellStart = cellStart;
   cd.e = de;
   cd.wgt = dw;
   cd.T = dT;
@@ -1052,10 +1035,12 @@ int solve_core(wf_ctx* ctx, const wf_problem* probs, int B, const wf_lbfgs_opts&
       ks.push_back(k);
     }
   }
-  // catalogs binned on the fine grid (host)
-  std::vector<CatHost> ch(isCat ? B : 0);
+  // catalogs: shapes and the sorts' workspaces
+  std::vector<CatPlan> ch(isCat ? B : 0);
+  std::vector<size_t> sortB(ch.size(), 0);
   for (int i = 0; i < (int)ch.size(); ++i) {
-    int rc = cat_bin(ctx, &cats[i], probs[i].n, probs[i].ncomp, ch[i]);
+    cat_plan(&cats[i], probs[i].n, probs[i].ncomp, ch[i]);
+    int rc = cat_sort_bytes(ctx, ch[i].N, ch[i].ngal, sortB[i]);
     if (rc) return rc;
   }
   // distinct priors within the call
@@ -1106,7 +1091,7 @@ int solve_core(wf_ctx* ctx, const wf_problem* probs, int B, const wf_lbfgs_opts&
       k.nblkI = 1;
       for (int ui : k.members) {
         k.nblkI = std::max(k.nblkI, (ch[ui].ngal + NT - 1) / NT);
-        total += cat_bytes(k.n, k.c, ch[ui].ngal);
+        total += cat_bytes(k.n, k.c, ch[ui].ngal, sortB[ui]);
       }
       total += 2 * align_up(sizeof(Job) * k.members.size()) + align_up(sizeof(CatDesc) * k.members.size());
       k.cfgN = op_cfg(ctx, WF_F32, k.N, k.c);
@@ -1182,7 +1167,7 @@ int solve_core(wf_ctx* ctx, const wf_problem* probs, int B, const wf_lbfgs_opts&
       out.prior[ui] = ptabs[pidx[ui]];
       out.order[ui] = gi;
       if (k.cat) {
-        rc = cat_fill(ctx, A, ch[ui], D.sq, true, hcd[j], hjf[j], hja[j]);
+        rc = cat_fill(ctx, A, ch[ui], sortB[ui], D.sq, true, hcd[j], hjf[j], hja[j]);
         if (rc) return rc;
         hcd[j].jfwd = k.fjobs + j;
         hcd[j].jadj = k.ajobs + j;
@@ -2022,12 +2007,14 @@ int cat_operator(wf_ctx* ctx, const wf_problem* p, const wf_catalog* cat, const 
   if (!in || !out) return fail(ctx, WF_EINVAL, "null array");
   StreamScope ss(ctx, stream);
   const int n = p->n, c = p->ncomp, N = 2 * n;
-  CatHost h;
-  rc = cat_bin(ctx, cat, n, c, h);
+  CatPlan h;
+  cat_plan(cat, n, c, h);
+  size_t sortBytes = 0;
+  rc = cat_sort_bytes(ctx, N, h.ngal, sortBytes);
   if (rc) return rc;
   const int64_t L = (int64_t)c * n * (n / 2);
-  rc = arena_reserve(ctx, ctx->opA,
-                     cat_bytes(n, c, h.ngal) + align_up((size_t)L * 8) + align_up(3 * sizeof(Job)) + align_up(sizeof(CatDesc)));
+  rc = arena_reserve(ctx, ctx->opA, cat_bytes(n, c, h.ngal, sortBytes) + align_up((size_t)L * 8) +
+                                        align_up(3 * sizeof(Job)) + align_up(sizeof(CatDesc)));
   if (rc) return rc;
   Job* dj = (Job*)arena_take(ctx->opA, 3 * sizeof(Job));   // coarse job, fine forward, fine adjoint
   CatDesc* dc = (CatDesc*)arena_take(ctx->opA, sizeof(CatDesc));
@@ -2039,7 +2026,7 @@ int cat_operator(wf_ctx* ctx, const wf_problem* p, const wf_catalog* cat, const 
   if (rc) return rc;
   CatDesc hc;
   Job hj[3];
-  rc = cat_fill(ctx, ctx->opA, h, nullptr, false, hc, hj[1], hj[2]);
+  rc = cat_fill(ctx, ctx->opA, h, sortBytes, nullptr, false, hc, hj[1], hj[2]);
   if (rc) return rc;
   hc.jfwd = dj + 1;
   hc.jadj = dj + 2;
@@ -2051,7 +2038,7 @@ int cat_operator(wf_ctx* ctx, const wf_problem* p, const wf_catalog* cat, const 
     hj[0].vin = vc;
     hj[1].mode = CM_FWD;
   } else {
-    HIPCHK(cat_permute_launch((const float*)in, h.dperm, hc.r, h.ngal, c, 1, ctx->cs));
+    HIPCHK(cat_permute_launch((const float*)in, (const int*)h.perm, hc.r, h.ngal, c, 1, 1, ctx->cs));
     hj[0].vout = vc;
     hj[2].mode = CM_ADJ;
   }
@@ -2063,7 +2050,7 @@ int cat_operator(wf_ctx* ctx, const wf_problem* p, const wf_catalog* cat, const 
     HIPCHK(chain(ctx, WF_F32, N, c, CH_COLINV, dj + 1, 1, twN, &cfg));
     HIPCHK(chain(ctx, WF_F32, N, c, CH_ROW, dj + 1, 1, twN, &cfg));
     HIPCHK(cat_step(ctx, CAT_INTERP, c, (h.ngal + NT - 1) / NT, dj, dc, 1));
-    HIPCHK(cat_permute_launch(hc.r, h.dperm, (float*)out, h.ngal, c, 0, ctx->cs));
+    HIPCHK(cat_permute_launch(hc.r, (const int*)h.perm, (float*)out, h.ngal, c, 0, 1, ctx->cs));
   } else {
     HIPCHK(cat_step(ctx, CAT_SPREAD, c, h.tiles * h.tiles, dj, dc, 1));
     HIPCHK(chain(ctx, WF_F32, N, c, CH_ROW, dj + 2, 1, twN, &cfg));

@@ -6,18 +6,24 @@
 //   pad      coarse field -> fine half-plane spectrum, each band mode scaled by T_k
 //            = (prior scale) (N/n) / (phi^(ky/N) phi^(kx/N)) (deconvolution of the kernel);
 //   forward  the transform passes of the chain at size N (column inverse, row) -> fine map u;
-//   interp   per galaxy, sum of u over the CAT_W x CAT_W fine points around rho = 2 r with
-//            the separable exponential-of-semicircle kernel phi -> gamma(r_g), and the
-//            weighted residual (solver) or the value (forward operator);
-//   spread   the adjoint of interp: per fine-grid tile, each point gathers phi-weighted
-//            residuals of the galaxies whose window covers it (deterministic order);
+//   interp   per galaxy, sum of u over the (CAT_W + 1)^2 fine points around its cell (the
+//            kernel phi is 0 beyond W/2, so these hold every point it reaches) with the
+//            separable exponential-of-semicircle weights -> gamma(r_g), and the weighted
+//            residual (solver) or the value (forward operator);
+//   spread   the adjoint of interp with the same weights, per fine-grid tile in two passes:
+//            along x per galaxy cell row, then the CAT_W + 1 rows per point, each sum in a
+//            fixed order;
 //   adjoint  the transform passes at size N (row, column forward) -> fine spectrum;
 //   unpad    band modes back to the coarse layout, times T_k, plus the solver's prior term
 //            and the dot partials of the chain's column-forward pass.
 //
 // Inside the batched solver these replace the three coarse passes of a curvature product or
 // exact gradient; the jobs the solver writes each iteration drive them as they drive the
-// chain.  The kernel: phi(z) = exp(beta (sqrt(1 - (2z/W)^2) - 1)) on |z| <= W/2, beta = 2.3 W for
+// chain.  Set-up, once per call: each galaxy's fine cell (key), a stable radix sort of the
+// galaxies by cell, and in the sorted order the cells, a 48-byte record per galaxy (its CAT_W + 1
+// weights along y and the fraction of its x coordinate, from which a pass computes the x weight
+// it needs: fewer bytes per galaxy than a stored x row, which the spreading pass is bound by)
+// and the first galaxy of every cell.  The kernel: phi(z) = exp(beta (sqrt(1 - (2z/W)^2) - 1)) on |z| <= W/2, beta = 2.3 W for
 // oversampling 2 (Barnett, Magland & af Klinteberg, SIAM J. Sci. Comput. 41, 2019); its
 // Fourier transform is tabulated on the host in float64.
 #pragma once
@@ -31,12 +37,18 @@ __device__ __forceinline__ float es_kernel(float z) {
   return q >= 0.0f ? expf(CAT_BETA * (sqrtf(q) - 1.0f)) : 0.0f;
 }
 
-// first fine point of a galaxy's window, ceil(rho - W/2), and the CAT_W weights phi(rho - j)
-__device__ __forceinline__ int es_window(int cell, float frac, float (&w)[CAT_W]) {
-  const int off = frac > 0.0f ? -(CAT_W / 2 - 1) : -(CAT_W / 2);
-#pragma unroll
-  for (int t = 0; t < CAT_W; ++t) w[t] = es_kernel(frac - (float)(off + t));
-  return cell + off;
+// j in [-N, 2N) -> j mod N
+__device__ __forceinline__ int cat_wrap(int j, int N) {
+  j += j < 0 ? N : 0;
+  return j >= N ? j - N : j;
+}
+
+// XCD-aware work order: the dispatcher hands work-groups to the 8 XCDs in turn, so one XCD runs
+// every 8th; logical block of work-group b (of nblk) such that each XCD takes one contiguous
+// range of logical blocks (neighbouring tiles, which read the same galaxies, share its L2)
+__device__ __forceinline__ int xcd_order(int b, int nblk) {
+  const int x = b & 7, q = nblk >> 3, rem = nblk & 7;
+  return x * q + min(x, rem) + (b >> 3);
 }
 
 __device__ __forceinline__ bool cat_solver_mode(int mode) { return mode == CM_HV || mode == CM_GRAD; }
@@ -106,31 +118,40 @@ __global__ __launch_bounds__(NT) void k_cat_interp(const Job* __restrict__ jobs,
   const int mode = jb.mode;
   if (!(cat_solver_mode(mode) || mode == CM_FWD)) return;
   const CatDesc& cd = cats[i];
-  if ((int)blockIdx.x * NT >= cd.ngal) return;   // the grid covers the class's largest catalog
+  const int lb = xcd_order(blockIdx.x, gridDim.x);
+  if (lb * NT >= cd.ngal) return;   // the grid covers the class's largest catalog
   __shared__ double red[NT / 64];
-  const int g = blockIdx.x * NT + threadIdx.x;
+  const int g = lb * NT + threadIdx.x;
   double acc = 0.0;
   if (g < cd.ngal) {
     const int N = cd.N;
-    const GalPos gp = cd.pos[g];
-    float wy[CAT_W], wx[CAT_W];
-    const int jy0 = es_window(gp.cy, gp.fy, wy), jx0 = es_window(gp.cx, gp.fx, wx);
-    int jx[CAT_W];
+    const int2 c0 = cd.cell[g];
+    float w[2 * CAT_D];
+    {
+      const float4 a0 = cd.rec[3 * (size_t)g], a1 = cd.rec[3 * (size_t)g + 1], a2 = cd.rec[3 * (size_t)g + 2];
+      const float rw[CAT_REC] = {a0.x, a0.y, a0.z, a0.w, a1.x, a1.y, a1.z, a1.w, a2.x, a2.y, a2.z, a2.w};
 #pragma unroll
-    for (int t = 0; t < CAT_W; ++t) jx[t] = (jx0 + t + N) % N;
+      for (int t = 0; t < CAT_D; ++t) {
+        w[t] = rw[t];
+        w[CAT_D + t] = es_kernel(rw[CAT_D] + (float)(CAT_H - t));
+      }
+    }
+    int jx[CAT_D];
+#pragma unroll
+    for (int t = 0; t < CAT_D; ++t) jx[t] = cat_wrap(c0.y - CAT_H + t, N);
     float gam[C];
 #pragma unroll
     for (int cc = 0; cc < C; ++cc) gam[cc] = 0.0f;
-#pragma unroll
-    for (int ty = 0; ty < CAT_W; ++ty) {
-      const int jy = (jy0 + ty + N) % N;
+#pragma unroll 3
+    for (int ty = 0; ty < CAT_D; ++ty) {
+      const int jy = cat_wrap(c0.x - CAT_H + ty, N);
 #pragma unroll
       for (int cc = 0; cc < C; ++cc) {
         const float* row = cd.u + ((size_t)cc * N + jy) * N;
         float a = 0.0f;
 #pragma unroll
-        for (int tx = 0; tx < CAT_W; ++tx) a += wx[tx] * row[jx[tx]];
-        gam[cc] += wy[ty] * a;
+        for (int tx = 0; tx < CAT_D; ++tx) a += w[CAT_D + tx] * row[jx[tx]];
+        gam[cc] += w[ty] * a;
       }
     }
     const float wg = mode == CM_FWD ? 1.0f : cd.wgt[g];
@@ -146,7 +167,7 @@ __global__ __launch_bounds__(NT) void k_cat_interp(const Job* __restrict__ jobs,
       } else {
         r = gam[cc];
       }
-      cd.r[(size_t)cc * cd.ngal + g] = r;
+      cd.r[(size_t)g * C + cc] = r;
     }
   }
   if (mode == CM_GRAD) {
@@ -157,80 +178,130 @@ __global__ __launch_bounds__(NT) void k_cat_interp(const Job* __restrict__ jobs,
       double t = 0.0;
 #pragma unroll
       for (int k = 0; k < NT / 64; ++k) t += red[k];
-      cd.partI[blockIdx.x] = t;
+      cd.partI[lb] = t;
     }
   }
 }
 
 // ------------------------------------------------------------------------ spreading
-// grid (tiles * tiles, instances), NT = CAT_TS^2 threads, one fine point each: v(j) = sum over
-// the galaxies of the tile and its neighbours (whose windows can reach it) of phi phi r, the
-// galaxies staged through LDS in chunks of NT and summed in their sorted order.  Block 0 of an
-// exact gradient also reduces the interpolation's chi^2 partials (one per NT galaxies) into
-// the residual slots the solver reads.
+// grid (tiles * tiles, instances), CAT_SPREAD_NT threads: the adjoint of interp on a CAT_TS x
+// CAT_TS tile of fine points, v(jy, jx) = sum_g wy_g[jy - cy_g + H] wx_g[jx - cx_g + H] r_g.
+// A galaxy reaches the tile only from the cell rows of the tile widened by H on each side
+// (CAT_ROWS rows).  Pass 1, one thread per (widened row R, tile column jx): the galaxies of the
+// cells jx - H .. jx + H of row R, consecutive in sorted order (two runs where the row wraps),
+// t_d = sum wy_g[d] wx_g[e] r_g for d = 0 .. 2H, e = jx + H - (cell of g), in registers, CAT_U
+// galaxies at a time so that their loads are in flight together.
+// Pass 2, one thread per point: v(jy, jx) = sum_d t_d of row R = jy + H - d, in order of d.
+// Every pair it forms contributes, and each point's sum has the same order on every call.
+// Block 0 of an exact gradient also reduces the interpolation's chi^2 partials (one per NT
+// galaxies, in a fixed order) into the residual slots the solver reads.
+constexpr int CAT_ROWS = CAT_TS + 2 * CAT_H;
+constexpr int CAT_SPREAD_NT = CAT_ROWS * CAT_TS;
+constexpr int CAT_U = 2;   // galaxies per step of a pass-1 thread
 template <int C>
-__global__ __launch_bounds__(NT) void k_cat_spread(const Job* __restrict__ jobs, const CatDesc* __restrict__ cats) {
+__global__ __launch_bounds__(CAT_SPREAD_NT) void k_cat_spread(const Job* __restrict__ jobs,
+                                                                const CatDesc* __restrict__ cats) {
   const int i = blockIdx.y;
   const Job& jb = jobs[i];
   const int mode = jb.mode;
   if (!(cat_solver_mode(mode) || mode == CM_ADJ || mode == CM_ADJ_GRAD)) return;
   const CatDesc& cd = cats[i];
-  const int tiles = cd.tiles, N = cd.N;
+  const int tiles = cd.tiles, N = cd.N, ngal = cd.ngal;
+  __shared__ float tsh[CAT_D][C][CAT_ROWS][CAT_TS];   // [d][c][widened row][column]
+  __shared__ double red[CAT_SPREAD_NT / 64];
   if (mode == CM_GRAD && blockIdx.x == 0) {
+    // strided per-thread sums, then the waves' fixed-order shuffle trees, then wave order
+    const int nb = (ngal + NT - 1) / NT;
+    double a = 0.0;
+    for (int k = threadIdx.x; k < nb; k += CAT_SPREAD_NT) a += cd.partI[k];
+    a = wave_sum(a);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = a;
+    __syncthreads();
     double t = 0.0;
     if (threadIdx.x == 0)
-      for (int k = 0; k < (cd.ngal + NT - 1) / NT; ++k) t += cd.partI[k];
-    for (int k = threadIdx.x; k < cd.nrowPart; k += NT) jb.part[PK_RES * jb.pstride + k] = k == 0 ? t : 0.0;
+      for (int w = 0; w < CAT_SPREAD_NT / 64; ++w) t += red[w];
+    for (int k = threadIdx.x; k < cd.nrowPart; k += CAT_SPREAD_NT)
+      jb.part[PK_RES * jb.pstride + k] = k == 0 ? t : 0.0;
   }
   if ((int)blockIdx.x >= tiles * tiles) return;
-  __shared__ int sjy[NT], sjx[NT];
-  __shared__ float swy[NT][CAT_W + 1], swx[NT][CAT_W + 1];
-  __shared__ float sr[C][NT];
-  const int ty = blockIdx.x / tiles, tx = blockIdx.x % tiles;
-  const int jy = ty * CAT_TS + (int)threadIdx.x / CAT_TS, jx = tx * CAT_TS + (int)threadIdx.x % CAT_TS;
-  float acc[C];
+  const int tb = xcd_order(blockIdx.x, tiles * tiles);
+  const int ty = tb / tiles, tx = tb % tiles;
+  {
+    const int r = (int)threadIdx.x / CAT_TS, col = (int)threadIdx.x % CAT_TS;
+    const int jx = tx * CAT_TS + col;
+    const int* cs = cd.cellStart + (size_t)cat_wrap(ty * CAT_TS - CAT_H + r, N) * N;
+    const float4* __restrict__ rec = cd.rec;
+    const float* __restrict__ rr = cd.r;
+    float t[CAT_D][C];
 #pragma unroll
-  for (int cc = 0; cc < C; ++cc) acc[cc] = 0.0f;
-  // distinct neighbour tiles: all three offsets, or every tile of a grid of fewer than three
-  const int nd = tiles >= 3 ? 3 : tiles;
-  for (int ay = 0; ay < nd; ++ay) {
-    for (int ax = 0; ax < nd; ++ax) {
-      const int ny = (ty + (nd == 3 ? ay - 1 : ay) + tiles) % tiles;
-      const int nx = (tx + (nd == 3 ? ax - 1 : ax) + tiles) % tiles;
-      const int nt = ny * tiles + nx;
-      const int g0 = cd.tileStart[nt], g1 = cd.tileStart[nt + 1];
-      for (int base = g0; base < g1; base += NT) {
-        const int cnt = min(NT, g1 - base);
-        __syncthreads();
-        if ((int)threadIdx.x < cnt) {
-          const int g = base + threadIdx.x;
-          const GalPos gp = cd.pos[g];
-          float wy[CAT_W], wx[CAT_W];
-          sjy[threadIdx.x] = es_window(gp.cy, gp.fy, wy);
-          sjx[threadIdx.x] = es_window(gp.cx, gp.fx, wx);
+    for (int d = 0; d < CAT_D; ++d)
 #pragma unroll
-          for (int t = 0; t < CAT_W; ++t) {
-            swy[threadIdx.x][t] = wy[t];
-            swx[threadIdx.x][t] = wx[t];
+      for (int cc = 0; cc < C; ++cc) t[d][cc] = 0.0f;
+    // first galaxy of each of the thread's cells jx - H + m, m = 0 .. 2H, and the end of the last
+    int beg[CAT_D + 1];
+#pragma unroll
+    for (int m = 0; m < CAT_D; ++m) beg[m] = cs[cat_wrap(jx - CAT_H + m, N)];
+    beg[CAT_D] = cs[cat_wrap(jx + CAT_H, N) + 1];
+    // the row wraps between cells m = mw - 1 and mw (mw = CAT_D: no wrap)
+    const int mw = jx - CAT_H < 0 ? CAT_H - jx : (jx + CAT_H >= N ? N - (jx - CAT_H) : CAT_D);
+    // beg[mw] by selects (a register array indexed at run time would live in scratch)
+    int begW = beg[CAT_D];
+#pragma unroll
+    for (int k = 0; k < CAT_D; ++k) begW = k == mw ? beg[k] : begW;
+    for (int run = 0; run < 2; ++run) {
+      const int m0 = run == 0 ? 0 : mw, m1 = run == 0 ? mw : CAT_D;   // cells [m0, m1)
+      if (m1 <= m0) continue;
+      const int ga = run == 0 ? beg[0] : begW;
+      const int gb = m1 == CAT_D ? beg[CAT_D] : cs[N];   // a wrapping run ends with the row
+      for (int g0 = ga; g0 < gb; g0 += CAT_U) {
+#pragma unroll
+        for (int j = 0; j < CAT_U; ++j) {
+          const bool ok = g0 + j < gb;
+          const int g = ok ? g0 + j : gb - 1;
+          int m = m0;   // cell of g: the last m in [m0, m1) with beg[m] <= g
+#pragma unroll
+          for (int k = 1; k < CAT_D; ++k) m += (k > m0 && k < m1 && beg[k] <= g) ? 1 : 0;
+          const int e = 2 * CAT_H - m;
+          const float4 a0 = rec[3 * (size_t)g], a1 = rec[3 * (size_t)g + 1], a2 = rec[3 * (size_t)g + 2];
+          const float w[CAT_REC] = {a0.x, a0.y, a0.z, a0.w, a1.x, a1.y, a1.z, a1.w, a2.x, a2.y, a2.z, a2.w};
+          const float wx = ok ? es_kernel(w[CAT_D] + (float)(CAT_H - e)) : 0.0f;
+          float rv[C];
+          if constexpr (C == 2) {
+            const float2 q = reinterpret_cast<const float2*>(rr)[g];
+            rv[0] = q.x;
+            rv[1] = q.y;
+          } else {
+            rv[0] = rr[g];
           }
 #pragma unroll
-          for (int cc = 0; cc < C; ++cc) sr[cc][threadIdx.x] = cd.r[(size_t)cc * cd.ngal + g];
-        }
-        __syncthreads();
-        for (int q = 0; q < cnt; ++q) {
-          const int oy = (jy - sjy[q] + 2 * N) % N;
-          const int ox = (jx - sjx[q] + 2 * N) % N;
-          if (oy < CAT_W && ox < CAT_W) {
-            const float w = swy[q][oy] * swx[q][ox];
+          for (int cc = 0; cc < C; ++cc) {
+            const float a = wx * rv[cc];
 #pragma unroll
-            for (int cc = 0; cc < C; ++cc) acc[cc] += w * sr[cc][q];
+            for (int d = 0; d < CAT_D; ++d) t[d][cc] += w[d] * a;
           }
         }
       }
     }
-  }
 #pragma unroll
-  for (int cc = 0; cc < C; ++cc) cd.v[((size_t)cc * N + jy) * N + jx] = acc[cc];
+    for (int d = 0; d < CAT_D; ++d)
+#pragma unroll
+      for (int cc = 0; cc < C; ++cc) tsh[d][cc][r][col] = t[d][cc];
+  }
+  __syncthreads();
+  if ((int)threadIdx.x < CAT_TS * CAT_TS) {
+    const int py = (int)threadIdx.x / CAT_TS, px = (int)threadIdx.x % CAT_TS;
+    const int jy = ty * CAT_TS + py, jx = tx * CAT_TS + px;
+    float acc[C];
+#pragma unroll
+    for (int cc = 0; cc < C; ++cc) acc[cc] = 0.0f;
+    // galaxy row R = jy + H - d is widened row py + 2H - d
+#pragma unroll
+    for (int d = 0; d < CAT_D; ++d)
+#pragma unroll
+      for (int cc = 0; cc < C; ++cc) acc[cc] += tsh[d][cc][py + 2 * CAT_H - d][px];
+#pragma unroll
+    for (int cc = 0; cc < C; ++cc) cd.v[((size_t)cc * N + jy) * N + jx] = acc[cc];
+  }
 }
 
 // ------------------------------------------------------------------------ unpad
@@ -347,16 +418,89 @@ __global__ void k_cat_table(int n, int N, int C, const float* __restrict__ sq, c
   }
 }
 
-// dst[c][g] = src[c][perm[g]] (to the sorted order) or dst[c][perm[g]] = src[c][g] (back)
+// ------------------------------------------------------------------------ set-up
+// fine-grid cell and fraction of coordinate x (pixel units): rho = 2 x wrapped into [0, N)
+__device__ __forceinline__ void cat_cell(double x, int N, int& cell, float& frac) {
+  double r = fmod(2.0 * x, (double)N);
+  if (r < 0.0) r += (double)N;
+  const double fl = floor(r);
+  int ci = (int)fl;
+  float fr = (float)(r - fl);
+  if (fr >= 1.0f) {   // rounded up to the next cell
+    fr = 0.0f;
+    ++ci;
+  }
+  if (ci >= N) ci -= N;   // r == N after the wrap of a tiny negative value
+  cell = ci;
+  frac = fr;
+}
+
+// key[g] = fine cell (row-major) of galaxy g, idx[g] = g; *bad = 1 if a position is not finite
+__global__ void k_cat_keys(const double* __restrict__ pos, int ngal, int N, uint32_t* __restrict__ key,
+                           uint32_t* __restrict__ idx, int* __restrict__ bad) {
+  for (int g = blockIdx.x * blockDim.x + threadIdx.x; g < ngal; g += gridDim.x * blockDim.x) {
+    const double y = pos[2 * (size_t)g], x = pos[2 * (size_t)g + 1];
+    uint32_t k = 0;
+    if (isfinite(y) && isfinite(x)) {
+      int cy, cx;
+      float fy, fx;
+      cat_cell(y, N, cy, fy);
+      cat_cell(x, N, cx, fx);
+      k = (uint32_t)cy * (uint32_t)N + (uint32_t)cx;
+    } else {
+      *bad = 1;
+    }
+    key[g] = k;
+    idx[g] = (uint32_t)g;
+  }
+}
+
+// In the sorted order (skey, perm from the stable sort): cells, records (the weights
+// phi(rho_y - j) at j = cell - H .. cell + H and the fraction of rho_x) and the first galaxy of
+// every cell (cells before the first galaxy start at 0, after the last at ngal)
+__global__ void k_cat_prep(const double* __restrict__ pos, const uint32_t* __restrict__ skey,
+                           const uint32_t* __restrict__ perm, int ngal, int N, int2* __restrict__ cell,
+                           float4* __restrict__ rec, int* __restrict__ cellStart) {
+  const uint32_t ncell = (uint32_t)N * (uint32_t)N;
+  for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < ngal; q += gridDim.x * blockDim.x) {
+    const uint32_t g = perm[q];
+    const double y = pos[2 * (size_t)g], x = pos[2 * (size_t)g + 1];
+    int cy = 0, cx = 0;
+    float fy = 0.0f, fx = 0.0f;
+    if (isfinite(y) && isfinite(x)) {
+      cat_cell(y, N, cy, fy);
+      cat_cell(x, N, cx, fx);
+    }
+    cell[q] = make_int2(cy, cx);
+    float w[CAT_REC];
+#pragma unroll
+    for (int t = 0; t < CAT_D; ++t) w[t] = es_kernel(fy + (float)(CAT_H - t));
+    w[CAT_D] = fx;
+#pragma unroll
+    for (int t = CAT_D + 1; t < CAT_REC; ++t) w[t] = 0.0f;
+#pragma unroll
+    for (int k = 0; k < CAT_REC / 4; ++k)
+      rec[(size_t)q * (CAT_REC / 4) + k] = make_float4(w[4 * k], w[4 * k + 1], w[4 * k + 2], w[4 * k + 3]);
+    const uint32_t k = skey[q];
+    const uint32_t kp = q == 0 ? 0u : skey[q - 1] + 1u;
+    for (uint32_t c = kp; c <= k; ++c) cellStart[c] = q;
+    if (q == ngal - 1)
+      for (uint32_t c = k + 1; c <= ncell; ++c) cellStart[c] = ngal;
+  }
+}
+
+// To the sorted order, dst = src[c][perm[g]] at [c][g] (planar) or [g][c] (interleaved), or back,
+// dst[c][perm[g]] = src at [c][g] or [g][c]
 __global__ void k_cat_permute(const float* __restrict__ src, const int* __restrict__ perm, float* __restrict__ dst,
-                              int ngal, int C, int gather) {
+                              int ngal, int C, int gather, int inter) {
   const int64_t tot = (int64_t)C * ngal;
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < tot; e += (int64_t)gridDim.x * blockDim.x) {
     const int c = (int)(e / ngal), g = (int)(e % ngal);
+    const int64_t s = inter ? (int64_t)g * C + c : e;   // sorted side
     if (gather)
-      dst[e] = src[(int64_t)c * ngal + perm[g]];
+      dst[s] = src[(int64_t)c * ngal + perm[g]];
     else
-      dst[(int64_t)c * ngal + perm[g]] = src[e];
+      dst[(int64_t)c * ngal + perm[g]] = src[s];
   }
 }
 

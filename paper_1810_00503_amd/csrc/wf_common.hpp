@@ -265,21 +265,23 @@ struct RhsJob {
 // ------------------------------------------------------------------------ catalog response
 // A galaxy of a catalog in fine-grid coordinates rho = 2 r (the fine grid has N = 2n points per
 // side): integer cell and fraction, so that kernel offsets keep full float32 precision.
-struct GalPos {
-  int cy, cx;
-  float fy, fx;
-};
 constexpr int CAT_W = 8;      // interpolation kernel width in fine-grid points
-constexpr int CAT_TS = 16;    // fine-grid tile side of the spreading pass (256 points, one per thread)
+constexpr int CAT_H = CAT_W / 2;
+constexpr int CAT_D = CAT_W + 1;   // fine points per axis around a galaxy's cell: cell - H .. cell + H
+constexpr int CAT_REC = 12;   // floats of a galaxy record: CAT_D weights along y, the x fraction, 0, 0
+constexpr int CAT_TS = 16;    // fine-grid tile side of the spreading pass
 constexpr float CAT_BETA = 2.30f * CAT_W;   // exponential-of-semicircle shape for oversampling 2
 
-// One catalog instance: sorted galaxies, tables and the buffers of its fine-grid passes.
+// One catalog instance: galaxies sorted by fine-grid cell, their windows, tables and the
+// buffers of its fine-grid passes.
 struct CatDesc {
   int n, N, c, ngal;
   int tiles;              // fine-grid tiles per side (N / CAT_TS)
   int nrowPart;           // row-partial slots of the coarse grid (c n / RB_MIN)
-  const GalPos* pos;      // [ngal], sorted by tile
-  const int* tileStart;   // [tiles * tiles + 1]
+  const int2* cell;       // [ngal] fine-grid cell (y, x) of each galaxy
+  const float4* rec;      // [ngal][CAT_REC / 4]: phi at the fine rows cell - H .. cell + H, and the
+                          // fraction fx of rho_x (the x weights are phi(fx + H - t))
+  const int* cellStart;   // [N * N + 1] first sorted galaxy of each fine cell (row-major)
   const float* e;         // [c][ngal] measurements (sorted), solver gradients only
   const float* wgt;       // [ngal] inverse noise variance (sorted)
   const float* T;         // [c][n][n/2] coarse internal layout: prior (or 1) x (N/n) / deconvolution
@@ -287,7 +289,7 @@ struct CatDesc {
   void* y2;               // fine-grid half-plane field, internal layout (complex float)
   float* u;               // [c][N][N] fine-grid map
   float* v;               // [c][N][N] spread residuals (may be u: interpolation is done first)
-  float* r;               // [c][ngal] residuals or field values (sorted)
+  float* r;               // [ngal][c] residuals or field values (sorted, components interleaved)
   double* partI;          // [ceil(ngal / NT)] chi^2 partials of the interpolation
   Job* jfwd;              // this instance's fine-grid forward and adjoint jobs
   Job* jadj;

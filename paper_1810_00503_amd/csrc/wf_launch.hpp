@@ -96,7 +96,16 @@ hipError_t refine_rhs_launch(const RhsJob* jobs, int count, int nblk, hipStream_
 enum { CAT_PAD = 0, CAT_INTERP = 1, CAT_SPREAD = 2, CAT_UNPAD = 3 };
 hipError_t cat_launch(int which, int c, int blocks, const Job* jobs, CatDesc* cats, int count, hipStream_t s);
 hipError_t cat_table_launch(int n, int N, int c, const float* sq, const double* dk, float* T, hipStream_t s);
-hipError_t cat_permute_launch(const float* src, const int* perm, float* dst, int ngal, int c, int gather,
+// catalog set-up: cell keys of the positions (pos [ngal][2] float64), the stable sort of
+// (key, index) pairs on the low endBit bits (temp == nullptr: *tempBytes gets the workspace
+// size and nothing runs), then the cells, weights and cell table in the sorted order
+hipError_t cat_keys_launch(const double* pos, int ngal, int N, uint32_t* key, uint32_t* idx, int* bad, hipStream_t s);
+hipError_t cat_sort_launch(void* temp, size_t* tempBytes, const uint32_t* kin, uint32_t* kout, const uint32_t* vin,
+                           uint32_t* vout, int ngal, int endBit, hipStream_t s);
+hipError_t cat_prep_launch(const double* pos, const uint32_t* skey, const uint32_t* perm, int ngal, int N,
+                           int2* cell, float4* rec, int* cellStart, hipStream_t s);
+// inter: the sorted side is [ngal][c] (interleaved) instead of [c][ngal]
+hipError_t cat_permute_launch(const float* src, const int* perm, float* dst, int ngal, int c, int gather, int inter,
                               hipStream_t s);
 // streaming copy of `bytes` (a multiple of 16) for the bandwidth reference
 hipError_t stream_copy_launch(const void* src, void* dst, uint64_t bytes, hipStream_t s);
