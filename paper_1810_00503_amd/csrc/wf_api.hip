@@ -91,6 +91,8 @@ struct wf_ctx {
   void* scratch = nullptr;
   // on-disk cache of tuned tiles (empty path: none) and the device it is keyed by
   std::string tunePath, tuneDev;
+  // catalog response: deconvolution tables 1 / phi^(k / 2n) per n
+  std::map<int, std::vector<double>> catDk;
 };
 
 namespace {
@@ -438,21 +440,27 @@ int cat_key_bits(int N) {
 // 1 / phi^(k / N) for k = 0 .. n/2, phi the spreading kernel exp(beta (sqrt(1 - (2z/W)^2) - 1))
 // on |z| <= W/2 (the device's beta, W): phi^(xi) = int phi(z) cos(2 pi xi z) dz
 // = W int_0^{pi/2} exp(beta (cos t - 1)) cos(pi xi W sin t) cos t dt  (z = W/2 sin t), whose
-// integrand is smooth, by composite Simpson in float64.
-void cat_deconv(int n, int N, std::vector<double>& dk) {
-  constexpr int M = 2048;
+// integrand is smooth (analytic in t), by composite Simpson in float64 on 1024 intervals (the
+// k-independent factors tabulated once); kept per context and n.
+const std::vector<double>& cat_deconv(wf_ctx* ctx, int n, int N) {
+  auto it = ctx->catDk.find(n);
+  if (it != ctx->catDk.end()) return it->second;
+  constexpr int M = 1024;
   const double W = CAT_W, beta = (double)CAT_BETA, hq = 0.5 * M_PI / M;
-  dk.assign(n / 2 + 1, 0.0);
+  std::vector<double> amp(M + 1), arg(M + 1);
+  for (int q = 0; q <= M; ++q) {
+    const double t = q * hq;
+    amp[q] = std::exp(beta * (std::cos(t) - 1.0)) * std::cos(t) * ((q == 0 || q == M) ? 1.0 : (q % 2 ? 4.0 : 2.0));
+    arg[q] = M_PI * W * std::sin(t);
+  }
+  std::vector<double> dk(n / 2 + 1, 0.0);
   for (int k = 0; k <= n / 2; ++k) {
     const double xi = (double)k / N;
     double s = 0.0;
-    for (int q = 0; q <= M; ++q) {
-      const double t = q * hq;
-      const double f = std::exp(beta * (std::cos(t) - 1.0)) * std::cos(M_PI * xi * W * std::sin(t)) * std::cos(t);
-      s += f * ((q == 0 || q == M) ? 1.0 : (q % 2 ? 4.0 : 2.0));
-    }
+    for (int q = 0; q <= M; ++q) s += amp[q] * std::cos(xi * arg[q]);
     dk[k] = 1.0 / (W * s * hq / 3.0);
   }
+  return ctx->catDk[n] = std::move(dk);
 }
 
 int cat_sort_bytes(wf_ctx* ctx, int N, int ngal, size_t& bytes) {
@@ -495,8 +503,7 @@ int cat_fill(wf_ctx* ctx, Arena& A, CatPlan& h, size_t sortBytes, const void* sq
   void* yN = arena_take(A, 8 * (size_t)c * N * (N / 2));
   float* map = (float*)arena_take(A, 4 * (size_t)c * N * N);
   if (A.used > A.cap) return fail(ctx, WF_ENOMEM, "internal: catalog workspace overflow");
-  std::vector<double> dk;
-  cat_deconv(n, N, dk);
+  const std::vector<double>& dk = cat_deconv(ctx, n, N);
   int hbad = 0;
   HIPCHK(hipMemcpyAsync(bad, &hbad, sizeof(int), hipMemcpyHostToDevice, ctx->cs));
   HIPCHK(hipMemcpyAsync(ddk, dk.data(), 8 * dk.size(), hipMemcpyHostToDevice, ctx->cs));
@@ -505,7 +512,7 @@ int cat_fill(wf_ctx* ctx, Arena& A, CatPlan& h, size_t sortBytes, const void* sq
   HIPCHK(cat_sort_launch(temp, &tb, kin, kout, vin, perm, g, cat_key_bits(N), ctx->cs));
   HIPCHK(cat_prep_launch(h.src->pos, kout, perm, g, N, cell, rec, cellStart, ctx->cs));
   HIPCHK(hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, ctx->cs));
-  HIPCHK(hipStreamSynchronize(ctx->cs));   // hbad, dk are local
+  HIPCHK(hipStreamSynchronize(ctx->cs));   // hbad is local
   if (hbad) return fail(ctx, WF_ENONFINITE, "non-finite galaxy position");
   HIPCHK(cat_table_launch(n, N, c, (const float*)sq, ddk, dT, ctx->cs));
   if (solve) {
