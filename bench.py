@@ -13,7 +13,7 @@ dominant kernel (HIP events around every launch of one instrumented step; bytes 
 the kernels' algorithmic bytes counted on the device), the FP64 oracle on the host
 (cpu_baseline, solves of the same data map and simulations), and one line per other
 workload ("secondary": 256^2 density band powers, 512^2 density maps, 1024^2 CMB maps,
-the 96-map uneven batch against its plain path).
+the 96-map uneven batch against its plain path, the 512^2 shear catalog at the catalog level).
 
     python bench.py [--steps K] [--warmup W] [--nsim 6] [--n 512] [--no-cpu] [--no-plain]
                     [--no-secondary]
@@ -397,7 +397,66 @@ def secondary_workloads(args):
                                    "speedup_batched_vs_per_map": round(dtm / dtb, 2),
                                    "all_converged": rcb == wf.WF_OK and all(r == wf.WF_OK for r in rcs)}
     out["uneven96"] = line
+    out["shear512_catalog"] = catalog_line(args)
     return out
+
+
+def catalog_line(args):
+    """512^2 E/B shear at the catalog level (sec. 3.4): ~10 galaxies per observed pixel at
+    their own positions, the field evaluated at each galaxy by the library's non-uniform
+    transform.  Data: a field drawn from the truth (complex normals times sqrt(S_true / 2) on
+    the half plane), evaluated at the galaxies by the library, plus shape noise sigma_e.  One
+    catalog, then a batch of 8 catalogs (same positions, other noise), and the binned-map solve
+    of the same galaxies (mean shape per pixel, weight = count / sigma_e^2) for reference."""
+    import numpy as np
+    import torch
+
+    import paper_1810_00503_amd as wf
+    from paper_1810_00503_amd import workloads as WL
+    dev = "cuda:0"
+    n = 512
+    cat = WL.shear_catalog(n, 5100, ngal_mean=10.0)
+    S_true = np.where(cat.band >= 0, cat.theta_true[np.maximum(cat.band, 0)], 1.0) * cat.pshape   # band -1: amplitude 1
+    g = torch.Generator(device="cpu").manual_seed(5101)
+    z = torch.complex(torch.randn(S_true.shape, generator=g, dtype=torch.float64),
+                      torch.randn(S_true.shape, generator=g, dtype=torch.float64))
+    s_true = (z * torch.from_numpy(np.sqrt(S_true / 2.0))).to(torch.complex64).to(dev)
+    prob = wf.Problem.for_catalog(n, cat.pshape, cat.band, cat.theta_fid, device=dev)
+    pos = torch.tensor(cat.pos, device=dev)
+    gam = wf.catalog_forward(prob, wf.GalaxyCatalog(pos), s_true)
+    sig = float(1.0 / np.sqrt(cat.wgt[0]))
+    wgt = torch.tensor(cat.wgt, dtype=torch.float32, device=dev)
+    cats = [wf.GalaxyCatalog(pos, gam + sig * torch.randn(gam.shape, generator=torch.Generator(device=dev).manual_seed(
+        5200 + i), device=dev), wgt) for i in range(8)]
+    opts = wf.LbfgsOpts(m=args.m, rel_grad_tol=args.tol)
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = fn()
+        torch.cuda.synchronize()
+        return r, time.perf_counter() - t0
+
+    (_, st1, _), dt1 = timed(lambda: wf.map_wf_solve_catalog([prob], cats[:1], opts))
+    (_, st8, _), dt8 = timed(lambda: wf.map_wf_solve_catalog([prob] * 8, cats, opts))
+    # the same galaxies binned: mean shape per pixel, weight count / sigma_e^2
+    iy = torch.floor(pos[:, 0]).long().clamp_(0, n - 1)
+    ix = torch.floor(pos[:, 1]).long().clamp_(0, n - 1)
+    pix = iy * n + ix
+    cnt = torch.zeros(n * n, dtype=torch.float32, device=dev).index_add_(0, pix, torch.ones_like(pix, dtype=torch.float32))
+    dmap = torch.stack([torch.zeros(n * n, device=dev).index_add_(0, pix, cats[0].e[c]) for c in range(2)])
+    dmap = torch.where(cnt > 0, dmap / cnt.clamp(min=1.0), torch.zeros_like(dmap)).reshape(2, n, n)
+    W = (cnt / sig ** 2).reshape(n, n)
+    pb = wf.Problem(W, cat.pshape, cat.band, cat.theta_fid, d=dmap)
+    (_, _, stb, _), dtb = timed(lambda: wf.map_wf_solve([pb], opts))
+    return {"workload": f"512^2 E/B shear catalog, Poisson(10) galaxies per observed pixel ({cat.ngal} galaxies), "
+                        f"catalog-level response (non-uniform transform on a 1024^2 grid)",
+            "galaxies": cat.ngal, "solves_per_s": round(1.0 / dt1, 2), "ms_per_solve": round(dt1 * 1e3, 2),
+            "iters": st1[0].iters, "batch8_solves_per_s": round(8 / dt8, 2),
+            "batch8_iters_mean": round(float(np.mean([x.iters for x in st8])), 1),
+            "galaxy_evaluations_per_s": round(cat.ngal * 2 * (st1[0].iters + st1[0].ngrad) / dt1, 1),
+            "binned_map_solves_per_s": round(1.0 / dtb, 2), "binned_map_iters": stb[0].iters}
 
 
 def main():
