@@ -31,8 +31,12 @@ independently built pixel covariance (masked, off-diagonals included); the
 simulation b and F, every entry, within their own Monte Carlo error of the dense
 ones; the full estimate with simulation b and F unbiased over data realisations;
 the sampled-row Fisher matrix and the fiducial iteration by reduction to the full
-estimate and closed-form histories.  Iteration counts of the solver are not pinned
-(the paper prints none).
+estimate and closed-form histories; the catalog response by the map response at
+pixel positions, periodicity, single-mode closed forms (spin-0 and spin-2), the
+dot-product test with its adjoint, exact central differences of its objective, and
+its MAP against the dense Wiener filter of the catalog and, for one galaxy per pixel
+centre, against the map solve.  Iteration counts of the solver are not pinned (the
+paper prints none).
 This module is test infrastructure: only the tests, the smoke check and the
 benchmark's CPU-baseline leg use it; the library never does.
 """
