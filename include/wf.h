@@ -369,9 +369,14 @@ int wf_catalog_adjoint(wf_ctx* ctx, const wf_problem* prob, const wf_catalog* ca
  * instances per launch (0 = all), reg = which passes run the register-staged FFT instead
  * of the LDS-staged one (bit 0: row pass, whose rows per work-group are then fixed by n;
  * bit 1: column inverse, bit 2: column forward, which need cpb * ncomp * 2 * n / 256 in
- * [4, 32]; float32 and power-of-two n >= 128 only).  By default (rbv = 0) the library autotunes them: on the
- * first float32 solve of a batch of >= 4 maps of a given (n, ncomp, batch-size bucket) it
- * times every supported choice on that batch and keeps the fastest for the context.
+ * [4, 32]; float32 and power-of-two n >= 128 only), or reg = 8 alone: one kernel per
+ * instance does all three passes of the solver's curvature product or gradient in LDS
+ * (the field read once, Dp written once; maps whose field and twiddles fit 150 KB of LDS:
+ * n <= 128 in float32, n <= 96 for spin-2 float64; solver passes only, operator calls keep
+ * the three passes; rbv and cpb are ignored, group must be 0).  By default (rbv = 0) the
+ * library autotunes them: on the first float32 solve of a batch of >= 4 maps of a given
+ * (n, ncomp, batch-size bucket) it times every supported choice, the single pass included,
+ * on that batch and keeps the fastest for the context.
  * float64 uses (4, 1, 0, 0), as does a fixed choice that the shape does not support.
  * Tuned choices persist on disk, keyed by device architecture and compute-unit count: in the
  * file WF_TUNE_CACHE names (empty: none), else $XDG_CACHE_HOME/libwf/tiles.txt or

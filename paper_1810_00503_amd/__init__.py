@@ -745,8 +745,8 @@ def reset_kernel_stats(ctx: Context | None = None):
 def set_chain_tiles(rbv: int = 0, cpb: int = 1, group: int = 0, reg: int = 0, ctx: Context | None = None):
     """Fix the transform chain's tiles (rbv rows, cpb column blocks, group instances per
     launch, reg = register-staged passes: bit 0 row, bit 1 column inverse, bit 2 column
-    forward), or return to
-    autotuning with rbv = 0."""
+    forward; or reg = 8: the single-pass kernel of small maps), or return to autotuning
+    with rbv = 0."""
     cx = ctx or context(0)
     cx.check(cx.lib.wf_set_chain_tiles(cx.h, int(rbv), int(cpb), int(group), int(reg)))
 

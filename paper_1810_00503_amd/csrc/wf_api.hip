@@ -299,8 +299,10 @@ int drain_events(wf_ctx* ctx) {
 }
 
 // tiles of operator-level calls: the fixed choice if one is set and supported, else the default
+// operator calls run every mode through the three passes (the single pass is for solvers)
 ChainCfg op_cfg(const wf_ctx* ctx, int dtype, int n, int c) {
-  return ctx->fixedSet && chain_cfg_supported(dtype, n, c, ctx->fixedCfg) ? ctx->fixedCfg : ChainCfg();
+  return ctx->fixedSet && ctx->fixedCfg.reg != 8 && chain_cfg_supported(dtype, n, c, ctx->fixedCfg) ? ctx->fixedCfg
+                                                                                                     : ChainCfg();
 }
 
 hipError_t chain(wf_ctx* ctx, int dtype, int n, int c, int which, const Job* jobs, int batch, const void* tw,
@@ -708,6 +710,11 @@ int tune_chain(wf_ctx* ctx, Klass& k, const std::vector<InstDesc>& hd, Job* djob
           if (chain_cfg_supported(k.dtype, k.n, k.c, c)) cands.push_back(c);
         }
     }
+  {   // the single pass for maps that fit one work-group's LDS
+    ChainCfg c;
+    c.reg = 8;
+    if (chain_cfg_supported(k.dtype, k.n, k.c, c)) cands.push_back(c);
+  }
   hipEvent_t e0 = ev_get(ctx), e1 = ev_get(ctx);
   std::vector<float> times;
   for (const ChainCfg& c : cands) {
@@ -2884,8 +2891,8 @@ int wf_set_chain_tiles(wf_ctx* ctx, int32_t rbv, int32_t cpb, int32_t group, int
     ctx->fixedSet = false;
     return WF_OK;
   }
-  if (!(rbv == 2 || rbv == 4 || rbv == 8) || !(cpb == 1 || cpb == 2 || cpb == 4) || group < 0 || reg < 0 || reg > 7)
-    return fail(ctx, WF_EINVAL, "tiles: rbv in {2,4,8}, cpb in {1,2,4}, group >= 0, reg in [0, 7]");
+  if (!(rbv == 2 || rbv == 4 || rbv == 8) || !(cpb == 1 || cpb == 2 || cpb == 4) || group < 0 || reg < 0 || reg > 8)
+    return fail(ctx, WF_EINVAL, "tiles: rbv in {2,4,8}, cpb in {1,2,4}, group >= 0, reg in [0, 8]");
   ctx->fixedCfg.rbv = rbv;
   ctx->fixedCfg.cpb = cpb;
   ctx->fixedCfg.group = group;

@@ -710,6 +710,197 @@ __global__ __launch_bounds__(NT) void k_colfwd(const Job* __restrict__ jobs, con
   colfwd_reduce(jb, mode, extras, avo, aoo, adg, add, q, CPB);
 }
 
+// ======================================================================== single pass
+// Small maps (the whole field fits one work-group's LDS): the three passes of a solver's
+// curvature product or exact gradient (CM_HV, CM_GRAD) in one kernel, one work-group per
+// instance.  The field is read once and Dp written once, against 7 vectors of traffic for the
+// three passes; the intermediate never leaves LDS.  LDS layout [c][y][k] (k < N/2 complex): the
+// column transforms run per component over the H columns (stride H), the row transforms over
+// the C N rows.  The complex-to-real and real-to-complex untangle steps pair k with H - k in
+// one thread, so they run in place without a barrier between reads and writes.  Partial sums
+// go to the same slots the three passes fill (the first slot of each kind, the others 0).
+// Other modes return: operator calls use the three passes.
+template <typename T, int N, int C>
+constexpr size_t lds_chain1() { return (size_t)(N + C * N * (N / 2)) * sizeof(cpx<T>); }
+constexpr int CHAIN1_NT = 1024;   // threads per work-group: one work-group fills a CU (LDS-bound)
+
+template <typename T, int N, int C>
+__global__ __launch_bounds__(CHAIN1_NT) void k_chain1(const Job* __restrict__ jobs, const cpx<T>* __restrict__ twg) {
+  const Job& jb = jobs[blockIdx.x];
+  const int mode = jb.mode;
+  if (!(mode == CM_HV || mode == CM_GRAD)) return;
+  constexpr int H = N / 2, NE = C * N * H;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cpx<T>* tw = reinterpret_cast<cpx<T>*>(smem_raw);
+  cpx<T>* buf = tw + N;
+  constexpr int TP = CHAIN1_NT, NW = TP / 64;
+  const int tid = threadIdx.x;
+  const bool grad = mode == CM_GRAD;
+  for (int i = tid; i < N; i += TP) tw[i] = twg[i];
+  // ---- column-inverse prologue: scale, Hermitian completion, rotation, prior partial
+  double accP = 0.0;
+  for (int e = tid; e < N * H; e += TP) {
+    const int ky = e / H, kx = e % H;
+    cpx<T> a[C];
+    bool part = false;
+    int kyr = ky;
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      cpx<T> v;
+      T sc, wa;
+      colinv_ld<T, N>(jb, grad, false, c, ky, kx, v, sc, wa);
+      a[c] = colinv_fin<T, N>(grad, false, ky, kx, v, sc, wa, part, kyr, accP);
+    }
+    if constexpr (C == 2) {
+      T c2, s2;
+      rot2<T>(kx, kyr < H ? kyr : kyr - N, c2, s2);
+      const cpx<T> e0 = a[0], b0 = a[1];
+      a[0] = mk(c2 * e0.x - s2 * b0.x, c2 * e0.y - s2 * b0.y);
+      a[1] = mk(s2 * e0.x + c2 * b0.x, s2 * e0.y + c2 * b0.y);
+    }
+    if (part) {
+#pragma unroll
+      for (int c = 0; c < C; ++c) a[c] = conj(a[c]);
+    }
+#pragma unroll
+    for (int c = 0; c < C; ++c) buf[(c * N + ky) * H + kx] = a[c];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int c = 0; c < C; ++c) lds_fft<T, N, H, 1, H, 1, false, true, TP>(buf + c * N * H, tw);
+  // ---- complex-to-real untangle, per row b and pair (k, H - k):
+  //   Z_k = (X_k + conj X_{H-k}) + i w^-k (X_k - conj X_{H-k}),  X_0 real part only
+  for (int e = tid; e < C * N * (H / 2 + 1); e += TP) {
+    const int b = e / (H / 2 + 1), k = e % (H / 2 + 1);
+    cpx<T>* row = buf + b * H;
+    if (k == 0) {
+      const cpx<T> X = row[0];
+      row[0] = mk(X.x, X.x);
+    } else {
+      const cpx<T> X = row[k], Y = row[H - k];
+      const cpx<T> Xm = conj(Y), Ym = conj(X);
+      const cpx<T> t1 = mulc(sub(X, Xm), tw[k]), s1 = add(X, Xm);
+      const cpx<T> t2 = mulc(sub(Y, Ym), tw[H - k]), s2 = add(Y, Ym);
+      row[k] = mk(s1.x - t1.y, s1.y + t1.x);
+      if (k != H - k) row[H - k] = mk(s2.x - t2.y, s2.y + t2.x);
+    }
+  }
+  __syncthreads();
+  lds_fft<T, H, C * N, H, 1, 2, true, true, TP>(buf, tw);
+  // ---- pixel step: element j of row (c, y) holds pixels (2j, 2j + 1)
+  double accR = 0.0;
+  {
+    using T2 = typename std::conditional<std::is_same<T, float>::value, float2, double2>::type;
+    const T2* W2 = reinterpret_cast<const T2*>(jb.W);
+    const T2* D2 = grad ? reinterpret_cast<const T2*>(jb.d) : nullptr;
+    for (int e = tid; e < NE; e += TP) {
+      const int b = e / H, j = e % H;
+      const int c = b / N, y = b % N;
+      const uint32_t p2 = (uint32_t)y * H + j;
+      const T2 w = gld(W2, p2);
+      const T2 d = grad ? gld(D2, (uint32_t)c * (N * H) + p2) : T2{T(0), T(0)};
+      cpx<T> z = buf[e];
+      row_pixel_hot<T, N>(grad, w, d, z, accR);
+      buf[e] = z;
+    }
+  }
+  __syncthreads();
+  lds_fft<T, H, C * N, H, 1, 2, true, false, TP>(buf, tw);
+  // ---- real-to-complex untangle, pair (k, H - k), Z_H = Z_0:
+  //   X_k = 1/2 (Z_k + conj Z_{H-k}) - i/2 w^k (Z_k - conj Z_{H-k})
+  for (int e = tid; e < C * N * (H / 2 + 1); e += TP) {
+    const int b = e / (H / 2 + 1), k = e % (H / 2 + 1);
+    cpx<T>* row = buf + b * H;
+    const int km = k == 0 ? 0 : H - k;
+    const cpx<T> Zk = row[k], Zm = row[km];
+    auto untangle = [&](cpx<T> A0, cpx<T> B0, int kk) {
+      const cpx<T> Bc = conj(B0);
+      const cpx<T> A = add(A0, Bc);
+      const cpx<T> t = mul(tw[kk], sub(A0, Bc));
+      return mk(T(0.5) * (A.x + t.y), T(0.5) * (A.y - t.x));
+    };
+    const cpx<T> xk = untangle(Zk, Zm, k);
+    if (k != 0 && k != km) {
+      const cpx<T> xm = untangle(Zm, Zk, km);
+      row[km] = xm;
+    }
+    row[k] = xk;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int c = 0; c < C; ++c) lds_fft<T, N, H, 1, H, 1, false, false, TP>(buf + c * N * H, tw);
+  // ---- column-forward epilogue: inverse rotation, x S^1/2, + added term, solver dots
+  double avo = 0.0, aoo = 0.0, adg = 0.0;
+  double add[MMAX];
+#pragma unroll
+  for (int j = 0; j < MMAX; ++j) add[j] = 0.0;
+  const bool extras = (mode == CM_HV) && jb.dpBase != nullptr;
+  cpx<T>* vo = reinterpret_cast<cpx<T>*>(jb.vout);
+  for (int e = tid; e < N * H; e += TP) {
+    const int ky = e / H, kx = e % H;
+    cpx<T> t[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) t[c] = buf[(c * N + ky) * H + kx];
+    if constexpr (C == 2) {
+      T c2, s2;
+      rot2<T>(kx, ky < H ? ky : ky - N, c2, s2);
+      const cpx<T> g1 = t[0], g2 = t[1];
+      t[0] = mk(c2 * g1.x + s2 * g2.x, c2 * g1.y + s2 * g2.y);
+      t[1] = mk(-s2 * g1.x + c2 * g2.x, -s2 * g1.y + c2 * g2.y);
+    }
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      const int64_t o = fidx(N, c, ky, kx);
+      T sq, wa;
+      cpx<T> va;
+      colfwd_ld<T>(jb, (uint32_t)o, sq, va, wa);
+      const cpx<T> out = colfwd_fin<T, N>(false, ky, kx, t[c], sq, va, wa, avo, aoo);
+      gst(vo, (uint32_t)o, out);
+      if (extras) colfwd_extras<T>(jb, o, out, adg, add);
+    }
+  }
+  // work-group sums of the partials (wave shuffle trees, then the waves in order), each kind
+  // into its first slot and 0 into the others the solver reduces
+  const int lane = tid & 63, wv = tid >> 6;
+  constexpr int NV = 3 + MMAX + 2;   // VO, OO, DG, DD_0..DD_{MMAX-1}, prior, residual
+  double vals[NV];
+  vals[0] = avo;
+  vals[1] = aoo;
+  vals[2] = adg;
+#pragma unroll
+  for (int j = 0; j < MMAX; ++j) vals[3 + j] = add[j];
+  vals[3 + MMAX] = accP;
+  vals[4 + MMAX] = accR;
+  __shared__ double redv[NW][NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    const double x = wave_sum(vals[v]);
+    if (lane == 0) redv[wv][v] = x;
+  }
+  __syncthreads();
+  constexpr int NCOL = N / 2 / TB, NROW = C * N / RB_MIN;
+  const uint32_t mask = extras ? jb.dpMask : 0u;
+  if (tid < NV) {
+    double t = 0.0;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) t += redv[w][tid];
+    if (tid < 2 || (extras && tid < 3) || (tid >= 3 && tid < 3 + MMAX && ((mask >> (tid - 3)) & 1u)))
+      jb.part[(PK_VO + tid) * jb.pstride] = t;
+    else if (grad && tid == 3 + MMAX)
+      jb.part[PK_PRIOR * jb.pstride] = t;
+    else if (grad && tid == 4 + MMAX)
+      jb.part[PK_RES * jb.pstride] = t;
+  }
+  for (int k = tid; k < (NCOL - 1) * (3 + MMAX); k += TP) {
+    const int kind = k / (NCOL - 1), slot = 1 + k % (NCOL - 1);
+    if (kind < 3 || ((mask >> (kind - 3)) & 1u)) jb.part[(PK_VO + kind) * jb.pstride + slot] = 0.0;
+  }
+  if (grad) {
+    for (int k = tid; k < NCOL - 1; k += TP) jb.part[PK_PRIOR * jb.pstride + 1 + k] = 0.0;
+    for (int k = tid; k < NROW - 1; k += TP) jb.part[PK_RES * jb.pstride + 1 + k] = 0.0;
+  }
+}
+
 // ======================================================================== register-staged
 // Power-of-two n >= 128, float32: the same passes with the register-staged FFT of
 // wf_rfft.hpp (simulation jobs run on the LDS-staged variants).  First-stage inputs are read from global memory (column passes) or from the

@@ -49,9 +49,19 @@ static hipError_t prep_colr() {
   return hipSuccess;
 }
 
+// single-pass kernel: the field and the twiddles in at most 150 KB of LDS
+template <typename T, int N, int C>
+constexpr bool chain1_ok() {
+  return N <= 128 && lds_chain1<T, N, C>() <= (size_t)150 * 1024;
+}
+
 template <typename T, int N, int C>
 static hipError_t prep_t() {
-  hipError_t e = prep_col<T, N, C, 1>();
+  hipError_t e = hipSuccess;
+  if constexpr (chain1_ok<T, N, C>())
+    e = hipFuncSetAttribute((const void*)k_chain1<T, N, C>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)lds_chain1<T, N, C>());
+  if (e == hipSuccess) e = prep_col<T, N, C, 1>();
   if (e == hipSuccess) e = prep_row<T, N, C, 4>();
   if (e == hipSuccess) e = prep_col<T, N, C, 1, true>();
   if (e == hipSuccess) e = prep_row<T, N, C, 4, true>();
@@ -104,6 +114,13 @@ template <typename T, int N, int C>
 static hipError_t launch_t(int which, const ChainCfg& cfg, const Job* jobs, int batch, const void* tw,
                            hipStream_t st) {
   const cpx<T>* t = reinterpret_cast<const cpx<T>*>(tw);
+  if (cfg.reg == 8 && !cfg.sim) {   // single pass: launched by the column-inverse call
+    if constexpr (chain1_ok<T, N, C>()) {
+      if (which == CH_COLINV) k_chain1<T, N, C><<<dim3(batch), dim3(CHAIN1_NT), lds_chain1<T, N, C>(), st>>>(jobs, t);
+      return hipGetLastError();
+    }
+    return hipErrorInvalidValue;
+  }
   if (cfg.sim) {   // simulation jobs: the LDS-staged passes with the simulation mode compiled in
     if (which == CH_ROW)
       launch_row<T, N, C, 4, true>(jobs, batch, t, st);

@@ -106,18 +106,18 @@ __device__ __forceinline__ void dft(cpx<T>* v) {
 
 // ------------------------------------------------------------------------ LDS stages
 // JFAST: consecutive threads take consecutive j (row layout, SJ = 1); otherwise
-// consecutive b (column layout, SB = 1).
-template <typename T, int N, int NB, int SB, int SJ, int TS, bool JFAST, int R, int NS, bool INV>
+// consecutive b (column layout, SB = 1).  TPB threads per work-group.
+template <typename T, int N, int NB, int SB, int SJ, int TS, bool JFAST, int R, int NS, bool INV, int TPB = NT>
 __device__ __forceinline__ void fft_stage(cpx<T>* __restrict__ a, const cpx<T>* __restrict__ tw) {
   constexpr int NQ = N / R;
   constexpr int NBF = NB * NQ;
-  constexpr int K = (NBF + NT - 1) / NT;
+  constexpr int K = (NBF + TPB - 1) / TPB;
   const int tid = threadIdx.x;
   cpx<T> v[K][R];
 #pragma unroll
   for (int kk = 0; kk < K; ++kk) {
-    const int u = tid + kk * NT;
-    if ((NBF % NT == 0) || u < NBF) {
+    const int u = tid + kk * TPB;
+    if ((NBF % TPB == 0) || u < NBF) {
       const int b = JFAST ? u / NQ : u % NB;
       const int j = JFAST ? u % NQ : u / NB;
 #pragma unroll
@@ -127,8 +127,8 @@ __device__ __forceinline__ void fft_stage(cpx<T>* __restrict__ a, const cpx<T>* 
   __syncthreads();
 #pragma unroll
   for (int kk = 0; kk < K; ++kk) {
-    const int u = tid + kk * NT;
-    if ((NBF % NT == 0) || u < NBF) {
+    const int u = tid + kk * TPB;
+    if ((NBF % TPB == 0) || u < NBF) {
       const int b = JFAST ? u / NQ : u % NB;
       const int j = JFAST ? u % NQ : u / NB;
       const int k = j % NS;
@@ -149,19 +149,19 @@ __device__ __forceinline__ void fft_stage(cpx<T>* __restrict__ a, const cpx<T>* 
   __syncthreads();
 }
 
-template <typename T, int N, int NB, int SB, int SJ, int TS, bool JFAST, bool INV, int S, int NS>
+template <typename T, int N, int NB, int SB, int SJ, int TS, bool JFAST, bool INV, int S, int NS, int TPB>
 __device__ __forceinline__ void fft_stages(cpx<T>* a, const cpx<T>* tw) {
   if constexpr (S < fft_num_stages(N)) {
     constexpr int R = fft_stage_radix(N, S);
-    fft_stage<T, N, NB, SB, SJ, TS, JFAST, R, NS, INV>(a, tw);
-    fft_stages<T, N, NB, SB, SJ, TS, JFAST, INV, S + 1, NS * R>(a, tw);
+    fft_stage<T, N, NB, SB, SJ, TS, JFAST, R, NS, INV, TPB>(a, tw);
+    fft_stages<T, N, NB, SB, SJ, TS, JFAST, INV, S + 1, NS * R, TPB>(a, tw);
   }
 }
 
 // Entry: caller has synchronised after filling `a`; returns synchronised.
-template <typename T, int N, int NB, int SB, int SJ, int TS, bool JFAST, bool INV>
+template <typename T, int N, int NB, int SB, int SJ, int TS, bool JFAST, bool INV, int TPB = NT>
 __device__ __forceinline__ void lds_fft(cpx<T>* a, const cpx<T>* tw) {
-  fft_stages<T, N, NB, SB, SJ, TS, JFAST, INV, 0, 1>(a, tw);
+  fft_stages<T, N, NB, SB, SJ, TS, JFAST, INV, 0, 1, TPB>(a, tw);
 }
 
 }  // namespace wf

@@ -14,7 +14,9 @@ bool chain_supported(int n);
 // (0 = all) and which passes use the register-staged FFT (bit 0: row pass, whose tile is
 // then fixed by n; bit 1: column inverse; bit 2: column forward).  float32 supports every
 // choice (register-staged passes for power-of-two n >= 128), float64 the defaults (4, 1,
-// LDS-staged).
+// LDS-staged).  reg = 8 alone: the single-pass kernel (k_chain1) for maps whose field fits
+// one work-group's LDS; the column-inverse call then runs all three passes of a solver's
+// curvature product or gradient and the other two calls launch nothing.
 struct ChainCfg {
   int rbv = 4;
   int cpb = 1;
@@ -52,7 +54,12 @@ inline bool chain_regcol_supported(int n, int c, int cpb) {
   const int e = cpb * c * TB * n / NT;
   return e >= 4 && e <= 32;
 }
+// single pass: the field and the twiddles in at most 150 KB of LDS (n <= 128)
+inline bool chain1_supported(int dtype, int n, int c) {
+  return n <= 128 && (size_t)(n + c * n * (n / 2)) * (dtype != 0 ? 16 : 8) <= (size_t)150 * 1024;
+}
 inline bool chain_cfg_supported(int dtype, int n, int c, const ChainCfg& cfg) {
+  if (cfg.reg == 8) return cfg.group == 0 && chain1_supported(dtype, n, c);
   if (dtype != 0) return cfg.rbv == 4 && cfg.cpb == 1 && cfg.reg == 0;
   const int ncb = n / 2 / TB;   // column blocks
   if (cfg.reg < 0 || cfg.reg > 7) return false;
