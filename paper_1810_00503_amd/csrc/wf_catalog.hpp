@@ -305,18 +305,24 @@ __global__ __launch_bounds__(CAT_SPREAD_NT) void k_cat_spread(const Job* __restr
 }
 
 // ------------------------------------------------------------------------ unpad
-// grid (n / 4 coarse column blocks, instances): the fine spectrum t of the band modes back on
-// the coarse layout; solver modes: out = wa v + T t on the free modes with the dot partials
-// [VO, OO, DG, DD_j] of the column-forward pass (one slot per column block); operator modes:
-// out = T t on the live modes (metric adjoint) or 2 T t on the free ones (gradient form).
+// grid (n / 4 coarse column blocks, instances), CAT_UNPAD_NT threads: the fine spectrum t of
+// the band modes back on the coarse layout; solver modes: out = wa v + T t on the free modes
+// with the dot partials [VO, OO, DG, DD_j] of the column-forward pass (one slot per column
+// block); operator modes: out = T t on the live modes (metric adjoint) or 2 T t on the free ones
+// (gradient form).  A thread's elements (CAT_UNPAD_K at most) have all their loads issued before
+// the arithmetic, and the loads of each kept Dp_j together.
+constexpr int CAT_UNPAD_NT = 1024;
+constexpr int CAT_UNPAD_K = 4;
 template <int C>
-__global__ __launch_bounds__(NT) void k_cat_unpad(const Job* __restrict__ jobs, const CatDesc* __restrict__ cats) {
+__global__ __launch_bounds__(CAT_UNPAD_NT) void k_cat_unpad(const Job* __restrict__ jobs,
+                                                              const CatDesc* __restrict__ cats) {
   const int i = blockIdx.y;
   const Job& jb = jobs[i];
   const int mode = jb.mode;
   if (!(cat_solver_mode(mode) || mode == CM_ADJ || mode == CM_ADJ_GRAD)) return;
   const CatDesc& cd = cats[i];
-  __shared__ double red2[NT / 64][3 + MMAX];
+  constexpr int NW = CAT_UNPAD_NT / 64;
+  __shared__ double red2[NW][3 + MMAX];
   const int n = cd.n, N = cd.N, h = n / 2;
   const int b = blockIdx.x;
   const cpx<float>* y2 = reinterpret_cast<const cpx<float>*>(cd.y2);
@@ -327,43 +333,63 @@ __global__ __launch_bounds__(NT) void k_cat_unpad(const Job* __restrict__ jobs, 
   double avo = 0.0, aoo = 0.0, adg = 0.0, add[MMAX];
 #pragma unroll
   for (int j = 0; j < MMAX; ++j) add[j] = 0.0;
-  for (int e = threadIdx.x; e < C * n * TB; e += NT) {
-    const int cc = e / (n * TB), r = e % (n * TB), ky = r / TB, kx = 2 * b + r % TB;
-    const uint32_t o = (uint32_t)fidx(n, cc, ky, kx);
-    const int KY = ky < h ? ky : ky - n + N;
-    const float T = cd.T[o];
-    cpx<float> out = mk(0.0f, 0.0f);
-    if (solver) {
-      if (T != 0.0f && is_free(n, ky, kx)) {
-        const cpx<float> t = y2[fidx(N, cc, KY, kx)];
-        const cpx<float> a = reinterpret_cast<const cpx<float>*>(jb.vadd)[o];
-        const float wa = cd.aTab ? cd.aTab[o] : 1.0f;
-        out = mk(wa * a.x + T * t.x, wa * a.y + T * t.y);
-        avo += (double)a.x * out.x + (double)a.y * out.y;
-      }
-      aoo += (double)out.x * out.x + (double)out.y * out.y;
-      if (extras) {
-        const cpx<float> gv = reinterpret_cast<const cpx<float>*>(jb.gvec)[o];
-        adg += (double)gv.x * out.x + (double)gv.y * out.y;
-        const cpx<float>* dpb = reinterpret_cast<const cpx<float>*>(jb.dpBase);
+  const int NEL = C * n * TB;
+  for (int e0 = threadIdx.x; e0 < NEL; e0 += CAT_UNPAD_NT * CAT_UNPAD_K) {
+    uint32_t o[CAT_UNPAD_K];
+    bool ok[CAT_UNPAD_K], keep[CAT_UNPAD_K];
+    float Tv[CAT_UNPAD_K];
+    cpx<float> t[CAT_UNPAD_K], a[CAT_UNPAD_K], out[CAT_UNPAD_K];
 #pragma unroll
-        for (int j = 0; j < MMAX; ++j) {
-          if ((mask >> j) & 1u) {
-            const cpx<float> dj = dpb[(int64_t)j * jb.dpStride + o];
-            add[j] += (double)dj.x * out.x + (double)dj.y * out.y;
-          }
+    for (int k = 0; k < CAT_UNPAD_K; ++k) {
+      const int e = e0 + k * CAT_UNPAD_NT;
+      ok[k] = e < NEL;
+      const int ee = ok[k] ? e : NEL - 1;   // past the end: any valid element, not stored
+      const int cc = ee / (n * TB), r = ee % (n * TB), ky = r / TB, kx = 2 * b + r % TB;
+      o[k] = (uint32_t)fidx(n, cc, ky, kx);
+      const int KY = ky < h ? ky : ky - n + N;
+      Tv[k] = cd.T[o[k]];
+      t[k] = y2[fidx(N, cc, KY, kx)];
+      a[k] = solver ? reinterpret_cast<const cpx<float>*>(jb.vadd)[o[k]] : mk(0.0f, 0.0f);
+      keep[k] = ok[k] && (solver || mode == CM_ADJ_GRAD ? is_free(n, ky, kx) : is_live(n, ky, kx));
+    }
+#pragma unroll
+    for (int k = 0; k < CAT_UNPAD_K; ++k) {
+      cpx<float> v = mk(0.0f, 0.0f);
+      if (solver) {
+        if (keep[k] && Tv[k] != 0.0f) {
+          const float wa = cd.aTab ? cd.aTab[o[k]] : 1.0f;
+          v = mk(wa * a[k].x + Tv[k] * t[k].x, wa * a[k].y + Tv[k] * t[k].y);
+          avo += (double)a[k].x * v.x + (double)a[k].y * v.y;
+        }
+        if (ok[k]) aoo += (double)v.x * v.x + (double)v.y * v.y;
+      } else if (keep[k]) {
+        const float f = mode == CM_ADJ ? Tv[k] : 2.0f * Tv[k];
+        v = mk(f * t[k].x, f * t[k].y);
+      }
+      out[k] = v;
+      if (ok[k]) vout[o[k]] = v;
+    }
+    if (extras) {
+      const cpx<float>* gvec = reinterpret_cast<const cpx<float>*>(jb.gvec);
+      cpx<float> gv[CAT_UNPAD_K];
+#pragma unroll
+      for (int k = 0; k < CAT_UNPAD_K; ++k) gv[k] = gvec[o[k]];
+#pragma unroll
+      for (int k = 0; k < CAT_UNPAD_K; ++k)
+        if (ok[k]) adg += (double)gv[k].x * out[k].x + (double)gv[k].y * out[k].y;
+      const cpx<float>* dpb = reinterpret_cast<const cpx<float>*>(jb.dpBase);
+#pragma unroll
+      for (int j = 0; j < MMAX; ++j) {
+        if ((mask >> j) & 1u) {
+          cpx<float> dj[CAT_UNPAD_K];
+#pragma unroll
+          for (int k = 0; k < CAT_UNPAD_K; ++k) dj[k] = gldnt(dpb, (uint32_t)((int64_t)j * jb.dpStride + o[k]));
+#pragma unroll
+          for (int k = 0; k < CAT_UNPAD_K; ++k)
+            if (ok[k]) add[j] += (double)dj[k].x * out[k].x + (double)dj[k].y * out[k].y;
         }
       }
-    } else if (mode == CM_ADJ) {
-      if (is_live(n, ky, kx)) {
-        const cpx<float> t = y2[fidx(N, cc, KY, kx)];
-        out = mk(T * t.x, T * t.y);
-      }
-    } else if (is_free(n, ky, kx)) {
-      const cpx<float> t = y2[fidx(N, cc, KY, kx)];
-      out = mk(2.0f * T * t.x, 2.0f * T * t.y);
     }
-    vout[o] = out;
   }
   if (!solver) return;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -391,7 +417,7 @@ __global__ __launch_bounds__(NT) void k_cat_unpad(const Job* __restrict__ jobs, 
   if (tid < nv && (tid < 3 || ((mask >> (tid - 3)) & 1u))) {
     double sum = 0.0;
 #pragma unroll
-    for (int k = 0; k < NT / 64; ++k) sum += red2[k][tid];
+    for (int k = 0; k < NW; ++k) sum += red2[k][tid];
     jb.part[(PK_VO + tid) * jb.pstride + b] = sum;
   }
 }

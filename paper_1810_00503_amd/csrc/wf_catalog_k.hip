@@ -22,7 +22,8 @@ hipError_t cat_launch(int which, int c, int blocks, const Job* jobs, CatDesc* ca
       else k_cat_spread<2><<<g, CAT_SPREAD_NT, 0, s>>>(jobs, cats);
       break;
     case CAT_UNPAD:
-      if (c == 1) k_cat_unpad<1><<<g, NT, 0, s>>>(jobs, cats); else k_cat_unpad<2><<<g, NT, 0, s>>>(jobs, cats);
+      if (c == 1) k_cat_unpad<1><<<g, CAT_UNPAD_NT, 0, s>>>(jobs, cats);
+      else k_cat_unpad<2><<<g, CAT_UNPAD_NT, 0, s>>>(jobs, cats);
       break;
     default: return hipErrorInvalidValue;
   }
