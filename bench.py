@@ -440,6 +440,18 @@ def catalog_line(args):
 
     (_, st1, _), dt1 = timed(lambda: wf.map_wf_solve_catalog([prob], cats[:1], opts))
     (_, st8, _), dt8 = timed(lambda: wf.map_wf_solve_catalog([prob] * 8, cats, opts))
+    # where one solve's device time goes (HIP events around every launch: graphs off, so this
+    # call is slower than the timed one; the split is what it reports)
+    wf.set_profiling(True)
+    wf.reset_kernel_stats()
+    wf.map_wf_solve_catalog([prob], cats[:1], opts)
+    torch.cuda.synchronize()
+    ks = wf.kernel_stats()
+    wf.set_profiling(False)
+    split = {"galaxy_passes_ms": ks["catalog"]["ms"],
+             "transforms_2n_ms": ks["colinv"]["ms"] + ks["row"]["ms"] + ks["colfwd"]["ms"],
+             "solver_vector_passes_ms": sum(ks[k]["ms"] for k in ("passA", "passB", "post", "coef", "misc")),
+             "galaxy_pass_launches": ks["catalog"]["launches"]}
     # the same galaxies binned: mean shape per pixel, weight count / sigma_e^2
     iy = torch.floor(pos[:, 0]).long().clamp_(0, n - 1)
     ix = torch.floor(pos[:, 1]).long().clamp_(0, n - 1)
@@ -456,7 +468,8 @@ def catalog_line(args):
             "iters": st1[0].iters, "batch8_solves_per_s": round(8 / dt8, 2),
             "batch8_iters_mean": round(float(np.mean([x.iters for x in st8])), 1),
             "galaxy_evaluations_per_s": round(cat.ngal * 2 * (st1[0].iters + st1[0].ngrad) / dt1, 1),
-            "binned_map_solves_per_s": round(1.0 / dtb, 2), "binned_map_iters": stb[0].iters}
+            "binned_map_solves_per_s": round(1.0 / dtb, 2), "binned_map_iters": stb[0].iters,
+            "device_time_split": {k: round(v, 3) if isinstance(v, float) else v for k, v in split.items()}}
 
 
 def main():

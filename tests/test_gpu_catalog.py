@@ -248,3 +248,27 @@ def test_catalog_argument_checks(lib):
     g0 = lib.catalog_forward(prob, _gcat(lib, torch, p0), sf).cpu().numpy()
     g1 = lib.catalog_forward(prob, _gcat(lib, torch, p0 + np.array([n, -3 * n])), sf).cpu().numpy()
     assert np.max(np.abs(g0 - g1)) <= 1e-6 * np.max(np.abs(g0))
+
+
+def test_dense_cell_and_edges(lib):
+    """Thousands of galaxies in one fine cell (a long run for the spreading pass), galaxies on
+    the patch's edges and corners, and exact integer and half-integer positions."""
+    import torch
+    print("[catalog dense cell, edges]", flush=True)
+    n = 32
+    rng = np.random.default_rng(11)
+    dense = np.array([7.2, 19.6]) + rng.uniform(0.0, 0.4, (3000, 2))            # one fine cell
+    edges = np.concatenate([rng.uniform(0, n, (200, 1)), rng.choice([0.0, n - 1e-9, n - 0.25], (200, 1))], 1)
+    corners = np.array([[0.0, 0.0], [n - 1e-12, n - 1e-12], [0.0, n - 0.5], [n - 0.5, 0.0], [0.5, 0.5]])
+    pos = np.concatenate([dense, edges, edges[:, ::-1], corners, np.round(rng.uniform(0, n, (50, 2))) / 2])
+    s = _field(rng, 2, n)
+    prob = _problem(lib, n, 2)
+    cat = _gcat(lib, torch, pos)
+    g = lib.catalog_forward(prob, cat, torch.tensor(s, dtype=torch.complex64, device="cuda:0")).cpu().numpy()
+    go = O.catalog_forward(s.astype(np.complex64).astype(np.complex128), pos)
+    assert np.max(np.abs(g - go)) <= 5e-6 * np.max(np.abs(go))
+    r = rng.standard_normal((2, len(pos))).astype(np.float32)
+    a = lib.catalog_adjoint(prob, cat, torch.tensor(r, device="cuda:0")).cpu().numpy()
+    ao = O.catalog_adjoint(r.astype(np.float64), pos, n)
+    print(f"   adjoint max err {np.max(np.abs(a - ao)) / np.max(np.abs(ao)):.2e}", flush=True)
+    assert np.max(np.abs(a - ao)) <= 5e-6 * np.max(np.abs(ao))
