@@ -16,7 +16,8 @@ workload ("secondary": 256^2 density band powers, 512^2 density maps, 1024^2 CMB
 the 96-map uneven batch against its plain path, the 512^2 shear catalog at the catalog level).
 
     python bench.py [--steps K] [--warmup W] [--nsim 6] [--n 512] [--no-cpu] [--no-plain]
-                    [--no-secondary]
+                    [--no-secondary] [--catalog-only]
+    python bench.py --pmc-summary FETCH_CSV WRITE_CSV   # profiles/pmc_traffic.json from rocprofv3 --pmc
 """
 from __future__ import annotations
 
@@ -48,28 +49,118 @@ def parse():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--plain-solves", type=int, default=0, help="plain-path solves to time (0 = all)")
     ap.add_argument("--no-secondary", action="store_true", help="skip the other workloads' lines")
+    ap.add_argument("--catalog-only", action="store_true",
+                    help="print only the 512^2 shear catalog line (for profiling the catalog solve)")
+    ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"), default=None,
+                    help="write profiles/pmc_traffic.json from two rocprofv3 --pmc counter files of this benchmark")
     ap.add_argument("--cpu-child", action="store_true", help=argparse.SUPPRESS)
     ap.add_argument("--cpu-out", default="", help=argparse.SUPPRESS)
     ap.add_argument("--cpu-cores", type=int, default=1, help=argparse.SUPPRESS)
     return ap.parse_args()
 
 
-def measured_traffic(kernel: str):
-    """HBM bytes per launch of `kernel` from the committed rocprofv3 PMC summary
-    (profiles/pmc_traffic.json), or None if the kernel sources changed since it was taken."""
-    import glob
+# translation unit each profiled kernel is compiled in (the PMC record is keyed to its sources)
+KERNEL_UNITS = {"k_passB": "wf_solver_k.hip", "k_passA": "wf_solver_k.hip", "k_cg_pass": "wf_solver_k.hip",
+                "k_cg_dir": "wf_solver_k.hip", "k_stream_copy": "wf_solver_k.hip",
+                "k_colinv": "wf_chain_f32l.hip", "k_colinvr": "wf_chain_f32l.hip", "k_row": "wf_chain_f32l.hip",
+                "k_rowr": "wf_chain_f32l.hip", "k_colfwd": "wf_chain_f32l.hip", "k_colfwdr": "wf_chain_f32l.hip"}
+
+
+def source_closure(unit: str):
+    """(files, sha1) of a kernel translation unit and every local header it includes."""
     import hashlib
+    import re
+    dirs = [os.path.join(ROOT, "paper_1810_00503_amd", "csrc"), os.path.join(ROOT, "include")]
+    seen, todo = [], [unit]
+    while todo:
+        f = todo.pop()
+        if f in seen:
+            continue
+        path = next((os.path.join(d, f) for d in dirs if os.path.exists(os.path.join(d, f))), None)
+        if path is None:
+            continue
+        seen.append(f)
+        for line in open(path):
+            m = re.match(r'\s*#include\s+"([^"]+)"', line)
+            if m:
+                todo.append(m.group(1))
+    h = hashlib.sha1()
+    for f in sorted(seen):
+        path = next(os.path.join(d, f) for d in dirs if os.path.exists(os.path.join(d, f)))
+        h.update(f.encode() + b"\0" + open(path, "rb").read())
+    return sorted(seen), h.hexdigest()
+
+
+def measured_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 PMC record
+    (profiles/pmc_traffic.json), or None if the sources the kernel is compiled from changed
+    since the counters were taken."""
     path = os.path.join(ROOT, "profiles", "pmc_traffic.json")
     if not os.path.exists(path):
         return None
-    rec = json.load(open(path))
-    h = hashlib.sha1()
-    for p in sorted(glob.glob(os.path.join(ROOT, "paper_1810_00503_amd", "csrc", "*"))):
-        h.update(open(p, "rb").read())
-    if h.hexdigest() != rec.get("csrc_sha1"):
+    k = json.load(open(path)).get("kernels", {}).get("k_" + kernel)
+    if k is None or "unit" not in k or source_closure(k["unit"])[1] != k.get("sources_sha1"):
         return None
-    k = rec.get("kernels", {}).get("k_" + kernel)
-    return None if k is None else k["traffic_bytes_per_launch"]
+    return k["traffic_bytes_per_launch"]
+
+
+def pmc_summary(fetch_csv: str, write_csv: str, copy_bytes: int = 2 * 1024 ** 3):
+    """Per-dispatch HBM bytes from two rocprofv3 --pmc runs of this benchmark (FETCH_SIZE, then
+    WRITE_SIZE; KiB per dispatch), calibrated by the library's streaming copy of copy_bytes that
+    the benchmark runs (k_stream_copy reads and writes copy_bytes).  Writes
+    profiles/pmc_traffic.json and prints a markdown table."""
+    import csv
+    from collections import defaultdict
+
+    def load(path, counter):
+        acc = defaultdict(list)
+        for r in csv.DictReader(open(path)):
+            if r["Counter_Name"] != counter:
+                continue
+            acc[(r["Kernel_Name"], int(r["Grid_Size"]))].append(float(r["Counter_Value"]) * 1024.0)
+        return acc
+
+    fetch, write = load(fetch_csv, "FETCH_SIZE"), load(write_csv, "WRITE_SIZE")
+
+    def short(name):
+        b = name.split("(")[0].replace("void ", "").strip()
+        return b.split("::")[-1].split("<")[0]
+
+    cf = [v for (k, g), vs in fetch.items() if short(k) == "k_stream_copy" for v in vs]
+    cw = [v for (k, g), vs in write.items() if short(k) == "k_stream_copy" for v in vs]
+    if not cf or not cw:
+        raise SystemExit("pmc-summary: no k_stream_copy dispatches in the counter files")
+    ff = copy_bytes / (sum(cf) / len(cf))
+    wf_ = copy_bytes / (sum(cw) / len(cw))
+    rows = []
+    for key in fetch:
+        if key not in write:
+            continue
+        f = sum(fetch[key]) / len(fetch[key])
+        w = sum(write[key]) / len(write[key])
+        rows.append((key[0], key[1], len(fetch[key]), f, w, ff * f + wf_ * w))
+    rows.sort(key=lambda r: -r[2] * r[5])
+    kernels = {}
+    for name, grid, disp, f, w, t in rows:
+        k = short(name)
+        if k not in KERNEL_UNITS or k in kernels:
+            continue   # the most-dispatched traffic of each kernel (the solver's own launches)
+        files, sha = source_closure(KERNEL_UNITS[k])
+        kernels[k] = {"name": name.split("(")[0].replace("void ", "").strip(), "grid": grid, "dispatches": disp,
+                      "traffic_bytes_per_launch": t, "unit": KERNEL_UNITS[k], "sources": files,
+                      "sources_sha1": sha}
+    rec = {"fetch_factor": ff, "write_factor": wf_, "copy_bytes": copy_bytes, "kernels": kernels}
+    with open(os.path.join(ROOT, "profiles", "pmc_traffic.json"), "w") as fh:
+        json.dump(rec, fh, indent=1)
+    mib = 1024.0 ** 2
+    print(f"calibration: k_stream_copy of {copy_bytes / mib:.0f} MiB reads FETCH_SIZE = "
+          f"{copy_bytes / ff / mib:.1f} MiB and WRITE_SIZE = {copy_bytes / wf_ / mib:.1f} MiB: read bytes = "
+          f"{ff:.3f} x FETCH_SIZE, written bytes = {wf_:.3f} x WRITE_SIZE")
+    print("| kernel | grid | dispatches | FETCH_SIZE avg (MiB) | WRITE_SIZE avg (MiB) | calibrated traffic avg (MiB) |")
+    print("|---|---:|---:|---:|---:|---:|")
+    for name, grid, disp, f, w, t in rows[:20]:
+        nm = name.split("(")[0].replace("void ", "").strip()
+        print(f"| `{nm}` | {grid} | {disp} | {f / mib:.1f} | {w / mib:.1f} | {t / mib:.1f} |")
 
 
 def host_cores() -> int:
@@ -474,8 +565,14 @@ def catalog_line(args):
 
 def main():
     args = parse()
+    if args.pmc_summary:
+        pmc_summary(*args.pmc_summary)
+        return
     if args.cpu_child:
         cpu_child(args)
+        return
+    if args.catalog_only:
+        print(json.dumps({"shear512_catalog": catalog_line(args)}), flush=True)
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the simulation batches would shard "
