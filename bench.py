@@ -51,6 +51,8 @@ def parse():
     ap.add_argument("--no-secondary", action="store_true", help="skip the other workloads' lines")
     ap.add_argument("--catalog-only", action="store_true",
                     help="print only the 512^2 shear catalog line (for profiling the catalog solve)")
+    ap.add_argument("--cmb-full", action="store_true",
+                    help="only the 1024^2 CMB band-power estimate at 256 simulations (10497 solves), one JSON line")
     ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"), default=None,
                     help="write profiles/pmc_traffic.json from two rocprofv3 --pmc counter files of this benchmark")
     ap.add_argument("--cpu-child", action="store_true", help=argparse.SUPPRESS)
@@ -492,6 +494,46 @@ def secondary_workloads(args):
     return out
 
 
+def cmb_full_line(args):
+    """The 1024^2 CMB band-power estimate at its full size: 40 linear bands, 256 simulations
+    (1 + 256 x 41 = 10497 MAP solves, run in batches of 256), preconditioned L-BFGS to the
+    bench's tolerance; one untimed estimate with 2 simulations first (tile tuning, graph capture)."""
+    import numpy as np
+    import torch
+
+    import paper_1810_00503_amd as wf
+    from paper_1810_00503_amd import workloads as WL
+    wf.load()
+    dev = "cuda:0"
+    wl = WL.cmb_patch()
+    base = wf.Problem(torch.tensor(wl.W, dtype=torch.float32, device=dev), wl.pshape, wl.band, wl.theta_fid)
+    d = wf.wf_simulate(base, 1, 4100, theta_true=wl.theta_true)[0]
+    prob = base.with_data(d)
+    popts = wf.LbfgsOpts(m=args.m, rel_grad_tol=args.tol, max_iter=4000, precond=1)
+    nsim = 256
+    wf.bandpower_qe(prob, 2, 4201, opts=popts)
+    torch.cuda.synchronize()
+    print(f"cmb-full: warm-up done, {nsim} simulations next", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    th, E, b, F, rc = wf.bandpower_qe(prob, nsim, 4201, opts=popts)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ns = 1 + nsim * (1 + wl.nbands)
+    # deviation from the truth in units of each band's conditional error 1 / sqrt(F_bb) (the
+    # damping tail's bands carry almost no signal, so the full inverse is dominated by noise)
+    fd = np.diag(F)
+    okb = fd > 0
+    z = np.abs(th - wl.theta_true)[okb] * np.sqrt(fd[okb])
+    return {"workload": f"1024^2 CMB (cmb_patch generator), {wl.nbands} linear bands, {nsim} simulations, "
+                        f"preconditioned L-BFGS m={args.m} to {args.tol:g} rel. grad",
+            "nsim": nsim, "solves": ns, "seconds": round(dt, 2), "estimates_per_s": round(1.0 / dt, 5),
+            "solves_per_s": round(ns / dt, 1), "all_converged": rc == wf.WF_OK,
+            "theta_hat_first_bands": [round(float(x), 4) for x in th[:5]],
+            "theta_hat_minus_truth_over_cond_sigma": {"median": round(float(np.median(z)), 3) if z.size else None,
+                                                      "max": round(float(np.max(z)), 3) if z.size else None,
+                                                      "bands": int(okb.sum())}}
+
+
 def catalog_line(args):
     """512^2 E/B shear at the catalog level (sec. 3.4): ~10 galaxies per observed pixel at
     their own positions, the field evaluated at each galaxy by the library's non-uniform
@@ -573,6 +615,9 @@ def main():
         return
     if args.catalog_only:
         print(json.dumps({"shear512_catalog": catalog_line(args)}), flush=True)
+        return
+    if args.cmb_full:
+        print(json.dumps({"cmb1024_bandpowers_nsim256": cmb_full_line(args)}), flush=True)
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the simulation batches would shard "
@@ -664,6 +709,26 @@ def main():
                    "iters_max": int(max(x.iters for x in st_p)),
                    "rel_grad_max": float(max(x.rel_grad for x in st_p)),
                    "converged": f"{sum(x.status == wf.WF_SOLVE_CONVERGED for x in st_p)}/{nsolve}"}
+    # the same batch at other history lengths (the paper does not fix m): per iteration the solver
+    # moves about 3m + 11 field vectors, so the history length trades traffic per iteration
+    # against the iterations it saves
+    m_sweep = None
+    if not args.no_secondary:
+        m_sweep = {}
+        for mm in (3, 5, 10, 16):
+            mopts = wf.LbfgsOpts(m=mm, rel_grad_tol=args.tol)
+            wf.map_wf_solve(sims, mopts)
+            torch.cuda.synchronize()
+            tm = []
+            for _ in range(3):
+                t0 = time.perf_counter()
+                _, _, st_m, _ = wf.map_wf_solve(sims, mopts)
+                torch.cuda.synchronize()
+                tm.append(time.perf_counter() - t0)
+            m_sweep[f"m={mm}"] = {"solves_per_s": round(nsolve / float(np.median(tm)), 2),
+                                  "iters_mean": round(float(np.mean([x.iters for x in st_m])), 1),
+                                  "iters_max": int(max(x.iters for x in st_m)),
+                                  "converged": f"{sum(x.status == wf.WF_SOLVE_CONVERGED for x in st_m)}/{nsolve}"}
     tiles = wf.get_chain_tiles(args.n, 2, wf.WF_F32, nsolve)
     conv = sum(s.status == wf.WF_SOLVE_CONVERGED for s in st_b)
 
@@ -761,6 +826,7 @@ def main():
         "batched_solve_only_solves_per_s": round(len(sims) / t_batch, 2),
         "batched_solve_only_cg": cg_line,
         "batched_solve_only_precond": pc_line,
+        "batched_solve_only_m_sweep": m_sweep,
         "plain_solves_per_s": None if plain is None else round(plain, 2),
         "plain_graph_solves_per_s": None if plain_graph is None else round(plain_graph, 2),
         "speedup_batched_vs_plain": None if plain is None else round(len(sims) / t_batch / plain, 2),
