@@ -34,8 +34,6 @@ def _close(got, ref, dtype):
 @pytest.mark.parametrize("n", SIZES)
 def test_forward_adjoint_match_oracle(lib, n, ncomp, dtype):
     import torch
-    if dtype == "f64" and n > 256:
-        pytest.skip("float64 transforms are checked up to 256^2")
     print(f"[forward/adjoint n={n} ncomp={ncomp} {dtype}]", flush=True)
     wl = _wl(n, ncomp)
     prob = make_problem(lib, torch, wl, dtype)
@@ -68,8 +66,6 @@ def test_forward_adjoint_match_oracle(lib, n, ncomp, dtype):
 @pytest.mark.parametrize("n", [16, 48, 64, 256, 512])
 def test_chi2_grad_hvp_band_E_match_oracle(lib, n, ncomp, dtype):
     import torch
-    if dtype == "f64" and n > 256:
-        pytest.skip("float64 checked up to 256^2")
     print(f"[chi2/grad/hvp/E n={n} ncomp={ncomp} {dtype}]", flush=True)
     if ncomp == 2:
         wl = WL.shear_workload(n, 3, nbands_e=3, nbands_b=3)
