@@ -13,10 +13,15 @@ by one and on properties that hold at any size:
   solve; sampled maps pass the oracle's gradient check and agree with their one-map-at-a-time
   solves (in the gradient, i.e. the energy norm, for the badly conditioned CMB maps, whose
   fields at a 1e-6 gradient tolerance differ by up to ~1e-3 in L2, and agree within 2e-5 once
-  refined in float64); the smallest shear map equals the oracle's MAP.
+  refined in float64); the smallest shear map equals the oracle's MAP; a 768^2 and a 1024^2 CMB
+  map of the batch, refined, against the oracle's MAP of the same data (committed references,
+  oracle to 1e-11).
 
 Bars: MAP 1e-5 relative L2 (the method's map tolerance), E_l 1e-4 (band powers), gradients
 1e-4 against central differences."""
+import json
+import os
+
 import numpy as np
 import pytest
 
@@ -25,6 +30,8 @@ from paper_1810_00503_amd import workloads as WL
 from tests.gpu_util import rel_l2
 
 pytestmark = pytest.mark.gpu
+
+UNEVEN_CMB_REFS = (75, 88)   # uneven_batch(96) maps with a committed oracle MAP (768^2, 1024^2)
 
 
 def _problem(lib, torch, wl, d=None):
@@ -102,9 +109,6 @@ def test_cmb1024_full_size(lib):
     this badly conditioned map far from it.  Also: a Philox simulation of the workload
     against the oracle's from the same stream, E_l of the field, and d chi^2 / d theta of the
     40 bands by central differences and against the oracle."""
-    import json
-    import os
-
     import torch
     print("[1024^2 cmb vs the oracle reference]", flush=True)
     here = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
@@ -159,6 +163,17 @@ def test_uneven96_batch_full_size(lib):
     for i, wl in enumerate(wls):
         base = _problem(lib, torch, wl)
         probs.append(base.with_data(lib.wf_simulate(base, 1, 5100 + i, theta_true=wl.theta_true)[0]))
+    # two CMB maps (768^2 and 1024^2) take the oracle's simulation of the same Philox streams,
+    # whose MAP the oracle has solved to 1e-11 (tests/golden/uneven_cmb*_map.npy)
+    here = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+    refs = {}
+    for i in UNEVEN_CMB_REFS:
+        wl = wls[i]
+        draws = O.philox.draws_for_sims(5100 + i, [0], wl.n, wl.ncomp)[0]
+        d = O.simulate(draws, O.prior_S(wl.pshape, wl.band, wl.theta_true), wl.W)
+        probs[i] = probs[i].with_data(torch.tensor(d, dtype=torch.float32, device="cuda:0"))
+        refs[i] = (np.load(os.path.join(here, f"uneven_cmb{i}_map.npy")).astype(np.complex128),
+                   json.load(open(os.path.join(here, f"uneven_cmb{i}_map.json"))))
     opts = lib.LbfgsOpts(rel_grad_tol=1e-6, max_iter=4000, precond=1)
     s, _, st, rc = lib.map_wf_solve(probs, opts)
     stat = [x.status for x in st]
@@ -203,6 +218,14 @@ def test_uneven96_batch_full_size(lib):
         dl2 = rel_l2(sr[i].cpu().numpy(), one[0].cpu().numpy())
         print(f"  refined {wls[i].name}: {str_[i].iters} iterations, batched vs alone {dl2:.2e}", flush=True)
         assert st1[0].status == lib.WF_SOLVE_CONVERGED and dl2 < 2e-5
+    # the refined fields of the batch against the oracle's MAP of the same data (field and map)
+    for i, (ref, meta) in refs.items():
+        got = sr[i].cpu().numpy().astype(np.complex128)
+        ef, em = rel_l2(got, ref), rel_l2(O.forward(got), O.forward(ref))
+        print(f"  refined {wls[i].name} (map {i}) vs oracle MAP: field {ef:.2e}, map {em:.2e}; chi2 "
+              f"{str_[i].chi2:.10e} vs {meta['chi2']:.10e}", flush=True)
+        assert ef <= 1e-5 and em <= 1e-5
+        assert abs(str_[i].chi2 - meta["chi2"]) <= 1e-7 * meta["chi2"]
     shear = [i for i, wl in enumerate(wls) if wl.ncomp == 2]
     i = min(shear, key=lambda j: wls[j].n)
     wl = wls[i]
@@ -219,9 +242,6 @@ def test_bandpowers_full_size_vs_oracle(lib, case):
     (all 12 / 20 bands; 3 / 2 simulations from the Philox stream) against the oracle's
     estimate of the same data and simulations (tests/golden/bandpowers_full.json): E, b and
     F within 1e-4, Theta_hat within that bar carried through the Newton step."""
-    import json
-    import os
-
     import torch
     ref = json.load(open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
                                       "bandpowers_full.json")))[case]
