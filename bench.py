@@ -49,6 +49,8 @@ def parse():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--plain-solves", type=int, default=0, help="plain-path solves to time (0 = all)")
     ap.add_argument("--no-secondary", action="store_true", help="skip the other workloads' lines")
+    ap.add_argument("--lbfgs-only", action="store_true",
+                    help="skip the conjugate-gradient comparison (for counter runs: only L-BFGS launches of the chain)")
     ap.add_argument("--catalog-only", action="store_true",
                     help="print only the 512^2 shear catalog line (for profiling the catalog solve)")
     ap.add_argument("--cmb-full", action="store_true",
@@ -676,25 +678,27 @@ def main():
     t_batch = float(np.median(tb))
     iters = [s.iters for s in st_b]
     # the same batch with conjugate gradients (same operator, tolerance and stop test)
-    copts = wf.LbfgsOpts(m=args.m, rel_grad_tol=args.tol, method=wf.WF_METHOD_CG)
-    wf.map_wf_solve(sims, copts)
-    torch.cuda.synchronize()
-    tc = []
-    for _ in range(3):
-        t0 = time.perf_counter()
-        _, _, st_c, _ = wf.map_wf_solve(sims, copts)
+    cg_line = None
+    if not args.lbfgs_only:
+        copts = wf.LbfgsOpts(m=args.m, rel_grad_tol=args.tol, method=wf.WF_METHOD_CG)
+        wf.map_wf_solve(sims, copts)
         torch.cuda.synchronize()
-        tc.append(time.perf_counter() - t0)
-    cg_line = {"solves_per_s": round(nsolve / float(np.median(tc)), 2),
-               "iters_mean": round(float(np.mean([x.iters for x in st_c])), 1),
-               "iters_max": int(max(x.iters for x in st_c)),
-               "exact_gradients_mean": round(float(np.mean([x.ngrad for x in st_c])), 1),
-               "converged": f"{sum(x.status == wf.WF_SOLVE_CONVERGED for x in st_c)}/{nsolve}"}
+        tc = []
+        for _ in range(3):
+            t0 = time.perf_counter()
+            _, _, st_c, _ = wf.map_wf_solve(sims, copts)
+            torch.cuda.synchronize()
+            tc.append(time.perf_counter() - t0)
+        cg_line = {"solves_per_s": round(nsolve / float(np.median(tc)), 2),
+                   "iters_mean": round(float(np.mean([x.iters for x in st_c])), 1),
+                   "iters_max": int(max(x.iters for x in st_c)),
+                   "exact_gradients_mean": round(float(np.mean([x.ngrad for x in st_c])), 1),
+                   "converged": f"{sum(x.status == wf.WF_SOLVE_CONVERGED for x in st_c)}/{nsolve}"}
     # the same batch with the optional diagonal noise-aware preconditioner (off by default: the method
     # solves without one); the stop test stays the exact whitened relative gradient
     # (with the secondary lines: it would mix shorter-history pass-B launches into a profile of the step)
     pc_line = None
-    if not args.no_secondary:
+    if not args.no_secondary and not args.lbfgs_only:
         pcopts = wf.LbfgsOpts(m=args.m, rel_grad_tol=args.tol, precond=1)
         wf.map_wf_solve(sims, pcopts)
         torch.cuda.synchronize()
@@ -713,7 +717,7 @@ def main():
     # moves about 3m + 11 field vectors, so the history length trades traffic per iteration
     # against the iterations it saves
     m_sweep = None
-    if not args.no_secondary:
+    if not args.no_secondary and not args.lbfgs_only:
         m_sweep = {}
         for mm in (3, 5, 10, 16):
             mopts = wf.LbfgsOpts(m=mm, rel_grad_tol=args.tol)
@@ -729,7 +733,6 @@ def main():
                                   "iters_mean": round(float(np.mean([x.iters for x in st_m])), 1),
                                   "iters_max": int(max(x.iters for x in st_m)),
                                   "converged": f"{sum(x.status == wf.WF_SOLVE_CONVERGED for x in st_m)}/{nsolve}"}
-    tiles = wf.get_chain_tiles(args.n, 2, wf.WF_F32, nsolve)
     conv = sum(s.status == wf.WF_SOLVE_CONVERGED for s in st_b)
 
     plain = plain_graph = None
@@ -797,6 +800,22 @@ def main():
     ag = (alg + gram) / (cm * 1e-3) / 1e9 if cm > 0 else 0.0
     roof_chain["algorithmic_with_gram_bytes_per_step"] = alg + gram
     roof_chain["algorithmic_with_gram_frac"] = round(ag / HBM_PEAK_GBS, 4)
+
+    # the chain's HBM bytes by the committed counters (rocprofv3 FETCH_SIZE / WRITE_SIZE of the
+    # L-BFGS launches of these kernels, calibrated by the streaming copy), per step: each
+    # kernel's counted bytes per launch times its launches in the instrumented step; null when
+    # any of the three kernels' sources changed since the counters were taken
+    tiles = wf.get_chain_tiles(args.n, 2, wf.WF_F32, nsolve)
+    names = {"colinv": "colinvr" if tiles[3] & 2 else "colinv", "row": "rowr" if tiles[3] & 1 else "row",
+             "colfwd": "colfwdr" if tiles[3] & 4 else "colfwd"}
+    per_launch = {k: measured_traffic(v) for k, v in names.items()}
+    if all(v is not None for v in per_launch.values()):
+        tb = sum(per_launch[k] * ks[k]["launches"] for k in chain_k)
+        roof_chain["traffic"] = tb
+        roof_chain["traffic_GBps"] = round(tb / (cm * 1e-3) / 1e9, 1) if cm > 0 else None
+        roof_chain["traffic_frac"] = round(tb / (cm * 1e-3) / 1e9 / HBM_PEAK_GBS, 4) if cm > 0 else None
+    else:
+        roof_chain["traffic"] = None
 
     # measured copy ceiling (context for the roofline): the library's streaming copy of 2 GiB
     roof["copy_ceiling_GBps"] = round(wf.copy_bandwidth(2 * 1024 ** 3, 5), 1)
