@@ -296,7 +296,7 @@ def cpu_child(args):
 
 def secondary_workloads(args):
     """The other workloads, one timed call each after one untimed call (inputs resident):
-    256^2 density band powers (128 simulations, 1665 solves per estimate; then with 5 of the
+    the 64^2 float64 density map alone and 1024 of them, 256^2 density band powers (128 simulations, 1665 solves per estimate; then with 5 of the
     12 Fisher rows simulated, and two steps of the fiducial iteration with those), the scalar
     512^2 density variant (127 maps), 1024^2 CMB maps (preconditioned, 16 maps) and the
     96-map uneven batch (preconditioned) against its plain one-map-at-a-time path."""
@@ -327,6 +327,24 @@ def secondary_workloads(args):
                 "converged": f"{conv}/{len(probs)}"}
 
     out = {}
+    # 64^2 projected density in float64 (m = 10, stop at 1e-8): one map alone (the map the tests
+    # compare with the dense Wiener filter), and 1024 such maps (distinct noise realisations) in
+    # one batched call with preallocated outputs
+    wl = WL.density64()
+    b64 = wf.Problem(torch.tensor(wl.W, dtype=torch.float64, device=dev), wl.pshape, wl.band, wl.theta_fid)
+    d64 = wf.wf_simulate(b64, 1024, 1100, theta_true=wl.theta_true)
+    o64 = wf.LbfgsOpts(m=10, rel_grad_tol=1e-8)
+    one = [b64.with_data(d64[0])]
+    (_, _, st1, _), dt1 = timed(lambda: wf.map_wf_solve(one, o64))
+    many = [b64.with_data(d64[i]) for i in range(1024)]
+    buf = [torch.empty((1, 64, 33), dtype=torch.complex128, device=dev) for _ in many]
+    (_, _, stm, _), dtm = timed(lambda: wf.map_wf_solve(many, o64, out=buf))
+    out["density64_f64"] = {"workload": "64^2 projected density, float64, L-BFGS m=10 to 1e-8 rel. grad",
+                            "one_map_ms": round(dt1 * 1e3, 3), "one_map_iters": st1[0].iters,
+                            "batch1024_solves_per_s": round(1024 / dtm, 1),
+                            "batch1024_iters_mean": round(float(np.mean([x.iters for x in stm])), 1),
+                            "batch1024_converged": f"{sum(x.status == wf.WF_SOLVE_CONVERGED for x in stm)}/1024"}
+    del d64, many, buf
     # 256^2 density band powers: one estimate = data + 128 simulations x (1 + 12 bands)
     wl = WL.density_bands()
     base = base_of(wl)

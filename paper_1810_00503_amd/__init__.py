@@ -173,6 +173,7 @@ class Problem:
     def with_data(self, d) -> "Problem":
         p = object.__new__(Problem)
         p.__dict__.update(self.__dict__)
+        p.__dict__.pop("_cstruct", None)
         torch = _torch()
         p.d = torch.as_tensor(d, dtype=self.rdtype, device=self.device).contiguous()
         p._check()
@@ -181,6 +182,7 @@ class Problem:
     def with_theta(self, theta) -> "Problem":
         p = object.__new__(Problem)
         p.__dict__.update(self.__dict__)
+        p.__dict__.pop("_cstruct", None)
         p.theta = np.ascontiguousarray(np.asarray(theta, dtype=np.float64).reshape(-1))
         return p
 
@@ -198,11 +200,21 @@ class Problem:
         return int(self.theta.size)
 
     def c(self) -> L.WfProblem:
+        """The C-ABI struct of this problem: plain pointers to its tensors and to theta.  Built
+        once per object and reused while the object still holds the same tensors and theta
+        (with_data / with_theta make new objects), so a batch call does not rebuild a struct
+        per problem; the cache keeps those objects alive, so their pointers stay valid."""
+        objs = (self.d, self.w, self.pshape, self.band, self.theta)
+        cached = self.__dict__.get("_cstruct")
+        if cached is not None and all(a is b for a, b in zip(cached[0], objs)):
+            return cached[1]
         th = self.theta.ctypes.data_as(C.POINTER(C.c_double)) if self.theta.size else None
-        return L.WfProblem(self.n, self.ncomp, self.dtype_code, self.theta.size,
-                           self.d.data_ptr() if self.d is not None else None,
-                           self.w.data_ptr() if self.w is not None else None,
-                           self.pshape.data_ptr(), self.band.data_ptr(), th)
+        cs = L.WfProblem(self.n, self.ncomp, self.dtype_code, self.theta.size,
+                         self.d.data_ptr() if self.d is not None else None,
+                         self.w.data_ptr() if self.w is not None else None,
+                         self.pshape.data_ptr(), self.band.data_ptr(), th)
+        self.__dict__["_cstruct"] = (objs, cs)
+        return cs
 
     def device_index(self) -> int:
         return self.device.index or 0
@@ -224,7 +236,17 @@ def _dptr(t):
 def _out_buffers(torch, given, problems, shape_of, dtype_of, what):
     """Caller-supplied output tensors, checked against the problems, or new ones."""
     if given is None:
-        return [torch.empty(shape_of(p), dtype=dtype_of(p), device=p.device) for p in problems]
+        # one allocation per distinct (shape, dtype, device), handed out as views: a batch of
+        # many small maps would otherwise spend most of a call in the allocator
+        groups = {}
+        for i, p in enumerate(problems):
+            groups.setdefault((shape_of(p), dtype_of(p), p.device), []).append(i)
+        outs = [None] * len(problems)
+        for (shape, dt, dev), idx in groups.items():
+            big = torch.empty((len(idx),) + tuple(shape), dtype=dt, device=dev)
+            for j, t in zip(idx, big.unbind(0)):
+                outs[j] = t
+        return outs
     given = list(given)
     if len(given) != len(problems):
         raise ValueError(f"{what}: {len(given)} tensors for {len(problems)} problems")
