@@ -584,7 +584,7 @@ struct SolveOut {
   std::vector<void*> w;         // per user index: whitened solution
   std::vector<void*> y;         // per user index: intermediate buffer
   std::vector<PriorTab> prior;  // per user index
-  std::vector<LbState> st;      // per user index
+  std::vector<StateStat> st;    // per user index
   std::vector<int> order;       // class-ordered position of each user index
 };
 
@@ -788,7 +788,8 @@ constexpr int kRefineMinIter = 200;
 
 template <typename InitF, typename RunF>
 int refine_f64(wf_ctx* ctx, const wf_lbfgs_opts& o, const std::vector<Klass>& ks, std::vector<InstDesc>& hd,
-               InstDesc* ddesc, LbState* dst, std::vector<LbState>& hs, InitF& init_class, RunF& run_loop) {
+               InstDesc* ddesc, LbState* dst, StateStat* dss, std::vector<StateStat>& hs, InitF& init_class,
+               RunF& run_loop) {
   const double T = o.refine_tol;
   std::vector<int> fk;
   for (size_t c = 0; c < ks.size(); ++c)
@@ -967,8 +968,9 @@ int refine_f64(wf_ctx* ctx, const wf_lbfgs_opts& o, const std::vector<Klass>& ks
     }
     rc = run_loop(nrun);
     if (rc) return rc;
-    std::vector<LbState> cs(B);
-    HIPCHK(hipMemcpyAsync(cs.data(), dst, sizeof(LbState) * B, hipMemcpyDeviceToHost, ctx->cs));
+    std::vector<StateStat> cs(B);
+    HIPCHK(state_stats_launch(dst, dss, B, ctx->cs));
+    HIPCHK(hipMemcpyAsync(cs.data(), dss, sizeof(StateStat) * B, hipMemcpyDeviceToHost, ctx->cs));
     HIPCHK(hipStreamSynchronize(ctx->cs));
     for (int c : fk) {
       if (nrun[c] == 0) continue;
@@ -1002,7 +1004,7 @@ int refine_f64(wf_ctx* ctx, const wf_lbfgs_opts& o, const std::vector<Klass>& ks
       const int gi = k.first + (int)j;
       hc.push_back(CvtJob{rf[gi].v64, hd[gi].X, 2 * k.L, CVT_F64_F32, 0});
       if (!conv0[gi]) continue;
-      LbState& S = hs[gi];
+      StateStat& S = hs[gi];
       S.status = rho[gi] <= T ? WF_SOLVE_CONVERGED : WF_SOLVE_MAXITER;
       S.iter += addIt[gi];
       S.ngrad += addGrad[gi];
@@ -1116,7 +1118,7 @@ int solve_core(wf_ctx* ctx, const wf_problem* probs, int B, const wf_lbfgs_opts&
     }
   }
   total += align_up(sizeof(InstDesc) * B) + align_up(sizeof(LbState) * B) + align_up(sizeof(Job) * B) +
-           align_up(sizeof(int) * B);
+           align_up(sizeof(int) * B) + align_up(sizeof(StateStat) * B);
   int rc = arena_reserve(ctx, ctx->solveA, total);
   if (rc) return rc;
   Arena& A = ctx->solveA;
@@ -1124,6 +1126,7 @@ int solve_core(wf_ctx* ctx, const wf_problem* probs, int B, const wf_lbfgs_opts&
   LbState* dst = (LbState*)arena_take(A, sizeof(LbState) * B);
   Job* djobs = (Job*)arena_take(A, sizeof(Job) * B);
   int* dstat = (int*)arena_take(A, sizeof(int) * B);
+  StateStat* dss = (StateStat*)arena_take(A, sizeof(StateStat) * B);
   // the catalog classes' descriptor and job arrays next, at offsets fixed by the batch shape
   // (captured graphs take them as kernel arguments)
   for (auto& k : ks) {
@@ -1394,18 +1397,19 @@ int solve_core(wf_ctx* ctx, const wf_problem* probs, int B, const wf_lbfgs_opts&
     rc = run_loop(nrun);
     if (rc) return rc;
   }
-  std::vector<LbState> hs(B);
-  HIPCHK(hipMemcpyAsync(hs.data(), dst, sizeof(LbState) * B, hipMemcpyDeviceToHost, ctx->cs));
+  std::vector<StateStat> hs(B);
+  HIPCHK(state_stats_launch(dst, dss, B, ctx->cs));
+  HIPCHK(hipMemcpyAsync(hs.data(), dss, sizeof(StateStat) * B, hipMemcpyDeviceToHost, ctx->cs));
   HIPCHK(hipStreamSynchronize(ctx->cs));
   for (int gi = 0; gi < B; ++gi) {
     if (hs[gi].status == ST_RUNNING) hs[gi].status = WF_SOLVE_MAXITER;
     for (int k = 0; k < KK_COUNT; ++k) ctx->bytes[k] += hs[gi].bytes[k];
   }
   if (o.refine > 0) {
-    rc = refine_f64(ctx, o, ks, hd, ddesc, dst, hs, init_class, run_loop);
+    rc = refine_f64(ctx, o, ks, hd, ddesc, dst, dss, hs, init_class, run_loop);
     if (rc) return rc;
   }
-  out.st.assign(B, LbState());
+  out.st.resize(B);
   for (int ui = 0; ui < B; ++ui) out.st[ui] = hs[out.order[ui]];
   return WF_OK;
 }
@@ -1413,7 +1417,7 @@ int solve_core(wf_ctx* ctx, const wf_problem* probs, int B, const wf_lbfgs_opts&
 void fill_stats(const SolveOut& so, int B, wf_solve_stats* stats) {
   if (!stats) return;
   for (int i = 0; i < B; ++i) {
-    const LbState& S = so.st[i];
+    const StateStat& S = so.st[i];
     stats[i].iters = S.iter;
     stats[i].status = S.status;
     stats[i].ngrad = S.ngrad;

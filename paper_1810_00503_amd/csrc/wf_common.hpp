@@ -234,6 +234,19 @@ struct LbState {
   int confirm;                 // the pending exact gradient confirms a stop: pass A takes g.g only
 };
 
+// What the host reads back of an instance's state at the end of a solve (the full state is
+// ~4.7 KB per instance; this is what the statistics, the refinement and the byte counts use).
+struct StateStat {
+  int status;
+  int iter;
+  int ngrad;
+  int pad;
+  double chi2;
+  double gg;
+  double g0norm;
+  double bytes[KK_COUNT];
+};
+
 // One instance of a batched pack (internal whitened field -> caller's external field).
 struct PackEntry {
   const void* in;   // internal field

@@ -114,6 +114,8 @@ hipError_t cat_prep_launch(const double* pos, const uint32_t* skey, const uint32
 // inter: the sorted side is [ngal][c] (interleaved) instead of [c][ngal]
 hipError_t cat_permute_launch(const float* src, const int* perm, float* dst, int ngal, int c, int gather, int inter,
                               hipStream_t s);
+// the states' scalars the host reads at the end of a solve, [batch] StateStat
+hipError_t state_stats_launch(const LbState* st, StateStat* out, int batch, hipStream_t s);
 // streaming copy of `bytes` (a multiple of 16) for the bandwidth reference
 hipError_t stream_copy_launch(const void* src, void* dst, uint64_t bytes, hipStream_t s);
 

@@ -1227,6 +1227,23 @@ __global__ void k_band_final(const BandJob* __restrict__ jobs, int nblk) {
 }
 
 // ------------------------------------------------------------------------ float64 refinement
+// compact copy of the states' scalars the host reads at the end of a solve
+__global__ void k_state_stats(const LbState* __restrict__ st, StateStat* __restrict__ out, int batch) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= batch) return;
+  const LbState& S = st[i];
+  StateStat r;
+  r.status = S.status;
+  r.iter = S.iter;
+  r.ngrad = S.ngrad;
+  r.pad = 0;
+  r.chi2 = S.chi2;
+  r.gg = S.gg;
+  r.g0norm = S.g0norm;
+  for (int k = 0; k < KK_COUNT; ++k) r.bytes[k] = S.bytes[k];
+  out[i] = r;
+}
+
 __global__ void k_convert(const CvtJob* __restrict__ jobs) {
   const CvtJob J = jobs[blockIdx.y];
   const int64_t step = (int64_t)gridDim.x * blockDim.x;

@@ -177,6 +177,12 @@ hipError_t refine_rhs_launch(const RhsJob* jobs, int count, int nblk, hipStream_
   return hipGetLastError();
 }
 
+hipError_t state_stats_launch(const LbState* st, StateStat* out, int batch, hipStream_t s) {
+  if (batch <= 0) return hipSuccess;
+  k_state_stats<<<dim3((unsigned)((batch + 255) / 256)), 256, 0, s>>>(st, out, batch);
+  return hipGetLastError();
+}
+
 hipError_t stream_copy_launch(const void* src, void* dst, uint64_t bytes, hipStream_t s) {
   const uint64_t n = bytes / 16;
   const uint64_t blocks = (n + 256 * COPY_U - 1) / (256 * COPY_U);
