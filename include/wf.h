@@ -97,7 +97,7 @@ typedef struct {
   double dchi2_tol;       /* also stop when |chi^2_k - chi^2_{k-1}| < this (0 = off)      */
   int32_t refresh_every;  /* recompute the exact gradient every this many iterations
                              (0 = only when the running gradient meets the tolerance)    */
-  int32_t iters_per_poll; /* iterations enqueued between host checks (0 = automatic)     */
+  int32_t iters_per_poll; /* iterations enqueued between host checks (0 = automatic: 8)  */
   int32_t use_graph;      /* 1 = replay captured HIP graphs of the iteration (default),
                              0 = launch kernels one by one                               */
   int32_t precond;        /* 0 = H0 = gamma I in the whitened variable w = S^-1/2 s (the

@@ -1269,7 +1269,7 @@ int solve_core(wf_ctx* ctx, const wf_problem* probs, int B, const wf_lbfgs_opts&
   };
   rc = host_status(ctx, B);
   if (rc) return rc;
-  int K = o.iters_per_poll > 0 ? o.iters_per_poll : (B > 1 ? 8 : 1);
+  int K = o.iters_per_poll > 0 ? o.iters_per_poll : 8;   // iterations an instance may run past its stop are no-ops
   const bool graph = o.use_graph != 0 && !ctx->prof && K > 0;
   const int nk = (int)ks.size();
   std::vector<hipGraphExec_t> gx(nk, nullptr);
