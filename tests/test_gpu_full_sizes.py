@@ -263,3 +263,51 @@ def test_bandpowers_full_size_vs_oracle(lib, case):
     Fi[np.ix_(use, use)] = np.abs(np.linalg.inv(Fo[np.ix_(use, use)]))
     bound = 1e-4 * (Fi @ (np.abs(Eo) + np.abs(bo)) + Fi @ np.abs(Fo) @ np.abs(tho - wl.theta_fid) + np.abs(tho))
     assert np.all(np.abs(th - tho) <= bound), (th, tho, bound)
+
+
+@pytest.mark.parametrize("case", ["density256_rows", "shear512_leakage"])
+def test_estimators_full_size_vs_oracle(lib, case):
+    """At full size against the oracle with the same Philox simulations
+    (tests/golden/estimators_full.json): the 256^2 density workload's b and F with 5 of its 12
+    Fisher rows simulated and the others interpolated (3 simulations; float64 and float32), and
+    the 512^2 E/B shear workload's B-mode estimate with the E->B leakage as its bias (2
+    simulations): E_B, b_B, F_BB within 1e-4 and Theta_hat_B within that bar carried through its
+    solve."""
+    import torch
+    ref = json.load(open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                                      "estimators_full.json")))[case]
+    print(f"[{case} vs oracle, nsim={ref['nsim']}]", flush=True)
+    opts = lib.LbfgsOpts(rel_grad_tol=1e-6)
+    if case == "density256_rows":
+        # The interpolated Fisher entries are rescaled by the per-band sample variance of E over
+        # the simulations, which with 3 simulations amplifies a solve's own error (~1e-6 at the
+        # float32 stop) about a thousandfold in some entries: the float64 solve (to 1e-10) is held
+        # to the 1e-4 bar, the float32 solve to 3e-3 of the largest entry.
+        wl = WL.density_bands(256)
+        bo, Fo = np.array(ref["b"]), np.array(ref["F"])
+        for dt, tol, bar in (("f64", 1e-10, 1e-4), ("f32", 1e-6, 3e-3)):
+            W = torch.tensor(wl.W, dtype=torch.float64 if dt == "f64" else torch.float32, device="cuda:0")
+            prob = lib.Problem(W, wl.pshape, wl.band, wl.theta_fid)
+            F, b, _, rc = lib.sim_fisher_rows(prob, ref["nsim"], ref["sim_seed"], rows=ref["rows"],
+                                              opts=lib.LbfgsOpts(rel_grad_tol=tol))
+            assert rc == lib.WF_OK
+            print(f"  {dt}: max |b/bo - 1| {np.max(np.abs(b / bo - 1)):.2e}, "
+                  f"max |F - Fo| / max|Fo| {np.max(np.abs(F - Fo)) / np.abs(Fo).max():.2e}", flush=True)
+            np.testing.assert_allclose(b, bo, rtol=1e-4)
+            np.testing.assert_allclose(F, Fo, rtol=bar, atol=bar * np.abs(Fo).max())
+        return
+    wl = WL.shear_eb(512)
+    d = O.simulate(WL.white_draws(wl.n, wl.ncomp, 1, ref["data_seed"])[0],
+                   O.prior_S(wl.pshape, wl.band, wl.theta_true), wl.W)
+    prob = _problem(lib, torch, wl, d=torch.tensor(d, dtype=torch.float32, device="cuda:0"))
+    th, E, b, F, rc = lib.bmode_leakage_qe(prob, ref["nsim"], ref["sim_seed"], ref["b_bands"], opts=opts)
+    assert rc == lib.WF_OK
+    Eo, bo, Fo, tho = (np.array(ref[k]) for k in ("E_B", "b_B", "F_BB", "theta_hat_B"))
+    print(f"  max |E/Eo - 1| {np.max(np.abs(E / Eo - 1)):.2e}, max |b/bo - 1| {np.max(np.abs(b / bo - 1)):.2e}, "
+          f"max |F - Fo| / max|Fo| {np.max(np.abs(F - Fo)) / np.abs(Fo).max():.2e}", flush=True)
+    np.testing.assert_allclose(E, Eo, rtol=1e-4)
+    np.testing.assert_allclose(b, bo, rtol=1e-4)
+    np.testing.assert_allclose(F, Fo, rtol=1e-4, atol=1e-4 * np.abs(Fo).max())
+    Fi = np.abs(np.linalg.inv(Fo))
+    bound = 1e-4 * (Fi @ (np.abs(Eo) + np.abs(bo)) + Fi @ np.abs(Fo) @ np.abs(tho)) + 1e-12
+    assert np.all(np.abs(th - tho) <= bound), (th, tho, bound)
