@@ -263,7 +263,8 @@ def map_wf_solve(problems: Sequence[Problem], opts: LbfgsOpts | None = None, wan
     """MAP fields of a batch of problems (uneven sizes allowed).
     Returns (s list of complex [ncomp][n][n/2+1], maps list or None, stats list, rc).
     `out` (and `maps_out`, which implies want_maps) are optional preallocated output tensors,
-    one per problem; a loop that passes the same ones every call allocates nothing per call."""
+    one per problem; a loop that passes the same ones every call allocates nothing per call.
+    Outputs allocated here are views into one tensor per distinct shape (disjoint rows of it)."""
     torch = _torch()
     problems = list(problems)
     B = len(problems)
