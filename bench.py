@@ -838,6 +838,10 @@ def main():
     # measured copy ceiling (context for the roofline): the library's streaming copy of 2 GiB
     roof["copy_ceiling_GBps"] = round(wf.copy_bandwidth(2 * 1024 ** 3, 5), 1)
     roof_chain["copy_ceiling_GBps"] = roof["copy_ceiling_GBps"]
+    # the same rates as fractions of that measured ceiling (context beside the peak fraction)
+    if roof["copy_ceiling_GBps"] > 0:
+        roof["frac_of_copy_ceiling"] = round(achieved / roof["copy_ceiling_GBps"], 4)
+        roof_chain["frac_of_copy_ceiling"] = round(ca / roof["copy_ceiling_GBps"], 4)
 
     def gpu_solve(ds):
         probs = [base.with_data(torch.tensor(np.asarray(d), dtype=torch.float32, device=dev)) for d in ds]
