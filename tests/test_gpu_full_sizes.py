@@ -311,3 +311,37 @@ def test_estimators_full_size_vs_oracle(lib, case):
     Fi = np.abs(np.linalg.inv(Fo))
     bound = 1e-4 * (Fi @ (np.abs(Eo) + np.abs(bo)) + Fi @ np.abs(Fo) @ np.abs(tho)) + 1e-12
     assert np.all(np.abs(th - tho) <= bound), (th, tho, bound)
+
+
+def test_uneven_batch_estimates_full_size_vs_oracle(lib):
+    """Three maps of the 96-map uneven batch (a 128^2 CMB, a 256^2 density and a 512^2 shear
+    map) estimated together by bandpower_qe_batch (their solves shared among batched solves,
+    preconditioned and refined in float64) against the oracle's estimate of each with the same
+    data and Philox simulations (tests/golden/batch_full.json): E, b, F within 1e-4, Theta_hat
+    within that bar carried through the Newton step."""
+    import torch
+    ref = json.load(open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "batch_full.json")))
+    print(f"[uneven batch estimates vs oracle, maps {ref['maps']}, nsim={ref['nsim']}]", flush=True)
+    wls = [WL.uneven_batch(96)[i] for i in ref["maps"]]
+    probs = []
+    for j, wl in enumerate(wls):
+        d = O.simulate(WL.white_draws(wl.n, wl.ncomp, 1, ref["data_seed0"] + j)[0],
+                       O.prior_S(wl.pshape, wl.band, wl.theta_true), wl.W)
+        probs.append(_problem(lib, torch, wl, d=torch.tensor(d, dtype=torch.float32, device="cuda:0")))
+    opts = lib.LbfgsOpts(rel_grad_tol=1e-6, max_iter=4000, precond=1, refine=4, refine_tol=1e-11)
+    th, E, b, F, rc = lib.bandpower_qe_batch(probs, ref["nsim"], ref["sim_seed"], opts=opts)
+    assert rc == lib.WF_OK
+    for j, (wl, est) in enumerate(zip(wls, ref["estimates"])):
+        Eo, bo, Fo, tho = (np.array(est[k]) for k in ("E", "b", "F", "theta_hat"))
+        print(f"  {wl.name}: max |E/Eo - 1| {np.max(np.abs(E[j] / Eo - 1)):.2e}, "
+              f"max |b/bo - 1| {np.max(np.abs(b[j] / bo - 1)):.2e}, "
+              f"max |F - Fo| / max|Fo| {np.max(np.abs(F[j] - Fo)) / np.abs(Fo).max():.2e}", flush=True)
+        np.testing.assert_allclose(E[j], Eo, rtol=1e-4)
+        np.testing.assert_allclose(b[j], bo, rtol=1e-4)
+        np.testing.assert_allclose(F[j], Fo, rtol=1e-4, atol=1e-4 * np.abs(Fo).max())
+        use = np.diag(Fo) > 1e-9 * np.diag(Fo).max()
+        Fi = np.zeros_like(Fo)
+        Fi[np.ix_(use, use)] = np.abs(np.linalg.inv(Fo[np.ix_(use, use)]))
+        bound = 1e-4 * (Fi @ (np.abs(Eo) + np.abs(bo)) + Fi @ np.abs(Fo) @ np.abs(tho - wl.theta_fid)
+                        + np.abs(tho))
+        assert np.all(np.abs(th[j] - tho) <= bound), (wl.name, th[j], tho, bound)
