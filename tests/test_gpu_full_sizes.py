@@ -13,7 +13,8 @@ by one and on properties that hold at any size:
   solve; sampled maps pass the oracle's gradient check and agree with their one-map-at-a-time
   solves (in the gradient, i.e. the energy norm, for the badly conditioned CMB maps, whose
   fields at a 1e-6 gradient tolerance differ by up to ~1e-3 in L2, and agree within 2e-5 once
-  refined in float64); the smallest shear map equals the oracle's MAP; a 768^2 and a 1024^2 CMB
+  refined in float64); the smallest shear map and the largest (1024^2) shear and density maps
+  equal the oracle's MAP; a 768^2 and a 1024^2 CMB
   map of the batch, refined, against the oracle's MAP of the same data (committed references,
   oracle to 1e-11).
 
@@ -81,13 +82,14 @@ def test_shear512_map_full_size(lib):
     print("[512^2 shear]", flush=True)
     wl = WL.shear_eb()
     base = _problem(lib, torch, wl)
-    d = lib.wf_simulate(base, 4, 3000, sim0=0, theta_true=wl.theta_true)
-    probs = [base.with_data(d[i]) for i in range(4)]
+    # the data: the oracle's simulations of Philox stream 3000 (simulations 0..3) at the truth
+    S_true = O.prior_S(wl.pshape, wl.band, wl.theta_true)
+    dh = [O.simulate(dr, S_true, wl.W) for dr in O.philox.draws_for_sims(3000, range(4), wl.n, wl.ncomp)]
+    probs = [base.with_data(torch.tensor(x, dtype=torch.float32, device="cuda:0")) for x in dh]
     s, _, st, rc = lib.map_wf_solve(probs, lib.LbfgsOpts(rel_grad_tol=1e-6))
     assert all(x.status == lib.WF_SOLVE_CONVERGED for x in st)
     S = O.prior_S(wl.pshape, wl.band, wl.theta_fid)
-    dh = d[2].cpu().numpy().astype(np.float64)
-    ref = O.lbfgs_solve(dh, wl.W, S, tol=1e-8)["s"]
+    ref = O.lbfgs_solve(dh[2], wl.W, S, tol=1e-8)["s"]
     got = s[2].cpu().numpy()
     err = rel_l2(got, ref)
     print(f"  map rel L2 vs oracle {err:.2e}", flush=True)
@@ -159,19 +161,18 @@ def test_uneven96_batch_full_size(lib):
     import torch
     print("[96 uneven maps]", flush=True)
     wls = WL.uneven_batch(96)
-    probs = []
+    # every map's data: the oracle's simulation at the truth of Philox stream (key 5100 + i,
+    # simulation 0), the stream the library's own simulation of the map would draw
+    probs, dhs = [], []
     for i, wl in enumerate(wls):
-        base = _problem(lib, torch, wl)
-        probs.append(base.with_data(lib.wf_simulate(base, 1, 5100 + i, theta_true=wl.theta_true)[0]))
-    # two CMB maps (768^2 and 1024^2) take the oracle's simulation of the same Philox streams,
-    # whose MAP the oracle has solved to 1e-11 (tests/golden/uneven_cmb*_map.npy)
+        draws = O.philox.draws_for_sims(5100 + i, [0], wl.n, wl.ncomp)[0]
+        dhs.append(O.simulate(draws, O.prior_S(wl.pshape, wl.band, wl.theta_true), wl.W))
+        probs.append(_problem(lib, torch, wl, d=torch.tensor(dhs[-1], dtype=torch.float32, device="cuda:0")))
+    # two CMB maps (768^2 and 1024^2) whose MAP the oracle has solved to 1e-11
+    # (tests/golden/uneven_cmb*_map.npy, the same data)
     here = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
     refs = {}
     for i in UNEVEN_CMB_REFS:
-        wl = wls[i]
-        draws = O.philox.draws_for_sims(5100 + i, [0], wl.n, wl.ncomp)[0]
-        d = O.simulate(draws, O.prior_S(wl.pshape, wl.band, wl.theta_true), wl.W)
-        probs[i] = probs[i].with_data(torch.tensor(d, dtype=torch.float32, device="cuda:0"))
         refs[i] = (np.load(os.path.join(here, f"uneven_cmb{i}_map.npy")).astype(np.complex128),
                    json.load(open(os.path.join(here, f"uneven_cmb{i}_map.json"))))
     opts = lib.LbfgsOpts(rel_grad_tol=1e-6, max_iter=4000, precond=1)
@@ -189,7 +190,7 @@ def test_uneven96_batch_full_size(lib):
         one, _, st1, _ = lib.map_wf_solve([probs[i]], opts)
         assert st1[0].status == lib.WF_SOLVE_CONVERGED
         S = O.prior_S(wl.pshape, wl.band, wl.theta_fid)
-        dh = probs[i].d.cpu().numpy().astype(np.float64)
+        dh = dhs[i]
         sb = s[i].cpu().numpy().astype(np.complex128)
         sa = one[0].cpu().numpy().astype(np.complex128)
         g0 = np.linalg.norm(O.whitened_grad(np.zeros_like(sb), dh, wl.W, S))
@@ -226,14 +227,17 @@ def test_uneven96_batch_full_size(lib):
               f"{str_[i].chi2:.10e} vs {meta['chi2']:.10e}", flush=True)
         assert ef <= 1e-5 and em <= 1e-5
         assert abs(str_[i].chi2 - meta["chi2"]) <= 1e-7 * meta["chi2"]
+    # the smallest shear map and the largest density and shear maps against the oracle's MAP
     shear = [i for i, wl in enumerate(wls) if wl.ncomp == 2]
-    i = min(shear, key=lambda j: wls[j].n)
-    wl = wls[i]
-    S = O.prior_S(wl.pshape, wl.band, wl.theta_fid)
-    ref = O.lbfgs_solve(probs[i].d.cpu().numpy().astype(np.float64), wl.W, S, tol=1e-8)["s"]
-    err = rel_l2(s[i].cpu().numpy(), ref)
-    print(f"  {wl.name} vs oracle MAP {err:.2e}", flush=True)
-    assert err < 1e-5
+    dens = [i for i, wl in enumerate(wls) if wl.name.startswith("uneven-density")]
+    for i in (min(shear, key=lambda j: wls[j].n), max(shear, key=lambda j: wls[j].n),
+              max(dens, key=lambda j: wls[j].n)):
+        wl = wls[i]
+        S = O.prior_S(wl.pshape, wl.band, wl.theta_fid)
+        ref = O.lbfgs_solve(dhs[i], wl.W, S, tol=1e-8)["s"]
+        err = rel_l2(s[i].cpu().numpy(), ref)
+        print(f"  {wl.name} (map {i}) vs oracle MAP {err:.2e}", flush=True)
+        assert err < 1e-5
 
 
 @pytest.mark.parametrize("case", ["density256", "shear512"])
