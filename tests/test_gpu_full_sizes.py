@@ -8,7 +8,8 @@ by one and on properties that hold at any size:
   bench's conjugate-gradient and preconditioned comparisons).
 * 1024^2 CMB patch (preconditioned solve refined in float64): the field against the oracle's
   MAP of the same data (a committed reference, oracle to 1e-11), E_l, a Philox simulation
-  against the oracle's, and d chi^2 / d theta of its 40 bands (autograd, central differences).
+  against the oracle's, and d chi^2 / d theta of its 40 bands at the oracle's MAP (autograd
+  against the oracle and central differences).
 * 96-map uneven batch (sides 128..1024, three kinds): every map converges in one batched
   solve; sampled maps pass the oracle's gradient check and agree with their one-map-at-a-time
   solves (in the gradient, i.e. the energy norm, for the badly conditioned CMB maps, whose
@@ -140,12 +141,13 @@ def test_cmb1024_full_size(lib):
     dsim = lib.wf_simulate(prob, 1, 4200, sim0=3)[0].cpu().numpy().astype(np.float64)
     osim = O.simulate(O.philox.draws_for_sims(4200, [3], wl.n, wl.ncomp)[0], S, wl.W)
     assert np.max(np.abs(dsim - osim)) <= 2e-5 * np.max(np.abs(osim))
-    # d chi^2 / d theta_b of the 40 bands (autograd through the library) at the refined field
+    # d chi^2 / d theta_b of the 40 bands (autograd through the library) at the oracle's MAP
     theta = torch.tensor(wl.theta_fid, dtype=torch.float64, requires_grad=True)
-    sf = s1[0].detach()
+    sf = torch.tensor(ref, dtype=torch.complex64, device="cuda:0")
     lib.autograd.chi2(sf, theta, prob).backward()
     gth = theta.grad.numpy()
-    np.testing.assert_allclose(gth, O.dchi2_dtheta(got, wl.pshape, wl.band, wl.theta_fid, wl.nbands), rtol=1e-5)
+    refc = ref.astype(np.complex64).astype(np.complex128)   # the field the GPU was given
+    np.testing.assert_allclose(gth, O.dchi2_dtheta(refc, wl.pshape, wl.band, wl.theta_fid, wl.nbands), rtol=1e-5)
     for bnd in (0, 7, 19, 39):
         hh = 3e-3 * wl.theta_fid[bnd]
         tp, tm = theta.detach().clone(), theta.detach().clone()
