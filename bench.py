@@ -169,7 +169,7 @@ def pmc_summary(fetch_csv: str, write_csv: str, copy_bytes: int = 2 * 1024 ** 3)
 
 def host_cores() -> int:
     """Cores this process may use: its CPU affinity, capped by OMP_NUM_THREADS where the host
-    sets it (the GPU machine gives each GPU a share of its cores that way)."""
+    sets it (a host that shares its cores among its GPUs limits each process that way)."""
     n = len(os.sched_getaffinity(0))
     try:
         n = min(n, int(os.environ.get("OMP_NUM_THREADS", n)))
