@@ -4,7 +4,7 @@ against the FP64 oracle.
 Bars (from the method's accuracy targets): maps within 1e-5 relative L2 of the oracle's
 MAP for float32 solves, 1e-9 for float64; band statistics within 1e-4 relative for
 identical draws.  The MAP is unique (strictly convex objective), so converged results
-are compared; iteration counts are not (they depend on round-off)."""
+are compared here; iteration counts against the oracle's are in test_gpu_iterations."""
 import numpy as np
 import pytest
 

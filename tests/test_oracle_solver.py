@@ -216,3 +216,50 @@ def test_bandpower_estimate_unbiased():
     est = np.array(est)
     sd = est.std(0) / math.sqrt(len(est))
     assert np.all(np.abs(est.mean(0) - theta_true) < 4 * sd), (est.mean(0), sd)
+
+
+def _pcg_iterates(d, W, S, P, k):
+    """The first k iterates of textbook (preconditioned) conjugate gradients (Hestenes and
+    Stiefel; Nocedal & Wright, Numerical Optimization, algorithm 5.3) on the whitened normal
+    equations D w = S^1/2 R^T W d, from w = 0; P is the diagonal preconditioner or None."""
+    fr = O.free_mask(S.shape[1])[None] & (S > 0)
+    w = np.zeros(S.shape, np.complex128)
+    r = -O.whitened_grad(w, d, W, S)          # b - D w at w = 0
+    z = r if P is None else np.where(fr, P, 0) * r
+    p = z.copy()
+    rz = np.vdot(r, z).real
+    out = []
+    for _ in range(k):
+        Dp = O.whitened_hvp(p, W, S)
+        a = rz / np.vdot(p, Dp).real
+        w = w + a * p
+        r = r - a * Dp
+        z = r if P is None else np.where(fr, P, 0) * r
+        rz_new = np.vdot(r, z).real
+        p = z + (rz_new / rz) * p
+        rz = rz_new
+        out.append(w.copy())
+    return out
+
+
+@pytest.mark.parametrize("ncomp,m,precond", [(1, 1, False), (1, 10, False), (2, 3, False), (1, 10, True),
+                                             (2, 1, True)])
+def test_lbfgs_iterates_equal_conjugate_gradients(ncomp, m, precond):
+    """On a quadratic with exact line searches, L-BFGS with any history length m >= 1 and
+    initial matrix gamma I (or gamma P) takes the same steps as conjugate gradients (with
+    preconditioner P): each direction is a multiple of the (preconditioned) CG direction and
+    the exact step removes the multiple (Nocedal & Wright, secs. 5.1 and 7.2).  Pins the
+    oracle's two-loop recursion, its curvature pairs, its scaling and its preconditioner use,
+    none of which change the converged MAP.  Iterate k of the oracle (max_iter = k) is
+    compared with iterate k of CG, for k up to 12."""
+    n = 12
+    pshape, band, nb, W, theta = _small(n, ncomp, 70 + 3 * m + ncomp)
+    S = O.prior_S(pshape, band, theta)
+    rng = np.random.default_rng(71)
+    d = np.where(W[None] > 0, rng.standard_normal((ncomp, n, n)), 0.0)
+    P = O.precond_diag(W, S) if precond else None
+    cg = _pcg_iterates(d, W, S, P, 12)
+    for k in range(1, 13):
+        w = O.lbfgs_solve(d, W, S, m=m, tol=0.0, max_iter=k, precond=precond)["w"]
+        err = np.linalg.norm(w - cg[k - 1]) / np.linalg.norm(cg[k - 1])
+        assert err < 1e-9, (k, err)
