@@ -138,6 +138,15 @@ def test_catalog_map_matches_oracle(lib, n):
     if n == 16:
         wf = O.catalog_wiener_dense(e, cat.wgt, cat.pos, S)
         assert rel_l2(s[0], wf["s"]) < 1e-5
+    # iteration counts against the oracle's L-BFGS with the exact sums, stopped at 1e-6: L-BFGS
+    # and CG take its steps up to float32 round-off and the interpolation's ~1e-6 error (at most
+    # 2 fewer and max(2, 25 %) more iterations; observed 0 to 3 more)
+    it_ref = O.catalog_lbfgs_solve(e, cat.wgt, cat.pos, S, tol=1e-6)["iters"]
+    for method in (lib.WF_METHOD_LBFGS, lib.WF_METHOD_CG):
+        _, st1, _ = _solve(lib, torch, [cat], [e], [_cat_problem(lib, cat)], rel_grad_tol=1e-6, method=method)
+        print(f"   method {method}: {st1[0].iters} iterations to 1e-6 (oracle {it_ref})", flush=True)
+        assert st1[0].status == lib.WF_SOLVE_CONVERGED
+        assert it_ref - 2 <= st1[0].iters <= it_ref + max(2, 0.25 * it_ref), (method, st1[0].iters, it_ref)
     # float64 whitened gradient of the returned field
     sq = np.sqrt(S)
     w = np.where(S > 0, s[0] / np.where(S > 0, sq, 1), 0)

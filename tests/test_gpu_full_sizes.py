@@ -95,15 +95,26 @@ def test_shear512_map_full_size(lib):
     err = rel_l2(got, ref)
     print(f"  map rel L2 vs oracle {err:.2e}", flush=True)
     assert err < 1e-5
+    # iteration counts of map 2 against the oracle's L-BFGS stopped at the same tolerance: the
+    # solvers take the same steps on a quadratic, so they agree up to float32 round-off (at
+    # most 2 fewer and max(2, 25 %) more iterations, the bar of the small-map comparisons)
+    it_ref = {pc: O.lbfgs_solve(dh[2], wl.W, S, tol=1e-6, precond=pc)["iters"] for pc in (False, True)}
+
+    def check_iters(name, it, pc):
+        print(f"  {name}: map 2 took {it} iterations (oracle {it_ref[pc]})", flush=True)
+        assert it_ref[pc] - 2 <= it <= it_ref[pc] + max(2, 0.25 * it_ref[pc]), (name, it, it_ref[pc])
+
+    check_iters("lbfgs", st[2].iters, False)
     # the bench's comparison solvers on the same maps: conjugate gradients and the preconditioned
     # L-BFGS, same stop test
-    for name, opts in (("cg", lib.LbfgsOpts(rel_grad_tol=1e-6, method=lib.WF_METHOD_CG)),
-                       ("precond", lib.LbfgsOpts(rel_grad_tol=1e-6, precond=1))):
+    for name, opts, pc in (("cg", lib.LbfgsOpts(rel_grad_tol=1e-6, method=lib.WF_METHOD_CG), False),
+                           ("precond", lib.LbfgsOpts(rel_grad_tol=1e-6, precond=1), True)):
         s2, _, st2, rc2 = lib.map_wf_solve(probs, opts)
         assert rc2 == 0 and all(x.status == lib.WF_SOLVE_CONVERGED and x.rel_grad <= 1e-6 for x in st2)
         err2 = rel_l2(s2[2].cpu().numpy(), ref)
         print(f"  {name}: iterations {[x.iters for x in st2]}, map rel L2 vs oracle {err2:.2e}", flush=True)
         assert err2 < 1e-5
+        check_iters(name, st2[2].iters, pc)
 
 
 def test_cmb1024_full_size(lib):
