@@ -193,10 +193,11 @@ def cpu_baseline(args, gpu_solve=None):
     and fiducial simulations of the workload at the benchmark's tolerance, on every core this
     process may use (one independent solve per process, all started together) and on one core.
     The child also writes three maps with the oracle's MAP at 1e-10 (untimed);
-    gpu_solve(maps) -> (fields, maps, stats) solves the same data on the GPU at the benchmark's
-    tolerance, and the accuracy beside the throughput is the GPU against that reference (field
-    relative L2; per-pixel map error on observed and on masked pixels, relative to the largest
-    reference pixel)."""
+    gpu_solve(maps, ref_fields) -> (fields, maps, stats, E, dtheta) solves the same data on the
+    GPU at the benchmark's tolerance, and the accuracy beside the throughput is the GPU against
+    that reference (field relative L2; per-pixel map error on observed and on masked pixels,
+    relative to the largest reference pixel; E_l of the solved fields per band; the library's
+    d chi^2 / d theta_b at the reference fields per band)."""
     import tempfile
 
     import numpy as np
@@ -212,19 +213,28 @@ def cpu_baseline(args, gpu_solve=None):
         if gpu_solve is not None and os.path.exists(out):
             ref = np.load(out)
             k = int(ref["count"])
-            s, x, st = gpu_solve([ref[f"d{i}"] for i in range(k)])
+            s, x, st, E, th = gpu_solve([ref[f"d{i}"] for i in range(k)], [ref[f"s{i}"] for i in range(k)])
             obs = ref["observed"]
-            el2, eo, em = [], [], []
+            el2, eo, em, eE, et = [], [], [], [], []
             for i in range(k):
                 sr, xr = ref[f"s{i}"], ref[f"x{i}"]
                 el2.append(float(np.linalg.norm(s[i] - sr) / np.linalg.norm(sr)))
                 dx = np.abs(x[i] - xr) / np.abs(xr).max()
                 eo.append(float(dx[:, obs].max()))
                 em.append(float(dx[:, ~obs].max()))
+                Er, tr = ref[f"E{i}"], ref[f"t{i}"]
+                nE, nt = np.abs(Er) > 0, np.abs(tr) > 0
+                eE.append(float(np.max(np.abs(E[i] - Er)[nE] / np.abs(Er)[nE])))
+                et.append(float(np.max(np.abs(th[i] - tr)[nt] / np.abs(tr)[nt])))
             res["accuracy"] = {"maps": k, "reference": "oracle float64 MAP to 1e-10 of the same data",
                                "field_rel_l2_max": max(el2), "map_max_abs_observed_rel": max(eo),
                                "map_max_abs_masked_rel": max(em),
-                               "gpu_rel_grad_max": max(float(x_.rel_grad) for x_ in st)}
+                               "gpu_rel_grad_max": max(float(x_.rel_grad) for x_ in st),
+                               # E_l of the GPU's MAP against E_l of the reference MAP, per band
+                               "band_E_rel_max": max(eE),
+                               # the library's d chi^2 / d theta_b against the oracle's, both at
+                               # the reference MAP, per band
+                               "dchi2_dtheta_rel_max": max(et)}
     return res
 
 
@@ -283,6 +293,9 @@ def cpu_child(args):
         for i, (wl, S, d) in enumerate(maps):
             sr = O.lbfgs_solve(d, wl.W, S, m=args.m, tol=1e-10, max_iter=50000)["s"]
             ref[f"d{i}"], ref[f"s{i}"], ref[f"x{i}"] = d, sr, O.forward(sr)
+            # band powers of the reference MAP (eq. el) and d chi^2 / d theta_b at it
+            ref[f"E{i}"] = O.band_E(sr, S, wl.band, wl.theta_fid, wl.nbands)
+            ref[f"t{i}"] = O.dchi2_dtheta(sr, wl.pshape, wl.band, wl.theta_fid, wl.nbands)
         np.savez(args.cpu_out, **ref)
     print(json.dumps({"value": round(par, 4), "unit": "solves/s", "cores": P, "kind": "oracle",
                       "cpu_model": cpu_model(), "nproc": os.cpu_count(),
@@ -850,10 +863,13 @@ def main():
         roof["frac_of_copy_ceiling"] = round(achieved / roof["copy_ceiling_GBps"], 4)
         roof_chain["frac_of_copy_ceiling"] = round(ca / roof["copy_ceiling_GBps"], 4)
 
-    def gpu_solve(ds):
+    def gpu_solve(ds, srefs):
         probs = [base.with_data(torch.tensor(np.asarray(d), dtype=torch.float32, device=dev)) for d in ds]
         s_, x_, st_, _ = wf.map_wf_solve(probs, opts, want_maps=True)
-        return [t.cpu().numpy() for t in s_], [t.cpu().numpy() for t in x_], st_
+        E_ = [wf.wf_band_E(p, t) for p, t in zip(probs, s_)]
+        th_ = [wf.wf_chi2_dtheta(p, torch.tensor(np.asarray(sr), dtype=torch.complex64, device=dev))
+               for p, sr in zip(probs, srefs)]
+        return [t.cpu().numpy() for t in s_], [t.cpu().numpy() for t in x_], st_, E_, th_
 
     cpu = None if args.no_cpu else cpu_baseline(args, gpu_solve)
     accuracy = cpu.pop("accuracy", None) if isinstance(cpu, dict) else None
