@@ -135,6 +135,49 @@ def test_edge_cases(lib):
     assert out[0] == []
 
 
+@pytest.mark.parametrize("n", [6, 12, 40, 1032, 1536, 2048])
+def test_unsupported_sizes_rejected(lib, n):
+    """Sides outside the supported set (n % 8 == 0, 8 <= n <= 1024, n = 2^a or 3 * 2^a) are
+    rejected by the library before any launch, for the solver and the operator calls.  The
+    buffers have the claimed size, so nothing could be read out of bounds either way."""
+    import torch
+    print(f"[unsupported n={n}]", flush=True)
+    dev = "cuda:0"
+    h = n // 2 + 1
+    prob = lib.Problem(torch.ones((n, n), dtype=torch.float32, device=dev),
+                       torch.ones((1, n, h), dtype=torch.float64, device=dev),
+                       torch.zeros((1, n, h), dtype=torch.int32, device=dev), [1.0],
+                       d=torch.zeros((1, n, n), dtype=torch.float32, device=dev))
+    for call in (lambda: lib.map_wf_solve([prob]),
+                 lambda: lib.wf_forward(prob, torch.zeros((1, n, h), dtype=torch.complex64, device=dev)),
+                 lambda: lib.wf_hvp(prob, torch.zeros((1, n, h), dtype=torch.complex64, device=dev))):
+        with pytest.raises(lib.WFError) as e:
+            call()
+        assert e.value.code == -1, e.value
+
+
+def test_bad_components_and_theta_rejected(lib):
+    """Three components, and a non-finite band amplitude, are rejected before any launch."""
+    import torch
+    print("[bad ncomp / theta]", flush=True)
+    dev = "cuda:0"
+    n, h = 16, 9
+    three = lib.Problem(torch.ones((n, n), dtype=torch.float32, device=dev),
+                        torch.ones((3, n, h), dtype=torch.float64, device=dev),
+                        torch.zeros((3, n, h), dtype=torch.int32, device=dev), [1.0],
+                        d=torch.zeros((3, n, n), dtype=torch.float32, device=dev))
+    with pytest.raises(lib.WFError) as e:
+        lib.map_wf_solve([three])
+    assert e.value.code == -1
+    nan = lib.Problem(torch.ones((n, n), dtype=torch.float32, device=dev),
+                      torch.ones((1, n, h), dtype=torch.float64, device=dev),
+                      torch.zeros((1, n, h), dtype=torch.int32, device=dev), [float("nan")],
+                      d=torch.zeros((1, n, n), dtype=torch.float32, device=dev))
+    with pytest.raises(lib.WFError) as e:
+        lib.map_wf_solve([nan])
+    assert e.value.code == -5
+
+
 @pytest.mark.parametrize("ncomp", [1, 2])
 def test_sim_fisher_and_bandpower_match_oracle(lib, ncomp):
     """Identical draws on both sides: b, F and Theta_hat agree to 1e-4."""
