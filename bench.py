@@ -16,7 +16,7 @@ workload ("secondary": 256^2 density band powers, 512^2 density maps, 1024^2 CMB
 the 96-map uneven batch against its plain path, the 512^2 shear catalog at the catalog level).
 
     python bench.py [--steps K] [--warmup W] [--nsim 6] [--n 512] [--no-cpu] [--no-plain]
-                    [--no-secondary] [--catalog-only]
+                    [--no-secondary] [--catalog-only] [--density-bands-only] [--cmb-full]
     python bench.py --pmc-summary FETCH_CSV WRITE_CSV   # profiles/pmc_traffic.json from rocprofv3 --pmc
 """
 from __future__ import annotations
@@ -53,6 +53,8 @@ def parse():
                     help="skip the conjugate-gradient comparison (for counter runs: only L-BFGS launches of the chain)")
     ap.add_argument("--catalog-only", action="store_true",
                     help="print only the 512^2 shear catalog line (for profiling the catalog solve)")
+    ap.add_argument("--density-bands-only", action="store_true",
+                    help="print only the 256^2 density band-power line (for profiling that estimate)")
     ap.add_argument("--cmb-full", action="store_true",
                     help="only the 1024^2 CMB band-power estimate at 256 simulations (10497 solves), one JSON line")
     ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"), default=None,
@@ -645,6 +647,36 @@ def catalog_line(args):
             "device_time_split": {k: round(v, 3) if isinstance(v, float) else v for k, v in split.items()}}
 
 
+def density_bands_line(args):
+    """The 256^2 density band-power estimate alone (12 bands, 128 simulations, 1665 MAP solves
+    per estimate, L-BFGS to the benchmark's tolerance): one untimed estimate, then --steps
+    timed ones, the same inputs as the secondary line."""
+    import numpy as np
+    import torch
+
+    import paper_1810_00503_amd as wf
+    from paper_1810_00503_amd import workloads as WL
+    wf.load()
+    dev = "cuda:0"
+    wl = WL.density_bands()
+    base = wf.Problem(torch.tensor(wl.W, dtype=torch.float32, device=dev), wl.pshape, wl.band, wl.theta_fid)
+    prob = base.with_data(wf.wf_simulate(base, 1, 2000, theta_true=wl.theta_true)[0])
+    nsim = 128
+    opts = wf.LbfgsOpts(m=args.m, rel_grad_tol=args.tol)
+    wf.bandpower_qe(prob, nsim, 2001, opts=opts)
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(max(1, args.steps)):
+        t0 = time.perf_counter()
+        wf.bandpower_qe(prob, nsim, 2001, opts=opts)
+        torch.cuda.synchronize()
+        ts.append(time.perf_counter() - t0)
+    dt = float(np.median(ts))
+    ns = 1 + nsim * (1 + wl.nbands)
+    return {"workload": f"256^2 density, {wl.nbands} bands, {nsim} simulations ({ns} MAP solves per estimate)",
+            "estimates": len(ts), "bandpower_estimates_per_s": round(1.0 / dt, 3), "solves_per_s": round(ns / dt, 1)}
+
+
 def main():
     args = parse()
     if args.pmc_summary:
@@ -658,6 +690,9 @@ def main():
         return
     if args.cmb_full:
         print(json.dumps({"cmb1024_bandpowers_nsim256": cmb_full_line(args)}), flush=True)
+        return
+    if args.density_bands_only:
+        print(json.dumps({"density256_bandpowers": density_bands_line(args)}), flush=True)
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the simulation batches would shard "
