@@ -13,6 +13,9 @@ import oracle.philox as OP
 import oracle.wf_oracle as OW
 from tests import test_oracle_catalog as TC
 from tests import test_oracle_estimator_pins as TE
+from tests import test_oracle_fisher_rows as TF
+from tests import test_oracle_leakage as TL
+from tests import test_oracle_posterior as TP
 from tests import test_oracle_solver as TS
 from tests import test_oracle_transforms as TT
 
@@ -140,6 +143,60 @@ def _m_dot_real_parts(orig):
     return lambda a, b: float(np.sum(a.real * b.real))
 
 
+def _m_catalog_adjoint_b_sign(orig):
+    # the catalog adjoint rotates B the wrong way
+    def f(r, pos, n):
+        a = orig(r, pos, n)
+        return np.stack([a[0], -a[1]]) if a.shape[0] == 2 else a
+    return f
+
+
+def _m_dtheta_one_power(orig):
+    # d chi^2 / d Theta_b with 1 / Theta_b where the prior term gives 1 / Theta_b^2
+    return lambda s, pshape, band, theta, nbands: orig(s, pshape, band, theta, nbands) * np.asarray(theta)
+
+
+def _m_posterior_half(orig):
+    # the simulation variance of one coordinate only (real part) per stored entry
+    def f(*a, **k):
+        vm, vp = orig(*a, **k)
+        return 0.5 * vm, vp
+    return f
+
+
+def _m_dense_posterior_half(orig):
+    def f(W, S):
+        vm, vp = orig(W, S)
+        return 0.5 * vm, vp
+    return f
+
+
+def _m_fisher_scale_ignored(orig):
+    # the sample-variance scale of the response dropped
+    return lambda Fcols, rows, nbands, groups=None, scale=None: orig(Fcols, rows, nbands, groups, None)
+
+
+def _m_fiducial_no_floor(orig):
+    return lambda estimate, theta0, max_iter, rel_tol, floor: orig(estimate, theta0, max_iter, rel_tol, 0.0)
+
+
+def _m_leakage_fisher_half(orig):
+    def f(*a, **k):
+        th, EB, bB, FBB = orig(*a, **k)
+        return th, EB, bB, 0.5 * FBB
+    return f
+
+
+def _m_cosmic_variance_one_mode(orig):
+    # sqrt(1 / N_l): each free entry counted once instead of with its mirror
+    return lambda S, band, nbands: orig(S, band, nbands) / np.sqrt(2.0)
+
+
+def _m_sim_signal_full_variance(orig):
+    # each of the real and imaginary parts drawn with variance S instead of S / 2
+    return lambda draw, S_true: np.sqrt(2.0) * orig(draw, S_true)
+
+
 def _m_philox_bit(orig):
     def f(*a, **k):
         r = np.array(orig(*a, **k), dtype=np.uint64, copy=True)
@@ -178,9 +235,28 @@ CASES = [
      lambda: TS.test_sim_bias_and_fisher_converge_to_closed_forms()),
     ("catalog plane waves with the opposite phase", "catalog_forward", _m_catalog_phase,
      lambda: TC.test_integer_positions_reduce_to_the_map_response(1)),
+    ("catalog adjoint's B rotation with the wrong sign", "catalog_adjoint", _m_catalog_adjoint_b_sign,
+     lambda: TC.test_catalog_adjoint_dot_product(2)),
+    ("d chi^2 / d theta with one power of theta", "dchi2_dtheta", _m_dtheta_one_power,
+     lambda: TE.test_dchi2_dtheta_central_differences(1)),
+    ("posterior variance of one coordinate", "posterior_error", _m_posterior_half,
+     lambda: TP.test_posterior_error_simulations_match_dense_diagonal()),
+    ("dense posterior variance of one coordinate", "dense_posterior_variance", _m_dense_posterior_half,
+     lambda: TP.test_dense_posterior_variance_homogeneous_closed_form()),
+    ("Fisher rows' sample-variance scale dropped", "fisher_from_columns", _m_fisher_scale_ignored,
+     lambda: TF.test_scaled_toeplitz_is_reproduced_exactly_with_its_scale()),
+    ("fiducial iteration without its floor", "fiducial_iteration", _m_fiducial_no_floor,
+     lambda: TF.test_fiducial_iteration_floor()),
+    ("B-mode leakage Fisher halved", "bmode_leakage_qe", _m_leakage_fisher_half,
+     lambda: TL.test_unmasked_leakage_bias_is_the_noise_only_mean()),
+    ("cosmic variance counting each mode once", "cosmic_variance", _m_cosmic_variance_one_mode,
+     lambda: TP.test_cosmic_variance_counts_modes()),
+    ("simulated signal with twice the variance", "sim_signal", _m_sim_signal_full_variance,
+     lambda: TP.test_sim_signal_has_the_prior_variance()),
 ]
 
 
+@pytest.mark.filterwarnings("ignore::RuntimeWarning")   # a planted mistake may drive a value to 0 or inf
 @pytest.mark.parametrize("what,name,mutate,pin", CASES, ids=[c[0] for c in CASES])
 def test_planted_mistake_is_caught(monkeypatch, what, name, mutate, pin):
     _plant(monkeypatch, name, mutate(getattr(OW, name)))
