@@ -249,8 +249,13 @@ def test_uneven96_batch_full_size(lib):
         S = O.prior_S(wl.pshape, wl.band, wl.theta_fid)
         ref = O.lbfgs_solve(dhs[i], wl.W, S, tol=1e-8)["s"]
         err = rel_l2(s[i].cpu().numpy(), ref)
-        print(f"  {wl.name} (map {i}) vs oracle MAP {err:.2e}", flush=True)
+        # and its iteration count in the batch against the oracle's preconditioned L-BFGS at the
+        # batch's tolerance (the float32 bar of the iteration-count tests)
+        it_ref = O.lbfgs_solve(dhs[i], wl.W, S, tol=1e-6, precond=True)["iters"]
+        print(f"  {wl.name} (map {i}) vs oracle MAP {err:.2e}; {st[i].iters} iterations (oracle {it_ref})",
+              flush=True)
         assert err < 1e-5
+        assert it_ref - 2 <= st[i].iters <= it_ref + max(2, 0.25 * it_ref), (st[i].iters, it_ref)
 
 
 @pytest.mark.parametrize("case", ["density256", "shear512"])
