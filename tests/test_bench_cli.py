@@ -1,0 +1,25 @@
+"""The benchmark's command line on the CPU: the library runs on one GPU, so asking for more
+exits with status 2 and a message (before any GPU work), and --help documents the modes."""
+import os
+import subprocess
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _run(*args):
+    return subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), *args], capture_output=True, text=True,
+                          timeout=120, cwd=ROOT)
+
+
+def test_more_than_one_gpu_is_refused():
+    r = _run("--gpus", "2")
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr and r.stdout == ""
+
+
+def test_help_lists_the_modes():
+    r = _run("--help")
+    assert r.returncode == 0
+    for flag in ("--steps", "--warmup", "--gpus", "--catalog-only", "--density-bands-only", "--cmb-full"):
+        assert flag in r.stdout, flag
