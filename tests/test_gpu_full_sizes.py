@@ -117,6 +117,32 @@ def test_shear512_map_full_size(lib):
         check_iters(name, st2[2].iters, pc)
 
 
+def test_shear512_float64_solve_matches_oracle(lib):
+    """The headline 512^2 E/B shear map solved in float64 to 1e-8: the oracle's L-BFGS takes
+    the same steps (same recursion, exact step, stop test), so the iteration counts agree
+    within the float64 bar of the iteration-count tests, and the field equals the oracle's field
+    stopped at the same tolerance to float64 rounding (the same iterates: observed 3e-16; bar
+    1e-12) and its MAP at 1e-12 within the 1e-8 stop (bar 1e-7)."""
+    import torch
+    print("[512^2 shear float64]", flush=True)
+    wl = WL.shear_eb()
+    S_true = O.prior_S(wl.pshape, wl.band, wl.theta_true)
+    dh = O.simulate(O.philox.draws_for_sims(3000, [1], wl.n, wl.ncomp)[0], S_true, wl.W)
+    prob = lib.Problem(torch.tensor(wl.W, dtype=torch.float64, device="cuda:0"), wl.pshape, wl.band, wl.theta_fid,
+                       d=torch.tensor(dh, dtype=torch.float64, device="cuda:0"))
+    s, _, st, rc = lib.map_wf_solve([prob], lib.LbfgsOpts(rel_grad_tol=1e-8))
+    assert st[0].status == lib.WF_SOLVE_CONVERGED
+    S = O.prior_S(wl.pshape, wl.band, wl.theta_fid)
+    ref8 = O.lbfgs_solve(dh, wl.W, S, tol=1e-8)
+    ref12 = O.lbfgs_solve(dh, wl.W, S, tol=1e-12, x0=ref8["w"])
+    got = s[0].cpu().numpy()
+    e8, e12 = rel_l2(got, ref8["s"]), rel_l2(got, ref12["s"])
+    print(f"  {st[0].iters} iterations (oracle {ref8['iters']}); field vs oracle at 1e-8 {e8:.2e}, "
+          f"vs its MAP at 1e-12 {e12:.2e}", flush=True)
+    assert abs(st[0].iters - ref8["iters"]) <= max(2, 0.06 * ref8["iters"])
+    assert e8 < 1e-12 and e12 < 1e-7
+
+
 def test_cmb1024_full_size(lib):
     """The 1024^2 CMB map refined in float64 against the oracle's MAP of the same data
     (tests/golden/cmb1024_map.npy, oracle L-BFGS to 1e-11); the unrefined 1e-6 stop leaves
