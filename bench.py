@@ -16,7 +16,7 @@ workload ("secondary": 256^2 density band powers, 512^2 density maps, 1024^2 CMB
 the 96-map uneven batch against its plain path, the 512^2 shear catalog at the catalog level).
 
     python bench.py [--steps K] [--warmup W] [--nsim 6] [--n 512] [--no-cpu] [--no-plain]
-                    [--no-secondary] [--catalog-only] [--density-bands-only] [--cmb-full]
+                    [--no-secondary] [--catalog-only] [--density-bands-only] [--cmb-full] [--cmb-iterate]
     python bench.py --pmc-summary FETCH_CSV WRITE_CSV   # profiles/pmc_traffic.json from rocprofv3 --pmc
 """
 from __future__ import annotations
@@ -55,6 +55,8 @@ def parse():
                     help="print only the 512^2 shear catalog line (for profiling the catalog solve)")
     ap.add_argument("--density-bands-only", action="store_true",
                     help="print only the 256^2 density band-power line (for profiling that estimate)")
+    ap.add_argument("--cmb-iterate", action="store_true",
+                    help="only the 1024^2 CMB estimate (64 simulations) before and after one fiducial step")
     ap.add_argument("--cmb-full", action="store_true",
                     help="only the 1024^2 CMB band-power estimate at 256 simulations (10497 solves), one JSON line")
     ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"), default=None,
@@ -536,6 +538,28 @@ def secondary_workloads(args):
     return out
 
 
+def _deviation_from_truth(th, F, theta_true):
+    """|theta_hat - theta_true| in units of each band's conditional error 1 / sqrt(F_bb), and of
+    the marginal error sqrt((F^-1)_bb) over the bands carrying signal (F_bb above 1e-6 of the
+    largest) when that block of F is positive definite (the conditional error ignores the
+    mask's couplings between neighbouring bands)."""
+    import numpy as np
+    fd = np.diag(F)
+    okb = fd > 0
+    z = np.abs(th - theta_true)[okb] * np.sqrt(fd[okb])
+    cond = {"median": round(float(np.median(z)), 3) if z.size else None,
+            "max": round(float(np.max(z)), 3) if z.size else None,
+            "worst_band": int(np.flatnonzero(okb)[np.argmax(z)]) if z.size else None, "bands": int(okb.sum())}
+    sig = fd > 1e-6 * fd.max()
+    Fs = 0.5 * (F[np.ix_(sig, sig)] + F[np.ix_(sig, sig)].T)
+    marg = None
+    if sig.any() and np.linalg.eigvalsh(Fs).min() > 0:
+        zm = np.abs(th - theta_true)[sig] / np.sqrt(np.diag(np.linalg.inv(Fs)))
+        marg = {"median": round(float(np.median(zm)), 3), "max": round(float(np.max(zm)), 3),
+                "bands": int(sig.sum())}
+    return cond, marg
+
+
 def cmb_full_line(args):
     """The 1024^2 CMB band-power estimate at its full size: 40 linear bands, 256 simulations
     (1 + 256 x 41 = 10497 MAP solves, run in batches of 256), preconditioned L-BFGS to the
@@ -561,32 +585,49 @@ def cmb_full_line(args):
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     ns = 1 + nsim * (1 + wl.nbands)
-    # deviation from the truth in units of each band's conditional error 1 / sqrt(F_bb) (the
-    # damping tail's bands carry almost no signal, so the full inverse is dominated by noise)
-    fd = np.diag(F)
-    okb = fd > 0
-    z = np.abs(th - wl.theta_true)[okb] * np.sqrt(fd[okb])
-    # and in units of the marginal error sqrt((F^-1)_bb) over the bands carrying signal (F_bb
-    # above 1e-6 of the largest), when that block of F is positive definite: the conditional
-    # error ignores the mask's couplings between neighbouring bands
-    sig = fd > 1e-6 * fd.max()
-    Fs = 0.5 * (F[np.ix_(sig, sig)] + F[np.ix_(sig, sig)].T)
-    marg = None
-    if sig.any() and np.linalg.eigvalsh(Fs).min() > 0:
-        zm = np.abs(th - wl.theta_true)[sig] / np.sqrt(np.diag(np.linalg.inv(Fs)))
-        marg = {"median": round(float(np.median(zm)), 3), "max": round(float(np.max(zm)), 3),
-                "bands": int(sig.sum())}
+    # deviation from the truth (the damping tail's bands carry almost no signal, so the full
+    # inverse of F is dominated by noise there)
+    cond, marg = _deviation_from_truth(th, F, wl.theta_true)
     return {"workload": f"1024^2 CMB (cmb_patch generator), {wl.nbands} linear bands, {nsim} simulations, "
                         f"preconditioned L-BFGS m={args.m} to {args.tol:g} rel. grad",
             "nsim": nsim, "solves": ns, "seconds": round(dt, 2), "estimates_per_s": round(1.0 / dt, 5),
             "solves_per_s": round(ns / dt, 1), "all_converged": rc == wf.WF_OK,
             "theta_hat_first_bands": [round(float(x), 4) for x in th[:5]],
-            "theta_hat_minus_truth_over_cond_sigma": {"median": round(float(np.median(z)), 3) if z.size else None,
-                                                      "max": round(float(np.max(z)), 3) if z.size else None,
-                                                      "worst_band": int(np.flatnonzero(okb)[np.argmax(z)])
-                                                      if z.size else None,
-                                                      "bands": int(okb.sum())},
+            "theta_hat_minus_truth_over_cond_sigma": cond,
             "theta_hat_minus_truth_over_marginal_sigma": marg}
+
+
+def cmb_iterate_line(args):
+    """The 1024^2 CMB band-power estimate with 64 simulations (2625 MAP solves per estimate),
+    once at the workload's fiducial (the truth scaled band by band by U(0.01, 1)) and after one
+    step of the fiducial iteration (sec. 2.3: the fiducial reset to the first estimate), each
+    with its deviation from the truth in the errors of its own F."""
+    import torch
+
+    import paper_1810_00503_amd as wf
+    from paper_1810_00503_amd import workloads as WL
+    wf.load()
+    dev = "cuda:0"
+    wl = WL.cmb_patch()
+    base = wf.Problem(torch.tensor(wl.W, dtype=torch.float32, device=dev), wl.pshape, wl.band, wl.theta_fid)
+    prob = base.with_data(wf.wf_simulate(base, 1, 4200, theta_true=wl.theta_true)[0])
+    popts = wf.LbfgsOpts(m=args.m, rel_grad_tol=args.tol, max_iter=4000, precond=1)
+    nsim = 64
+    t0 = time.perf_counter()
+    th1, _, _, F1, rc1 = wf.bandpower_qe(prob, nsim, 4201, opts=popts)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    th2, hist, _, _, F2, rc2 = wf.bandpower_iterate(prob, nsim, 4201, max_iter=2, rel_tol=0.0, opts=popts)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    c1, m1 = _deviation_from_truth(th1, F1, wl.theta_true)
+    c2, m2 = _deviation_from_truth(th2, F2, wl.theta_true)
+    return {"workload": f"1024^2 CMB (cmb_patch generator), {wl.nbands} linear bands, {nsim} simulations per "
+                        f"estimate, preconditioned L-BFGS m={args.m} to {args.tol:g} rel. grad",
+            "one_estimate_seconds": round(t1 - t0, 2), "two_step_iteration_seconds": round(t2 - t1, 2),
+            "all_converged": rc1 == wf.WF_OK and rc2 == wf.WF_OK, "iteration_steps": int(len(hist) - 1),
+            "at_workload_fiducial": {"cond_sigma": c1, "marginal_sigma": m1},
+            "after_one_fiducial_step": {"cond_sigma": c2, "marginal_sigma": m2}}
 
 
 def catalog_line(args):
@@ -703,6 +744,9 @@ def main():
         return
     if args.cmb_full:
         print(json.dumps({"cmb1024_bandpowers_nsim256": cmb_full_line(args)}), flush=True)
+        return
+    if args.cmb_iterate:
+        print(json.dumps({"cmb1024_fiducial_iteration": cmb_iterate_line(args)}), flush=True)
         return
     if args.density_bands_only:
         print(json.dumps({"density256_bandpowers": density_bands_line(args)}), flush=True)

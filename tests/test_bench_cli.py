@@ -21,5 +21,5 @@ def test_more_than_one_gpu_is_refused():
 def test_help_lists_the_modes():
     r = _run("--help")
     assert r.returncode == 0
-    for flag in ("--steps", "--warmup", "--gpus", "--catalog-only", "--density-bands-only", "--cmb-full"):
+    for flag in ("--steps", "--warmup", "--gpus", "--catalog-only", "--density-bands-only", "--cmb-full", "--cmb-iterate"):
         assert flag in r.stdout, flag
