@@ -564,7 +564,6 @@ def cmb_full_line(args):
     """The 1024^2 CMB band-power estimate at its full size: 40 linear bands, 256 simulations
     (1 + 256 x 41 = 10497 MAP solves, run in batches of 256), preconditioned L-BFGS to the
     bench's tolerance; one untimed estimate with 2 simulations first (tile tuning, graph capture)."""
-    import numpy as np
     import torch
 
     import paper_1810_00503_amd as wf
